@@ -1,0 +1,283 @@
+"""ctypes shim over ``liborc.so`` (built from ``imask_oracle.c``).
+
+Every function takes and returns float64 numpy arrays shaped like the paper's
+objects: images are (N_l, N_l), sinograms are (n_angles, n_det).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "imask_oracle.c")
+_LIB = os.path.join(_HERE, "liborc.so")
+
+MODE_PAPER = 0
+MODE_UNBIASED = 1
+REG_TIKHONOV = 0
+REG_SMOOTH_TV = 1
+
+_D = ctypes.POINTER(ctypes.c_double)
+_I32 = ctypes.POINTER(ctypes.c_int32)
+_U64 = ctypes.POINTER(ctypes.c_uint64)
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (FP64, no fast-math, OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp",
+                               "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = ctypes.CDLL(build())
+        L = _lib
+        geo = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double]
+        L.orc_project.argtypes = geo + [ctypes.c_int, _D, _D]
+        L.orc_backproject.argtypes = geo + [ctypes.c_int, _D, _D]
+        L.orc_count_samples.argtypes = geo + [ctypes.c_int]
+        L.orc_count_samples.restype = ctypes.c_longlong
+        L.orc_restrict.argtypes = [ctypes.c_int, ctypes.c_int, _D, _D]
+        L.orc_prolong.argtypes = [ctypes.c_int, ctypes.c_int, _D, _D]
+        L.orc_compensate.argtypes = [ctypes.c_int, ctypes.c_int, _I32, _D, _D, _D]
+        sk = geo + [ctypes.c_int, _I32, _D, ctypes.c_int, ctypes.c_int, _D, _D]
+        L.orc_sketch_fwd.argtypes = sk
+        L.orc_sketch_adj.argtypes = sk
+        L.orc_splitmix64.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+        L.orc_splitmix64.restype = ctypes.c_uint64
+        L.orc_thresholds.argtypes = [ctypes.c_int, _D, _U64]
+        L.orc_draws.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int,
+                                ctypes.c_int, _D, _I32]
+        L.orc_tv_value.argtypes = [ctypes.c_int, _D, ctypes.c_double]
+        L.orc_tv_value.restype = ctypes.c_double
+        L.orc_tv_gradient.argtypes = [ctypes.c_int, _D, ctypes.c_double, _D]
+        L.orc_tv_prox.argtypes = [ctypes.c_int, _D, _D, ctypes.c_double, ctypes.c_double,
+                                  ctypes.c_double, ctypes.c_double, ctypes.c_int, _D]
+        L.orc_imask_run.argtypes = geo + [ctypes.c_int, _I32, _D, ctypes.c_int,
+                                          ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                          ctypes.c_double, ctypes.c_int,
+                                          ctypes.c_double, ctypes.c_uint64, ctypes.c_uint32,
+                                          ctypes.c_uint64, _D, ctypes.c_int,
+                                          _D, _D, _D, _D, _I32, _D]
+        L.orc_imask_run.restype = ctypes.c_int
+    return _lib
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(_D)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+@dataclass(frozen=True)
+class Geometry:
+    """2-D parallel-beam geometry: N x N image on [-1,1]^2, n_angles angles
+    a*pi/n_angles, n_det bins of spacing ds (default: full-res pixel size)."""
+    n: int
+    n_angles: int
+    n_det: int
+    ds: float = 0.0
+    s0: float = 0.0
+
+    @property
+    def spacing(self) -> float:
+        return self.ds if self.ds > 0 else 2.0 / self.n
+
+    def args(self):
+        return (self.n, self.n_angles, self.n_det, self.spacing, self.s0)
+
+
+@dataclass
+class Levels:
+    """Resolution set: log2 downsampling factors (first one 0) and the
+    sampling probabilities p of each sketch."""
+    log2f: list
+    p: list
+    mode: int = MODE_PAPER
+
+    @property
+    def r(self) -> int:
+        return len(self.log2f)
+
+    def carrays(self):
+        lf = np.ascontiguousarray(self.log2f, dtype=np.int32)
+        pp = _f64(self.p)
+        return lf, pp
+
+
+def project(g: Geometry, lvl: int, z) -> np.ndarray:
+    z = _f64(z)
+    assert z.shape == (g.n >> lvl, g.n >> lvl)
+    out = np.empty((g.n_angles, g.n_det))
+    lib().orc_project(*g.args(), lvl, _dp(z), _dp(out))
+    return out
+
+
+def backproject(g: Geometry, lvl: int, sino) -> np.ndarray:
+    s = _f64(sino)
+    assert s.shape == (g.n_angles, g.n_det)
+    nl = g.n >> lvl
+    out = np.empty((nl, nl))
+    lib().orc_backproject(*g.args(), lvl, _dp(s), _dp(out))
+    return out
+
+
+def count_samples(g: Geometry, lvl: int) -> int:
+    return int(lib().orc_count_samples(*g.args(), lvl))
+
+
+def restrict(x, lvl: int) -> np.ndarray:
+    x = _f64(x)
+    n = x.shape[0]
+    out = np.empty((n >> lvl, n >> lvl))
+    lib().orc_restrict(n, lvl, _dp(x), _dp(out))
+    return out
+
+
+def prolong(z, lvl: int) -> np.ndarray:
+    z = _f64(z)
+    n = z.shape[0] << lvl
+    out = np.empty((n, n))
+    lib().orc_prolong(n, lvl, _dp(z), _dp(out))
+    return out
+
+
+def compensate(x, lv: Levels) -> np.ndarray:
+    x = _f64(x)
+    lf, pp = lv.carrays()
+    out = np.empty_like(x)
+    lib().orc_compensate(x.shape[0], lv.r, lf.ctypes.data_as(_I32), _dp(pp), _dp(x), _dp(out))
+    return out
+
+
+def sketch_fwd(g: Geometry, lv: Levels, k: int, x) -> np.ndarray:
+    x = _f64(x)
+    lf, pp = lv.carrays()
+    out = np.empty((g.n_angles, g.n_det))
+    lib().orc_sketch_fwd(*g.args(), lv.r, lf.ctypes.data_as(_I32), _dp(pp), lv.mode, k,
+                         _dp(x), _dp(out))
+    return out
+
+
+def sketch_adj(g: Geometry, lv: Levels, k: int, y) -> np.ndarray:
+    y = _f64(y)
+    lf, pp = lv.carrays()
+    out = np.empty((g.n, g.n))
+    lib().orc_sketch_adj(*g.args(), lv.r, lf.ctypes.data_as(_I32), _dp(pp), lv.mode, k,
+                         _dp(y), _dp(out))
+    return out
+
+
+def splitmix64(seed: int, k: int) -> int:
+    return int(lib().orc_splitmix64(seed, k))
+
+
+def thresholds(p) -> np.ndarray:
+    pp = _f64(p)
+    out = np.empty(len(pp), dtype=np.uint64)
+    lib().orc_thresholds(len(pp), _dp(pp), out.ctypes.data_as(_U64))
+    return out
+
+
+def draws(seed: int, stream: int, k0: int, count: int, p) -> np.ndarray:
+    pp = _f64(p)
+    out = np.empty(count, dtype=np.int32)
+    lib().orc_draws(seed, stream, k0, count, len(pp), _dp(pp), out.ctypes.data_as(_I32))
+    return out
+
+
+def tv_value(u, eps: float) -> float:
+    u = _f64(u)
+    return float(lib().orc_tv_value(u.shape[0], _dp(u), eps))
+
+
+def tv_gradient(u, eps: float) -> np.ndarray:
+    u = _f64(u)
+    out = np.empty_like(u)
+    lib().orc_tv_gradient(u.shape[0], _dp(u), eps, _dp(out))
+    return out
+
+
+def tv_prox(v, u0, tau: float, lam: float, w: float, eps: float, J: int) -> np.ndarray:
+    v, u0 = _f64(v), _f64(u0)
+    out = np.empty_like(v)
+    lib().orc_tv_prox(v.shape[0], _dp(v), _dp(u0), tau, lam, w, eps, J, _dp(out))
+    return out
+
+
+@dataclass
+class Reg:
+    """Regulariser: TIKHONOV R = lam/2 |x|^2, or SMOOTH_TV
+    R = w TV_eps + lam/2 |x|^2 with J FISTA iterations; mu = lam."""
+    kind: int = REG_TIKHONOV
+    lam: float = 1e-2
+    tv_weight: float = 0.0
+    tv_eps: float = 1e-3
+    tv_inner: int = 10
+
+
+@dataclass
+class State:
+    x: np.ndarray
+    y: np.ndarray
+    phi: np.ndarray  # (r, N, N)
+    psi: np.ndarray  # (r, n_angles, n_det)
+    k: int = 0
+    epochs: float = 0.0
+    draws: list = field(default_factory=list)
+
+    @staticmethod
+    def zeros(g: Geometry, lv: Levels) -> "State":
+        return State(np.zeros((g.n, g.n)), np.zeros((g.n_angles, g.n_det)),
+                     np.zeros((lv.r, g.n, g.n)), np.zeros((lv.r, g.n_angles, g.n_det)))
+
+    def copy(self) -> "State":
+        return State(self.x.copy(), self.y.copy(), self.phi.copy(), self.psi.copy(),
+                     self.k, self.epochs, list(self.draws))
+
+
+def imask_run(g: Geometry, lv: Levels, reg: Reg, sigma: float, seed: int, stream: int,
+              b, n_iter: int, state: State | None = None) -> State:
+    """Alg. 1 (ImaSk) for n_iter iterations from `state` (zeros if None)."""
+    st = State.zeros(g, lv) if state is None else state.copy()
+    b = _f64(b)
+    lf, pp = lv.carrays()
+    dr = np.empty(max(n_iter, 1), dtype=np.int32)
+    ep = np.array([st.epochs])
+    rc = lib().orc_imask_run(*g.args(), lv.r, lf.ctypes.data_as(_I32), _dp(pp), lv.mode,
+                             reg.kind, reg.lam, reg.tv_weight, reg.tv_eps, reg.tv_inner,
+                             sigma, seed, stream, st.k, _dp(b), n_iter,
+                             _dp(st.x), _dp(st.y), _dp(st.phi), _dp(st.psi),
+                             dr.ctypes.data_as(_I32), _dp(ep))
+    if rc != 0:
+        raise ValueError("oracle rejected the level set")
+    st.k += n_iter
+    st.epochs = float(ep[0])
+    st.draws.extend(int(v) for v in dr[:n_iter])
+    return st
+
+
+def dense_matrix(fwd, n_in_shape, n_out: int) -> np.ndarray:
+    """Explicit matrix of a linear map by applying it to unit vectors."""
+    n_in = int(np.prod(n_in_shape))
+    A = np.empty((n_out, n_in))
+    e = np.zeros(n_in)
+    for q in range(n_in):
+        e[q] = 1.0
+        A[:, q] = np.ravel(fwd(e.reshape(n_in_shape)))
+        e[q] = 0.0
+    return A

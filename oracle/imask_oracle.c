@@ -1,0 +1,470 @@
+/*
+ * imask_oracle.c - plain FP64 CPU oracle for the ImaSk hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library calls, links or
+ * loads this file; only the test-suite, the smoke check and the benchmark's
+ * CPU-baseline leg do.  It shares no code, header or constant table with the
+ * HIP implementation.
+ *
+ * Everything is double precision, written straight from the definitions:
+ *   - ray-driven Joseph projector R_l on the level-l grid and its literal
+ *     scatter transpose (the paper's "forward model on the i-th low resolution
+ *     grid", Sec. 4.1, eq. (CT_sketches));
+ *   - block-average decimation T_l and replication T_l^* (Sec. 4.1), the
+ *     projection P_l = T_l^* T_l and the full-resolution compensation
+ *     S_r = p_r^{-1}(I - sum_l p_l P_l) (Sec. 4.1);
+ *   - the sketched operators K_l and their transposes (eq. (CT_sketches));
+ *   - the counter-based SplitMix64 draw of the sketch index (Alg. 1, step
+ *     "sample i_k with probability p");
+ *   - Algorithm 1 (ImaSk) with the Tikhonov prox and a smoothed-TV prox
+ *     evaluated by FISTA (Sec. 4.2 and 4.5).
+ *
+ * Conventions: domain [-1,1]^2; level l has N_l = N >> l pixels per side and
+ * pixel size h_l = 2/N_l; pixel (i,j) has centre (x_j, y_i) with
+ * x_j = -1 + (j+1/2) h_l; rows are y, columns are x, storage row-major.
+ * Angle a is theta_a = a*pi/n_angles, bin b has centre
+ * s_b = (b - (n_det-1)/2) ds + s0 and the ray is x cos + y sin = s.
+ * Angle a steps along rows iff 4a <= n_angles or 4a >= 3 n_angles, else
+ * along columns.  Interpolation reads zero outside the image.
+ */
+#include <math.h>
+#include <omp.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
+#define ORC_MAX_LEVELS 16
+
+enum { ORC_MODE_PAPER = 0, ORC_MODE_UNBIASED = 1 };
+enum { ORC_REG_TIKHONOV = 0, ORC_REG_SMOOTH_TV = 1 };
+
+static int orc_row_stepping(int a, int na) { return 4 * a <= na || 4 * a >= 3 * na; }
+
+static double orc_pix(const double* z, int nl, long i, long j)
+{
+    if (i < 0 || j < 0 || i >= nl || j >= nl) return 0.0;
+    return z[i * nl + j];
+}
+
+/* ---------------------------------------------------------------- Joseph R_l */
+
+/* sino[a][b] = (h_l/|cos|) sum_i interp_j(z[i][.], u)   (row stepping)
+ *            = (h_l/|sin|) sum_j interp_i(z[.][j], v)   (column stepping) */
+void orc_project(int n, int na, int nd, double ds, double s0, int lvl,
+                 const double* z, double* sino)
+{
+    const int nl = n >> lvl;
+    const double hl = 2.0 / nl;
+    const double c0 = -1.0 + 0.5 * hl; /* centre of pixel 0 along either axis */
+#pragma omp parallel for schedule(static)
+    for (long ab = 0; ab < (long)na * nd; ++ab) {
+        const int a = (int)(ab / nd), b = (int)(ab % nd);
+        const double th = a * M_PI / na, ct = cos(th), st = sin(th);
+        const double sb = (b - (nd - 1) / 2.0) * ds + s0;
+        double acc = 0.0;
+        if (orc_row_stepping(a, na)) {
+            for (int i = 0; i < nl; ++i) {
+                const double yi = -1.0 + (i + 0.5) * hl;
+                const double u = ((sb - yi * st) / ct - c0) / hl;
+                const double fl = floor(u);
+                const long j0 = (long)fl;
+                const double w = u - fl;
+                acc += (1.0 - w) * orc_pix(z, nl, i, j0) + w * orc_pix(z, nl, i, j0 + 1);
+            }
+            sino[ab] = acc * (hl / fabs(ct));
+        } else {
+            for (int j = 0; j < nl; ++j) {
+                const double xj = -1.0 + (j + 0.5) * hl;
+                const double v = ((sb - xj * ct) / st - c0) / hl;
+                const double fl = floor(v);
+                const long i0 = (long)fl;
+                const double w = v - fl;
+                acc += (1.0 - w) * orc_pix(z, nl, i0, j) + w * orc_pix(z, nl, i0 + 1, j);
+            }
+            sino[ab] = acc * (hl / fabs(st));
+        }
+    }
+}
+
+/* The literal transpose of orc_project: the same loops, scattering
+ * t*(1-w) and t*w into the two pixels each sample reads. */
+void orc_backproject(int n, int na, int nd, double ds, double s0, int lvl,
+                     const double* sino, double* z)
+{
+    const int nl = n >> lvl;
+    const double hl = 2.0 / nl;
+    const double c0 = -1.0 + 0.5 * hl;
+    const long dl = (long)nl * nl;
+    memset(z, 0, sizeof(double) * dl);
+    /* per-thread partial images, summed in thread order afterwards so that
+     * the result is reproducible for a fixed thread count */
+    const int nt = omp_get_max_threads();
+    double* part = (double*)calloc((size_t)nt * dl, sizeof(double));
+#pragma omp parallel num_threads(nt)
+    {
+        double* acc = part + (size_t)omp_get_thread_num() * dl;
+#pragma omp for schedule(static)
+        for (int a = 0; a < na; ++a) {
+            const double th = a * M_PI / na, ct = cos(th), st = sin(th);
+            const int rows = orc_row_stepping(a, na);
+            for (int b = 0; b < nd; ++b) {
+                const double sb = (b - (nd - 1) / 2.0) * ds + s0;
+                const double t = (rows ? hl / fabs(ct) : hl / fabs(st)) * sino[(long)a * nd + b];
+                for (int k = 0; k < nl; ++k) {
+                    const double ck = -1.0 + (k + 0.5) * hl;
+                    const double u = rows ? ((sb - ck * st) / ct - c0) / hl : ((sb - ck * ct) / st - c0) / hl;
+                    const double fl = floor(u);
+                    const long q0 = (long)fl;
+                    const double w = u - fl;
+                    if (rows) {
+                        if (q0 >= 0 && q0 < nl) acc[(long)k * nl + q0] += t * (1.0 - w);
+                        if (q0 + 1 >= 0 && q0 + 1 < nl) acc[(long)k * nl + q0 + 1] += t * w;
+                    } else {
+                        if (q0 >= 0 && q0 < nl) acc[q0 * nl + k] += t * (1.0 - w);
+                        if (q0 + 1 >= 0 && q0 + 1 < nl) acc[(q0 + 1) * nl + k] += t * w;
+                    }
+                }
+            }
+        }
+    }
+    for (int q = 0; q < nt; ++q)
+        for (long e = 0; e < dl; ++e) z[e] += part[(size_t)q * dl + e];
+    free(part);
+}
+
+/* Number of (ray, step) samples with at least one interpolation tap inside
+ * the image: the nonzero-sample count of R_l (work accounting only). */
+long long orc_count_samples(int n, int na, int nd, double ds, double s0, int lvl)
+{
+    const int nl = n >> lvl;
+    const double hl = 2.0 / nl;
+    const double c0 = -1.0 + 0.5 * hl;
+    long long total = 0;
+#pragma omp parallel for reduction(+ : total) schedule(static)
+    for (long ab = 0; ab < (long)na * nd; ++ab) {
+        const int a = (int)(ab / nd), b = (int)(ab % nd);
+        const double th = a * M_PI / na, ct = cos(th), st = sin(th);
+        const double sb = (b - (nd - 1) / 2.0) * ds + s0;
+        const int rows = orc_row_stepping(a, na);
+        for (int k = 0; k < nl; ++k) {
+            const double ck = -1.0 + (k + 0.5) * hl;
+            const double u = rows ? ((sb - ck * st) / ct - c0) / hl : ((sb - ck * ct) / st - c0) / hl;
+            const long q0 = (long)floor(u);
+            if (q0 >= -1 && q0 < nl) ++total;
+        }
+    }
+    return total;
+}
+
+/* ------------------------------------------------------------ resampling */
+
+/* T_l: 2^l x 2^l block mean (Sec. 4.1). */
+void orc_restrict(int n, int lvl, const double* x, double* z)
+{
+    const int nl = n >> lvl, f = 1 << lvl;
+    for (int I = 0; I < nl; ++I)
+        for (int J = 0; J < nl; ++J) {
+            double s = 0.0;
+            for (int a = 0; a < f; ++a)
+                for (int b = 0; b < f; ++b) s += x[(long)(I * f + a) * n + (J * f + b)];
+            z[(long)I * nl + J] = s / ((double)f * f);
+        }
+}
+
+/* T_l^*: replication, x[i][j] = z[i >> l][j >> l] (Sec. 4.1). */
+void orc_prolong(int n, int lvl, const double* z, double* x)
+{
+    const int nl = n >> lvl;
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) x[(long)i * n + j] = z[(long)(i >> lvl) * nl + (j >> lvl)];
+}
+
+/* S_r x = p_0^{-1} (x - sum_{k>0} p_k P_k x) with P_k = T_k^* T_k. */
+void orc_compensate(int n, int r, const int* log2f, const double* p, const double* x, double* out)
+{
+    const long d = (long)n * n;
+    double* z = (double*)malloc(sizeof(double) * d);
+    double* px = (double*)malloc(sizeof(double) * d);
+    for (long q = 0; q < d; ++q) out[q] = x[q];
+    for (int k = 1; k < r; ++k) {
+        orc_restrict(n, log2f[k], x, z);
+        orc_prolong(n, log2f[k], z, px);
+        for (long q = 0; q < d; ++q) out[q] -= p[k] * px[q];
+    }
+    for (long q = 0; q < d; ++q) out[q] /= p[0];
+    free(z);
+    free(px);
+}
+
+/* ------------------------------------------------------ sketched operators */
+
+/* g = K_k x (sinogram), for sketch k of the level set (log2f[0] == 0). */
+void orc_sketch_fwd(int n, int na, int nd, double ds, double s0, int r, const int* log2f,
+                    const double* p, int mode, int k, const double* x, double* g)
+{
+    const long d = (long)n * n, m = (long)na * nd;
+    double* z = (double*)malloc(sizeof(double) * d);
+    if (k > 0) {
+        orc_restrict(n, log2f[k], x, z);
+        orc_project(n, na, nd, ds, s0, log2f[k], z, g);
+    } else if (mode == ORC_MODE_PAPER) {
+        orc_compensate(n, r, log2f, p, x, z);
+        orc_project(n, na, nd, ds, s0, 0, z, g);
+    } else {
+        double* t = (double*)malloc(sizeof(double) * m);
+        orc_project(n, na, nd, ds, s0, 0, x, g);
+        for (int q = 1; q < r; ++q) {
+            orc_restrict(n, log2f[q], x, z);
+            orc_project(n, na, nd, ds, s0, log2f[q], z, t);
+            for (long e = 0; e < m; ++e) g[e] -= p[q] * t[e];
+        }
+        for (long e = 0; e < m; ++e) g[e] /= p[0];
+        free(t);
+    }
+    free(z);
+}
+
+/* g = K_k^T y (image), the exact transpose of orc_sketch_fwd. */
+void orc_sketch_adj(int n, int na, int nd, double ds, double s0, int r, const int* log2f,
+                    const double* p, int mode, int k, const double* y, double* g)
+{
+    const long d = (long)n * n;
+    double* c = (double*)malloc(sizeof(double) * d);
+    double* t = (double*)malloc(sizeof(double) * d);
+    if (k > 0) {
+        const int l = log2f[k];
+        const double s = 1.0 / (double)(1L << (2 * l)); /* T_l^T = 4^{-l} T_l^* */
+        orc_backproject(n, na, nd, ds, s0, l, y, c);
+        orc_prolong(n, l, c, g);
+        for (long q = 0; q < d; ++q) g[q] *= s;
+    } else if (mode == ORC_MODE_PAPER) {
+        orc_backproject(n, na, nd, ds, s0, 0, y, c);
+        orc_compensate(n, r, log2f, p, c, g); /* S_r is symmetric */
+    } else {
+        orc_backproject(n, na, nd, ds, s0, 0, y, g);
+        for (int q = 1; q < r; ++q) {
+            const int l = log2f[q];
+            const double s = 1.0 / (double)(1L << (2 * l));
+            orc_backproject(n, na, nd, ds, s0, l, y, c);
+            orc_prolong(n, l, c, t);
+            for (long e = 0; e < d; ++e) g[e] -= p[q] * s * t[e];
+        }
+        for (long e = 0; e < d; ++e) g[e] /= p[0];
+    }
+    free(c);
+    free(t);
+}
+
+/* ---------------------------------------------------------------- draws */
+
+/* SplitMix64 (Steele, Lea & Flood, OOPSLA 2014), counter form: the k-th
+ * output (k = 0, 1, ...) of the generator whose state starts at `seed`. */
+uint64_t orc_splitmix64(uint64_t seed, uint64_t k)
+{
+    uint64_t z = seed + (k + 1) * 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+/* Cumulative thresholds T_j = min(2^32, floor(2^32 * sum_{t<=j} p_t)),
+ * with the last one forced to 2^32. */
+void orc_thresholds(int r, const double* p, uint64_t* thr)
+{
+    double cum = 0.0;
+    for (int j = 0; j < r; ++j) {
+        cum += p[j];
+        double t = floor(4294967296.0 * cum);
+        if (t > 4294967296.0) t = 4294967296.0;
+        thr[j] = (uint64_t)t;
+    }
+    thr[r - 1] = 4294967296ULL;
+}
+
+/* i_k for k = k0 .. k0+count-1 of stream `stream` under base seed `seed`. */
+void orc_draws(uint64_t seed, uint32_t stream, uint64_t k0, int count, int r,
+               const double* p, int32_t* out)
+{
+    uint64_t thr[ORC_MAX_LEVELS];
+    orc_thresholds(r, p, thr);
+    const uint64_t ss = orc_splitmix64(seed, stream);
+    for (int q = 0; q < count; ++q) {
+        const uint64_t u = orc_splitmix64(ss, k0 + (uint64_t)q) >> 32;
+        int j = 0;
+        while (u >= thr[j]) ++j;
+        out[q] = j;
+    }
+}
+
+/* ------------------------------------------------------------ smoothed TV */
+
+/* Forward differences with a zero difference at the last row / column. */
+static void orc_grad(int n, const double* u, double* g1, double* g2)
+{
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            const long q = (long)i * n + j;
+            g1[q] = (i < n - 1) ? u[q + n] - u[q] : 0.0;
+            g2[q] = (j < n - 1) ? u[q + 1] - u[q] : 0.0;
+        }
+}
+
+/* Adjoint of orc_grad. */
+static void orc_grad_adj(int n, const double* q1, const double* q2, double* out)
+{
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            const long q = (long)i * n + j;
+            double s = 0.0;
+            if (i >= 1) s += q1[q - n];
+            if (i < n - 1) s -= q1[q];
+            if (j >= 1) s += q2[q - 1];
+            if (j < n - 1) s -= q2[q];
+            out[q] = s;
+        }
+}
+
+/* TV_eps(u) = sum sqrt(|grad u|^2 + eps^2). */
+double orc_tv_value(int n, const double* u, double eps)
+{
+    const long d = (long)n * n;
+    double* g1 = (double*)malloc(sizeof(double) * d);
+    double* g2 = (double*)malloc(sizeof(double) * d);
+    orc_grad(n, u, g1, g2);
+    double s = 0.0;
+    for (long q = 0; q < d; ++q) s += sqrt(g1[q] * g1[q] + g2[q] * g2[q] + eps * eps);
+    free(g1);
+    free(g2);
+    return s;
+}
+
+/* Gradient of TV_eps: grad^T (grad u / sqrt(|grad u|^2 + eps^2)). */
+void orc_tv_gradient(int n, const double* u, double eps, double* out)
+{
+    const long d = (long)n * n;
+    double* g1 = (double*)malloc(sizeof(double) * d);
+    double* g2 = (double*)malloc(sizeof(double) * d);
+    orc_grad(n, u, g1, g2);
+    for (long q = 0; q < d; ++q) {
+        const double nrm = sqrt(g1[q] * g1[q] + g2[q] * g2[q] + eps * eps);
+        g1[q] /= nrm;
+        g2[q] /= nrm;
+    }
+    orc_grad_adj(n, g1, g2, out);
+    free(g1);
+    free(g2);
+}
+
+/* prox of tau*R with R = w TV_eps + (lam/2)|.|^2, approximated by J FISTA
+ * iterations (Beck-Teboulle) on h(u) = 1/2|u-v|^2 + tau w TV_eps(u) +
+ * tau lam/2 |u|^2, started at u0, step 1/L with L = 1 + tau lam + 8 tau w/eps. */
+void orc_tv_prox(int n, const double* v, const double* u0, double tau, double lam,
+                 double w, double eps, int J, double* out)
+{
+    const long d = (long)n * n;
+    const double L = 1.0 + tau * lam + 8.0 * tau * w / eps;
+    double* uk = (double*)malloc(sizeof(double) * d);
+    double* yk = (double*)malloc(sizeof(double) * d);
+    double* gr = (double*)malloc(sizeof(double) * d);
+    double* un = (double*)malloc(sizeof(double) * d);
+    memcpy(uk, u0, sizeof(double) * d);
+    memcpy(yk, u0, sizeof(double) * d);
+    double t = 1.0;
+    for (int it = 0; it < J; ++it) {
+        orc_tv_gradient(n, yk, eps, gr);
+        for (long q = 0; q < d; ++q) {
+            const double gh = (yk[q] - v[q]) + tau * w * gr[q] + tau * lam * yk[q];
+            un[q] = yk[q] - gh / L;
+        }
+        const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
+        const double beta = (t - 1.0) / tn;
+        for (long q = 0; q < d; ++q) {
+            yk[q] = un[q] + beta * (un[q] - uk[q]);
+            uk[q] = un[q];
+        }
+        t = tn;
+    }
+    memcpy(out, uk, sizeof(double) * d);
+    free(uk);
+    free(yk);
+    free(gr);
+    free(un);
+}
+
+/* ------------------------------------------------------------ Algorithm 1 */
+
+/* Runs n_iter iterations of ImaSk (Alg. 1) from the state (x, y, phi, psi)
+ * given at iteration k0, in place.  phi holds r full-resolution images
+ * (phi_k = K_k^T y at the last refresh), psi holds r sinograms
+ * (psi_k = K_k x at the last refresh).  mu = lam.  draws_out[q] receives
+ * i_{k0+q}; *epochs accumulates sum_q 2^{-log2f[i_q]} (PAPER cost model) or,
+ * in UNBIASED mode, 1 + sum_{k>0} 2^{-log2f[k]} for a full-resolution step. */
+int orc_imask_run(int n, int na, int nd, double ds, double s0,
+                  int r, const int* log2f, const double* p, int mode,
+                  int reg_kind, double lam, double tv_w, double tv_eps, int tv_inner,
+                  double sigma, uint64_t seed, uint32_t stream, uint64_t k0,
+                  const double* bdata, int n_iter,
+                  double* x, double* y, double* phi, double* psi,
+                  int32_t* draws_out, double* epochs)
+{
+    if (r < 1 || r > ORC_MAX_LEVELS || log2f[0] != 0) return -1;
+    const long d = (long)n * n, m = (long)na * nd;
+    const double tau = sigma / lam;
+    double* gx = (double*)malloc(sizeof(double) * d);
+    double* gy = (double*)malloc(sizeof(double) * m);
+    double* xi = (double*)malloc(sizeof(double) * d);
+    double* zeta = (double*)malloc(sizeof(double) * m);
+    double* xn = (double*)malloc(sizeof(double) * d);
+    int32_t* idx = (int32_t*)malloc(sizeof(int32_t) * (n_iter > 0 ? n_iter : 1));
+    orc_draws(seed, stream, k0, n_iter, r, p, idx);
+    double unbiased_full = 1.0;
+    for (int k = 1; k < r; ++k) unbiased_full += ldexp(1.0, -log2f[k]);
+    for (int it = 0; it < n_iter; ++it) {
+        const int k = idx[it];
+        /* both refreshed gradients from the old iterates x^k, y^k */
+        orc_sketch_adj(n, na, nd, ds, s0, r, log2f, p, mode, k, y, gx);
+        orc_sketch_fwd(n, na, nd, ds, s0, r, log2f, p, mode, k, x, gy);
+        /* SAGA estimates with the old tables */
+        for (long q = 0; q < d; ++q) {
+            double avg = 0.0;
+            for (int j = 0; j < r; ++j) avg += p[j] * phi[(long)j * d + q];
+            xi[q] = gx[q] - phi[(long)k * d + q] + avg;
+        }
+        for (long e = 0; e < m; ++e) {
+            double avg = 0.0;
+            for (int j = 0; j < r; ++j) avg += p[j] * psi[(long)j * m + e];
+            zeta[e] = gy[e] - psi[(long)k * m + e] + avg;
+        }
+        /* primal: prox_{tau R}(x - tau xi) */
+        for (long q = 0; q < d; ++q) xn[q] = x[q] - tau * xi[q];
+        if (reg_kind == ORC_REG_TIKHONOV) {
+            for (long q = 0; q < d; ++q) xn[q] = xn[q] / (1.0 + tau * lam);
+        } else {
+            double* v = (double*)malloc(sizeof(double) * d);
+            memcpy(v, xn, sizeof(double) * d);
+            orc_tv_prox(n, v, x, tau, lam, tv_w, tv_eps, tv_inner, xn);
+            free(v);
+        }
+        /* dual: (y + sigma zeta - sigma b)/(1 + sigma) */
+        for (long e = 0; e < m; ++e) y[e] = (y[e] + sigma * zeta[e] - sigma * bdata[e]) / (1.0 + sigma);
+        memcpy(x, xn, sizeof(double) * d);
+        memcpy(phi + (long)k * d, gx, sizeof(double) * d);
+        memcpy(psi + (long)k * m, gy, sizeof(double) * m);
+        if (draws_out) draws_out[it] = k;
+        if (epochs) {
+            if (k == 0 && mode == ORC_MODE_UNBIASED) *epochs += unbiased_full;
+            else *epochs += ldexp(1.0, -log2f[k]);
+        }
+    }
+    free(gx);
+    free(gy);
+    free(xi);
+    free(zeta);
+    free(xn);
+    free(idx);
+    return 0;
+}

@@ -1,0 +1,150 @@
+"""Seeded phantoms and measurement data for 2-D parallel-beam CT.
+
+Geometry conventions (shared by every consumer, stated once here):
+
+* The image domain is the square [-E, E]^2 with E = 1.  An N x N image has
+  pixel size h = 2E/N; pixel (i, j) is row i, column j, with centre
+  x_j = -E + (j + 1/2) h and y_i = -E + (i + 1/2) h, stored row-major.
+* Projection angle a of n_angles is theta_a = a*pi/n_angles (uniform over
+  [0, pi), as in the paper's parallel-beam experiments, Sec. 4.1).
+* Detector bin b of n_det has centre s_b = (b - (n_det-1)/2) * ds + s0 with
+  ds = the full-resolution pixel size 2E/N and s0 = 0.
+* A ray is the line {x cos(theta) + y sin(theta) = s}.
+
+The phantom family (random ellipses) stands in for the XCAT and AAPM images
+of the paper's Sec. 4, which are not reproduced here.  The measured data are
+the *analytic* line integrals of the ellipses (not a discrete projector, so
+no inverse crime), passed through Poisson counting noise and the log
+transform, as in the paper's noisy CT simulations (Sec. 4.1-4.2).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+EXTENT = 1.0
+
+
+@dataclass(frozen=True)
+class Ellipse:
+    cx: float
+    cy: float
+    a: float  # semi-axis along the rotated x direction
+    b: float  # semi-axis along the rotated y direction
+    phi: float  # rotation angle
+    value: float  # additive intensity
+
+
+def angles_uniform(n_angles: int) -> np.ndarray:
+    return np.arange(n_angles, dtype=np.float64) * np.pi / n_angles
+
+
+def detector_centres(n: int, n_det: int, det_offset: float = 0.0) -> np.ndarray:
+    ds = 2.0 * EXTENT / n
+    return (np.arange(n_det, dtype=np.float64) - (n_det - 1) / 2.0) * ds + det_offset
+
+
+def pixel_centres(n: int) -> np.ndarray:
+    h = 2.0 * EXTENT / n
+    return -EXTENT + (np.arange(n, dtype=np.float64) + 0.5) * h
+
+
+def random_ellipses(seed: int, n_ellipses: int = 8) -> list[Ellipse]:
+    """Random-ellipse phantom: centres uniform in the disk of radius 0.45,
+    semi-axes U[0.08, 0.45], rotation U[0, pi), intensity U[0, 1]; an
+    ellipse is redrawn until it lies inside the disk of radius 0.95."""
+    rng = np.random.default_rng(seed)
+    out: list[Ellipse] = []
+    while len(out) < n_ellipses:
+        rad = 0.45 * np.sqrt(rng.uniform())
+        ang = rng.uniform(0.0, 2.0 * np.pi)
+        cx, cy = rad * np.cos(ang), rad * np.sin(ang)
+        a, b = rng.uniform(0.08, 0.45, size=2)
+        phi = rng.uniform(0.0, np.pi)
+        val = rng.uniform(0.0, 1.0)
+        if np.hypot(cx, cy) + max(a, b) > 0.95:
+            continue
+        out.append(Ellipse(float(cx), float(cy), float(a), float(b), float(phi), float(val)))
+    return out
+
+
+def rasterize_ellipses(ells: list[Ellipse], n: int) -> np.ndarray:
+    """Sample the additive ellipse phantom at the N x N pixel centres."""
+    xc = pixel_centres(n)
+    X, Y = np.meshgrid(xc, xc, indexing="xy")  # X[i, j] = x_j, Y[i, j] = y_i
+    img = np.zeros((n, n), dtype=np.float64)
+    for e in ells:
+        dx, dy = X - e.cx, Y - e.cy
+        c, s = np.cos(e.phi), np.sin(e.phi)
+        xr = c * dx + s * dy
+        yr = -s * dx + c * dy
+        img += e.value * ((xr / e.a) ** 2 + (yr / e.b) ** 2 <= 1.0)
+    return img
+
+
+def ellipse_line_integrals(ells: list[Ellipse], n: int, n_angles: int, n_det: int,
+                           det_offset: float = 0.0) -> np.ndarray:
+    """Exact line integrals of the ellipse phantom on the ray grid, [angle][bin].
+
+    For an ellipse centred at c with semi-axes (a, b) rotated by phi, the
+    chord along the ray at angle theta and offset s has length
+    2ab sqrt(a_t^2 - s'^2)/a_t^2, where s' = s - (cx cos theta + cy sin theta)
+    and a_t^2 = a^2 cos^2(theta-phi) + b^2 sin^2(theta-phi)."""
+    th = angles_uniform(n_angles)[:, None]
+    s = detector_centres(n, n_det, det_offset)[None, :]
+    out = np.zeros((n_angles, n_det), dtype=np.float64)
+    for e in ells:
+        sp = s - (e.cx * np.cos(th) + e.cy * np.sin(th))
+        at2 = (e.a * np.cos(th - e.phi)) ** 2 + (e.b * np.sin(th - e.phi)) ** 2
+        inside = sp * sp < at2
+        chord = np.where(inside, 2.0 * e.a * e.b * np.sqrt(np.maximum(at2 - sp * sp, 0.0)) / at2, 0.0)
+        out += e.value * chord
+    return out
+
+
+def poisson_log_data(line_integrals: np.ndarray, i0: float, seed: int) -> np.ndarray:
+    """Counts n ~ Poisson(I0 exp(-p)); data b = -ln(max(n, 1)/I0)."""
+    rng = np.random.default_rng(seed)
+    counts = rng.poisson(i0 * np.exp(-line_integrals))
+    return -np.log(np.maximum(counts, 1).astype(np.float64) / i0)
+
+
+def ct_problem(n: int, n_angles: int, n_det: int, i0: float, phantom_seed: int,
+               noise_seed: int, n_ellipses: int = 8):
+    """(x_true, b): rasterised phantom and noisy post-log data, float64."""
+    ells = random_ellipses(phantom_seed, n_ellipses)
+    x_true = rasterize_ellipses(ells, n)
+    p = ellipse_line_integrals(ells, n, n_angles, n_det)
+    b = poisson_log_data(p, i0, noise_seed)
+    return x_true, b
+
+
+def disk_image(n: int, rho: float, cx: float = 0.0, cy: float = 0.0) -> np.ndarray:
+    """Unit disk of radius rho centred at (cx, cy), sampled at pixel centres."""
+    xc = pixel_centres(n)
+    X, Y = np.meshgrid(xc, xc, indexing="xy")
+    return ((X - cx) ** 2 + (Y - cy) ** 2 <= rho * rho).astype(np.float64)
+
+
+def square_insert(n: int, block: int, lo: int, hi: int, value: float = 1.0) -> np.ndarray:
+    """Square insert whose edges lie on the grid of block x block cells
+    (the paper's Sec. 5 test image): pixels with lo*block <= i, j < hi*block."""
+    img = np.zeros((n, n), dtype=np.float64)
+    img[lo * block:hi * block, lo * block:hi * block] = value
+    return img
+
+
+def affine_image(n: int, alpha: float, beta: float, gamma: float) -> np.ndarray:
+    """f(x, y) = alpha x + beta y + gamma at the pixel centres."""
+    xc = pixel_centres(n)
+    X, Y = np.meshgrid(xc, xc, indexing="xy")
+    return alpha * X + beta * Y + gamma
+
+
+def random_image(n: int, seed: int) -> np.ndarray:
+    return np.random.default_rng(seed).uniform(-1.0, 1.0, size=(n, n))
+
+
+def random_sinogram(n_angles: int, n_det: int, seed: int) -> np.ndarray:
+    return np.random.default_rng(seed).uniform(-1.0, 1.0, size=(n_angles, n_det))

@@ -1,0 +1,195 @@
+/*
+ * imask.h - C ABI of libimask, the MI355X (gfx950) implementation of the
+ * ImaSk hot path: stochastic multiresolution image-domain sketching for CT
+ * (Perelli, Schönlieb, Ehrhardt, arXiv 2412.10249).
+ *
+ * Problem (Sec. 1, eq. (min_obj)):  min_x 1/2 |K x - b|^2 + R(x), K the 2-D
+ * parallel-beam CT model.  ImaSk (Alg. 1) replaces K by a family of sketched
+ * operators K_i = K S_i (eq. (CT_sketches)) with probabilities p_i and runs a
+ * SAGA-type primal-dual iteration that applies one K_i and one K_i^T per step.
+ *
+ * Conventions (all functions):
+ *   - The image domain is [-1,1]^2.  A full-resolution image is N x N,
+ *     row-major, float32; pixel (i,j) is row i (y), column j (x), centre
+ *     (-1 + (j+1/2)h, -1 + (i+1/2)h), h = 2/N.
+ *   - Level l (l = log2 of the downsampling factor) has N_l = N >> l pixels
+ *     per side; N must be divisible by 2^l.
+ *   - Angle a of n_angles is a*pi/n_angles; bin b of n_det has centre
+ *     (b - (n_det-1)/2)*det_spacing + det_offset; the ray is
+ *     x cos(theta) + y sin(theta) = s.  Sinograms are [n_angles][n_det] float32.
+ *   - Every array argument is a DEVICE pointer owned by the caller, unless
+ *     the comment says "host".  The library allocates no device memory and
+ *     keeps no pointer after a call returns.
+ *   - `stream` is a hipStream_t (NULL = default stream).  All device work is
+ *     enqueued asynchronously on it; no call synchronises the device, so the
+ *     calls can be captured into a HIP graph.
+ *   - Return value: IMASK_OK (0) or a negative error code.  Arguments are
+ *     validated before anything is enqueued, so a failed call writes nothing.
+ *     IMASK_EHIP reports a failed kernel launch (hipGetLastError).
+ */
+#ifndef IMASK_H
+#define IMASK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define IMASK_MAX_LEVELS 8   /* sketches per level set (r) */
+#define IMASK_MAX_LOG2F 6    /* coarsest level: 2^6 downsampling */
+#define IMASK_MAX_TV_INNER 12
+
+enum {
+    IMASK_OK = 0,
+    IMASK_EINVAL = -1,  /* bad size, pointer, level set or parameter */
+    IMASK_ENOTSUP = -2, /* valid but unsupported combination */
+    IMASK_EHIP = -3,    /* a HIP launch failed */
+    IMASK_ESIZE = -4    /* workspace too small */
+};
+
+enum { IMASK_FULL_PAPER = 0, IMASK_FULL_UNBIASED = 1 };
+enum { IMASK_REG_TIKHONOV = 0, IMASK_REG_SMOOTH_TV = 1 };
+enum {
+    IMASK_RESTRICT = 0,     /* out (N_l^2)  = T_l in, 2^l x 2^l block mean (Sec. 4.1) */
+    IMASK_PROLONG = 1,      /* out (N^2)    = T_l^* in, replication (Sec. 4.1) */
+    IMASK_RESTRICT_ADJ = 2, /* out (N^2)    = T_l^T in = 4^{-l} T_l^* in (true adjoint of T_l) */
+    IMASK_PROJECT = 3,      /* out (N^2)    = P_l in = T_l^* T_l in (S_i of Sec. 4.1) */
+    IMASK_COMPENSATE = 4    /* out (N^2)    = S_r in = p_0^{-1}(in - sum_{k>0} p_k P_{l_k} in) */
+};
+enum { IMASK_BUDGET_ITERS = 0, IMASK_BUDGET_EPOCHS = 1 };
+
+/* Acquisition geometry (Sec. 4.1: parallel beam, m = n_angles * n_det). */
+typedef struct {
+    int32_t n;          /* full-resolution image side N (>= 4, multiple of 4) */
+    int32_t n_angles;   /* >= 1 */
+    int32_t n_det;      /* >= 1 */
+    double det_spacing; /* bin spacing; <= 0 selects the full-res pixel size 2/N */
+    double det_offset;  /* detector centre offset s0 */
+} imask_geometry;
+
+/* Resolution set and sampling probabilities (Alg. 1 REQUIRE line; Sec. 4.1).
+ * Sketch k uses level log2f[k]; log2f[0] must be 0 (the full-resolution
+ * sketch) and the list strictly increasing; p[k] > 0 with sum 1 (1e-9).
+ * full_mode selects the full-resolution sketch:
+ *   IMASK_FULL_PAPER    K_0 = K S_r, S_r = p_0^{-1}(I - sum_{k>0} p_k P_k)
+ *                       (the paper's construction; cost 1 epoch)
+ *   IMASK_FULL_UNBIASED K_0 = p_0^{-1}(R_0 - sum_{k>0} p_k R_{l_k} T_{l_k}),
+ *                       so that sum_k p_k K_k = R_0 exactly
+ *                       (cost 1 + sum_{k>0} 2^{-l_k} epochs). */
+typedef struct {
+    int32_t r;
+    int32_t log2f[IMASK_MAX_LEVELS];
+    double p[IMASK_MAX_LEVELS];
+    int32_t full_mode;
+} imask_levels;
+
+/* Regulariser R, mu-strongly convex with mu = lambda (Sec. 2.2, Sec. 4.2):
+ *   IMASK_REG_TIKHONOV  R = lambda/2 |x|^2, prox closed form
+ *   IMASK_REG_SMOOTH_TV R = tv_weight * sum sqrt(|grad x|^2 + tv_eps^2)
+ *                           + lambda/2 |x|^2, prox by tv_inner FISTA steps
+ *                           (Sec. 4.5 evaluates the TV prox with FISTA). */
+typedef struct {
+    int32_t kind;
+    double lambda;    /* > 0 */
+    double tv_weight; /* >= 0 */
+    double tv_eps;    /* > 0 */
+    int32_t tv_inner; /* 1 .. IMASK_MAX_TV_INNER */
+} imask_reg;
+
+/* Step size sigma (Alg. 1) and the sketch-index generator: SplitMix64 in
+ * counter form; stream seed = the stream_id-th output of the generator at
+ * state `seed`; draw k uses the k-th output of the stream (top 32 bits)
+ * against floor(2^32 * cumulative p). */
+typedef struct {
+    double sigma;
+    uint64_t seed;
+    uint32_t stream_id;
+} imask_params;
+
+/* ImaSk state (Alg. 1): iterates, gradient tables and counters.
+ *   x[2]   two N*N buffers (ping-pong): x[cur] is the current iterate
+ *   y[2]   two n_angles*n_det buffers: y[cur] is the current dual iterate
+ *   phi    image-space table K_k^T y: sketch 0 holds N*N floats, sketch k>0
+ *          holds its coarse image N_{l_k}^2 (phi_k = T_{l_k}^T(...) is
+ *          piecewise constant); concatenated in sketch order,
+ *          imask_phi_floats() floats in total
+ *   psi    sinogram-space table K_k x: r * n_angles*n_det floats
+ *   work   workspace prepared by imask_prepare() for this geometry
+ *   k      iteration counter (index of the next draw)
+ *   epochs equivalent full-resolution operator applications so far
+ *   cur    0 or 1 */
+typedef struct {
+    float* x[2];
+    float* y[2];
+    float* phi;
+    float* psi;
+    void* work;
+    uint64_t k;
+    double epochs;
+    int32_t cur;
+} imask_state;
+
+/* Bytes of device workspace needed for geometry g (host function). */
+size_t imask_workspace_bytes(const imask_geometry* g);
+
+/* Floats in the phi table for level set lv (host function). */
+size_t imask_phi_floats(const imask_geometry* g, const imask_levels* lv);
+
+/* Fills `work` (device, work_bytes >= imask_workspace_bytes(g)) with the
+ * per-(level, angle) projector constants and zeroes its scratch.  Every
+ * other call taking `work` requires a workspace prepared for the same
+ * geometry; calls sharing one workspace must be ordered on one stream. */
+int imask_prepare(const imask_geometry* g, void* work, size_t work_bytes, void* stream);
+
+/* sino = R_l T_l x_full  (x_full N*N; T_0 = I).  R_l is the ray-driven
+ * Joseph projector on the level-l grid: the forward model "on the l-th low
+ * resolution grid" of Sec. 4.1 (eq. (CT_sketches), K_i = R_i T_i). */
+int imask_project(const imask_geometry* g, int32_t log2f, const void* work,
+                  const float* x_full, float* sino, void* stream);
+
+/* x_full = T_l^T R_l^T sino = 4^{-l} T_l^* R_l^T sino, the exact transpose
+ * of imask_project (gather form: each pixel recomputes the forward weights,
+ * no atomics, deterministic). */
+int imask_backproject(const imask_geometry* g, int32_t log2f, const void* work,
+                      const float* sino, float* x_full, void* stream);
+
+/* Resampling operators of Sec. 4.1 on an N x N grid (see IMASK_RESTRICT ...).
+ * lv is read only for IMASK_COMPENSATE (may be NULL otherwise). */
+int imask_resample(int32_t n, int32_t log2f, int32_t mode, const imask_levels* lv,
+                   const float* in, float* out, void* stream);
+
+/* out = K_k in (adjoint == 0: in N*N, out sinogram) or K_k^T in (adjoint != 0:
+ * in sinogram, out N*N) for sketch k of level set lv (eq. (CT_sketches)). */
+int imask_sketch_apply(const imask_geometry* g, const imask_levels* lv, int32_t k,
+                       int32_t adjoint, const void* work, const float* in, float* out,
+                       void* stream);
+
+/* Host: the sketch indices i_k, k = k0 .. k0+count-1 (Alg. 1, "sample i_k"). */
+int imask_draws(const imask_params* prm, const imask_levels* lv, uint64_t k0, int32_t count,
+                int32_t* out_host);
+
+/* Runs n_steps iterations of Alg. 1 on each of n_problems independent
+ * problems (arrays of n_problems structs; b[q] is problem q's data, a
+ * sinogram).  For each step: draw k, psi_new = K_k x^k, phi_new = K_k^T y^k
+ * (both from the old iterates), xi/zeta from the old tables,
+ * x^{k+1} = prox_{sigma/mu R}(x^k - sigma/mu xi),
+ * y^{k+1} = (y^k + sigma zeta - sigma b)/(1 + sigma), then the tables are
+ * refreshed, cur flips, k += 1 and epochs += the sketch's cost. */
+int imask_step(int32_t n_problems, const imask_geometry* g, const imask_levels* lv,
+               const imask_reg* reg, const imask_params* prm, const float* const* b,
+               imask_state* s, int32_t n_steps, void* stream);
+
+/* Runs imask_step until every problem has done `budget` more iterations
+ * (IMASK_BUDGET_ITERS) or accumulated `budget` more epochs
+ * (IMASK_BUDGET_EPOCHS).  Returns after enqueueing; the epoch budget is
+ * evaluated on the host from the draws, without synchronising. */
+int imask_solve(int32_t n_problems, const imask_geometry* g, const imask_levels* lv,
+                const imask_reg* reg, const imask_params* prm, const float* const* b,
+                imask_state* s, double budget, int32_t budget_kind, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IMASK_H */

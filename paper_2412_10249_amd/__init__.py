@@ -1,0 +1,13 @@
+"""ImaSk (arXiv 2412.10249) hot path on AMD Instinct MI355X (gfx950).
+
+The computation lives in libimask (HIP kernels behind the C ABI of
+include/imask.h); this package marshals torch tensors and streams into it.
+"""
+from ._abi import (  # noqa: F401
+    BUDGET_EPOCHS, BUDGET_ITERS, COMPENSATE, FULL_PAPER, FULL_UNBIASED, PROJECT, PROLONG,
+    REG_SMOOTH_TV, REG_TIKHONOV, RESTRICT, RESTRICT_ADJ, ImaskError, LIB_PATH,
+)
+from .imask import (  # noqa: F401
+    Geometry, Levels, Params, Problem, Regularizer, backproject, draws, project, resample,
+    sketch_apply, step_many, workspace,
+)

@@ -1,0 +1,141 @@
+// internal.h - launch interface between the C ABI (api.hip) and the gfx950
+// kernels (kernels.hip).  Not installed; not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "imask.h"
+
+namespace imk {
+
+// Projector constants of one (level, angle).  The interpolation coordinate
+// of ray b at step i (row for row-stepping angles, column otherwise) is the
+// exact fixed-point value u = cfx + i*afx + b*bfx in units of 2^-32 pixel:
+// its high word is the left tap j0 and its low word the weight of the right
+// tap.  Both projector directions use this integer formula, so they agree on
+// every weight bit for bit.  The float fields mirror it for range estimates;
+// w is the step length h_l/|cos| (or h_l/|sin|), ib = 1/b.
+struct RayConst {
+    long long afx, bfx, cfx, pad;
+    float a, b, c, w, ib, r0, r1, r2;
+};
+static_assert(sizeof(RayConst) == 64, "RayConst is 64 bytes");
+constexpr int kConstStride = 16;  // floats per RayConst
+// Zero columns around every padded image row: kPadL before, kPadL after.
+constexpr int kPadL = 4;
+constexpr int kPad = 2 * kPadL;
+
+// Workspace layout for one geometry (offsets in floats from the start).
+struct Layout {
+    int n = 0, na = 0, nd = 0, lmax = 0;
+    size_t consts = 0;
+    size_t zp[IMASK_MAX_LOG2F + 1] = {};   // padded level-l image, rows
+    size_t zpT[IMASK_MAX_LOG2F + 1] = {};  // padded level-l image, transposed
+    size_t craw[IMASK_MAX_LOG2F + 1] = {}; // raw level-l backprojection N_l^2
+    size_t vbuf = 0;                       // N^2 prox input
+    size_t total = 0;
+};
+
+Layout make_layout(const imask_geometry& g);
+inline int side(int n, int l) { return n >> l; }
+inline int pstride(int n, int l) { return (n >> l) + kPad; }
+
+// ---- kernels' argument blocks (passed by value) ----
+
+enum { FWD_STORE = 0, FWD_ACCUM = 1, FWD_DUAL = 2 };
+
+struct FwdTerm {
+    const float* img;   // padded rows of the level image
+    const float* imgT;  // padded transposed level image
+    int lvl;
+    float coef;
+};
+
+struct FwdArgs {
+    const RayConst* consts;
+    int n, na, nd;
+    int nterms;
+    FwdTerm term[IMASK_MAX_LEVELS];
+    int mode;
+    float* out;
+    // dual SAGA epilogue
+    const float* y_old;
+    const float* bdat;
+    float* y_new;
+    float* psi;
+    int r, kidx;
+    float p[IMASK_MAX_LEVELS];
+    float sigma, inv1ps;
+};
+
+struct BpArgs {
+    const RayConst* consts;
+    int n, na, nd, lvl;
+    const float* y;
+    float* out;
+    float coef;
+    int accumulate;
+    int prolong;  // 1: write the 2^l x 2^l block of an N x N image
+};
+
+enum { PREP_MEAN = 0, PREP_COMP = 1 };
+
+struct PrepOut {
+    float* dst;
+    float* dstT;  // may be null
+    int lvl;
+    int kind;
+    int padded;
+};
+
+struct PrepArgs {
+    const float* x;
+    int n, T, pyr_levels;
+    int nout;
+    PrepOut out[IMASK_MAX_LEVELS + 1];
+    int ncomp;
+    int comp_lvl[IMASK_MAX_LEVELS];
+    float comp_p[IMASK_MAX_LEVELS];
+    float inv_p0;
+};
+
+struct PrimalArgs {
+    int n, T, pyr_levels;
+    int r, kidx, full_mode;
+    int lvl[IMASK_MAX_LEVELS];
+    float p[IMASK_MAX_LEVELS];
+    const float* craw[IMASK_MAX_LEVELS];
+    float* phi;
+    long long phi_off[IMASK_MAX_LEVELS];
+    const float* x_old;
+    float* x_out;
+    float tau, prox_scale;
+};
+
+struct TvArgs {
+    int n, J;
+    const float* v;
+    const float* u0;
+    float* out;
+    float tau_w, tau_lam, eps, invL;
+    float beta[IMASK_MAX_TV_INNER];
+};
+
+// ---- launchers (return hipError_t of the launch) ----
+hipError_t launch_consts(const imask_geometry& g, const Layout& L, float* work, hipStream_t s);
+hipError_t launch_fill(float* p, size_t count, float value, hipStream_t s);
+hipError_t launch_prep(const PrepArgs& a, hipStream_t s);
+hipError_t launch_fwd(const FwdArgs& a, hipStream_t s);
+hipError_t launch_bp(const BpArgs& a, hipStream_t s);
+hipError_t launch_primal(const PrimalArgs& a, hipStream_t s);
+hipError_t launch_tv(const TvArgs& a, hipStream_t s);
+hipError_t launch_prolong(const float* in, float* out, int n, int lvl, float coef, hipStream_t s);
+hipError_t launch_project_block(const float* in, float* out, int n, int lvl, hipStream_t s);
+
+// pyramid tile side used by prep/primal for a set of levels up to lmax
+int tile_side(int n, int lmax);
+
+}  // namespace imk

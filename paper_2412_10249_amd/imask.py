@@ -1,0 +1,277 @@
+"""PyTorch-facing binding of libimask: tensors in, tensors out.
+
+Each function checks shapes/dtypes, passes raw device pointers and the
+current HIP stream to the C ABI, and raises ImaskError on a nonzero return.
+No arithmetic of the method happens here.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import _abi
+from ._abi import ImaskError, check, lib
+
+
+def _stream() -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: torch.Tensor) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _need(t: torch.Tensor, shape, name: str) -> None:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ImaskError(f"{name} must be a CUDA/HIP tensor")
+    if t.dtype != torch.float32 or not t.is_contiguous():
+        raise ImaskError(f"{name} must be contiguous float32")
+    if tuple(t.shape) != tuple(shape):
+        raise ImaskError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+@dataclass(frozen=True)
+class Geometry:
+    """Parallel-beam geometry: N x N image on [-1,1]^2, n_angles angles
+    a*pi/n_angles, n_det bins (spacing <= 0: full-resolution pixel size)."""
+    n: int
+    n_angles: int
+    n_det: int
+    det_spacing: float = 0.0
+    det_offset: float = 0.0
+
+    def c(self) -> _abi.Geometry:
+        return _abi.Geometry(self.n, self.n_angles, self.n_det, self.det_spacing, self.det_offset)
+
+    @property
+    def sino_shape(self):
+        return (self.n_angles, self.n_det)
+
+    @property
+    def image_shape(self):
+        return (self.n, self.n)
+
+
+@dataclass(frozen=True)
+class Levels:
+    """Resolution set (log2 factors, first 0) and probabilities p."""
+    log2f: tuple
+    p: tuple
+    full_mode: int = _abi.FULL_PAPER
+
+    def c(self) -> _abi.Levels:
+        lv = _abi.Levels()
+        lv.r = len(self.log2f)
+        for k, (l, pk) in enumerate(zip(self.log2f, self.p)):
+            lv.log2f[k] = int(l)
+            lv.p[k] = float(pk)
+        lv.full_mode = int(self.full_mode)
+        return lv
+
+    @property
+    def r(self) -> int:
+        return len(self.log2f)
+
+    @staticmethod
+    def uniform(log2f, full_mode: int = _abi.FULL_PAPER) -> "Levels":
+        r = len(log2f)
+        return Levels(tuple(log2f), tuple([1.0 / r] * r), full_mode)
+
+
+@dataclass(frozen=True)
+class Regularizer:
+    kind: int = _abi.REG_TIKHONOV
+    lam: float = 1e-2
+    tv_weight: float = 0.0
+    tv_eps: float = 1e-3
+    tv_inner: int = 10
+
+    def c(self) -> _abi.Reg:
+        return _abi.Reg(self.kind, self.lam, self.tv_weight, self.tv_eps, self.tv_inner)
+
+
+@dataclass(frozen=True)
+class Params:
+    sigma: float
+    seed: int = 42
+    stream_id: int = 0
+
+    def c(self) -> _abi.Params:
+        return _abi.Params(self.sigma, self.seed, self.stream_id)
+
+
+def workspace(g: Geometry, device="cuda") -> torch.Tensor:
+    nbytes = lib().imask_workspace_bytes(ctypes.byref(g.c()))
+    if nbytes == 0:
+        raise ImaskError("invalid geometry")
+    w = torch.empty(nbytes, dtype=torch.uint8, device=device)
+    check(lib().imask_prepare(ctypes.byref(g.c()), _ptr(w), nbytes, _stream()), "imask_prepare")
+    return w
+
+
+def project(g: Geometry, log2f: int, x: torch.Tensor, work: torch.Tensor, out: torch.Tensor | None = None):
+    """sino = R_l T_l x."""
+    _need(x, g.image_shape, "x")
+    if out is None:
+        out = torch.empty(g.sino_shape, dtype=torch.float32, device=x.device)
+    _need(out, g.sino_shape, "out")
+    check(lib().imask_project(ctypes.byref(g.c()), log2f, _ptr(work), _ptr(x), _ptr(out), _stream()),
+          "imask_project")
+    return out
+
+
+def backproject(g: Geometry, log2f: int, sino: torch.Tensor, work: torch.Tensor, out: torch.Tensor | None = None):
+    """x = T_l^T R_l^T sino (exact transpose of project)."""
+    _need(sino, g.sino_shape, "sino")
+    if out is None:
+        out = torch.empty(g.image_shape, dtype=torch.float32, device=sino.device)
+    _need(out, g.image_shape, "out")
+    check(lib().imask_backproject(ctypes.byref(g.c()), log2f, _ptr(work), _ptr(sino), _ptr(out), _stream()),
+          "imask_backproject")
+    return out
+
+
+def resample(x: torch.Tensor, log2f: int, mode: int, levels: Levels | None = None):
+    n = x.shape[-1]
+    nl = n >> log2f
+    if mode == _abi.RESTRICT:
+        _need(x, (n, n), "x")
+        out_shape = (nl, nl)
+    elif mode in (_abi.PROLONG, _abi.RESTRICT_ADJ):
+        _need(x, (x.shape[0], x.shape[0]), "x")
+        n = x.shape[0] << log2f
+        out_shape = (n, n)
+    else:
+        _need(x, (n, n), "x")
+        out_shape = (n, n)
+    out = torch.empty(out_shape, dtype=torch.float32, device=x.device)
+    lv = ctypes.byref(levels.c()) if levels is not None else None
+    check(lib().imask_resample(n, log2f, mode, lv, _ptr(x), _ptr(out), _stream()), "imask_resample")
+    return out
+
+
+def sketch_apply(g: Geometry, levels: Levels, k: int, inp: torch.Tensor, adjoint: bool, work: torch.Tensor):
+    """K_k inp (adjoint=False) or K_k^T inp (adjoint=True)."""
+    if adjoint:
+        _need(inp, g.sino_shape, "in")
+        out = torch.empty(g.image_shape, dtype=torch.float32, device=inp.device)
+    else:
+        _need(inp, g.image_shape, "in")
+        out = torch.empty(g.sino_shape, dtype=torch.float32, device=inp.device)
+    check(lib().imask_sketch_apply(ctypes.byref(g.c()), ctypes.byref(levels.c()), k, int(adjoint), _ptr(work),
+                                   _ptr(inp), _ptr(out), _stream()), "imask_sketch_apply")
+    return out
+
+
+def draws(params: Params, levels: Levels, k0: int, count: int) -> np.ndarray:
+    out = (ctypes.c_int32 * max(count, 1))()
+    check(lib().imask_draws(ctypes.byref(params.c()), ctypes.byref(levels.c()), k0, count, out), "imask_draws")
+    return np.frombuffer(out, dtype=np.int32, count=count).copy()
+
+
+@dataclass
+class Problem:
+    """Device-resident ImaSk state for one reconstruction (Alg. 1 INPUT)."""
+    geom: Geometry
+    levels: Levels
+    reg: Regularizer
+    params: Params
+    b: torch.Tensor
+    device: str = "cuda"
+    x: list = field(default_factory=list)
+    y: list = field(default_factory=list)
+    phi: torch.Tensor | None = None
+    psi: torch.Tensor | None = None
+    work: torch.Tensor | None = None
+    k: int = 0
+    epochs: float = 0.0
+    cur: int = 0
+
+    def __post_init__(self):
+        g = self.geom
+        _need(self.b, g.sino_shape, "b")
+        dev = self.b.device
+        nphi = lib().imask_phi_floats(ctypes.byref(g.c()), ctypes.byref(self.levels.c()))
+        if nphi == 0:
+            raise ImaskError("invalid geometry or level set")
+        self.x = [torch.zeros(g.image_shape, device=dev) for _ in range(2)]
+        self.y = [torch.zeros(g.sino_shape, device=dev) for _ in range(2)]
+        self.phi = torch.zeros(nphi, device=dev)
+        self.psi = torch.zeros((self.levels.r,) + g.sino_shape, device=dev)
+        self.work = workspace(g, dev)
+
+    # -- C struct round trip
+    def _cstate(self) -> _abi.State:
+        s = _abi.State()
+        s.x[0], s.x[1] = self.x[0].data_ptr(), self.x[1].data_ptr()
+        s.y[0], s.y[1] = self.y[0].data_ptr(), self.y[1].data_ptr()
+        s.phi, s.psi, s.work = self.phi.data_ptr(), self.psi.data_ptr(), self.work.data_ptr()
+        s.k, s.epochs, s.cur = self.k, self.epochs, self.cur
+        return s
+
+    def _absorb(self, s: _abi.State) -> None:
+        self.k, self.epochs, self.cur = int(s.k), float(s.epochs), int(s.cur)
+
+    @property
+    def x_cur(self) -> torch.Tensor:
+        return self.x[self.cur]
+
+    @property
+    def y_cur(self) -> torch.Tensor:
+        return self.y[self.cur]
+
+    def step(self, n_steps: int = 1) -> None:
+        s = self._cstate()
+        bp = (ctypes.c_void_p * 1)(self.b.data_ptr())
+        check(lib().imask_step(1, ctypes.byref(self.geom.c()), ctypes.byref(self.levels.c()),
+                               ctypes.byref(self.reg.c()), ctypes.byref(self.params.c()), bp,
+                               ctypes.byref(s), n_steps, _stream()), "imask_step")
+        self._absorb(s)
+
+    def solve(self, budget: float, kind: int = _abi.BUDGET_ITERS) -> None:
+        s = self._cstate()
+        bp = (ctypes.c_void_p * 1)(self.b.data_ptr())
+        check(lib().imask_solve(1, ctypes.byref(self.geom.c()), ctypes.byref(self.levels.c()),
+                                ctypes.byref(self.reg.c()), ctypes.byref(self.params.c()), bp,
+                                ctypes.byref(s), float(budget), kind, _stream()), "imask_solve")
+        self._absorb(s)
+
+    def phi_tables(self):
+        """The table as a list of images: sketch 0 full size, k > 0 coarse."""
+        out, off = [], 0
+        for l in self.levels.log2f:
+            nl = self.geom.n >> l
+            out.append(self.phi[off:off + nl * nl].view(nl, nl))
+            off += nl * nl
+        return out
+
+    def state_dict(self) -> dict:
+        return {"x": self.x_cur.clone(), "y": self.y_cur.clone(), "phi": self.phi.clone(),
+                "psi": self.psi.clone(), "k": self.k, "epochs": self.epochs}
+
+    def load_state_dict(self, d: dict) -> None:
+        self.cur = 0
+        self.x[0].copy_(d["x"])
+        self.y[0].copy_(d["y"])
+        self.phi.copy_(d["phi"])
+        self.psi.copy_(d["psi"])
+        self.k, self.epochs = int(d["k"]), float(d["epochs"])
+
+
+def step_many(problems: list, n_steps: int = 1) -> None:
+    """One imask_step call advancing several independent problems."""
+    n = len(problems)
+    if n == 0:
+        return
+    G = (_abi.Geometry * n)(*[p.geom.c() for p in problems])
+    L = (_abi.Levels * n)(*[p.levels.c() for p in problems])
+    R = (_abi.Reg * n)(*[p.reg.c() for p in problems])
+    P = (_abi.Params * n)(*[p.params.c() for p in problems])
+    B = (ctypes.c_void_p * n)(*[p.b.data_ptr() for p in problems])
+    S = (_abi.State * n)(*[p._cstate() for p in problems])
+    check(lib().imask_step(n, G, L, R, P, B, S, n_steps, _stream()), "imask_step")
+    for p, s in zip(problems, S):
+        p._absorb(s)

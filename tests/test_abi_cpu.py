@@ -1,0 +1,98 @@
+"""Host-side checks of libimask that need no GPU: the library loads, exports
+every function include/imask.h declares, validates arguments before touching
+the device, and its host sketch draw equals the oracle's bit for bit."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2412_10249_amd import _abi
+from paper_2412_10249_amd import imask as im
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    text = open(os.path.join(ROOT, "include", "imask.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:int|size_t)\s+(imask_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = _abi.lib()
+    names = _header_functions()
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) == set(_abi.EXPORTS)
+
+
+def test_struct_sizes_match_c_layout():
+    assert ctypes.sizeof(_abi.Geometry) == 32
+    assert ctypes.sizeof(_abi.Levels) == 4 + 32 + 4 + 64 + 4 + 4
+    assert ctypes.sizeof(_abi.Params) == 24
+    assert ctypes.sizeof(_abi.State) == 8 * 7 + 8 + 8 + 8
+
+
+def test_workspace_and_table_sizes():
+    g = _abi.Geometry(64, 90, 92, 0.0, 0.0)
+    assert _abi.lib().imask_workspace_bytes(ctypes.byref(g)) > 4 * 64 * 64 * 4
+    lv = im.Levels((0, 1, 2), (1 / 3,) * 3).c()
+    assert _abi.lib().imask_phi_floats(ctypes.byref(g), ctypes.byref(lv)) == 64 * 64 + 32 * 32 + 16 * 16
+
+
+@pytest.mark.parametrize("geom", [(0, 90, 92), (63, 90, 92), (40, 90, 92), (64, 0, 92), (64, 90, -1)])
+def test_invalid_geometry_rejected_before_any_launch(geom):
+    g = _abi.Geometry(*geom, 0.0, 0.0)
+    assert _abi.lib().imask_workspace_bytes(ctypes.byref(g)) == 0
+    rc = _abi.lib().imask_project(ctypes.byref(g), 0, ctypes.c_void_p(16), ctypes.c_void_p(16),
+                                  ctypes.c_void_p(16), None)
+    assert rc == _abi.EINVAL
+
+
+@pytest.mark.parametrize("bad", [
+    ((1, 2), (0.5, 0.5)),          # level 0 missing
+    ((0, 0), (0.5, 0.5)),          # not increasing
+    ((0, 1), (0.6, 0.6)),          # p does not sum to one
+    ((0, 1), (1.0, 0.0)),          # p must be positive
+    ((0, 9), (0.5, 0.5)),          # deeper than the geometry allows
+])
+def test_invalid_level_sets_rejected(bad):
+    g = _abi.Geometry(64, 10, 10, 0.0, 0.0)
+    lv = im.Levels(*bad).c()
+    assert _abi.lib().imask_phi_floats(ctypes.byref(g), ctypes.byref(lv)) == 0
+
+
+def test_invalid_step_arguments_rejected():
+    g = _abi.Geometry(64, 10, 10, 0.0, 0.0)
+    lv = im.Levels((0, 1), (0.5, 0.5)).c()
+    reg = _abi.Reg(_abi.REG_TIKHONOV, 0.01, 0.0, 1e-3, 10)
+    prm = _abi.Params(0.01, 1, 0)
+    s = _abi.State()  # null pointers
+    b = (ctypes.c_void_p * 1)(16)
+    assert _abi.lib().imask_step(1, ctypes.byref(g), ctypes.byref(lv), ctypes.byref(reg), ctypes.byref(prm), b,
+                                 ctypes.byref(s), 1, None) == _abi.EINVAL
+    s.x[0], s.x[1], s.y[0], s.y[1] = 16, 32, 48, 64
+    s.phi, s.psi, s.work = 80, 96, 112
+    bad_reg = _abi.Reg(_abi.REG_TIKHONOV, -1.0, 0.0, 1e-3, 10)
+    assert _abi.lib().imask_step(1, ctypes.byref(g), ctypes.byref(lv), ctypes.byref(bad_reg), ctypes.byref(prm),
+                                 b, ctypes.byref(s), 1, None) == _abi.EINVAL
+    tv = _abi.Reg(_abi.REG_SMOOTH_TV, 0.01, 1.0, 1e-3, 99)
+    assert _abi.lib().imask_step(1, ctypes.byref(g), ctypes.byref(lv), ctypes.byref(tv), ctypes.byref(prm),
+                                 b, ctypes.byref(s), 1, None) == _abi.EINVAL
+    bad_prm = _abi.Params(-0.5, 1, 0)
+    assert _abi.lib().imask_step(1, ctypes.byref(g), ctypes.byref(lv), ctypes.byref(reg), ctypes.byref(bad_prm),
+                                 b, ctypes.byref(s), 1, None) == _abi.EINVAL
+    assert _abi.lib().imask_solve(1, ctypes.byref(g), ctypes.byref(lv), ctypes.byref(reg), ctypes.byref(prm),
+                                  b, ctypes.byref(s), 5.0, 7, None) == _abi.EINVAL
+
+
+@pytest.mark.parametrize("seed,stream,p", [(42, 0, (1 / 3,) * 3), (7, 5, (0.25,) * 4),
+                                           (2 ** 63 + 11, 123, (0.3, 0.3, 0.2, 0.2)), (1, 9, (1.0,))])
+def test_host_draws_match_oracle_bitwise(seed, stream, p):
+    lv = im.Levels(tuple(range(len(p))), p)
+    got = im.draws(im.Params(0.1, seed, stream), lv, 1000, 100_000)
+    exp = oracle.draws(seed, stream, 1000, 100_000, list(p))
+    assert np.array_equal(got, exp)

@@ -42,6 +42,8 @@ Layout make_layout(const imask_geometry& g)
     }
     L.vbuf = off;
     off = align64(off + (size_t)g.n * g.n);
+    L.part = off;
+    off = align64(off + (size_t)4 * g.n * g.n);
     L.total = off;
     return L;
 }
@@ -201,6 +203,7 @@ static int backproject_raw(const Layout& L, const float* W, int lvl, const float
     ba.coef = coef;
     ba.accumulate = accumulate;
     ba.prolong = prolong;
+    ba.part = const_cast<float*>(W) + L.part;
     IMK_TRY(launch_bp(ba, s));
     return IMASK_OK;
 }

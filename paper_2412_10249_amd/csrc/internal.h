@@ -36,6 +36,7 @@ struct Layout {
     size_t zpT[IMASK_MAX_LOG2F + 1] = {};  // padded level-l image, transposed
     size_t craw[IMASK_MAX_LOG2F + 1] = {}; // raw level-l backprojection N_l^2
     size_t vbuf = 0;                       // N^2 prox input
+    size_t part = 0;                       // 4 N^2 per-angle-group partial backprojections
     size_t total = 0;
 };
 
@@ -79,6 +80,9 @@ struct BpArgs {
     float coef;
     int accumulate;
     int prolong;  // 1: write the 2^l x 2^l block of an N x N image
+    float* part;  // G > 1: per-angle-group partial sums, G * N_l^2 floats
+    int G;        // angle groups (grid z); partials are summed in group order
+    int apg;      // angles per group
 };
 
 enum { PREP_MEAN = 0, PREP_COMP = 1 };

@@ -11,6 +11,7 @@
 // launch on LDS-resident overlapped tiles (k_tv).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "internal.h"
@@ -186,7 +187,29 @@ __global__ void __launch_bounds__(256) k_fwd(FwdArgs a)
         if (lo <= hi) {
             long long u = kc.cfx + (long long)b * kc.bfx + (long long)lo * kc.afx;
             const float* row = img + (size_t)lo * P + kPadL;
-            for (int i = lo; i <= hi; ++i) {
+            int i = lo;
+            // four steps per trip: all eight taps are loaded before use
+            for (; i + 3 <= hi; i += 4) {
+                const long long u1 = u + kc.afx, u2 = u1 + kc.afx, u3 = u2 + kc.afx;
+                const float* p0 = row + tap_index(u);
+                const float* p1 = row + P + tap_index(u1);
+                const float* p2 = row + 2 * P + tap_index(u2);
+                const float* p3 = row + 3 * P + tap_index(u3);
+                const float a0 = p0[0], b0 = p0[1], a1 = p1[0], b1 = p1[1];
+                const float a2 = p2[0], b2 = p2[1], a3 = p3[0], b3 = p3[1];
+                const float w0 = tap_weight(u), w1 = tap_weight(u1), w2 = tap_weight(u2), w3 = tap_weight(u3);
+                acc = fmaf(1.0f - w0, a0, acc);
+                acc = fmaf(w0, b0, acc);
+                acc = fmaf(1.0f - w1, a1, acc);
+                acc = fmaf(w1, b1, acc);
+                acc = fmaf(1.0f - w2, a2, acc);
+                acc = fmaf(w2, b2, acc);
+                acc = fmaf(1.0f - w3, a3, acc);
+                acc = fmaf(w3, b3, acc);
+                u = u3 + kc.afx;
+                row += 4 * P;
+            }
+            for (; i <= hi; ++i) {
                 const float* px = row + tap_index(u);
                 const float w = tap_weight(u);
                 acc = fmaf(1.0f - w, px[0], acc);
@@ -219,16 +242,36 @@ __global__ void __launch_bounds__(256) k_fwd(FwdArgs a)
 // touch this pixel form a short interval; each candidate recomputes the
 // forward's tap (j0, w) and keeps (1-w) if j0 is this pixel, w if it is the
 // left neighbour.  No atomics: the result is deterministic.
+__device__ __forceinline__ void bp_store(const BpArgs& a, int nl, int I, int J, float total)
+{
+    const float v = a.coef * total;
+    if (!a.prolong) {
+        float* o = a.out + (size_t)I * nl + J;
+        *o = a.accumulate ? *o + v : v;
+    } else {
+        const int f = 1 << a.lvl;
+        for (int di = 0; di < f; ++di) {
+            float* o = a.out + (size_t)(I * f + di) * a.n + (size_t)J * f;
+            for (int dj = 0; dj < f; ++dj) o[dj] = a.accumulate ? o[dj] + v : v;
+        }
+    }
+}
+
+// Workgroup = 16 x 16 level-l pixels x one group of angles (grid z), so the
+// coarse levels, with few pixels, still fill the chip.
 __global__ void __launch_bounds__(256) k_bp(BpArgs a)
 {
     const int nl = a.n >> a.lvl;
     const int J = blockIdx.x * 16 + (threadIdx.x & 15);
     const int I = blockIdx.y * 16 + (threadIdx.x >> 4);
     if (I >= nl || J >= nl) return;
+    const int g = blockIdx.z;
+    const int a0 = g * a.apg;
+    const int a1 = min(a.na, a0 + a.apg);
     const float bmax = (float)(a.nd - 1);
     float total = 0.0f;
     const RayConst* kbase = a.consts + (size_t)a.lvl * a.na;
-    for (int ang = 0; ang < a.na; ++ang) {
+    for (int ang = a0; ang < a1; ++ang) {
         const RayConst& kc = kbase[ang];
         const bool rows = row_stepping(ang, a.na);
         const int s = rows ? I : J;  // step index of the samples touching this pixel
@@ -254,17 +297,22 @@ __global__ void __launch_bounds__(256) k_bp(BpArgs a)
         }
         total = fmaf(kc.w, acc, total);
     }
-    const float v = a.coef * total;
-    if (!a.prolong) {
-        float* o = a.out + (size_t)I * nl + J;
-        *o = a.accumulate ? *o + v : v;
-    } else {
-        const int f = 1 << a.lvl;
-        for (int di = 0; di < f; ++di) {
-            float* o = a.out + (size_t)(I * f + di) * a.n + (size_t)J * f;
-            for (int dj = 0; dj < f; ++dj) o[dj] = a.accumulate ? o[dj] + v : v;
-        }
-    }
+    if (a.G == 1)
+        bp_store(a, nl, I, J, total);
+    else
+        a.part[(size_t)g * nl * nl + (size_t)I * nl + J] = total;
+}
+
+// Sums the angle-group partials in group order (deterministic) and stores.
+__global__ void __launch_bounds__(256) k_bp_reduce(BpArgs a)
+{
+    const int nl = a.n >> a.lvl;
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nl * nl) return;
+    const size_t d = (size_t)nl * nl;
+    float t = 0.0f;
+    for (int g = 0; g < a.G; ++g) t += a.part[g * d + q];
+    bp_store(a, nl, q / nl, q % nl, t);
 }
 
 // ------------------------------------------------------------ primal step
@@ -496,11 +544,22 @@ hipError_t launch_fwd(const FwdArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_bp(const BpArgs& a, hipStream_t s)
+hipError_t launch_bp(const BpArgs& a0, hipStream_t s)
 {
+    BpArgs a = a0;
     const int nl = a.n >> a.lvl;
     const int t = (nl + 15) / 16;
-    hipLaunchKernelGGL(k_bp, dim3(t, t), dim3(256), 0, s, a);
+    // enough angle groups for ~1024 workgroups, within the 4 N^2 partial buffer
+    const int gmax = std::min(a.na, 4 << (2 * a.lvl));
+    int G = std::max(1, std::min(gmax, (1024 + t * t - 1) / (t * t)));
+    a.apg = (a.na + G - 1) / G;
+    a.G = (a.na + a.apg - 1) / a.apg;
+    hipLaunchKernelGGL(k_bp, dim3(t, t, a.G), dim3(256), 0, s, a);
+    if (a.G > 1) {
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_bp_reduce, dim3((nl * nl + 255) / 256), dim3(256), 0, s, a);
+    }
     return hipGetLastError();
 }
 

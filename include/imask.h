@@ -63,8 +63,8 @@ enum { IMASK_BUDGET_ITERS = 0, IMASK_BUDGET_EPOCHS = 1 };
 /* Acquisition geometry (Sec. 4.1: parallel beam, m = n_angles * n_det). */
 typedef struct {
     int32_t n;          /* full-resolution image side N (>= 4, multiple of 4) */
-    int32_t n_angles;   /* >= 1 */
-    int32_t n_det;      /* >= 1 */
+    int32_t n_angles;   /* 1 .. 65536 */
+    int32_t n_det;      /* 1 .. 8192 */
     double det_spacing; /* bin spacing; <= 0 selects the full-res pixel size 2/N */
     double det_offset;  /* detector centre offset s0 */
 } imask_geometry;

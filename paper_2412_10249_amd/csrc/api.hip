@@ -43,7 +43,15 @@ Layout make_layout(const imask_geometry& g)
     L.vbuf = off;
     off = align64(off + (size_t)g.n * g.n);
     L.part = off;
-    off = align64(off + (size_t)4 * g.n * g.n);
+    off = align64(off + (size_t)8 * g.n * g.n);
+    L.ptmp = off;
+    off = align64(off + (size_t)g.n * g.n);
+    const size_t m = (size_t)g.n_angles * g.n_det;
+    for (int l = 0; l <= L.lmax; ++l) {
+        fwd_bands(side(g.n, l), &L.fbands[l], &L.frows[l]);
+        L.fpart[l] = off;
+        off = align64(off + (size_t)L.fbands[l] * m);
+    }
     L.total = off;
     return L;
 }
@@ -55,7 +63,7 @@ static bool geometry_ok(const imask_geometry* g)
     if (!g) return false;
     if (g->n < 4 || g->n > 16384 || (g->n % 4) != 0) return false;
     if (g->n > 16 && (g->n % 16) != 0) return false;
-    if (g->n_angles < 1 || g->n_det < 1 || g->n_angles > (1 << 20) || g->n_det > (1 << 20)) return false;
+    if (g->n_angles < 1 || g->n_det < 1 || g->n_angles > 65536 || g->n_det > 8192) return false;
     if (!std::isfinite(g->det_spacing) || !std::isfinite(g->det_offset)) return false;
     return true;
 }
@@ -154,7 +162,7 @@ static void forward_plan(const Layout& L, const imask_levels& lv, int k, const f
         pa.out[0] = PrepOut{W + L.zp[l], W + L.zpT[l], l, PREP_MEAN, 1};
         pa.nout = 1;
         pa.pyr_levels = l;
-        fa.term[0] = FwdTerm{W + L.zp[l], W + L.zpT[l], l, 1.0f};
+        fa.term[0] = FwdTerm{W + L.zp[l], W + L.zpT[l], l, 1.0f, W + L.fpart[l], L.fbands[l], L.frows[l]};
         fa.nterms = 1;
     } else if (lv.r == 1 || lv.full_mode == IMASK_FULL_PAPER) {
         pa.out[0] = PrepOut{W + L.zp[0], W + L.zpT[0], 0, lv.r > 1 ? PREP_COMP : PREP_MEAN, 1};
@@ -166,7 +174,7 @@ static void forward_plan(const Layout& L, const imask_levels& lv, int k, const f
             pa.comp_p[j - 1] = (float)lv.p[j];
         }
         pa.inv_p0 = (float)(1.0 / lv.p[0]);
-        fa.term[0] = FwdTerm{W + L.zp[0], W + L.zpT[0], 0, 1.0f};
+        fa.term[0] = FwdTerm{W + L.zp[0], W + L.zpT[0], 0, 1.0f, W + L.fpart[0], L.fbands[0], L.frows[0]};
         fa.nterms = 1;
     } else {
         pa.nout = lv.r;
@@ -175,7 +183,7 @@ static void forward_plan(const Layout& L, const imask_levels& lv, int k, const f
             const int l = lv.log2f[j];
             pa.out[j] = PrepOut{W + L.zp[l], W + L.zpT[l], l, PREP_MEAN, 1};
             const float coef = (float)(j == 0 ? 1.0 / lv.p[0] : -lv.p[j] / lv.p[0]);
-            fa.term[j] = FwdTerm{W + L.zp[l], W + L.zpT[l], l, coef};
+            fa.term[j] = FwdTerm{W + L.zp[l], W + L.zpT[l], l, coef, W + L.fpart[l], L.fbands[l], L.frows[l]};
         }
         fa.nterms = lv.r;
     }
@@ -204,6 +212,7 @@ static int backproject_raw(const Layout& L, const float* W, int lvl, const float
     ba.accumulate = accumulate;
     ba.prolong = prolong;
     ba.part = const_cast<float*>(W) + L.part;
+    ba.tmp = const_cast<float*>(W) + L.ptmp;
     IMK_TRY(launch_bp(ba, s));
     return IMASK_OK;
 }
@@ -361,7 +370,8 @@ int imask_project(const imask_geometry* g, int32_t log2f, const void* work, cons
     FwdArgs fa{};
     fwd_common(L, W, fa);
     fa.nterms = 1;
-    fa.term[0] = FwdTerm{W + L.zp[log2f], W + L.zpT[log2f], log2f, 1.0f};
+    fa.term[0] = FwdTerm{W + L.zp[log2f], W + L.zpT[log2f], log2f, 1.0f, W + L.fpart[log2f], L.fbands[log2f],
+                         L.frows[log2f]};
     fa.mode = FWD_STORE;
     fa.out = sino;
     IMK_TRY(launch_prep(pa, s));

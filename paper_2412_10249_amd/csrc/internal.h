@@ -19,7 +19,9 @@ namespace imk {
 // every weight bit for bit.  The float fields mirror it for range estimates;
 // w is the step length h_l/|cos| (or h_l/|sin|), ib = 1/b.
 struct RayConst {
-    long long afx, bfx, cfx, pad;
+    long long afx, bfx, cfx;
+    int phases;  // ceil(2^32/|bfx|): rays this far apart never share a tap
+    int pad;
     float a, b, c, w, ib, r0, r1, r2;
 };
 static_assert(sizeof(RayConst) == 64, "RayConst is 64 bytes");
@@ -36,13 +38,34 @@ struct Layout {
     size_t zpT[IMASK_MAX_LOG2F + 1] = {};  // padded level-l image, transposed
     size_t craw[IMASK_MAX_LOG2F + 1] = {}; // raw level-l backprojection N_l^2
     size_t vbuf = 0;                       // N^2 prox input
-    size_t part = 0;                       // 4 N^2 per-angle-group partial backprojections
+    size_t part = 0;                       // 8 N^2 per-angle-group partial backprojections
+    size_t ptmp = 0;                       // N^2 coarse result before prolongation
+    size_t fpart[IMASK_MAX_LOG2F + 1] = {};// per-band partial projections, fwd_bands(l) * m
+    int fbands[IMASK_MAX_LOG2F + 1] = {};  // row bands of the level-l forward
+    int frows[IMASK_MAX_LOG2F + 1] = {};   // rows per band (0: direct kernel, one band)
     size_t total = 0;
 };
 
 Layout make_layout(const imask_geometry& g);
 inline int side(int n, int l) { return n >> l; }
 inline int pstride(int n, int l) { return (n >> l) + kPad; }
+
+// Angle lists of the two stepping directions: row-stepping angles are
+// 0..n_lo-1 and a_hi0..na-1, column-stepping angles n_lo..a_hi0-1.
+struct AngleSplit {
+    int n_lo, a_hi0, nrow, ncol;
+};
+inline AngleSplit angle_split(int na)
+{
+    AngleSplit s;
+    s.n_lo = na / 4 + 1;
+    s.a_hi0 = (3 * na + 3) / 4;
+    if (s.n_lo > na) s.n_lo = na;
+    if (s.a_hi0 < s.n_lo) s.a_hi0 = s.n_lo;
+    s.nrow = s.n_lo + (na - s.a_hi0);
+    s.ncol = s.a_hi0 - s.n_lo;
+    return s;
+}
 
 // ---- kernels' argument blocks (passed by value) ----
 
@@ -53,6 +76,8 @@ struct FwdTerm {
     const float* imgT;  // padded transposed level image
     int lvl;
     float coef;
+    float* part;        // this level's per-band partial projections
+    int bands, rows;    // band layout (rows == 0: one band, direct kernel)
 };
 
 struct FwdArgs {
@@ -72,6 +97,29 @@ struct FwdArgs {
     float sigma, inv1ps;
 };
 
+struct FwdBandArgs {
+    const RayConst* consts;
+    int n, na, nd, lvl;
+    const float* img;
+    const float* imgT;
+    float* part;
+    int R, bands, apg, groups_row, groups_col;
+    AngleSplit split;
+};
+
+struct BpOwnArgs {
+    const RayConst* consts;
+    int n, na, nd, lvl;
+    const float* y;
+    float* part;  // [2 passes][G][N_l][N_l]; the column pass is stored transposed
+    int G;
+    int batch;  // angles whose sinogram rows are staged in LDS together
+    AngleSplit split;
+    float* out;
+    float coef;
+    int accumulate, prolong;
+};
+
 struct BpArgs {
     const RayConst* consts;
     int n, na, nd, lvl;
@@ -80,9 +128,8 @@ struct BpArgs {
     float coef;
     int accumulate;
     int prolong;  // 1: write the 2^l x 2^l block of an N x N image
-    float* part;  // G > 1: per-angle-group partial sums, G * N_l^2 floats
-    int G;        // angle groups (grid z); partials are summed in group order
-    int apg;      // angles per group
+    float* part;  // per-angle-group partial sums (8 N^2 floats of workspace)
+    float* tmp;   // N_l^2 scratch for the prolonged store
 };
 
 enum { PREP_MEAN = 0, PREP_COMP = 1 };
@@ -127,6 +174,10 @@ struct TvArgs {
     float tau_w, tau_lam, eps, invL;
     float beta[IMASK_MAX_TV_INNER];
 };
+
+// Forward band layout of a level with nl pixels per side (LDS-resident
+// bands of rows); rows == 0 selects the direct (global-memory) kernel.
+void fwd_bands(int nl, int* bands, int* rows);
 
 // ---- launchers (return hipError_t of the launch) ----
 hipError_t launch_consts(const imask_geometry& g, const Layout& L, float* work, hipStream_t s);

@@ -58,6 +58,8 @@ __global__ void k_consts(int n, int na, int nd, double ds, double s0, int lmax, 
     r.afx = __double2ll_rn(A * scale);
     r.bfx = __double2ll_rn(B * scale);
     r.cfx = __double2ll_rn(C0 * scale);
+    const long long ab = r.bfx < 0 ? -r.bfx : r.bfx;
+    r.phases = (int)((4294967296LL + ab - 1) / ab);
     r.pad = 0;
     r.a = (float)A;
     r.b = (float)B;
@@ -147,9 +149,117 @@ __global__ void __launch_bounds__(256) k_prep(PrepArgs a)
 
 // ---------------------------------------------------------- Joseph forward
 
-// One thread per ray; each wavefront covers 64 consecutive bins of one
-// angle, so the angle's constants are wavefront-uniform (scalar loads).
-__global__ void __launch_bounds__(256) k_fwd(FwdArgs a)
+__device__ __forceinline__ int angle_of(const AngleSplit& sp, int pass, int k)
+{
+    return pass == 0 ? (k < sp.n_lo ? k : sp.a_hi0 + (k - sp.n_lo)) : sp.n_lo + k;
+}
+
+// Steps lo..hi (clamped to [s0, s1]) at which ray b's coordinate can reach
+// [-1, nl]: a 0.01-pixel margin covers the float estimate, the zero padding
+// of the image rows covers the rest.
+__device__ __forceinline__ void ray_steps(const RayConst& kc, float fb, int nl, int s0, int s1, int& lo, int& hi)
+{
+    const float fnl = (float)nl;
+    const float tf = fmaf(fb, kc.b, kc.c);  // ~coordinate at step 0
+    lo = s0;
+    hi = s1;
+    if (kc.a != 0.0f) {
+        const float t1 = (-1.01f - tf) / kc.a, t2 = (fnl + 0.01f - tf) / kc.a;
+        lo = (int)fminf(fmaxf(ceilf(fminf(t1, t2)), (float)s0), (float)(s1 + 1));
+        hi = (int)fmaxf(fminf(floorf(fmaxf(t1, t2)), (float)s1), (float)(s0 - 1));
+    } else if (tf < -1.01f || tf > fnl + 0.01f) {
+        lo = s0 + 1;
+        hi = s0;
+    }
+}
+
+// Sum over steps lo..hi of the interpolated row values; rows are P floats
+// apart starting at `row` (already offset by kPadL).
+__device__ __forceinline__ float joseph_sum(const float* row, int P, long long u, long long du, int n)
+{
+    float acc = 0.0f;
+    int i = 0;
+    for (; i + 4 <= n; i += 4) {  // all eight taps are loaded before use
+        const long long u1 = u + du, u2 = u1 + du, u3 = u2 + du;
+        const float* p0 = row + tap_index(u);
+        const float* p1 = row + P + tap_index(u1);
+        const float* p2 = row + 2 * P + tap_index(u2);
+        const float* p3 = row + 3 * P + tap_index(u3);
+        const float a0 = p0[0], b0 = p0[1], a1 = p1[0], b1 = p1[1];
+        const float a2 = p2[0], b2 = p2[1], a3 = p3[0], b3 = p3[1];
+        const float w0 = tap_weight(u), w1 = tap_weight(u1), w2 = tap_weight(u2), w3 = tap_weight(u3);
+        acc = fmaf(1.0f - w0, a0, acc);
+        acc = fmaf(w0, b0, acc);
+        acc = fmaf(1.0f - w1, a1, acc);
+        acc = fmaf(w1, b1, acc);
+        acc = fmaf(1.0f - w2, a2, acc);
+        acc = fmaf(w2, b2, acc);
+        acc = fmaf(1.0f - w3, a3, acc);
+        acc = fmaf(w3, b3, acc);
+        u = u3 + du;
+        row += 4 * P;
+    }
+    for (; i < n; ++i) {
+        const float* px = row + tap_index(u);
+        const float w = tap_weight(u);
+        acc = fmaf(1.0f - w, px[0], acc);
+        acc = fmaf(w, px[1], acc);
+        u += du;
+        row += P;
+    }
+    return acc;
+}
+
+// LDS-band forward: the workgroup copies rows [i0, i0+R) of the padded level
+// image (columns of it for column-stepping angles) into LDS and sums, for
+// every ray of its angle group, the samples falling in the band.  The ray's
+// partial sum goes to part[band][a][b]; k_fwd_reduce adds the bands in order.
+__global__ void __launch_bounds__(1024) k_fwd_band(FwdBandArgs a)
+{
+    extern __shared__ float band[];
+    const int nl = a.n >> a.lvl;
+    const int P = nl + kPad;
+    const int bi = blockIdx.x % a.bands;
+    const int gidx = blockIdx.x / a.bands;
+    const int pass = gidx < a.groups_row ? 0 : 1;
+    const int g = pass == 0 ? gidx : gidx - a.groups_row;
+    const int npass = pass == 0 ? a.split.nrow : a.split.ncol;
+    const int k0 = g * a.apg;
+    const int nang = min(a.apg, npass - k0);
+    const int i0 = bi * a.R;
+    const int i1 = min(nl, i0 + a.R);
+    {
+        const float* src = (pass == 0 ? a.img : a.imgT) + (size_t)i0 * P;
+        const int cnt = (i1 - i0) * P;
+        if ((P & 3) == 0) {  // rows start 16-byte aligned
+            const float4* s4 = (const float4*)src;
+            float4* d4 = (float4*)band;
+            for (int q = threadIdx.x; q < cnt / 4; q += blockDim.x) d4[q] = s4[q];
+        } else {
+            for (int q = threadIdx.x; q < cnt; q += blockDim.x) band[q] = src[q];
+        }
+    }
+    __syncthreads();
+    const size_t m = (size_t)a.na * a.nd;
+    for (int it = threadIdx.x; it < nang * a.nd; it += blockDim.x) {
+        const int kk = it / a.nd;
+        const int b = it - kk * a.nd;
+        const int ang = angle_of(a.split, pass, k0 + kk);
+        const RayConst& kc = a.consts[(size_t)a.lvl * a.na + ang];
+        int lo, hi;
+        ray_steps(kc, (float)b, nl, i0, i1 - 1, lo, hi);
+        float acc = 0.0f;
+        if (lo <= hi) {
+            const long long u = kc.cfx + (long long)b * kc.bfx + (long long)lo * kc.afx;
+            acc = joseph_sum(band + (size_t)(lo - i0) * P + kPadL, P, u, kc.afx, hi - lo + 1);
+        }
+        a.part[(size_t)bi * m + (size_t)ang * a.nd + b] = kc.w * acc;
+    }
+}
+
+// Direct forward for levels too large for LDS bands: one thread per ray
+// reading the padded image from global memory; writes a single band.
+__global__ void __launch_bounds__(256) k_fwd_direct(FwdBandArgs a)
 {
     const int lane = threadIdx.x & 63;
     const int wpa = (a.nd + 63) >> 6;
@@ -157,162 +267,211 @@ __global__ void __launch_bounds__(256) k_fwd(FwdArgs a)
     const int ang = __builtin_amdgcn_readfirstlane(wave / wpa);
     if (ang >= a.na) return;
     const int b = (wave - ang * wpa) * 64 + lane;
-    const bool active = b < a.nd;
-    const bool rows = row_stepping(ang, a.na);
-    const float fb = (float)b;
-    float total = 0.0f;
-    for (int q = 0; q < a.nterms; ++q) {
-        const FwdTerm& t = a.term[q];
-        const int nl = a.n >> t.lvl;
-        const int P = nl + kPad;
-        const RayConst& kc = a.consts[(size_t)t.lvl * a.na + ang];
-        const float* img = rows ? t.img : t.imgT;
-        const float fnl = (float)nl;
-        const float tf = fmaf(fb, kc.b, kc.c);  // ~u at step 0
-        // steps whose coordinate can reach [-1, nl]: a 0.01-pixel margin
-        // covers the float estimate; the zero padding covers the rest
-        int lo = 0, hi = nl - 1;
-        if (!active) {
-            lo = 1;
-            hi = 0;
-        } else if (kc.a != 0.0f) {
-            const float s1 = (-1.01f - tf) / kc.a, s2 = (fnl + 0.01f - tf) / kc.a;
-            lo = (int)fminf(fmaxf(ceilf(fminf(s1, s2)), 0.0f), fnl);
-            hi = (int)fmaxf(fminf(floorf(fmaxf(s1, s2)), fnl - 1.0f), -1.0f);
-        } else if (tf < -1.01f || tf > fnl + 0.01f) {
-            lo = 1;
-            hi = 0;
-        }
-        float acc = 0.0f;
-        if (lo <= hi) {
-            long long u = kc.cfx + (long long)b * kc.bfx + (long long)lo * kc.afx;
-            const float* row = img + (size_t)lo * P + kPadL;
-            int i = lo;
-            // four steps per trip: all eight taps are loaded before use
-            for (; i + 3 <= hi; i += 4) {
-                const long long u1 = u + kc.afx, u2 = u1 + kc.afx, u3 = u2 + kc.afx;
-                const float* p0 = row + tap_index(u);
-                const float* p1 = row + P + tap_index(u1);
-                const float* p2 = row + 2 * P + tap_index(u2);
-                const float* p3 = row + 3 * P + tap_index(u3);
-                const float a0 = p0[0], b0 = p0[1], a1 = p1[0], b1 = p1[1];
-                const float a2 = p2[0], b2 = p2[1], a3 = p3[0], b3 = p3[1];
-                const float w0 = tap_weight(u), w1 = tap_weight(u1), w2 = tap_weight(u2), w3 = tap_weight(u3);
-                acc = fmaf(1.0f - w0, a0, acc);
-                acc = fmaf(w0, b0, acc);
-                acc = fmaf(1.0f - w1, a1, acc);
-                acc = fmaf(w1, b1, acc);
-                acc = fmaf(1.0f - w2, a2, acc);
-                acc = fmaf(w2, b2, acc);
-                acc = fmaf(1.0f - w3, a3, acc);
-                acc = fmaf(w3, b3, acc);
-                u = u3 + kc.afx;
-                row += 4 * P;
-            }
-            for (; i <= hi; ++i) {
-                const float* px = row + tap_index(u);
-                const float w = tap_weight(u);
-                acc = fmaf(1.0f - w, px[0], acc);
-                acc = fmaf(w, px[1], acc);
-                u += kc.afx;
-                row += P;
-            }
-        }
-        total = fmaf(t.coef, kc.w * acc, total);
+    if (b >= a.nd) return;
+    const int nl = a.n >> a.lvl;
+    const int P = nl + kPad;
+    const RayConst& kc = a.consts[(size_t)a.lvl * a.na + ang];
+    const float* img = row_stepping(ang, a.na) ? a.img : a.imgT;
+    int lo, hi;
+    ray_steps(kc, (float)b, nl, 0, nl - 1, lo, hi);
+    float acc = 0.0f;
+    if (lo <= hi) {
+        const long long u = kc.cfx + (long long)b * kc.bfx + (long long)lo * kc.afx;
+        acc = joseph_sum(img + (size_t)lo * P + kPadL, P, u, kc.afx, hi - lo + 1);
     }
-    if (!active) return;
-    const size_t e = (size_t)ang * a.nd + b;
-    if (a.mode == FWD_STORE) {
-        a.out[e] = total;
-    } else if (a.mode == FWD_ACCUM) {
-        a.out[e] += total;
-    } else {
-        const size_t m = (size_t)a.na * a.nd;
-        float avg = 0.0f;
-        for (int j = 0; j < a.r; ++j) avg = fmaf(a.p[j], a.psi[(size_t)j * m + e], avg);
-        const float zeta = (total - a.psi[(size_t)a.kidx * m + e]) + avg;
-        a.y_new[e] = (a.y_old[e] + a.sigma * zeta - a.sigma * a.bdat[e]) * a.inv1ps;
-        a.psi[(size_t)a.kidx * m + e] = total;
-    }
+    a.part[(size_t)ang * a.nd + b] = kc.w * acc;
 }
 
-// ------------------------------------------------------ gather transpose
-
-// One thread per level-l pixel.  For every angle, the bins whose samples
-// touch this pixel form a short interval; each candidate recomputes the
-// forward's tap (j0, w) and keeps (1-w) if j0 is this pixel, w if it is the
-// left neighbour.  No atomics: the result is deterministic.
-__device__ __forceinline__ void bp_store(const BpArgs& a, int nl, int I, int J, float total)
+// Adds the band partials of every term (in band order), then stores,
+// accumulates, or applies the dual SAGA step of Alg. 1:
+// zeta = psi_new - psi_k + sum_j p_j psi_j (old tables),
+// y+ = (y + sigma zeta - sigma b)/(1 + sigma), psi_k <- psi_new.
+__global__ void __launch_bounds__(256) k_fwd_reduce(FwdArgs a)
 {
-    const float v = a.coef * total;
-    if (!a.prolong) {
-        float* o = a.out + (size_t)I * nl + J;
-        *o = a.accumulate ? *o + v : v;
-    } else {
-        const int f = 1 << a.lvl;
-        for (int di = 0; di < f; ++di) {
-            float* o = a.out + (size_t)(I * f + di) * a.n + (size_t)J * f;
-            for (int dj = 0; dj < f; ++dj) o[dj] = a.accumulate ? o[dj] + v : v;
+    const size_t m = (size_t)a.na * a.nd;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (size_t)gridDim.x * blockDim.x) {
+        float total = 0.0f;
+        for (int t = 0; t < a.nterms; ++t) {
+            const float* pp = a.term[t].part + e;
+            float sum = 0.0f;
+            for (int bnd = 0; bnd < a.term[t].bands; ++bnd) sum += pp[(size_t)bnd * m];
+            total = fmaf(a.term[t].coef, sum, total);
+        }
+        if (a.mode == FWD_STORE) {
+            a.out[e] = total;
+        } else if (a.mode == FWD_ACCUM) {
+            a.out[e] += total;
+        } else {
+            float avg = 0.0f;
+            for (int j = 0; j < a.r; ++j) avg = fmaf(a.p[j], a.psi[(size_t)j * m + e], avg);
+            const float zeta = (total - a.psi[(size_t)a.kidx * m + e]) + avg;
+            a.y_new[e] = (a.y_old[e] + a.sigma * zeta - a.sigma * a.bdat[e]) * a.inv1ps;
+            a.psi[(size_t)a.kidx * m + e] = total;
         }
     }
 }
 
-// Workgroup = 16 x 16 level-l pixels x one group of angles (grid z), so the
-// coarse levels, with few pixels, still fill the chip.
-__global__ void __launch_bounds__(256) k_bp(BpArgs a)
+// ------------------------------------------------------ exact transpose
+
+// Ray-driven transpose with exclusive ownership: every wavefront owns two
+// level-l image rows (columns, for column-stepping angles) as LDS
+// accumulators and scatters into them the two taps of every sample of its
+// angle group.  Within one instruction the lanes' rays are `phases` bins
+// apart, so their coordinates differ by at least a pixel and no two lanes
+// touch the same pixel; each pixel therefore receives its contributions in
+// program order and the result is deterministic.  The weights come from the
+// same fixed-point coordinate as the forward: the pair is an exact transpose.
+// The sinogram values of a batch of angles are staged in LDS first.
+constexpr int kBpPad = 8;
+constexpr int kBpRowsPerWave = 2;
+constexpr int kBpWaves = 4;
+constexpr int kBpRowsPerWg = kBpRowsPerWave * kBpWaves;
+
+// Bins whose coordinate at steps r0 .. r0+nr-1 can reach [-1, nl].
+__device__ __forceinline__ void bin_range(const RayConst& kc, int r0, int nrows, int nl, int nd, int& blo, int& cnt)
+{
+    const float fnl = (float)nl, bmax = (float)(nd - 1);
+    const float base0 = fmaf((float)r0, kc.a, kc.c);
+    const float base1 = base0 + (float)(nrows - 1) * kc.a;
+    const float e0 = (-1.01f - base0) * kc.ib, e1 = (fnl + 0.01f - base0) * kc.ib;
+    const float e2 = (-1.01f - base1) * kc.ib, e3 = (fnl + 0.01f - base1) * kc.ib;
+    blo = (int)fminf(fmaxf(ceilf(fminf(fminf(e0, e1), fminf(e2, e3))), 0.0f), bmax + 1.0f);
+    const int bhi = (int)fmaxf(fminf(floorf(fmaxf(fmaxf(e0, e1), fmaxf(e2, e3))), bmax), -1.0f);
+    cnt = bhi - blo + 1;
+}
+
+// Compiler-only ordering point: LDS operations of one wavefront execute in
+// program order, so this is all that is needed between the two phases.
+#define IMK_LDS_ORDER() asm volatile("" ::: "memory")
+
+__global__ void __launch_bounds__(256) k_bp_own(BpOwnArgs a)
+{
+    extern __shared__ float smem[];
+    const int nl = a.n >> a.lvl;
+    const int S = nl + 2 * kBpPad;
+    float* acc = smem;                                   // kBpRowsPerWg x S
+    float* dummy = smem + kBpRowsPerWg * S;              // two cells per lane
+    float* ybuf = dummy + kBpWaves * 128;                // a.batch x nd (W-scaled sinogram values)
+    const int nb = (nl + kBpRowsPerWg - 1) / kBpRowsPerWg;
+    const int bi = blockIdx.x % nb;
+    const int gidx = blockIdx.x / nb;
+    const int pass = gidx / a.G;
+    const int g = gidx - pass * a.G;
+    const int npass = pass == 0 ? a.split.nrow : a.split.ncol;
+    const int apg = (npass + a.G - 1) / a.G;
+    const int k0 = g * apg;
+    const int nang = max(0, min(apg, npass - k0));
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int rwg = bi * kBpRowsPerWg;                 // first row of the workgroup
+    const int nwg = min(kBpRowsPerWg, nl - rwg);
+    const int r0 = rwg + wave * kBpRowsPerWave;        // first row of this wavefront
+    const int nown = max(0, min(kBpRowsPerWave, nl - r0));
+    float* rows = acc + (size_t)wave * kBpRowsPerWave * S;
+    float* mine = dummy + wave * 128 + 2 * lane;       // private sink (2 cells) for idle lanes
+    for (int q = lane; q < kBpRowsPerWave * S; q += 64) rows[q] = 0.0f;
+    for (int kb = 0; kb < nang; kb += a.batch) {
+        const int nbat = min(a.batch, nang - kb);
+        __syncthreads();  // the previous batch's values are consumed
+        for (int t = 0; t < nbat; ++t) {
+            const int ang = angle_of(a.split, pass, k0 + kb + t);
+            const RayConst& kc = a.consts[(size_t)a.lvl * a.na + ang];
+            int blo, cnt;
+            bin_range(kc, rwg, nwg, nl, a.nd, blo, cnt);
+            const float* yr = a.y + (size_t)ang * a.nd + blo;
+            for (int q = threadIdx.x; q < cnt; q += blockDim.x) ybuf[t * a.nd + q] = kc.w * yr[q];
+        }
+        __syncthreads();
+        if (nown == 0) continue;
+        for (int t = 0; t < nbat; ++t) {
+            const int ang = angle_of(a.split, pass, k0 + kb + t);
+            const RayConst& kc = a.consts[(size_t)a.lvl * a.na + ang];
+            int blo, cnt;
+            bin_range(kc, rwg, nwg, nl, a.nd, blo, cnt);
+            if (cnt <= 0) continue;
+            const int P = kc.phases;
+            const float* yb = ybuf + t * a.nd;
+            const long long urow = kc.cfx + (long long)r0 * kc.afx;
+            const long long cstep = (long long)64 * P * kc.bfx;
+            for (int ph = 0; ph < P; ++ph) {
+                long long u = urow + (long long)(blo + lane * P + ph) * kc.bfx;
+                // two chunks of 64 rays x the wavefront's rows per trip: four
+                // independent read-modify-write chains per phase
+                for (int c0 = ph; c0 < cnt; c0 += 128 * P, u += 2 * cstep) {
+                    float* cl[2 * kBpRowsPerWave];
+                    float lv[2 * kBpRowsPerWave], rv[2 * kBpRowsPerWave];
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const int idx = c0 + h * 64 * P + lane * P;
+                        const bool vb = idx < cnt;
+                        const float wy = vb ? yb[idx] : 0.0f;
+                        long long ur = u + h * cstep;
+#pragma unroll
+                        for (int rr = 0; rr < kBpRowsPerWave; ++rr, ur += kc.afx) {
+                            const int j = tap_index(ur);
+                            const bool ok = vb && rr < nown && j >= -1 && j <= nl - 1;
+                            const float w = tap_weight(ur);
+                            cl[h * kBpRowsPerWave + rr] = ok ? rows + rr * S + kBpPad + j : mine;
+                            lv[h * kBpRowsPerWave + rr] = (1.0f - w) * wy;
+                            rv[h * kBpRowsPerWave + rr] = w * wy;
+                        }
+                    }
+                    float old[2 * kBpRowsPerWave];
+#pragma unroll
+                    for (int c = 0; c < 2 * kBpRowsPerWave; ++c) old[c] = cl[c][0];
+#pragma unroll
+                    for (int c = 0; c < 2 * kBpRowsPerWave; ++c) cl[c][0] = old[c] + lv[c];
+                    IMK_LDS_ORDER();
+#pragma unroll
+                    for (int c = 0; c < 2 * kBpRowsPerWave; ++c) old[c] = cl[c][1];
+#pragma unroll
+                    for (int c = 0; c < 2 * kBpRowsPerWave; ++c) cl[c][1] = old[c] + rv[c];
+                    IMK_LDS_ORDER();
+                }
+            }
+        }
+    }
+    // write back in image orientation: rows of the row pass directly, the
+    // column pass through LDS as 8-column strips
+    float* out = a.part + (size_t)gidx * nl * nl;
+    if (pass == 0) {
+        for (int rr = 0; rr < nown; ++rr)
+            for (int q = lane; q < nl; q += 64) out[(size_t)(r0 + rr) * nl + q] = rows[rr * S + kBpPad + q];
+    } else {
+        __syncthreads();
+        for (int q = threadIdx.x; q < nl * kBpRowsPerWg; q += blockDim.x) {
+            const int i = q / kBpRowsPerWg, jj = q - i * kBpRowsPerWg;
+            if (jj < nwg) out[(size_t)i * nl + rwg + jj] = acc[jj * S + kBpPad + i];
+        }
+    }
+}
+
+// c = sum over the 2G partial images in order; coef * c is stored coarse
+// (or into `tmp` for a later prolongation).
+__global__ void __launch_bounds__(256) k_bp_sum(BpOwnArgs a, float* tmp)
 {
     const int nl = a.n >> a.lvl;
-    const int J = blockIdx.x * 16 + (threadIdx.x & 15);
-    const int I = blockIdx.y * 16 + (threadIdx.x >> 4);
-    if (I >= nl || J >= nl) return;
-    const int g = blockIdx.z;
-    const int a0 = g * a.apg;
-    const int a1 = min(a.na, a0 + a.apg);
-    const float bmax = (float)(a.nd - 1);
-    float total = 0.0f;
-    const RayConst* kbase = a.consts + (size_t)a.lvl * a.na;
-    for (int ang = a0; ang < a1; ++ang) {
-        const RayConst& kc = kbase[ang];
-        const bool rows = row_stepping(ang, a.na);
-        const int s = rows ? I : J;  // step index of the samples touching this pixel
-        const int q = rows ? J : I;  // interpolation index of this pixel
-        // bins whose coordinate lies in (q-1, q+1): |b - bpos| < |1/B|; the
-        // 1% + 0.01-bin margin covers the float estimate of bpos, the exact
-        // fixed-point test below decides
-        const float bpos = ((float)q - fmaf((float)s, kc.a, kc.c)) * kc.ib;
-        const float R = 1.01f * fabsf(kc.ib) + 0.01f;
-        const int blo = (int)fminf(fmaxf(ceilf(bpos - R), 0.0f), bmax + 1.0f);
-        const int bhi = (int)fmaxf(fminf(floorf(bpos + R), bmax), -1.0f);
-        float acc = 0.0f;
-        if (blo <= bhi) {
-            long long u = kc.cfx + (long long)s * kc.afx + (long long)blo * kc.bfx;
-            const float* yr = a.y + (size_t)ang * a.nd;
-            for (int b = blo; b <= bhi; ++b) {
-                const int j0 = tap_index(u);
-                const float w = tap_weight(u);
-                const float wt = (j0 == q) ? (1.0f - w) : ((j0 == q - 1) ? w : 0.0f);
-                acc = fmaf(wt, yr[b], acc);
-                u += kc.bfx;
-            }
-        }
-        total = fmaf(kc.w, acc, total);
-    }
-    if (a.G == 1)
-        bp_store(a, nl, I, J, total);
-    else
-        a.part[(size_t)g * nl * nl + (size_t)I * nl + J] = total;
-}
-
-// Sums the angle-group partials in group order (deterministic) and stores.
-__global__ void __launch_bounds__(256) k_bp_reduce(BpArgs a)
-{
-    const int nl = a.n >> a.lvl;
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= nl * nl) return;
     const size_t d = (size_t)nl * nl;
-    float t = 0.0f;
-    for (int g = 0; g < a.G; ++g) t += a.part[g * d + q];
-    bp_store(a, nl, q / nl, q % nl, t);
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= d) return;
+    float sum = 0.0f;
+    for (int q = 0; q < 2 * a.G; ++q) sum += a.part[q * d + e];
+    const float v = a.coef * sum;
+    if (a.prolong) {
+        tmp[e] = v;
+    } else {
+        float* o = a.out + e;
+        *o = a.accumulate ? *o + v : v;
+    }
+}
+
+__global__ void k_prolong_acc(const float* in, float* out, int n, int lvl, int accumulate)
+{
+    const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= (size_t)n * n) return;
+    const int i = (int)(q / n), j = (int)(q % n);
+    const float v = in[(size_t)(i >> lvl) * (n >> lvl) + (j >> lvl)];
+    out[q] = accumulate ? out[q] + v : v;
 }
 
 // ------------------------------------------------------------ primal step
@@ -536,30 +695,104 @@ hipError_t launch_prep(const PrepArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
+constexpr int kFwdLdsBytes = 136 * 1024;
+
+void fwd_bands(int nl, int* bands, int* rows)
+{
+    if (nl > 512) {  // rows of more than 2 KB: too few per band, use the direct kernel
+        *bands = 1;
+        *rows = 0;
+        return;
+    }
+    const int maxr = kFwdLdsBytes / (int)(sizeof(float) * (nl + kPad));
+    const int nb = (nl + maxr - 1) / maxr;
+    *bands = nb;
+    *rows = (nl + nb - 1) / nb;
+}
+
+static hipError_t allow_lds(const void* fn, int bytes)
+{
+    if (bytes <= 64 * 1024) return hipSuccess;
+    return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
 hipError_t launch_fwd(const FwdArgs& a, hipStream_t s)
 {
-    const int wpa = (a.nd + 63) / 64;
-    const long waves = (long)wpa * a.na;
-    hipLaunchKernelGGL(k_fwd, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, a);
+    const AngleSplit sp = angle_split(a.na);
+    for (int t = 0; t < a.nterms; ++t) {
+        const FwdTerm& tm = a.term[t];
+        FwdBandArgs fb{};
+        fb.consts = a.consts;
+        fb.n = a.n;
+        fb.na = a.na;
+        fb.nd = a.nd;
+        fb.lvl = tm.lvl;
+        fb.img = tm.img;
+        fb.imgT = tm.imgT;
+        fb.part = tm.part;
+        fb.split = sp;
+        if (tm.rows > 0) {
+            const int nl = a.n >> tm.lvl;
+            fb.R = tm.rows;
+            fb.bands = tm.bands;
+            // about 512 workgroups of 1024 threads
+            fb.apg = std::max(1, (a.na * tm.bands + 511) / 512);
+            fb.groups_row = (sp.nrow + fb.apg - 1) / fb.apg;
+            fb.groups_col = (sp.ncol + fb.apg - 1) / fb.apg;
+            const int lds = (int)(sizeof(float) * (size_t)fb.R * (nl + kPad));
+            hipError_t e = allow_lds((const void*)k_fwd_band, lds);
+            if (e != hipSuccess) return e;
+            const int grid = tm.bands * (fb.groups_row + fb.groups_col);
+            hipLaunchKernelGGL(k_fwd_band, dim3(grid), dim3(1024), lds, s, fb);
+        } else {
+            const int wpa = (a.nd + 63) / 64;
+            const long waves = (long)wpa * a.na;
+            hipLaunchKernelGGL(k_fwd_direct, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, fb);
+        }
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    const size_t m = (size_t)a.na * a.nd;
+    const unsigned blocks = (unsigned)std::min<size_t>((m + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_fwd_reduce, dim3(blocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_bp(const BpArgs& a0, hipStream_t s)
+hipError_t launch_bp(const BpArgs& ba, hipStream_t s)
 {
-    BpArgs a = a0;
-    const int nl = a.n >> a.lvl;
-    const int t = (nl + 15) / 16;
-    // enough angle groups for ~1024 workgroups, within the 4 N^2 partial buffer
-    const int gmax = std::min(a.na, 4 << (2 * a.lvl));
-    int G = std::max(1, std::min(gmax, (1024 + t * t - 1) / (t * t)));
-    a.apg = (a.na + G - 1) / G;
-    a.G = (a.na + a.apg - 1) / a.apg;
-    hipLaunchKernelGGL(k_bp, dim3(t, t, a.G), dim3(256), 0, s, a);
-    if (a.G > 1) {
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_bp_reduce, dim3((nl * nl + 255) / 256), dim3(256), 0, s, a);
-    }
+    BpOwnArgs a{};
+    a.consts = ba.consts;
+    a.n = ba.n;
+    a.na = ba.na;
+    a.nd = ba.nd;
+    a.lvl = ba.lvl;
+    a.y = ba.y;
+    a.part = ba.part;
+    a.split = angle_split(ba.na);
+    a.out = ba.out;
+    a.coef = ba.coef;
+    a.accumulate = ba.accumulate;
+    a.prolong = ba.prolong;
+    const int nl = ba.n >> ba.lvl;
+    const int nb = (nl + kBpRowsPerWg - 1) / kBpRowsPerWg;
+    // about 512 workgroups, within the 8 N^2 partial buffer (2 G N_l^2)
+    const int gmax = std::max(1, std::min(std::max(a.split.nrow, a.split.ncol), 4 << (2 * ba.lvl)));
+    a.G = std::max(1, std::min(gmax, (512 + 2 * nb - 1) / (2 * nb)));
+    a.batch = std::max(1, std::min(8, 8192 / ba.nd));
+    const int lds = (int)(sizeof(float) *
+                          ((size_t)kBpRowsPerWg * (nl + 2 * kBpPad) + kBpWaves * 128 + (size_t)a.batch * ba.nd));
+    hipError_t e = allow_lds((const void*)k_bp_own, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_bp_own, dim3(nb * 2 * a.G), dim3(64 * kBpWaves), lds, s, a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const size_t d = (size_t)nl * nl;
+    hipLaunchKernelGGL(k_bp_sum, dim3((unsigned)((d + 255) / 256)), dim3(256), 0, s, a, ba.tmp);
+    e = hipGetLastError();
+    if (e != hipSuccess || !ba.prolong) return e;
+    const size_t fine = (size_t)ba.n * ba.n;
+    hipLaunchKernelGGL(k_prolong_acc, dim3((unsigned)((fine + 255) / 256)), dim3(256), 0, s, (const float*)ba.tmp,
+                       ba.out, ba.n, ba.lvl, ba.accumulate);
     return hipGetLastError();
 }
 

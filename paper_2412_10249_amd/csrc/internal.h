@@ -111,8 +111,9 @@ struct BpOwnArgs {
     const RayConst* consts;
     int n, na, nd, lvl;
     const float* y;
-    float* part;  // [2 passes][G][N_l][N_l]; the column pass is stored transposed
+    float* part;  // nq partial images N_l x N_l, image orientation
     int G;
+    int nq;     // partial images to sum (2 G for the scatter, G for the gather)
     int batch;  // angles whose sinogram rows are staged in LDS together
     AngleSplit split;
     float* out;

@@ -446,7 +446,53 @@ __global__ void __launch_bounds__(256) k_bp_own(BpOwnArgs a)
     }
 }
 
-// c = sum over the 2G partial images in order; coef * c is stored coarse
+// Gather form of the same transpose, used on coarse levels where a pixel
+// sees many bins per angle: one thread per level-l pixel and angle group;
+// each candidate bin recomputes the forward's fixed-point coordinate and
+// keeps (1-w) if its left tap is this pixel, w if it is the left neighbour.
+__global__ void __launch_bounds__(256) k_bp_gather(BpOwnArgs a)
+{
+    const int nl = a.n >> a.lvl;
+    const int J = blockIdx.x * 16 + (threadIdx.x & 15);
+    const int I = blockIdx.y * 16 + (threadIdx.x >> 4);
+    if (I >= nl || J >= nl) return;
+    const int g = blockIdx.z;
+    const int apg = (a.na + a.G - 1) / a.G;
+    const int a0 = g * apg;
+    const int a1 = min(a.na, a0 + apg);
+    const float bmax = (float)(a.nd - 1);
+    float total = 0.0f;
+    const RayConst* kbase = a.consts + (size_t)a.lvl * a.na;
+    for (int ang = a0; ang < a1; ++ang) {
+        const RayConst& kc = kbase[ang];
+        const bool rows = row_stepping(ang, a.na);
+        const int s = rows ? I : J;  // step index of the samples touching this pixel
+        const int q = rows ? J : I;  // interpolation index of this pixel
+        // bins whose coordinate lies in (q-1, q+1): |b - bpos| < |1/B|; the
+        // 1% + 0.01-bin margin covers the float estimate of bpos, the exact
+        // fixed-point test below decides
+        const float bpos = ((float)q - fmaf((float)s, kc.a, kc.c)) * kc.ib;
+        const float R = 1.01f * fabsf(kc.ib) + 0.01f;
+        const int blo = (int)fminf(fmaxf(ceilf(bpos - R), 0.0f), bmax + 1.0f);
+        const int bhi = (int)fmaxf(fminf(floorf(bpos + R), bmax), -1.0f);
+        float acc = 0.0f;
+        if (blo <= bhi) {
+            long long u = kc.cfx + (long long)s * kc.afx + (long long)blo * kc.bfx;
+            const float* yr = a.y + (size_t)ang * a.nd;
+            for (int b = blo; b <= bhi; ++b) {
+                const int j0 = tap_index(u);
+                const float w = tap_weight(u);
+                const float wt = (j0 == q) ? (1.0f - w) : ((j0 == q - 1) ? w : 0.0f);
+                acc = fmaf(wt, yr[b], acc);
+                u += kc.bfx;
+            }
+        }
+        total = fmaf(kc.w, acc, total);
+    }
+    a.part[(size_t)g * nl * nl + (size_t)I * nl + J] = total;
+}
+
+// c = sum over the nq partial images in a fixed order; coef * c is stored coarse
 // (or into `tmp` for a later prolongation).
 __global__ void __launch_bounds__(256) k_bp_sum(BpOwnArgs a, float* tmp)
 {
@@ -454,9 +500,17 @@ __global__ void __launch_bounds__(256) k_bp_sum(BpOwnArgs a, float* tmp)
     const size_t d = (size_t)nl * nl;
     const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= d) return;
-    float sum = 0.0f;
-    for (int q = 0; q < 2 * a.G; ++q) sum += a.part[q * d + e];
-    const float v = a.coef * sum;
+    // four interleaved partial sums, combined in a fixed order
+    float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
+    int q = 0;
+    for (; q + 4 <= a.nq; q += 4) {
+        s0 += a.part[q * d + e];
+        s1 += a.part[(q + 1) * d + e];
+        s2 += a.part[(q + 2) * d + e];
+        s3 += a.part[(q + 3) * d + e];
+    }
+    for (; q < a.nq; ++q) s0 += a.part[q * d + e];
+    const float v = a.coef * ((s0 + s1) + (s2 + s3));
     if (a.prolong) {
         tmp[e] = v;
     } else {
@@ -558,7 +612,7 @@ __global__ void __launch_bounds__(256) k_primal(PrimalArgs a)
 // inner solve reads v and u0 once and writes the result once.
 constexpr int kTvTile = 32;
 
-__global__ void __launch_bounds__(256) k_tv(TvArgs a)
+__global__ void __launch_bounds__(1024) k_tv(TvArgs a)
 {
     extern __shared__ float sm[];
     const int H = a.J;
@@ -774,16 +828,27 @@ hipError_t launch_bp(const BpArgs& ba, hipStream_t s)
     a.accumulate = ba.accumulate;
     a.prolong = ba.prolong;
     const int nl = ba.n >> ba.lvl;
-    const int nb = (nl + kBpRowsPerWg - 1) / kBpRowsPerWg;
-    // about 512 workgroups, within the 8 N^2 partial buffer (2 G N_l^2)
-    const int gmax = std::max(1, std::min(std::max(a.split.nrow, a.split.ncol), 4 << (2 * ba.lvl)));
-    a.G = std::max(1, std::min(gmax, (512 + 2 * nb - 1) / (2 * nb)));
-    a.batch = std::max(1, std::min(8, 8192 / ba.nd));
-    const int lds = (int)(sizeof(float) *
-                          ((size_t)kBpRowsPerWg * (nl + 2 * kBpPad) + kBpWaves * 128 + (size_t)a.batch * ba.nd));
-    hipError_t e = allow_lds((const void*)k_bp_own, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_bp_own, dim3(nb * 2 * a.G), dim3(64 * kBpWaves), lds, s, a);
+    hipError_t e;
+    if (ba.lvl <= 1) {
+        // ownership scatter: about 512 workgroups, 2 G N_l^2 <= 8 N^2 partials
+        const int nb = (nl + kBpRowsPerWg - 1) / kBpRowsPerWg;
+        const int gmax = std::max(1, std::min(std::max(a.split.nrow, a.split.ncol), 4 << (2 * ba.lvl)));
+        a.G = std::max(1, std::min(gmax, (512 + 2 * nb - 1) / (2 * nb)));
+        a.nq = 2 * a.G;
+        a.batch = std::max(1, std::min(8, 8192 / ba.nd));
+        const int lds = (int)(sizeof(float) *
+                              ((size_t)kBpRowsPerWg * (nl + 2 * kBpPad) + kBpWaves * 128 + (size_t)a.batch * ba.nd));
+        e = allow_lds((const void*)k_bp_own, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_bp_own, dim3(nb * 2 * a.G), dim3(64 * kBpWaves), lds, s, a);
+    } else {
+        // gather: about 1024 workgroups, G N_l^2 <= 8 N^2 partials
+        const int t = (nl + 15) / 16;
+        a.G = std::max(1, std::min(std::min(a.na, 8 << (2 * ba.lvl)), (1024 + t * t - 1) / (t * t)));
+        a.G = (a.na + ((a.na + a.G - 1) / a.G) - 1) / ((a.na + a.G - 1) / a.G);  // no empty group
+        a.nq = a.G;
+        hipLaunchKernelGGL(k_bp_gather, dim3(t, t, a.G), dim3(256), 0, s, a);
+    }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const size_t d = (size_t)nl * nl;
@@ -810,7 +875,7 @@ hipError_t launch_tv(const TvArgs& a, hipStream_t s)
     const int R = kTvTile + 2 * a.J;
     const size_t sh = (size_t)5 * R * R * sizeof(float);
     const int tiles = (a.n + kTvTile - 1) / kTvTile;
-    hipLaunchKernelGGL(k_tv, dim3(tiles * tiles), dim3(256), sh, s, a);
+    hipLaunchKernelGGL(k_tv, dim3(tiles * tiles), dim3(1024), sh, s, a);
     return hipGetLastError();
 }
 

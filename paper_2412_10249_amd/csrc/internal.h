@@ -38,7 +38,7 @@ struct Layout {
     size_t zpT[IMASK_MAX_LOG2F + 1] = {};  // padded level-l image, transposed
     size_t craw[IMASK_MAX_LOG2F + 1] = {}; // raw level-l backprojection N_l^2
     size_t vbuf = 0;                       // N^2 prox input
-    size_t part = 0;                       // 8 N^2 per-angle-group partial backprojections
+    size_t part = 0;                       // 16 N^2 per-angle-group partial backprojections
     size_t ptmp = 0;                       // N^2 coarse result before prolongation
     size_t fpart[IMASK_MAX_LOG2F + 1] = {};// per-band partial projections, fwd_bands(l) * m
     int fbands[IMASK_MAX_LOG2F + 1] = {};  // row bands of the level-l forward
@@ -129,7 +129,7 @@ struct BpArgs {
     float coef;
     int accumulate;
     int prolong;  // 1: write the 2^l x 2^l block of an N x N image
-    float* part;  // per-angle-group partial sums (8 N^2 floats of workspace)
+    float* part;  // per-angle-group partial sums (16 N^2 floats of workspace)
     float* tmp;   // N_l^2 scratch for the prolonged store
 };
 

@@ -344,7 +344,7 @@ __device__ __forceinline__ void bin_range(const RayConst& kc, int r0, int nrows,
 // program order, so this is all that is needed between the two phases.
 #define IMK_LDS_ORDER() asm volatile("" ::: "memory")
 
-__global__ void __launch_bounds__(256) k_bp_own(BpOwnArgs a)
+__global__ void __launch_bounds__(64 * kBpWaves) k_bp_own(BpOwnArgs a)
 {
     extern __shared__ float smem[];
     const int nl = a.n >> a.lvl;
@@ -830,21 +830,21 @@ hipError_t launch_bp(const BpArgs& ba, hipStream_t s)
     const int nl = ba.n >> ba.lvl;
     hipError_t e;
     if (ba.lvl <= 1) {
-        // ownership scatter: about 512 workgroups, 2 G N_l^2 <= 8 N^2 partials
+        // ownership scatter: about 1024 workgroups, 2 G N_l^2 <= 16 N^2 partials
         const int nb = (nl + kBpRowsPerWg - 1) / kBpRowsPerWg;
-        const int gmax = std::max(1, std::min(std::max(a.split.nrow, a.split.ncol), 4 << (2 * ba.lvl)));
-        a.G = std::max(1, std::min(gmax, (512 + 2 * nb - 1) / (2 * nb)));
+        const int gmax = std::max(1, std::min(std::max(a.split.nrow, a.split.ncol), 8 << (2 * ba.lvl)));
+        a.G = std::max(1, std::min(gmax, (1024 + 2 * nb - 1) / (2 * nb)));
         a.nq = 2 * a.G;
-        a.batch = std::max(1, std::min(8, 8192 / ba.nd));
+        a.batch = std::max(1, std::min(4, 4096 / ba.nd));
         const int lds = (int)(sizeof(float) *
                               ((size_t)kBpRowsPerWg * (nl + 2 * kBpPad) + kBpWaves * 128 + (size_t)a.batch * ba.nd));
         e = allow_lds((const void*)k_bp_own, lds);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_bp_own, dim3(nb * 2 * a.G), dim3(64 * kBpWaves), lds, s, a);
     } else {
-        // gather: about 1024 workgroups, G N_l^2 <= 8 N^2 partials
+        // gather: about 1024 workgroups, G N_l^2 <= 16 N^2 partials
         const int t = (nl + 15) / 16;
-        a.G = std::max(1, std::min(std::min(a.na, 8 << (2 * ba.lvl)), (1024 + t * t - 1) / (t * t)));
+        a.G = std::max(1, std::min(std::min(a.na, 16 << (2 * ba.lvl)), (1024 + t * t - 1) / (t * t)));
         a.G = (a.na + ((a.na + a.G - 1) / a.G) - 1) / ((a.na + a.G - 1) / a.G);  // no empty group
         a.nq = a.G;
         hipLaunchKernelGGL(k_bp_gather, dim3(t, t, a.G), dim3(256), 0, s, a);

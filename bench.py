@@ -8,10 +8,18 @@ with p = 1/4 (the paper's literal construction, PAPER mode).  Epochs count
 equivalent full-resolution operator applications (cost 2^{-l} per step).
 
 Prints one JSON line.  --gpus above 1 is refused: this build runs on one GPU.
+
+Profiling helpers (no GPU needed for --summarize):
+  --copy-calib          also run a 64 MiB plain copy (for counter calibration)
+  --summarize DIR...    turn rocprofv3 CSV output into the markdown summaries
+                        kept under profiles/
 """
 from __future__ import annotations
 
 import argparse
+import csv
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -28,11 +36,24 @@ LEVELS = (0, 1, 2, 3)
 LAM, TV_W, TV_EPS, TV_J = 1e-3, 2e-4, 1e-3, 10
 SIGMA = 1e-3
 SEED, STREAM = 42, 0
-# Joseph sample arithmetic counted per (ray, step) sample: the right-tap
-# weight (1 - w) and two fused multiply-adds into the accumulator.
-FLOP_PER_SAMPLE = 5
-PEAK_FP32_TFLOPS = 157.3
+# FP32 arithmetic per Joseph sample (a (ray, step) pair, two matrix entries):
+# coordinate step (1), right-tap weight w and left weight 1 - w (2), two
+# multiply-adds into the accumulator (4).
+FLOP_PER_SAMPLE = 7
+PEAK_FP32_TFLOPS = 157.3   # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2 (dual FP32) x 2.4 GHz
 HBM_PEAK_GBS = 8000.0
+COPY_N = 4096               # calibration copy: 4096^2 floats = 64 MiB each way
+KERNEL_SOURCES = ["paper_2412_10249_amd/csrc/kernels.hip", "paper_2412_10249_amd/csrc/api.hip",
+                  "paper_2412_10249_amd/csrc/internal.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def sample_counts(n, na, nd, lvl):
@@ -74,19 +95,47 @@ def cpu_baseline(b, budget_s=12.0):
                       f"{el:.1f} s"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=400)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--kernel-reps", type=int, default=20)
-    ap.add_argument("--no-cpu", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path does not shard "
-              f"across GPUs in this build", file=sys.stderr)
-        sys.exit(2)
+def stored_traffic(kernel_key):
+    """HBM bytes per launch from the committed counter summary, or None when
+    the kernel sources changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except OSError:
+        return None
+    if t.get("source_hash") != source_hash():
+        return None
+    ent = t.get("kernels", {}).get(kernel_key)
+    return None if ent is None else ent.get("bytes_per_launch")
 
+
+def counter_run(spec: str):
+    """Launch only one projector kernel (plus the calibration copy), for a
+    rocprofv3 --pmc pass: spec is fwd:LEVEL or bp:LEVEL."""
+    import torch
+
+    import paper_2412_10249_amd as pk
+
+    kind, lvl = spec.split(":")
+    lvl = int(lvl)
+    torch.cuda.set_device(0)
+    geom = pk.Geometry(N, NA, ND)
+    work = pk.workspace(geom)
+    g = torch.Generator(device="cuda").manual_seed(5)
+    src = torch.rand((COPY_N, COPY_N), device="cuda", generator=g)
+    for _ in range(3):
+        pk.resample(src, 0, pk.PROLONG)
+    if kind == "fwd":
+        x = torch.rand((N, N), device="cuda", generator=g)
+        pk.time_kernel(geom, pk.KERNEL_FORWARD, lvl, x, work, 5)
+    else:
+        y = torch.rand((NA, ND), device="cuda", generator=g)
+        pk.time_kernel(geom, pk.KERNEL_TRANSPOSE, lvl, y, work, 5)
+    torch.cuda.synchronize()
+    print(f"counter run done: {spec}", flush=True)
+
+
+def run(args):
     import torch
 
     import paper_2412_10249_amd as pk
@@ -112,34 +161,26 @@ def main():
     draws = pk.draws(prob.params, lv, k0, args.steps)
     mix = np.bincount(draws, minlength=len(LEVELS)) / args.steps
 
-    # per-kernel durations of the projector pair, HIP events on the stream
-    # the kernels run on (torch's current stream, which the library uses)
-    work = prob.work
+    # main projector kernels, HIP events on the stream the library launches on
     x = prob.x_cur.clone()
     y = prob.y_cur.clone()
-    sino = torch.empty((NA, ND), device="cuda")
-    img = torch.empty((N, N), device="cuda")
-    stream = torch.cuda.current_stream()
     kern = {}
     for lvl in LEVELS:
-        for name, fn in (("fwd", lambda: pk.project(geom, lvl, x, work, sino)),
-                         ("bp", lambda: pk.backproject(geom, lvl, y, work, img))):
-            fn()
-            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            ev0.record(stream)
-            for _ in range(args.kernel_reps):
-                fn()
-            ev1.record(stream)
-            torch.cuda.synchronize()
-            kern[(name, lvl)] = ev0.elapsed_time(ev1) / 1e3 / args.kernel_reps
+        kern[("fwd", lvl)] = pk.time_kernel(geom, pk.KERNEL_FORWARD, lvl, x, prob.work, args.kernel_reps)
+        kern[("bp", lvl)] = pk.time_kernel(geom, pk.KERNEL_TRANSPOSE, lvl, y, prob.work, args.kernel_reps)
+    if args.copy_calib:
+        src = torch.rand((COPY_N, COPY_N), device="cuda")
+        for _ in range(3):
+            pk.resample(src, 0, pk.PROLONG)
+        torch.cuda.synchronize()
     samples = {lvl: sample_counts(N, NA, ND, lvl) for lvl in LEVELS}
-    # dominant kernel: largest expected time share per step under p
-    share = {key: t * (1.0 / len(LEVELS)) for key, t in kern.items()}
+    # dominant kernel: largest expected time per step under the level mix
+    share = {key: t * lv.p[LEVELS.index(key[1])] for key, t in kern.items()}
     dom = max(share, key=share.get)
     dom_t = kern[dom]
+    name = {"fwd": "k_fwd_band", "bp": "k_bp_own" if dom[1] <= 1 else "k_bp_gather"}[dom[0]]
+    key = f"{name}_l{dom[1]}"
     achieved = samples[dom[1]] * FLOP_PER_SAMPLE / dom_t / 1e12
-    proj_pair_sps = {f"l{lvl}": samples[lvl] * 2 / (kern[("fwd", lvl)] + kern[("bp", lvl)]) for lvl in LEVELS}
-
     out = {
         "metric": "ImaSk epochs/s (512x512 smoothed-TV race workload)",
         "value": epochs / el,
@@ -156,17 +197,437 @@ def main():
         "config": {"workload": "2D parallel-beam CT 512x512, 720 angles x 768 bins, smoothed TV eps=1e-3 + "
                                "lambda=1e-3, levels 512/256/128/64 uniform p, ImaSk (PAPER sketches)",
                    "steps_level_mix": [round(float(v), 4) for v in mix], "epochs_timed": epochs},
-        "roofline": {"bound": "alu", "kernel": f"k_{dom[0]} level {dom[1]}", "achieved": achieved,
-                     "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
-                     "traffic": None, "samples_per_launch": samples[dom[1]],
-                     "avg_launch_us": dom_t * 1e6,
+        "roofline": {"bound": "alu", "kernel": key, "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": stored_traffic(key),
+                     "samples_per_launch": samples[dom[1]], "avg_launch_us": dom_t * 1e6,
+                     "samples_per_s": samples[dom[1]] / dom_t,
                      "effective_gather_frac_hbm": samples[dom[1]] * 8 / dom_t / 1e9 / HBM_PEAK_GBS},
         "kernels_us": {f"{k[0]}_l{k[1]}": round(v * 1e6, 2) for k, v in kern.items()},
-        "projector_pair_samples_per_s": proj_pair_sps,
+        "projector_samples_per_s": {f"{k[0]}_l{k[1]}": samples[k[1]] / v for k, v in kern.items()},
+        "kernel_source_hash": source_hash(),
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(b)
     print(json.dumps(out), flush=True)
+
+
+# ------------------------------------------------------------ the race
+
+def tv_grad_torch(u, eps):
+    """Gradient of sum sqrt(|grad u|^2 + eps^2) (forward differences, zero at
+    the last row/column) - measurement code for the reference solution."""
+    import torch
+
+    g1 = torch.zeros_like(u)
+    g2 = torch.zeros_like(u)
+    g1[:-1, :] = u[1:, :] - u[:-1, :]
+    g2[:, :-1] = u[:, 1:] - u[:, :-1]
+    nrm = torch.sqrt(g1 * g1 + g2 * g2 + eps * eps)
+    q1, q2 = g1 / nrm, g2 / nrm
+    div = -q1 - q2
+    div[1:, :] += q1[:-1, :]
+    div[:, 1:] += q2[:, :-1]
+    return div
+
+
+def reference_solution(geom, work, b32, lam, w, eps, iters, log):
+    """x_ref = argmin 1/2|R0 x - b|^2 + w TV_eps(x) + lam/2 |x|^2 by Nesterov's
+    accelerated gradient with the known strong convexity (mu = lam) and
+    Lipschitz constant; returns x and the final relative gradient norm."""
+    import torch
+
+    import paper_2412_10249_amd as pk
+
+    x = torch.zeros(geom.image_shape, device="cuda")
+    v = torch.randn(geom.image_shape, device="cuda", generator=torch.Generator(device="cuda").manual_seed(3))
+    for _ in range(50):  # power method for |R0|^2
+        v = pk.backproject(geom, 0, pk.project(geom, 0, v, work), work)
+        nrm = torch.linalg.vector_norm(v)
+        v = v / nrm
+    L = float(nrm) + lam + 8.0 * w / eps
+    q = np.sqrt(lam / L)
+    beta = (1 - q) / (1 + q)
+    atb = pk.backproject(geom, 0, b32, work)
+    scale = float(torch.linalg.vector_norm(atb))
+
+    def grad(z):
+        r = pk.project(geom, 0, z, work) - b32
+        return pk.backproject(geom, 0, r.contiguous(), work) + w * tv_grad_torch(z, eps) + lam * z
+
+    y = x.clone()
+    for it in range(iters):
+        xn = y - grad(y) / L
+        y = xn + beta * (xn - x)
+        x = xn
+        if (it + 1) % 500 == 0:
+            gn = float(torch.linalg.vector_norm(grad(x))) / scale
+            log(f"reference: {it + 1} iterations, |grad F|/|R0^T b| = {gn:.3e}")
+    gn = float(torch.linalg.vector_norm(grad(x))) / scale
+    return x, gn
+
+
+def race(args):
+    """Time to a relative error of 1e-3 against the common limit: ImaSk with
+    UNBIASED sketches (levels 512/256/128/64) vs full-resolution SAGA (r = 1),
+    same kernels, same GPU; each method runs a few step sizes."""
+    import torch
+
+    import paper_2412_10249_amd as pk
+    import synth
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    torch.cuda.set_device(0)
+    _, b = synth.ct_problem(N, NA, ND, I0, 1000, 2000)
+    b32 = torch.from_numpy(b.astype(np.float32)).cuda()
+    geom = pk.Geometry(N, NA, ND)
+    work = pk.workspace(geom)
+    t0 = time.perf_counter()
+    xref, gnorm = reference_solution(geom, work, b32, LAM, TV_W, TV_EPS, args.ref_iters, log)
+    log(f"reference done in {time.perf_counter() - t0:.1f} s, relative gradient {gnorm:.2e}")
+    rnorm = float(torch.linalg.vector_norm(xref))
+    reg = pk.Regularizer(pk.REG_SMOOTH_TV, LAM, TV_W, TV_EPS, TV_J)
+    results = {}
+    for name, lv in (("imask_r4", pk.Levels.uniform(LEVELS, pk.FULL_UNBIASED)), ("saga_r1", pk.Levels((0,), (1.0,)))):
+        L2, lb, lp = pk.step_constants(geom, lv, LAM, work, iters=40)
+        s3, th = pk.sigma_thm3(L2, lb, lp, min(lv.p), 100)
+        results[name] = {"constants": [L2, lb, lp], "sigma_thm3": s3, "theta_thm3": th, "runs": []}
+        for mult in args.sigma_mults:
+            sigma = s3 * mult
+            prob = pk.Problem(geom, lv, reg, pk.Params(sigma, SEED, STREAM), b32)
+            torch.cuda.synchronize()
+            hist = []
+            tstart = time.perf_counter()
+            tlog = tstart
+            while prob.epochs < args.race_epochs:
+                prob.solve(args.check_every, pk.BUDGET_EPOCHS)
+                err = float(torch.linalg.vector_norm(prob.x_cur - xref)) / rnorm  # synchronises
+                hist.append((time.perf_counter() - tstart, prob.epochs, err))
+                if time.perf_counter() - tlog > 20.0:
+                    tlog = time.perf_counter()
+                    log(f"  {name} sigma x{mult}: {prob.epochs:.0f} epochs, rel err {err:.3e}")
+                if err <= args.target or not np.isfinite(err) or time.perf_counter() - tstart > args.race_seconds:
+                    break
+            t_hit = None
+            for (t1, e1, r1), (t2, e2, r2) in zip(hist, hist[1:]):
+                if r2 <= args.target < r1:  # interpolate in log error
+                    f = (np.log(r1) - np.log(args.target)) / (np.log(r1) - np.log(r2))
+                    t_hit = t1 + f * (t2 - t1)
+                    break
+            run_res = {"sigma": sigma, "sigma_over_thm3": mult, "epochs": prob.epochs, "final_rel_err": hist[-1][2],
+                       "seconds": hist[-1][0], "time_to_target_s": t_hit,
+                       "check_every_epochs": args.check_every,
+                       "rel_err_history": [(round(h[1], 2), round(h[2], 7)) for h in hist[::max(1, len(hist) // 60)]]}
+            log(f"{name} sigma x{mult}: {run_res['final_rel_err']:.3e} after {prob.epochs:.1f} epochs, "
+                f"{hist[-1][0]:.2f} s, t(1e-3) = {t_hit}")
+            results[name]["runs"].append(run_res)
+    best = {k: min([r["time_to_target_s"] for r in v["runs"] if r["time_to_target_s"]] or [None], key=lambda z: z or 1e30)
+            for k, v in results.items()}
+    print(json.dumps({"metric": "time to relative error 1e-3 vs the common limit (512x512 smoothed TV)",
+                      "target": args.target, "reference_relative_gradient": gnorm, "best_time_s": best,
+                      "results": results}), flush=True)
+
+
+# ------------------------------------------------------------ systems workloads
+
+def _sigma_for(geom, levels, lam, work, cache={}):
+    """Thm. 3 step size (x2, the fastest stable multiple in the race) per geometry."""
+    import paper_2412_10249_amd as pk
+
+    key = (geom, levels)
+    if key not in cache:
+        L2, lb, lp = pk.step_constants(geom, levels, lam, work, iters=30)
+        cache[key] = 2.0 * pk.sigma_thm3(L2, lb, lp, min(levels.p), 100)[0]
+    return cache[key]
+
+
+def batched(args):
+    """64 slices of mixed sizes (256..1024, angles = bins = 1.5 N), each with its
+    own draw stream, Tikhonov lam = 1e-2, 30 epochs each, all in flight on
+    several streams; aggregate throughput and per-slice equality with alone."""
+    import torch
+
+    import paper_2412_10249_amd as pk
+    import synth
+    from paper_2412_10249_amd import batch
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    torch.cuda.set_device(0)
+    sizes = [256, 384, 512, 768, 1024]
+    lv = pk.Levels.uniform(LEVELS)
+    reg = pk.Regularizer(pk.REG_TIKHONOV, 1e-2)
+    data = {}
+    for n in sizes:
+        data[n] = [torch.from_numpy(synth.ct_problem(n, 3 * n // 2, 3 * n // 2, 1e5, 1000 + s, 2000 + s)[1]
+                                    .astype(np.float32)).cuda() for s in range(2)]
+        log(f"data for N={n} ready")
+    sig = {}
+    probs = []
+    for s in range(args.slices):
+        n = sizes[s % 5]
+        geom = pk.Geometry(n, 3 * n // 2, 3 * n // 2)
+        if n not in sig:
+            sig[n] = _sigma_for(geom, lv, 1e-2, pk.workspace(geom))
+        probs.append(pk.Problem(geom, lv, reg, pk.Params(sig[n], SEED, s), data[n][s % 2]))
+    torch.cuda.synchronize()
+    rays_per_epoch = sum(p.geom.n_angles * p.geom.n_det for p in probs)
+    runner = batch.BatchRunner(probs, n_streams=args.streams)
+    t0 = time.perf_counter()
+    runner.solve_all(args.epochs, pk.BUDGET_EPOCHS)
+    runner.synchronize()
+    el = time.perf_counter() - t0
+    tot_epochs = sum(p.epochs for p in probs)
+    log(f"batch done: {len(probs)} slices, {tot_epochs:.1f} slice-epochs in {el:.2f} s")
+    # the same slices alone, one after another on one stream, for equality and speed-up
+    same = []
+    t1 = time.perf_counter()
+    for s in (0, 4):
+        p = probs[s]
+        q = pk.Problem(p.geom, lv, reg, pk.Params(sig[p.geom.n], SEED, s), data[p.geom.n][s % 2])
+        q.solve(args.epochs, pk.BUDGET_EPOCHS)
+        torch.cuda.synchronize()
+        same.append(bool(torch.equal(q.x_cur, p.x_cur)))
+    print(json.dumps({"metric": "batched ImaSk, 64 mixed slices", "slices": len(probs), "streams": args.streams,
+                      "epochs_per_slice": args.epochs, "seconds": el, "slice_epochs_per_s": tot_epochs / el,
+                      "full_res_ray_epochs_per_s": rays_per_epoch * args.epochs / el,
+                      "equal_to_alone": same, "alone_check_seconds": time.perf_counter() - t1}), flush=True)
+
+
+def serving(args):
+    """Poisson arrivals of reconstructions (N in 128/256/512/1024, weights
+    4:3:2:1, angles = bins = 1.5 N, 30 epochs each) at the given rates."""
+    import torch
+
+    import paper_2412_10249_amd as pk
+    import synth
+    from paper_2412_10249_amd import serve
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    torch.cuda.set_device(0)
+    lv = pk.Levels.uniform(LEVELS)
+    reg = pk.Regularizer(pk.REG_TIKHONOV, 1e-2)
+    pool = {}
+    sig = {}
+    for n in (128, 256, 512, 1024):
+        geom = pk.Geometry(n, 3 * n // 2, 3 * n // 2)
+        pool[n] = [torch.from_numpy(synth.ct_problem(n, 3 * n // 2, 3 * n // 2, 1e5, 3000 + s, 4000 + s)[1]
+                                    .astype(np.float32)).cuda() for s in range(3)]
+        sig[geom] = _sigma_for(geom, lv, 1e-2, pk.workspace(geom))
+    log("serving data ready")
+    out = []
+    for rate in args.rates:
+        ex = serve.GpuExecutor(args.slots, lambda n: lv, reg, lambda g: sig[g])
+        sch = serve.Scheduler(ex, hbm_budget=int(args.hbm_gb * 2 ** 30), max_active=args.slots,
+                              chunk_epochs=args.chunk)
+        arr = serve.poisson_arrivals(rate, args.window, seed=7)
+        t0 = time.perf_counter()
+        done = serve.run_load(sch, arr, lambda rid, n, t: serve.Request(rid, n, t, args.serve_epochs,
+                                                                          data=pool[n][rid % 3]))
+        summ = serve.latency_summary(done)
+        summ.update({"offered_per_s": rate, "requests": len(arr), "window_s": args.window,
+                     "wall_s": time.perf_counter() - t0})
+        log(f"rate {rate}: {summ}")
+        out.append(summ)
+    print(json.dumps({"metric": "serving ImaSk reconstructions, p50/p99 latency", "slots": args.slots,
+                      "epochs_per_request": args.serve_epochs, "results": out}), flush=True)
+
+
+def autograd_bench(args):
+    """Differentiable unrolled ImaSk: batch 32 of 256^2, 384 angles x 384 bins,
+    10 iterations, checkpoint every 2; gradients to the image and lam."""
+    import torch
+
+    import paper_2412_10249_amd as pk
+    import synth
+    from paper_2412_10249_amd import autograd as ag
+
+    torch.cuda.set_device(0)
+    n, na, nd = 256, 384, 384
+    geom = pk.Geometry(n, na, nd)
+    lv = pk.Levels.uniform(LEVELS)
+    work = pk.workspace(geom)
+    sigma = _sigma_for(geom, lv, 1e-2, work)
+    xs = [torch.from_numpy(synth.ct_problem(n, na, nd, 1e5, 5000 + s, 6000 + s)[0].astype(np.float32)).cuda()
+          for s in range(args.batch)]
+    x_in = torch.stack(xs) * 0.9
+    x_in.requires_grad_(True)
+    lam = torch.tensor(1e-2, device="cuda", requires_grad=True)
+
+    def loss(xin, lam_):
+        tot = 0.0
+        for s in range(xin.shape[0]):
+            b = ag.ProjectFn.apply(xin[s], geom, 0, work)
+            xk = ag.unrolled_imask(b, lam_, geom, lv, sigma, 10, stream_id=s, work=work, checkpoint_every=2)
+            tot = tot + 0.5 * ((xk - xs[s]) ** 2).sum()
+        return tot
+
+    L = loss(x_in, lam)
+    gx, gl = torch.autograd.grad(L, (x_in, lam))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    L = loss(x_in, lam)
+    gx, gl = torch.autograd.grad(L, (x_in, lam))
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    d = torch.randn_like(x_in)
+    with torch.no_grad():
+        h = 1e-2
+        fd = (loss(x_in + h * d, lam) - loss(x_in - h * d, lam)) / (2 * h)
+        hl = 1e-4
+        fdl = (loss(x_in, lam + hl) - loss(x_in, lam - hl)) / (2 * hl)
+    dd = float((gx * d).sum())
+    print(json.dumps({"metric": "unrolled ImaSk forward+backward", "batch": args.batch, "iterations": 10,
+                      "checkpoint_every": 2, "seconds": el, "ms_per_sample": el / args.batch * 1e3,
+                      "dir_derivative": dd, "fd_dir_derivative": float(fd),
+                      "rel_err_dx": abs(dd - float(fd)) / abs(float(fd)),
+                      "dlam": float(gl), "fd_dlam": float(fdl),
+                      "rel_err_dlam": abs(float(gl) - float(fdl)) / abs(float(fdl))}), flush=True)
+
+
+# ------------------------------------------------------------ profile summaries
+
+def _short(name: str) -> str:
+    i = name.find("::k_")
+    if i >= 0:
+        return name[i + 2:name.find("(", i)]
+    return name.split("(")[0][:48]
+
+
+def summarize(dirs, command_note, counter_key=None):
+    """Markdown summaries of rocprofv3 CSVs: kernel stats, and per-launch HBM
+    traffic from FETCH_SIZE / WRITE_SIZE calibrated against the plain copy."""
+    lines = []
+    stats = [p for d in dirs for p in glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True)]
+    for p in stats:
+        rows = list(csv.DictReader(open(p)))
+        lines.append(f"### kernel stats ({os.path.basename(p)})\n")
+        lines.append("| kernel | calls | avg us | total ms | % |")
+        lines.append("|---|---|---|---|---|")
+        for r in rows[:14]:
+            lines.append(f"| {_short(r['Name'])} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                         f"{float(r['TotalDurationNs']) / 1e6:.3f} | {float(r['Percentage']):.1f} |")
+        lines.append("")
+    traces = [p for d in dirs for p in glob.glob(os.path.join(d, "**", "*kernel_trace.csv"), recursive=True)]
+    for p in traces:
+        agg = {}
+        for r in csv.DictReader(open(p)):
+            k = (_short(r["Kernel_Name"]), f"{r['Grid_Size_X']}x{r['Grid_Size_Y']}x{r['Grid_Size_Z']}",
+                 r.get("LDS_Block_Size", ""))
+            agg.setdefault(k, []).append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+        lines.append(f"### per launch shape ({os.path.basename(p)})\n")
+        lines.append("| kernel | grid (threads) | LDS bytes | launches | avg us |")
+        lines.append("|---|---|---|---|---|")
+        for k, v in sorted(agg.items(), key=lambda kv: -sum(kv[1]))[:16]:
+            lines.append(f"| {k[0]} | {k[1]} | {k[2]} | {len(v)} | {sum(v) / len(v) / 1e3:.1f} |")
+        lines.append("")
+    counters = {}
+    for d in dirs:
+        for p in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(p)):
+                k = (_short(r["Kernel_Name"]), r.get("Grid_Size", r.get("Grid_Size_X", "?")), r["Counter_Name"])
+                counters.setdefault(k, []).append(float(r["Counter_Value"]))
+    traffic = None
+    if counters and counter_key:
+        lines.append("### HBM counters per dispatch (KiB, mean over dispatches)\n")
+        lines.append("| kernel | grid | counter | dispatches | KiB |")
+        lines.append("|---|---|---|---|---|")
+        for k, v in sorted(counters.items()):
+            lines.append(f"| {k[0]} | {k[1]} | {k[2]} | {len(v)} | {np.mean(v):.1f} |")
+        lines.append("")
+        copy_bytes = COPY_N * COPY_N * 4
+        cal = {}
+        for cn in ("FETCH_SIZE", "WRITE_SIZE"):
+            vals = [np.mean(v) for (kn, g, c), v in counters.items()
+                    if kn == "k_prolong" and c == cn and str(g).startswith(str(COPY_N * COPY_N))]
+            if vals:
+                cal[cn] = vals[0] * 1024 / copy_bytes
+        lines.append(f"copy calibration (64 MiB read + 64 MiB write): measured/ideal = {cal}\n")
+        traffic = {"source_hash": source_hash(), "calibration": cal, "kernels": {}}
+        kname = counter_key.rsplit("_l", 1)[0]
+        per = {c: float(np.mean([np.mean(v) for (kn, g, cc), v in counters.items() if kn == kname and cc == c]))
+               for c in ("FETCH_SIZE", "WRITE_SIZE")}
+        if cal.get("FETCH_SIZE") and cal.get("WRITE_SIZE"):
+            nbytes = per["FETCH_SIZE"] * 1024 / cal["FETCH_SIZE"] + per["WRITE_SIZE"] * 1024 / cal["WRITE_SIZE"]
+            traffic["kernels"][counter_key] = {"fetch_kib": per["FETCH_SIZE"], "write_kib": per["WRITE_SIZE"],
+                                               "bytes_per_launch": nbytes}
+            lines.append(f"{counter_key}: {nbytes / 1e6:.2f} MB of HBM traffic per launch (calibrated)\n")
+    lines.append(f"command: {command_note}\n")
+    return "\n".join(lines), traffic
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--kernel-reps", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calib", action="store_true")
+    ap.add_argument("--summarize", nargs="+")
+    ap.add_argument("--note", default="")
+    ap.add_argument("--counters", help="fwd:LEVEL or bp:LEVEL: launch only that kernel (for --pmc runs)")
+    ap.add_argument("--counter-key", help="with --summarize: kernel key the counter CSVs belong to")
+    ap.add_argument("--write-traffic", action="store_true", help="with --summarize: update profiles/traffic.json")
+    ap.add_argument("--race", action="store_true", help="ImaSk vs full-resolution SAGA, time to --target")
+    ap.add_argument("--target", type=float, default=1e-3)
+    ap.add_argument("--ref-iters", type=int, default=3000)
+    ap.add_argument("--race-epochs", type=float, default=300.0)
+    ap.add_argument("--race-seconds", type=float, default=60.0)
+    ap.add_argument("--sigma-mults", type=float, nargs="+", default=[1.0, 2.0])
+    ap.add_argument("--check-every", type=float, default=10.0, help="epochs between error checks in the race")
+    ap.add_argument("--batched", action="store_true", help="64 mixed slices in flight")
+    ap.add_argument("--slices", type=int, default=64)
+    ap.add_argument("--streams", type=int, default=8)
+    ap.add_argument("--epochs", type=float, default=30.0)
+    ap.add_argument("--serve", action="store_true", help="continuous-batching server under Poisson load")
+    ap.add_argument("--rates", type=float, nargs="+", default=[25.0, 50.0, 100.0, 200.0])
+    ap.add_argument("--window", type=float, default=2.0)
+    ap.add_argument("--slots", type=int, default=16)
+    ap.add_argument("--hbm-gb", type=float, default=64.0)
+    ap.add_argument("--chunk", type=float, default=2.0)
+    ap.add_argument("--serve-epochs", type=float, default=30.0)
+    ap.add_argument("--autograd", action="store_true", help="differentiable unrolled ImaSk")
+    ap.add_argument("--batch", type=int, default=32)
+    args = ap.parse_args()
+    if args.batched:
+        batched(args)
+        return
+    if args.serve:
+        serving(args)
+        return
+    if args.autograd:
+        autograd_bench(args)
+        return
+    if args.race:
+        race(args)
+        return
+    if args.summarize:
+        text, traffic = summarize(args.summarize, args.note, args.counter_key)
+        print(text)
+        if traffic and args.write_traffic:
+            old = {}
+            if os.path.exists(TRAFFIC_FILE):
+                with open(TRAFFIC_FILE) as f:
+                    old = json.load(f)
+            if old.get("source_hash") == traffic["source_hash"]:
+                old.setdefault("kernels", {}).update(traffic["kernels"])
+                traffic = old
+            with open(TRAFFIC_FILE, "w") as f:
+                json.dump(traffic, f, indent=1)
+        return
+    if args.counters:
+        counter_run(args.counters)
+        return
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path does not shard "
+              f"across GPUs in this build", file=sys.stderr)
+        sys.exit(2)
+    run(args)
 
 
 if __name__ == "__main__":

@@ -166,6 +166,39 @@ int imask_sketch_apply(const imask_geometry* g, const imask_levels* lv, int32_t 
                        int32_t adjoint, const void* work, const float* in, float* out,
                        void* stream);
 
+/* Diagnostic (not on the hot path): average duration in ms over `reps`
+ * back-to-back launches of one projector kernel at level log2f, exactly as
+ * a step launches it, measured with HIP events recorded on `stream`;
+ * synchronises on the second event.  IMASK_KERNEL_FORWARD: the Joseph
+ * forward kernel on the level-l restriction of `in` (N*N; `out`, a
+ * sinogram, receives one full projection first).  IMASK_KERNEL_TRANSPOSE:
+ * the transpose kernel on sinogram `in` (its partial images stay in the
+ * workspace; `out` is unused but must be non-null). */
+enum { IMASK_KERNEL_FORWARD = 0, IMASK_KERNEL_TRANSPOSE = 1 };
+int imask_time_kernel(const imask_geometry* g, int32_t which, int32_t log2f, const void* work, const float* in,
+                      float* out, int32_t reps, void* stream, double* avg_ms);
+
+/* Step-size constants (setup, not the hot path; synchronises `stream`).
+ * For ImaSk as the saddle-point method of Sec. 3 with A_i = p_i K_i,
+ * mu_f* = 1 and mu_g = mu, writes to out_host[0..2] the normalised squared
+ * norms of Sec. 3.4:
+ *   L^2      = lmax(Kbar^T Kbar)/mu, Kbar = sum_i p_i K_i
+ *   Lbar^2   = max(lmax(sum p_i^2 K_i^T K_i), lmax(sum p_i^2 K_i K_i^T))/mu
+ *   Lbar_p^2 = max(lmax(sum p_i K_i^T K_i),   lmax(sum p_i K_i K_i^T))/mu
+ * each by `iters` power iterations on the GPU sketch operators from a
+ * random start drawn from `seed`.  `scratch`: device, at least
+ * imask_constants_scratch_bytes(g) bytes; `work` as for imask_sketch_apply. */
+size_t imask_constants_scratch_bytes(const imask_geometry* g);
+int imask_step_constants(const imask_geometry* g, const imask_levels* lv, double mu, int32_t iters, uint64_t seed,
+                         const void* work, void* scratch, double* out_host, void* stream);
+
+/* Host: the step size of Thm. 3 (eq. (opt:cond) and eq. (eta_opt)),
+ * minimising the rate theta over c = cbar*i/(grid+1), rho = j/(grid+1),
+ * i, j = 1..grid, cbar = 1/(1 + L^2 + Lbar_p^2); sigma = eta_opt/(1 - eta_opt).
+ * theta_out (may be NULL) receives the rate. */
+int imask_sigma_thm3(double L2, double Lbar2, double Lbarp2, double pmin, int32_t grid, double* sigma_out,
+                     double* theta_out);
+
 /* Host: the sketch indices i_k, k = k0 .. k0+count-1 (Alg. 1, "sample i_k"). */
 int imask_draws(const imask_params* prm, const imask_levels* lv, uint64_t k0, int32_t count,
                 int32_t* out_host);

@@ -23,7 +23,9 @@ BUDGET_ITERS, BUDGET_EPOCHS = 0, 1
 
 EXPORTS = ["imask_workspace_bytes", "imask_phi_floats", "imask_prepare", "imask_project",
            "imask_backproject", "imask_resample", "imask_sketch_apply", "imask_draws",
-           "imask_step", "imask_solve"]
+           "imask_step", "imask_solve", "imask_time_kernel", "imask_constants_scratch_bytes",
+           "imask_step_constants", "imask_sigma_thm3"]
+KERNEL_FORWARD, KERNEL_TRANSPOSE = 0, 1
 
 
 class Geometry(ctypes.Structure):
@@ -76,6 +78,13 @@ def lib():
         L.imask_resample.argtypes = [i32, i32, i32, P(Levels), vp, vp, vp]
         L.imask_sketch_apply.argtypes = [P(Geometry), P(Levels), i32, i32, vp, vp, vp, vp]
         L.imask_draws.argtypes = [P(Params), P(Levels), ctypes.c_uint64, i32, P(i32)]
+        L.imask_time_kernel.argtypes = [P(Geometry), i32, i32, vp, vp, vp, i32, vp, P(ctypes.c_double)]
+        L.imask_constants_scratch_bytes.argtypes = [P(Geometry)]
+        L.imask_constants_scratch_bytes.restype = sz
+        L.imask_step_constants.argtypes = [P(Geometry), P(Levels), ctypes.c_double, i32, ctypes.c_uint64, vp, vp,
+                                           P(ctypes.c_double), vp]
+        L.imask_sigma_thm3.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double, i32,
+                                       P(ctypes.c_double), P(ctypes.c_double)]
         L.imask_step.argtypes = [i32, P(Geometry), P(Levels), P(Reg), P(Params), P(vp), P(State), i32, vp]
         L.imask_solve.argtypes = [i32, P(Geometry), P(Levels), P(Reg), P(Params), P(vp), P(State),
                                   ctypes.c_double, i32, vp]

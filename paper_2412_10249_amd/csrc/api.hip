@@ -4,6 +4,7 @@
 // allocates, frees or synchronises.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -13,6 +14,9 @@
 namespace imk {
 
 static size_t align64(size_t f) { return (f + 63) & ~(size_t)63; }
+
+constexpr size_t kDotPartials = 256;                 // per-block partials of a dot product
+constexpr size_t kConstDotDoubles = kDotPartials + 64;  // partials + result, keeps floats aligned
 
 static int level_limit(int n)
 {
@@ -475,6 +479,254 @@ int imask_sketch_apply(const imask_geometry* g, const imask_levels* lv, int32_t 
         const float coef = (float)(-lv->p[j] / lv->p[0] / (double)(1 << (2 * l)));
         if (int rc = backproject_raw(L, W, l, in, out, coef, 1, 1, s)) return rc;
     }
+    return IMASK_OK;
+}
+
+int imask_time_kernel(const imask_geometry* g, int32_t which, int32_t log2f, const void* work, const float* in,
+                      float* out, int32_t reps, void* stream, double* avg_ms)
+{
+    if (!geometry_ok(g) || !work || !in || !out || !avg_ms || reps < 1) return IMASK_EINVAL;
+    const Layout L = make_layout(*g);
+    if (log2f < 0 || log2f > L.lmax) return IMASK_EINVAL;
+    if (which != IMASK_KERNEL_FORWARD && which != IMASK_KERNEL_TRANSPOSE) return IMASK_EINVAL;
+    float* W = (float*)work;
+    hipStream_t s = (hipStream_t)stream;
+    FwdArgs fa{};
+    BpArgs ba{};
+    if (which == IMASK_KERNEL_FORWARD) {
+        // stage the restricted image once, then time the projector kernel alone
+        if (int rc = imask_project(g, log2f, work, in, out, stream)) return rc;
+        fwd_common(L, W, fa);
+        fa.nterms = 1;
+        fa.term[0] = FwdTerm{W + L.zp[log2f], W + L.zpT[log2f], log2f, 1.0f, W + L.fpart[log2f], L.fbands[log2f],
+                             L.frows[log2f]};
+    } else {
+        ba.consts = (const RayConst*)(W + L.consts);
+        ba.n = L.n;
+        ba.na = L.na;
+        ba.nd = L.nd;
+        ba.lvl = log2f;
+        ba.y = in;
+        ba.out = out;
+        ba.coef = 1.0f;
+        ba.part = W + L.part;
+        ba.tmp = W + L.ptmp;
+    }
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return IMASK_EHIP;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return IMASK_EHIP;
+    }
+    int rc = IMASK_OK;
+    BpOwnArgs used;
+    if (hipEventRecord(e0, s) != hipSuccess) rc = IMASK_EHIP;
+    for (int r = 0; r < reps && rc == IMASK_OK; ++r) {
+        const hipError_t e = which == IMASK_KERNEL_FORWARD ? launch_fwd_terms(fa, s) : launch_bp_main(ba, s, used);
+        if (e != hipSuccess) rc = IMASK_EHIP;
+    }
+    float ms = 0.0f;
+    if (rc == IMASK_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                           hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        rc = IMASK_EHIP;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc == IMASK_OK) *avg_ms = (double)ms / reps;
+    return rc;
+}
+
+size_t imask_constants_scratch_bytes(const imask_geometry* g)
+{
+    if (!geometry_ok(g)) return 0;
+    const size_t d = (size_t)g->n * g->n, m = (size_t)g->n_angles * g->n_det;
+    return (3 * d + 3 * m) * sizeof(float) + (kConstDotDoubles) * sizeof(double);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Buffers of the power method, carved from the caller's scratch.
+struct PowerBufs {
+    float *x, *xs, *xt;  // image vectors
+    float *y, *ys, *yt;  // sinogram vectors
+    double* part;        // dot partials
+    double* dot;         // one dot result
+};
+
+struct PowerCtx {
+    const imask_geometry* g;
+    const imask_levels* lv;
+    const void* work;
+    hipStream_t s;
+    PowerBufs b;
+    size_t d, m;
+};
+
+int sk(PowerCtx& c, int k, int adj, const float* in, float* out)
+{
+    return imask_sketch_apply(c.g, c.lv, k, adj, c.work, in, out, (void*)c.s);
+}
+
+int zero(float* p, size_t n, hipStream_t s) { return launch_fill(p, n, 0.0f, s) == hipSuccess ? IMASK_OK : IMASK_EHIP; }
+
+// out = sum_k w_k K_k^T K_k v (image side) or sum_k w_k K_k K_k^T v (sinogram side)
+int gram(PowerCtx& c, bool image_side, const double* w, const float* v, float* out)
+{
+    const size_t no = image_side ? c.d : c.m;
+    if (int rc = zero(out, no, c.s)) return rc;
+    float* mid = image_side ? c.b.ys : c.b.xs;
+    float* t = image_side ? c.b.xt : c.b.yt;
+    for (int k = 0; k < c.lv->r; ++k) {
+        if (int rc = sk(c, k, image_side ? 0 : 1, v, mid)) return rc;
+        if (int rc = sk(c, k, image_side ? 1 : 0, mid, t)) return rc;
+        if (launch_axpy(out, t, (float)w[k], no, c.s) != hipSuccess) return IMASK_EHIP;
+    }
+    return IMASK_OK;
+}
+
+// out = Kbar^T Kbar v, Kbar = sum_k p_k K_k
+int kbar_gram(PowerCtx& c, const float* v, float* out)
+{
+    if (int rc = zero(c.b.ys, c.m, c.s)) return rc;
+    for (int k = 0; k < c.lv->r; ++k) {
+        if (int rc = sk(c, k, 0, v, c.b.yt)) return rc;
+        if (launch_axpy(c.b.ys, c.b.yt, (float)c.lv->p[k], c.m, c.s) != hipSuccess) return IMASK_EHIP;
+    }
+    if (int rc = zero(out, c.d, c.s)) return rc;
+    for (int k = 0; k < c.lv->r; ++k) {
+        if (int rc = sk(c, k, 1, c.b.ys, c.b.xt)) return rc;
+        if (launch_axpy(out, c.b.xt, (float)c.lv->p[k], c.d, c.s) != hipSuccess) return IMASK_EHIP;
+    }
+    return IMASK_OK;
+}
+
+int dot_host(PowerCtx& c, const float* a, const float* b, size_t n, double* out)
+{
+    if (launch_dot(a, b, n, c.b.part, c.b.dot, c.s) != hipSuccess) return IMASK_EHIP;
+    if (hipMemcpyAsync(out, c.b.dot, sizeof(double), hipMemcpyDeviceToHost, c.s) != hipSuccess) return IMASK_EHIP;
+    if (hipStreamSynchronize(c.s) != hipSuccess) return IMASK_EHIP;
+    return IMASK_OK;
+}
+
+// Largest eigenvalue of a symmetric PSD operator by the power method:
+// lambda = <v, A v> with v normalised, `iters` times.
+template <class Op>
+int power(PowerCtx& c, float* v, float* w, size_t n, int iters, unsigned long long seed, Op op, double* lam)
+{
+    if (launch_fill_random(v, n, seed, c.s) != hipSuccess) return IMASK_EHIP;
+    double nrm2 = 0.0;
+    if (int rc = dot_host(c, v, v, n, &nrm2)) return rc;
+    if (launch_scale(v, (float)(1.0 / std::sqrt(nrm2)), n, c.s) != hipSuccess) return IMASK_EHIP;
+    *lam = 0.0;
+    for (int it = 0; it < iters; ++it) {
+        if (int rc = op(v, w)) return rc;
+        if (int rc = dot_host(c, v, w, n, lam)) return rc;
+        if (int rc = dot_host(c, w, w, n, &nrm2)) return rc;
+        if (!(nrm2 > 0.0)) {
+            *lam = 0.0;
+            return IMASK_OK;
+        }
+        std::swap(v, w);
+        if (launch_scale(v, (float)(1.0 / std::sqrt(nrm2)), n, c.s) != hipSuccess) return IMASK_EHIP;
+    }
+    return IMASK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int imask_step_constants(const imask_geometry* g, const imask_levels* lv, double mu, int32_t iters, uint64_t seed,
+                         const void* work, void* scratch, double* out_host, void* stream)
+{
+    if (!geometry_ok(g) || !work || !scratch || !out_host || iters < 1 || !(mu > 0.0)) return IMASK_EINVAL;
+    if (!levels_ok(lv, level_limit(g->n))) return IMASK_EINVAL;
+    PowerCtx c;
+    c.g = g;
+    c.lv = lv;
+    c.work = work;
+    c.s = (hipStream_t)stream;
+    c.d = (size_t)g->n * g->n;
+    c.m = (size_t)g->n_angles * g->n_det;
+    double* dd = (double*)scratch;
+    c.b.part = dd;
+    c.b.dot = dd + kDotPartials;
+    float* f = (float*)(dd + kConstDotDoubles);
+    c.b.x = f;
+    c.b.xs = f + c.d;
+    c.b.xt = f + 2 * c.d;
+    c.b.y = f + 3 * c.d;
+    c.b.ys = c.b.y + c.m;
+    c.b.yt = c.b.ys + c.m;
+    double p[IMASK_MAX_LEVELS], p2[IMASK_MAX_LEVELS];
+    for (int k = 0; k < lv->r; ++k) {
+        p[k] = lv->p[k];
+        p2[k] = lv->p[k] * lv->p[k];
+    }
+    // iterates alternate x <-> xs (image side) and y <-> ys (sinogram side);
+    // the operators' temporaries are ys, yt, xt (image side) and xs, yt
+    // (sinogram side), disjoint from the iterates they work on
+    float* xv = c.b.x;
+    float* yv = c.b.y;
+    double l2 = 0, lbx = 0, lby = 0, lpx = 0, lpy = 0;
+    {
+        auto op = [&](const float* v, float* w) { return kbar_gram(c, v, w); };
+        if (int rc = power(c, xv, c.b.xs, c.d, iters, seed ^ 0x1ULL, op, &l2)) return rc;
+    }
+    {
+        auto op = [&](const float* v, float* w) { return gram(c, true, p2, v, w); };
+        if (int rc = power(c, xv, c.b.xs, c.d, iters, seed ^ 0x2ULL, op, &lbx)) return rc;
+    }
+    {
+        auto op = [&](const float* v, float* w) { return gram(c, true, p, v, w); };
+        if (int rc = power(c, xv, c.b.xs, c.d, iters, seed ^ 0x3ULL, op, &lpx)) return rc;
+    }
+    {
+        auto op = [&](const float* v, float* w) { return gram(c, false, p2, v, w); };
+        if (int rc = power(c, yv, c.b.ys, c.m, iters, seed ^ 0x4ULL, op, &lby)) return rc;
+    }
+    {
+        auto op = [&](const float* v, float* w) { return gram(c, false, p, v, w); };
+        if (int rc = power(c, yv, c.b.ys, c.m, iters, seed ^ 0x5ULL, op, &lpy)) return rc;
+    }
+    out_host[0] = l2 / mu;
+    out_host[1] = std::max(lbx, lby) / mu;
+    out_host[2] = std::max(lpx, lpy) / mu;
+    return IMASK_OK;
+}
+
+int imask_sigma_thm3(double L2, double Lbar2, double Lbarp2, double pmin, int32_t grid, double* sigma_out,
+                     double* theta_out)
+{
+    if (!(L2 > 0) || !(Lbar2 > 0) || !(Lbarp2 > 0) || !(pmin > 0 && pmin <= 1) || grid < 2 || !sigma_out)
+        return IMASK_EINVAL;
+    const double cbar = 1.0 / (1.0 + L2 + Lbarp2);
+    double best_theta = 2.0, best_eta = 0.0;
+    for (int ic = 1; ic <= grid; ++ic) {
+        const double c = cbar * ic / (grid + 1.0);
+        for (int ir = 1; ir <= grid; ++ir) {
+            const double rho = ir / (grid + 1.0);
+            // alpha^{-1} (eq. (alpha)); phi and psi of Sec. 3.5
+            const double ainv = (Lbar2 / (rho * c)) * (1.0 - (1.0 + L2) * c) / (1.0 - (1.0 + L2 + Lbarp2) * c);
+            double eta, theta;
+            if (pmin > ainv * c * c + (1.0 - rho) * c) {  // eq. (opt:cond): eta* = c
+                eta = c;
+                theta = 1.0 - (1.0 - rho) * c;
+            } else {  // eq. (eta_opt): phi(eta) = psi(eta)
+                const double q = ainv - 1.0 / c;
+                eta = std::fabs(q) < 1e-300 ? 0.5 * (pmin + rho * c)
+                                            : (std::sqrt(1.0 + q * (pmin + rho * c)) - 1.0) / q;
+                theta = (eta - c) * (eta - c) / c + 1.0 - (1.0 - rho) * c;
+            }
+            if (theta < best_theta) {
+                best_theta = theta;
+                best_eta = eta;
+            }
+        }
+    }
+    *sigma_out = best_eta / (1.0 - best_eta);
+    if (theta_out) *theta_out = best_theta;
     return IMASK_OK;
 }
 

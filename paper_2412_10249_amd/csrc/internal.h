@@ -184,12 +184,20 @@ void fwd_bands(int nl, int* bands, int* rows);
 hipError_t launch_consts(const imask_geometry& g, const Layout& L, float* work, hipStream_t s);
 hipError_t launch_fill(float* p, size_t count, float value, hipStream_t s);
 hipError_t launch_prep(const PrepArgs& a, hipStream_t s);
-hipError_t launch_fwd(const FwdArgs& a, hipStream_t s);
-hipError_t launch_bp(const BpArgs& a, hipStream_t s);
+hipError_t launch_fwd(const FwdArgs& a, hipStream_t s);        // projector kernels + reduce/epilogue
+hipError_t launch_fwd_terms(const FwdArgs& a, hipStream_t s);  // projector kernels only
+hipError_t launch_bp(const BpArgs& a, hipStream_t s);          // transpose kernel + ordered sum
+hipError_t launch_bp_main(const BpArgs& a, hipStream_t s, BpOwnArgs& used);  // transpose kernel only
 hipError_t launch_primal(const PrimalArgs& a, hipStream_t s);
 hipError_t launch_tv(const TvArgs& a, hipStream_t s);
 hipError_t launch_prolong(const float* in, float* out, int n, int lvl, float coef, hipStream_t s);
 hipError_t launch_project_block(const float* in, float* out, int n, int lvl, hipStream_t s);
+
+hipError_t launch_axpy(float* y, const float* x, float a, size_t n, hipStream_t s);
+hipError_t launch_scale(float* x, float a, size_t n, hipStream_t s);
+hipError_t launch_fill_random(float* x, size_t n, unsigned long long seed, hipStream_t s);
+// out = sum a[q] b[q] in FP64 (256 block partials in `part`, then one block)
+hipError_t launch_dot(const float* a, const float* b, size_t n, double* part, double* out, hipStream_t s);
 
 // pyramid tile side used by prep/primal for a set of levels up to lmax
 int tile_side(int n, int lmax);

@@ -219,8 +219,8 @@ __global__ void __launch_bounds__(1024) k_fwd_band(FwdBandArgs a)
     extern __shared__ float band[];
     const int nl = a.n >> a.lvl;
     const int P = nl + kPad;
-    const int bi = blockIdx.x % a.bands;
-    const int gidx = blockIdx.x / a.bands;
+    const int bi = blockIdx.x;    // band
+    const int gidx = blockIdx.y;  // angle group (row-stepping groups first)
     const int pass = gidx < a.groups_row ? 0 : 1;
     const int g = pass == 0 ? gidx : gidx - a.groups_row;
     const int npass = pass == 0 ? a.split.nrow : a.split.ncol;
@@ -352,9 +352,8 @@ __global__ void __launch_bounds__(64 * kBpWaves) k_bp_own(BpOwnArgs a)
     float* acc = smem;                                   // kBpRowsPerWg x S
     float* dummy = smem + kBpRowsPerWg * S;              // two cells per lane
     float* ybuf = dummy + kBpWaves * 128;                // a.batch x nd (W-scaled sinogram values)
-    const int nb = (nl + kBpRowsPerWg - 1) / kBpRowsPerWg;
-    const int bi = blockIdx.x % nb;
-    const int gidx = blockIdx.x / nb;
+    const int bi = blockIdx.x;    // band of kBpRowsPerWg rows
+    const int gidx = blockIdx.y;  // pass * G + angle group
     const int pass = gidx / a.G;
     const int g = gidx - pass * a.G;
     const int npass = pass == 0 ? a.split.nrow : a.split.ncol;
@@ -706,6 +705,63 @@ __global__ void k_project_block(const float* in, float* out, int n, int lvl)
     out[q] = s / (float)(f * f);
 }
 
+// ------------------------------------------------------- vector utilities
+
+// y += a x
+__global__ void k_axpy(float* y, const float* x, float a, size_t n)
+{
+    for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (size_t)gridDim.x * blockDim.x)
+        y[q] = fmaf(a, x[q], y[q]);
+}
+
+// x *= a
+__global__ void k_scale(float* x, float a, size_t n)
+{
+    for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (size_t)gridDim.x * blockDim.x)
+        x[q] *= a;
+}
+
+// x[q] = uniform(-1, 1) from SplitMix64 of (seed, q)
+__global__ void k_fill_random(float* x, size_t n, unsigned long long seed)
+{
+    for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (size_t)gridDim.x * blockDim.x) {
+        unsigned long long z = seed + (q + 1) * 0x9E3779B97F4A7C15ULL;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+        z ^= z >> 31;
+        x[q] = (float)((double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0);
+    }
+}
+
+// Per-block FP64 partial sums of a[q] * b[q] (fixed block count, fixed order).
+constexpr int kDotBlocks = 256;
+__global__ void __launch_bounds__(256) k_dot_partial(const float* a, const float* b, size_t n, double* part)
+{
+    __shared__ double red[256];
+    double acc = 0.0;
+    for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (size_t)gridDim.x * blockDim.x)
+        acc += (double)a[q] * (double)b[q];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(256) k_dot_final(const double* part, double* out)
+{
+    __shared__ double red[kDotBlocks];
+    red[threadIdx.x] = part[threadIdx.x];
+    __syncthreads();
+    for (int w = kDotBlocks / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0];
+}
+
 }  // namespace
 
 // ----------------------------------------------------------------- launchers
@@ -770,7 +826,7 @@ static hipError_t allow_lds(const void* fn, int bytes)
     return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
-hipError_t launch_fwd(const FwdArgs& a, hipStream_t s)
+hipError_t launch_fwd_terms(const FwdArgs& a, hipStream_t s)
 {
     const AngleSplit sp = angle_split(a.na);
     for (int t = 0; t < a.nterms; ++t) {
@@ -796,8 +852,7 @@ hipError_t launch_fwd(const FwdArgs& a, hipStream_t s)
             const int lds = (int)(sizeof(float) * (size_t)fb.R * (nl + kPad));
             hipError_t e = allow_lds((const void*)k_fwd_band, lds);
             if (e != hipSuccess) return e;
-            const int grid = tm.bands * (fb.groups_row + fb.groups_col);
-            hipLaunchKernelGGL(k_fwd_band, dim3(grid), dim3(1024), lds, s, fb);
+            hipLaunchKernelGGL(k_fwd_band, dim3(tm.bands, fb.groups_row + fb.groups_col), dim3(1024), lds, s, fb);
         } else {
             const int wpa = (a.nd + 63) / 64;
             const long waves = (long)wpa * a.na;
@@ -806,15 +861,22 @@ hipError_t launch_fwd(const FwdArgs& a, hipStream_t s)
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
+    return hipSuccess;
+}
+
+hipError_t launch_fwd(const FwdArgs& a, hipStream_t s)
+{
+    hipError_t e = launch_fwd_terms(a, s);
+    if (e != hipSuccess) return e;
     const size_t m = (size_t)a.na * a.nd;
     const unsigned blocks = (unsigned)std::min<size_t>((m + 255) / 256, 8192);
     hipLaunchKernelGGL(k_fwd_reduce, dim3(blocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_bp(const BpArgs& ba, hipStream_t s)
+hipError_t launch_bp_main(const BpArgs& ba, hipStream_t s, BpOwnArgs& a)
 {
-    BpOwnArgs a{};
+    a = BpOwnArgs{};
     a.consts = ba.consts;
     a.n = ba.n;
     a.na = ba.na;
@@ -840,7 +902,7 @@ hipError_t launch_bp(const BpArgs& ba, hipStream_t s)
                               ((size_t)kBpRowsPerWg * (nl + 2 * kBpPad) + kBpWaves * 128 + (size_t)a.batch * ba.nd));
         e = allow_lds((const void*)k_bp_own, lds);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_bp_own, dim3(nb * 2 * a.G), dim3(64 * kBpWaves), lds, s, a);
+        hipLaunchKernelGGL(k_bp_own, dim3(nb, 2 * a.G), dim3(64 * kBpWaves), lds, s, a);
     } else {
         // gather: about 1024 workgroups, G N_l^2 <= 16 N^2 partials
         const int t = (nl + 15) / 16;
@@ -849,8 +911,15 @@ hipError_t launch_bp(const BpArgs& ba, hipStream_t s)
         a.nq = a.G;
         hipLaunchKernelGGL(k_bp_gather, dim3(t, t, a.G), dim3(256), 0, s, a);
     }
-    e = hipGetLastError();
+    return hipGetLastError();
+}
+
+hipError_t launch_bp(const BpArgs& ba, hipStream_t s)
+{
+    BpOwnArgs a;
+    hipError_t e = launch_bp_main(ba, s, a);
     if (e != hipSuccess) return e;
+    const int nl = ba.n >> ba.lvl;
     const size_t d = (size_t)nl * nl;
     hipLaunchKernelGGL(k_bp_sum, dim3((unsigned)((d + 255) / 256)), dim3(256), 0, s, a, ba.tmp);
     e = hipGetLastError();
@@ -890,6 +959,43 @@ hipError_t launch_project_block(const float* in, float* out, int n, int lvl, hip
 {
     const size_t count = (size_t)n * n;
     hipLaunchKernelGGL(k_project_block, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, in, out, n, lvl);
+    return hipGetLastError();
+}
+
+}  // namespace imk
+
+namespace imk {
+
+static unsigned vec_blocks(size_t n)
+{
+    size_t b = (n + 255) / 256;
+    return (unsigned)std::max<size_t>(1, std::min<size_t>(b, 2048));
+}
+
+hipError_t launch_axpy(float* y, const float* x, float a, size_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_axpy, dim3(vec_blocks(n)), dim3(256), 0, s, y, x, a, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale(float* x, float a, size_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_scale, dim3(vec_blocks(n)), dim3(256), 0, s, x, a, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_random(float* x, size_t n, unsigned long long seed, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill_random, dim3(vec_blocks(n)), dim3(256), 0, s, x, n, seed);
+    return hipGetLastError();
+}
+
+hipError_t launch_dot(const float* a, const float* b, size_t n, double* part, double* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(256), 0, s, a, b, n, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(kDotBlocks), 0, s, (const double*)part, out);
     return hipGetLastError();
 }
 

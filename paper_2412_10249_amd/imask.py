@@ -166,6 +166,40 @@ def sketch_apply(g: Geometry, levels: Levels, k: int, inp: torch.Tensor, adjoint
     return out
 
 
+def time_kernel(g: Geometry, which: int, log2f: int, inp: torch.Tensor, work: torch.Tensor, reps: int = 10) -> float:
+    """Average launch duration (s) of one projector kernel, HIP events on the current stream."""
+    if which == _abi.KERNEL_FORWARD:
+        _need(inp, g.image_shape, "in")
+        out = torch.empty(g.sino_shape, dtype=torch.float32, device=inp.device)
+    else:
+        _need(inp, g.sino_shape, "in")
+        out = torch.empty(1, dtype=torch.float32, device=inp.device)
+    ms = ctypes.c_double()
+    check(lib().imask_time_kernel(ctypes.byref(g.c()), which, log2f, _ptr(work), _ptr(inp), _ptr(out), reps,
+                                  _stream(), ctypes.byref(ms)), "imask_time_kernel")
+    return ms.value / 1e3
+
+
+def step_constants(g: Geometry, levels: Levels, mu: float, work: torch.Tensor, iters: int = 60, seed: int = 7):
+    """(L^2, Lbar^2, Lbar_p^2) of Sec. 3.4 by power iterations on the GPU operators."""
+    nbytes = lib().imask_constants_scratch_bytes(ctypes.byref(g.c()))
+    if nbytes == 0:
+        raise ImaskError("invalid geometry")
+    scratch = torch.empty(nbytes, dtype=torch.uint8, device=work.device)
+    out = (ctypes.c_double * 3)()
+    check(lib().imask_step_constants(ctypes.byref(g.c()), ctypes.byref(levels.c()), mu, iters, seed, _ptr(work),
+                                     _ptr(scratch), out, _stream()), "imask_step_constants")
+    return out[0], out[1], out[2]
+
+
+def sigma_thm3(L2: float, Lbar2: float, Lbarp2: float, pmin: float, grid: int = 200):
+    """(sigma, theta) from Thm. 3 minimised over a (c, rho) grid."""
+    sig, th = ctypes.c_double(), ctypes.c_double()
+    check(lib().imask_sigma_thm3(L2, Lbar2, Lbarp2, pmin, grid, ctypes.byref(sig), ctypes.byref(th)),
+          "imask_sigma_thm3")
+    return sig.value, th.value
+
+
 def draws(params: Params, levels: Levels, k0: int, count: int) -> np.ndarray:
     out = (ctypes.c_int32 * max(count, 1))()
     check(lib().imask_draws(ctypes.byref(params.c()), ctypes.byref(levels.c()), k0, count, out), "imask_draws")

@@ -96,3 +96,21 @@ def test_host_draws_match_oracle_bitwise(seed, stream, p):
     got = im.draws(im.Params(0.1, seed, stream), lv, 1000, 100_000)
     exp = oracle.draws(seed, stream, 1000, 100_000, list(p))
     assert np.array_equal(got, exp)
+
+
+@pytest.mark.parametrize("consts", [(6.0, 2.0, 6.0, 1 / 3), (543.0, 181.0, 543.0, 1 / 3), (5.7, 1.9, 5.8, 0.25),
+                                    (50.0, 0.5, 80.0, 0.1)])
+def test_sigma_thm3_matches_oracle(consts):
+    from oracle import steps
+
+    L2, lb, lp, pmin = consts
+    sig, th = im.sigma_thm3(L2, lb, lp, pmin, 60)
+    osig, oth, _, _ = steps.sigma_thm3(L2, lb, lp, pmin, 60, 60)
+    assert sig == pytest.approx(osig, rel=1e-12) and th == pytest.approx(oth, rel=1e-12)
+
+
+def test_sigma_thm3_rejects_bad_constants():
+    with pytest.raises(im.ImaskError):
+        im.sigma_thm3(-1.0, 1.0, 1.0, 0.5)
+    with pytest.raises(im.ImaskError):
+        im.sigma_thm3(1.0, 1.0, 1.0, 0.0)

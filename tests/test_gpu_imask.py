@@ -144,3 +144,24 @@ def test_solve_epoch_budget():
     assert costs.sum() == prob.epochs >= 5.0 and costs[:-1].sum() < 5.0
     prob.solve(7, pk.BUDGET_ITERS)
     assert prob.k == len(seq) + 7
+
+
+@pytest.mark.parametrize("mode", [pk.FULL_PAPER, pk.FULL_UNBIASED])
+def test_step_constants_match_dense_oracle(mode):
+    """Power iterations on the GPU operators vs eigenvalues of the oracle's
+    explicit matrices (Sec. 3.4 constants, normalised by mu)."""
+    from oracle import steps
+
+    n, na, nd = 16, 24, 24
+    g = pk.Geometry(n, na, nd)
+    lv = pk.Levels((0, 1, 2), (0.5, 0.3, 0.2), mode)
+    og = oracle.Geometry(n, na, nd)
+    olv = oracle.Levels([0, 1, 2], [0.5, 0.3, 0.2], mode)
+    Ks = [oracle.dense_matrix(lambda e, k=k: oracle.sketch_fwd(og, olv, k, e), (n, n), na * nd) for k in range(3)]
+    mu = 0.1
+    exp = steps.constants_dense(Ks, olv.p, mu)
+    got = pk.step_constants(g, lv, mu, pk.workspace(g), iters=400)
+    np.testing.assert_allclose(got, exp, rtol=2e-4)
+    sig, th = pk.sigma_thm3(*got, 0.2, 60)
+    osig, oth, _, _ = steps.sigma_thm3(*exp, 0.2, 60, 60)
+    assert sig == pytest.approx(osig, rel=1e-3) and 0 < th < 1

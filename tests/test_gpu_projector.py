@@ -146,6 +146,23 @@ def test_full_size_projector_pair():
         assert rel(got, oracle.prolong(oracle.backproject(og, l, y), l) / 4 ** l) <= 1e-5
 
 
+def test_large_grid_projector_pair():
+    """1024^2 grid, 1536 angles x 1536 bins: the level-0 forward exceeds one
+    LDS band (direct path) and the scatter stages two angles per batch."""
+    n, na, nd = 1024, 1536, 1536
+    g = pk.Geometry(n, na, nd)
+    og = oracle.Geometry(n, na, nd)
+    work = pk.workspace(g)
+    x = f32(synth.random_image(n, 21))
+    y = f32(synth.random_sinogram(na, nd, 22))
+    for l in (0, 1):
+        say(f"1024 grid level {l}")
+        got = host(pk.project(g, l, dev(x), work))
+        assert rel(got, oracle.project(og, l, oracle.restrict(x, l))) <= 1e-5
+        got = host(pk.backproject(g, l, dev(y), work))
+        assert rel(got, oracle.prolong(oracle.backproject(og, l, y), l) / 4 ** l) <= 1e-5
+
+
 def test_projection_is_deterministic():
     g = pk.Geometry(128, 180, 192)
     work = pk.workspace(g)

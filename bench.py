@@ -56,8 +56,10 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def sample_counts(n, na, nd, lvl):
-    """Samples (ray, step) with a tap inside the level-l image (geometry only)."""
+def sample_counts(n, na, nd, lvl, angle_stride=1):
+    """Samples (ray, step) with a tap inside the level-l image (geometry only).
+    With angle_stride > 1 only every stride-th angle is counted and the total
+    is scaled up (an estimate, for large batches of geometries)."""
     nl = n >> lvl
     h = 2.0 / nl
     th = np.arange(na) * np.pi / na
@@ -66,7 +68,8 @@ def sample_counts(n, na, nd, lvl):
     c0 = -1.0 + 0.5 * h
     total = 0
     k = -1.0 + (np.arange(nl) + 0.5) * h
-    for a in range(na):
+    picked = range(0, na, angle_stride)
+    for a in picked:
         ct, st = np.cos(th[a]), np.sin(th[a])
         if rows[a]:
             u = ((s[:, None] - k[None, :] * st) / ct - c0) / h
@@ -74,7 +77,7 @@ def sample_counts(n, na, nd, lvl):
             u = ((s[:, None] - k[None, :] * ct) / st - c0) / h
         q = np.floor(u)
         total += int(np.count_nonzero((q >= -1) & (q < nl)))
-    return total
+    return total if angle_stride == 1 else int(round(total * na / len(picked)))
 
 
 def cpu_baseline(b, budget_s=12.0):
@@ -373,7 +376,9 @@ def batched(args):
             sig[n] = _sigma_for(geom, lv, 1e-2, pk.workspace(geom))
         probs.append(pk.Problem(geom, lv, reg, pk.Params(sig[n], SEED, s), data[n][s % 2]))
     torch.cuda.synchronize()
-    rays_per_epoch = sum(p.geom.n_angles * p.geom.n_det for p in probs)
+    # one epoch = one full-resolution projection and one backprojection
+    s0 = {n: sample_counts(n, 3 * n // 2, 3 * n // 2, 0, angle_stride=16) for n in sizes}
+    samples_per_epoch = sum(2 * s0[p.geom.n] for p in probs)
     runner = batch.BatchRunner(probs, n_streams=args.streams)
     t0 = time.perf_counter()
     runner.solve_all(args.epochs, pk.BUDGET_EPOCHS)
@@ -381,19 +386,24 @@ def batched(args):
     el = time.perf_counter() - t0
     tot_epochs = sum(p.epochs for p in probs)
     log(f"batch done: {len(probs)} slices, {tot_epochs:.1f} slice-epochs in {el:.2f} s")
-    # the same slices alone, one after another on one stream, for equality and speed-up
+    # the same slices alone, one after another on one stream: equality and the overlap gain
     same = []
     t1 = time.perf_counter()
-    for s in (0, 4):
-        p = probs[s]
+    for s, p in enumerate(probs):
         q = pk.Problem(p.geom, lv, reg, pk.Params(sig[p.geom.n], SEED, s), data[p.geom.n][s % 2])
         q.solve(args.epochs, pk.BUDGET_EPOCHS)
-        torch.cuda.synchronize()
-        same.append(bool(torch.equal(q.x_cur, p.x_cur)))
+        if s % 5 == 0:
+            same.append(q.x_cur)
+        else:
+            del q
+    torch.cuda.synchronize()
+    seq = time.perf_counter() - t1
+    same = [bool(torch.equal(q, probs[5 * i].x_cur)) for i, q in enumerate(same)]
     print(json.dumps({"metric": "batched ImaSk, 64 mixed slices", "slices": len(probs), "streams": args.streams,
                       "epochs_per_slice": args.epochs, "seconds": el, "slice_epochs_per_s": tot_epochs / el,
-                      "full_res_ray_epochs_per_s": rays_per_epoch * args.epochs / el,
-                      "equal_to_alone": same, "alone_check_seconds": time.perf_counter() - t1}), flush=True)
+                      "samples_per_s": samples_per_epoch * args.epochs / el,
+                      "sequential_seconds": seq, "overlap_speedup": seq / el,
+                      "equal_to_alone": all(same), "checked_slices": len(same)}), flush=True)
 
 
 def serving(args):
@@ -433,8 +443,11 @@ def serving(args):
                      "wall_s": time.perf_counter() - t0})
         log(f"rate {rate}: {summ}")
         out.append(summ)
+    # sustainable: the queue drains within a second of the arrival window
+    ok = [r["offered_per_s"] for r in out if r["wall_s"] <= args.window + 1.0]
     print(json.dumps({"metric": "serving ImaSk reconstructions, p50/p99 latency", "slots": args.slots,
-                      "epochs_per_request": args.serve_epochs, "results": out}), flush=True)
+                      "epochs_per_request": args.serve_epochs, "window_s": args.window,
+                      "highest_sustained_rate_per_s": max(ok) if ok else None, "results": out}), flush=True)
 
 
 def autograd_bench(args):
@@ -463,7 +476,7 @@ def autograd_bench(args):
         for s in range(xin.shape[0]):
             b = ag.ProjectFn.apply(xin[s], geom, 0, work)
             xk = ag.unrolled_imask(b, lam_, geom, lv, sigma, 10, stream_id=s, work=work, checkpoint_every=2)
-            tot = tot + 0.5 * ((xk - xs[s]) ** 2).sum()
+            tot = tot + 0.5 * ((xk - xs[s]).double() ** 2).sum()
         return tot
 
     L = loss(x_in, lam)
@@ -476,7 +489,7 @@ def autograd_bench(args):
     el = time.perf_counter() - t0
     d = torch.randn_like(x_in)
     with torch.no_grad():
-        h = 1e-2
+        h = 1.0  # the loss is quadratic in x_in, so the central difference is exact
         fd = (loss(x_in + h * d, lam) - loss(x_in - h * d, lam)) / (2 * h)
         hl = 1e-4
         fdl = (loss(x_in, lam + hl) - loss(x_in, lam - hl)) / (2 * hl)
@@ -585,8 +598,8 @@ def main():
     ap.add_argument("--streams", type=int, default=8)
     ap.add_argument("--epochs", type=float, default=30.0)
     ap.add_argument("--serve", action="store_true", help="continuous-batching server under Poisson load")
-    ap.add_argument("--rates", type=float, nargs="+", default=[25.0, 50.0, 100.0, 200.0])
-    ap.add_argument("--window", type=float, default=2.0)
+    ap.add_argument("--rates", type=float, nargs="+", default=[50.0, 75.0, 100.0, 125.0, 150.0, 200.0])
+    ap.add_argument("--window", type=float, default=10.0)
     ap.add_argument("--slots", type=int, default=16)
     ap.add_argument("--hbm-gb", type=float, default=64.0)
     ap.add_argument("--chunk", type=float, default=2.0)

@@ -114,7 +114,6 @@ struct BpOwnArgs {
     float* part;  // nq partial images N_l x N_l, image orientation
     int G;
     int nq;     // partial images to sum (2 G for the scatter, G for the gather)
-    int batch;  // angles whose sinogram rows are staged in LDS together
     AngleSplit split;
     float* out;
     float coef;

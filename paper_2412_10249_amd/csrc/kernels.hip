@@ -321,11 +321,34 @@ __global__ void __launch_bounds__(256) k_fwd_reduce(FwdArgs a)
 // touch the same pixel; each pixel therefore receives its contributions in
 // program order and the result is deterministic.  The weights come from the
 // same fixed-point coordinate as the forward: the pair is an exact transpose.
-// The sinogram values of a batch of angles are staged in LDS first.
-constexpr int kBpPad = 8;
-constexpr int kBpRowsPerWave = 2;
-constexpr int kBpWaves = 4;
+// Sinogram values are read from global memory, one trip ahead of their use.
+//
+// Taps are not range-tested per sample.  Every bin of a workgroup's range
+// reaches [-1, nl] at one of its kBpRowsPerWg rows, and the coordinate moves
+// by at most one pixel per row (|slope| <= 1 on the stepping axis), so at any
+// row of the workgroup the left tap lies in [-(rows+1), nl+rows-1].  Each LDS
+// row of S = nl + 2 kBpPad cells puts kBpPad >= rows+3 spare cells on both
+// sides; a tap's cell index (tap + kBpPad) is clamped as an unsigned number to
+// S-2, so every tap outside the row (beyond either end) lands in the last two
+// cells, which no in-range tap reaches and which are never read back.  Only
+// lanes whose bin lies past the range (zero contributions) get there.
+// Unclamped lanes stay on the bin lattice, so they never share a cell within
+// one instruction.
+#ifndef IMK_BP_ROWS_PER_WAVE
+#define IMK_BP_ROWS_PER_WAVE 2
+#endif
+#ifndef IMK_BP_CHUNKS
+#define IMK_BP_CHUNKS 2
+#endif
+#ifndef IMK_BP_WAVES
+#define IMK_BP_WAVES 8
+#endif
+constexpr int kBpRowsPerWave = IMK_BP_ROWS_PER_WAVE;
+constexpr int kBpChunks = IMK_BP_CHUNKS;  // 64-ray chunks per trip of a wavefront
+constexpr int kBpWaves = IMK_BP_WAVES;
 constexpr int kBpRowsPerWg = kBpRowsPerWave * kBpWaves;
+constexpr int kBpPad = kBpRowsPerWg + 4;
+static_assert(kBpPad >= kBpRowsPerWg + 3, "sink cells must lie beyond every in-range tap");
 
 // Bins whose coordinate at steps r0 .. r0+nr-1 can reach [-1, nl].
 __device__ __forceinline__ void bin_range(const RayConst& kc, int r0, int nrows, int nl, int nd, int& blo, int& cnt)
@@ -340,18 +363,88 @@ __device__ __forceinline__ void bin_range(const RayConst& kc, int r0, int nrows,
     cnt = bhi - blo + 1;
 }
 
+// LDS offset of the row of chain c (chains run over chunks, then rows).
+__device__ __forceinline__ int rr_offset(int c, int S) { return (c % kBpRowsPerWave) * S; }
+
 // Compiler-only ordering point: LDS operations of one wavefront execute in
 // program order, so this is all that is needed between the two phases.
 #define IMK_LDS_ORDER() asm volatile("" ::: "memory")
+
+// One trip of a wavefront over CH chunks of 64 rays and its kBpRowsPerWave
+// rows (chains chunk-major): both taps of every sample, as two
+// read-modify-write phases.  U[c] is chain c's shifted coordinate, wy[h] the
+// weighted sinogram value of chunk h's ray (zero past the bin range).  With
+// CLAMP the cell index is clamped (lanes past the range); without it every
+// lane of the trip is in range and its taps lie inside the padded row.
+template <int CH, bool CLAMP>
+__device__ __forceinline__ void scatter_trip(float* rows, int S, const long long* U, const float* wy)
+{
+    constexpr int NC = CH * kBpRowsPerWave;
+    int cl[NC];
+    float omw[NC], cw[NC], wys[CH];
+#pragma unroll
+    for (int h = 0; h < CH; ++h) wys[h] = wy[h] * kTwoM32;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        const unsigned hi = (unsigned)(U[c] >> 32);
+        // unsigned clamp: taps past either end land in the last two cells
+        const unsigned jj = CLAMP ? min(hi, (unsigned)(S - 2)) : hi;
+        const float cu = (float)(unsigned)(U[c] & 0xffffffffLL);
+        cl[c] = rr_offset(c, S) + (int)jj;
+        cw[c] = cu;
+        omw[c] = fmaf(cu, -kTwoM32, 1.0f);  // 1 - w, exactly as in the forward
+    }
+    float old[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) old[c] = rows[cl[c]];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) rows[cl[c]] = fmaf(omw[c], wy[c / kBpRowsPerWave], old[c]);
+    IMK_LDS_ORDER();
+#pragma unroll
+    for (int c = 0; c < NC; ++c) old[c] = rows[cl[c] + 1];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) rows[cl[c] + 1] = fmaf(cw[c], wys[c / kBpRowsPerWave], old[c]);
+    IMK_LDS_ORDER();
+}
+
+__device__ __forceinline__ long long uniform64(long long v)
+{
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)(v & 0xffffffffLL));
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)((unsigned long long)v >> 32));
+    return (long long)(((unsigned long long)hi << 32) | lo);
+}
+
+// Raw buffer view of n floats: loads at or past the end return zero.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t float_buffer(const float* base, int n)
+{
+    return __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, n * 4, 0x00020000);
+}
+
+// The whole byte offset goes in the per-lane operand, which is the part the
+// range check covers.
+__device__ __forceinline__ float buffer_float(__amdgpu_buffer_rsrc_t r, int byte_offset)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, byte_offset, 0, 0));
+}
+
+// What a wavefront needs of one angle, tabulated in LDS by the workgroup.
+struct BpAngle {
+    long long afx, bfx, cfx;  // fixed-point coordinate constants
+    float w;                  // ray weight
+    int phases;
+    int blo, cnt;             // bins of the workgroup's range
+    int ang, pad;
+};
+static_assert(sizeof(BpAngle) == 48, "BpAngle layout");
+constexpr int kBpAngTab = 128;  // angles a workgroup tabulates at once
 
 __global__ void __launch_bounds__(64 * kBpWaves) k_bp_own(BpOwnArgs a)
 {
     extern __shared__ float smem[];
     const int nl = a.n >> a.lvl;
     const int S = nl + 2 * kBpPad;
-    float* acc = smem;                                   // kBpRowsPerWg x S
-    float* dummy = smem + kBpRowsPerWg * S;              // two cells per lane
-    float* ybuf = dummy + kBpWaves * 128;                // a.batch x nd (W-scaled sinogram values)
+    float* acc = smem;                                     // kBpRowsPerWg x S
+    BpAngle* tab = reinterpret_cast<BpAngle*>(smem + ((kBpRowsPerWg * S + 3) & ~3));
     const int bi = blockIdx.x;    // band of kBpRowsPerWg rows
     const int gidx = blockIdx.y;  // pass * G + angle group
     const int pass = gidx / a.G;
@@ -367,65 +460,80 @@ __global__ void __launch_bounds__(64 * kBpWaves) k_bp_own(BpOwnArgs a)
     const int r0 = rwg + wave * kBpRowsPerWave;        // first row of this wavefront
     const int nown = max(0, min(kBpRowsPerWave, nl - r0));
     float* rows = acc + (size_t)wave * kBpRowsPerWave * S;
-    float* mine = dummy + wave * 128 + 2 * lane;       // private sink (2 cells) for idle lanes
     for (int q = lane; q < kBpRowsPerWave * S; q += 64) rows[q] = 0.0f;
-    for (int kb = 0; kb < nang; kb += a.batch) {
-        const int nbat = min(a.batch, nang - kb);
-        __syncthreads();  // the previous batch's values are consumed
-        for (int t = 0; t < nbat; ++t) {
+    constexpr int NC = kBpChunks * kBpRowsPerWave;
+    for (int kb = 0; kb < nang; kb += kBpAngTab) {
+        const int nk = min(kBpAngTab, nang - kb);
+        __syncthreads();  // the previous block of the table is consumed
+        for (int t = threadIdx.x; t < nk; t += blockDim.x) {
             const int ang = angle_of(a.split, pass, k0 + kb + t);
             const RayConst& kc = a.consts[(size_t)a.lvl * a.na + ang];
-            int blo, cnt;
-            bin_range(kc, rwg, nwg, nl, a.nd, blo, cnt);
-            const float* yr = a.y + (size_t)ang * a.nd + blo;
-            for (int q = threadIdx.x; q < cnt; q += blockDim.x) ybuf[t * a.nd + q] = kc.w * yr[q];
+            BpAngle e;
+            e.afx = kc.afx;
+            e.bfx = kc.bfx;
+            e.cfx = kc.cfx;
+            e.w = kc.w;
+            e.phases = kc.phases;
+            bin_range(kc, rwg, nwg, nl, a.nd, e.blo, e.cnt);
+            e.ang = ang;
+            e.pad = 0;
+            tab[t] = e;
         }
         __syncthreads();
         if (nown == 0) continue;
-        for (int t = 0; t < nbat; ++t) {
-            const int ang = angle_of(a.split, pass, k0 + kb + t);
-            const RayConst& kc = a.consts[(size_t)a.lvl * a.na + ang];
-            int blo, cnt;
-            bin_range(kc, rwg, nwg, nl, a.nd, blo, cnt);
+        for (int t = 0; t < nk; ++t) {
+            const BpAngle& e = tab[t];
+            const int cnt = __builtin_amdgcn_readfirstlane(e.cnt);
             if (cnt <= 0) continue;
-            const int P = kc.phases;
-            const float* yb = ybuf + t * a.nd;
-            const long long urow = kc.cfx + (long long)r0 * kc.afx;
-            const long long cstep = (long long)64 * P * kc.bfx;
+            const int blo = __builtin_amdgcn_readfirstlane(e.blo);
+            const int ang = __builtin_amdgcn_readfirstlane(e.ang);
+            const int P = __builtin_amdgcn_readfirstlane(e.phases);
+            const float kw = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, e.w)));
+            // register copies: the ordering points below must not force reloads
+            const long long afx = uniform64(e.afx), bfx = uniform64(e.bfx), cfx = uniform64(e.cfx);
+            // sinogram values of the range, read straight from global memory
+            // (L2/MALL-resident; lanes read consecutive bins), one trip ahead
+            const __amdgpu_buffer_rsrc_t yr = float_buffer(a.y + (size_t)ang * a.nd + blo, cnt);
+            const int vb = lane * P * 4;
+            const long long urow = cfx + (long long)r0 * afx + ((long long)kBpPad << 32);
+            const long long cstep = (long long)64 * P * bfx;
+            const int tstride = kBpChunks * 64 * P;
+            const int full_end = cnt - (kBpChunks * 64 - 1) * P;  // trips starting below this are full
             for (int ph = 0; ph < P; ++ph) {
-                long long u = urow + (long long)(blo + lane * P + ph) * kc.bfx;
-                // two chunks of 64 rays x the wavefront's rows per trip: four
-                // independent read-modify-write chains per phase
-                for (int c0 = ph; c0 < cnt; c0 += 128 * P, u += 2 * cstep) {
-                    float* cl[2 * kBpRowsPerWave];
-                    float lv[2 * kBpRowsPerWave], rv[2 * kBpRowsPerWave];
+                // per chain (chunk h, row rr) the coordinate of its current ray,
+                // shifted by kBpPad pixels so that its high word is the cell
+                // index of the left tap within the padded LDS row
+                long long U[NC];
+                {
+                    const long long u0 = urow + (long long)(blo + ph) * bfx + (long long)(lane * P) * bfx;
 #pragma unroll
-                    for (int h = 0; h < 2; ++h) {
-                        const int idx = c0 + h * 64 * P + lane * P;
-                        const bool vb = idx < cnt;
-                        const float wy = vb ? yb[idx] : 0.0f;
-                        long long ur = u + h * cstep;
+                    for (int h = 0; h < kBpChunks; ++h)
 #pragma unroll
-                        for (int rr = 0; rr < kBpRowsPerWave; ++rr, ur += kc.afx) {
-                            const int j = tap_index(ur);
-                            const bool ok = vb && rr < nown && j >= -1 && j <= nl - 1;
-                            const float w = tap_weight(ur);
-                            cl[h * kBpRowsPerWave + rr] = ok ? rows + rr * S + kBpPad + j : mine;
-                            lv[h * kBpRowsPerWave + rr] = (1.0f - w) * wy;
-                            rv[h * kBpRowsPerWave + rr] = w * wy;
-                        }
+                        for (int rr = 0; rr < kBpRowsPerWave; ++rr) U[h * kBpRowsPerWave + rr] = u0 + h * cstep + rr * afx;
+                }
+                const long long trip = kBpChunks * cstep;
+                float ynext[kBpChunks];
+#pragma unroll
+                for (int h = 0; h < kBpChunks; ++h) ynext[h] = buffer_float(yr, vb + (ph + h * 64 * P) * 4);
+                int c0 = ph;
+                for (; c0 < full_end; c0 += tstride) {
+                    float wy[kBpChunks];
+#pragma unroll
+                    for (int h = 0; h < kBpChunks; ++h) {
+                        wy[h] = kw * ynext[h];
+                        ynext[h] = buffer_float(yr, vb + (c0 + tstride + h * 64 * P) * 4);
                     }
-                    float old[2 * kBpRowsPerWave];
+                    scatter_trip<kBpChunks, false>(rows, S, U, wy);
 #pragma unroll
-                    for (int c = 0; c < 2 * kBpRowsPerWave; ++c) old[c] = cl[c][0];
+                    for (int c = 0; c < NC; ++c) U[c] += trip;
+                }
+                // the rest one chunk at a time, on the chains of chunk 0
+                for (; c0 < cnt; c0 += 64 * P) {
+                    float wy = kw * ynext[0];
+                    ynext[0] = buffer_float(yr, vb + (c0 + 64 * P) * 4);
+                    scatter_trip<1, true>(rows, S, U, &wy);
 #pragma unroll
-                    for (int c = 0; c < 2 * kBpRowsPerWave; ++c) cl[c][0] = old[c] + lv[c];
-                    IMK_LDS_ORDER();
-#pragma unroll
-                    for (int c = 0; c < 2 * kBpRowsPerWave; ++c) old[c] = cl[c][1];
-#pragma unroll
-                    for (int c = 0; c < 2 * kBpRowsPerWave; ++c) cl[c][1] = old[c] + rv[c];
-                    IMK_LDS_ORDER();
+                    for (int rr = 0; rr < kBpRowsPerWave; ++rr) U[rr] += cstep;
                 }
             }
         }
@@ -897,9 +1005,8 @@ hipError_t launch_bp_main(const BpArgs& ba, hipStream_t s, BpOwnArgs& a)
         const int gmax = std::max(1, std::min(std::max(a.split.nrow, a.split.ncol), 8 << (2 * ba.lvl)));
         a.G = std::max(1, std::min(gmax, (1024 + 2 * nb - 1) / (2 * nb)));
         a.nq = 2 * a.G;
-        a.batch = std::max(1, std::min(4, 4096 / ba.nd));
         const int lds = (int)(sizeof(float) *
-                              ((size_t)kBpRowsPerWg * (nl + 2 * kBpPad) + kBpWaves * 128 + (size_t)a.batch * ba.nd));
+                              ((size_t)kBpRowsPerWg * (nl + 2 * kBpPad) + 3) + sizeof(BpAngle) * kBpAngTab);
         e = allow_lds((const void*)k_bp_own, lds);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_bp_own, dim3(nb, 2 * a.G), dim3(64 * kBpWaves), lds, s, a);

@@ -66,7 +66,8 @@ __global__ void k_consts(int n, int na, int nd, double ds, double s0, int lmax, 
     r.c = (float)C0;
     r.w = (float)W;
     r.ib = (float)(1.0 / B);
-    r.r0 = r.r1 = r.r2 = 0.0f;
+    r.r0 = A != 0.0 ? (float)(1.0 / A) : 0.0f;  // 1/a, for step ranges without a division
+    r.r1 = r.r2 = 0.0f;
     out[idx] = r;
 }
 
@@ -164,7 +165,9 @@ __device__ __forceinline__ void ray_steps(const RayConst& kc, float fb, int nl, 
     lo = s0;
     hi = s1;
     if (kc.a != 0.0f) {
-        const float t1 = (-1.01f - tf) / kc.a, t2 = (fnl + 0.01f - tf) / kc.a;
+        // the reciprocal's relative error (~1e-7 of at most a few thousand
+        // steps) is far inside the 0.01-pixel margin
+        const float t1 = (-1.01f - tf) * kc.r0, t2 = (fnl + 0.01f - tf) * kc.r0;
         lo = (int)fminf(fmaxf(ceilf(fminf(t1, t2)), (float)s0), (float)(s1 + 1));
         hi = (int)fmaxf(fminf(floorf(fmaxf(t1, t2)), (float)s1), (float)(s0 - 1));
     } else if (tf < -1.01f || tf > fnl + 0.01f) {
@@ -210,6 +213,51 @@ __device__ __forceinline__ float joseph_sum(const float* row, int P, long long u
     return acc;
 }
 
+// Sum along one ray over a band held in LDS.  U's high word is the LDS cell
+// of the left tap (the row offset folded in), dU advances one row.  The
+// interpolation (1-w) a + w b is accumulated as sum(a) + 2^-32 sum(f (b - a))
+// with f = 2^32 w the coordinate's low word: four VALU operations per sample
+// besides the coordinate step and the address.  A single term reproduces the
+// transpose's matrix entries exactly (1-w rounded once, w exact).
+__device__ __forceinline__ float band_sum(const float* band, long long U, long long dU, int n)
+{
+    float s1 = 0.0f, s2 = 0.0f;
+    int i = 0;
+    // four coordinates a row apart, each advanced by four rows per trip
+    long long u1 = U + dU, u2 = U + 2 * dU, u3 = U + 3 * dU;
+    const long long d4 = 4 * dU;
+    for (; i + 4 <= n; i += 4) {  // all eight taps are loaded before use
+        const float* p0 = band + (int)(U >> 32);
+        const float* p1 = band + (int)(u1 >> 32);
+        const float* p2 = band + (int)(u2 >> 32);
+        const float* p3 = band + (int)(u3 >> 32);
+        const float a0 = p0[0], b0 = p0[1], a1 = p1[0], b1 = p1[1];
+        const float a2 = p2[0], b2 = p2[1], a3 = p3[0], b3 = p3[1];
+        s1 += a0;
+        s2 = fmaf((float)(unsigned)(U & 0xffffffffLL), b0 - a0, s2);
+        s1 += a1;
+        s2 = fmaf((float)(unsigned)(u1 & 0xffffffffLL), b1 - a1, s2);
+        s1 += a2;
+        s2 = fmaf((float)(unsigned)(u2 & 0xffffffffLL), b2 - a2, s2);
+        s1 += a3;
+        s2 = fmaf((float)(unsigned)(u3 & 0xffffffffLL), b3 - a3, s2);
+        U += d4;
+        u1 += d4;
+        u2 += d4;
+        u3 += d4;
+        // opaque to induction-variable rewriting: keeps one 64-bit add per coordinate
+        asm("" : "+v"(U), "+v"(u1), "+v"(u2), "+v"(u3));
+    }
+    for (; i < n; ++i) {
+        const float* p = band + (int)(U >> 32);
+        const float a0 = p[0], b0 = p[1];
+        s1 += a0;
+        s2 = fmaf((float)(unsigned)(U & 0xffffffffLL), b0 - a0, s2);
+        U += dU;
+    }
+    return fmaf(s2, kTwoM32, s1);
+}
+
 // LDS-band forward: the workgroup copies rows [i0, i0+R) of the padded level
 // image (columns of it for column-stepping angles) into LDS and sums, for
 // every ray of its angle group, the samples falling in the band.  The ray's
@@ -241,19 +289,27 @@ __global__ void __launch_bounds__(1024) k_fwd_band(FwdBandArgs a)
     }
     __syncthreads();
     const size_t m = (size_t)a.na * a.nd;
-    for (int it = threadIdx.x; it < nang * a.nd; it += blockDim.x) {
-        const int kk = it / a.nd;
-        const int b = it - kk * a.nd;
+    const long long rowfx = (long long)P << 32;
+    // (angle kk, bin b) of this thread's ray, advanced without a division
+    int kk = threadIdx.x / a.nd;
+    int b = threadIdx.x - kk * a.nd;
+    while (kk < nang) {
         const int ang = angle_of(a.split, pass, k0 + kk);
         const RayConst& kc = a.consts[(size_t)a.lvl * a.na + ang];
         int lo, hi;
         ray_steps(kc, (float)b, nl, i0, i1 - 1, lo, hi);
         float acc = 0.0f;
         if (lo <= hi) {
-            const long long u = kc.cfx + (long long)b * kc.bfx + (long long)lo * kc.afx;
-            acc = joseph_sum(band + (size_t)(lo - i0) * P + kPadL, P, u, kc.afx, hi - lo + 1);
+            const long long U = kc.cfx + (long long)b * kc.bfx + (long long)lo * kc.afx +
+                                (long long)((lo - i0) * P + kPadL) * 4294967296LL;
+            acc = band_sum(band, U, kc.afx + rowfx, hi - lo + 1);
         }
         a.part[(size_t)bi * m + (size_t)ang * a.nd + b] = kc.w * acc;
+        b += blockDim.x;
+        while (b >= a.nd) {
+            b -= a.nd;
+            ++kk;
+        }
     }
 }
 

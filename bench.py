@@ -181,7 +181,7 @@ def run(args):
     share = {key: t * lv.p[LEVELS.index(key[1])] for key, t in kern.items()}
     dom = max(share, key=share.get)
     dom_t = kern[dom]
-    name = {"fwd": "k_fwd_band", "bp": "k_bp_own" if dom[1] <= 1 else "k_bp_gather"}[dom[0]]
+    name = {"fwd": "k_fwd_band" if (N >> dom[1]) <= 512 else "k_fwd_direct", "bp": "k_bp_own"}[dom[0]]
     key = f"{name}_l{dom[1]}"
     achieved = samples[dom[1]] * FLOP_PER_SAMPLE / dom_t / 1e12
     out = {

@@ -150,8 +150,9 @@ int imask_project(const imask_geometry* g, int32_t log2f, const void* work,
                   const float* x_full, float* sino, void* stream);
 
 /* x_full = T_l^T R_l^T sino = 4^{-l} T_l^* R_l^T sino, the exact transpose
- * of imask_project (gather form: each pixel recomputes the forward weights,
- * no atomics, deterministic). */
+ * of imask_project (ray-driven: the weights come from the forward's own
+ * fixed-point coordinate; each image row is accumulated by one wavefront, so
+ * there are no atomics and the result is deterministic). */
 int imask_backproject(const imask_geometry* g, int32_t log2f, const void* work,
                       const float* sino, float* x_full, void* stream);
 

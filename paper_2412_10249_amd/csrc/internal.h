@@ -113,7 +113,7 @@ struct BpOwnArgs {
     const float* y;
     float* part;  // nq partial images N_l x N_l, image orientation
     int G;
-    int nq;     // partial images to sum (2 G for the scatter, G for the gather)
+    int nq;     // partial images to sum (2 G: both passes)
     AngleSplit split;
     float* out;
     float coef;

@@ -1,9 +1,10 @@
 // kernels.hip - gfx950 kernels of the ImaSk hot path.
 //
 // Projector pair (Sec. 4.1, eq. (CT_sketches)): ray-driven Joseph forward
-// projection R_l (k_fwd) and a gather-form transpose R_l^T (k_bp) that
-// recomputes the forward's interpolation weights from the same FP32
-// expression, so the pair is an exact transpose without atomics.  Resampling
+// projection R_l (k_fwd_band, k_fwd_direct) and a ray-driven transpose R_l^T
+// (k_bp_own: every wavefront owns image rows in LDS, no atomics) that
+// recomputes the forward's interpolation weights from the same 64-bit
+// fixed-point coordinate, so the pair is an exact transpose.  Resampling
 // (block mean T_l, compensation S_r) is done by the tile-pyramid kernel
 // k_prep that feeds the projector; the SAGA table refresh and the primal /
 // dual proximal steps of Alg. 1 are fused into k_fwd's store (dual) and
@@ -390,21 +391,15 @@ __global__ void __launch_bounds__(256) k_fwd_reduce(FwdArgs a)
 // lanes whose bin lies past the range (zero contributions) get there.
 // Unclamped lanes stay on the bin lattice, so they never share a cell within
 // one instruction.
-#ifndef IMK_BP_ROWS_PER_WAVE
-#define IMK_BP_ROWS_PER_WAVE 2
-#endif
-#ifndef IMK_BP_CHUNKS
-#define IMK_BP_CHUNKS 2
-#endif
-#ifndef IMK_BP_WAVES
-#define IMK_BP_WAVES 8
-#endif
-constexpr int kBpRowsPerWave = IMK_BP_ROWS_PER_WAVE;
-constexpr int kBpChunks = IMK_BP_CHUNKS;  // 64-ray chunks per trip of a wavefront
-constexpr int kBpWaves = IMK_BP_WAVES;
-constexpr int kBpRowsPerWg = kBpRowsPerWave * kBpWaves;
-constexpr int kBpPad = kBpRowsPerWg + 4;
-static_assert(kBpPad >= kBpRowsPerWg + 3, "sink cells must lie beyond every in-range tap");
+// The tile shape (rows per wavefront R, wavefronts per workgroup W) is a
+// template parameter; the launcher picks it per level.
+constexpr int kBpChunks = 2;  // 64-ray chunks per trip of a wavefront
+template <int R, int W>
+struct BpShape {
+    static constexpr int rows = R * W;   // rows of a workgroup
+    static constexpr int pad = rows + 4;  // spare cells on each side of an LDS row
+    static_assert(pad >= rows + 3, "sink cells must lie beyond every in-range tap");
+};
 
 // Bins whose coordinate at steps r0 .. r0+nr-1 can reach [-1, nl].
 __device__ __forceinline__ void bin_range(const RayConst& kc, int r0, int nrows, int nl, int nd, int& blo, int& cnt)
@@ -419,23 +414,21 @@ __device__ __forceinline__ void bin_range(const RayConst& kc, int r0, int nrows,
     cnt = bhi - blo + 1;
 }
 
-// LDS offset of the row of chain c (chains run over chunks, then rows).
-__device__ __forceinline__ int rr_offset(int c, int S) { return (c % kBpRowsPerWave) * S; }
 
 // Compiler-only ordering point: LDS operations of one wavefront execute in
 // program order, so this is all that is needed between the two phases.
 #define IMK_LDS_ORDER() asm volatile("" ::: "memory")
 
-// One trip of a wavefront over CH chunks of 64 rays and its kBpRowsPerWave
-// rows (chains chunk-major): both taps of every sample, as two
+// One trip of a wavefront over CH chunks of 64 rays and its R rows (chains
+// chunk-major): both taps of every sample, as two
 // read-modify-write phases.  U[c] is chain c's shifted coordinate, wy[h] the
 // weighted sinogram value of chunk h's ray (zero past the bin range).  With
 // CLAMP the cell index is clamped (lanes past the range); without it every
 // lane of the trip is in range and its taps lie inside the padded row.
-template <int CH, bool CLAMP>
+template <int R, int CH, bool CLAMP>
 __device__ __forceinline__ void scatter_trip(float* rows, int S, const long long* U, const float* wy)
 {
-    constexpr int NC = CH * kBpRowsPerWave;
+    constexpr int NC = CH * R;
     int cl[NC];
     float omw[NC], cw[NC], wys[CH];
 #pragma unroll
@@ -446,7 +439,7 @@ __device__ __forceinline__ void scatter_trip(float* rows, int S, const long long
         // unsigned clamp: taps past either end land in the last two cells
         const unsigned jj = CLAMP ? min(hi, (unsigned)(S - 2)) : hi;
         const float cu = (float)(unsigned)(U[c] & 0xffffffffLL);
-        cl[c] = rr_offset(c, S) + (int)jj;
+        cl[c] = (c % R) * S + (int)jj;  // chains run over chunks, then rows
         cw[c] = cu;
         omw[c] = fmaf(cu, -kTwoM32, 1.0f);  // 1 - w, exactly as in the forward
     }
@@ -454,12 +447,12 @@ __device__ __forceinline__ void scatter_trip(float* rows, int S, const long long
 #pragma unroll
     for (int c = 0; c < NC; ++c) old[c] = rows[cl[c]];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) rows[cl[c]] = fmaf(omw[c], wy[c / kBpRowsPerWave], old[c]);
+    for (int c = 0; c < NC; ++c) rows[cl[c]] = fmaf(omw[c], wy[c / R], old[c]);
     IMK_LDS_ORDER();
 #pragma unroll
     for (int c = 0; c < NC; ++c) old[c] = rows[cl[c] + 1];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) rows[cl[c] + 1] = fmaf(cw[c], wys[c / kBpRowsPerWave], old[c]);
+    for (int c = 0; c < NC; ++c) rows[cl[c] + 1] = fmaf(cw[c], wys[c / R], old[c]);
     IMK_LDS_ORDER();
 }
 
@@ -494,8 +487,12 @@ struct BpAngle {
 static_assert(sizeof(BpAngle) == 48, "BpAngle layout");
 constexpr int kBpAngTab = 128;  // angles a workgroup tabulates at once
 
-__global__ void __launch_bounds__(64 * kBpWaves) k_bp_own(BpOwnArgs a)
+template <int R, int W>
+__global__ void __launch_bounds__(64 * W) k_bp_own(BpOwnArgs a)
 {
+    constexpr int kBpRowsPerWave = R;
+    constexpr int kBpRowsPerWg = BpShape<R, W>::rows;
+    constexpr int kBpPad = BpShape<R, W>::pad;
     extern __shared__ float smem[];
     const int nl = a.n >> a.lvl;
     const int S = nl + 2 * kBpPad;
@@ -579,7 +576,7 @@ __global__ void __launch_bounds__(64 * kBpWaves) k_bp_own(BpOwnArgs a)
                         wy[h] = kw * ynext[h];
                         ynext[h] = buffer_float(yr, vb + (c0 + tstride + h * 64 * P) * 4);
                     }
-                    scatter_trip<kBpChunks, false>(rows, S, U, wy);
+                    scatter_trip<R, kBpChunks, false>(rows, S, U, wy);
 #pragma unroll
                     for (int c = 0; c < NC; ++c) U[c] += trip;
                 }
@@ -587,7 +584,7 @@ __global__ void __launch_bounds__(64 * kBpWaves) k_bp_own(BpOwnArgs a)
                 for (; c0 < cnt; c0 += 64 * P) {
                     float wy = kw * ynext[0];
                     ynext[0] = buffer_float(yr, vb + (c0 + 64 * P) * 4);
-                    scatter_trip<1, true>(rows, S, U, &wy);
+                    scatter_trip<R, 1, true>(rows, S, U, &wy);
 #pragma unroll
                     for (int rr = 0; rr < kBpRowsPerWave; ++rr) U[rr] += cstep;
                 }
@@ -607,52 +604,6 @@ __global__ void __launch_bounds__(64 * kBpWaves) k_bp_own(BpOwnArgs a)
             if (jj < nwg) out[(size_t)i * nl + rwg + jj] = acc[jj * S + kBpPad + i];
         }
     }
-}
-
-// Gather form of the same transpose, used on coarse levels where a pixel
-// sees many bins per angle: one thread per level-l pixel and angle group;
-// each candidate bin recomputes the forward's fixed-point coordinate and
-// keeps (1-w) if its left tap is this pixel, w if it is the left neighbour.
-__global__ void __launch_bounds__(256) k_bp_gather(BpOwnArgs a)
-{
-    const int nl = a.n >> a.lvl;
-    const int J = blockIdx.x * 16 + (threadIdx.x & 15);
-    const int I = blockIdx.y * 16 + (threadIdx.x >> 4);
-    if (I >= nl || J >= nl) return;
-    const int g = blockIdx.z;
-    const int apg = (a.na + a.G - 1) / a.G;
-    const int a0 = g * apg;
-    const int a1 = min(a.na, a0 + apg);
-    const float bmax = (float)(a.nd - 1);
-    float total = 0.0f;
-    const RayConst* kbase = a.consts + (size_t)a.lvl * a.na;
-    for (int ang = a0; ang < a1; ++ang) {
-        const RayConst& kc = kbase[ang];
-        const bool rows = row_stepping(ang, a.na);
-        const int s = rows ? I : J;  // step index of the samples touching this pixel
-        const int q = rows ? J : I;  // interpolation index of this pixel
-        // bins whose coordinate lies in (q-1, q+1): |b - bpos| < |1/B|; the
-        // 1% + 0.01-bin margin covers the float estimate of bpos, the exact
-        // fixed-point test below decides
-        const float bpos = ((float)q - fmaf((float)s, kc.a, kc.c)) * kc.ib;
-        const float R = 1.01f * fabsf(kc.ib) + 0.01f;
-        const int blo = (int)fminf(fmaxf(ceilf(bpos - R), 0.0f), bmax + 1.0f);
-        const int bhi = (int)fmaxf(fminf(floorf(bpos + R), bmax), -1.0f);
-        float acc = 0.0f;
-        if (blo <= bhi) {
-            long long u = kc.cfx + (long long)s * kc.afx + (long long)blo * kc.bfx;
-            const float* yr = a.y + (size_t)ang * a.nd;
-            for (int b = blo; b <= bhi; ++b) {
-                const int j0 = tap_index(u);
-                const float w = tap_weight(u);
-                const float wt = (j0 == q) ? (1.0f - w) : ((j0 == q - 1) ? w : 0.0f);
-                acc = fmaf(wt, yr[b], acc);
-                u += kc.bfx;
-            }
-        }
-        total = fmaf(kc.w, acc, total);
-    }
-    a.part[(size_t)g * nl * nl + (size_t)I * nl + J] = total;
 }
 
 // c = sum over the nq partial images in a fixed order; coef * c is stored coarse
@@ -969,7 +920,10 @@ hipError_t launch_prep(const PrepArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
-constexpr int kFwdLdsBytes = 136 * 1024;
+// LDS budget of a forward band: the full 136 KB (one workgroup per CU) for
+// 512-pixel rows, where fewer bands keep the partial sinograms few; 64 KB
+// (two workgroups per CU) for coarser levels.
+static int fwd_lds_bytes(int nl) { return (nl >= 512 ? 136 : 64) * 1024; }
 
 void fwd_bands(int nl, int* bands, int* rows)
 {
@@ -978,7 +932,7 @@ void fwd_bands(int nl, int* bands, int* rows)
         *rows = 0;
         return;
     }
-    const int maxr = kFwdLdsBytes / (int)(sizeof(float) * (nl + kPad));
+    const int maxr = fwd_lds_bytes(nl) / (int)(sizeof(float) * (nl + kPad));
     const int nb = (nl + maxr - 1) / maxr;
     *bands = nb;
     *rows = (nl + nb - 1) / nb;
@@ -1038,6 +992,23 @@ hipError_t launch_fwd(const FwdArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
+// Ownership scatter with about 1024 workgroups: G angle groups per pass,
+// 2 G N_l^2 <= 16 N^2 partial images.
+template <int R, int W>
+static hipError_t launch_scatter(BpOwnArgs& a, int nl, int lvl, hipStream_t s)
+{
+    using Sh = BpShape<R, W>;
+    const int nb = (nl + Sh::rows - 1) / Sh::rows;
+    const int gmax = std::max(1, std::min(std::max(a.split.nrow, a.split.ncol), 8 << (2 * lvl)));
+    a.G = std::max(1, std::min(gmax, (1024 + 2 * nb - 1) / (2 * nb)));
+    a.nq = 2 * a.G;
+    const int lds = (int)(sizeof(float) * ((size_t)Sh::rows * (nl + 2 * Sh::pad) + 3) + sizeof(BpAngle) * kBpAngTab);
+    const hipError_t e = allow_lds((const void*)k_bp_own<R, W>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_bp_own<R, W>), dim3(nb, 2 * a.G), dim3(64 * W), lds, s, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_bp_main(const BpArgs& ba, hipStream_t s, BpOwnArgs& a)
 {
     a = BpOwnArgs{};
@@ -1054,27 +1025,10 @@ hipError_t launch_bp_main(const BpArgs& ba, hipStream_t s, BpOwnArgs& a)
     a.accumulate = ba.accumulate;
     a.prolong = ba.prolong;
     const int nl = ba.n >> ba.lvl;
-    hipError_t e;
-    if (ba.lvl <= 1) {
-        // ownership scatter: about 1024 workgroups, 2 G N_l^2 <= 16 N^2 partials
-        const int nb = (nl + kBpRowsPerWg - 1) / kBpRowsPerWg;
-        const int gmax = std::max(1, std::min(std::max(a.split.nrow, a.split.ncol), 8 << (2 * ba.lvl)));
-        a.G = std::max(1, std::min(gmax, (1024 + 2 * nb - 1) / (2 * nb)));
-        a.nq = 2 * a.G;
-        const int lds = (int)(sizeof(float) *
-                              ((size_t)kBpRowsPerWg * (nl + 2 * kBpPad) + 3) + sizeof(BpAngle) * kBpAngTab);
-        e = allow_lds((const void*)k_bp_own, lds);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_bp_own, dim3(nb, 2 * a.G), dim3(64 * kBpWaves), lds, s, a);
-    } else {
-        // gather: about 1024 workgroups, G N_l^2 <= 16 N^2 partials
-        const int t = (nl + 15) / 16;
-        a.G = std::max(1, std::min(std::min(a.na, 16 << (2 * ba.lvl)), (1024 + t * t - 1) / (t * t)));
-        a.G = (a.na + ((a.na + a.G - 1) / a.G) - 1) / ((a.na + a.G - 1) / a.G);  // no empty group
-        a.nq = a.G;
-        hipLaunchKernelGGL(k_bp_gather, dim3(t, t, a.G), dim3(256), 0, s, a);
-    }
-    return hipGetLastError();
+    // tile shapes measured best on the 512^2 / 720 x 768 workload: two rows
+    // per wavefront and 8 wavefronts at the two finest levels, four rows and
+    // 4 wavefronts on the coarse ones
+    return ba.lvl <= 1 ? launch_scatter<2, 8>(a, nl, ba.lvl, s) : launch_scatter<4, 4>(a, nl, ba.lvl, s);
 }
 
 hipError_t launch_bp(const BpArgs& ba, hipStream_t s)

@@ -88,7 +88,7 @@ def test_explicit_matrix_tiny(lvl):
         e = np.zeros((na, nd), dtype=np.float32)
         e.flat[q] = 1.0
         At_gpu[:, q] = host(pk.backproject(g, lvl, dev(e), work)).ravel()
-    # the gather recomputes the forward's weights: an exact transpose
+    # the transpose recomputes the forward's weights: an exact transpose
     assert np.array_equal(A_gpu, At_gpu.T)
     A_orc = oracle.dense_matrix(lambda z: oracle.project(og, lvl, oracle.restrict(z, lvl)), (n, n), na * nd)
     np.testing.assert_allclose(A_gpu, A_orc, rtol=0, atol=1e-6 * np.abs(A_orc).max())

@@ -722,77 +722,87 @@ __global__ void __launch_bounds__(256) k_primal(PrimalArgs a)
 
 // J FISTA iterations of the prox of tau*(w TV_eps + lam/2 |.|^2) on one
 // 32 x 32 output tile; the workgroup holds the tile plus a J-pixel halo in
-// LDS and shrinks the valid region by one pixel per iteration, so the whole
-// inner solve reads v and u0 once and writes the result once.
+// LDS, so the whole inner solve reads v and u0 once and writes the result
+// once.  Every thread keeps a fixed set of cells (their input v, previous
+// iterate and neighbour masks in registers) and updates them at every
+// iteration: a cell at the tile's edge sees no neighbour beyond it, an error
+// that moves inward one pixel per iteration and so never reaches the output
+// tile, which lies J pixels inside.
 constexpr int kTvTile = 32;
+constexpr int kTvCells = ((kTvTile + 2 * IMASK_MAX_TV_INNER) * (kTvTile + 2 * IMASK_MAX_TV_INNER) + 1023) / 1024;
 
 __global__ void __launch_bounds__(1024) k_tv(TvArgs a)
 {
     extern __shared__ float sm[];
     const int H = a.J;
     const int R = kTvTile + 2 * H;
-    float* vs = sm;
-    float* up = vs + R * R;
-    float* ys = up + R * R;
-    float* q1 = ys + R * R;
-    float* q2 = q1 + R * R;
+    float* ys = sm;          // extrapolated point y of FISTA
+    float* q1 = ys + R * R;  // normalised gradient, row direction
+    float* q2 = q1 + R * R;  // normalised gradient, column direction
     const int tiles = (a.n + kTvTile - 1) / kTvTile;
     const int ty = blockIdx.x / tiles, tx = blockIdx.x - ty * tiles;
     const int gi0 = ty * kTvTile - H, gj0 = tx * kTvTile - H;
     const int n = a.n;
-    for (int q = threadIdx.x; q < R * R; q += blockDim.x) {
+    const float eps2 = a.eps * a.eps;
+    enum { kIn = 1, kDown = 2, kRight = 4, kUp = 8, kLeft = 16, kOut = 32 };
+    int cell[kTvCells], flag[kTvCells];
+    float vv[kTvCells], up[kTvCells];
+#pragma unroll
+    for (int k = 0; k < kTvCells; ++k) {
+        const int q = threadIdx.x + k * 1024;
+        flag[k] = 0;
+        cell[k] = q;
+        vv[k] = up[k] = 0.0f;
+        if (q >= R * R) continue;
         const int li = q / R, lj = q - li * R;
         const int gi = gi0 + li, gj = gj0 + lj;
-        float v = 0.f, u = 0.f;
-        if (gi >= 0 && gi < n && gj >= 0 && gj < n) {
-            v = a.v[(size_t)gi * n + gj];
-            u = a.u0[(size_t)gi * n + gj];
+        if (gi < 0 || gi >= n || gj < 0 || gj >= n) {
+            ys[q] = 0.0f;
+            continue;
         }
-        vs[q] = v;
-        up[q] = u;
-        ys[q] = u;
+        flag[k] = kIn | (gi < n - 1 && li < R - 1 ? kDown : 0) | (gj < n - 1 && lj < R - 1 ? kRight : 0) |
+                  (gi >= 1 && li >= 1 ? kUp : 0) | (gj >= 1 && lj >= 1 ? kLeft : 0) |
+                  (li >= H && li < H + kTvTile && lj >= H && lj < H + kTvTile ? kOut : 0);
+        vv[k] = a.v[(size_t)gi * n + gj];
+        up[k] = a.u0[(size_t)gi * n + gj];
+        ys[q] = up[k];
     }
     __syncthreads();
     for (int t = 0; t < a.J; ++t) {
-        // q = grad y / sqrt(|grad y|^2 + eps^2) on [t, R-2-t]^2
-        const int lo = t, hiq = R - 2 - t;
-        const int wq = hiq - lo + 1;
-        for (int q = threadIdx.x; q < wq * wq; q += blockDim.x) {
-            const int li = lo + q / wq, lj = lo + q % wq;
-            const int gi = gi0 + li, gj = gj0 + lj;
-            if (gi < 0 || gi >= n || gj < 0 || gj >= n) continue;
-            const int c = li * R + lj;
+        // q = grad y / sqrt(|grad y|^2 + eps^2), zero difference past the image
+#pragma unroll
+        for (int k = 0; k < kTvCells; ++k) {
+            if (!(flag[k] & kIn)) continue;
+            const int c = cell[k];
             const float yc = ys[c];
-            const float d1 = (gi < n - 1) ? ys[c + R] - yc : 0.0f;
-            const float d2 = (gj < n - 1) ? ys[c + 1] - yc : 0.0f;
-            const float inv = 1.0f / sqrtf(d1 * d1 + d2 * d2 + a.eps * a.eps);
+            const float d1 = (flag[k] & kDown) ? ys[c + R] - yc : 0.0f;
+            const float d2 = (flag[k] & kRight) ? ys[c + 1] - yc : 0.0f;
+            const float inv = rsqrtf(fmaf(d1, d1, fmaf(d2, d2, eps2)));
             q1[c] = d1 * inv;
             q2[c] = d2 * inv;
         }
         __syncthreads();
-        const int lo2 = t + 1, hi2 = R - 2 - t;
-        const int w2 = hi2 - lo2 + 1;
         const float beta = a.beta[t];
-        for (int q = threadIdx.x; q < w2 * w2; q += blockDim.x) {
-            const int li = lo2 + q / w2, lj = lo2 + q % w2;
-            const int gi = gi0 + li, gj = gj0 + lj;
-            if (gi < 0 || gi >= n || gj < 0 || gj >= n) continue;
-            const int c = li * R + lj;
+#pragma unroll
+        for (int k = 0; k < kTvCells; ++k) {
+            if (!(flag[k] & kIn)) continue;
+            const int c = cell[k];
             float div = -q1[c] - q2[c];  // grad^T q
-            if (gi >= 1) div += q1[c - R];
-            if (gj >= 1) div += q2[c - 1];
+            if (flag[k] & kUp) div += q1[c - R];
+            if (flag[k] & kLeft) div += q2[c - 1];
             const float yc = ys[c];
-            const float gh = (yc - vs[c]) + a.tau_w * div + a.tau_lam * yc;
+            const float gh = (yc - vv[k]) + a.tau_w * div + a.tau_lam * yc;
             const float un = yc - a.invL * gh;
-            ys[c] = un + beta * (un - up[c]);
-            up[c] = un;
+            ys[c] = un + beta * (un - up[k]);
+            up[k] = un;
         }
         __syncthreads();
     }
-    for (int q = threadIdx.x; q < kTvTile * kTvTile; q += blockDim.x) {
-        const int li = H + q / kTvTile, lj = H + q % kTvTile;
-        const int gi = gi0 + li, gj = gj0 + lj;
-        if (gi < n && gj < n) a.out[(size_t)gi * n + gj] = up[li * R + lj];
+#pragma unroll
+    for (int k = 0; k < kTvCells; ++k) {
+        if (!(flag[k] & kOut)) continue;
+        const int li = cell[k] / R, lj = cell[k] - (cell[k] / R) * R;
+        a.out[(size_t)(gi0 + li) * n + gj0 + lj] = up[k];
     }
 }
 
@@ -1059,7 +1069,7 @@ hipError_t launch_primal(const PrimalArgs& a, hipStream_t s)
 hipError_t launch_tv(const TvArgs& a, hipStream_t s)
 {
     const int R = kTvTile + 2 * a.J;
-    const size_t sh = (size_t)5 * R * R * sizeof(float);
+    const size_t sh = (size_t)3 * R * R * sizeof(float);
     const int tiles = (a.n + kTvTile - 1) / kTvTile;
     hipLaunchKernelGGL(k_tv, dim3(tiles * tiles), dim3(1024), sh, s, a);
     return hipGetLastError();

@@ -504,10 +504,11 @@ def autograd_bench(args):
 
 # ------------------------------------------------------------ profile summaries
 
-def _short(name: str) -> str:
+def _short(name: str, templates: bool = True) -> str:
     i = name.find("::k_")
     if i >= 0:
-        return name[i + 2:name.find("(", i)]
+        out = name[i + 2:name.find("(", i)]
+        return out if templates else out.split("<")[0]
     return name.split("(")[0][:48]
 
 
@@ -542,7 +543,7 @@ def summarize(dirs, command_note, counter_key=None):
     for d in dirs:
         for p in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
             for r in csv.DictReader(open(p)):
-                k = (_short(r["Kernel_Name"]), r.get("Grid_Size", r.get("Grid_Size_X", "?")), r["Counter_Name"])
+                k = (_short(r["Kernel_Name"], False), r.get("Grid_Size", r.get("Grid_Size_X", "?")), r["Counter_Name"])
                 counters.setdefault(k, []).append(float(r["Counter_Value"]))
     traffic = None
     if counters and counter_key:

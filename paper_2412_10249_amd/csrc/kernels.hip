@@ -607,24 +607,30 @@ __global__ void __launch_bounds__(64 * W) k_bp_own(BpOwnArgs a)
 }
 
 // c = sum over the nq partial images in a fixed order; coef * c is stored coarse
-// (or into `tmp` for a later prolongation).
-__global__ void __launch_bounds__(256) k_bp_sum(BpOwnArgs a, float* tmp)
+// (or into `tmp` for a later prolongation).  A workgroup takes 64 pixels;
+// its 16 wavefronts sum consecutive slices of the partials, and the slice
+// sums are added in slice order, so coarse levels with many small partial
+// images still spread over the whole chip.
+constexpr int kSumSlices = 16;
+__global__ void __launch_bounds__(64 * kSumSlices) k_bp_sum(BpOwnArgs a, float* tmp)
 {
+    __shared__ float red[kSumSlices][64];
     const int nl = a.n >> a.lvl;
     const size_t d = (size_t)nl * nl;
-    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= d) return;
-    // four interleaved partial sums, combined in a fixed order
-    float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
-    int q = 0;
-    for (; q + 4 <= a.nq; q += 4) {
-        s0 += a.part[q * d + e];
-        s1 += a.part[(q + 1) * d + e];
-        s2 += a.part[(q + 2) * d + e];
-        s3 += a.part[(q + 3) * d + e];
-    }
-    for (; q < a.nq; ++q) s0 += a.part[q * d + e];
-    const float v = a.coef * ((s0 + s1) + (s2 + s3));
+    const int lane = threadIdx.x & 63;
+    const int sl = threadIdx.x >> 6;
+    const size_t e = (size_t)blockIdx.x * 64 + lane;
+    const int q0 = sl * a.nq / kSumSlices, q1 = (sl + 1) * a.nq / kSumSlices;
+    float sum = 0.0f;
+    if (e < d)
+        for (int q = q0; q < q1; ++q) sum += a.part[q * d + e];
+    red[sl][lane] = sum;
+    __syncthreads();
+    if (sl != 0 || e >= d) return;
+    float c = red[0][lane];
+#pragma unroll
+    for (int k = 1; k < kSumSlices; ++k) c += red[k][lane];
+    const float v = a.coef * c;
     if (a.prolong) {
         tmp[e] = v;
     } else {
@@ -1048,7 +1054,7 @@ hipError_t launch_bp(const BpArgs& ba, hipStream_t s)
     if (e != hipSuccess) return e;
     const int nl = ba.n >> ba.lvl;
     const size_t d = (size_t)nl * nl;
-    hipLaunchKernelGGL(k_bp_sum, dim3((unsigned)((d + 255) / 256)), dim3(256), 0, s, a, ba.tmp);
+    hipLaunchKernelGGL(k_bp_sum, dim3((unsigned)((d + 63) / 64)), dim3(64 * kSumSlices), 0, s, a, ba.tmp);
     e = hipGetLastError();
     if (e != hipSuccess || !ba.prolong) return e;
     const size_t fine = (size_t)ba.n * ba.n;

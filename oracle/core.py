@@ -72,6 +72,13 @@ def lib():
                                           ctypes.c_uint64, _D, ctypes.c_int,
                                           _D, _D, _D, _D, _I32, _D]
         L.orc_imask_run.restype = ctypes.c_int
+        L.orc_imask_seq_run.argtypes = geo + [ctypes.c_int, _I32, _D, ctypes.c_int,
+                                              ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                              ctypes.c_double, ctypes.c_int,
+                                              ctypes.c_double, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint32,
+                                              ctypes.c_uint64, _D, ctypes.c_int,
+                                              _D, _D, _D, _D, _D, _I32, _D]
+        L.orc_imask_seq_run.restype = ctypes.c_int
     return _lib
 
 
@@ -239,15 +246,18 @@ class State:
     k: int = 0
     epochs: float = 0.0
     draws: list = field(default_factory=list)
+    xbar: np.ndarray | None = None  # extrapolated point (ImaSk-Seq only)
 
     @staticmethod
     def zeros(g: Geometry, lv: Levels) -> "State":
         return State(np.zeros((g.n, g.n)), np.zeros((g.n_angles, g.n_det)),
-                     np.zeros((lv.r, g.n, g.n)), np.zeros((lv.r, g.n_angles, g.n_det)))
+                     np.zeros((lv.r, g.n, g.n)), np.zeros((lv.r, g.n_angles, g.n_det)),
+                     xbar=np.zeros((g.n, g.n)))
 
     def copy(self) -> "State":
         return State(self.x.copy(), self.y.copy(), self.phi.copy(), self.psi.copy(),
-                     self.k, self.epochs, list(self.draws))
+                     self.k, self.epochs, list(self.draws),
+                     None if self.xbar is None else self.xbar.copy())
 
 
 def imask_run(g: Geometry, lv: Levels, reg: Reg, sigma: float, seed: int, stream: int,
@@ -263,6 +273,29 @@ def imask_run(g: Geometry, lv: Levels, reg: Reg, sigma: float, seed: int, stream
                              sigma, seed, stream, st.k, _dp(b), n_iter,
                              _dp(st.x), _dp(st.y), _dp(st.phi), _dp(st.psi),
                              dr.ctypes.data_as(_I32), _dp(ep))
+    if rc != 0:
+        raise ValueError("oracle rejected the level set")
+    st.k += n_iter
+    st.epochs = float(ep[0])
+    st.draws.extend(int(v) for v in dr[:n_iter])
+    return st
+
+
+def imask_seq_run(g: Geometry, lv: Levels, reg: Reg, sigma: float, theta: float, seed: int, stream: int,
+                  b, n_iter: int, state: State | None = None) -> State:
+    """ImaSk-Seq (Sec. 5) for n_iter iterations from `state` (zeros if None)."""
+    st = State.zeros(g, lv) if state is None else state.copy()
+    if st.xbar is None:
+        st.xbar = st.x.copy()
+    b = _f64(b)
+    lf, pp = lv.carrays()
+    dr = np.empty(max(n_iter, 1), dtype=np.int32)
+    ep = np.array([st.epochs])
+    rc = lib().orc_imask_seq_run(*g.args(), lv.r, lf.ctypes.data_as(_I32), _dp(pp), lv.mode,
+                                 reg.kind, reg.lam, reg.tv_weight, reg.tv_eps, reg.tv_inner,
+                                 sigma, theta, seed, stream, st.k, _dp(b), n_iter,
+                                 _dp(st.x), _dp(st.xbar), _dp(st.y), _dp(st.phi), _dp(st.psi),
+                                 dr.ctypes.data_as(_I32), _dp(ep))
     if rc != 0:
         raise ValueError("oracle rejected the level set")
     st.k += n_iter

@@ -17,7 +17,9 @@
  *   - the counter-based SplitMix64 draw of the sketch index (Alg. 1, step
  *     "sample i_k with probability p");
  *   - Algorithm 1 (ImaSk) with the Tikhonov prox and a smoothed-TV prox
- *     evaluated by FISTA (Sec. 4.2 and 4.5).
+ *     evaluated by FISTA (Sec. 4.2 and 4.5);
+ *   - the ImaSk-Seq variant of Sec. 5 (dual step first, primal step with the
+ *     new dual iterate, extrapolated primal point).
  *
  * Conventions: domain [-1,1]^2; level l has N_l = N >> l pixels per side and
  * pixel size h_l = 2/N_l; pixel (i,j) has centre (x_j, y_i) with
@@ -465,6 +467,80 @@ int orc_imask_run(int n, int na, int nd, double ds, double s0,
     free(xi);
     free(zeta);
     free(xn);
+    free(idx);
+    return 0;
+}
+
+/* ImaSk-Seq (Sec. 5, algorithm "Variant ImaSk-Seq"): n_iter iterations from
+ * the state (x, xbar, y, phi, psi); mu = lam.  Each iteration, in the order
+ * the variant states it:
+ *   sample i; psi_new = K_i xbar;
+ *   zeta = psi_new - psi_i + sum_j p_j psi_j            (old tables)
+ *   y <- (y + sigma zeta - sigma b) / (1 + sigma);
+ *   phi_new = K_i^T y                                    (the new y)
+ *   xi = phi_new - phi_i + sum_j p_j phi_j               (old tables)
+ *   x_new = prox_{tau R}(x - tau xi), tau = sigma / mu;
+ *   xbar <- x_new + theta (x_new - x);  x <- x_new;  psi_i, phi_i refreshed.
+ * Draws and epoch accounting as in orc_imask_run. */
+int orc_imask_seq_run(int n, int na, int nd, double ds, double s0,
+                      int r, const int* log2f, const double* p, int mode,
+                      int reg_kind, double lam, double tv_w, double tv_eps, int tv_inner,
+                      double sigma, double theta, uint64_t seed, uint32_t stream, uint64_t k0,
+                      const double* bdata, int n_iter,
+                      double* x, double* xbar, double* y, double* phi, double* psi,
+                      int32_t* draws_out, double* epochs)
+{
+    if (r < 1 || r > ORC_MAX_LEVELS || log2f[0] != 0) return -1;
+    const long d = (long)n * n, m = (long)na * nd;
+    const double tau = sigma / lam;
+    double* gx = (double*)malloc(sizeof(double) * d);
+    double* gy = (double*)malloc(sizeof(double) * m);
+    double* xn = (double*)malloc(sizeof(double) * d);
+    double* v = (double*)malloc(sizeof(double) * d);
+    int32_t* idx = (int32_t*)malloc(sizeof(int32_t) * (n_iter > 0 ? n_iter : 1));
+    orc_draws(seed, stream, k0, n_iter, r, p, idx);
+    double unbiased_full = 1.0;
+    for (int k = 1; k < r; ++k) unbiased_full += ldexp(1.0, -log2f[k]);
+    for (int it = 0; it < n_iter; ++it) {
+        const int k = idx[it];
+        /* dual step from the extrapolated point */
+        orc_sketch_fwd(n, na, nd, ds, s0, r, log2f, p, mode, k, xbar, gy);
+        for (long e = 0; e < m; ++e) {
+            double avg = 0.0;
+            for (int j = 0; j < r; ++j) avg += p[j] * psi[(long)j * m + e];
+            const double zeta = gy[e] - psi[(long)k * m + e] + avg;
+            y[e] = (y[e] + sigma * zeta - sigma * bdata[e]) / (1.0 + sigma);
+        }
+        /* primal step with the new dual iterate */
+        orc_sketch_adj(n, na, nd, ds, s0, r, log2f, p, mode, k, y, gx);
+        for (long q = 0; q < d; ++q) {
+            double avg = 0.0;
+            for (int j = 0; j < r; ++j) avg += p[j] * phi[(long)j * d + q];
+            const double xi = gx[q] - phi[(long)k * d + q] + avg;
+            v[q] = x[q] - tau * xi;
+        }
+        if (reg_kind == ORC_REG_TIKHONOV) {
+            for (long q = 0; q < d; ++q) xn[q] = v[q] / (1.0 + tau * lam);
+        } else {
+            orc_tv_prox(n, v, x, tau, lam, tv_w, tv_eps, tv_inner, xn);
+        }
+        /* extrapolation, then the new iterate and the table refresh */
+        for (long q = 0; q < d; ++q) {
+            xbar[q] = xn[q] + theta * (xn[q] - x[q]);
+            x[q] = xn[q];
+        }
+        memcpy(phi + (long)k * d, gx, sizeof(double) * d);
+        memcpy(psi + (long)k * m, gy, sizeof(double) * m);
+        if (draws_out) draws_out[it] = k;
+        if (epochs) {
+            if (k == 0 && mode == ORC_MODE_UNBIASED) *epochs += unbiased_full;
+            else *epochs += ldexp(1.0, -log2f[k]);
+        }
+    }
+    free(gx);
+    free(gy);
+    free(xn);
+    free(v);
     free(idx);
     return 0;
 }

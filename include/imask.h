@@ -51,6 +51,7 @@ enum {
 
 enum { IMASK_FULL_PAPER = 0, IMASK_FULL_UNBIASED = 1 };
 enum { IMASK_REG_TIKHONOV = 0, IMASK_REG_SMOOTH_TV = 1 };
+enum { IMASK_SCHEDULE_PARALLEL = 0, IMASK_SCHEDULE_SEQUENTIAL = 1 };
 enum {
     IMASK_RESTRICT = 0,     /* out (N_l^2)  = T_l in, 2^l x 2^l block mean (Sec. 4.1) */
     IMASK_PROLONG = 1,      /* out (N^2)    = T_l^* in, replication (Sec. 4.1) */
@@ -101,11 +102,20 @@ typedef struct {
 /* Step size sigma (Alg. 1) and the sketch-index generator: SplitMix64 in
  * counter form; stream seed = the stream_id-th output of the generator at
  * state `seed`; draw k uses the k-th output of the stream (top 32 bits)
- * against floor(2^32 * cumulative p). */
+ * against floor(2^32 * cumulative p).
+ * schedule selects the iteration:
+ *   IMASK_SCHEDULE_PARALLEL   Alg. 1: primal and dual steps both from
+ *                             (x^k, y^k); theta is ignored
+ *   IMASK_SCHEDULE_SEQUENTIAL the ImaSk-Seq variant of Sec. 5: the dual step
+ *                             uses K_i xbar^k, the primal step K_i^T y^{k+1},
+ *                             and xbar^{k+1} = x^{k+1} + theta (x^{k+1} - x^k);
+ *                             0 <= theta <= 1, and imask_state.xbar is needed */
 typedef struct {
     double sigma;
     uint64_t seed;
     uint32_t stream_id;
+    int32_t schedule;
+    double theta;
 } imask_params;
 
 /* ImaSk state (Alg. 1): iterates, gradient tables and counters.
@@ -117,6 +127,9 @@ typedef struct {
  *          imask_phi_floats() floats in total
  *   psi    sinogram-space table K_k x: r * n_angles*n_det floats
  *   work   workspace prepared by imask_prepare() for this geometry
+ *   xbar   N*N extrapolated point (IMASK_SCHEDULE_SEQUENTIAL only, updated
+ *          in place; start it equal to x, e.g. both zero); may be NULL for
+ *          the parallel schedule
  *   k      iteration counter (index of the next draw)
  *   epochs equivalent full-resolution operator applications so far
  *   cur    0 or 1 */
@@ -129,6 +142,7 @@ typedef struct {
     uint64_t k;
     double epochs;
     int32_t cur;
+    float* xbar;
 } imask_state;
 
 /* Bytes of device workspace needed for geometry g (host function). */

@@ -20,6 +20,7 @@ FULL_PAPER, FULL_UNBIASED = 0, 1
 REG_TIKHONOV, REG_SMOOTH_TV = 0, 1
 RESTRICT, PROLONG, RESTRICT_ADJ, PROJECT, COMPENSATE = 0, 1, 2, 3, 4
 BUDGET_ITERS, BUDGET_EPOCHS = 0, 1
+SCHEDULE_PARALLEL, SCHEDULE_SEQUENTIAL = 0, 1
 
 EXPORTS = ["imask_workspace_bytes", "imask_phi_floats", "imask_prepare", "imask_project",
            "imask_backproject", "imask_resample", "imask_sketch_apply", "imask_draws",
@@ -44,13 +45,14 @@ class Reg(ctypes.Structure):
 
 
 class Params(ctypes.Structure):
-    _fields_ = [("sigma", ctypes.c_double), ("seed", ctypes.c_uint64), ("stream_id", ctypes.c_uint32)]
+    _fields_ = [("sigma", ctypes.c_double), ("seed", ctypes.c_uint64), ("stream_id", ctypes.c_uint32),
+                ("schedule", ctypes.c_int32), ("theta", ctypes.c_double)]
 
 
 class State(ctypes.Structure):
     _fields_ = [("x", ctypes.c_void_p * 2), ("y", ctypes.c_void_p * 2), ("phi", ctypes.c_void_p),
                 ("psi", ctypes.c_void_p), ("work", ctypes.c_void_p), ("k", ctypes.c_uint64),
-                ("epochs", ctypes.c_double), ("cur", ctypes.c_int32)]
+                ("epochs", ctypes.c_double), ("cur", ctypes.c_int32), ("xbar", ctypes.c_void_p)]
 
 
 class ImaskError(RuntimeError):

@@ -240,11 +240,16 @@ static int one_step(const imask_geometry& g, const Layout& L, const imask_levels
     float* W = (float*)st.work;
     const int cur = st.cur, nxt = 1 - cur;
     const int lmax_set = lv.log2f[lv.r - 1];
+    // Alg. 1 takes both steps from (x^k, y^k); ImaSk-Seq (Sec. 5) projects the
+    // extrapolated point and backprojects the new dual iterate
+    const bool seq = prm.schedule == IMASK_SCHEDULE_SEQUENTIAL;
+    const float* x_fwd = seq ? st.xbar : st.x[cur];
+    const float* y_bp = seq ? st.y[nxt] : st.y[cur];
 
     // a2-a4: restriction, forward projection, dual SAGA step and psi refresh
     PrepArgs pa;
     FwdArgs fa{};
-    forward_plan(L, lv, k, st.x[cur], W, pa, fa);
+    forward_plan(L, lv, k, x_fwd, W, pa, fa);
     fwd_common(L, W, fa);
     fa.mode = FWD_DUAL;
     fa.y_old = st.y[cur];
@@ -259,16 +264,16 @@ static int one_step(const imask_geometry& g, const Layout& L, const imask_levels
     IMK_TRY(launch_prep(pa, s));
     IMK_TRY(launch_fwd(fa, s));
 
-    // a5: raw backprojections R_l^T y^k needed by sketch k
+    // a5: raw backprojections R_l^T y needed by sketch k
     if (k > 0) {
         const int l = lv.log2f[k];
-        if (int rc = backproject_raw(L, W, l, st.y[cur], W + L.craw[l], 1.0f, 0, 0, s)) return rc;
+        if (int rc = backproject_raw(L, W, l, y_bp, W + L.craw[l], 1.0f, 0, 0, s)) return rc;
     } else {
-        if (int rc = backproject_raw(L, W, 0, st.y[cur], W + L.craw[0], 1.0f, 0, 0, s)) return rc;
+        if (int rc = backproject_raw(L, W, 0, y_bp, W + L.craw[0], 1.0f, 0, 0, s)) return rc;
         if (lv.full_mode == IMASK_FULL_UNBIASED)
             for (int j = 1; j < lv.r; ++j) {
                 const int l = lv.log2f[j];
-                if (int rc = backproject_raw(L, W, l, st.y[cur], W + L.craw[l], 1.0f, 0, 0, s)) return rc;
+                if (int rc = backproject_raw(L, W, l, y_bp, W + L.craw[l], 1.0f, 0, 0, s)) return rc;
             }
     }
 
@@ -293,6 +298,10 @@ static int one_step(const imask_geometry& g, const Layout& L, const imask_levels
     pr.x_out = tv ? W + L.vbuf : st.x[nxt];
     pr.tau = (float)tau;
     pr.prox_scale = tv ? 1.0f : (float)(1.0 / (1.0 + tau * reg.lambda));
+    // extrapolation xbar^{k+1} = x^{k+1} + theta (x^{k+1} - x^k), fused into
+    // whichever kernel writes x^{k+1}
+    pr.xbar = seq && !tv ? st.xbar : nullptr;
+    pr.theta = (float)prm.theta;
     IMK_TRY(launch_primal(pr, s));
 
     // a8: smoothed-TV prox by FISTA, warm-started at x^k
@@ -303,6 +312,8 @@ static int one_step(const imask_geometry& g, const Layout& L, const imask_levels
         ta.v = W + L.vbuf;
         ta.u0 = st.x[cur];
         ta.out = st.x[nxt];
+        ta.xbar = seq ? st.xbar : nullptr;
+        ta.theta = (float)prm.theta;
         ta.tau_w = (float)(tau * reg.tv_weight);
         ta.tau_lam = (float)(tau * reg.lambda);
         ta.eps = (float)reg.tv_eps;
@@ -747,6 +758,12 @@ static int check_problem(const imask_geometry* g, const imask_levels* lv, const 
     const int lmax = level_limit(g->n);
     if (!levels_ok(lv, lmax) || !reg_ok(reg) || !prm || !b || !state_ok(s)) return IMASK_EINVAL;
     if (!(prm->sigma > 0.0) || !std::isfinite(prm->sigma)) return IMASK_EINVAL;
+    if (prm->schedule == IMASK_SCHEDULE_SEQUENTIAL) {
+        if (!(prm->theta >= 0.0 && prm->theta <= 1.0) || !s->xbar) return IMASK_EINVAL;
+        if (s->xbar == s->x[0] || s->xbar == s->x[1]) return IMASK_EINVAL;
+    } else if (prm->schedule != IMASK_SCHEDULE_PARALLEL) {
+        return IMASK_EINVAL;
+    }
     return IMASK_OK;
 }
 

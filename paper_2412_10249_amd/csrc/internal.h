@@ -164,6 +164,8 @@ struct PrimalArgs {
     const float* x_old;
     float* x_out;
     float tau, prox_scale;
+    float* xbar;  // when set: xbar = x_out + theta (x_out - x_old)
+    float theta;
 };
 
 struct TvArgs {
@@ -171,6 +173,8 @@ struct TvArgs {
     const float* v;
     const float* u0;
     float* out;
+    float* xbar;  // when set: xbar = out + theta (out - u0)
+    float theta;
     float tau_w, tau_lam, eps, invL;
     float beta[IMASK_MAX_TV_INNER];
 };

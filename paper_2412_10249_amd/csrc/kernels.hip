@@ -707,8 +707,10 @@ __global__ void __launch_bounds__(256) k_primal(PrimalArgs a)
             if (c == a.kidx) own = ph;
         }
         const float xi = (g - own) + avg;
-        const float v = a.x_old[pix] - a.tau * xi;
-        a.x_out[pix] = v * a.prox_scale;
+        const float xo = a.x_old[pix];
+        const float xn = (xo - a.tau * xi) * a.prox_scale;
+        a.x_out[pix] = xn;
+        if (a.xbar) a.xbar[pix] = xn + a.theta * (xn - xo);
         if (a.kidx == 0) a.phi[a.phi_off[0] + pix] = g;
     }
     if (a.kidx > 0) {
@@ -808,7 +810,9 @@ __global__ void __launch_bounds__(1024) k_tv(TvArgs a)
     for (int k = 0; k < kTvCells; ++k) {
         if (!(flag[k] & kOut)) continue;
         const int li = cell[k] / R, lj = cell[k] - (cell[k] / R) * R;
-        a.out[(size_t)(gi0 + li) * n + gj0 + lj] = up[k];
+        const size_t g = (size_t)(gi0 + li) * n + gj0 + lj;
+        a.out[g] = up[k];
+        if (a.xbar) a.xbar[g] = up[k] + a.theta * (up[k] - a.u0[g]);
     }
 }
 

@@ -95,12 +95,16 @@ class Regularizer:
 
 @dataclass(frozen=True)
 class Params:
+    """Step size, draw stream, and the schedule: Alg. 1 (parallel) or the
+    ImaSk-Seq variant of Sec. 5 with extrapolation theta."""
     sigma: float
     seed: int = 42
     stream_id: int = 0
+    schedule: int = _abi.SCHEDULE_PARALLEL
+    theta: float = 1.0
 
     def c(self) -> _abi.Params:
-        return _abi.Params(self.sigma, self.seed, self.stream_id)
+        return _abi.Params(self.sigma, self.seed, self.stream_id, self.schedule, self.theta)
 
 
 def workspace(g: Geometry, device="cuda") -> torch.Tensor:
@@ -220,6 +224,7 @@ class Problem:
     phi: torch.Tensor | None = None
     psi: torch.Tensor | None = None
     work: torch.Tensor | None = None
+    xbar: torch.Tensor | None = None  # extrapolated point (sequential schedule)
     k: int = 0
     epochs: float = 0.0
     cur: int = 0
@@ -236,6 +241,8 @@ class Problem:
         self.phi = torch.zeros(nphi, device=dev)
         self.psi = torch.zeros((self.levels.r,) + g.sino_shape, device=dev)
         self.work = workspace(g, dev)
+        if self.params.schedule == _abi.SCHEDULE_SEQUENTIAL:
+            self.xbar = torch.zeros(g.image_shape, device=dev)
 
     # -- C struct round trip
     def _cstate(self) -> _abi.State:
@@ -244,6 +251,7 @@ class Problem:
         s.y[0], s.y[1] = self.y[0].data_ptr(), self.y[1].data_ptr()
         s.phi, s.psi, s.work = self.phi.data_ptr(), self.psi.data_ptr(), self.work.data_ptr()
         s.k, s.epochs, s.cur = self.k, self.epochs, self.cur
+        s.xbar = self.xbar.data_ptr() if self.xbar is not None else None
         return s
 
     def _absorb(self, s: _abi.State) -> None:
@@ -283,8 +291,11 @@ class Problem:
         return out
 
     def state_dict(self) -> dict:
-        return {"x": self.x_cur.clone(), "y": self.y_cur.clone(), "phi": self.phi.clone(),
-                "psi": self.psi.clone(), "k": self.k, "epochs": self.epochs}
+        d = {"x": self.x_cur.clone(), "y": self.y_cur.clone(), "phi": self.phi.clone(),
+             "psi": self.psi.clone(), "k": self.k, "epochs": self.epochs}
+        if self.xbar is not None:
+            d["xbar"] = self.xbar.clone()
+        return d
 
     def load_state_dict(self, d: dict) -> None:
         self.cur = 0
@@ -292,6 +303,8 @@ class Problem:
         self.y[0].copy_(d["y"])
         self.phi.copy_(d["phi"])
         self.psi.copy_(d["psi"])
+        if self.xbar is not None:
+            self.xbar.copy_(d["xbar"])
         self.k, self.epochs = int(d["k"]), float(d["epochs"])
 
 

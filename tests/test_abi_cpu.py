@@ -32,8 +32,8 @@ def test_library_exports_every_declared_symbol():
 def test_struct_sizes_match_c_layout():
     assert ctypes.sizeof(_abi.Geometry) == 32
     assert ctypes.sizeof(_abi.Levels) == 4 + 32 + 4 + 64 + 4 + 4
-    assert ctypes.sizeof(_abi.Params) == 24
-    assert ctypes.sizeof(_abi.State) == 8 * 7 + 8 + 8 + 8
+    assert ctypes.sizeof(_abi.Params) == 8 + 8 + 4 + 4 + 8
+    assert ctypes.sizeof(_abi.State) == 8 * 7 + 8 + 8 + 8 + 8
 
 
 def test_workspace_and_table_sizes():
@@ -87,6 +87,14 @@ def test_invalid_step_arguments_rejected():
                                  b, ctypes.byref(s), 1, None) == _abi.EINVAL
     assert _abi.lib().imask_solve(1, ctypes.byref(g), ctypes.byref(lv), ctypes.byref(reg), ctypes.byref(prm),
                                   b, ctypes.byref(s), 5.0, 7, None) == _abi.EINVAL
+    # schedules: unknown value; sequential without xbar, with xbar aliasing x, with theta outside [0, 1]
+    for sched, theta, xbar in [(5, 1.0, 128), (_abi.SCHEDULE_SEQUENTIAL, 1.0, None),
+                               (_abi.SCHEDULE_SEQUENTIAL, 1.0, 16), (_abi.SCHEDULE_SEQUENTIAL, 1.5, 128),
+                               (_abi.SCHEDULE_SEQUENTIAL, -0.1, 128)]:
+        s.xbar = xbar
+        bad = _abi.Params(0.01, 1, 0, sched, theta)
+        assert _abi.lib().imask_step(1, ctypes.byref(g), ctypes.byref(lv), ctypes.byref(reg), ctypes.byref(bad),
+                                     b, ctypes.byref(s), 1, None) == _abi.EINVAL, (sched, theta, xbar)
 
 
 @pytest.mark.parametrize("seed,stream,p", [(42, 0, (1 / 3,) * 3), (7, 5, (0.25,) * 4),

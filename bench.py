@@ -270,9 +270,16 @@ def reference_solution(geom, work, b32, lam, w, eps, iters, log):
 
 
 def race(args):
-    """Time to a relative error of 1e-3 against the common limit: ImaSk with
-    UNBIASED sketches (levels 512/256/128/64) vs full-resolution SAGA (r = 1),
-    same kernels, same GPU; each method runs a few step sizes."""
+    """Time to a relative error of 1e-3 against the common limit, same kernels,
+    same GPU, UNBIASED sketches (levels 512/256/128/64) so that every method
+    shares the limit:
+      imask_r4 / saga_r1  Alg. 1 with r = 4 / r = 1, sigma = m * sigma_thm3
+      seq_r4 / seq_r1     ImaSk-Seq (Sec. 5, theta = 1) with r = 4 / r = 1
+                          (r = 1 is PDHG), sigma = m * sigma_pd, where
+                          sigma_pd = (L^2)^{-1/2} is the single-level PDHG
+                          limit sigma tau |K|^2 < 1 with tau = sigma / mu.
+    Each method runs its grid of multiples m; the best time is reported
+    (the paper tunes ImaSk-Seq's step by a grid search too)."""
     import torch
 
     import paper_2412_10249_amd as pk
@@ -291,36 +298,48 @@ def race(args):
     log(f"reference done in {time.perf_counter() - t0:.1f} s, relative gradient {gnorm:.2e}")
     rnorm = float(torch.linalg.vector_norm(xref))
     reg = pk.Regularizer(pk.REG_SMOOTH_TV, LAM, TV_W, TV_EPS, TV_J)
+    r4 = pk.Levels.uniform(LEVELS, pk.FULL_UNBIASED)
+    r1 = pk.Levels((0,), (1.0,))
+    methods = {"imask_r4": (r4, pk.SCHEDULE_PARALLEL), "saga_r1": (r1, pk.SCHEDULE_PARALLEL),
+               "seq_r4": (r4, pk.SCHEDULE_SEQUENTIAL), "seq_r1": (r1, pk.SCHEDULE_SEQUENTIAL)}
     results = {}
-    for name, lv in (("imask_r4", pk.Levels.uniform(LEVELS, pk.FULL_UNBIASED)), ("saga_r1", pk.Levels((0,), (1.0,)))):
+    for name in args.methods:
+        lv, sched = methods[name]
         L2, lb, lp = pk.step_constants(geom, lv, LAM, work, iters=40)
         s3, th = pk.sigma_thm3(L2, lb, lp, min(lv.p), 100)
-        results[name] = {"constants": [L2, lb, lp], "sigma_thm3": s3, "theta_thm3": th, "runs": []}
-        for mult in args.sigma_mults:
-            sigma = s3 * mult
-            prob = pk.Problem(geom, lv, reg, pk.Params(sigma, SEED, STREAM), b32)
+        spd = 1.0 / np.sqrt(L2)
+        seq = sched == pk.SCHEDULE_SEQUENTIAL
+        base, mults = (spd, args.seq_sigma_mults) if seq else (s3, args.sigma_mults)
+        results[name] = {"constants": [L2, lb, lp], "sigma_thm3": s3, "theta_thm3": th, "sigma_pd": spd,
+                         "schedule": "sequential" if seq else "parallel", "runs": []}
+        check = args.seq_check_every if seq else args.check_every
+        for mult in mults:
+            sigma = base * mult
+            prob = pk.Problem(geom, lv, reg, pk.Params(sigma, SEED, STREAM, sched, 1.0), b32)
             torch.cuda.synchronize()
             hist = []
             tstart = time.perf_counter()
             tlog = tstart
             while prob.epochs < args.race_epochs:
-                prob.solve(args.check_every, pk.BUDGET_EPOCHS)
+                prob.solve(check, pk.BUDGET_EPOCHS)
                 err = float(torch.linalg.vector_norm(prob.x_cur - xref)) / rnorm  # synchronises
                 hist.append((time.perf_counter() - tstart, prob.epochs, err))
                 if time.perf_counter() - tlog > 20.0:
                     tlog = time.perf_counter()
                     log(f"  {name} sigma x{mult}: {prob.epochs:.0f} epochs, rel err {err:.3e}")
-                if err <= args.target or not np.isfinite(err) or time.perf_counter() - tstart > args.race_seconds:
+                if (err <= args.target or not np.isfinite(err) or err > 10.0
+                        or time.perf_counter() - tstart > args.race_seconds):
                     break
-            t_hit = None
-            for (t1, e1, r1), (t2, e2, r2) in zip(hist, hist[1:]):
-                if r2 <= args.target < r1:  # interpolate in log error
-                    f = (np.log(r1) - np.log(args.target)) / (np.log(r1) - np.log(r2))
+            t_hit = e_hit = None
+            for (t1, e1, r1_), (t2, e2, r2_) in zip([(0.0, 0.0, 1.0)] + hist, hist):
+                if r2_ <= args.target < r1_:  # interpolate in log error
+                    f = (np.log(r1_) - np.log(args.target)) / (np.log(r1_) - np.log(r2_))
                     t_hit = t1 + f * (t2 - t1)
+                    e_hit = e1 + f * (e2 - e1)
                     break
-            run_res = {"sigma": sigma, "sigma_over_thm3": mult, "epochs": prob.epochs, "final_rel_err": hist[-1][2],
-                       "seconds": hist[-1][0], "time_to_target_s": t_hit,
-                       "check_every_epochs": args.check_every,
+            run_res = {"sigma": sigma, "sigma_multiple": mult, "epochs": prob.epochs,
+                       "final_rel_err": hist[-1][2], "seconds": hist[-1][0], "time_to_target_s": t_hit,
+                       "epochs_to_target": e_hit, "check_every_epochs": check,
                        "rel_err_history": [(round(h[1], 2), round(h[2], 7)) for h in hist[::max(1, len(hist) // 60)]]}
             log(f"{name} sigma x{mult}: {run_res['final_rel_err']:.3e} after {prob.epochs:.1f} epochs, "
                 f"{hist[-1][0]:.2f} s, t(1e-3) = {t_hit}")
@@ -594,6 +613,9 @@ def main():
     ap.add_argument("--race-seconds", type=float, default=60.0)
     ap.add_argument("--sigma-mults", type=float, nargs="+", default=[1.0, 2.0])
     ap.add_argument("--check-every", type=float, default=10.0, help="epochs between error checks in the race")
+    ap.add_argument("--methods", nargs="+", default=["seq_r4", "seq_r1", "imask_r4", "saga_r1"])
+    ap.add_argument("--seq-sigma-mults", type=float, nargs="+", default=[0.125, 0.25, 0.35, 0.5, 0.7, 0.9])
+    ap.add_argument("--seq-check-every", type=float, default=1.0)
     ap.add_argument("--batched", action="store_true", help="64 mixed slices in flight")
     ap.add_argument("--slices", type=int, default=64)
     ap.add_argument("--streams", type=int, default=8)

@@ -736,10 +736,18 @@ __global__ void __launch_bounds__(256) k_primal(PrimalArgs a)
 // iteration: a cell at the tile's edge sees no neighbour beyond it, an error
 // that moves inward one pixel per iteration and so never reaches the output
 // tile, which lies J pixels inside.
-constexpr int kTvTile = 32;
-constexpr int kTvCells = ((kTvTile + 2 * IMASK_MAX_TV_INNER) * (kTvTile + 2 * IMASK_MAX_TV_INNER) + 1023) / 1024;
+#ifndef IMK_TV_TILE
+#define IMK_TV_TILE 32
+#endif
+#ifndef IMK_TV_THREADS
+#define IMK_TV_THREADS 1024
+#endif
+constexpr int kTvTile = IMK_TV_TILE;
+constexpr int kTvThreads = IMK_TV_THREADS;
+constexpr int kTvCells =
+    ((kTvTile + 2 * IMASK_MAX_TV_INNER) * (kTvTile + 2 * IMASK_MAX_TV_INNER) + kTvThreads - 1) / kTvThreads;
 
-__global__ void __launch_bounds__(1024) k_tv(TvArgs a)
+__global__ void __launch_bounds__(kTvThreads) k_tv(TvArgs a)
 {
     extern __shared__ float sm[];
     const int H = a.J;
@@ -757,7 +765,7 @@ __global__ void __launch_bounds__(1024) k_tv(TvArgs a)
     float vv[kTvCells], up[kTvCells];
 #pragma unroll
     for (int k = 0; k < kTvCells; ++k) {
-        const int q = threadIdx.x + k * 1024;
+        const int q = threadIdx.x + k * kTvThreads;
         flag[k] = 0;
         cell[k] = q;
         vv[k] = up[k] = 0.0f;
@@ -1081,7 +1089,9 @@ hipError_t launch_tv(const TvArgs& a, hipStream_t s)
     const int R = kTvTile + 2 * a.J;
     const size_t sh = (size_t)3 * R * R * sizeof(float);
     const int tiles = (a.n + kTvTile - 1) / kTvTile;
-    hipLaunchKernelGGL(k_tv, dim3(tiles * tiles), dim3(1024), sh, s, a);
+    const hipError_t e = allow_lds((const void*)k_tv, (int)sh);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_tv, dim3(tiles * tiles), dim3(kTvThreads), sh, s, a);
     return hipGetLastError();
 }
 

@@ -607,29 +607,29 @@ __global__ void __launch_bounds__(64 * W) k_bp_own(BpOwnArgs a)
 }
 
 // c = sum over the nq partial images in a fixed order; coef * c is stored coarse
-// (or into `tmp` for a later prolongation).  A workgroup takes 64 pixels;
-// its 16 wavefronts sum consecutive slices of the partials, and the slice
-// sums are added in slice order, so coarse levels with many small partial
-// images still spread over the whole chip.
-constexpr int kSumSlices = 16;
-__global__ void __launch_bounds__(64 * kSumSlices) k_bp_sum(BpOwnArgs a, float* tmp)
+// (or into `tmp` for a later prolongation).  The nq partials are cut into S
+// consecutive slices (S a power of two, chosen from the image size only so
+// that every level keeps about 2^18 threads busy): a workgroup of 1024
+// threads takes 1024/S pixels, each thread sums one slice of one pixel in
+// partial order, and the slice sums are added in slice order.
+__global__ void __launch_bounds__(1024) k_bp_sum(BpOwnArgs a, float* tmp, int S)
 {
-    __shared__ float red[kSumSlices][64];
+    __shared__ float red[1024];
     const int nl = a.n >> a.lvl;
     const size_t d = (size_t)nl * nl;
-    const int lane = threadIdx.x & 63;
-    const int sl = threadIdx.x >> 6;
-    const size_t e = (size_t)blockIdx.x * 64 + lane;
-    const int q0 = sl * a.nq / kSumSlices, q1 = (sl + 1) * a.nq / kSumSlices;
+    const int per = 1024 / S;  // pixels per workgroup
+    const int sl = threadIdx.x / per;
+    const int pi = threadIdx.x - sl * per;
+    const size_t e = (size_t)blockIdx.x * per + pi;
+    const int q0 = sl * a.nq / S, q1 = (sl + 1) * a.nq / S;
     float sum = 0.0f;
     if (e < d)
         for (int q = q0; q < q1; ++q) sum += a.part[q * d + e];
-    red[sl][lane] = sum;
+    red[threadIdx.x] = sum;
     __syncthreads();
     if (sl != 0 || e >= d) return;
-    float c = red[0][lane];
-#pragma unroll
-    for (int k = 1; k < kSumSlices; ++k) c += red[k][lane];
+    float c = red[pi];
+    for (int k = 1; k < S; ++k) c += red[k * per + pi];
     const float v = a.coef * c;
     if (a.prolong) {
         tmp[e] = v;
@@ -1066,7 +1066,10 @@ hipError_t launch_bp(const BpArgs& ba, hipStream_t s)
     if (e != hipSuccess) return e;
     const int nl = ba.n >> ba.lvl;
     const size_t d = (size_t)nl * nl;
-    hipLaunchKernelGGL(k_bp_sum, dim3((unsigned)((d + 63) / 64)), dim3(64 * kSumSlices), 0, s, a, ba.tmp);
+    int S = 1;  // slices: about 2^18 threads, at most 16, at most nq
+    while (S < 16 && S < a.nq && d * (size_t)S < ((size_t)1 << 18)) S *= 2;
+    const size_t per = 1024 / S;
+    hipLaunchKernelGGL(k_bp_sum, dim3((unsigned)((d + per - 1) / per)), dim3(1024), 0, s, a, ba.tmp, S);
     e = hipGetLastError();
     if (e != hipSuccess || !ba.prolong) return e;
     const size_t fine = (size_t)ba.n * ba.n;

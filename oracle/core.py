@@ -20,6 +20,7 @@ MODE_PAPER = 0
 MODE_UNBIASED = 1
 REG_TIKHONOV = 0
 REG_SMOOTH_TV = 1
+REG_TV = 2
 
 _D = ctypes.POINTER(ctypes.c_double)
 _I32 = ctypes.POINTER(ctypes.c_int32)
@@ -63,6 +64,8 @@ def lib():
         L.orc_tv_value.argtypes = [ctypes.c_int, _D, ctypes.c_double]
         L.orc_tv_value.restype = ctypes.c_double
         L.orc_tv_gradient.argtypes = [ctypes.c_int, _D, ctypes.c_double, _D]
+        L.orc_tv_fgp.argtypes = [ctypes.c_int, _D, ctypes.c_double, ctypes.c_int, _D, _D, _D]
+        L.orc_tv_fgp.restype = None
         L.orc_tv_prox.argtypes = [ctypes.c_int, _D, _D, ctypes.c_double, ctypes.c_double,
                                   ctypes.c_double, ctypes.c_double, ctypes.c_int, _D]
         L.orc_imask_run.argtypes = geo + [ctypes.c_int, _I32, _D, ctypes.c_int,
@@ -70,14 +73,14 @@ def lib():
                                           ctypes.c_double, ctypes.c_int,
                                           ctypes.c_double, ctypes.c_uint64, ctypes.c_uint32,
                                           ctypes.c_uint64, _D, ctypes.c_int,
-                                          _D, _D, _D, _D, _I32, _D]
+                                          _D, _D, _D, _D, _D, _I32, _D]
         L.orc_imask_run.restype = ctypes.c_int
         L.orc_imask_seq_run.argtypes = geo + [ctypes.c_int, _I32, _D, ctypes.c_int,
                                               ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                               ctypes.c_double, ctypes.c_int,
                                               ctypes.c_double, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint32,
                                               ctypes.c_uint64, _D, ctypes.c_int,
-                                              _D, _D, _D, _D, _D, _I32, _D]
+                                              _D, _D, _D, _D, _D, _D, _I32, _D]
         L.orc_imask_seq_run.restype = ctypes.c_int
     return _lib
 
@@ -226,10 +229,24 @@ def tv_prox(v, u0, tau: float, lam: float, w: float, eps: float, J: int) -> np.n
     return out
 
 
+def tv_fgp(b, gamma: float, J: int, p=None):
+    """prox of gamma TV + nonnegativity at b by J dual fast gradient
+    projection steps from the dual pair p (2, N, N; zeros if None).
+    Returns (u, p_after)."""
+    b = _f64(b)
+    n = b.shape[0]
+    pp = np.zeros((2, n, n)) if p is None else np.array(p, dtype=np.float64, copy=True)
+    u = np.empty_like(b)
+    lib().orc_tv_fgp(n, _dp(b), gamma, J, _dp(pp[0]), _dp(pp[1]), _dp(u))
+    return u, pp
+
+
 @dataclass
 class Reg:
-    """Regulariser: TIKHONOV R = lam/2 |x|^2, or SMOOTH_TV
-    R = w TV_eps + lam/2 |x|^2 with J FISTA iterations; mu = lam."""
+    """Regulariser: TIKHONOV R = lam/2 |x|^2; SMOOTH_TV
+    R = w TV_eps + lam/2 |x|^2 with J FISTA iterations; TV (the paper's
+    prior) R = w TV + chi_{>=0} + lam/2 |x|^2 with J dual FGP iterations
+    warm-started at the state's dual pair; mu = lam."""
     kind: int = REG_TIKHONOV
     lam: float = 1e-2
     tv_weight: float = 0.0
@@ -247,23 +264,32 @@ class State:
     epochs: float = 0.0
     draws: list = field(default_factory=list)
     xbar: np.ndarray | None = None  # extrapolated point (ImaSk-Seq only)
+    tvd: np.ndarray | None = None   # TV dual pair (2, N, N) of REG_TV's prox
 
     @staticmethod
     def zeros(g: Geometry, lv: Levels) -> "State":
         return State(np.zeros((g.n, g.n)), np.zeros((g.n_angles, g.n_det)),
                      np.zeros((lv.r, g.n, g.n)), np.zeros((lv.r, g.n_angles, g.n_det)),
-                     xbar=np.zeros((g.n, g.n)))
+                     xbar=np.zeros((g.n, g.n)), tvd=np.zeros((2, g.n, g.n)))
 
     def copy(self) -> "State":
         return State(self.x.copy(), self.y.copy(), self.phi.copy(), self.psi.copy(),
                      self.k, self.epochs, list(self.draws),
-                     None if self.xbar is None else self.xbar.copy())
+                     None if self.xbar is None else self.xbar.copy(),
+                     None if self.tvd is None else self.tvd.copy())
+
+    def ensure(self, g: Geometry) -> None:
+        if self.xbar is None:
+            self.xbar = self.x.copy()
+        if self.tvd is None:
+            self.tvd = np.zeros((2, g.n, g.n))
 
 
 def imask_run(g: Geometry, lv: Levels, reg: Reg, sigma: float, seed: int, stream: int,
               b, n_iter: int, state: State | None = None) -> State:
     """Alg. 1 (ImaSk) for n_iter iterations from `state` (zeros if None)."""
     st = State.zeros(g, lv) if state is None else state.copy()
+    st.ensure(g)
     b = _f64(b)
     lf, pp = lv.carrays()
     dr = np.empty(max(n_iter, 1), dtype=np.int32)
@@ -271,7 +297,7 @@ def imask_run(g: Geometry, lv: Levels, reg: Reg, sigma: float, seed: int, stream
     rc = lib().orc_imask_run(*g.args(), lv.r, lf.ctypes.data_as(_I32), _dp(pp), lv.mode,
                              reg.kind, reg.lam, reg.tv_weight, reg.tv_eps, reg.tv_inner,
                              sigma, seed, stream, st.k, _dp(b), n_iter,
-                             _dp(st.x), _dp(st.y), _dp(st.phi), _dp(st.psi),
+                             _dp(st.x), _dp(st.y), _dp(st.phi), _dp(st.psi), _dp(st.tvd),
                              dr.ctypes.data_as(_I32), _dp(ep))
     if rc != 0:
         raise ValueError("oracle rejected the level set")
@@ -285,8 +311,7 @@ def imask_seq_run(g: Geometry, lv: Levels, reg: Reg, sigma: float, theta: float,
                   b, n_iter: int, state: State | None = None) -> State:
     """ImaSk-Seq (Sec. 5) for n_iter iterations from `state` (zeros if None)."""
     st = State.zeros(g, lv) if state is None else state.copy()
-    if st.xbar is None:
-        st.xbar = st.x.copy()
+    st.ensure(g)
     b = _f64(b)
     lf, pp = lv.carrays()
     dr = np.empty(max(n_iter, 1), dtype=np.int32)
@@ -294,7 +319,7 @@ def imask_seq_run(g: Geometry, lv: Levels, reg: Reg, sigma: float, theta: float,
     rc = lib().orc_imask_seq_run(*g.args(), lv.r, lf.ctypes.data_as(_I32), _dp(pp), lv.mode,
                                  reg.kind, reg.lam, reg.tv_weight, reg.tv_eps, reg.tv_inner,
                                  sigma, theta, seed, stream, st.k, _dp(b), n_iter,
-                                 _dp(st.x), _dp(st.xbar), _dp(st.y), _dp(st.phi), _dp(st.psi),
+                                 _dp(st.x), _dp(st.xbar), _dp(st.y), _dp(st.phi), _dp(st.psi), _dp(st.tvd),
                                  dr.ctypes.data_as(_I32), _dp(ep))
     if rc != 0:
         raise ValueError("oracle rejected the level set")

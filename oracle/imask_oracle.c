@@ -16,8 +16,9 @@
  *   - the sketched operators K_l and their transposes (eq. (CT_sketches));
  *   - the counter-based SplitMix64 draw of the sketch index (Alg. 1, step
  *     "sample i_k with probability p");
- *   - Algorithm 1 (ImaSk) with the Tikhonov prox and a smoothed-TV prox
- *     evaluated by FISTA (Sec. 4.2 and 4.5);
+ *   - Algorithm 1 (ImaSk) with the Tikhonov prox, a smoothed-TV prox
+ *     evaluated by FISTA, and the paper's TV + nonnegativity prox by the
+ *     fast gradient projection on the dual (Sec. 4.2 and 4.5);
  *   - the ImaSk-Seq variant of Sec. 5 (dual step first, primal step with the
  *     new dual iterate, extrapolated primal point).
  *
@@ -42,7 +43,7 @@
 #define ORC_MAX_LEVELS 16
 
 enum { ORC_MODE_PAPER = 0, ORC_MODE_UNBIASED = 1 };
-enum { ORC_REG_TIKHONOV = 0, ORC_REG_SMOOTH_TV = 1 };
+enum { ORC_REG_TIKHONOV = 0, ORC_REG_SMOOTH_TV = 1, ORC_REG_TV = 2 };
 
 static int orc_row_stepping(int a, int na) { return 4 * a <= na || 4 * a >= 3 * na; }
 
@@ -397,6 +398,75 @@ void orc_tv_prox(int n, const double* v, const double* u0, double tau, double la
     free(un);
 }
 
+/* Prox of the paper's TV prior with nonnegativity (Sec. 4.5):
+ * argmin_u 1/2|u - b|^2 + gamma TV(u) + chi_{>=0}(u), TV(u) = sum |grad u|_2,
+ * by J iterations of the fast gradient projection on the dual (Beck and
+ * Teboulle, constrained TV denoising): the dual pair (p1, p2), one vector per
+ * pixel in the unit disc, gives u(p) = max(0, b - gamma grad^T p); a step
+ * of length 1/(8 gamma) along grad u(p) is projected back onto the discs,
+ * with FISTA extrapolation.  (p1, p2) is the warm start on entry and the
+ * last iterate on exit (the outer iteration keeps it); u = u(p_J). */
+void orc_tv_fgp(int n, const double* b, double gamma, int J, double* p1, double* p2, double* u)
+{
+    const long d = (long)n * n;
+    double* r1 = (double*)malloc(sizeof(double) * d);
+    double* r2 = (double*)malloc(sizeof(double) * d);
+    double* g1 = (double*)malloc(sizeof(double) * d);
+    double* g2 = (double*)malloc(sizeof(double) * d);
+    double* w = (double*)malloc(sizeof(double) * d);
+    memcpy(r1, p1, sizeof(double) * d);
+    memcpy(r2, p2, sizeof(double) * d);
+    double t = 1.0;
+    for (int it = 0; it < J; ++it) {
+        /* u at the extrapolated dual point */
+        orc_grad_adj(n, r1, r2, w);
+        for (long q = 0; q < d; ++q) w[q] = fmax(0.0, b[q] - gamma * w[q]);
+        /* projected gradient step on the dual */
+        orc_grad(n, w, g1, g2);
+        const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
+        const double beta = (t - 1.0) / tn;
+        for (long q = 0; q < d; ++q) {
+            const double a1 = r1[q] + g1[q] / (8.0 * gamma);
+            const double a2 = r2[q] + g2[q] / (8.0 * gamma);
+            const double nrm = fmax(1.0, sqrt(a1 * a1 + a2 * a2));
+            const double n1 = a1 / nrm, n2 = a2 / nrm;
+            r1[q] = n1 + beta * (n1 - p1[q]);
+            r2[q] = n2 + beta * (n2 - p2[q]);
+            p1[q] = n1;
+            p2[q] = n2;
+        }
+        t = tn;
+    }
+    orc_grad_adj(n, p1, p2, w);
+    for (long q = 0; q < d; ++q) u[q] = fmax(0.0, b[q] - gamma * w[q]);
+    free(r1);
+    free(r2);
+    free(g1);
+    free(g2);
+    free(w);
+}
+
+/* prox_{tau R}(v) for the three regularisers, x^k the current iterate (the
+ * smoothed-TV FISTA starts there), tvd the TV dual pair (2 n^2, ORC_REG_TV). */
+static void orc_prox(int n, int reg_kind, double tau, double lam, double tv_w, double tv_eps, int tv_inner,
+                     const double* v, const double* xk, double* tvd, double* out)
+{
+    const long d = (long)n * n;
+    if (reg_kind == ORC_REG_TIKHONOV) {
+        for (long q = 0; q < d; ++q) out[q] = v[q] / (1.0 + tau * lam);
+    } else if (reg_kind == ORC_REG_SMOOTH_TV) {
+        orc_tv_prox(n, v, xk, tau, lam, tv_w, tv_eps, tv_inner, out);
+    } else {
+        /* R = w TV + chi_{>=0} + lam/2 |.|^2: the quadratic folds into a
+         * rescaled TV denoising problem at v / (1 + tau lam) */
+        const double s = 1.0 + tau * lam;
+        double* bt = (double*)malloc(sizeof(double) * d);
+        for (long q = 0; q < d; ++q) bt[q] = v[q] / s;
+        orc_tv_fgp(n, bt, tau * tv_w / s, tv_inner, tvd, tvd + d, out);
+        free(bt);
+    }
+}
+
 /* ------------------------------------------------------------ Algorithm 1 */
 
 /* Runs n_iter iterations of ImaSk (Alg. 1) from the state (x, y, phi, psi)
@@ -410,7 +480,7 @@ int orc_imask_run(int n, int na, int nd, double ds, double s0,
                   int reg_kind, double lam, double tv_w, double tv_eps, int tv_inner,
                   double sigma, uint64_t seed, uint32_t stream, uint64_t k0,
                   const double* bdata, int n_iter,
-                  double* x, double* y, double* phi, double* psi,
+                  double* x, double* y, double* phi, double* psi, double* tvd,
                   int32_t* draws_out, double* epochs)
 {
     if (r < 1 || r > ORC_MAX_LEVELS || log2f[0] != 0) return -1;
@@ -442,13 +512,10 @@ int orc_imask_run(int n, int na, int nd, double ds, double s0,
             zeta[e] = gy[e] - psi[(long)k * m + e] + avg;
         }
         /* primal: prox_{tau R}(x - tau xi) */
-        for (long q = 0; q < d; ++q) xn[q] = x[q] - tau * xi[q];
-        if (reg_kind == ORC_REG_TIKHONOV) {
-            for (long q = 0; q < d; ++q) xn[q] = xn[q] / (1.0 + tau * lam);
-        } else {
+        {
             double* v = (double*)malloc(sizeof(double) * d);
-            memcpy(v, xn, sizeof(double) * d);
-            orc_tv_prox(n, v, x, tau, lam, tv_w, tv_eps, tv_inner, xn);
+            for (long q = 0; q < d; ++q) v[q] = x[q] - tau * xi[q];
+            orc_prox(n, reg_kind, tau, lam, tv_w, tv_eps, tv_inner, v, x, tvd, xn);
             free(v);
         }
         /* dual: (y + sigma zeta - sigma b)/(1 + sigma) */
@@ -487,7 +554,7 @@ int orc_imask_seq_run(int n, int na, int nd, double ds, double s0,
                       int reg_kind, double lam, double tv_w, double tv_eps, int tv_inner,
                       double sigma, double theta, uint64_t seed, uint32_t stream, uint64_t k0,
                       const double* bdata, int n_iter,
-                      double* x, double* xbar, double* y, double* phi, double* psi,
+                      double* x, double* xbar, double* y, double* phi, double* psi, double* tvd,
                       int32_t* draws_out, double* epochs)
 {
     if (r < 1 || r > ORC_MAX_LEVELS || log2f[0] != 0) return -1;
@@ -519,11 +586,7 @@ int orc_imask_seq_run(int n, int na, int nd, double ds, double s0,
             const double xi = gx[q] - phi[(long)k * d + q] + avg;
             v[q] = x[q] - tau * xi;
         }
-        if (reg_kind == ORC_REG_TIKHONOV) {
-            for (long q = 0; q < d; ++q) xn[q] = v[q] / (1.0 + tau * lam);
-        } else {
-            orc_tv_prox(n, v, x, tau, lam, tv_w, tv_eps, tv_inner, xn);
-        }
+        orc_prox(n, reg_kind, tau, lam, tv_w, tv_eps, tv_inner, v, x, tvd, xn);
         /* extrapolation, then the new iterate and the table refresh */
         for (long q = 0; q < d; ++q) {
             xbar[q] = xn[q] + theta * (xn[q] - x[q]);

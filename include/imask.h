@@ -50,7 +50,7 @@ enum {
 };
 
 enum { IMASK_FULL_PAPER = 0, IMASK_FULL_UNBIASED = 1 };
-enum { IMASK_REG_TIKHONOV = 0, IMASK_REG_SMOOTH_TV = 1 };
+enum { IMASK_REG_TIKHONOV = 0, IMASK_REG_SMOOTH_TV = 1, IMASK_REG_TV = 2 };
 enum { IMASK_SCHEDULE_PARALLEL = 0, IMASK_SCHEDULE_SEQUENTIAL = 1 };
 enum {
     IMASK_RESTRICT = 0,     /* out (N_l^2)  = T_l in, 2^l x 2^l block mean (Sec. 4.1) */
@@ -90,7 +90,14 @@ typedef struct {
  *   IMASK_REG_TIKHONOV  R = lambda/2 |x|^2, prox closed form
  *   IMASK_REG_SMOOTH_TV R = tv_weight * sum sqrt(|grad x|^2 + tv_eps^2)
  *                           + lambda/2 |x|^2, prox by tv_inner FISTA steps
- *                           (Sec. 4.5 evaluates the TV prox with FISTA). */
+ *                           (Sec. 4.5 evaluates the TV prox with FISTA)
+ *   IMASK_REG_TV        the paper's prior of Sec. 4.5, tv_weight |grad x|_{1,2}
+ *                       + chi_{x >= 0}, plus lambda/2 |x|^2 (which supplies
+ *                       the strong convexity mu = lambda of the step rule);
+ *                       prox by tv_inner iterations of the fast gradient
+ *                       projection on the dual (Beck-Teboulle), warm-started at
+ *                       the dual pair kept in imask_state.tvd; tv_eps unused.
+ * Differences are forward, with zero difference past the last row/column. */
 typedef struct {
     int32_t kind;
     double lambda;    /* > 0 */
@@ -130,6 +137,9 @@ typedef struct {
  *   xbar   N*N extrapolated point (IMASK_SCHEDULE_SEQUENTIAL only, updated
  *          in place; start it equal to x, e.g. both zero); may be NULL for
  *          the parallel schedule
+ *   tvd[2] two buffers of 2*N*N floats (IMASK_REG_TV only, ping-pong with
+ *          cur like x): the TV dual pair, row differences then column
+ *          differences; start tvd[cur] at zero; may be NULL otherwise
  *   k      iteration counter (index of the next draw)
  *   epochs equivalent full-resolution operator applications so far
  *   cur    0 or 1 */
@@ -143,6 +153,7 @@ typedef struct {
     double epochs;
     int32_t cur;
     float* xbar;
+    float* tvd[2];
 } imask_state;
 
 /* Bytes of device workspace needed for geometry g (host function). */

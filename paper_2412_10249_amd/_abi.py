@@ -17,7 +17,7 @@ MAX_TV_INNER = 12
 
 OK, EINVAL, ENOTSUP, EHIP, ESIZE = 0, -1, -2, -3, -4
 FULL_PAPER, FULL_UNBIASED = 0, 1
-REG_TIKHONOV, REG_SMOOTH_TV = 0, 1
+REG_TIKHONOV, REG_SMOOTH_TV, REG_TV = 0, 1, 2
 RESTRICT, PROLONG, RESTRICT_ADJ, PROJECT, COMPENSATE = 0, 1, 2, 3, 4
 BUDGET_ITERS, BUDGET_EPOCHS = 0, 1
 SCHEDULE_PARALLEL, SCHEDULE_SEQUENTIAL = 0, 1
@@ -52,7 +52,8 @@ class Params(ctypes.Structure):
 class State(ctypes.Structure):
     _fields_ = [("x", ctypes.c_void_p * 2), ("y", ctypes.c_void_p * 2), ("phi", ctypes.c_void_p),
                 ("psi", ctypes.c_void_p), ("work", ctypes.c_void_p), ("k", ctypes.c_uint64),
-                ("epochs", ctypes.c_double), ("cur", ctypes.c_int32), ("xbar", ctypes.c_void_p)]
+                ("epochs", ctypes.c_double), ("cur", ctypes.c_int32), ("xbar", ctypes.c_void_p),
+                ("tvd", ctypes.c_void_p * 2)]
 
 
 class ImaskError(RuntimeError):

@@ -91,9 +91,10 @@ static bool reg_ok(const imask_reg* r)
 {
     if (!r || !(r->lambda > 0.0) || !std::isfinite(r->lambda)) return false;
     if (r->kind == IMASK_REG_TIKHONOV) return true;
+    const bool inner = r->tv_inner >= 1 && r->tv_inner <= IMASK_MAX_TV_INNER;
+    if (r->kind == IMASK_REG_TV) return r->tv_weight > 0.0 && std::isfinite(r->tv_weight) && inner;
     if (r->kind != IMASK_REG_SMOOTH_TV) return false;
-    return r->tv_weight >= 0.0 && std::isfinite(r->tv_weight) && r->tv_eps > 0.0 && std::isfinite(r->tv_eps) &&
-           r->tv_inner >= 1 && r->tv_inner <= IMASK_MAX_TV_INNER;
+    return r->tv_weight >= 0.0 && std::isfinite(r->tv_weight) && r->tv_eps > 0.0 && std::isfinite(r->tv_eps) && inner;
 }
 
 static bool state_ok(const imask_state* s)
@@ -231,6 +232,17 @@ static void phi_offsets(const imask_geometry& g, const imask_levels& lv, long lo
     }
 }
 
+// FISTA extrapolation weights (t_j - 1) / t_{j+1}, t_0 = 1 (Beck-Teboulle).
+static void fista_betas(int J, float* beta)
+{
+    double t = 1.0;
+    for (int it = 0; it < J; ++it) {
+        const double tn = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t * t));
+        beta[it] = (float)((t - 1.0) / tn);
+        t = tn;
+    }
+}
+
 static int one_step(const imask_geometry& g, const Layout& L, const imask_levels& lv, const imask_reg& reg,
                     const imask_params& prm, const float* bdat, imask_state& st, hipStream_t s)
 {
@@ -279,7 +291,7 @@ static int one_step(const imask_geometry& g, const Layout& L, const imask_levels
 
     // a6-a7: prolongation / compensation, primal SAGA step, phi refresh
     const double tau = prm.sigma / reg.lambda;
-    const bool tv = reg.kind == IMASK_REG_SMOOTH_TV;
+    const bool tv = reg.kind != IMASK_REG_TIKHONOV;  // the prox runs in its own kernel
     PrimalArgs pr{};
     pr.n = g.n;
     pr.T = tile_side(g.n, lmax_set);
@@ -304,8 +316,28 @@ static int one_step(const imask_geometry& g, const Layout& L, const imask_levels
     pr.theta = (float)prm.theta;
     IMK_TRY(launch_primal(pr, s));
 
+    // a8: the paper's TV prior: dual FGP from the kept dual pair at
+    // v / (1 + tau lam) with weight tau w / (1 + tau lam)
+    if (reg.kind == IMASK_REG_TV) {
+        const double sc = 1.0 + tau * reg.lambda;
+        TvdArgs ta{};
+        ta.n = g.n;
+        ta.J = reg.tv_inner;
+        ta.v = W + L.vbuf;
+        ta.pin = st.tvd[cur];
+        ta.pout = st.tvd[nxt];
+        ta.out = st.x[nxt];
+        ta.u0 = st.x[cur];
+        ta.xbar = seq ? st.xbar : nullptr;
+        ta.theta = (float)prm.theta;
+        ta.inv_scale = (float)(1.0 / sc);
+        ta.gamma = (float)(tau * reg.tv_weight / sc);
+        ta.inv8g = (float)(1.0 / (8.0 * tau * reg.tv_weight / sc));
+        fista_betas(reg.tv_inner, ta.beta);
+        IMK_TRY(launch_tvd(ta, s));
+    }
     // a8: smoothed-TV prox by FISTA, warm-started at x^k
-    if (tv) {
+    if (reg.kind == IMASK_REG_SMOOTH_TV) {
         TvArgs ta{};
         ta.n = g.n;
         ta.J = reg.tv_inner;
@@ -318,12 +350,7 @@ static int one_step(const imask_geometry& g, const Layout& L, const imask_levels
         ta.tau_lam = (float)(tau * reg.lambda);
         ta.eps = (float)reg.tv_eps;
         ta.invL = (float)(1.0 / (1.0 + tau * reg.lambda + 8.0 * tau * reg.tv_weight / reg.tv_eps));
-        double t = 1.0;
-        for (int it = 0; it < reg.tv_inner; ++it) {
-            const double tn = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t * t));
-            ta.beta[it] = (float)((t - 1.0) / tn);
-            t = tn;
-        }
+        fista_betas(reg.tv_inner, ta.beta);
         IMK_TRY(launch_tv(ta, s));
     }
 
@@ -758,6 +785,7 @@ static int check_problem(const imask_geometry* g, const imask_levels* lv, const 
     const int lmax = level_limit(g->n);
     if (!levels_ok(lv, lmax) || !reg_ok(reg) || !prm || !b || !state_ok(s)) return IMASK_EINVAL;
     if (!(prm->sigma > 0.0) || !std::isfinite(prm->sigma)) return IMASK_EINVAL;
+    if (reg->kind == IMASK_REG_TV && (!s->tvd[0] || !s->tvd[1] || s->tvd[0] == s->tvd[1])) return IMASK_EINVAL;
     if (prm->schedule == IMASK_SCHEDULE_SEQUENTIAL) {
         if (!(prm->theta >= 0.0 && prm->theta <= 1.0) || !s->xbar) return IMASK_EINVAL;
         if (s->xbar == s->x[0] || s->xbar == s->x[1]) return IMASK_EINVAL;

@@ -193,6 +193,21 @@ hipError_t launch_bp(const BpArgs& a, hipStream_t s);          // transpose kern
 hipError_t launch_bp_main(const BpArgs& a, hipStream_t s, BpOwnArgs& used);  // transpose kernel only
 hipError_t launch_primal(const PrimalArgs& a, hipStream_t s);
 hipError_t launch_tv(const TvArgs& a, hipStream_t s);
+
+// Prox of gamma TV + nonnegativity at v / scale by J dual FGP iterations.
+struct TvdArgs {
+    int n, J;
+    const float* v;       // prox input (before the 1/scale)
+    const float* pin;     // dual pair in (2 n^2)
+    float* pout;          // dual pair out (2 n^2)
+    float* out;           // x^{k+1}
+    const float* u0;      // x^k, for the extrapolation
+    float* xbar;          // when set: xbar = out + theta (out - u0)
+    float theta;
+    float inv_scale, gamma, inv8g;
+    float beta[IMASK_MAX_TV_INNER];
+};
+hipError_t launch_tvd(const TvdArgs& a, hipStream_t s);
 hipError_t launch_prolong(const float* in, float* out, int n, int lvl, float coef, hipStream_t s);
 hipError_t launch_project_block(const float* in, float* out, int n, int lvl, hipStream_t s);
 

@@ -744,8 +744,9 @@ __global__ void __launch_bounds__(256) k_primal(PrimalArgs a)
 #endif
 constexpr int kTvTile = IMK_TV_TILE;
 constexpr int kTvThreads = IMK_TV_THREADS;
-constexpr int kTvCells =
-    ((kTvTile + 2 * IMASK_MAX_TV_INNER) * (kTvTile + 2 * IMASK_MAX_TV_INNER) + kTvThreads - 1) / kTvThreads;
+// cells per thread: the tile with the largest halo either kernel uses (J + 1)
+constexpr int kTvSideMax = kTvTile + 2 * (IMASK_MAX_TV_INNER + 1);
+constexpr int kTvCells = (kTvSideMax * kTvSideMax + kTvThreads - 1) / kTvThreads;
 
 __global__ void __launch_bounds__(kTvThreads) k_tv(TvArgs a)
 {
@@ -821,6 +822,111 @@ __global__ void __launch_bounds__(kTvThreads) k_tv(TvArgs a)
         const size_t g = (size_t)(gi0 + li) * n + gj0 + lj;
         a.out[g] = up[k];
         if (a.xbar) a.xbar[g] = up[k] + a.theta * (up[k] - a.u0[g]);
+    }
+}
+
+// Prox of gamma TV + chi_{>=0} at bt = v / scale (the paper's TV prior,
+// Sec. 4.5), by J iterations of the fast gradient projection on the dual
+// pair (p1, p2) (Beck-Teboulle), warm-started at the pair of the previous
+// outer step.  Per iteration: u = max(0, bt - gamma grad^T r); the dual takes
+// a step 1/(8 gamma) along grad u, is projected onto the unit disc per pixel
+// and extrapolated.  Tiled like k_tv with a (J+1)-pixel halo: u reads r one
+// pixel up/left, the dual step reads u one pixel down/right, so an edge
+// error moves inward one pixel per iteration and the final u one more.
+__global__ void __launch_bounds__(kTvThreads) k_tvd(TvdArgs a)
+{
+    extern __shared__ float sm[];
+    const int H = a.J + 1;
+    const int R = kTvTile + 2 * H;
+    float* r1 = sm;          // extrapolated dual, row differences
+    float* r2 = r1 + R * R;  // extrapolated dual, column differences
+    float* uu = r2 + R * R;  // primal u(r)
+    const int tiles = (a.n + kTvTile - 1) / kTvTile;
+    const int ty = blockIdx.x / tiles, tx = blockIdx.x - ty * tiles;
+    const int gi0 = ty * kTvTile - H, gj0 = tx * kTvTile - H;
+    const int n = a.n;
+    const size_t d = (size_t)n * n;
+    enum { kIn = 1, kDown = 2, kRight = 4, kUp = 8, kLeft = 16, kOut = 32 };
+    int cell[kTvCells], flag[kTvCells];
+    float bt[kTvCells], p1[kTvCells], p2[kTvCells];
+#pragma unroll
+    for (int k = 0; k < kTvCells; ++k) {
+        const int q = threadIdx.x + k * kTvThreads;
+        flag[k] = 0;
+        cell[k] = q;
+        bt[k] = p1[k] = p2[k] = 0.0f;
+        if (q >= R * R) continue;
+        const int li = q / R, lj = q - li * R;
+        const int gi = gi0 + li, gj = gj0 + lj;
+        if (gi < 0 || gi >= n || gj < 0 || gj >= n) {
+            r1[q] = r2[q] = uu[q] = 0.0f;
+            continue;
+        }
+        const bool down = gi < n - 1, right = gj < n - 1;  // differences that exist in the image
+        flag[k] = kIn | (down && li < R - 1 ? kDown : 0) | (right && lj < R - 1 ? kRight : 0) |
+                  (gi >= 1 && li >= 1 ? kUp : 0) | (gj >= 1 && lj >= 1 ? kLeft : 0) |
+                  (li >= H && li < H + kTvTile && lj >= H && lj < H + kTvTile ? kOut : 0);
+        const size_t g = (size_t)gi * n + gj;
+        bt[k] = a.v[g] * a.inv_scale;
+        p1[k] = down ? a.pin[g] : 0.0f;
+        p2[k] = right ? a.pin[d + g] : 0.0f;
+        r1[q] = p1[k];
+        r2[q] = p2[k];
+    }
+    __syncthreads();
+    for (int t = 0; t < a.J; ++t) {
+        // u = max(0, bt - gamma grad^T r)
+#pragma unroll
+        for (int k = 0; k < kTvCells; ++k) {
+            if (!(flag[k] & kIn)) continue;
+            const int c = cell[k];
+            float gt = -r1[c] - r2[c];
+            if (flag[k] & kUp) gt += r1[c - R];
+            if (flag[k] & kLeft) gt += r2[c - 1];
+            uu[c] = fmaxf(0.0f, bt[k] - a.gamma * gt);
+        }
+        __syncthreads();
+        const float beta = a.beta[t];
+#pragma unroll
+        for (int k = 0; k < kTvCells; ++k) {
+            if (!(flag[k] & kIn)) continue;
+            const int c = cell[k];
+            const float uc = uu[c];
+            const float g1 = (flag[k] & kDown) ? uu[c + R] - uc : 0.0f;
+            const float g2 = (flag[k] & kRight) ? uu[c + 1] - uc : 0.0f;
+            const float a1 = fmaf(g1, a.inv8g, r1[c]);
+            const float a2 = fmaf(g2, a.inv8g, r2[c]);
+            const float sc = fminf(1.0f, rsqrtf(fmaf(a1, a1, a2 * a2)));  // 1 / max(1, |a|)
+            const float n1 = a1 * sc, n2 = a2 * sc;
+            r1[c] = n1 + beta * (n1 - p1[k]);
+            r2[c] = n2 + beta * (n2 - p2[k]);
+            p1[k] = n1;
+            p2[k] = n2;
+        }
+        __syncthreads();
+    }
+    // u(p_J) on the output tile, and the dual pair for the next outer step
+#pragma unroll
+    for (int k = 0; k < kTvCells; ++k) {
+        if (!(flag[k] & kIn)) continue;
+        r1[cell[k]] = p1[k];
+        r2[cell[k]] = p2[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kTvCells; ++k) {
+        if (!(flag[k] & kOut)) continue;
+        const int c = cell[k];
+        float gt = -r1[c] - r2[c];
+        if (flag[k] & kUp) gt += r1[c - R];
+        if (flag[k] & kLeft) gt += r2[c - 1];
+        const float u = fmaxf(0.0f, bt[k] - a.gamma * gt);
+        const int li = c / R, lj = c - li * R;
+        const size_t g = (size_t)(gi0 + li) * n + gj0 + lj;
+        a.out[g] = u;
+        if (a.xbar) a.xbar[g] = u + a.theta * (u - a.u0[g]);
+        a.pout[g] = p1[k];
+        a.pout[d + g] = p2[k];
     }
 }
 
@@ -1095,6 +1201,17 @@ hipError_t launch_tv(const TvArgs& a, hipStream_t s)
     const hipError_t e = allow_lds((const void*)k_tv, (int)sh);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_tv, dim3(tiles * tiles), dim3(kTvThreads), sh, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_tvd(const TvdArgs& a, hipStream_t s)
+{
+    const int R = kTvTile + 2 * (a.J + 1);
+    const size_t sh = (size_t)3 * R * R * sizeof(float);
+    const int tiles = (a.n + kTvTile - 1) / kTvTile;
+    const hipError_t e = allow_lds((const void*)k_tvd, (int)sh);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_tvd, dim3(tiles * tiles), dim3(kTvThreads), sh, s, a);
     return hipGetLastError();
 }
 

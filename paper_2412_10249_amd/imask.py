@@ -225,6 +225,7 @@ class Problem:
     psi: torch.Tensor | None = None
     work: torch.Tensor | None = None
     xbar: torch.Tensor | None = None  # extrapolated point (sequential schedule)
+    tvd: list = field(default_factory=list)  # TV dual pair, two ping-pong buffers (REG_TV)
     k: int = 0
     epochs: float = 0.0
     cur: int = 0
@@ -243,6 +244,8 @@ class Problem:
         self.work = workspace(g, dev)
         if self.params.schedule == _abi.SCHEDULE_SEQUENTIAL:
             self.xbar = torch.zeros(g.image_shape, device=dev)
+        if self.reg.kind == _abi.REG_TV:
+            self.tvd = [torch.zeros((2,) + g.image_shape, device=dev) for _ in range(2)]
 
     # -- C struct round trip
     def _cstate(self) -> _abi.State:
@@ -252,6 +255,8 @@ class Problem:
         s.phi, s.psi, s.work = self.phi.data_ptr(), self.psi.data_ptr(), self.work.data_ptr()
         s.k, s.epochs, s.cur = self.k, self.epochs, self.cur
         s.xbar = self.xbar.data_ptr() if self.xbar is not None else None
+        if self.tvd:
+            s.tvd[0], s.tvd[1] = self.tvd[0].data_ptr(), self.tvd[1].data_ptr()
         return s
 
     def _absorb(self, s: _abi.State) -> None:
@@ -295,6 +300,8 @@ class Problem:
              "psi": self.psi.clone(), "k": self.k, "epochs": self.epochs}
         if self.xbar is not None:
             d["xbar"] = self.xbar.clone()
+        if self.tvd:
+            d["tvd"] = self.tvd[self.cur].clone()
         return d
 
     def load_state_dict(self, d: dict) -> None:
@@ -305,6 +312,8 @@ class Problem:
         self.psi.copy_(d["psi"])
         if self.xbar is not None:
             self.xbar.copy_(d["xbar"])
+        if self.tvd:
+            self.tvd[0].copy_(d["tvd"])
         self.k, self.epochs = int(d["k"]), float(d["epochs"])
 
 

@@ -33,7 +33,7 @@ def test_struct_sizes_match_c_layout():
     assert ctypes.sizeof(_abi.Geometry) == 32
     assert ctypes.sizeof(_abi.Levels) == 4 + 32 + 4 + 64 + 4 + 4
     assert ctypes.sizeof(_abi.Params) == 8 + 8 + 4 + 4 + 8
-    assert ctypes.sizeof(_abi.State) == 8 * 7 + 8 + 8 + 8 + 8
+    assert ctypes.sizeof(_abi.State) == 8 * 7 + 8 + 8 + 8 + 8 + 16
 
 
 def test_workspace_and_table_sizes():
@@ -87,6 +87,16 @@ def test_invalid_step_arguments_rejected():
                                  b, ctypes.byref(s), 1, None) == _abi.EINVAL
     assert _abi.lib().imask_solve(1, ctypes.byref(g), ctypes.byref(lv), ctypes.byref(reg), ctypes.byref(prm),
                                   b, ctypes.byref(s), 5.0, 7, None) == _abi.EINVAL
+    # the TV prior needs two distinct dual buffers and a positive weight
+    tvr = _abi.Reg(_abi.REG_TV, 0.01, 1.0, 0.0, 10)
+    s.tvd[0], s.tvd[1] = 144, 144
+    assert _abi.lib().imask_step(1, ctypes.byref(g), ctypes.byref(lv), ctypes.byref(tvr), ctypes.byref(prm),
+                                 b, ctypes.byref(s), 1, None) == _abi.EINVAL
+    s.tvd[0], s.tvd[1] = 144, 160
+    tv0 = _abi.Reg(_abi.REG_TV, 0.01, 0.0, 0.0, 10)
+    assert _abi.lib().imask_step(1, ctypes.byref(g), ctypes.byref(lv), ctypes.byref(tv0), ctypes.byref(prm),
+                                 b, ctypes.byref(s), 1, None) == _abi.EINVAL
+    s.tvd[0], s.tvd[1] = None, None
     # schedules: unknown value; sequential without xbar, with xbar aliasing x, with theta outside [0, 1]
     for sched, theta, xbar in [(5, 1.0, 128), (_abi.SCHEDULE_SEQUENTIAL, 1.0, None),
                                (_abi.SCHEDULE_SEQUENTIAL, 1.0, 16), (_abi.SCHEDULE_SEQUENTIAL, 1.5, 128),

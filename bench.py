@@ -351,6 +351,81 @@ def race(args):
                       "results": results}), flush=True)
 
 
+def study(args):
+    """Fixed-budget studies on the 512^2 workload, PSNR against the phantom
+    every few epochs (the quantity of the paper's Sec. 4 figures):
+      stepsize  ImaSk r = 4 (PAPER sketches), Tikhonov lam = 1e-2, with
+                sigma in {sigma*/2, sigma*, sigma_B} (sigma* of Thm. 3, sigma_B
+                of Sec. 3.6)
+      tv        the paper's TV + nonnegativity prior (w = 2e-4, lam = 1e-4 for
+                the step rule), ImaSk with r = 1, 2, 4 at 1, 4, 16 and 64 times
+                its Thm. 3 step (the prior is barely strongly convex, so the
+                theorem's step is very conservative), and ImaSk-Seq with
+                r = 1, 4 at a quarter and half of the PDHG limit"""
+    import torch
+
+    import paper_2412_10249_amd as pk
+    import synth
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    torch.cuda.set_device(0)
+    x_true, b = synth.ct_problem(N, NA, ND, I0, 1000, 2000)
+    b32 = torch.from_numpy(b.astype(np.float32)).cuda()
+    xt = torch.from_numpy(x_true.astype(np.float32)).cuda()
+    peak = float(xt.max())
+    geom = pk.Geometry(N, NA, ND)
+    work = pk.workspace(geom)
+
+    def psnr(x):
+        mse = float(torch.mean((x - xt) ** 2))
+        return 10.0 * np.log10(peak * peak / mse)
+
+    runs = []
+    if args.study == "stepsize":
+        lam = 1e-2
+        lv = pk.Levels.uniform(LEVELS, pk.FULL_PAPER)
+        reg = pk.Regularizer(pk.REG_TIKHONOV, lam)
+        L2, lb, lp = pk.step_constants(geom, lv, lam, work, iters=40)
+        s3 = pk.sigma_thm3(L2, lb, lp, min(lv.p), 100)[0]
+        sb = pk.sigma_balamurugan(L2, lb)
+        cases = [("sigma*/2", lv, reg, s3 / 2, pk.SCHEDULE_PARALLEL), ("sigma*", lv, reg, s3, pk.SCHEDULE_PARALLEL),
+                 ("sigma_B", lv, reg, sb, pk.SCHEDULE_PARALLEL)]
+        info = {"constants": [L2, lb, lp], "sigma_star": s3, "sigma_B": sb, "lam": lam}
+    else:
+        lam, w = 1e-4, 2e-4
+        reg = pk.Regularizer(pk.REG_TV, lam, w, 0.0, TV_J)
+        cases = []
+        info = {"lam": lam, "tv_weight": w, "tv_inner": TV_J}
+        for r in (1, 2, 4):
+            lv = pk.Levels.uniform(LEVELS[:r], pk.FULL_PAPER)
+            L2, lb, lp = pk.step_constants(geom, lv, lam, work, iters=40)
+            s3 = pk.sigma_thm3(L2, lb, lp, min(lv.p), 100)[0]
+            for m in (1, 4, 16, 64):
+                cases.append((f"imask_r{r} x{m}", lv, reg, m * s3, pk.SCHEDULE_PARALLEL))
+            if r != 2:
+                for m in (0.25, 0.5):
+                    cases.append((f"seq_r{r} x{m}", lv, reg, m / np.sqrt(L2), pk.SCHEDULE_SEQUENTIAL))
+    for name, lv, reg, sigma, sched in cases:
+        prob = pk.Problem(geom, lv, reg, pk.Params(sigma, SEED, STREAM, sched, 1.0), b32)
+        torch.cuda.synchronize()
+        prob.step(1)  # first launches (code objects, LDS attributes) outside the clock
+        torch.cuda.synchronize()
+        hist = []
+        t0 = time.perf_counter()
+        while prob.epochs < args.study_epochs:
+            prob.solve(args.study_every, pk.BUDGET_EPOCHS)
+            hist.append((round(time.perf_counter() - t0, 4), round(prob.epochs, 3), round(psnr(prob.x_cur), 3)))
+            if not np.isfinite(hist[-1][2]):
+                break
+        log(f"{name}: sigma {sigma:.3e}, {prob.epochs:.1f} epochs, {hist[-1][0]:.2f} s, PSNR {hist[-1][2]:.2f} dB")
+        runs.append({"name": name, "sigma": sigma, "schedule": "sequential" if sched else "parallel",
+                     "levels": list(lv.log2f), "history_s_epochs_psnr": hist})
+    print(json.dumps({"metric": f"PSNR vs epochs, {args.study} study (512x512, 720 x 768)", "info": info,
+                      "runs": runs}), flush=True)
+
+
 # ------------------------------------------------------------ systems workloads
 
 def _sigma_for(geom, levels, lam, work, cache={}):
@@ -629,7 +704,13 @@ def main():
     ap.add_argument("--serve-epochs", type=float, default=30.0)
     ap.add_argument("--autograd", action="store_true", help="differentiable unrolled ImaSk")
     ap.add_argument("--batch", type=int, default=32)
+    ap.add_argument("--study", choices=["stepsize", "tv"], help="fixed-budget PSNR studies")
+    ap.add_argument("--study-epochs", type=float, default=100.0)
+    ap.add_argument("--study-every", type=float, default=5.0)
     args = ap.parse_args()
+    if args.study:
+        study(args)
+        return
     if args.batched:
         batched(args)
         return

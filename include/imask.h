@@ -222,6 +222,11 @@ int imask_step_constants(const imask_geometry* g, const imask_levels* lv, double
  * minimising the rate theta over c = cbar*i/(grid+1), rho = j/(grid+1),
  * i, j = 1..grid, cbar = 1/(1 + L^2 + Lbar_p^2); sigma = eta_opt/(1 - eta_opt).
  * theta_out (may be NULL) receives the rate. */
+/* Host: the comparison step size of Sec. 3.6 taken from Balamurugan & Bach,
+ * sigma_B = 1 / (L^2 + 3 Lbar^2), from the constants of imask_step_constants.
+ * Returns IMASK_EINVAL for non-positive constants or a NULL output. */
+int imask_sigma_balamurugan(double L2, double Lbar2, double* sigma_out);
+
 int imask_sigma_thm3(double L2, double Lbar2, double Lbarp2, double pmin, int32_t grid, double* sigma_out,
                      double* theta_out);
 

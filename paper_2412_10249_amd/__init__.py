@@ -10,5 +10,5 @@ from ._abi import (  # noqa: F401
 )
 from .imask import (  # noqa: F401
     Geometry, Levels, Params, Problem, Regularizer, backproject, draws, project, resample,
-    sigma_thm3, sketch_apply, step_constants, step_many, time_kernel, workspace,
+    sigma_balamurugan, sigma_thm3, sketch_apply, step_constants, step_many, time_kernel, workspace,
 )

@@ -25,7 +25,7 @@ SCHEDULE_PARALLEL, SCHEDULE_SEQUENTIAL = 0, 1
 EXPORTS = ["imask_workspace_bytes", "imask_phi_floats", "imask_prepare", "imask_project",
            "imask_backproject", "imask_resample", "imask_sketch_apply", "imask_draws",
            "imask_step", "imask_solve", "imask_time_kernel", "imask_constants_scratch_bytes",
-           "imask_step_constants", "imask_sigma_thm3"]
+           "imask_step_constants", "imask_sigma_thm3", "imask_sigma_balamurugan"]
 KERNEL_FORWARD, KERNEL_TRANSPOSE = 0, 1
 
 
@@ -88,6 +88,7 @@ def lib():
                                            P(ctypes.c_double), vp]
         L.imask_sigma_thm3.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double, i32,
                                        P(ctypes.c_double), P(ctypes.c_double)]
+        L.imask_sigma_balamurugan.argtypes = [ctypes.c_double, ctypes.c_double, P(ctypes.c_double)]
         L.imask_step.argtypes = [i32, P(Geometry), P(Levels), P(Reg), P(Params), P(vp), P(State), i32, vp]
         L.imask_solve.argtypes = [i32, P(Geometry), P(Levels), P(Reg), P(Params), P(vp), P(State),
                                   ctypes.c_double, i32, vp]

@@ -734,6 +734,13 @@ int imask_step_constants(const imask_geometry* g, const imask_levels* lv, double
     return IMASK_OK;
 }
 
+int imask_sigma_balamurugan(double L2, double Lbar2, double* sigma_out)
+{
+    if (!(L2 > 0) || !(Lbar2 > 0) || !std::isfinite(L2) || !std::isfinite(Lbar2) || !sigma_out) return IMASK_EINVAL;
+    *sigma_out = 1.0 / (L2 + 3.0 * Lbar2);
+    return IMASK_OK;
+}
+
 int imask_sigma_thm3(double L2, double Lbar2, double Lbarp2, double pmin, int32_t grid, double* sigma_out,
                      double* theta_out)
 {

@@ -204,6 +204,13 @@ def sigma_thm3(L2: float, Lbar2: float, Lbarp2: float, pmin: float, grid: int = 
     return sig.value, th.value
 
 
+def sigma_balamurugan(L2: float, Lbar2: float) -> float:
+    """sigma_B = 1/(L^2 + 3 Lbar^2), the comparison step of Sec. 3.6."""
+    out = ctypes.c_double()
+    check(lib().imask_sigma_balamurugan(L2, Lbar2, ctypes.byref(out)), "imask_sigma_balamurugan")
+    return out.value
+
+
 def draws(params: Params, levels: Levels, k0: int, count: int) -> np.ndarray:
     out = (ctypes.c_int32 * max(count, 1))()
     check(lib().imask_draws(ctypes.byref(params.c()), ctypes.byref(levels.c()), k0, count, out), "imask_draws")

@@ -132,3 +132,13 @@ def test_sigma_thm3_rejects_bad_constants():
         im.sigma_thm3(-1.0, 1.0, 1.0, 0.5)
     with pytest.raises(im.ImaskError):
         im.sigma_thm3(1.0, 1.0, 1.0, 0.0)
+
+
+def test_sigma_balamurugan_matches_oracle():
+    from oracle import steps
+
+    for L2, lb in [(5431.3, 1357.9), (7.0, 2.5), (1.0, 1.0)]:
+        assert abs(im.sigma_balamurugan(L2, lb) - steps.sigma_balamurugan(L2, lb)) <= 1e-15 * steps.sigma_balamurugan(L2, lb)
+    out = ctypes.c_double()
+    assert _abi.lib().imask_sigma_balamurugan(-1.0, 1.0, ctypes.byref(out)) == _abi.EINVAL
+

@@ -47,7 +47,7 @@ Layout make_layout(const imask_geometry& g)
     L.vbuf = off;
     off = align64(off + (size_t)g.n * g.n);
     L.part = off;
-    off = align64(off + (size_t)16 * g.n * g.n);
+    off = align64(off + (size_t)kPartImages * g.n * g.n);
     L.ptmp = off;
     off = align64(off + (size_t)g.n * g.n);
     const size_t m = (size_t)g.n_angles * g.n_det;

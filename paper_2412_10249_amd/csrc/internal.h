@@ -27,6 +27,11 @@ struct RayConst {
 static_assert(sizeof(RayConst) == 64, "RayConst is 64 bytes");
 constexpr int kConstStride = 16;  // floats per RayConst
 // Zero columns around every padded image row: kPadL before, kPadL after.
+#ifndef IMK_PART_IMAGES
+#define IMK_PART_IMAGES 16
+#endif
+// Full-resolution partial images the transpose may write (2 G N_l^2 <= this * N^2).
+constexpr int kPartImages = IMK_PART_IMAGES;
 constexpr int kPadL = 4;
 constexpr int kPad = 2 * kPadL;
 
@@ -38,7 +43,7 @@ struct Layout {
     size_t zpT[IMASK_MAX_LOG2F + 1] = {};  // padded level-l image, transposed
     size_t craw[IMASK_MAX_LOG2F + 1] = {}; // raw level-l backprojection N_l^2
     size_t vbuf = 0;                       // N^2 prox input
-    size_t part = 0;                       // 16 N^2 per-angle-group partial backprojections
+    size_t part = 0;                       // kPartImages N^2 per-angle-group partial backprojections
     size_t ptmp = 0;                       // N^2 coarse result before prolongation
     size_t fpart[IMASK_MAX_LOG2F + 1] = {};// per-band partial projections, fwd_bands(l) * m
     int fbands[IMASK_MAX_LOG2F + 1] = {};  // row bands of the level-l forward

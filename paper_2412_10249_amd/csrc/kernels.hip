@@ -1126,15 +1126,18 @@ hipError_t launch_fwd(const FwdArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
-// Ownership scatter with about 1024 workgroups: G angle groups per pass,
-// 2 G N_l^2 <= 16 N^2 partial images.
+#ifndef IMK_BP_TARGET_WG
+#define IMK_BP_TARGET_WG 1024
+#endif
+// Ownership scatter with about IMK_BP_TARGET_WG workgroups: G angle groups
+// per pass, 2 G N_l^2 <= kPartImages N^2 partial images.
 template <int R, int W>
 static hipError_t launch_scatter(BpOwnArgs& a, int nl, int lvl, hipStream_t s)
 {
     using Sh = BpShape<R, W>;
     const int nb = (nl + Sh::rows - 1) / Sh::rows;
-    const int gmax = std::max(1, std::min(std::max(a.split.nrow, a.split.ncol), 8 << (2 * lvl)));
-    a.G = std::max(1, std::min(gmax, (1024 + 2 * nb - 1) / (2 * nb)));
+    const int gmax = std::max(1, std::min(std::max(a.split.nrow, a.split.ncol), (kPartImages / 2) << (2 * lvl)));
+    a.G = std::max(1, std::min(gmax, (IMK_BP_TARGET_WG + 2 * nb - 1) / (2 * nb)));
     a.nq = 2 * a.G;
     const int lds = (int)(sizeof(float) * ((size_t)Sh::rows * (nl + 2 * Sh::pad) + 3) + sizeof(BpAngle) * kBpAngTab);
     const hipError_t e = allow_lds((const void*)k_bp_own<R, W>, lds);

@@ -82,6 +82,13 @@ def lib():
                                               ctypes.c_uint64, _D, ctypes.c_int,
                                               _D, _D, _D, _D, _D, _D, _I32, _D]
         L.orc_imask_seq_run.restype = ctypes.c_int
+        L.orc_imask_compact_run.argtypes = geo + [ctypes.c_int, _I32, _D, ctypes.c_int,
+                                                  ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                                  ctypes.c_double, ctypes.c_int,
+                                                  ctypes.c_double, ctypes.c_uint64, ctypes.c_uint32,
+                                                  ctypes.c_uint64, _D, ctypes.c_int,
+                                                  _D, _D, _D, _D, _D, _D, _I32, _D]
+        L.orc_imask_compact_run.restype = ctypes.c_int
     return _lib
 
 
@@ -321,6 +328,51 @@ def imask_seq_run(g: Geometry, lv: Levels, reg: Reg, sigma: float, theta: float,
                                  sigma, theta, seed, stream, st.k, _dp(b), n_iter,
                                  _dp(st.x), _dp(st.xbar), _dp(st.y), _dp(st.phi), _dp(st.psi), _dp(st.tvd),
                                  dr.ctypes.data_as(_I32), _dp(ep))
+    if rc != 0:
+        raise ValueError("oracle rejected the level set")
+    st.k += n_iter
+    st.epochs = float(ep[0])
+    st.draws.extend(int(v) for v in dr[:n_iter])
+    return st
+
+
+@dataclass
+class CompactState:
+    """State of Alg. 1 with Remark 1's compact dual tables: z (r, N, N) holds
+    the iterate at each sketch's last refresh, psibar the table average."""
+    x: np.ndarray
+    y: np.ndarray
+    phi: np.ndarray
+    z: np.ndarray
+    psibar: np.ndarray
+    tvd: np.ndarray
+    k: int = 0
+    epochs: float = 0.0
+    draws: list = field(default_factory=list)
+
+    @staticmethod
+    def zeros(g: Geometry, lv: Levels) -> "CompactState":
+        return CompactState(np.zeros((g.n, g.n)), np.zeros((g.n_angles, g.n_det)), np.zeros((lv.r, g.n, g.n)),
+                            np.zeros((lv.r, g.n, g.n)), np.zeros((g.n_angles, g.n_det)), np.zeros((2, g.n, g.n)))
+
+    def copy(self) -> "CompactState":
+        return CompactState(self.x.copy(), self.y.copy(), self.phi.copy(), self.z.copy(), self.psibar.copy(),
+                            self.tvd.copy(), self.k, self.epochs, list(self.draws))
+
+
+def imask_compact_run(g: Geometry, lv: Levels, reg: Reg, sigma: float, seed: int, stream: int,
+                      b, n_iter: int, state: CompactState | None = None) -> CompactState:
+    """Alg. 1 with Remark 1's compact dual tables for n_iter iterations."""
+    st = CompactState.zeros(g, lv) if state is None else state.copy()
+    b = _f64(b)
+    lf, pp = lv.carrays()
+    dr = np.empty(max(n_iter, 1), dtype=np.int32)
+    ep = np.array([st.epochs])
+    rc = lib().orc_imask_compact_run(*g.args(), lv.r, lf.ctypes.data_as(_I32), _dp(pp), lv.mode,
+                                     reg.kind, reg.lam, reg.tv_weight, reg.tv_eps, reg.tv_inner,
+                                     sigma, seed, stream, st.k, _dp(b), n_iter,
+                                     _dp(st.x), _dp(st.y), _dp(st.phi), _dp(st.z), _dp(st.psibar), _dp(st.tvd),
+                                     dr.ctypes.data_as(_I32), _dp(ep))
     if rc != 0:
         raise ValueError("oracle rejected the level set")
     st.k += n_iter

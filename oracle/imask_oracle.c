@@ -20,7 +20,9 @@
  *     evaluated by FISTA, and the paper's TV + nonnegativity prox by the
  *     fast gradient projection on the dual (Sec. 4.2 and 4.5);
  *   - the ImaSk-Seq variant of Sec. 5 (dual step first, primal step with the
- *     new dual iterate, extrapolated primal point).
+ *     new dual iterate, extrapolated primal point);
+ *   - Alg. 1 with the compact dual tables of Remark 1 (iterates instead of
+ *     their projections, plus a running table average).
  *
  * Conventions: domain [-1,1]^2; level l has N_l = N >> l pixels per side and
  * pixel size h_l = 2/N_l; pixel (i,j) has centre (x_j, y_i) with
@@ -607,3 +609,69 @@ int orc_imask_seq_run(int n, int na, int nd, double ds, double s0,
     free(idx);
     return 0;
 }
+
+/* Alg. 1 with the compact dual tables of Remark 1 (appendix, after the
+ * saddle-point SAGA algorithm): instead of psi_i = K_i x^{k_i} the state
+ * keeps the iterate itself, z_i = x^{k_i} (r * n^2), and the running average
+ * psibar = sum_i p_i psi_i (m).  With linearity one forward projection per
+ * step still suffices: d = K_i (x^k - z_i) = psi_new - psi_i, so
+ * zeta = d + psibar, psibar <- psibar + p_i d and z_i <- x^k.  Everything
+ * else is orc_imask_run. */
+int orc_imask_compact_run(int n, int na, int nd, double ds, double s0,
+                          int r, const int* log2f, const double* p, int mode,
+                          int reg_kind, double lam, double tv_w, double tv_eps, int tv_inner,
+                          double sigma, uint64_t seed, uint32_t stream, uint64_t k0,
+                          const double* bdata, int n_iter,
+                          double* x, double* y, double* phi, double* zsnap, double* psibar, double* tvd,
+                          int32_t* draws_out, double* epochs)
+{
+    if (r < 1 || r > ORC_MAX_LEVELS || log2f[0] != 0) return -1;
+    const long d = (long)n * n, m = (long)na * nd;
+    const double tau = sigma / lam;
+    double* gx = (double*)malloc(sizeof(double) * d);
+    double* dd = (double*)malloc(sizeof(double) * m);
+    double* diff = (double*)malloc(sizeof(double) * d);
+    double* xi = (double*)malloc(sizeof(double) * d);
+    double* xn = (double*)malloc(sizeof(double) * d);
+    double* v = (double*)malloc(sizeof(double) * d);
+    int32_t* idx = (int32_t*)malloc(sizeof(int32_t) * (n_iter > 0 ? n_iter : 1));
+    orc_draws(seed, stream, k0, n_iter, r, p, idx);
+    double unbiased_full = 1.0;
+    for (int k = 1; k < r; ++k) unbiased_full += ldexp(1.0, -log2f[k]);
+    for (int it = 0; it < n_iter; ++it) {
+        const int k = idx[it];
+        /* both refreshed gradients from the old iterates x^k, y^k */
+        orc_sketch_adj(n, na, nd, ds, s0, r, log2f, p, mode, k, y, gx);
+        for (long q = 0; q < d; ++q) diff[q] = x[q] - zsnap[(long)k * d + q];
+        orc_sketch_fwd(n, na, nd, ds, s0, r, log2f, p, mode, k, diff, dd);
+        for (long q = 0; q < d; ++q) {
+            double avg = 0.0;
+            for (int j = 0; j < r; ++j) avg += p[j] * phi[(long)j * d + q];
+            xi[q] = gx[q] - phi[(long)k * d + q] + avg;
+        }
+        for (long q = 0; q < d; ++q) v[q] = x[q] - tau * xi[q];
+        orc_prox(n, reg_kind, tau, lam, tv_w, tv_eps, tv_inner, v, x, tvd, xn);
+        for (long e = 0; e < m; ++e) {
+            const double zeta = dd[e] + psibar[e];
+            y[e] = (y[e] + sigma * zeta - sigma * bdata[e]) / (1.0 + sigma);
+            psibar[e] += p[k] * dd[e];
+        }
+        memcpy(zsnap + (long)k * d, x, sizeof(double) * d);
+        memcpy(x, xn, sizeof(double) * d);
+        memcpy(phi + (long)k * d, gx, sizeof(double) * d);
+        if (draws_out) draws_out[it] = k;
+        if (epochs) {
+            if (k == 0 && mode == ORC_MODE_UNBIASED) *epochs += unbiased_full;
+            else *epochs += ldexp(1.0, -log2f[k]);
+        }
+    }
+    free(gx);
+    free(dd);
+    free(diff);
+    free(xi);
+    free(xn);
+    free(v);
+    free(idx);
+    return 0;
+}
+

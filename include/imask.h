@@ -140,6 +140,16 @@ typedef struct {
  *   tvd[2] two buffers of 2*N*N floats (IMASK_REG_TV only, ping-pong with
  *          cur like x): the TV dual pair, row differences then column
  *          differences; start tvd[cur] at zero; may be NULL otherwise
+ *   ztab   NULL for the tables above.  Non-NULL selects the compact dual
+ *          tables of Remark 1 (the iterate is kept instead of its
+ *          projection): psi then holds only the running average
+ *          sum_k p_k K_k x^{(k)} (n_angles*n_det floats) and ztab the
+ *          restricted iterate at each sketch's last refresh (sketch 0 the
+ *          N*N image, sketch k > 0 its N_{l_k}^2 block mean; the phi layout,
+ *          imask_phi_floats() floats); start both at zero.  One projection of
+ *          the difference per step gives psi_new - psi_k, so the cost is
+ *          unchanged and the dual tables shrink from r*m to m + sum d_l
+ *          floats.  Parallel schedule only (IMASK_ENOTSUP otherwise)
  *   k      iteration counter (index of the next draw)
  *   epochs equivalent full-resolution operator applications so far
  *   cur    0 or 1 */
@@ -154,6 +164,7 @@ typedef struct {
     int32_t cur;
     float* xbar;
     float* tvd[2];
+    float* ztab;
 } imask_state;
 
 /* Bytes of device workspace needed for geometry g (host function). */

@@ -53,7 +53,7 @@ class State(ctypes.Structure):
     _fields_ = [("x", ctypes.c_void_p * 2), ("y", ctypes.c_void_p * 2), ("phi", ctypes.c_void_p),
                 ("psi", ctypes.c_void_p), ("work", ctypes.c_void_p), ("k", ctypes.c_uint64),
                 ("epochs", ctypes.c_double), ("cur", ctypes.c_int32), ("xbar", ctypes.c_void_p),
-                ("tvd", ctypes.c_void_p * 2)]
+                ("tvd", ctypes.c_void_p * 2), ("ztab", ctypes.c_void_p)]
 
 
 class ImaskError(RuntimeError):

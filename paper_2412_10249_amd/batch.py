@@ -19,17 +19,22 @@ from .imask import Problem, lib
 
 def footprint_bytes(p: Problem) -> int:
     """Device bytes one problem holds (state tables + workspace)."""
-    return sum(t.numel() * t.element_size() for t in (*p.x, *p.y, p.phi, p.psi, p.work, p.b))
+    ts = [*p.x, *p.y, p.phi, p.psi, p.work, p.b, *p.tvd]
+    ts += [t for t in (p.xbar, p.ztab) if t is not None]
+    return sum(t.numel() * t.element_size() for t in ts)
 
 
-def state_bytes(geom, levels) -> int:
-    """Bytes a problem of this geometry and level set will need, before allocating it."""
+def state_bytes(geom, levels, compact_tables: bool = False) -> int:
+    """Bytes a problem of this geometry and level set will need, before
+    allocating it (parallel schedule, Tikhonov or smoothed TV).  Compact
+    dual tables (Remark 1) keep m + sum d_l floats instead of r m."""
     g = geom.c()
     work = lib().imask_workspace_bytes(ctypes.byref(g))
     nphi = lib().imask_phi_floats(ctypes.byref(g), ctypes.byref(levels.c()))
     m = geom.n_angles * geom.n_det
     d = geom.n * geom.n
-    return int(work + 4 * (2 * d + 2 * m + nphi + levels.r * m + m))
+    dual_tables = m + nphi if compact_tables else levels.r * m
+    return int(work + 4 * (2 * d + 2 * m + nphi + dual_tables + m))
 
 
 class BatchRunner:

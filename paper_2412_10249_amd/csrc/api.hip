@@ -263,6 +263,13 @@ static int one_step(const imask_geometry& g, const Layout& L, const imask_levels
     FwdArgs fa{};
     forward_plan(L, lv, k, x_fwd, W, pa, fa);
     fwd_common(L, W, fa);
+    if (st.ztab) {  // compact dual tables (Remark 1): project x - z_k, refresh z_k
+        long long zoff[IMASK_MAX_LEVELS];
+        phi_offsets(g, lv, zoff);
+        pa.snap = st.ztab + zoff[k];
+        pa.snap_lvl = lv.log2f[k];
+        fa.compact = 1;
+    }
     fa.mode = FWD_DUAL;
     fa.y_old = st.y[cur];
     fa.y_new = st.y[nxt];
@@ -793,6 +800,10 @@ static int check_problem(const imask_geometry* g, const imask_levels* lv, const 
     if (!levels_ok(lv, lmax) || !reg_ok(reg) || !prm || !b || !state_ok(s)) return IMASK_EINVAL;
     if (!(prm->sigma > 0.0) || !std::isfinite(prm->sigma)) return IMASK_EINVAL;
     if (reg->kind == IMASK_REG_TV && (!s->tvd[0] || !s->tvd[1] || s->tvd[0] == s->tvd[1])) return IMASK_EINVAL;
+    if (s->ztab) {
+        if (s->ztab == s->phi || s->ztab == s->psi || s->ztab == s->x[0] || s->ztab == s->x[1]) return IMASK_EINVAL;
+        if (prm->schedule != IMASK_SCHEDULE_PARALLEL) return IMASK_ENOTSUP;
+    }
     if (prm->schedule == IMASK_SCHEDULE_SEQUENTIAL) {
         if (!(prm->theta >= 0.0 && prm->theta <= 1.0) || !s->xbar) return IMASK_EINVAL;
         if (s->xbar == s->x[0] || s->xbar == s->x[1]) return IMASK_EINVAL;

@@ -96,8 +96,8 @@ struct FwdArgs {
     const float* y_old;
     const float* bdat;
     float* y_new;
-    float* psi;
-    int r, kidx;
+    float* psi;   // r tables, or the running average when compact
+    int r, kidx, compact;
     float p[IMASK_MAX_LEVELS];
     float sigma, inv1ps;
 };
@@ -149,6 +149,10 @@ struct PrepOut {
 
 struct PrepArgs {
     const float* x;
+    // compact dual tables: the restricted input is taken relative to this
+    // snapshot (level snap_lvl, N_l^2), which is then replaced by it
+    float* snap;
+    int snap_lvl;
     int n, T, pyr_levels;
     int nout;
     PrepOut out[IMASK_MAX_LEVELS + 1];

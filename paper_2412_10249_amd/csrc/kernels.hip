@@ -121,7 +121,18 @@ __global__ void __launch_bounds__(256) k_prep(PrepArgs a)
     extern __shared__ float pyr[];
     const int tiles = a.n / a.T;
     const int ty = blockIdx.x / tiles, tx = blockIdx.x - ty * tiles;
-    load_tile(pyr, a.x, a.n, a.T, ty, tx);
+    if (a.snap && a.snap_lvl == 0) {
+        // compact tables, full-resolution sketch: restrict x - z_0, then z_0 <- x
+        for (int q = threadIdx.x; q < a.T * a.T; q += blockDim.x) {
+            const int i = q / a.T, j = q - i * a.T;
+            const size_t g = (size_t)(ty * a.T + i) * a.n + tx * a.T + j;
+            const float xv = a.x[g];
+            pyr[q] = xv - a.snap[g];
+            a.snap[g] = xv;
+        }
+    } else {
+        load_tile(pyr, a.x, a.n, a.T, ty, tx);
+    }
     build_pyramid(pyr, a.T, a.pyr_levels);
     for (int o = 0; o < a.nout; ++o) {
         const PrepOut& po = a.out[o];
@@ -142,6 +153,13 @@ __global__ void __launch_bounds__(256) k_prep(PrepArgs a)
                     acc -= a.comp_p[c] * pyr[pyr_offset(a.T, lc) + (i >> lc) * tc + (j >> lc)];
                 }
                 v = acc * a.inv_p0;
+            }
+            if (a.snap && a.snap_lvl == l && l > 0) {
+                // compact tables, coarse sketch: T_l x - z_k, then z_k <- T_l x
+                float* zc = a.snap + (size_t)(oy + i) * nl + ox + j;
+                const float mean = v;
+                v = mean - *zc;
+                *zc = mean;
             }
             po.dst[(size_t)(oy + i) * P + ox + j + sh] = v;
             if (po.dstT) po.dstT[(size_t)(ox + j) * P + oy + i + sh] = v;
@@ -358,6 +376,12 @@ __global__ void __launch_bounds__(256) k_fwd_reduce(FwdArgs a)
             a.out[e] = total;
         } else if (a.mode == FWD_ACCUM) {
             a.out[e] += total;
+        } else if (a.compact) {
+            // total = K_k (x - z_k) = psi_new - psi_k; psi holds the average
+            const float avg = a.psi[e];
+            const float zeta = total + avg;
+            a.y_new[e] = (a.y_old[e] + a.sigma * zeta - a.sigma * a.bdat[e]) * a.inv1ps;
+            a.psi[e] = fmaf(a.p[a.kidx], total, avg);
         } else {
             float avg = 0.0f;
             for (int j = 0; j < a.r; ++j) avg = fmaf(a.p[j], a.psi[(size_t)j * m + e], avg);

@@ -226,6 +226,7 @@ class Problem:
     params: Params
     b: torch.Tensor
     device: str = "cuda"
+    compact_tables: bool = False  # Remark 1: psi holds the average, ztab the snapshots
     x: list = field(default_factory=list)
     y: list = field(default_factory=list)
     phi: torch.Tensor | None = None
@@ -233,6 +234,7 @@ class Problem:
     work: torch.Tensor | None = None
     xbar: torch.Tensor | None = None  # extrapolated point (sequential schedule)
     tvd: list = field(default_factory=list)  # TV dual pair, two ping-pong buffers (REG_TV)
+    ztab: torch.Tensor | None = None  # compact dual tables: restricted iterate snapshots
     k: int = 0
     epochs: float = 0.0
     cur: int = 0
@@ -247,7 +249,11 @@ class Problem:
         self.x = [torch.zeros(g.image_shape, device=dev) for _ in range(2)]
         self.y = [torch.zeros(g.sino_shape, device=dev) for _ in range(2)]
         self.phi = torch.zeros(nphi, device=dev)
-        self.psi = torch.zeros((self.levels.r,) + g.sino_shape, device=dev)
+        if self.compact_tables:
+            self.psi = torch.zeros(g.sino_shape, device=dev)
+            self.ztab = torch.zeros(nphi, device=dev)
+        else:
+            self.psi = torch.zeros((self.levels.r,) + g.sino_shape, device=dev)
         self.work = workspace(g, dev)
         if self.params.schedule == _abi.SCHEDULE_SEQUENTIAL:
             self.xbar = torch.zeros(g.image_shape, device=dev)
@@ -264,6 +270,7 @@ class Problem:
         s.xbar = self.xbar.data_ptr() if self.xbar is not None else None
         if self.tvd:
             s.tvd[0], s.tvd[1] = self.tvd[0].data_ptr(), self.tvd[1].data_ptr()
+        s.ztab = self.ztab.data_ptr() if self.ztab is not None else None
         return s
 
     def _absorb(self, s: _abi.State) -> None:
@@ -309,6 +316,8 @@ class Problem:
             d["xbar"] = self.xbar.clone()
         if self.tvd:
             d["tvd"] = self.tvd[self.cur].clone()
+        if self.ztab is not None:
+            d["ztab"] = self.ztab.clone()
         return d
 
     def load_state_dict(self, d: dict) -> None:
@@ -321,6 +330,8 @@ class Problem:
             self.xbar.copy_(d["xbar"])
         if self.tvd:
             self.tvd[0].copy_(d["tvd"])
+        if self.ztab is not None:
+            self.ztab.copy_(d["ztab"])
         self.k, self.epochs = int(d["k"]), float(d["epochs"])
 
 

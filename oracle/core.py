@@ -89,6 +89,13 @@ def lib():
                                                   ctypes.c_uint64, _D, ctypes.c_int,
                                                   _D, _D, _D, _D, _D, _D, _I32, _D]
         L.orc_imask_compact_run.restype = ctypes.c_int
+        L.orc_imask_indep_run.argtypes = geo + [ctypes.c_int, _I32, _D, ctypes.c_int,
+                                                ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                                ctypes.c_double, ctypes.c_int,
+                                                ctypes.c_double, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+                                                ctypes.c_uint64, _D, ctypes.c_int,
+                                                _D, _D, _D, _D, _D, _I32, _I32, _D]
+        L.orc_imask_indep_run.restype = ctypes.c_int
     return _lib
 
 
@@ -272,6 +279,7 @@ class State:
     draws: list = field(default_factory=list)
     xbar: np.ndarray | None = None  # extrapolated point (ImaSk-Seq only)
     tvd: np.ndarray | None = None   # TV dual pair (2, N, N) of REG_TV's prox
+    dual_draws: list = field(default_factory=list)  # dual indices (independent draws only)
 
     @staticmethod
     def zeros(g: Geometry, lv: Levels) -> "State":
@@ -283,7 +291,7 @@ class State:
         return State(self.x.copy(), self.y.copy(), self.phi.copy(), self.psi.copy(),
                      self.k, self.epochs, list(self.draws),
                      None if self.xbar is None else self.xbar.copy(),
-                     None if self.tvd is None else self.tvd.copy())
+                     None if self.tvd is None else self.tvd.copy(), list(self.dual_draws))
 
     def ensure(self, g: Geometry) -> None:
         if self.xbar is None:
@@ -333,6 +341,31 @@ def imask_seq_run(g: Geometry, lv: Levels, reg: Reg, sigma: float, theta: float,
     st.k += n_iter
     st.epochs = float(ep[0])
     st.draws.extend(int(v) for v in dr[:n_iter])
+    return st
+
+
+def imask_indep_run(g: Geometry, lv: Levels, reg: Reg, sigma: float, seed: int, stream: int, dual_stream: int,
+                    b, n_iter: int, state: State | None = None) -> State:
+    """Alg. 1 with independent primal (stream) and dual (dual_stream) draws;
+    state.draws gets the primal indices, state.dual_draws the dual ones."""
+    st = State.zeros(g, lv) if state is None else state.copy()
+    st.ensure(g)
+    b = _f64(b)
+    lf, pp = lv.carrays()
+    dr = np.empty(max(n_iter, 1), dtype=np.int32)
+    dd = np.empty(max(n_iter, 1), dtype=np.int32)
+    ep = np.array([st.epochs])
+    rc = lib().orc_imask_indep_run(*g.args(), lv.r, lf.ctypes.data_as(_I32), _dp(pp), lv.mode,
+                                   reg.kind, reg.lam, reg.tv_weight, reg.tv_eps, reg.tv_inner,
+                                   sigma, seed, stream, dual_stream, st.k, _dp(b), n_iter,
+                                   _dp(st.x), _dp(st.y), _dp(st.phi), _dp(st.psi), _dp(st.tvd),
+                                   dr.ctypes.data_as(_I32), dd.ctypes.data_as(_I32), _dp(ep))
+    if rc != 0:
+        raise ValueError("oracle rejected the level set")
+    st.k += n_iter
+    st.epochs = float(ep[0])
+    st.draws.extend(int(v) for v in dr[:n_iter])
+    st.dual_draws.extend(int(v) for v in dd[:n_iter])
     return st
 
 

@@ -22,7 +22,8 @@
  *   - the ImaSk-Seq variant of Sec. 5 (dual step first, primal step with the
  *     new dual iterate, extrapolated primal point);
  *   - Alg. 1 with the compact dual tables of Remark 1 (iterates instead of
- *     their projections, plus a running table average).
+ *     their projections, plus a running table average);
+ *   - Alg. 1 with independent primal and dual sketch draws (Sec. 6 outlook).
  *
  * Conventions: domain [-1,1]^2; level l has N_l = N >> l pixels per side and
  * pixel size h_l = 2/N_l; pixel (i,j) has centre (x_j, y_i) with
@@ -672,6 +673,69 @@ int orc_imask_compact_run(int n, int na, int nd, double ds, double s0,
     free(xn);
     free(v);
     free(idx);
+    return 0;
+}
+
+/* Alg. 1 with independent primal and dual sketch draws (the first item of
+ * the paper's outlook, Sec. 6): the primal index i_k comes from stream
+ * `stream`, the dual index j_k from stream `dual_stream` (same seed and p).
+ * The dual step refreshes psi_{j_k} from K_{j_k} x^k, the primal step
+ * phi_{i_k} from K_{i_k}^T y^k; both from the old iterates, old-table
+ * averages.  An iteration costs half of each side's level cost:
+ * epochs += (c(i_k) + c(j_k)) / 2, so equal streams reproduce orc_imask_run.
+ * draws_out gets i_k, dual_draws_out j_k (either may be NULL). */
+int orc_imask_indep_run(int n, int na, int nd, double ds, double s0,
+                        int r, const int* log2f, const double* p, int mode,
+                        int reg_kind, double lam, double tv_w, double tv_eps, int tv_inner,
+                        double sigma, uint64_t seed, uint32_t stream, uint32_t dual_stream, uint64_t k0,
+                        const double* bdata, int n_iter,
+                        double* x, double* y, double* phi, double* psi, double* tvd,
+                        int32_t* draws_out, int32_t* dual_draws_out, double* epochs)
+{
+    if (r < 1 || r > ORC_MAX_LEVELS || log2f[0] != 0) return -1;
+    const long d = (long)n * n, m = (long)na * nd;
+    const double tau = sigma / lam;
+    double* gx = (double*)malloc(sizeof(double) * d);
+    double* gy = (double*)malloc(sizeof(double) * m);
+    double* xn = (double*)malloc(sizeof(double) * d);
+    double* v = (double*)malloc(sizeof(double) * d);
+    int32_t* ip = (int32_t*)malloc(sizeof(int32_t) * (n_iter > 0 ? n_iter : 1));
+    int32_t* jd = (int32_t*)malloc(sizeof(int32_t) * (n_iter > 0 ? n_iter : 1));
+    orc_draws(seed, stream, k0, n_iter, r, p, ip);
+    orc_draws(seed, dual_stream, k0, n_iter, r, p, jd);
+    double cost[ORC_MAX_LEVELS];
+    for (int k = 0; k < r; ++k) cost[k] = ldexp(1.0, -log2f[k]);
+    if (mode == ORC_MODE_UNBIASED)
+        for (int k = 1; k < r; ++k) cost[0] += ldexp(1.0, -log2f[k]);
+    for (int it = 0; it < n_iter; ++it) {
+        const int i = ip[it], j = jd[it];
+        orc_sketch_adj(n, na, nd, ds, s0, r, log2f, p, mode, i, y, gx);
+        orc_sketch_fwd(n, na, nd, ds, s0, r, log2f, p, mode, j, x, gy);
+        for (long q = 0; q < d; ++q) {
+            double avg = 0.0;
+            for (int c = 0; c < r; ++c) avg += p[c] * phi[(long)c * d + q];
+            v[q] = x[q] - tau * (gx[q] - phi[(long)i * d + q] + avg);
+        }
+        orc_prox(n, reg_kind, tau, lam, tv_w, tv_eps, tv_inner, v, x, tvd, xn);
+        for (long e = 0; e < m; ++e) {
+            double avg = 0.0;
+            for (int c = 0; c < r; ++c) avg += p[c] * psi[(long)c * m + e];
+            const double zeta = gy[e] - psi[(long)j * m + e] + avg;
+            y[e] = (y[e] + sigma * zeta - sigma * bdata[e]) / (1.0 + sigma);
+        }
+        memcpy(x, xn, sizeof(double) * d);
+        memcpy(phi + (long)i * d, gx, sizeof(double) * d);
+        memcpy(psi + (long)j * m, gy, sizeof(double) * m);
+        if (draws_out) draws_out[it] = i;
+        if (dual_draws_out) dual_draws_out[it] = j;
+        if (epochs) *epochs += 0.5 * (cost[i] + cost[j]);
+    }
+    free(gx);
+    free(gy);
+    free(xn);
+    free(v);
+    free(ip);
+    free(jd);
     return 0;
 }
 

@@ -52,6 +52,7 @@ enum {
 enum { IMASK_FULL_PAPER = 0, IMASK_FULL_UNBIASED = 1 };
 enum { IMASK_REG_TIKHONOV = 0, IMASK_REG_SMOOTH_TV = 1, IMASK_REG_TV = 2 };
 enum { IMASK_SCHEDULE_PARALLEL = 0, IMASK_SCHEDULE_SEQUENTIAL = 1 };
+enum { IMASK_DRAW_COMMON = 0, IMASK_DRAW_INDEPENDENT = 1 };
 enum {
     IMASK_RESTRICT = 0,     /* out (N_l^2)  = T_l in, 2^l x 2^l block mean (Sec. 4.1) */
     IMASK_PROLONG = 1,      /* out (N^2)    = T_l^* in, replication (Sec. 4.1) */
@@ -116,13 +117,23 @@ typedef struct {
  *   IMASK_SCHEDULE_SEQUENTIAL the ImaSk-Seq variant of Sec. 5: the dual step
  *                             uses K_i xbar^k, the primal step K_i^T y^{k+1},
  *                             and xbar^{k+1} = x^{k+1} + theta (x^{k+1} - x^k);
- *                             0 <= theta <= 1, and imask_state.xbar is needed */
+ *                             0 <= theta <= 1, and imask_state.xbar is needed
+ * draw_mode selects the sketch draws:
+ *   IMASK_DRAW_COMMON      Alg. 1: one index per iteration for both steps
+ *   IMASK_DRAW_INDEPENDENT the outlook of Sec. 6: the primal step (K_i^T,
+ *                          phi) uses stream_id, the dual step (K_j, psi) an
+ *                          independent index from stream dual_stream_id;
+ *                          an iteration then costs (c(i) + c(j)) / 2 epochs.
+ *                          Parallel schedule with full tables only
+ *                          (IMASK_ENOTSUP otherwise) */
 typedef struct {
     double sigma;
     uint64_t seed;
     uint32_t stream_id;
     int32_t schedule;
     double theta;
+    int32_t draw_mode;
+    uint32_t dual_stream_id;
 } imask_params;
 
 /* ImaSk state (Alg. 1): iterates, gradient tables and counters.

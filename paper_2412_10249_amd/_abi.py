@@ -21,6 +21,7 @@ REG_TIKHONOV, REG_SMOOTH_TV, REG_TV = 0, 1, 2
 RESTRICT, PROLONG, RESTRICT_ADJ, PROJECT, COMPENSATE = 0, 1, 2, 3, 4
 BUDGET_ITERS, BUDGET_EPOCHS = 0, 1
 SCHEDULE_PARALLEL, SCHEDULE_SEQUENTIAL = 0, 1
+DRAW_COMMON, DRAW_INDEPENDENT = 0, 1
 
 EXPORTS = ["imask_workspace_bytes", "imask_phi_floats", "imask_prepare", "imask_project",
            "imask_backproject", "imask_resample", "imask_sketch_apply", "imask_draws",
@@ -46,7 +47,8 @@ class Reg(ctypes.Structure):
 
 class Params(ctypes.Structure):
     _fields_ = [("sigma", ctypes.c_double), ("seed", ctypes.c_uint64), ("stream_id", ctypes.c_uint32),
-                ("schedule", ctypes.c_int32), ("theta", ctypes.c_double)]
+                ("schedule", ctypes.c_int32), ("theta", ctypes.c_double), ("draw_mode", ctypes.c_int32),
+                ("dual_stream_id", ctypes.c_uint32)]
 
 
 class State(ctypes.Structure):

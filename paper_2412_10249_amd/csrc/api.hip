@@ -248,7 +248,13 @@ static int one_step(const imask_geometry& g, const Layout& L, const imask_levels
 {
     uint64_t thr[IMASK_MAX_LEVELS];
     draw_thresholds(lv, thr);
-    const int k = draw_one(prm, thr, st.k);
+    const int k = draw_one(prm, thr, st.k);  // primal sketch (K_k^T, phi)
+    int kd = k;                                // dual sketch (K_kd, psi)
+    if (prm.draw_mode == IMASK_DRAW_INDEPENDENT) {
+        imask_params dual = prm;
+        dual.stream_id = prm.dual_stream_id;
+        kd = draw_one(dual, thr, st.k);
+    }
     float* W = (float*)st.work;
     const int cur = st.cur, nxt = 1 - cur;
     const int lmax_set = lv.log2f[lv.r - 1];
@@ -261,13 +267,13 @@ static int one_step(const imask_geometry& g, const Layout& L, const imask_levels
     // a2-a4: restriction, forward projection, dual SAGA step and psi refresh
     PrepArgs pa;
     FwdArgs fa{};
-    forward_plan(L, lv, k, x_fwd, W, pa, fa);
+    forward_plan(L, lv, kd, x_fwd, W, pa, fa);
     fwd_common(L, W, fa);
     if (st.ztab) {  // compact dual tables (Remark 1): project x - z_k, refresh z_k
         long long zoff[IMASK_MAX_LEVELS];
         phi_offsets(g, lv, zoff);
-        pa.snap = st.ztab + zoff[k];
-        pa.snap_lvl = lv.log2f[k];
+        pa.snap = st.ztab + zoff[kd];
+        pa.snap_lvl = lv.log2f[kd];
         fa.compact = 1;
     }
     fa.mode = FWD_DUAL;
@@ -276,7 +282,7 @@ static int one_step(const imask_geometry& g, const Layout& L, const imask_levels
     fa.bdat = bdat;
     fa.psi = st.psi;
     fa.r = lv.r;
-    fa.kidx = k;
+    fa.kidx = kd;
     for (int j = 0; j < lv.r; ++j) fa.p[j] = (float)lv.p[j];
     fa.sigma = (float)prm.sigma;
     fa.inv1ps = (float)(1.0 / (1.0 + prm.sigma));
@@ -363,7 +369,7 @@ static int one_step(const imask_geometry& g, const Layout& L, const imask_levels
 
     st.cur = nxt;
     st.k += 1;
-    st.epochs += sketch_cost(lv, k);
+    st.epochs += kd == k ? sketch_cost(lv, k) : 0.5 * (sketch_cost(lv, k) + sketch_cost(lv, kd));
     return IMASK_OK;
 }
 
@@ -803,6 +809,11 @@ static int check_problem(const imask_geometry* g, const imask_levels* lv, const 
     if (s->ztab) {
         if (s->ztab == s->phi || s->ztab == s->psi || s->ztab == s->x[0] || s->ztab == s->x[1]) return IMASK_EINVAL;
         if (prm->schedule != IMASK_SCHEDULE_PARALLEL) return IMASK_ENOTSUP;
+    }
+    if (prm->draw_mode == IMASK_DRAW_INDEPENDENT) {
+        if (prm->schedule != IMASK_SCHEDULE_PARALLEL || s->ztab) return IMASK_ENOTSUP;
+    } else if (prm->draw_mode != IMASK_DRAW_COMMON) {
+        return IMASK_EINVAL;
     }
     if (prm->schedule == IMASK_SCHEDULE_SEQUENTIAL) {
         if (!(prm->theta >= 0.0 && prm->theta <= 1.0) || !s->xbar) return IMASK_EINVAL;

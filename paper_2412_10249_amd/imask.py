@@ -95,16 +95,21 @@ class Regularizer:
 
 @dataclass(frozen=True)
 class Params:
-    """Step size, draw stream, and the schedule: Alg. 1 (parallel) or the
-    ImaSk-Seq variant of Sec. 5 with extrapolation theta."""
+    """Step size, draw stream, the schedule (Alg. 1's parallel update or the
+    ImaSk-Seq variant of Sec. 5 with extrapolation theta) and the draw mode
+    (one index per iteration, or independent primal/dual indices with the
+    dual one from dual_stream_id)."""
     sigma: float
     seed: int = 42
     stream_id: int = 0
     schedule: int = _abi.SCHEDULE_PARALLEL
     theta: float = 1.0
+    draw_mode: int = _abi.DRAW_COMMON
+    dual_stream_id: int = 0
 
     def c(self) -> _abi.Params:
-        return _abi.Params(self.sigma, self.seed, self.stream_id, self.schedule, self.theta)
+        return _abi.Params(self.sigma, self.seed, self.stream_id, self.schedule, self.theta, self.draw_mode,
+                           self.dual_stream_id)
 
 
 def workspace(g: Geometry, device="cuda") -> torch.Tensor:

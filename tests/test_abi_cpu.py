@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
 def test_struct_sizes_match_c_layout():
     assert ctypes.sizeof(_abi.Geometry) == 32
     assert ctypes.sizeof(_abi.Levels) == 4 + 32 + 4 + 64 + 4 + 4
-    assert ctypes.sizeof(_abi.Params) == 8 + 8 + 4 + 4 + 8
+    assert ctypes.sizeof(_abi.Params) == 8 + 8 + 4 + 4 + 8 + 4 + 4
     assert ctypes.sizeof(_abi.State) == 8 * 7 + 8 + 8 + 8 + 8 + 16 + 8
 
 
@@ -159,3 +159,23 @@ def test_compact_tables_need_parallel_schedule():
     par = _abi.Params(-1.0, 1, 0, _abi.SCHEDULE_PARALLEL, 1.0)  # and an invalid sigma: never launches
     assert _abi.lib().imask_step(1, ctypes.byref(g), ctypes.byref(lv), ctypes.byref(reg), ctypes.byref(par), b,
                                  ctypes.byref(s), 1, None) == _abi.EINVAL
+
+
+def test_independent_draws_limits():
+    g = _abi.Geometry(64, 10, 10, 0.0, 0.0)
+    lv = im.Levels((0, 1), (0.5, 0.5)).c()
+    reg = _abi.Reg(_abi.REG_TIKHONOV, 0.01, 0.0, 1e-3, 10)
+    s = _abi.State()
+    s.x[0], s.x[1], s.y[0], s.y[1] = 16, 32, 48, 64
+    s.phi, s.psi, s.work, s.xbar = 80, 96, 112, 128
+    b = (ctypes.c_void_p * 1)(16)
+    for prm, want in [(_abi.Params(0.01, 1, 0, _abi.SCHEDULE_PARALLEL, 1.0, 7, 1), _abi.EINVAL),
+                      (_abi.Params(0.01, 1, 0, _abi.SCHEDULE_SEQUENTIAL, 1.0, _abi.DRAW_INDEPENDENT, 1),
+                       _abi.ENOTSUP)]:
+        assert _abi.lib().imask_step(1, ctypes.byref(g), ctypes.byref(lv), ctypes.byref(reg), ctypes.byref(prm), b,
+                                     ctypes.byref(s), 1, None) == want
+    s.ztab = 144
+    prm = _abi.Params(0.01, 1, 0, _abi.SCHEDULE_PARALLEL, 1.0, _abi.DRAW_INDEPENDENT, 1)
+    assert _abi.lib().imask_step(1, ctypes.byref(g), ctypes.byref(lv), ctypes.byref(reg), ctypes.byref(prm), b,
+                                 ctypes.byref(s), 1, None) == _abi.ENOTSUP
+

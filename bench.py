@@ -274,6 +274,7 @@ def race(args):
     same GPU, UNBIASED sketches (levels 512/256/128/64) so that every method
     shares the limit:
       imask_r4 / saga_r1  Alg. 1 with r = 4 / r = 1, sigma = m * sigma_thm3
+      imask_r4_indep      Alg. 1, r = 4, independent primal/dual draws (Sec. 6)
       seq_r4 / seq_r1     ImaSk-Seq (Sec. 5, theta = 1) with r = 4 / r = 1
                           (r = 1 is PDHG), sigma = m * sigma_pd, where
                           sigma_pd = (L^2)^{-1/2} is the single-level PDHG
@@ -301,7 +302,8 @@ def race(args):
     r4 = pk.Levels.uniform(LEVELS, pk.FULL_UNBIASED)
     r1 = pk.Levels((0,), (1.0,))
     methods = {"imask_r4": (r4, pk.SCHEDULE_PARALLEL), "saga_r1": (r1, pk.SCHEDULE_PARALLEL),
-               "seq_r4": (r4, pk.SCHEDULE_SEQUENTIAL), "seq_r1": (r1, pk.SCHEDULE_SEQUENTIAL)}
+               "seq_r4": (r4, pk.SCHEDULE_SEQUENTIAL), "seq_r1": (r1, pk.SCHEDULE_SEQUENTIAL),
+               "imask_r4_indep": (r4, pk.SCHEDULE_PARALLEL)}
     results = {}
     for name in args.methods:
         lv, sched = methods[name]
@@ -315,7 +317,8 @@ def race(args):
         check = args.seq_check_every if seq else args.check_every
         for mult in mults:
             sigma = base * mult
-            prob = pk.Problem(geom, lv, reg, pk.Params(sigma, SEED, STREAM, sched, 1.0), b32)
+            draw = pk.DRAW_INDEPENDENT if name.endswith("_indep") else pk.DRAW_COMMON
+            prob = pk.Problem(geom, lv, reg, pk.Params(sigma, SEED, STREAM, sched, 1.0, draw, STREAM + 1), b32)
             torch.cuda.synchronize()
             hist = []
             tstart = time.perf_counter()
@@ -688,7 +691,7 @@ def main():
     ap.add_argument("--race-seconds", type=float, default=60.0)
     ap.add_argument("--sigma-mults", type=float, nargs="+", default=[1.0, 2.0])
     ap.add_argument("--check-every", type=float, default=10.0, help="epochs between error checks in the race")
-    ap.add_argument("--methods", nargs="+", default=["seq_r4", "seq_r1", "imask_r4", "saga_r1"])
+    ap.add_argument("--methods", nargs="+", default=["seq_r4", "seq_r1", "imask_r4", "imask_r4_indep", "saga_r1"])
     ap.add_argument("--seq-sigma-mults", type=float, nargs="+", default=[0.125, 0.25, 0.35, 0.5, 0.7, 0.9])
     ap.add_argument("--seq-check-every", type=float, default=1.0)
     ap.add_argument("--batched", action="store_true", help="64 mixed slices in flight")

@@ -7,9 +7,19 @@ I0 = 1e5, smoothed TV (eps = 1e-3) + lambda = 1e-3, levels 512/256/128/64
 with p = 1/4 (the paper's literal construction, PAPER mode).  Epochs count
 equivalent full-resolution operator applications (cost 2^{-l} per step).
 
-Prints one JSON line.  --gpus above 1 is refused: this build runs on one GPU.
+Prints one JSON line.  --gpus above 1 is refused: the path runs on one GPU
+(how it would shard is a design note, not code).
+
+Other workloads, each printing its own JSON line:
+  --race                time to relative error 1e-3 against a common limit:
+                        ImaSk, SAGA, ImaSk-Seq, PDHG, independent draws
+  --study stepsize|tv   PSNR against the phantom over a fixed epoch budget
+  --batched             64 slices of mixed sizes in flight on several streams
+  --serve               Poisson arrivals into the continuous-batching server
+  --autograd            unrolled, checkpointed ImaSk forward + backward
 
 Profiling helpers (no GPU needed for --summarize):
+  --counters fwd:L|bp:L launch one projector kernel, for rocprofv3 --pmc
   --copy-calib          also run a 64 MiB plain copy (for counter calibration)
   --summarize DIR...    turn rocprofv3 CSV output into the markdown summaries
                         kept under profiles/
@@ -745,7 +755,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path does not shard "
-              f"across GPUs in this build", file=sys.stderr)
+              f"across GPUs", file=sys.stderr)
         sys.exit(2)
     run(args)
 

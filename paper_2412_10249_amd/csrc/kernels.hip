@@ -1153,6 +1153,16 @@ hipError_t launch_fwd(const FwdArgs& a, hipStream_t s)
 #ifndef IMK_BP_TARGET_WG
 #define IMK_BP_TARGET_WG 1024
 #endif
+constexpr size_t kLdsBytes = 160 * 1024;  // LDS per CU on gfx950
+
+// Dynamic LDS of k_bp_own<R, W> for rows of nl pixels.
+template <int R, int W>
+static size_t scatter_lds(int nl)
+{
+    using Sh = BpShape<R, W>;
+    return sizeof(float) * ((size_t)Sh::rows * (nl + 2 * Sh::pad) + 3) + sizeof(BpAngle) * kBpAngTab;
+}
+
 // Ownership scatter with about IMK_BP_TARGET_WG workgroups: G angle groups
 // per pass, 2 G N_l^2 <= kPartImages N^2 partial images.
 template <int R, int W>
@@ -1163,7 +1173,7 @@ static hipError_t launch_scatter(BpOwnArgs& a, int nl, int lvl, hipStream_t s)
     const int gmax = std::max(1, std::min(std::max(a.split.nrow, a.split.ncol), (kPartImages / 2) << (2 * lvl)));
     a.G = std::max(1, std::min(gmax, (IMK_BP_TARGET_WG + 2 * nb - 1) / (2 * nb)));
     a.nq = 2 * a.G;
-    const int lds = (int)(sizeof(float) * ((size_t)Sh::rows * (nl + 2 * Sh::pad) + 3) + sizeof(BpAngle) * kBpAngTab);
+    const int lds = (int)scatter_lds<R, W>(nl);
     const hipError_t e = allow_lds((const void*)k_bp_own<R, W>, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_bp_own<R, W>), dim3(nb, 2 * a.G), dim3(64 * W), lds, s, a);
@@ -1188,8 +1198,12 @@ hipError_t launch_bp_main(const BpArgs& ba, hipStream_t s, BpOwnArgs& a)
     const int nl = ba.n >> ba.lvl;
     // tile shapes measured best on the 512^2 / 720 x 768 workload: two rows
     // per wavefront and 8 wavefronts at the two finest levels, four rows and
-    // 4 wavefronts on the coarse ones
-    return ba.lvl <= 1 ? launch_scatter<2, 8>(a, nl, ba.lvl, s) : launch_scatter<4, 4>(a, nl, ba.lvl, s);
+    // 4 wavefronts on the coarse ones; rows longer than about 2400 pixels
+    // take fewer rows per workgroup so that they fit in the 160 KB of LDS
+    if (scatter_lds<2, 8>(nl) <= kLdsBytes)
+        return ba.lvl <= 1 ? launch_scatter<2, 8>(a, nl, ba.lvl, s) : launch_scatter<4, 4>(a, nl, ba.lvl, s);
+    if (scatter_lds<1, 4>(nl) <= kLdsBytes) return launch_scatter<1, 4>(a, nl, ba.lvl, s);
+    return launch_scatter<1, 2>(a, nl, ba.lvl, s);
 }
 
 hipError_t launch_bp(const BpArgs& ba, hipStream_t s)

@@ -163,6 +163,25 @@ def test_large_grid_projector_pair():
         assert rel(got, oracle.prolong(oracle.backproject(og, l, y), l) / 4 ** l) <= 1e-5
 
 
+@pytest.mark.parametrize("n,na,nd", [(4096, 6, 5800), (8192, 3, 8192)])
+def test_very_large_grids(n, na, nd):
+    """Rows longer than the LDS of the default transpose tile (a fallback tile
+    of fewer rows), the direct forward, and the largest detector."""
+    g = pk.Geometry(n, na, nd)
+    og = oracle.Geometry(n, na, nd)
+    work = pk.workspace(g)
+    x = f32(synth.random_image(n, 23))
+    y = f32(synth.random_sinogram(na, nd, 24))
+    for l in (0, 1):
+        say(f"grid {n} level {l}")
+        got = host(pk.project(g, l, dev(x), work))
+        assert rel(got, oracle.project(og, l, oracle.restrict(x, l))) <= 1e-5
+        got = host(pk.backproject(g, l, dev(y), work))
+        assert rel(got, oracle.prolong(oracle.backproject(og, l, y), l) / 4 ** l) <= 1e-5
+    del work
+    torch.cuda.empty_cache()
+
+
 def test_projection_is_deterministic():
     g = pk.Geometry(128, 180, 192)
     work = pk.workspace(g)

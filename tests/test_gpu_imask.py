@@ -165,3 +165,18 @@ def test_step_constants_match_dense_oracle(mode):
     sig, th = pk.sigma_thm3(*got, 0.2, 60)
     osig, oth, _, _ = steps.sigma_thm3(*exp, 0.2, 60, 60)
     assert sig == pytest.approx(osig, rel=1e-3) and 0 < th < 1
+
+
+def test_steps_on_a_4096_grid():
+    """Whole iterations where the level-0 transpose takes the long-row tile:
+    4096^2, 4 angles x 4096 bins, smoothed TV, three levels."""
+    n, na, nd = 4096, 4, 4096
+    b = f32(synth.random_sinogram(na, nd, 31)) * 0.1 + 1.0
+    reg_o = oracle.Reg(oracle.REG_SMOOTH_TV, lam=0.1, tv_weight=0.01, tv_eps=0.05, tv_inner=3)
+    reg_g = pk.Regularizer(pk.REG_SMOOTH_TV, 0.1, 0.01, 0.05, 3)
+    say("4096 grid steps")
+    ost, prob = _run_both(n, na, nd, b, (0, 1, 2), (0.4, 0.3, 0.3), pk.FULL_UNBIASED, reg_o, reg_g, 0.05, 4)
+    assert prob.epochs == ost.epochs
+    assert rel(host(prob.x_cur), ost.x) <= 1e-4
+    assert rel(host(prob.y_cur), ost.y) <= 1e-4
+

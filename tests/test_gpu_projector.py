@@ -163,7 +163,7 @@ def test_large_grid_projector_pair():
         assert rel(got, oracle.prolong(oracle.backproject(og, l, y), l) / 4 ** l) <= 1e-5
 
 
-@pytest.mark.parametrize("n,na,nd", [(4096, 6, 5800), (8192, 3, 8192)])
+@pytest.mark.parametrize("n,na,nd", [(4096, 6, 5800), (8192, 3, 8192), (16384, 2, 8192)])
 def test_very_large_grids(n, na, nd):
     """Rows longer than the LDS of the default transpose tile (a fallback tile
     of fewer rows), the direct forward, and the largest detector."""

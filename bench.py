@@ -52,6 +52,10 @@ SEED, STREAM = 42, 0
 FLOP_PER_SAMPLE = 7
 PEAK_FP32_TFLOPS = 157.3   # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2 (dual FP32) x 2.4 GHz
 HBM_PEAK_GBS = 8000.0
+LDS_PEAK_TBPS = 256 * 128 * 2.4e9 / 1e12  # 78.6 TB/s: 128 B per clock per CU
+# LDS bytes per sample: the transpose reads and writes both taps' cells, the
+# forward reads both taps
+LDS_BYTES_PER_SAMPLE = {"bp": 16, "fwd": 8}
 COPY_N = 4096               # calibration copy: 4096^2 floats = 64 MiB each way
 KERNEL_SOURCES = ["paper_2412_10249_amd/csrc/kernels.hip", "paper_2412_10249_amd/csrc/api.hip",
                   "paper_2412_10249_amd/csrc/internal.h"]
@@ -215,6 +219,12 @@ def run(args):
                      "samples_per_launch": samples[dom[1]], "avg_launch_us": dom_t * 1e6,
                      "samples_per_s": samples[dom[1]] / dom_t,
                      "effective_gather_frac_hbm": samples[dom[1]] * 8 / dom_t / 1e9 / HBM_PEAK_GBS},
+        # the transpose's working limit: LDS traffic, two read-modify-writes of
+        # 4-byte cells per sample, against 256 CUs x 128 B/clk x 2.4 GHz
+        "lds_roofline": {"kernel": key, "bytes_per_sample": LDS_BYTES_PER_SAMPLE[dom[0]],
+                         "achieved_TBps": samples[dom[1]] * LDS_BYTES_PER_SAMPLE[dom[0]] / dom_t / 1e12,
+                         "peak_TBps": LDS_PEAK_TBPS,
+                         "frac": samples[dom[1]] * LDS_BYTES_PER_SAMPLE[dom[0]] / dom_t / 1e12 / LDS_PEAK_TBPS},
         "kernels_us": {f"{k[0]}_l{k[1]}": round(v * 1e6, 2) for k, v in kern.items()},
         "projector_samples_per_s": {f"{k[0]}_l{k[1]}": samples[k[1]] / v for k, v in kern.items()},
         "kernel_source_hash": source_hash(),

@@ -45,7 +45,7 @@ def lib():
     if _lib is None:
         _lib = ctypes.CDLL(build())
         L = _lib
-        geo = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double]
+        geo = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double, _D]
         L.orc_project.argtypes = geo + [ctypes.c_int, _D, _D]
         L.orc_backproject.argtypes = geo + [ctypes.c_int, _D, _D]
         L.orc_count_samples.argtypes = geo + [ctypes.c_int]
@@ -109,20 +109,36 @@ def _f64(a) -> np.ndarray:
 
 @dataclass(frozen=True)
 class Geometry:
-    """2-D parallel-beam geometry: N x N image on [-1,1]^2, n_angles angles
-    a*pi/n_angles, n_det bins of spacing ds (default: full-res pixel size)."""
+    """2-D parallel-beam geometry: N x N image on [-E,E]^2 (E = extent),
+    n_angles angles a*pi/n_angles or the given list (radians), n_det bins of
+    spacing ds (default: full-res pixel size 2E/N)."""
     n: int
     n_angles: int
     n_det: int
     ds: float = 0.0
     s0: float = 0.0
+    extent: float = 1.0
+    angles: tuple = None
+
+    def __post_init__(self):
+        if self.angles is not None:
+            a = tuple(float(t) for t in self.angles)
+            assert len(a) == self.n_angles
+            object.__setattr__(self, "angles", a)
+            object.__setattr__(self, "_ang", _f64(a))
 
     @property
     def spacing(self) -> float:
-        return self.ds if self.ds > 0 else 2.0 / self.n
+        return self.ds if self.ds > 0 else 2.0 * self.extent / self.n
+
+    def theta(self) -> np.ndarray:
+        if self.angles is not None:
+            return np.array(self.angles)
+        return np.arange(self.n_angles) * np.pi / self.n_angles
 
     def args(self):
-        return (self.n, self.n_angles, self.n_det, self.spacing, self.s0)
+        ang = _dp(self._ang) if self.angles is not None else None
+        return (self.n, self.n_angles, self.n_det, self.spacing, self.s0, self.extent, ang)
 
 
 @dataclass

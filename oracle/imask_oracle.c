@@ -25,13 +25,14 @@
  *     their projections, plus a running table average);
  *   - Alg. 1 with independent primal and dual sketch draws (Sec. 6 outlook).
  *
- * Conventions: domain [-1,1]^2; level l has N_l = N >> l pixels per side and
- * pixel size h_l = 2/N_l; pixel (i,j) has centre (x_j, y_i) with
- * x_j = -1 + (j+1/2) h_l; rows are y, columns are x, storage row-major.
- * Angle a is theta_a = a*pi/n_angles, bin b has centre
- * s_b = (b - (n_det-1)/2) ds + s0 and the ray is x cos + y sin = s.
- * Angle a steps along rows iff 4a <= n_angles or 4a >= 3 n_angles, else
- * along columns.  Interpolation reads zero outside the image.
+ * Conventions: domain [-E,E]^2 (E = extent); level l has N_l = N >> l pixels
+ * per side and pixel size h_l = 2E/N_l; pixel (i,j) has centre (x_j, y_i)
+ * with x_j = -E + (j+1/2) h_l; rows are y, columns are x, storage row-major.
+ * Angle a is theta_a = a*pi/n_angles, or the a-th entry of a given list; bin
+ * b has centre s_b = (b - (n_det-1)/2) ds + s0 and the ray is
+ * x cos + y sin = s.  Default angles step along rows iff 4a <= n_angles or
+ * 4a >= 3 n_angles, listed ones iff |cos| >= |sin|; else along columns.
+ * Interpolation reads zero outside the image.
  */
 #include <math.h>
 #include <omp.h>
@@ -48,7 +49,16 @@
 enum { ORC_MODE_PAPER = 0, ORC_MODE_UNBIASED = 1 };
 enum { ORC_REG_TIKHONOV = 0, ORC_REG_SMOOTH_TV = 1, ORC_REG_TV = 2 };
 
-static int orc_row_stepping(int a, int na) { return 4 * a <= na || 4 * a >= 3 * na; }
+/* Angle a: the given list (radians), or a*pi/na.  Row stepping: with the
+ * default angles the integer rule 4a <= na or 4a >= 3na (45 and 135 degrees
+ * step along rows); with a given list |cos| >= |sin| in FP64. */
+static double orc_theta(int a, int na, const double* ang) { return ang ? ang[a] : a * M_PI / na; }
+
+static int orc_rows(int a, int na, const double* ang)
+{
+    if (ang) return fabs(cos(ang[a])) >= fabs(sin(ang[a]));
+    return 4 * a <= na || 4 * a >= 3 * na;
+}
 
 static double orc_pix(const double* z, int nl, long i, long j)
 {
@@ -60,21 +70,21 @@ static double orc_pix(const double* z, int nl, long i, long j)
 
 /* sino[a][b] = (h_l/|cos|) sum_i interp_j(z[i][.], u)   (row stepping)
  *            = (h_l/|sin|) sum_j interp_i(z[.][j], v)   (column stepping) */
-void orc_project(int n, int na, int nd, double ds, double s0, int lvl,
+void orc_project(int n, int na, int nd, double ds, double s0, double E, const double* ang, int lvl,
                  const double* z, double* sino)
 {
     const int nl = n >> lvl;
-    const double hl = 2.0 / nl;
-    const double c0 = -1.0 + 0.5 * hl; /* centre of pixel 0 along either axis */
+    const double hl = 2.0 * E / nl;
+    const double c0 = -E + 0.5 * hl; /* centre of pixel 0 along either axis */
 #pragma omp parallel for schedule(static)
     for (long ab = 0; ab < (long)na * nd; ++ab) {
         const int a = (int)(ab / nd), b = (int)(ab % nd);
-        const double th = a * M_PI / na, ct = cos(th), st = sin(th);
+        const double th = orc_theta(a, na, ang), ct = cos(th), st = sin(th);
         const double sb = (b - (nd - 1) / 2.0) * ds + s0;
         double acc = 0.0;
-        if (orc_row_stepping(a, na)) {
+        if (orc_rows(a, na, ang)) {
             for (int i = 0; i < nl; ++i) {
-                const double yi = -1.0 + (i + 0.5) * hl;
+                const double yi = -E + (i + 0.5) * hl;
                 const double u = ((sb - yi * st) / ct - c0) / hl;
                 const double fl = floor(u);
                 const long j0 = (long)fl;
@@ -84,7 +94,7 @@ void orc_project(int n, int na, int nd, double ds, double s0, int lvl,
             sino[ab] = acc * (hl / fabs(ct));
         } else {
             for (int j = 0; j < nl; ++j) {
-                const double xj = -1.0 + (j + 0.5) * hl;
+                const double xj = -E + (j + 0.5) * hl;
                 const double v = ((sb - xj * ct) / st - c0) / hl;
                 const double fl = floor(v);
                 const long i0 = (long)fl;
@@ -98,12 +108,12 @@ void orc_project(int n, int na, int nd, double ds, double s0, int lvl,
 
 /* The literal transpose of orc_project: the same loops, scattering
  * t*(1-w) and t*w into the two pixels each sample reads. */
-void orc_backproject(int n, int na, int nd, double ds, double s0, int lvl,
+void orc_backproject(int n, int na, int nd, double ds, double s0, double E, const double* ang, int lvl,
                      const double* sino, double* z)
 {
     const int nl = n >> lvl;
-    const double hl = 2.0 / nl;
-    const double c0 = -1.0 + 0.5 * hl;
+    const double hl = 2.0 * E / nl;
+    const double c0 = -E + 0.5 * hl;
     const long dl = (long)nl * nl;
     memset(z, 0, sizeof(double) * dl);
     /* per-thread partial images, summed in thread order afterwards so that
@@ -115,13 +125,13 @@ void orc_backproject(int n, int na, int nd, double ds, double s0, int lvl,
         double* acc = part + (size_t)omp_get_thread_num() * dl;
 #pragma omp for schedule(static)
         for (int a = 0; a < na; ++a) {
-            const double th = a * M_PI / na, ct = cos(th), st = sin(th);
-            const int rows = orc_row_stepping(a, na);
+            const double th = orc_theta(a, na, ang), ct = cos(th), st = sin(th);
+            const int rows = orc_rows(a, na, ang);
             for (int b = 0; b < nd; ++b) {
                 const double sb = (b - (nd - 1) / 2.0) * ds + s0;
                 const double t = (rows ? hl / fabs(ct) : hl / fabs(st)) * sino[(long)a * nd + b];
                 for (int k = 0; k < nl; ++k) {
-                    const double ck = -1.0 + (k + 0.5) * hl;
+                    const double ck = -E + (k + 0.5) * hl;
                     const double u = rows ? ((sb - ck * st) / ct - c0) / hl : ((sb - ck * ct) / st - c0) / hl;
                     const double fl = floor(u);
                     const long q0 = (long)fl;
@@ -144,20 +154,20 @@ void orc_backproject(int n, int na, int nd, double ds, double s0, int lvl,
 
 /* Number of (ray, step) samples with at least one interpolation tap inside
  * the image: the nonzero-sample count of R_l (work accounting only). */
-long long orc_count_samples(int n, int na, int nd, double ds, double s0, int lvl)
+long long orc_count_samples(int n, int na, int nd, double ds, double s0, double E, const double* ang, int lvl)
 {
     const int nl = n >> lvl;
-    const double hl = 2.0 / nl;
-    const double c0 = -1.0 + 0.5 * hl;
+    const double hl = 2.0 * E / nl;
+    const double c0 = -E + 0.5 * hl;
     long long total = 0;
 #pragma omp parallel for reduction(+ : total) schedule(static)
     for (long ab = 0; ab < (long)na * nd; ++ab) {
         const int a = (int)(ab / nd), b = (int)(ab % nd);
-        const double th = a * M_PI / na, ct = cos(th), st = sin(th);
+        const double th = orc_theta(a, na, ang), ct = cos(th), st = sin(th);
         const double sb = (b - (nd - 1) / 2.0) * ds + s0;
-        const int rows = orc_row_stepping(a, na);
+        const int rows = orc_rows(a, na, ang);
         for (int k = 0; k < nl; ++k) {
-            const double ck = -1.0 + (k + 0.5) * hl;
+            const double ck = -E + (k + 0.5) * hl;
             const double u = rows ? ((sb - ck * st) / ct - c0) / hl : ((sb - ck * ct) / st - c0) / hl;
             const long q0 = (long)floor(u);
             if (q0 >= -1 && q0 < nl) ++total;
@@ -209,23 +219,23 @@ void orc_compensate(int n, int r, const int* log2f, const double* p, const doubl
 /* ------------------------------------------------------ sketched operators */
 
 /* g = K_k x (sinogram), for sketch k of the level set (log2f[0] == 0). */
-void orc_sketch_fwd(int n, int na, int nd, double ds, double s0, int r, const int* log2f,
+void orc_sketch_fwd(int n, int na, int nd, double ds, double s0, double E, const double* ang, int r, const int* log2f,
                     const double* p, int mode, int k, const double* x, double* g)
 {
     const long d = (long)n * n, m = (long)na * nd;
     double* z = (double*)malloc(sizeof(double) * d);
     if (k > 0) {
         orc_restrict(n, log2f[k], x, z);
-        orc_project(n, na, nd, ds, s0, log2f[k], z, g);
+        orc_project(n, na, nd, ds, s0, E, ang, log2f[k], z, g);
     } else if (mode == ORC_MODE_PAPER) {
         orc_compensate(n, r, log2f, p, x, z);
-        orc_project(n, na, nd, ds, s0, 0, z, g);
+        orc_project(n, na, nd, ds, s0, E, ang, 0, z, g);
     } else {
         double* t = (double*)malloc(sizeof(double) * m);
-        orc_project(n, na, nd, ds, s0, 0, x, g);
+        orc_project(n, na, nd, ds, s0, E, ang, 0, x, g);
         for (int q = 1; q < r; ++q) {
             orc_restrict(n, log2f[q], x, z);
-            orc_project(n, na, nd, ds, s0, log2f[q], z, t);
+            orc_project(n, na, nd, ds, s0, E, ang, log2f[q], z, t);
             for (long e = 0; e < m; ++e) g[e] -= p[q] * t[e];
         }
         for (long e = 0; e < m; ++e) g[e] /= p[0];
@@ -235,7 +245,7 @@ void orc_sketch_fwd(int n, int na, int nd, double ds, double s0, int r, const in
 }
 
 /* g = K_k^T y (image), the exact transpose of orc_sketch_fwd. */
-void orc_sketch_adj(int n, int na, int nd, double ds, double s0, int r, const int* log2f,
+void orc_sketch_adj(int n, int na, int nd, double ds, double s0, double E, const double* ang, int r, const int* log2f,
                     const double* p, int mode, int k, const double* y, double* g)
 {
     const long d = (long)n * n;
@@ -244,18 +254,18 @@ void orc_sketch_adj(int n, int na, int nd, double ds, double s0, int r, const in
     if (k > 0) {
         const int l = log2f[k];
         const double s = 1.0 / (double)(1L << (2 * l)); /* T_l^T = 4^{-l} T_l^* */
-        orc_backproject(n, na, nd, ds, s0, l, y, c);
+        orc_backproject(n, na, nd, ds, s0, E, ang, l, y, c);
         orc_prolong(n, l, c, g);
         for (long q = 0; q < d; ++q) g[q] *= s;
     } else if (mode == ORC_MODE_PAPER) {
-        orc_backproject(n, na, nd, ds, s0, 0, y, c);
+        orc_backproject(n, na, nd, ds, s0, E, ang, 0, y, c);
         orc_compensate(n, r, log2f, p, c, g); /* S_r is symmetric */
     } else {
-        orc_backproject(n, na, nd, ds, s0, 0, y, g);
+        orc_backproject(n, na, nd, ds, s0, E, ang, 0, y, g);
         for (int q = 1; q < r; ++q) {
             const int l = log2f[q];
             const double s = 1.0 / (double)(1L << (2 * l));
-            orc_backproject(n, na, nd, ds, s0, l, y, c);
+            orc_backproject(n, na, nd, ds, s0, E, ang, l, y, c);
             orc_prolong(n, l, c, t);
             for (long e = 0; e < d; ++e) g[e] -= p[q] * s * t[e];
         }
@@ -478,7 +488,7 @@ static void orc_prox(int n, int reg_kind, double tau, double lam, double tv_w, d
  * (psi_k = K_k x at the last refresh).  mu = lam.  draws_out[q] receives
  * i_{k0+q}; *epochs accumulates sum_q 2^{-log2f[i_q]} (PAPER cost model) or,
  * in UNBIASED mode, 1 + sum_{k>0} 2^{-log2f[k]} for a full-resolution step. */
-int orc_imask_run(int n, int na, int nd, double ds, double s0,
+int orc_imask_run(int n, int na, int nd, double ds, double s0, double E, const double* ang,
                   int r, const int* log2f, const double* p, int mode,
                   int reg_kind, double lam, double tv_w, double tv_eps, int tv_inner,
                   double sigma, uint64_t seed, uint32_t stream, uint64_t k0,
@@ -501,8 +511,8 @@ int orc_imask_run(int n, int na, int nd, double ds, double s0,
     for (int it = 0; it < n_iter; ++it) {
         const int k = idx[it];
         /* both refreshed gradients from the old iterates x^k, y^k */
-        orc_sketch_adj(n, na, nd, ds, s0, r, log2f, p, mode, k, y, gx);
-        orc_sketch_fwd(n, na, nd, ds, s0, r, log2f, p, mode, k, x, gy);
+        orc_sketch_adj(n, na, nd, ds, s0, E, ang, r, log2f, p, mode, k, y, gx);
+        orc_sketch_fwd(n, na, nd, ds, s0, E, ang, r, log2f, p, mode, k, x, gy);
         /* SAGA estimates with the old tables */
         for (long q = 0; q < d; ++q) {
             double avg = 0.0;
@@ -552,7 +562,7 @@ int orc_imask_run(int n, int na, int nd, double ds, double s0,
  *   x_new = prox_{tau R}(x - tau xi), tau = sigma / mu;
  *   xbar <- x_new + theta (x_new - x);  x <- x_new;  psi_i, phi_i refreshed.
  * Draws and epoch accounting as in orc_imask_run. */
-int orc_imask_seq_run(int n, int na, int nd, double ds, double s0,
+int orc_imask_seq_run(int n, int na, int nd, double ds, double s0, double E, const double* ang,
                       int r, const int* log2f, const double* p, int mode,
                       int reg_kind, double lam, double tv_w, double tv_eps, int tv_inner,
                       double sigma, double theta, uint64_t seed, uint32_t stream, uint64_t k0,
@@ -574,7 +584,7 @@ int orc_imask_seq_run(int n, int na, int nd, double ds, double s0,
     for (int it = 0; it < n_iter; ++it) {
         const int k = idx[it];
         /* dual step from the extrapolated point */
-        orc_sketch_fwd(n, na, nd, ds, s0, r, log2f, p, mode, k, xbar, gy);
+        orc_sketch_fwd(n, na, nd, ds, s0, E, ang, r, log2f, p, mode, k, xbar, gy);
         for (long e = 0; e < m; ++e) {
             double avg = 0.0;
             for (int j = 0; j < r; ++j) avg += p[j] * psi[(long)j * m + e];
@@ -582,7 +592,7 @@ int orc_imask_seq_run(int n, int na, int nd, double ds, double s0,
             y[e] = (y[e] + sigma * zeta - sigma * bdata[e]) / (1.0 + sigma);
         }
         /* primal step with the new dual iterate */
-        orc_sketch_adj(n, na, nd, ds, s0, r, log2f, p, mode, k, y, gx);
+        orc_sketch_adj(n, na, nd, ds, s0, E, ang, r, log2f, p, mode, k, y, gx);
         for (long q = 0; q < d; ++q) {
             double avg = 0.0;
             for (int j = 0; j < r; ++j) avg += p[j] * phi[(long)j * d + q];
@@ -618,7 +628,7 @@ int orc_imask_seq_run(int n, int na, int nd, double ds, double s0,
  * step still suffices: d = K_i (x^k - z_i) = psi_new - psi_i, so
  * zeta = d + psibar, psibar <- psibar + p_i d and z_i <- x^k.  Everything
  * else is orc_imask_run. */
-int orc_imask_compact_run(int n, int na, int nd, double ds, double s0,
+int orc_imask_compact_run(int n, int na, int nd, double ds, double s0, double E, const double* ang,
                           int r, const int* log2f, const double* p, int mode,
                           int reg_kind, double lam, double tv_w, double tv_eps, int tv_inner,
                           double sigma, uint64_t seed, uint32_t stream, uint64_t k0,
@@ -642,9 +652,9 @@ int orc_imask_compact_run(int n, int na, int nd, double ds, double s0,
     for (int it = 0; it < n_iter; ++it) {
         const int k = idx[it];
         /* both refreshed gradients from the old iterates x^k, y^k */
-        orc_sketch_adj(n, na, nd, ds, s0, r, log2f, p, mode, k, y, gx);
+        orc_sketch_adj(n, na, nd, ds, s0, E, ang, r, log2f, p, mode, k, y, gx);
         for (long q = 0; q < d; ++q) diff[q] = x[q] - zsnap[(long)k * d + q];
-        orc_sketch_fwd(n, na, nd, ds, s0, r, log2f, p, mode, k, diff, dd);
+        orc_sketch_fwd(n, na, nd, ds, s0, E, ang, r, log2f, p, mode, k, diff, dd);
         for (long q = 0; q < d; ++q) {
             double avg = 0.0;
             for (int j = 0; j < r; ++j) avg += p[j] * phi[(long)j * d + q];
@@ -684,7 +694,7 @@ int orc_imask_compact_run(int n, int na, int nd, double ds, double s0,
  * averages.  An iteration costs half of each side's level cost:
  * epochs += (c(i_k) + c(j_k)) / 2, so equal streams reproduce orc_imask_run.
  * draws_out gets i_k, dual_draws_out j_k (either may be NULL). */
-int orc_imask_indep_run(int n, int na, int nd, double ds, double s0,
+int orc_imask_indep_run(int n, int na, int nd, double ds, double s0, double E, const double* ang,
                         int r, const int* log2f, const double* p, int mode,
                         int reg_kind, double lam, double tv_w, double tv_eps, int tv_inner,
                         double sigma, uint64_t seed, uint32_t stream, uint32_t dual_stream, uint64_t k0,
@@ -709,8 +719,8 @@ int orc_imask_indep_run(int n, int na, int nd, double ds, double s0,
         for (int k = 1; k < r; ++k) cost[0] += ldexp(1.0, -log2f[k]);
     for (int it = 0; it < n_iter; ++it) {
         const int i = ip[it], j = jd[it];
-        orc_sketch_adj(n, na, nd, ds, s0, r, log2f, p, mode, i, y, gx);
-        orc_sketch_fwd(n, na, nd, ds, s0, r, log2f, p, mode, j, x, gy);
+        orc_sketch_adj(n, na, nd, ds, s0, E, ang, r, log2f, p, mode, i, y, gx);
+        orc_sketch_fwd(n, na, nd, ds, s0, E, ang, r, log2f, p, mode, j, x, gy);
         for (long q = 0; q < d; ++q) {
             double avg = 0.0;
             for (int c = 0; c < r; ++c) avg += p[c] * phi[(long)c * d + q];

@@ -13,6 +13,7 @@ from .phantom import (  # noqa: F401
     poisson_log_data,
     detector_centres,
     angles_uniform,
+    angles_random,
     pixel_centres,
     disk_image,
     square_insert,

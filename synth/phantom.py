@@ -2,11 +2,13 @@
 
 Geometry conventions (shared by every consumer, stated once here):
 
-* The image domain is the square [-E, E]^2 with E = 1.  An N x N image has
+* The image domain is the square [-E, E]^2 with E = 1 unless a generator is
+  given another extent.  An N x N image has
   pixel size h = 2E/N; pixel (i, j) is row i, column j, with centre
   x_j = -E + (j + 1/2) h and y_i = -E + (i + 1/2) h, stored row-major.
 * Projection angle a of n_angles is theta_a = a*pi/n_angles (uniform over
-  [0, pi), as in the paper's parallel-beam experiments, Sec. 4.1).
+  [0, pi), as in the paper's parallel-beam experiments, Sec. 4.1), unless an
+  explicit list of angles is used (angles_random draws one).
 * Detector bin b of n_det has centre s_b = (b - (n_det-1)/2) * ds + s0 with
   ds = the full-resolution pixel size 2E/N and s0 = 0.
 * A ray is the line {x cos(theta) + y sin(theta) = s}.
@@ -40,14 +42,19 @@ def angles_uniform(n_angles: int) -> np.ndarray:
     return np.arange(n_angles, dtype=np.float64) * np.pi / n_angles
 
 
-def detector_centres(n: int, n_det: int, det_offset: float = 0.0) -> np.ndarray:
-    ds = 2.0 * EXTENT / n
+def angles_random(n_angles: int, seed: int, lo: float = 0.0, hi: float = 2.0 * np.pi) -> np.ndarray:
+    """n_angles angles drawn uniformly from [lo, hi), in draw order."""
+    return np.random.default_rng(seed).uniform(lo, hi, size=n_angles)
+
+
+def detector_centres(n: int, n_det: int, det_offset: float = 0.0, extent: float = EXTENT) -> np.ndarray:
+    ds = 2.0 * extent / n
     return (np.arange(n_det, dtype=np.float64) - (n_det - 1) / 2.0) * ds + det_offset
 
 
-def pixel_centres(n: int) -> np.ndarray:
-    h = 2.0 * EXTENT / n
-    return -EXTENT + (np.arange(n, dtype=np.float64) + 0.5) * h
+def pixel_centres(n: int, extent: float = EXTENT) -> np.ndarray:
+    h = 2.0 * extent / n
+    return -extent + (np.arange(n, dtype=np.float64) + 0.5) * h
 
 
 def random_ellipses(seed: int, n_ellipses: int = 8) -> list[Ellipse]:
@@ -120,9 +127,9 @@ def ct_problem(n: int, n_angles: int, n_det: int, i0: float, phantom_seed: int,
     return x_true, b
 
 
-def disk_image(n: int, rho: float, cx: float = 0.0, cy: float = 0.0) -> np.ndarray:
+def disk_image(n: int, rho: float, cx: float = 0.0, cy: float = 0.0, extent: float = EXTENT) -> np.ndarray:
     """Unit disk of radius rho centred at (cx, cy), sampled at pixel centres."""
-    xc = pixel_centres(n)
+    xc = pixel_centres(n, extent)
     X, Y = np.meshgrid(xc, xc, indexing="xy")
     return ((X - cx) ** 2 + (Y - cy) ** 2 <= rho * rho).astype(np.float64)
 
@@ -135,9 +142,9 @@ def square_insert(n: int, block: int, lo: int, hi: int, value: float = 1.0) -> n
     return img
 
 
-def affine_image(n: int, alpha: float, beta: float, gamma: float) -> np.ndarray:
+def affine_image(n: int, alpha: float, beta: float, gamma: float, extent: float = EXTENT) -> np.ndarray:
     """f(x, y) = alpha x + beta y + gamma at the pixel centres."""
-    xc = pixel_centres(n)
+    xc = pixel_centres(n, extent)
     X, Y = np.meshgrid(xc, xc, indexing="xy")
     return alpha * X + beta * Y + gamma
 

@@ -8,7 +8,11 @@ R_l is the parallel-beam forward model evaluated on the level-l grid
     are exact for linear integrands), on every level;
   * theta = 0 and theta = pi/2 reduce to column and row sums;
   * the dot-product test and the explicit matrix, which tie the scatter
-    transpose to the forward map entry by entry.
+    transpose to the forward map entry by entry;
+  * with a listed set of angles anywhere in [0, 2pi) and a domain [-E, E]^2:
+    the disk chords and affine exactness again, bitwise agreement with the
+    default angles when the list is the default one, and the mirror symmetry
+    of opposite angles (theta + pi sees the detector reversed).
 """
 import numpy as np
 import pytest
@@ -116,3 +120,95 @@ def test_sample_count_bounded():
     for lvl in range(3):
         c = oracle.count_samples(g, lvl)
         assert 0 < c <= 90 * 92 * (64 >> lvl)
+
+
+# ---- listed angles (any real theta) and a domain [-E, E]^2 ----
+
+def _listed(n, n_det, seed, n_angles=16, extent=2.5):
+    th = synth.angles_random(n_angles, seed)
+    return oracle.Geometry(n, n_angles, n_det, extent=extent, angles=tuple(th)), th
+
+
+def test_listed_angles_disk_chords_converge():
+    E = 2.5
+    cx, cy, rho = 0.21 * E, -0.13 * E, 0.5 * E
+    means = []
+    for n in (64, 128, 256, 512):
+        g, th = _listed(n, 3 * n // 2, 11, extent=E)
+        sino = oracle.project(g, 0, synth.disk_image(n, rho, cx, cy, extent=E))
+        s = synth.detector_centres(n, 3 * n // 2, extent=E)[None, :]
+        t = th[:, None]
+        sp = s - (cx * np.cos(t) + cy * np.sin(t))
+        exact = 2.0 * np.sqrt(np.maximum(rho * rho - sp * sp, 0.0))
+        step = (2.0 * E / n) / np.maximum(np.abs(np.cos(t)), np.abs(np.sin(t)))
+        err = np.abs(sino - exact)
+        assert (err / step)[np.abs(sp) <= 0.9 * rho].max() < 2.0, n
+        means.append(err.mean())
+    ratios = np.array(means[1:]) / np.array(means[:-1])
+    assert ratios.max() < 0.65, ratios
+
+
+@pytest.mark.parametrize("lvl", [0, 1, 2])
+def test_listed_angles_affine_images_are_exact(lvl):
+    n, n_det, E = 64, 96, 1.7
+    g, th = _listed(n, n_det, 5 + lvl, n_angles=40, extent=E)
+    alpha, beta, gamma = 0.7, -0.45, 0.3
+    nl = n >> lvl
+    h = 2.0 * E / nl
+    sino = oracle.project(g, lvl, synth.affine_image(nl, alpha, beta, gamma, extent=E))
+    s = synth.detector_centres(n, n_det, extent=E)
+    c0 = -E + 0.5 * h
+    ends = np.array([c0, -c0])
+    checked = 0
+    for a, t in enumerate(th):
+        ct, st = np.cos(t), np.sin(t)
+        rows = abs(ct) >= abs(st)
+        for b, sb in enumerate(s):
+            if rows:
+                u = ((sb - ends * st) / ct - c0) / h
+                expect = 2.0 * E * (alpha * sb / ct + gamma) / abs(ct)
+            else:
+                u = ((sb - ends * ct) / st - c0) / h
+                expect = 2.0 * E * (beta * sb / st + gamma) / abs(st)
+            if u.min() >= 0.0 and u.max() <= nl - 1:
+                assert abs(sino[a, b] - expect) <= 1e-12 * max(1.0, abs(expect)), (a, b)
+                checked += 1
+    assert checked > 40 * 10
+
+
+def test_listed_uniform_angles_match_the_default_bitwise():
+    # 30 angles: none at exactly 45 or 135 degrees, where the two stepping
+    # rules may pick different (equally valid) axes
+    g0 = oracle.Geometry(64, 30, 92)
+    g1 = oracle.Geometry(64, 30, 92, angles=tuple(synth.angles_uniform(30)))
+    z = synth.random_image(64, 2)
+    y = synth.random_sinogram(30, 92, 3)
+    for lvl in (0, 2):
+        zl = z[:64 >> lvl, :64 >> lvl]
+        assert np.array_equal(oracle.project(g0, lvl, zl), oracle.project(g1, lvl, zl))
+        assert np.array_equal(oracle.backproject(g0, lvl, y), oracle.backproject(g1, lvl, y))
+
+
+def test_opposite_angles_mirror_the_detector():
+    # theta + pi is the same line set with s -> -s; bins symmetric about 0
+    th = synth.angles_random(12, 8, 0.0, np.pi)
+    g = oracle.Geometry(64, 24, 91, extent=1.3, angles=tuple(np.concatenate([th, th + np.pi])))
+    sino = oracle.project(g, 1, synth.random_image(32, 4))
+    np.testing.assert_allclose(sino[12:], sino[:12, ::-1], rtol=0, atol=1e-11)
+
+
+@pytest.mark.parametrize("lvl", [0, 2])
+def test_listed_angles_dot_product_and_matrix(lvl):
+    g, _ = _listed(64, 92, 21 + lvl, n_angles=50, extent=0.8)
+    nl = 64 >> lvl
+    rng = np.random.default_rng(lvl)
+    x = rng.standard_normal((nl, nl))
+    y = rng.standard_normal((50, 92))
+    lhs = np.vdot(oracle.project(g, lvl, x), y)
+    rhs = np.vdot(x, oracle.backproject(g, lvl, y))
+    assert abs(lhs - rhs) <= 1e-13 * np.sqrt(np.sum(x * x) * np.sum(y * y)) * 8
+    gs, _ = _listed(8, 12, 31 + lvl, n_angles=6, extent=0.8)
+    ns = 8 >> lvl
+    A = oracle.dense_matrix(lambda e: oracle.project(gs, lvl, e), (ns, ns), 6 * 12)
+    At = oracle.dense_matrix(lambda e: oracle.backproject(gs, lvl, e), (6, 12), ns * ns)
+    assert np.array_equal(A, At.T) and np.count_nonzero(A) > 0

@@ -14,15 +14,17 @@
  *     (-1 + (j+1/2)h, -1 + (i+1/2)h), h = 2/N.
  *   - Level l (l = log2 of the downsampling factor) has N_l = N >> l pixels
  *     per side; N must be divisible by 2^l.
- *   - Angle a of n_angles is a*pi/n_angles; bin b of n_det has centre
- *     (b - (n_det-1)/2)*det_spacing + det_offset; the ray is
- *     x cos(theta) + y sin(theta) = s.  Sinograms are [n_angles][n_det] float32.
+ *   - Angle a of n_angles is a*pi/n_angles or the a-th listed angle; bin b
+ *     of n_det has centre (b - (n_det-1)/2)*det_spacing + det_offset; the
+ *     ray is x cos(theta) + y sin(theta) = s.  Sinograms are
+ *     [n_angles][n_det] float32.
  *   - Every array argument is a DEVICE pointer owned by the caller, unless
  *     the comment says "host".  The library allocates no device memory and
  *     keeps no pointer after a call returns.
  *   - `stream` is a hipStream_t (NULL = default stream).  All device work is
  *     enqueued asynchronously on it; no call synchronises the device, so the
- *     calls can be captured into a HIP graph.
+ *     calls can be captured into a HIP graph (set-up calls excepted: they
+ *     say so).
  *   - Return value: IMASK_OK (0) or a negative error code.  Arguments are
  *     validated before anything is enqueued, so a failed call writes nothing.
  *     IMASK_EHIP reports a failed kernel launch (hipGetLastError).
@@ -62,13 +64,29 @@ enum {
 };
 enum { IMASK_BUDGET_ITERS = 0, IMASK_BUDGET_EPOCHS = 1 };
 
-/* Acquisition geometry (Sec. 4.1: parallel beam, m = n_angles * n_det). */
+/* Acquisition geometry (Sec. 4.1: parallel beam, m = n_angles * n_det).
+ * The image covers the square [-E, E]^2 (E = extent) with N x N pixels of
+ * side 2E/N; bin b has centre s_b = (b - (n_det-1)/2) det_spacing + s0 and
+ * angle a the ray set x cos(theta_a) + y sin(theta_a) = s_b.  Sinograms are
+ * stored angle-major in the order of the angles.
+ * angles: NULL selects theta_a = a*pi/n_angles; otherwise a HOST array of
+ * n_angles finite angles in radians (any real values, any order, repeats
+ * allowed).  imask_prepare copies it into the workspace, where the kernels
+ * read it, and waits for its stream; later calls read the host array only to
+ * size their launches, so they must pass the same values.  A listed angle
+ * steps along rows when |cos| >= |sin| in FP64, else along columns; the
+ * default angles step along rows iff 4a <= n_angles or 4a >= 3 n_angles.
+ * Invalid (EINVAL): n outside 4..16384,
+ * not a multiple of 4, or above 16 not a multiple of 16; n_angles or n_det
+ * out of range; a non-finite spacing, offset, extent or listed angle. */
 typedef struct {
-    int32_t n;          /* full-resolution image side N (>= 4, multiple of 4) */
-    int32_t n_angles;   /* 1 .. 65536 */
-    int32_t n_det;      /* 1 .. 8192 */
-    double det_spacing; /* bin spacing; <= 0 selects the full-res pixel size 2/N */
-    double det_offset;  /* detector centre offset s0 */
+    int32_t n;            /* full-resolution image side N */
+    int32_t n_angles;     /* 1 .. 65536 */
+    int32_t n_det;        /* 1 .. 8192 */
+    double det_spacing;   /* bin spacing; <= 0 selects the full-res pixel size 2E/N */
+    double det_offset;    /* detector centre offset s0 */
+    double extent;        /* half side E of the image square; <= 0 selects 1 */
+    const double* angles; /* host, n_angles radians, or NULL (see above) */
 } imask_geometry;
 
 /* Resolution set and sampling probabilities (Alg. 1 REQUIRE line; Sec. 4.1).
@@ -187,7 +205,9 @@ size_t imask_phi_floats(const imask_geometry* g, const imask_levels* lv);
 /* Fills `work` (device, work_bytes >= imask_workspace_bytes(g)) with the
  * per-(level, angle) projector constants and zeroes its scratch.  Every
  * other call taking `work` requires a workspace prepared for the same
- * geometry; calls sharing one workspace must be ordered on one stream. */
+ * geometry; calls sharing one workspace must be ordered on one stream.
+ * With listed angles it also copies them from the host and synchronises
+ * `stream` before returning (set-up, not for graph capture). */
 int imask_prepare(const imask_geometry* g, void* work, size_t work_bytes, void* stream);
 
 /* sino = R_l T_l x_full  (x_full N*N; T_0 = I).  R_l is the ray-driven

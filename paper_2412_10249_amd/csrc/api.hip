@@ -1,12 +1,13 @@
 // api.hip - the C ABI of libimask (include/imask.h): argument validation,
 // workspace layout, the host-side sketch draw and the per-step launch
 // sequence of Alg. 1.  All device work goes to the caller's stream; no call
-// allocates, frees or synchronises.
+// allocates or frees, and only set-up calls synchronise.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <vector>
 
 #include "imask.h"
 #include "internal.h"
@@ -23,6 +24,30 @@ static int level_limit(int n)
     int l = 0;
     while (l < IMASK_MAX_LOG2F && (n % (2 << l)) == 0 && (n >> (l + 1)) >= 2) ++l;
     return l;
+}
+
+// A listed angle steps along rows when |cos| >= |sin| (FP64, host libm):
+// the step between samples then stays within sqrt(2) pixels.
+static bool listed_row(double th) { return std::fabs(std::cos(th)) >= std::fabs(std::sin(th)); }
+
+// Row-stepping count of a listed angle set.  Launch sizes need it on every
+// call, so the last sets seen by this thread are kept and recognised by value.
+static int listed_nrow(const double* ang, int na)
+{
+    struct Seen {
+        std::vector<double> a;
+        int nrow = 0;
+    };
+    static thread_local Seen seen[4];
+    static thread_local int next = 0;
+    for (const Seen& e : seen)
+        if ((int)e.a.size() == na && std::memcmp(e.a.data(), ang, sizeof(double) * na) == 0) return e.nrow;
+    int nrow = 0;
+    for (int a = 0; a < na; ++a) nrow += listed_row(ang[a]) ? 1 : 0;
+    seen[next].a.assign(ang, ang + na);
+    seen[next].nrow = nrow;
+    next = (next + 1) & 3;
+    return nrow;
 }
 
 Layout make_layout(const imask_geometry& g)
@@ -56,6 +81,16 @@ Layout make_layout(const imask_geometry& g)
         L.fpart[l] = off;
         off = align64(off + (size_t)L.fbands[l] * m);
     }
+    L.angtab = off;
+    off = align64(off + 4 * (size_t)g.n_angles);
+    if (g.angles) {
+        L.listed = 1;
+        L.split = AngleSplit{};
+        L.split.nrow = listed_nrow(g.angles, g.n_angles);
+        L.split.ncol = g.n_angles - L.split.nrow;
+    } else {
+        L.split = angle_split(g.n_angles);
+    }
     L.total = off;
     return L;
 }
@@ -68,7 +103,10 @@ static bool geometry_ok(const imask_geometry* g)
     if (g->n < 4 || g->n > 16384 || (g->n % 4) != 0) return false;
     if (g->n > 16 && (g->n % 16) != 0) return false;
     if (g->n_angles < 1 || g->n_det < 1 || g->n_angles > 65536 || g->n_det > 8192) return false;
-    if (!std::isfinite(g->det_spacing) || !std::isfinite(g->det_offset)) return false;
+    if (!std::isfinite(g->det_spacing) || !std::isfinite(g->det_offset) || !std::isfinite(g->extent)) return false;
+    if (g->angles)
+        for (int a = 0; a < g->n_angles; ++a)
+            if (!std::isfinite(g->angles[a])) return false;
     return true;
 }
 
@@ -197,6 +235,7 @@ static void forward_plan(const Layout& L, const imask_levels& lv, int k, const f
 static void fwd_common(const Layout& L, const float* W, FwdArgs& fa)
 {
     fa.consts = (const RayConst*)(W + L.consts);
+    fa.split = split_at(L, W);
     fa.n = L.n;
     fa.na = L.na;
     fa.nd = L.nd;
@@ -207,6 +246,7 @@ static int backproject_raw(const Layout& L, const float* W, int lvl, const float
 {
     BpArgs ba{};
     ba.consts = (const RayConst*)(W + L.consts);
+    ba.split = split_at(L, W);
     ba.n = L.n;
     ba.na = L.na;
     ba.nd = L.nd;
@@ -403,6 +443,25 @@ int imask_prepare(const imask_geometry* g, void* work, size_t work_bytes, void* 
     if (work_bytes < L.total * sizeof(float)) return IMASK_ESIZE;
     hipStream_t s = (hipStream_t)stream;
     IMK_TRY(launch_fill((float*)work, L.total, 0.0f, s));
+    if (L.listed) {
+        // angle table: radians, then perm (row-stepping indices, then
+        // column-stepping ones, each ascending), then the row flags
+        const int na = g->n_angles;
+        std::vector<double> tab(2 * (size_t)na);
+        std::memcpy(tab.data(), g->angles, sizeof(double) * na);
+        int* perm = (int*)(tab.data() + na);
+        int* rows = perm + na;
+        int r = 0, c = L.split.nrow;
+        for (int a = 0; a < na; ++a) {
+            rows[a] = listed_row(g->angles[a]) ? 1 : 0;
+            perm[rows[a] ? r++ : c++] = a;
+        }
+        if (r != L.split.nrow || c != na) return IMASK_EINVAL;
+        if (hipMemcpyAsync((float*)work + L.angtab, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice,
+                           s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)  // tab is freed on return
+            return IMASK_EHIP;
+    }
     IMK_TRY(launch_consts(*g, L, (float*)work, s));
     return IMASK_OK;
 }
@@ -553,6 +612,7 @@ int imask_time_kernel(const imask_geometry* g, int32_t which, int32_t log2f, con
                              L.frows[log2f]};
     } else {
         ba.consts = (const RayConst*)(W + L.consts);
+        ba.split = split_at(L, W);
         ba.n = L.n;
         ba.na = L.na;
         ba.nd = L.nd;

@@ -35,6 +35,28 @@ constexpr int kPartImages = IMK_PART_IMAGES;
 constexpr int kPadL = 4;
 constexpr int kPad = 2 * kPadL;
 
+// Angle lists of the two stepping directions.  Default angles a*pi/na:
+// row-stepping angles are 0..n_lo-1 and a_hi0..na-1, column-stepping angles
+// n_lo..a_hi0-1.  Listed angles: perm (device) holds the nrow row-stepping
+// angle indices, then the ncol column-stepping ones, each ascending, and
+// rows[a] (device) is 1 for a row-stepping angle; both are null by default.
+struct AngleSplit {
+    int n_lo, a_hi0, nrow, ncol;
+    const int* perm;
+    const int* rows;
+};
+inline AngleSplit angle_split(int na)
+{
+    AngleSplit s{};
+    s.n_lo = na / 4 + 1;
+    s.a_hi0 = (3 * na + 3) / 4;
+    if (s.n_lo > na) s.n_lo = na;
+    if (s.a_hi0 < s.n_lo) s.a_hi0 = s.n_lo;
+    s.nrow = s.n_lo + (na - s.a_hi0);
+    s.ncol = s.a_hi0 - s.n_lo;
+    return s;
+}
+
 // Workspace layout for one geometry (offsets in floats from the start).
 struct Layout {
     int n = 0, na = 0, nd = 0, lmax = 0;
@@ -48,29 +70,27 @@ struct Layout {
     size_t fpart[IMASK_MAX_LOG2F + 1] = {};// per-band partial projections, fwd_bands(l) * m
     int fbands[IMASK_MAX_LOG2F + 1] = {};  // row bands of the level-l forward
     int frows[IMASK_MAX_LOG2F + 1] = {};   // rows per band (0: direct kernel, one band)
+    // listed angles: na doubles (radians), then perm and rows (na int32 each)
+    size_t angtab = 0;
+    int listed = 0;
+    AngleSplit split{};                    // perm / rows unset: see split_at
     size_t total = 0;
 };
 
 Layout make_layout(const imask_geometry& g);
-inline int side(int n, int l) { return n >> l; }
-inline int pstride(int n, int l) { return (n >> l) + kPad; }
-
-// Angle lists of the two stepping directions: row-stepping angles are
-// 0..n_lo-1 and a_hi0..na-1, column-stepping angles n_lo..a_hi0-1.
-struct AngleSplit {
-    int n_lo, a_hi0, nrow, ncol;
-};
-inline AngleSplit angle_split(int na)
+// The layout's angle split with its device tables in workspace W.
+inline AngleSplit split_at(const Layout& L, const float* W)
 {
-    AngleSplit s;
-    s.n_lo = na / 4 + 1;
-    s.a_hi0 = (3 * na + 3) / 4;
-    if (s.n_lo > na) s.n_lo = na;
-    if (s.a_hi0 < s.n_lo) s.a_hi0 = s.n_lo;
-    s.nrow = s.n_lo + (na - s.a_hi0);
-    s.ncol = s.a_hi0 - s.n_lo;
+    AngleSplit s = L.split;
+    if (L.listed) {
+        const int* t = (const int*)(W + L.angtab + 2 * (size_t)L.na);
+        s.perm = t;
+        s.rows = t + L.na;
+    }
     return s;
 }
+inline int side(int n, int l) { return n >> l; }
+inline int pstride(int n, int l) { return (n >> l) + kPad; }
 
 // ---- kernels' argument blocks (passed by value) ----
 
@@ -87,6 +107,7 @@ struct FwdTerm {
 
 struct FwdArgs {
     const RayConst* consts;
+    AngleSplit split;
     int n, na, nd;
     int nterms;
     FwdTerm term[IMASK_MAX_LEVELS];
@@ -127,6 +148,7 @@ struct BpOwnArgs {
 
 struct BpArgs {
     const RayConst* consts;
+    AngleSplit split;
     int n, na, nd, lvl;
     const float* y;
     float* out;

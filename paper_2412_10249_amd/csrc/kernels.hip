@@ -21,7 +21,13 @@ namespace imk {
 
 namespace {
 
+// Default angles a*pi/na step along rows iff 4a <= na or 4a >= 3na; listed
+// angles carry the host's choice (|cos| >= |sin|) in a table.
 __device__ __forceinline__ bool row_stepping(int a, int na) { return 4 * a <= na || 4 * a >= 3 * na; }
+__device__ __forceinline__ bool row_stepping(const AngleSplit& sp, int a, int na)
+{
+    return sp.rows ? sp.rows[a] != 0 : row_stepping(a, na);
+}
 
 constexpr float kTwoM32 = 2.3283064365386963e-10f;  // 2^-32
 
@@ -29,20 +35,24 @@ constexpr float kTwoM32 = 2.3283064365386963e-10f;  // 2^-32
 __device__ __forceinline__ int tap_index(long long u) { return (int)(u >> 32); }
 __device__ __forceinline__ float tap_weight(long long u) { return (float)(unsigned)(u & 0xffffffffLL) * kTwoM32; }
 
-__global__ void k_consts(int n, int na, int nd, double ds, double s0, int lmax, RayConst* out)
+// th / rows: listed angles (radians) and their stepping flags, or null for
+// a*pi/na; side = 2E, the side of the image square.
+__global__ void k_consts(int n, int na, int nd, double ds, double s0, double side, const double* th_tab,
+                         const int* rows_tab, int lmax, RayConst* out)
 {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (lmax + 1) * na) return;
     const int l = idx / na, a = idx - l * na;
-    const double th = (double)a * M_PI / (double)na;
+    const double th = th_tab ? th_tab[a] : (double)a * M_PI / (double)na;
+    const bool rows = rows_tab ? rows_tab[a] != 0 : row_stepping(a, na);
     const double c = cos(th), s = sin(th);
     const int nl = n >> l;
-    const double hl = 2.0 / nl;
+    const double hl = side / nl;
     const double half = 0.5 * (nl - 1), halfd = 0.5 * (nd - 1);
     // u(i, b) = A (i - half) + B (b - halfd) + C, the column (row) coordinate
     // of ray b where it crosses row (column) i, in pixels of level l.
     double A, B, C, W;
-    if (row_stepping(a, na)) {
+    if (rows) {
         A = -s / c;
         B = ds / (hl * c);
         C = s0 / (hl * c) + half;
@@ -171,6 +181,7 @@ __global__ void __launch_bounds__(256) k_prep(PrepArgs a)
 
 __device__ __forceinline__ int angle_of(const AngleSplit& sp, int pass, int k)
 {
+    if (sp.perm) return sp.perm[pass == 0 ? k : sp.nrow + k];
     return pass == 0 ? (k < sp.n_lo ? k : sp.a_hi0 + (k - sp.n_lo)) : sp.n_lo + k;
 }
 
@@ -346,7 +357,7 @@ __global__ void __launch_bounds__(256) k_fwd_direct(FwdBandArgs a)
     const int nl = a.n >> a.lvl;
     const int P = nl + kPad;
     const RayConst& kc = a.consts[(size_t)a.lvl * a.na + ang];
-    const float* img = row_stepping(ang, a.na) ? a.img : a.imgT;
+    const float* img = row_stepping(a.split, ang, a.na) ? a.img : a.imgT;
     int lo, hi;
     ray_steps(kc, (float)b, nl, 0, nl - 1, lo, hi);
     float acc = 0.0f;
@@ -1048,10 +1059,13 @@ int tile_side(int n, int lmax)
 
 hipError_t launch_consts(const imask_geometry& g, const Layout& L, float* work, hipStream_t s)
 {
-    const double ds = g.det_spacing > 0 ? g.det_spacing : 2.0 / g.n;
+    const double side = 2.0 * (g.extent > 0 ? g.extent : 1.0);
+    const double ds = g.det_spacing > 0 ? g.det_spacing : side / g.n;
     const int count = (L.lmax + 1) * g.n_angles;
+    const AngleSplit sp = split_at(L, work);
+    const double* th = L.listed ? (const double*)(work + L.angtab) : nullptr;
     hipLaunchKernelGGL(k_consts, dim3((count + 255) / 256), dim3(256), 0, s, g.n, g.n_angles, g.n_det, ds,
-                       g.det_offset, L.lmax, (RayConst*)(work + L.consts));
+                       g.det_offset, side, th, sp.rows, L.lmax, (RayConst*)(work + L.consts));
     return hipGetLastError();
 }
 
@@ -1104,7 +1118,7 @@ static hipError_t allow_lds(const void* fn, int bytes)
 
 hipError_t launch_fwd_terms(const FwdArgs& a, hipStream_t s)
 {
-    const AngleSplit sp = angle_split(a.na);
+    const AngleSplit sp = a.split;
     for (int t = 0; t < a.nterms; ++t) {
         const FwdTerm& tm = a.term[t];
         FwdBandArgs fb{};
@@ -1190,7 +1204,7 @@ hipError_t launch_bp_main(const BpArgs& ba, hipStream_t s, BpOwnArgs& a)
     a.lvl = ba.lvl;
     a.y = ba.y;
     a.part = ba.part;
-    a.split = angle_split(ba.na);
+    a.split = ba.split;
     a.out = ba.out;
     a.coef = ba.coef;
     a.accumulate = ba.accumulate;

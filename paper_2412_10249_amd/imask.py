@@ -35,16 +35,29 @@ def _need(t: torch.Tensor, shape, name: str) -> None:
 
 @dataclass(frozen=True)
 class Geometry:
-    """Parallel-beam geometry: N x N image on [-1,1]^2, n_angles angles
-    a*pi/n_angles, n_det bins (spacing <= 0: full-resolution pixel size)."""
+    """Parallel-beam geometry: N x N image on [-E,E]^2 (E = extent), n_angles
+    angles a*pi/n_angles or the listed ones (radians), n_det bins (spacing
+    <= 0: full-resolution pixel size 2E/N)."""
     n: int
     n_angles: int
     n_det: int
     det_spacing: float = 0.0
     det_offset: float = 0.0
+    extent: float = 1.0
+    angles: tuple = None
+
+    def __post_init__(self):
+        if self.angles is not None:
+            a = tuple(float(t) for t in self.angles)
+            if len(a) != self.n_angles:
+                raise ImaskError(f"{len(a)} angles listed for n_angles = {self.n_angles}")
+            object.__setattr__(self, "angles", a)
+            object.__setattr__(self, "_carr", (ctypes.c_double * len(a))(*a))
 
     def c(self) -> _abi.Geometry:
-        return _abi.Geometry(self.n, self.n_angles, self.n_det, self.det_spacing, self.det_offset)
+        # the struct points into this object's angle array: keep self alive
+        ang = ctypes.cast(self._carr, ctypes.POINTER(ctypes.c_double)) if self.angles is not None else None
+        return _abi.Geometry(self.n, self.n_angles, self.n_det, self.det_spacing, self.det_offset, self.extent, ang)
 
     @property
     def sino_shape(self):

@@ -30,7 +30,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_struct_sizes_match_c_layout():
-    assert ctypes.sizeof(_abi.Geometry) == 32
+    assert ctypes.sizeof(_abi.Geometry) == 4 * 3 + 4 + 8 * 3 + 8
     assert ctypes.sizeof(_abi.Levels) == 4 + 32 + 4 + 64 + 4 + 4
     assert ctypes.sizeof(_abi.Params) == 8 + 8 + 4 + 4 + 8 + 4 + 4
     assert ctypes.sizeof(_abi.State) == 8 * 7 + 8 + 8 + 8 + 8 + 16 + 8
@@ -50,6 +50,21 @@ def test_invalid_geometry_rejected_before_any_launch(geom):
     rc = _abi.lib().imask_project(ctypes.byref(g), 0, ctypes.c_void_p(16), ctypes.c_void_p(16),
                                   ctypes.c_void_p(16), None)
     assert rc == _abi.EINVAL
+
+
+def test_listed_angles_and_extent_validated():
+    L = _abi.lib()
+    good = im.Geometry(64, 5, 92, extent=2.0, angles=(0.1, 1.0, 2.0, 4.0, -7.5))
+    g0 = _abi.Geometry(64, 5, 92, 0.0, 0.0)
+    assert L.imask_workspace_bytes(ctypes.byref(good.c())) == L.imask_workspace_bytes(ctypes.byref(g0)) > 0
+    for bad in [im.Geometry(64, 3, 92, angles=(0.1, float("nan"), 0.2)),
+                im.Geometry(64, 3, 92, angles=(0.1, float("inf"), 0.2)),
+                im.Geometry(64, 3, 92, extent=float("nan"))]:
+        gc = bad.c()
+        assert L.imask_workspace_bytes(ctypes.byref(gc)) == 0
+        assert L.imask_prepare(ctypes.byref(gc), ctypes.c_void_p(16), 1 << 30, None) == _abi.EINVAL
+    with pytest.raises(_abi.ImaskError):
+        im.Geometry(64, 3, 92, angles=(0.1, 0.2))
 
 
 @pytest.mark.parametrize("bad", [

@@ -48,7 +48,8 @@ enum {
     IMASK_EINVAL = -1,  /* bad size, pointer, level set or parameter */
     IMASK_ENOTSUP = -2, /* valid but unsupported combination */
     IMASK_EHIP = -3,    /* a HIP launch failed */
-    IMASK_ESIZE = -4    /* workspace too small */
+    IMASK_ESIZE = -4,   /* workspace too small */
+    IMASK_ENONFINITE = -5 /* opt-in check: an iterate holds a NaN or infinity */
 };
 
 enum { IMASK_FULL_PAPER = 0, IMASK_FULL_UNBIASED = 1 };
@@ -143,7 +144,11 @@ typedef struct {
  *                          independent index from stream dual_stream_id;
  *                          an iteration then costs (c(i) + c(j)) / 2 epochs.
  *                          Parallel schedule with full tables only
- *                          (IMASK_ENOTSUP otherwise) */
+ *                          (IMASK_ENOTSUP otherwise)
+ * check_finite (opt-in): nonzero makes imask_step / imask_solve test x and y
+ * of this problem for NaN or infinity once, after its last step; the test
+ * synchronises `stream` and the call then returns IMASK_ENONFINITE if one
+ * is found (the steps have still been applied).  Zero: no test, no sync. */
 typedef struct {
     double sigma;
     uint64_t seed;
@@ -152,6 +157,8 @@ typedef struct {
     double theta;
     int32_t draw_mode;
     uint32_t dual_stream_id;
+    int32_t check_finite;
+    int32_t reserved; /* must be 0 */
 } imask_params;
 
 /* ImaSk state (Alg. 1): iterates, gradient tables and counters.

@@ -15,7 +15,7 @@ MAX_LEVELS = 8
 MAX_LOG2F = 6
 MAX_TV_INNER = 12
 
-OK, EINVAL, ENOTSUP, EHIP, ESIZE = 0, -1, -2, -3, -4
+OK, EINVAL, ENOTSUP, EHIP, ESIZE, ENONFINITE = 0, -1, -2, -3, -4, -5
 FULL_PAPER, FULL_UNBIASED = 0, 1
 REG_TIKHONOV, REG_SMOOTH_TV, REG_TV = 0, 1, 2
 RESTRICT, PROLONG, RESTRICT_ADJ, PROJECT, COMPENSATE = 0, 1, 2, 3, 4
@@ -49,7 +49,7 @@ class Reg(ctypes.Structure):
 class Params(ctypes.Structure):
     _fields_ = [("sigma", ctypes.c_double), ("seed", ctypes.c_uint64), ("stream_id", ctypes.c_uint32),
                 ("schedule", ctypes.c_int32), ("theta", ctypes.c_double), ("draw_mode", ctypes.c_int32),
-                ("dual_stream_id", ctypes.c_uint32)]
+                ("dual_stream_id", ctypes.c_uint32), ("check_finite", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class State(ctypes.Structure):
@@ -104,5 +104,5 @@ def lib():
 
 def check(rc: int, what: str) -> None:
     if rc != OK:
-        names = {EINVAL: "EINVAL", ENOTSUP: "ENOTSUP", EHIP: "EHIP", ESIZE: "ESIZE"}
+        names = {EINVAL: "EINVAL", ENOTSUP: "ENOTSUP", EHIP: "EHIP", ESIZE: "ESIZE", ENONFINITE: "ENONFINITE"}
         raise ImaskError(f"{what} failed: {names.get(rc, rc)}")

@@ -83,6 +83,8 @@ Layout make_layout(const imask_geometry& g)
     }
     L.angtab = off;
     off = align64(off + 4 * (size_t)g.n_angles);
+    L.flag = off;
+    off = align64(off + 1);
     if (g.angles) {
         L.listed = 1;
         L.split = AngleSplit{};
@@ -864,7 +866,7 @@ static int check_problem(const imask_geometry* g, const imask_levels* lv, const 
     if (!geometry_ok(g)) return IMASK_EINVAL;
     const int lmax = level_limit(g->n);
     if (!levels_ok(lv, lmax) || !reg_ok(reg) || !prm || !b || !state_ok(s)) return IMASK_EINVAL;
-    if (!(prm->sigma > 0.0) || !std::isfinite(prm->sigma)) return IMASK_EINVAL;
+    if (!(prm->sigma > 0.0) || !std::isfinite(prm->sigma) || prm->reserved != 0) return IMASK_EINVAL;
     if (reg->kind == IMASK_REG_TV && (!s->tvd[0] || !s->tvd[1] || s->tvd[0] == s->tvd[1])) return IMASK_EINVAL;
     if (s->ztab) {
         if (s->ztab == s->phi || s->ztab == s->psi || s->ztab == s->x[0] || s->ztab == s->x[1]) return IMASK_EINVAL;
@@ -884,6 +886,29 @@ static int check_problem(const imask_geometry* g, const imask_levels* lv, const 
     return IMASK_OK;
 }
 
+// The opt-in finiteness test of x and y after a call's last step (one
+// synchronisation for all problems that ask for it).
+static int check_finite_after(int n_problems, const imask_geometry* g, const imask_params* prm,
+                              const imask_state* s, hipStream_t st)
+{
+    std::vector<int> flags(n_problems, 0);
+    bool any = false;
+    for (int q = 0; q < n_problems; ++q) {
+        if (!prm[q].check_finite) continue;
+        const Layout L = make_layout(g[q]);
+        int* flag = (int*)((float*)s[q].work + L.flag);
+        IMK_TRY(launch_nonfinite(s[q].x[s[q].cur], (size_t)g[q].n * g[q].n, s[q].y[s[q].cur],
+                                 (size_t)g[q].n_angles * g[q].n_det, flag, st));
+        if (hipMemcpyAsync(&flags[q], flag, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess) return IMASK_EHIP;
+        any = true;
+    }
+    if (!any) return IMASK_OK;
+    if (hipStreamSynchronize(st) != hipSuccess) return IMASK_EHIP;
+    for (int q = 0; q < n_problems; ++q)
+        if (flags[q]) return IMASK_ENONFINITE;
+    return IMASK_OK;
+}
+
 int imask_step(int32_t n_problems, const imask_geometry* g, const imask_levels* lv, const imask_reg* reg,
                const imask_params* prm, const float* const* b, imask_state* s, int32_t n_steps, void* stream)
 {
@@ -897,7 +922,7 @@ int imask_step(int32_t n_problems, const imask_geometry* g, const imask_levels* 
             const Layout L = make_layout(g[q]);
             if (int rc = one_step(g[q], L, lv[q], reg[q], prm[q], b[q], s[q], st)) return rc;
         }
-    return IMASK_OK;
+    return check_finite_after(n_problems, g, prm, s, st);
 }
 
 int imask_solve(int32_t n_problems, const imask_geometry* g, const imask_levels* lv, const imask_reg* reg,
@@ -922,7 +947,7 @@ int imask_solve(int32_t n_problems, const imask_geometry* g, const imask_levels*
             if (int rc = one_step(g[q], L, lv[q], reg[q], prm[q], b[q], s[q], st)) return rc;
         }
     }
-    return IMASK_OK;
+    return check_finite_after(n_problems, g, prm, s, st);
 }
 
 }  // extern "C"

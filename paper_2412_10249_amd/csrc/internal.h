@@ -72,6 +72,7 @@ struct Layout {
     int frows[IMASK_MAX_LOG2F + 1] = {};   // rows per band (0: direct kernel, one band)
     // listed angles: na doubles (radians), then perm and rows (na int32 each)
     size_t angtab = 0;
+    size_t flag = 0;                       // int flag of the finiteness check
     int listed = 0;
     AngleSplit split{};                    // perm / rows unset: see split_at
     size_t total = 0;
@@ -217,6 +218,8 @@ void fwd_bands(int nl, int* bands, int* rows);
 // ---- launchers (return hipError_t of the launch) ----
 hipError_t launch_consts(const imask_geometry& g, const Layout& L, float* work, hipStream_t s);
 hipError_t launch_fill(float* p, size_t count, float value, hipStream_t s);
+// *flag = 1 if a[0..na) or b[0..nb) holds a NaN or an infinity, else 0
+hipError_t launch_nonfinite(const float* a, size_t na, const float* b, size_t nb, int* flag, hipStream_t s);
 hipError_t launch_prep(const PrepArgs& a, hipStream_t s);
 hipError_t launch_fwd(const FwdArgs& a, hipStream_t s);        // projector kernels + reduce/epilogue
 hipError_t launch_fwd_terms(const FwdArgs& a, hipStream_t s);  // projector kernels only

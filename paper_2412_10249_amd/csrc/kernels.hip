@@ -1069,6 +1069,27 @@ hipError_t launch_consts(const imask_geometry& g, const Layout& L, float* work, 
     return hipGetLastError();
 }
 
+// flag = 1 if any of a[0..na) or b[0..nb) is a NaN or an infinity (all
+// exponent bits set); flag is cleared beforehand by the caller.
+__global__ void k_nonfinite(const float* a, size_t na, const float* b, size_t nb, int* flag)
+{
+    const size_t i0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    bool bad = false;
+    for (size_t q = i0; q < na; q += stride) bad |= (__float_as_uint(a[q]) & 0x7f800000u) == 0x7f800000u;
+    for (size_t q = i0; q < nb; q += stride) bad |= (__float_as_uint(b[q]) & 0x7f800000u) == 0x7f800000u;
+    if (bad) flag[0] = 1;
+}
+
+hipError_t launch_nonfinite(const float* a, size_t na, const float* b, size_t nb, int* flag, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, s, (float*)flag, (size_t)1, 0.0f);
+    const size_t n = std::max(na, nb);
+    const unsigned blocks = (unsigned)std::max<size_t>(1, std::min<size_t>((n + 255) / 256, 2048));
+    hipLaunchKernelGGL(k_nonfinite, dim3(blocks), dim3(256), 0, s, a, na, b, nb, flag);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill(float* p, size_t count, float value, hipStream_t s)
 {
     size_t blocks = (count + 255) / 256;

@@ -111,7 +111,8 @@ class Params:
     """Step size, draw stream, the schedule (Alg. 1's parallel update or the
     ImaSk-Seq variant of Sec. 5 with extrapolation theta) and the draw mode
     (one index per iteration, or independent primal/dual indices with the
-    dual one from dual_stream_id)."""
+    dual one from dual_stream_id).  check_finite: after each call, test x and
+    y for NaN/infinity (one synchronisation) and raise ImaskError if found."""
     sigma: float
     seed: int = 42
     stream_id: int = 0
@@ -119,10 +120,11 @@ class Params:
     theta: float = 1.0
     draw_mode: int = _abi.DRAW_COMMON
     dual_stream_id: int = 0
+    check_finite: bool = False
 
     def c(self) -> _abi.Params:
         return _abi.Params(self.sigma, self.seed, self.stream_id, self.schedule, self.theta, self.draw_mode,
-                           self.dual_stream_id)
+                           self.dual_stream_id, int(bool(self.check_finite)), 0)
 
 
 def workspace(g: Geometry, device="cuda") -> torch.Tensor:
@@ -305,18 +307,20 @@ class Problem:
     def step(self, n_steps: int = 1) -> None:
         s = self._cstate()
         bp = (ctypes.c_void_p * 1)(self.b.data_ptr())
-        check(lib().imask_step(1, ctypes.byref(self.geom.c()), ctypes.byref(self.levels.c()),
-                               ctypes.byref(self.reg.c()), ctypes.byref(self.params.c()), bp,
-                               ctypes.byref(s), n_steps, _stream()), "imask_step")
-        self._absorb(s)
+        rc = lib().imask_step(1, ctypes.byref(self.geom.c()), ctypes.byref(self.levels.c()),
+                              ctypes.byref(self.reg.c()), ctypes.byref(self.params.c()), bp,
+                              ctypes.byref(s), n_steps, _stream())
+        self._absorb(s)  # steps taken before an error (ENONFINITE) are kept
+        check(rc, "imask_step")
 
     def solve(self, budget: float, kind: int = _abi.BUDGET_ITERS) -> None:
         s = self._cstate()
         bp = (ctypes.c_void_p * 1)(self.b.data_ptr())
-        check(lib().imask_solve(1, ctypes.byref(self.geom.c()), ctypes.byref(self.levels.c()),
-                                ctypes.byref(self.reg.c()), ctypes.byref(self.params.c()), bp,
-                                ctypes.byref(s), float(budget), kind, _stream()), "imask_solve")
+        rc = lib().imask_solve(1, ctypes.byref(self.geom.c()), ctypes.byref(self.levels.c()),
+                               ctypes.byref(self.reg.c()), ctypes.byref(self.params.c()), bp,
+                               ctypes.byref(s), float(budget), kind, _stream())
         self._absorb(s)
+        check(rc, "imask_solve")
 
     def phi_tables(self):
         """The table as a list of images: sketch 0 full size, k > 0 coarse."""
@@ -364,6 +368,7 @@ def step_many(problems: list, n_steps: int = 1) -> None:
     P = (_abi.Params * n)(*[p.params.c() for p in problems])
     B = (ctypes.c_void_p * n)(*[p.b.data_ptr() for p in problems])
     S = (_abi.State * n)(*[p._cstate() for p in problems])
-    check(lib().imask_step(n, G, L, R, P, B, S, n_steps, _stream()), "imask_step")
+    rc = lib().imask_step(n, G, L, R, P, B, S, n_steps, _stream())
     for p, s in zip(problems, S):
         p._absorb(s)
+    check(rc, "imask_step")

@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
 def test_struct_sizes_match_c_layout():
     assert ctypes.sizeof(_abi.Geometry) == 4 * 3 + 4 + 8 * 3 + 8
     assert ctypes.sizeof(_abi.Levels) == 4 + 32 + 4 + 64 + 4 + 4
-    assert ctypes.sizeof(_abi.Params) == 8 + 8 + 4 + 4 + 8 + 4 + 4
+    assert ctypes.sizeof(_abi.Params) == 8 + 8 + 4 + 4 + 8 + 4 + 4 + 4 + 4
     assert ctypes.sizeof(_abi.State) == 8 * 7 + 8 + 8 + 8 + 8 + 16 + 8
 
 
@@ -98,6 +98,9 @@ def test_invalid_step_arguments_rejected():
     assert _abi.lib().imask_step(1, ctypes.byref(g), ctypes.byref(lv), ctypes.byref(tv), ctypes.byref(prm),
                                  b, ctypes.byref(s), 1, None) == _abi.EINVAL
     bad_prm = _abi.Params(-0.5, 1, 0)
+    assert _abi.lib().imask_step(1, ctypes.byref(g), ctypes.byref(lv), ctypes.byref(reg), ctypes.byref(bad_prm),
+                                 b, ctypes.byref(s), 1, None) == _abi.EINVAL
+    bad_prm = _abi.Params(0.01, 1, 0, _abi.SCHEDULE_PARALLEL, 1.0, _abi.DRAW_COMMON, 0, 1, 3)  # reserved != 0
     assert _abi.lib().imask_step(1, ctypes.byref(g), ctypes.byref(lv), ctypes.byref(reg), ctypes.byref(bad_prm),
                                  b, ctypes.byref(s), 1, None) == _abi.EINVAL
     assert _abi.lib().imask_solve(1, ctypes.byref(g), ctypes.byref(lv), ctypes.byref(reg), ctypes.byref(prm),

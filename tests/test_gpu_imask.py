@@ -180,3 +180,23 @@ def test_steps_on_a_4096_grid():
     assert rel(host(prob.x_cur), ost.x) <= 1e-4
     assert rel(host(prob.y_cur), ost.y) <= 1e-4
 
+
+
+def test_finite_check_is_opt_in():
+    """check_finite reports a NaN that reached y (through b) as ENONFINITE;
+    without the flag the same call succeeds, and a clean run passes the check."""
+    n, na, nd = 32, 20, 40
+    b = f32(synth.random_sinogram(na, nd, 3))
+    geom, lv, reg = pk.Geometry(n, na, nd), pk.Levels.uniform((0, 1)), pk.Regularizer(pk.REG_TIKHONOV, 0.5)
+    clean = pk.Problem(geom, lv, reg, pk.Params(0.02, check_finite=True), dev(b))
+    clean.step(3)
+    clean.solve(1.0, pk.BUDGET_EPOCHS)
+    bad = b.copy()
+    bad[4, 7] = np.nan
+    quiet = pk.Problem(geom, lv, reg, pk.Params(0.02), dev(bad))
+    quiet.step(2)
+    assert not np.isfinite(host(quiet.y_cur)).all()
+    loud = pk.Problem(geom, lv, reg, pk.Params(0.02, check_finite=True), dev(bad))
+    with pytest.raises(pk.ImaskError, match="ENONFINITE"):
+        loud.step(2)
+    assert loud.k == 2  # the steps were applied before the check

@@ -79,7 +79,9 @@ enum { IMASK_BUDGET_ITERS = 0, IMASK_BUDGET_EPOCHS = 1 };
  * default angles step along rows iff 4a <= n_angles or 4a >= 3 n_angles.
  * Invalid (EINVAL): n outside 4..16384,
  * not a multiple of 4, or above 16 not a multiple of 16; n_angles or n_det
- * out of range; a non-finite spacing, offset, extent or listed angle. */
+ * out of range; a non-finite spacing, offset, extent or listed angle; an
+ * extent outside [1e-100, 1e100]; a positive spacing outside [1/64, 64]
+ * full-resolution pixels; |det_offset| > 4E. */
 typedef struct {
     int32_t n;            /* full-resolution image side N */
     int32_t n_angles;     /* 1 .. 65536 */

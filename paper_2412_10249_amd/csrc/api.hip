@@ -106,6 +106,13 @@ static bool geometry_ok(const imask_geometry* g)
     if (g->n > 16 && (g->n % 16) != 0) return false;
     if (g->n_angles < 1 || g->n_det < 1 || g->n_angles > 65536 || g->n_det > 8192) return false;
     if (!std::isfinite(g->det_spacing) || !std::isfinite(g->det_offset) || !std::isfinite(g->extent)) return false;
+    // bounds that keep every fixed-point coordinate far inside what the FP32
+    // range estimates resolve (the rows' zero padding absorbs their error)
+    const double E = g->extent > 0 ? g->extent : 1.0;
+    if (E < 1e-100 || E > 1e100) return false;
+    const double h = 2.0 * E / g->n;
+    if (g->det_spacing > 0 && (g->det_spacing < h / 64 || g->det_spacing > 64 * h)) return false;
+    if (std::fabs(g->det_offset) > 4 * E) return false;
     if (g->angles)
         for (int a = 0; a < g->n_angles; ++a)
             if (!std::isfinite(g->angles[a])) return false;

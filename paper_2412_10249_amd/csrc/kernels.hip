@@ -511,6 +511,81 @@ __device__ __forceinline__ float buffer_float(__amdgpu_buffer_rsrc_t r, int byte
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, byte_offset, 0, 0));
 }
 
+#ifndef IMK_BP_RUNS_MIN_P
+#define IMK_BP_RUNS_MIN_P 3
+#endif
+// Angles whose rays are at least this many bins per pixel apart take runs.
+constexpr int kBpRunsMinP = IMK_BP_RUNS_MIN_P;
+
+// Run form of the scatter, for angles with `phases` P >= kBpRunsMinP (coarse
+// levels, where neighbouring rays are less than a pixel apart).  Lane k
+// takes the P consecutive bins that start P k bins into the trip: together
+// they span less than one pixel ((P-1)|B| < 1 exactly, in the fixed-point
+// coordinate), so on each row their taps fall in three cells base..base+2.
+// The lane sums its contributions to those cells in registers and adds them
+// to LDS in three read-modify-write phases; bases of different lanes are at
+// least a pixel apart, so no two lanes share a cell in a phase.  A run costs
+// three LDS updates per row instead of 2P.  Lanes past the bin range read
+// zero sinogram values and have their base clamped (as an unsigned number)
+// to S-3, the last three cells of the row.  One chunk of 64 runs per trip
+// keeps the lanes busy when a range holds few runs.
+template <int R>
+__device__ __forceinline__ void scatter_runs(float* rows, int S, long long urow, long long afx, long long bfx,
+                                             int blo, int cnt, int P, float kw, __amdgpu_buffer_rsrc_t yr,
+                                             int lane)
+{
+    const int shift = bfx < 0 ? 1 : 0;  // a falling coordinate: the window starts one cell lower
+    for (int c0 = 0; c0 < cnt; c0 += 64 * P) {
+        long long U[R];
+        unsigned hi0[R];
+        int cl[R];
+        float v0[R], v1[R], v2[R];
+        const long long u0 = urow + (long long)(blo + c0 + lane * P) * bfx;
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr) {
+            U[rr] = u0 + rr * afx;
+            hi0[rr] = (unsigned)(U[rr] >> 32);
+            cl[rr] = rr * S + (int)min(hi0[rr] - (unsigned)shift, (unsigned)(S - 3));
+            v0[rr] = v1[rr] = v2[rr] = 0.0f;
+        }
+        const int yb = (c0 + lane * P) * 4;
+        float ynext = buffer_float(yr, yb);
+        for (int t = 0; t < P; ++t) {
+            const float wy = kw * ynext;
+            const float wys = wy * kTwoM32;
+            ynext = buffer_float(yr, yb + (t + 1) * 4);
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr) {
+                const unsigned hi = (unsigned)(U[rr] >> 32);
+                const float cu = (float)(unsigned)(U[rr] & 0xffffffffLL);
+                const float t0 = fmaf(cu, -kTwoM32, 1.0f) * wy;  // (1 - w) y, as in the forward
+                const float t1 = cu * wys;                       // w y
+                const bool up = hi - hi0[rr] + (unsigned)shift != 0u;  // taps at base+1, base+2
+                v0[rr] += up ? 0.0f : t0;
+                v1[rr] += up ? t0 : t1;
+                v2[rr] += up ? t1 : 0.0f;
+                U[rr] += bfx;
+            }
+        }
+        float old[R];
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr) old[rr] = rows[cl[rr]];
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr) rows[cl[rr]] = old[rr] + v0[rr];
+        IMK_LDS_ORDER();
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr) old[rr] = rows[cl[rr] + 1];
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr) rows[cl[rr] + 1] = old[rr] + v1[rr];
+        IMK_LDS_ORDER();
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr) old[rr] = rows[cl[rr] + 2];
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr) rows[cl[rr] + 2] = old[rr] + v2[rr];
+        IMK_LDS_ORDER();
+    }
+}
+
 // What a wavefront needs of one angle, tabulated in LDS by the workgroup.
 struct BpAngle {
     long long afx, bfx, cfx;  // fixed-point coordinate constants
@@ -584,6 +659,10 @@ __global__ void __launch_bounds__(64 * W) k_bp_own(BpOwnArgs a)
             const __amdgpu_buffer_rsrc_t yr = float_buffer(a.y + (size_t)ang * a.nd + blo, cnt);
             const int vb = lane * P * 4;
             const long long urow = cfx + (long long)r0 * afx + ((long long)kBpPad << 32);
+            if (kBpRunsMinP > 0 && P >= kBpRunsMinP) {
+                scatter_runs<R>(rows, S, urow, afx, bfx, blo, cnt, P, kw, yr, lane);
+                continue;
+            }
             const long long cstep = (long long)64 * P * bfx;
             const int tstride = kBpChunks * 64 * P;
             const int full_end = cnt - (kBpChunks * 64 - 1) * P;  // trips starting below this are full

@@ -65,6 +65,12 @@ def test_listed_angles_and_extent_validated():
         assert L.imask_prepare(ctypes.byref(gc), ctypes.c_void_p(16), 1 << 30, None) == _abi.EINVAL
     with pytest.raises(_abi.ImaskError):
         im.Geometry(64, 3, 92, angles=(0.1, 0.2))
+    # spacing within [1/64, 64] pixels of 2E/N, offset within 4E
+    pix = 2 * 2.0 / 64
+    for sp, off, ok in [(pix / 64, 0.0, True), (pix / 65, 0.0, False), (64 * pix, 0.0, True),
+                        (65 * pix, 0.0, False), (0.0, 8.0, True), (0.0, -8.01, False)]:
+        gc = im.Geometry(64, 3, 92, det_spacing=sp, det_offset=off, extent=2.0).c()
+        assert (L.imask_workspace_bytes(ctypes.byref(gc)) > 0) == ok, (sp, off)
 
 
 @pytest.mark.parametrize("bad", [

@@ -1,7 +1,8 @@
 """GPU parity of the projector pair and of Alg. 1 on listed angles (any real
 theta, any order) and a domain [-E, E]^2, against the FP64 oracle.
 
-Same bars as the default geometry: relative l2 <= 1e-5 for projections and
+Detector spacings and offsets other than the defaults ride along.  Same bars
+as the default geometry: relative l2 <= 1e-5 for projections and
 backprojections, an exact (bitwise) transpose on a tiny grid, 1e-4 for x and
 y after a run of Alg. 1; a listed copy of the default angles reproduces the
 default geometry bit for bit.
@@ -17,19 +18,21 @@ import paper_2412_10249_amd as pk
 
 pytestmark = pytest.mark.gpu
 
-# (n, n_det, angles, extent): full circle, limited angle, unsorted with
-# repeats and negative values, and a case spanning several forward bands
+# (n, n_det, angles, extent, spacing in pixels, offset / E): full circle,
+# limited angle, unsorted with repeats and negative values, and a case
+# spanning several forward bands; spacings and offsets off the defaults
 CASES = [
-    (64, 92, tuple(synth.angles_random(40, 1)), 2.3),
-    (48, 71, tuple(synth.angles_random(13, 2, 0.0, 2.0 * np.pi / 3)), 1.0),
-    (32, 50, (0.0, -0.3, 2.9, 0.0, 7.1, np.pi / 4, 3 * np.pi / 4, np.pi / 2), 0.6),
-    (256, 300, tuple(synth.angles_random(97, 3)), 1.7),
+    (64, 92, tuple(synth.angles_random(40, 1)), 2.3, 1.0, 0.0),
+    (48, 71, tuple(synth.angles_random(13, 2, 0.0, 2.0 * np.pi / 3)), 1.0, 0.7, 0.15),
+    (32, 50, (0.0, -0.3, 2.9, 0.0, 7.1, np.pi / 4, 3 * np.pi / 4, np.pi / 2), 0.6, 1.6, -0.4),
+    (256, 300, tuple(synth.angles_random(97, 3)), 1.7, 1.25, 0.05),
 ]
 
 
-def _geoms(n, nd, ang, E):
-    return (pk.Geometry(n, len(ang), nd, extent=E, angles=ang),
-            oracle.Geometry(n, len(ang), nd, extent=E, angles=ang))
+def _geoms(n, nd, ang, E, spacing_px=1.0, offset=0.0):
+    ds, s0 = spacing_px * 2.0 * E / n, offset * E
+    return (pk.Geometry(n, len(ang), nd, ds, s0, extent=E, angles=ang),
+            oracle.Geometry(n, len(ang), nd, ds, s0, extent=E, angles=ang))
 
 
 def _levels_for(n):
@@ -38,8 +41,8 @@ def _levels_for(n):
 
 @pytest.mark.parametrize("case", range(len(CASES)))
 def test_listed_project_and_backproject_match_oracle(case):
-    n, nd, ang, E = CASES[case]
-    g, og = _geoms(n, nd, ang, E)
+    n, nd, ang, E, sp, off = CASES[case]
+    g, og = _geoms(n, nd, ang, E, sp, off)
     work = pk.workspace(g)
     x = f32(synth.random_image(n, 10 + case))
     y = f32(synth.random_sinogram(len(ang), nd, 20 + case))

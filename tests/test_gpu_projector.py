@@ -72,9 +72,10 @@ def test_gpu_dot_product(geom):
         assert abs(lhs - rhs) <= 2e-6 * np.linalg.norm(ax) * np.linalg.norm(y), (l, lhs, rhs)
 
 
-@pytest.mark.parametrize("lvl", [0, 1, 2])
-def test_explicit_matrix_tiny(lvl):
-    n, na, nd = 8, 6, 12
+@pytest.mark.parametrize("n,lvl", [(8, 0), (8, 1), (8, 2), (16, 3)])
+def test_explicit_matrix_tiny(n, lvl):
+    # level 3 of a 16^2 grid has rays 6-8 bins per pixel: the transpose's run form
+    na, nd = 6, 12 * n // 8
     g = pk.Geometry(n, na, nd)
     og = oracle.Geometry(n, na, nd)
     work = pk.workspace(g)

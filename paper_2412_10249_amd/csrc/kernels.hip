@@ -726,6 +726,11 @@ __global__ void __launch_bounds__(64 * W) k_bp_own(BpOwnArgs a)
 // that every level keeps about 2^18 threads busy): a workgroup of 1024
 // threads takes 1024/S pixels, each thread sums one slice of one pixel in
 // partial order, and the slice sums are added in slice order.
+#ifndef IMK_BP_SUM_MAX_SLICES
+#define IMK_BP_SUM_MAX_SLICES 64
+#endif
+constexpr int kBpSumMaxSlices = IMK_BP_SUM_MAX_SLICES;  // <= 1024, a power of two
+
 __global__ void __launch_bounds__(1024) k_bp_sum(BpOwnArgs a, float* tmp, int S)
 {
     __shared__ float red[1024];
@@ -1327,8 +1332,8 @@ hipError_t launch_bp(const BpArgs& ba, hipStream_t s)
     if (e != hipSuccess) return e;
     const int nl = ba.n >> ba.lvl;
     const size_t d = (size_t)nl * nl;
-    int S = 1;  // slices: about 2^18 threads, at most 16, at most nq
-    while (S < 16 && S < a.nq && d * (size_t)S < ((size_t)1 << 18)) S *= 2;
+    int S = 1;  // slices: about 2^18 threads, at most kBpSumMaxSlices, at most nq
+    while (S < kBpSumMaxSlices && S < a.nq && d * (size_t)S < ((size_t)1 << 18)) S *= 2;
     const size_t per = 1024 / S;
     hipLaunchKernelGGL(k_bp_sum, dim3((unsigned)((d + per - 1) / per)), dim3(1024), 0, s, a, ba.tmp, S);
     e = hipGetLastError();

@@ -250,8 +250,8 @@ static void fwd_common(const Layout& L, const float* W, FwdArgs& fa)
     fa.nd = L.nd;
 }
 
-static int backproject_raw(const Layout& L, const float* W, int lvl, const float* y, float* out, float coef,
-                           int accumulate, int prolong, hipStream_t s)
+static BpArgs bp_args(const Layout& L, const float* W, int lvl, const float* y, float* out, float coef,
+                      int accumulate, int prolong)
 {
     BpArgs ba{};
     ba.consts = (const RayConst*)(W + L.consts);
@@ -267,7 +267,13 @@ static int backproject_raw(const Layout& L, const float* W, int lvl, const float
     ba.prolong = prolong;
     ba.part = const_cast<float*>(W) + L.part;
     ba.tmp = const_cast<float*>(W) + L.ptmp;
-    IMK_TRY(launch_bp(ba, s));
+    return ba;
+}
+
+static int backproject_raw(const Layout& L, const float* W, int lvl, const float* y, float* out, float coef,
+                           int accumulate, int prolong, hipStream_t s)
+{
+    IMK_TRY(launch_bp(bp_args(L, W, lvl, y, out, coef, accumulate, prolong), s));
     return IMASK_OK;
 }
 
@@ -338,19 +344,6 @@ static int one_step(const imask_geometry& g, const Layout& L, const imask_levels
     IMK_TRY(launch_prep(pa, s));
     IMK_TRY(launch_fwd(fa, s));
 
-    // a5: raw backprojections R_l^T y needed by sketch k
-    if (k > 0) {
-        const int l = lv.log2f[k];
-        if (int rc = backproject_raw(L, W, l, y_bp, W + L.craw[l], 1.0f, 0, 0, s)) return rc;
-    } else {
-        if (int rc = backproject_raw(L, W, 0, y_bp, W + L.craw[0], 1.0f, 0, 0, s)) return rc;
-        if (lv.full_mode == IMASK_FULL_UNBIASED)
-            for (int j = 1; j < lv.r; ++j) {
-                const int l = lv.log2f[j];
-                if (int rc = backproject_raw(L, W, l, y_bp, W + L.craw[l], 1.0f, 0, 0, s)) return rc;
-            }
-    }
-
     // a6-a7: prolongation / compensation, primal SAGA step, phi refresh
     const double tau = prm.sigma / reg.lambda;
     const bool tv = reg.kind != IMASK_REG_TIKHONOV;  // the prox runs in its own kernel
@@ -376,7 +369,21 @@ static int one_step(const imask_geometry& g, const Layout& L, const imask_levels
     // whichever kernel writes x^{k+1}
     pr.xbar = seq && !tv ? st.xbar : nullptr;
     pr.theta = (float)prm.theta;
-    IMK_TRY(launch_primal(pr, s));
+    // a5: raw backprojections R_l^T y needed by sketch k.  A sketch that
+    // needs one (coarse, or the only level) takes the primal step in the
+    // epilogue of that backprojection's ordered sum.
+    if (k > 0 || lv.r == 1) {
+        const int l = lv.log2f[k];
+        IMK_TRY(launch_bp_primal(bp_args(L, W, l, y_bp, W + L.craw[l], 1.0f, 0, 0), pr, s));
+    } else {
+        if (int rc = backproject_raw(L, W, 0, y_bp, W + L.craw[0], 1.0f, 0, 0, s)) return rc;
+        if (lv.full_mode == IMASK_FULL_UNBIASED)
+            for (int j = 1; j < lv.r; ++j) {
+                const int l = lv.log2f[j];
+                if (int rc = backproject_raw(L, W, l, y_bp, W + L.craw[l], 1.0f, 0, 0, s)) return rc;
+            }
+        IMK_TRY(launch_primal(pr, s));
+    }
 
     // a8: the paper's TV prior: dual FGP from the kept dual pair at
     // v / (1 + tau lam) with weight tau w / (1 + tau lam)

@@ -226,6 +226,9 @@ hipError_t launch_fwd_terms(const FwdArgs& a, hipStream_t s);  // projector kern
 hipError_t launch_bp(const BpArgs& a, hipStream_t s);          // transpose kernel + ordered sum
 hipError_t launch_bp_main(const BpArgs& a, hipStream_t s, BpOwnArgs& used);  // transpose kernel only
 hipError_t launch_primal(const PrimalArgs& a, hipStream_t s);
+// Transpose at level ba.lvl, its ordered partial sum and the primal step in
+// one epilogue kernel (steps whose sketch needs a single backprojection).
+hipError_t launch_bp_primal(const BpArgs& ba, const PrimalArgs& pr, hipStream_t s);
 hipError_t launch_tv(const TvArgs& a, hipStream_t s);
 
 // Prox of gamma TV + nonnegativity at v / scale by J dual FGP iterations.

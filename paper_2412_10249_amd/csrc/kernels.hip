@@ -758,6 +758,77 @@ __global__ void __launch_bounds__(1024) k_bp_sum(BpOwnArgs a, float* tmp, int S)
     }
 }
 
+// The ordered partial sum fused with the primal step of Alg. 1, for steps
+// whose sketch needs one backprojection (a coarse sketch k > 0, or a single
+// level): workgroup w sums its 1024/S cells c of the level-l raw
+// backprojection exactly as k_bp_sum does, forms g = 4^{-l} c, reads the old
+// phi_k of its cells into LDS and refreshes them with g, then updates every
+// full-resolution pixel of its cells as k_primal does (xi = (g - phi_k) +
+// sum_j p_j phi_j with the old tables; x+ = (x - tau xi) * prox_scale, and
+// xbar).  A cell's pixels and its phi_k entry belong to one workgroup, so
+// the old table values it reads are never overwritten by another.
+__global__ void __launch_bounds__(1024) k_bp_sum_primal(BpOwnArgs a, int S, PrimalArgs p)
+{
+    __shared__ float red[1024];
+    __shared__ float gsh[1024], own[1024];
+    const int l = a.lvl;
+    const int nl = a.n >> l;
+    const size_t d = (size_t)nl * nl;
+    const int per = 1024 / S;  // cells per workgroup
+    const int sl = threadIdx.x / per;
+    const int pi = threadIdx.x - sl * per;
+    const size_t e0 = (size_t)blockIdx.x * per;
+    const size_t e = e0 + pi;
+    const int q0 = sl * a.nq / S, q1 = (sl + 1) * a.nq / S;
+    float sum = 0.0f;
+    if (e < d)
+        for (int q = q0; q < q1; ++q) sum += a.part[q * d + e];
+    red[threadIdx.x] = sum;
+    __syncthreads();
+    const long long koff = p.phi_off[p.kidx];
+    if (sl == 0 && e < d) {
+        float c = red[pi];
+        for (int k = 1; k < S; ++k) c += red[k * per + pi];
+        const float g = (a.coef * c) * (1.0f / (float)(1 << (2 * l)));
+        gsh[pi] = g;
+        own[pi] = p.phi[koff + e];
+        p.phi[koff + e] = g;  // phi_k refresh
+    }
+    __syncthreads();
+    // the cells' pixels: 2^l rows of 2^l pixels per cell, cells in order
+    const int L2 = 1 << l;
+    const int ncell = (int)min((size_t)per, d - min(d, e0));
+    for (int q = threadIdx.x; q < ncell * L2 * L2; q += blockDim.x) {
+        const int fr = q / (ncell * L2), rem = q - fr * (ncell * L2);
+        const int c = rem >> l, fc = rem - (c << l);
+        const size_t ec = e0 + c;
+        const int ci = (int)(ec / nl), cj = (int)(ec - (size_t)ci * nl);
+        const int i = ci * L2 + fr, j = cj * L2 + fc;
+        const size_t pix = (size_t)i * p.n + j;
+        const float g = gsh[c];
+        float avg = 0.0f, ownv = 0.0f;
+        for (int cc = 0; cc < p.r; ++cc) {
+            float ph;
+            if (cc == p.kidx) {
+                ph = own[c];
+                ownv = ph;
+            } else if (cc == 0) {
+                ph = p.phi[p.phi_off[0] + pix];
+            } else {
+                const int lc = p.lvl[cc];
+                const int nc = p.n >> lc;
+                ph = p.phi[p.phi_off[cc] + (size_t)(i >> lc) * nc + (j >> lc)];
+            }
+            avg = fmaf(p.p[cc], ph, avg);
+        }
+        const float xi = (g - ownv) + avg;
+        const float xo = p.x_old[pix];
+        const float xn = (xo - p.tau * xi) * p.prox_scale;
+        p.x_out[pix] = xn;
+        if (p.xbar) p.xbar[pix] = xn + p.theta * (xn - xo);
+    }
+}
+
 __global__ void k_prolong_acc(const float* in, float* out, int n, int lvl, int accumulate)
 {
     const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1325,6 +1396,13 @@ hipError_t launch_bp_main(const BpArgs& ba, hipStream_t s, BpOwnArgs& a)
     return launch_scatter<1, 2>(a, nl, ba.lvl, s);
 }
 
+static int bp_sum_slices(size_t d, int nq)
+{
+    int S = 1;  // slices: about 2^18 threads, at most kBpSumMaxSlices, at most nq
+    while (S < kBpSumMaxSlices && S < nq && d * (size_t)S < ((size_t)1 << 18)) S *= 2;
+    return S;
+}
+
 hipError_t launch_bp(const BpArgs& ba, hipStream_t s)
 {
     BpOwnArgs a;
@@ -1332,8 +1410,7 @@ hipError_t launch_bp(const BpArgs& ba, hipStream_t s)
     if (e != hipSuccess) return e;
     const int nl = ba.n >> ba.lvl;
     const size_t d = (size_t)nl * nl;
-    int S = 1;  // slices: about 2^18 threads, at most kBpSumMaxSlices, at most nq
-    while (S < kBpSumMaxSlices && S < a.nq && d * (size_t)S < ((size_t)1 << 18)) S *= 2;
+    const int S = bp_sum_slices(d, a.nq);
     const size_t per = 1024 / S;
     hipLaunchKernelGGL(k_bp_sum, dim3((unsigned)((d + per - 1) / per)), dim3(1024), 0, s, a, ba.tmp, S);
     e = hipGetLastError();
@@ -1341,6 +1418,19 @@ hipError_t launch_bp(const BpArgs& ba, hipStream_t s)
     const size_t fine = (size_t)ba.n * ba.n;
     hipLaunchKernelGGL(k_prolong_acc, dim3((unsigned)((fine + 255) / 256)), dim3(256), 0, s, (const float*)ba.tmp,
                        ba.out, ba.n, ba.lvl, ba.accumulate);
+    return hipGetLastError();
+}
+
+hipError_t launch_bp_primal(const BpArgs& ba, const PrimalArgs& pr, hipStream_t s)
+{
+    BpOwnArgs a;
+    hipError_t e = launch_bp_main(ba, s, a);
+    if (e != hipSuccess) return e;
+    const int nl = ba.n >> ba.lvl;
+    const size_t d = (size_t)nl * nl;
+    const int S = bp_sum_slices(d, a.nq);
+    const size_t per = 1024 / S;
+    hipLaunchKernelGGL(k_bp_sum_primal, dim3((unsigned)((d + per - 1) / per)), dim3(1024), 0, s, a, S, pr);
     return hipGetLastError();
 }
 

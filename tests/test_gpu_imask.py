@@ -200,3 +200,20 @@ def test_finite_check_is_opt_in():
     with pytest.raises(pk.ImaskError, match="ENONFINITE"):
         loud.step(2)
     assert loud.k == 2  # the steps were applied before the check
+
+
+@pytest.mark.parametrize("mode", [pk.FULL_PAPER, pk.FULL_UNBIASED])
+def test_grid_side_not_a_power_of_two(mode):
+    """N = 96: level grids of 48, 24 and 12 cells per side, so a workgroup's
+    run of coarse cells in the fused sum + primal kernel crosses rows."""
+    n, na, nd = 96, 50, 140
+    _, b = synth.ct_problem(n, na, nd, 1e4, 1003, 2003)
+    b = f32(b)
+    say(f"n=96 mode {mode}")
+    ost, prob = _run_both(n, na, nd, b, (0, 1, 2, 3), (0.25,) * 4, mode, oracle.Reg(lam=0.5),
+                          pk.Regularizer(pk.REG_TIKHONOV, 0.5), 0.03, 40)
+    assert prob.epochs == ost.epochs
+    assert rel(host(prob.x_cur), ost.x) <= 1e-4
+    assert rel(host(prob.y_cur), ost.y) <= 1e-4
+    for k, (l, ph) in enumerate(zip((0, 1, 2, 3), prob.phi_tables())):
+        assert rel(oracle.prolong(host(ph), l), ost.phi[k]) <= 1e-4

@@ -793,82 +793,106 @@ __global__ void __launch_bounds__(64 * W) k_bp_own(BpOwnArgs a)
 
 // c = sum over the nq partial images in a fixed order; coef * c is stored coarse
 // (or into `tmp` for a later prolongation).  The nq partials are cut into S
-// consecutive slices (S a power of two, chosen from the image size only so
-// that every level keeps about 2^18 threads busy): a workgroup of 1024
-// threads takes 1024/S pixels, each thread sums one slice of one pixel in
-// partial order, and the slice sums are added in slice order.
+// consecutive slices (S a power of two, chosen from the image size so that
+// every level keeps about 2^18 threads busy): a workgroup of 1024 threads
+// takes V 1024/S cells, each thread sums one slice of V cells in partial
+// order, and the slice sums are added in slice order.
 #ifndef IMK_BP_SUM_MAX_SLICES
 #define IMK_BP_SUM_MAX_SLICES 64
 #endif
 constexpr int kBpSumMaxSlices = IMK_BP_SUM_MAX_SLICES;  // <= 1024, a power of two
 
+// Slice sl of the nq partial images at the V consecutive cells from e,
+// summed in partial order (V = 4: one 16-byte load per partial).
+template <int V>
+__device__ __forceinline__ void slice_sum(const BpOwnArgs& a, size_t d, size_t e, int q0, int q1, float* sum)
+{
+#pragma unroll
+    for (int c = 0; c < V; ++c) sum[c] = 0.0f;
+    if (e >= d) return;
+    for (int q = q0; q < q1; ++q) {
+        const float* pp = a.part + q * d + e;
+        if constexpr (V == 4) {
+            float v[4];
+            ld4(pp, v);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) sum[c] += v[c];
+        } else {
+            sum[0] += pp[0];
+        }
+    }
+}
+
+// Each thread sums its slice for V consecutive cells (V = 4 needs d a
+// multiple of 4); the slices are then added one cell per thread.
+template <int V>
 __global__ void __launch_bounds__(1024) k_bp_sum(BpOwnArgs a, float* tmp, int S)
 {
-    __shared__ float red[1024];
+    __shared__ float red[1024 * V];
     const int nl = a.n >> a.lvl;
     const size_t d = (size_t)nl * nl;
-    const int per = 1024 / S;  // pixels per workgroup
+    const int per = 1024 / S;  // threads per slice
     const int sl = threadIdx.x / per;
     const int pi = threadIdx.x - sl * per;
-    const size_t e = (size_t)blockIdx.x * per + pi;
-    const int q0 = sl * a.nq / S, q1 = (sl + 1) * a.nq / S;
-    float sum = 0.0f;
-    if (e < d)
-        for (int q = q0; q < q1; ++q) sum += a.part[q * d + e];
-    red[threadIdx.x] = sum;
+    const size_t e = ((size_t)blockIdx.x * per + pi) * V;
+    float sum[V];
+    slice_sum<V>(a, d, e, sl * a.nq / S, (sl + 1) * a.nq / S, sum);
+#pragma unroll
+    for (int c = 0; c < V; ++c) red[threadIdx.x * V + c] = sum[c];
     __syncthreads();
-    if (sl != 0 || e >= d) return;
-    float c = red[pi];
-    for (int k = 1; k < S; ++k) c += red[k * per + pi];
-    const float v = a.coef * c;
-    if (a.prolong) {
-        tmp[e] = v;
-    } else {
-        float* o = a.out + e;
-        *o = a.accumulate ? *o + v : v;
+    // slice sums in slice order, one cell per thread
+    const size_t e0 = (size_t)blockIdx.x * per * V;
+    const int ncell = (int)min((size_t)per * V, d - min(d, e0));
+    for (int t = threadIdx.x; t < ncell; t += blockDim.x) {
+        float cc = red[t];
+        for (int k = 1; k < S; ++k) cc += red[k * per * V + t];
+        const float v = a.coef * cc;
+        float* o = (a.prolong ? tmp : a.out) + e0 + t;
+        *o = a.accumulate && !a.prolong ? *o + v : v;
     }
 }
 
 // The ordered partial sum fused with the primal step of Alg. 1, for steps
 // whose sketch needs one backprojection (a coarse sketch k > 0, or a single
-// level): workgroup w sums its 1024/S cells c of the level-l raw
+// level): workgroup w sums its V 1024/S cells c of the level-l raw
 // backprojection exactly as k_bp_sum does, forms g = 4^{-l} c, reads the old
 // phi_k of its cells into LDS and refreshes them with g, then updates every
 // full-resolution pixel of its cells as k_primal does (xi = (g - phi_k) +
 // sum_j p_j phi_j with the old tables; x+ = (x - tau xi) * prox_scale, and
 // xbar).  A cell's pixels and its phi_k entry belong to one workgroup, so
 // the old table values it reads are never overwritten by another.
+template <int V>
 __global__ void __launch_bounds__(1024) k_bp_sum_primal(BpOwnArgs a, int S, PrimalArgs p)
 {
-    __shared__ float red[1024];
-    __shared__ float gsh[1024], own[1024];
+    __shared__ float red[1024 * V];
+    __shared__ float gsh[1024 * V], own[1024 * V];
     const int l = a.lvl;
     const int nl = a.n >> l;
     const size_t d = (size_t)nl * nl;
-    const int per = 1024 / S;  // cells per workgroup
+    const int per = 1024 / S;  // threads per slice
     const int sl = threadIdx.x / per;
     const int pi = threadIdx.x - sl * per;
-    const size_t e0 = (size_t)blockIdx.x * per;
-    const size_t e = e0 + pi;
-    const int q0 = sl * a.nq / S, q1 = (sl + 1) * a.nq / S;
-    float sum = 0.0f;
-    if (e < d)
-        for (int q = q0; q < q1; ++q) sum += a.part[q * d + e];
-    red[threadIdx.x] = sum;
+    const size_t e0 = (size_t)blockIdx.x * per * V;  // the workgroup's first cell
+    const size_t e = e0 + (size_t)pi * V;
+    float sum[V];
+    slice_sum<V>(a, d, e, sl * a.nq / S, (sl + 1) * a.nq / S, sum);
+#pragma unroll
+    for (int c = 0; c < V; ++c) red[threadIdx.x * V + c] = sum[c];
     __syncthreads();
     const long long koff = p.phi_off[p.kidx];
-    if (sl == 0 && e < d) {
-        float c = red[pi];
-        for (int k = 1; k < S; ++k) c += red[k * per + pi];
-        const float g = (a.coef * c) * (1.0f / (float)(1 << (2 * l)));
-        gsh[pi] = g;
-        own[pi] = p.phi[koff + e];
-        p.phi[koff + e] = g;  // phi_k refresh
+    const int ncell = (int)min((size_t)per * V, d - min(d, e0));
+    // slice sums in slice order, one cell per thread
+    for (int t = threadIdx.x; t < ncell; t += blockDim.x) {
+        float cc = red[t];
+        for (int k = 1; k < S; ++k) cc += red[k * per * V + t];
+        const float g = (a.coef * cc) * (1.0f / (float)(1 << (2 * l)));
+        gsh[t] = g;
+        own[t] = p.phi[koff + e0 + t];
+        p.phi[koff + e0 + t] = g;  // phi_k refresh
     }
     __syncthreads();
     // the cells' pixels: 2^l rows of 2^l pixels per cell, cells in order
     const int L2 = 1 << l;
-    const int ncell = (int)min((size_t)per, d - min(d, e0));
     for (int q = threadIdx.x; q < ncell * L2 * L2; q += blockDim.x) {
         const int fr = q / (ncell * L2), rem = q - fr * (ncell * L2);
         const int c = rem >> l, fc = rem - (c << l);
@@ -1474,6 +1498,11 @@ hipError_t launch_bp_main(const BpArgs& ba, hipStream_t s, BpOwnArgs& a)
     return launch_scatter<1, 2>(a, nl, ba.lvl, s);
 }
 
+// Cells per thread of the ordered sums: four (16-byte loads) where the level
+// has enough cells to keep the GPU busy that way, else one.
+static int sum_cells_per_thread(size_t d) { return d % 4 == 0 && d >= 16384 ? 4 : 1; }
+
+// Slices for about 2^18 threads over d units of work.
 static int bp_sum_slices(size_t d, int nq)
 {
     int S = 1;  // slices: about 2^18 threads, at most kBpSumMaxSlices, at most nq
@@ -1488,9 +1517,15 @@ hipError_t launch_bp(const BpArgs& ba, hipStream_t s)
     if (e != hipSuccess) return e;
     const int nl = ba.n >> ba.lvl;
     const size_t d = (size_t)nl * nl;
-    const int S = bp_sum_slices(d, a.nq);
-    const size_t per = 1024 / S;
-    hipLaunchKernelGGL(k_bp_sum, dim3((unsigned)((d + per - 1) / per)), dim3(1024), 0, s, a, ba.tmp, S);
+    if (sum_cells_per_thread(d) == 4) {
+        const int S = bp_sum_slices(d / 4, a.nq);
+        const size_t cells = 4 * (size_t)(1024 / S);
+        hipLaunchKernelGGL(k_bp_sum<4>, dim3((unsigned)((d + cells - 1) / cells)), dim3(1024), 0, s, a, ba.tmp, S);
+    } else {
+        const int S = bp_sum_slices(d, a.nq);
+        const size_t cells = 1024 / S;
+        hipLaunchKernelGGL(k_bp_sum<1>, dim3((unsigned)((d + cells - 1) / cells)), dim3(1024), 0, s, a, ba.tmp, S);
+    }
     e = hipGetLastError();
     if (e != hipSuccess || !ba.prolong) return e;
     const size_t fine = (size_t)ba.n * ba.n;
@@ -1506,9 +1541,15 @@ hipError_t launch_bp_primal(const BpArgs& ba, const PrimalArgs& pr, hipStream_t 
     if (e != hipSuccess) return e;
     const int nl = ba.n >> ba.lvl;
     const size_t d = (size_t)nl * nl;
-    const int S = bp_sum_slices(d, a.nq);
-    const size_t per = 1024 / S;
-    hipLaunchKernelGGL(k_bp_sum_primal, dim3((unsigned)((d + per - 1) / per)), dim3(1024), 0, s, a, S, pr);
+    if (sum_cells_per_thread(d) == 4) {
+        const int S = bp_sum_slices(d / 4, a.nq);
+        const size_t cells = 4 * (size_t)(1024 / S);
+        hipLaunchKernelGGL(k_bp_sum_primal<4>, dim3((unsigned)((d + cells - 1) / cells)), dim3(1024), 0, s, a, S, pr);
+    } else {
+        const int S = bp_sum_slices(d, a.nq);
+        const size_t cells = 1024 / S;
+        hipLaunchKernelGGL(k_bp_sum_primal<1>, dim3((unsigned)((d + cells - 1) / cells)), dim3(1024), 0, s, a, S, pr);
+    }
     return hipGetLastError();
 }
 

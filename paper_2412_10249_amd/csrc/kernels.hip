@@ -1300,9 +1300,14 @@ __global__ void __launch_bounds__(256) k_dot_final(const double* part, double* o
 
 // ----------------------------------------------------------------- launchers
 
+#ifndef IMK_TILE_MIN
+#define IMK_TILE_MIN 16
+#endif
 int tile_side(int n, int lmax)
 {
-    int T = 16 < n ? 16 : n;
+    int T = IMK_TILE_MIN;
+    while (T > 16 && n % T != 0) T >>= 1;  // a divisor of n (n > 16 is a multiple of 16)
+    if (T > n) T = n;
     while (T < (1 << lmax)) T <<= 1;
     return T;
 }

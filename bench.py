@@ -17,6 +17,8 @@ Other workloads, each printing its own JSON line:
   --batched             64 slices of mixed sizes in flight on several streams
   --serve               Poisson arrivals into the continuous-batching server
   --autograd            unrolled, checkpointed ImaSk forward + backward
+  --oracle-timing       the FP64 oracle (all threads, one thread) against the
+                        GPU: 50 iterations of the 64x64 Tikhonov workload
 
 Profiling helpers (no GPU needed for --summarize):
   --counters fwd:L|bp:L launch one projector kernel, for rocprofv3 --pmc
@@ -567,6 +569,62 @@ def serving(args):
                       "highest_sustained_rate_per_s": max(ok) if ok else None, "results": out}), flush=True)
 
 
+def _oracle_cfg1_seconds(reps: int = 5) -> list:
+    """Wall times of 50 oracle iterations on the 64x64 Tikhonov workload."""
+    import oracle
+    import synth
+
+    _, b = synth.ct_problem(64, 90, 92, 1e4, 1000, 2000)
+    b = np.asarray(b, dtype=np.float32).astype(np.float64)
+    g = oracle.Geometry(64, 90, 92)
+    lv = oracle.Levels([0, 1, 2], [1.0 / 3] * 3)
+    out = []
+    for _ in range(reps + 1):  # the first run warms up
+        t0 = time.perf_counter()
+        oracle.imask_run(g, lv, oracle.Reg(lam=1e-2), 0.02, SEED, STREAM, b, 50)
+        out.append(time.perf_counter() - t0)
+    return out[1:]
+
+
+def oracle_timing(args):
+    """The FP64 oracle (all host threads, and one thread in a child process)
+    against the GPU on the 64x64 Tikhonov workload: 50 iterations, median of
+    5 runs after a warm-up, same seed and step."""
+    import subprocess
+
+    import synth
+    import torch
+
+    import paper_2412_10249_amd as pk
+
+    if args.oracle_child:
+        print(json.dumps({"seconds": _oracle_cfg1_seconds()}))
+        return
+    all_threads = _oracle_cfg1_seconds()
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    child = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--oracle-timing", "--oracle-child"],
+                           env=env, capture_output=True, text=True, check=True)
+    one_thread = json.loads(child.stdout.strip().splitlines()[-1])["seconds"]
+    _, b = synth.ct_problem(64, 90, 92, 1e4, 1000, 2000)
+    b32 = torch.from_numpy(np.asarray(b, dtype=np.float32)).cuda()
+    gpu = []
+    for _ in range(6):
+        prob = pk.Problem(pk.Geometry(64, 90, 92), pk.Levels.uniform((0, 1, 2)), pk.Regularizer(pk.REG_TIKHONOV, 1e-2),
+                          pk.Params(0.02, SEED, STREAM), b32)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        prob.step(50)
+        torch.cuda.synchronize()
+        gpu.append(time.perf_counter() - t0)
+    med = lambda v: float(np.median(v))  # noqa: E731
+    print(json.dumps({"metric": "50 ImaSk iterations, 64x64 Tikhonov (90 x 92, levels 64/32/16), median of 5",
+                      "oracle_s": med(all_threads), "oracle_threads": int(os.environ.get("OMP_NUM_THREADS",
+                                                                                        os.cpu_count() or 1)),
+                      "oracle_1_thread_s": med(one_thread), "gpu_s": med(gpu[1:]),
+                      "speedup_vs_oracle": med(all_threads) / med(gpu[1:]),
+                      "speedup_vs_1_thread": med(one_thread) / med(gpu[1:])}))
+
+
 def autograd_bench(args):
     """Differentiable unrolled ImaSk: batch 32 of 256^2, 384 angles x 384 bins,
     10 iterations, checkpoint every 2; gradients to the image and lam."""
@@ -726,6 +784,8 @@ def main():
     ap.add_argument("--chunk", type=float, default=2.0)
     ap.add_argument("--serve-epochs", type=float, default=30.0)
     ap.add_argument("--autograd", action="store_true", help="differentiable unrolled ImaSk")
+    ap.add_argument("--oracle-timing", action="store_true", help="FP64 oracle vs GPU on the 64x64 workload")
+    ap.add_argument("--oracle-child", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--batch", type=int, default=32)
     ap.add_argument("--study", choices=["stepsize", "tv"], help="fixed-budget PSNR studies")
     ap.add_argument("--study-epochs", type=float, default=100.0)
@@ -742,6 +802,9 @@ def main():
         return
     if args.autograd:
         autograd_bench(args)
+        return
+    if args.oracle_timing:
+        oracle_timing(args)
         return
     if args.race:
         race(args)

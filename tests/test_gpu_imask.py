@@ -217,3 +217,20 @@ def test_grid_side_not_a_power_of_two(mode):
     assert rel(host(prob.y_cur), ost.y) <= 1e-4
     for k, (l, ph) in enumerate(zip((0, 1, 2, 3), prob.phi_tables())):
         assert rel(oracle.prolong(host(ph), l), ost.phi[k]) <= 1e-4
+
+
+def test_bench_workload_ten_epochs():
+    """The benchmarked workload itself (512^2, 720 x 768, I0 = 1e5, smoothed
+    TV eps = 1e-3, lam = 1e-3, w = 2e-4, J = 10, levels 512/256/128/64 with
+    p = 1/4, PAPER sketches, sigma = 1e-3) for 21 iterations, about 11
+    epochs, launched as the benchmark launches it: x and y within 1e-3."""
+    n, na, nd = 512, 720, 768
+    _, b = synth.ct_problem(n, na, nd, 1e5, 1000, 2000)
+    b = f32(b)
+    reg_o = oracle.Reg(oracle.REG_SMOOTH_TV, lam=1e-3, tv_weight=2e-4, tv_eps=1e-3, tv_inner=10)
+    reg_g = pk.Regularizer(pk.REG_SMOOTH_TV, 1e-3, 2e-4, 1e-3, 10)
+    say("bench workload, 21 iterations")
+    ost, prob = _run_both(n, na, nd, b, (0, 1, 2, 3), (0.25,) * 4, pk.FULL_PAPER, reg_o, reg_g, 1e-3, 21)
+    assert prob.epochs == ost.epochs > 10.0
+    assert rel(host(prob.x_cur), ost.x) <= 1e-3
+    assert rel(host(prob.y_cur), ost.y) <= 1e-3

@@ -1047,16 +1047,18 @@ __global__ void __launch_bounds__(kTvThreads) k_tv(TvArgs a)
     const int n = a.n;
     const float eps2 = a.eps * a.eps;
     enum { kIn = 1, kDown = 2, kRight = 4, kUp = 8, kLeft = 16, kOut = 32 };
-    int cell[kTvCells], flag[kTvCells];
+    int cell[kTvCells], flag[kTvCells], ring[kTvCells];
     float vv[kTvCells], up[kTvCells];
 #pragma unroll
     for (int k = 0; k < kTvCells; ++k) {
         const int q = threadIdx.x + k * kTvThreads;
         flag[k] = 0;
         cell[k] = q;
+        ring[k] = 0;
         vv[k] = up[k] = 0.0f;
         if (q >= R * R) continue;
         const int li = q / R, lj = q - li * R;
+        ring[k] = min(min(li, lj), min(R - 1 - li, R - 1 - lj));
         const int gi = gi0 + li, gj = gj0 + lj;
         if (gi < 0 || gi >= n || gj < 0 || gj >= n) {
             ys[q] = 0.0f;
@@ -1070,11 +1072,15 @@ __global__ void __launch_bounds__(kTvThreads) k_tv(TvArgs a)
         ys[q] = up[k];
     }
     __syncthreads();
+    // A cell's update reads cells at most one pixel away, so after iteration
+    // t+1 only cells at least t+1 pixels inside the tile's edge (ring t+1)
+    // still agree with the untiled iteration, and the output (ring J) needs
+    // no others: iteration t updates rings > t, from gradients on rings >= t.
     for (int t = 0; t < a.J; ++t) {
         // q = grad y / sqrt(|grad y|^2 + eps^2), zero difference past the image
 #pragma unroll
         for (int k = 0; k < kTvCells; ++k) {
-            if (!(flag[k] & kIn)) continue;
+            if (!(flag[k] & kIn) || ring[k] < t) continue;
             const int c = cell[k];
             const float yc = ys[c];
             const float d1 = (flag[k] & kDown) ? ys[c + R] - yc : 0.0f;
@@ -1087,7 +1093,7 @@ __global__ void __launch_bounds__(kTvThreads) k_tv(TvArgs a)
         const float beta = a.beta[t];
 #pragma unroll
         for (int k = 0; k < kTvCells; ++k) {
-            if (!(flag[k] & kIn)) continue;
+            if (!(flag[k] & kIn) || ring[k] <= t) continue;
             const int c = cell[k];
             float div = -q1[c] - q2[c];  // grad^T q
             if (flag[k] & kUp) div += q1[c - R];

@@ -7,9 +7,12 @@
 // fixed-point coordinate, so the pair is an exact transpose.  Resampling
 // (block mean T_l, compensation S_r) is done by the tile-pyramid kernel
 // k_prep that feeds the projector; the SAGA table refresh and the primal /
-// dual proximal steps of Alg. 1 are fused into k_fwd's store (dual) and
-// k_primal (primal); the smoothed-TV prox runs J FISTA iterations inside one
-// launch on LDS-resident overlapped tiles (k_tv).
+// dual proximal steps of Alg. 1 are fused into the forward's reduce (dual)
+// and into k_primal, or into the transpose's ordered partial sum when the
+// sketch needs a single backprojection (k_bp_sum_primal); the smoothed-TV
+// prox runs J FISTA iterations inside one launch on LDS-resident overlapped
+// tiles (k_tv), the paper's TV prior J dual projected-gradient iterations
+// (k_tvd).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

@@ -1377,10 +1377,12 @@ hipError_t launch_prep(const PrepArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
-// LDS budget of a forward band: the full 136 KB (one workgroup per CU) for
-// 512-pixel rows, where fewer bands keep the partial sinograms few; 64 KB
-// (two workgroups per CU) for coarser levels.
-static int fwd_lds_bytes(int nl) { return (nl >= 512 ? 136 : 64) * 1024; }
+// LDS budget of a forward band: up to 156 KB (one workgroup per CU, 7 bands
+// of 74 rows) for 512-pixel rows, where fewer bands keep the partial
+// sinograms few; 78 KB (two workgroups per CU, 4 bands) for 256-pixel rows;
+// 64 KB for coarser levels, whose single large band would leave too few
+// workgroups.
+static int fwd_lds_bytes(int nl) { return (nl >= 512 ? 156 : nl >= 256 ? 78 : 64) * 1024; }
 
 void fwd_bands(int nl, int* bands, int* rows)
 {

@@ -104,3 +104,48 @@ def test_imask_on_listed_angles_matches_oracle():
     assert prob.epochs == ost.epochs
     assert rel(host(prob.x_cur), ost.x) <= 1e-4
     assert rel(host(prob.y_cur), ost.y) <= 1e-4
+
+
+def test_listed_angles_with_the_paper_prior_and_sequential_schedule():
+    """ImaSk-Seq with the TV + nonnegativity prior on a limited-angle listed
+    geometry with a shifted, finer detector: x, xbar, y, dual pair within 1e-3."""
+    n, nd, E = 64, 110, 1.2
+    ang = tuple(synth.angles_random(45, 12, 0.2, 2.6))
+    g, og = _geoms(n, nd, ang, E, 0.8, 0.1)
+    b = f32(synth.random_sinogram(len(ang), nd, 40)) * 0.3 + 0.5
+    lv = (0, 1, 2)
+    say("listed angles, Seq + TV prior")
+    ost = oracle.imask_seq_run(og, oracle.Levels(list(lv), [0.5, 0.3, 0.2]),
+                               oracle.Reg(oracle.REG_TV, lam=1e-2, tv_weight=2e-3, tv_inner=8), 5e-3, 1.0, 42, 0, b, 30)
+    prob = pk.Problem(g, pk.Levels(lv, (0.5, 0.3, 0.2)), pk.Regularizer(pk.REG_TV, 1e-2, 2e-3, 0.0, 8),
+                      pk.Params(5e-3, 42, 0, pk.SCHEDULE_SEQUENTIAL, 1.0), dev(b))
+    prob.step(30)
+    assert prob.epochs == ost.epochs
+    assert host(prob.x_cur).min() >= 0.0
+    assert rel(host(prob.x_cur), ost.x) <= 1e-3
+    assert rel(host(prob.xbar), ost.xbar) <= 1e-3
+    assert rel(host(prob.y_cur), ost.y) <= 1e-3
+    assert rel(host(prob.tvd[prob.cur]), ost.tvd) <= 1e-3
+
+
+def test_listed_angles_with_compact_tables_and_independent_draws():
+    n, nd = 48, 70
+    ang = tuple(synth.angles_random(33, 13))
+    g, og = _geoms(n, nd, ang, 1.0)
+    b = f32(synth.random_sinogram(len(ang), nd, 41)) * 0.3 + 0.5
+    lv, p = (0, 1, 2), (0.4, 0.3, 0.3)
+    say("listed angles, compact tables")
+    ost = oracle.imask_compact_run(og, oracle.Levels(list(lv), list(p)), oracle.Reg(lam=0.5), 0.02, 42, 0, b, 30)
+    prob = pk.Problem(g, pk.Levels(lv, p), pk.Regularizer(pk.REG_TIKHONOV, 0.5), pk.Params(0.02, 42, 0), dev(b),
+                      compact_tables=True)
+    prob.step(30)
+    assert rel(host(prob.x_cur), ost.x) <= 1e-4
+    assert rel(host(prob.y_cur), ost.y) <= 1e-4
+    say("listed angles, independent draws")
+    ost = oracle.imask_indep_run(og, oracle.Levels(list(lv), list(p)), oracle.Reg(lam=0.5), 0.02, 42, 0, 5, b, 30)
+    prob = pk.Problem(g, pk.Levels(lv, p), pk.Regularizer(pk.REG_TIKHONOV, 0.5),
+                      pk.Params(0.02, 42, 0, draw_mode=pk.DRAW_INDEPENDENT, dual_stream_id=5), dev(b))
+    prob.step(30)
+    assert prob.epochs == ost.epochs
+    assert rel(host(prob.x_cur), ost.x) <= 1e-4
+    assert rel(host(prob.y_cur), ost.y) <= 1e-4

@@ -13,7 +13,8 @@ Prints one JSON line.  --gpus above 1 is refused: the path runs on one GPU
 Other workloads, each printing its own JSON line:
   --race                time to relative error 1e-3 against a common limit:
                         ImaSk, SAGA, ImaSk-Seq, PDHG, independent draws
-  --study stepsize|tv   PSNR against the phantom over a fixed epoch budget
+  --study stepsize|tv|square
+                        PSNR against the phantom over a fixed epoch budget
   --batched             64 slices of mixed sizes in flight on several streams
   --serve               Poisson arrivals into the continuous-batching server
   --autograd            unrolled, checkpointed ImaSk forward + backward
@@ -386,7 +387,14 @@ def study(args):
                 the step rule), ImaSk with r = 1, 2, 4 at 1, 4, 16 and 64 times
                 its Thm. 3 step (the prior is barely strongly convex, so the
                 theorem's step is very conservative), and ImaSk-Seq with
-                r = 1, 4 at a quarter and half of the PDHG limit"""
+                r = 1, 4 at a quarter and half of the PDHG limit
+      square    the comparison of the paper's Sec. 5: a square insert whose
+                edges lie on the coarsest grid (64-pixel blocks, levels
+                512..8, r = 7, the most this library takes), Poisson data
+                from its exact line integrals, the TV + nonnegativity prior;
+                ImaSk and ImaSk-Seq with r = 7, ImaSk r = 1 (SAGA) and PDHG
+                (ImaSk-Seq r = 1); PSNR against the square and the distance
+                to the PDHG solution after --ref-iters iterations"""
     import torch
 
     import paper_2412_10249_amd as pk
@@ -396,7 +404,11 @@ def study(args):
         print(msg, file=sys.stderr, flush=True)
 
     torch.cuda.set_device(0)
-    x_true, b = synth.ct_problem(N, NA, ND, I0, 1000, 2000)
+    if args.study == "square":
+        x_true = synth.square_insert(N, 64, 3, 5)
+        b = synth.poisson_log_data(synth.square_line_integrals(N, 64, 3, 5, NA, ND), I0, 2000)
+    else:
+        x_true, b = synth.ct_problem(N, NA, ND, I0, 1000, 2000)
     b32 = torch.from_numpy(b.astype(np.float32)).cuda()
     xt = torch.from_numpy(x_true.astype(np.float32)).cuda()
     peak = float(xt.max())
@@ -408,7 +420,38 @@ def study(args):
         return 10.0 * np.log10(peak * peak / mse)
 
     runs = []
-    if args.study == "stepsize":
+    ref = None
+    if args.study == "square":
+        lam, w = 1e-4, 2e-4
+        reg = pk.Regularizer(pk.REG_TV, lam, w, 0.0, TV_J)
+        info = {"lam": lam, "tv_weight": w, "tv_inner": TV_J, "phantom": "square insert, 64-pixel blocks 3..5",
+                "levels": list(range(7))}
+        lv7 = pk.Levels.uniform(tuple(range(7)), pk.FULL_PAPER)
+        lv1 = pk.Levels.uniform((0,), pk.FULL_PAPER)
+        cases = []
+        for lv, r in ((lv7, 7), (lv1, 1)):
+            L2, lb, lp = pk.step_constants(geom, lv, lam, work, iters=40)
+            s3 = pk.sigma_thm3(L2, lb, lp, min(lv.p), 100)[0]
+            info[f"constants_r{r}"] = [L2, lb, lp]
+            for m in (16, 64):
+                cases.append((f"imask_r{r} x{m}", lv, reg, m * s3, pk.SCHEDULE_PARALLEL))
+            for m in (0.25, 0.5, 0.9):
+                cases.append((f"{'pdhg' if r == 1 else 'seq_r7'} x{m}", lv, reg, m / np.sqrt(L2),
+                              pk.SCHEDULE_SEQUENTIAL))
+            if r == 1:
+                sig_ref = 0.9 / np.sqrt(L2)
+        # the reference: PDHG (ImaSk-Seq with one level) run long
+        rp = pk.Problem(geom, lv1, reg, pk.Params(sig_ref, SEED, STREAM, pk.SCHEDULE_SEQUENTIAL, 1.0), b32)
+        rp.step(args.ref_iters)
+        torch.cuda.synchronize()
+        ref = rp.x_cur.clone()
+        prev = rp.x_cur.clone()
+        rp.step(100)
+        info["reference"] = {"iterations": args.ref_iters, "sigma": sig_ref,
+                             "relative_change_last_100": float(torch.linalg.norm(rp.x_cur - prev) /
+                                                               torch.linalg.norm(prev))}
+        log(f"reference: {args.ref_iters} PDHG iterations, last-100 change {info['reference']}")
+    elif args.study == "stepsize":
         lam = 1e-2
         lv = pk.Levels.uniform(LEVELS, pk.FULL_PAPER)
         reg = pk.Regularizer(pk.REG_TIKHONOV, lam)
@@ -441,12 +484,17 @@ def study(args):
         t0 = time.perf_counter()
         while prob.epochs < args.study_epochs:
             prob.solve(args.study_every, pk.BUDGET_EPOCHS)
-            hist.append((round(time.perf_counter() - t0, 4), round(prob.epochs, 3), round(psnr(prob.x_cur), 3)))
+            row = [round(time.perf_counter() - t0, 4), round(prob.epochs, 3), round(psnr(prob.x_cur), 3)]
+            if ref is not None:
+                row.append(float(torch.linalg.norm(prob.x_cur - ref) / torch.linalg.norm(ref)))
+            hist.append(tuple(row))
             if not np.isfinite(hist[-1][2]):
                 break
-        log(f"{name}: sigma {sigma:.3e}, {prob.epochs:.1f} epochs, {hist[-1][0]:.2f} s, PSNR {hist[-1][2]:.2f} dB")
+        log(f"{name}: sigma {sigma:.3e}, {prob.epochs:.1f} epochs, {hist[-1][0]:.2f} s, PSNR {hist[-1][2]:.2f} dB"
+            + (f", distance to the reference {hist[-1][3]:.3e}" if ref is not None else ""))
+        key = "history_s_epochs_psnr" + ("_dist" if ref is not None else "")
         runs.append({"name": name, "sigma": sigma, "schedule": "sequential" if sched else "parallel",
-                     "levels": list(lv.log2f), "history_s_epochs_psnr": hist})
+                     "levels": list(lv.log2f), key: hist})
     print(json.dumps({"metric": f"PSNR vs epochs, {args.study} study (512x512, 720 x 768)", "info": info,
                       "runs": runs}), flush=True)
 
@@ -787,7 +835,7 @@ def main():
     ap.add_argument("--oracle-timing", action="store_true", help="FP64 oracle vs GPU on the 64x64 workload")
     ap.add_argument("--oracle-child", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--batch", type=int, default=32)
-    ap.add_argument("--study", choices=["stepsize", "tv"], help="fixed-budget PSNR studies")
+    ap.add_argument("--study", choices=["stepsize", "tv", "square"], help="fixed-budget PSNR studies")
     ap.add_argument("--study-epochs", type=float, default=100.0)
     ap.add_argument("--study-every", type=float, default=5.0)
     args = ap.parse_args()

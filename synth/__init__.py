@@ -17,6 +17,7 @@ from .phantom import (  # noqa: F401
     pixel_centres,
     disk_image,
     square_insert,
+    square_line_integrals,
     affine_image,
     random_image,
     random_sinogram,

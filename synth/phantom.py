@@ -142,6 +142,33 @@ def square_insert(n: int, block: int, lo: int, hi: int, value: float = 1.0) -> n
     return img
 
 
+def square_line_integrals(n: int, block: int, lo: int, hi: int, n_angles: int, n_det: int,
+                          value: float = 1.0) -> np.ndarray:
+    """Exact line integrals of square_insert(n, block, lo, hi, value) on the
+    ray grid, [angle][bin]: value times the length of the ray's chord through
+    the square [x0, x1] x [y0, y1] (slab clipping of the line
+    {s (cos, sin) + t (-sin, cos)})."""
+    h = 2.0 * EXTENT / n
+    x0, x1 = -EXTENT + lo * block * h, -EXTENT + hi * block * h  # rows and columns share the bounds
+    th = angles_uniform(n_angles)[:, None]
+    s = detector_centres(n, n_det)[None, :]
+    c, sn = np.cos(th), np.sin(th)
+    px, py, dx, dy = s * c, s * sn, -sn, c  # point on the ray and its direction
+    tmin = np.full(np.broadcast(px, dx).shape, -np.inf)
+    tmax = np.full_like(tmin, np.inf)
+    for p0, d in ((px, dx), (py, dy)):
+        d = np.broadcast_to(d, tmin.shape)
+        p0 = np.broadcast_to(p0, tmin.shape)
+        par = np.abs(d) < 1e-300
+        with np.errstate(divide="ignore", invalid="ignore"):
+            t1, t2 = (x0 - p0) / d, (x1 - p0) / d
+        lo_t, hi_t = np.minimum(t1, t2), np.maximum(t1, t2)
+        inside = (p0 >= x0) & (p0 <= x1)
+        tmin = np.where(par, np.where(inside, tmin, np.inf), np.maximum(tmin, lo_t))
+        tmax = np.where(par, np.where(inside, tmax, -np.inf), np.minimum(tmax, hi_t))
+    return value * np.maximum(tmax - tmin, 0.0)
+
+
 def affine_image(n: int, alpha: float, beta: float, gamma: float, extent: float = EXTENT) -> np.ndarray:
     """f(x, y) = alpha x + beta y + gamma at the pixel centres."""
     xc = pixel_centres(n, extent)

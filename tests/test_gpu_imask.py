@@ -234,3 +234,22 @@ def test_bench_workload_ten_epochs():
     assert prob.epochs == ost.epochs > 10.0
     assert rel(host(prob.x_cur), ost.x) <= 1e-3
     assert rel(host(prob.y_cur), ost.y) <= 1e-3
+
+
+@pytest.mark.parametrize("n,log2f,p", [(48, (0, 2, 4), (0.4, 0.3, 0.3)), (144, (0,), (1.0,))])
+def test_odd_level_grids_and_partial_workgroups(n, log2f, p):
+    """48^2 with a 3 x 3 coarsest grid (cell counts not a multiple of 4: one
+    cell per thread in the fused sum + primal kernel); 144^2 at one level
+    (four cells per thread, the last workgroup partly filled)."""
+    na, nd = 40, 3 * n // 2
+    _, b = synth.ct_problem(n, na, nd, 1e4, 1004, 2004)
+    b = f32(b)
+    for mode in (pk.FULL_PAPER, pk.FULL_UNBIASED):
+        say(f"n={n} levels {log2f} mode {mode}")
+        ost, prob = _run_both(n, na, nd, b, log2f, p, mode, oracle.Reg(lam=0.5),
+                              pk.Regularizer(pk.REG_TIKHONOV, 0.5), 0.02, 30)
+        assert prob.epochs == ost.epochs
+        assert rel(host(prob.x_cur), ost.x) <= 1e-4
+        assert rel(host(prob.y_cur), ost.y) <= 1e-4
+        for k, (l, ph) in enumerate(zip(log2f, prob.phi_tables())):
+            assert rel(oracle.prolong(host(ph), l), ost.phi[k]) <= 1e-4

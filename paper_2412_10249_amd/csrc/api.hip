@@ -522,7 +522,7 @@ int imask_backproject(const imask_geometry* g, int32_t log2f, const void* work, 
 int imask_resample(int32_t n, int32_t log2f, int32_t mode, const imask_levels* lv, const float* in, float* out,
                    void* stream)
 {
-    imask_geometry g{n, 1, 1, 0.0, 0.0};
+    imask_geometry g{n, 1, 1, 0.0, 0.0, 1.0, nullptr};
     if (!geometry_ok(&g) || !in || !out || in == out) return IMASK_EINVAL;
     const int lmax = level_limit(n);
     if (log2f < 0 || log2f > lmax) return IMASK_EINVAL;

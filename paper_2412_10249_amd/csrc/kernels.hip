@@ -1051,14 +1051,16 @@ __global__ void __launch_bounds__(kTvThreads) k_tv(TvArgs a)
     const float eps2 = a.eps * a.eps;
     enum { kIn = 1, kDown = 2, kRight = 4, kUp = 8, kLeft = 16, kOut = 32 };
     int cell[kTvCells], flag[kTvCells], ring[kTvCells];
-    float vv[kTvCells], up[kTvCells];
+    // per cell in registers: input v, previous iterate, current y and its
+    // normalised gradient (the LDS copies serve the neighbours)
+    float vv[kTvCells], up[kTvCells], yk[kTvCells], g1[kTvCells], g2[kTvCells];
 #pragma unroll
     for (int k = 0; k < kTvCells; ++k) {
         const int q = threadIdx.x + k * kTvThreads;
         flag[k] = 0;
         cell[k] = q;
         ring[k] = 0;
-        vv[k] = up[k] = 0.0f;
+        vv[k] = up[k] = yk[k] = g1[k] = g2[k] = 0.0f;
         if (q >= R * R) continue;
         const int li = q / R, lj = q - li * R;
         ring[k] = min(min(li, lj), min(R - 1 - li, R - 1 - lj));
@@ -1072,6 +1074,7 @@ __global__ void __launch_bounds__(kTvThreads) k_tv(TvArgs a)
                   (li >= H && li < H + kTvTile && lj >= H && lj < H + kTvTile ? kOut : 0);
         vv[k] = a.v[(size_t)gi * n + gj];
         up[k] = a.u0[(size_t)gi * n + gj];
+        yk[k] = up[k];
         ys[q] = up[k];
     }
     __syncthreads();
@@ -1085,12 +1088,14 @@ __global__ void __launch_bounds__(kTvThreads) k_tv(TvArgs a)
         for (int k = 0; k < kTvCells; ++k) {
             if (!(flag[k] & kIn) || ring[k] < t) continue;
             const int c = cell[k];
-            const float yc = ys[c];
+            const float yc = yk[k];
             const float d1 = (flag[k] & kDown) ? ys[c + R] - yc : 0.0f;
             const float d2 = (flag[k] & kRight) ? ys[c + 1] - yc : 0.0f;
             const float inv = rsqrtf(fmaf(d1, d1, fmaf(d2, d2, eps2)));
-            q1[c] = d1 * inv;
-            q2[c] = d2 * inv;
+            g1[k] = d1 * inv;
+            g2[k] = d2 * inv;
+            q1[c] = g1[k];
+            q2[c] = g2[k];
         }
         __syncthreads();
         const float beta = a.beta[t];
@@ -1098,13 +1103,14 @@ __global__ void __launch_bounds__(kTvThreads) k_tv(TvArgs a)
         for (int k = 0; k < kTvCells; ++k) {
             if (!(flag[k] & kIn) || ring[k] <= t) continue;
             const int c = cell[k];
-            float div = -q1[c] - q2[c];  // grad^T q
+            float div = -g1[k] - g2[k];  // grad^T q
             if (flag[k] & kUp) div += q1[c - R];
             if (flag[k] & kLeft) div += q2[c - 1];
-            const float yc = ys[c];
+            const float yc = yk[k];
             const float gh = (yc - vv[k]) + a.tau_w * div + a.tau_lam * yc;
             const float un = yc - a.invL * gh;
-            ys[c] = un + beta * (un - up[k]);
+            yk[k] = un + beta * (un - up[k]);
+            ys[c] = yk[k];
             up[k] = un;
         }
         __syncthreads();

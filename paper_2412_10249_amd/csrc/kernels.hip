@@ -1148,13 +1148,15 @@ __global__ void __launch_bounds__(kTvThreads) k_tvd(TvdArgs a)
     const size_t d = (size_t)n * n;
     enum { kIn = 1, kDown = 2, kRight = 4, kUp = 8, kLeft = 16, kOut = 32 };
     int cell[kTvCells], flag[kTvCells];
-    float bt[kTvCells], p1[kTvCells], p2[kTvCells];
+    // per cell in registers: prox input, dual iterate, extrapolated dual and
+    // u (the LDS copies serve the neighbours)
+    float bt[kTvCells], p1[kTvCells], p2[kTvCells], e1[kTvCells], e2[kTvCells], uk[kTvCells];
 #pragma unroll
     for (int k = 0; k < kTvCells; ++k) {
         const int q = threadIdx.x + k * kTvThreads;
         flag[k] = 0;
         cell[k] = q;
-        bt[k] = p1[k] = p2[k] = 0.0f;
+        bt[k] = p1[k] = p2[k] = e1[k] = e2[k] = uk[k] = 0.0f;
         if (q >= R * R) continue;
         const int li = q / R, lj = q - li * R;
         const int gi = gi0 + li, gj = gj0 + lj;
@@ -1170,6 +1172,8 @@ __global__ void __launch_bounds__(kTvThreads) k_tvd(TvdArgs a)
         bt[k] = a.v[g] * a.inv_scale;
         p1[k] = down ? a.pin[g] : 0.0f;
         p2[k] = right ? a.pin[d + g] : 0.0f;
+        e1[k] = p1[k];
+        e2[k] = p2[k];
         r1[q] = p1[k];
         r2[q] = p2[k];
     }
@@ -1180,10 +1184,11 @@ __global__ void __launch_bounds__(kTvThreads) k_tvd(TvdArgs a)
         for (int k = 0; k < kTvCells; ++k) {
             if (!(flag[k] & kIn)) continue;
             const int c = cell[k];
-            float gt = -r1[c] - r2[c];
+            float gt = -e1[k] - e2[k];
             if (flag[k] & kUp) gt += r1[c - R];
             if (flag[k] & kLeft) gt += r2[c - 1];
-            uu[c] = fmaxf(0.0f, bt[k] - a.gamma * gt);
+            uk[k] = fmaxf(0.0f, bt[k] - a.gamma * gt);
+            uu[c] = uk[k];
         }
         __syncthreads();
         const float beta = a.beta[t];
@@ -1191,15 +1196,17 @@ __global__ void __launch_bounds__(kTvThreads) k_tvd(TvdArgs a)
         for (int k = 0; k < kTvCells; ++k) {
             if (!(flag[k] & kIn)) continue;
             const int c = cell[k];
-            const float uc = uu[c];
+            const float uc = uk[k];
             const float g1 = (flag[k] & kDown) ? uu[c + R] - uc : 0.0f;
             const float g2 = (flag[k] & kRight) ? uu[c + 1] - uc : 0.0f;
-            const float a1 = fmaf(g1, a.inv8g, r1[c]);
-            const float a2 = fmaf(g2, a.inv8g, r2[c]);
+            const float a1 = fmaf(g1, a.inv8g, e1[k]);
+            const float a2 = fmaf(g2, a.inv8g, e2[k]);
             const float sc = fminf(1.0f, rsqrtf(fmaf(a1, a1, a2 * a2)));  // 1 / max(1, |a|)
             const float n1 = a1 * sc, n2 = a2 * sc;
-            r1[c] = n1 + beta * (n1 - p1[k]);
-            r2[c] = n2 + beta * (n2 - p2[k]);
+            e1[k] = n1 + beta * (n1 - p1[k]);
+            e2[k] = n2 + beta * (n2 - p2[k]);
+            r1[c] = e1[k];
+            r2[c] = e2[k];
             p1[k] = n1;
             p2[k] = n2;
         }

@@ -253,3 +253,22 @@ def test_odd_level_grids_and_partial_workgroups(n, log2f, p):
         assert rel(host(prob.y_cur), ost.y) <= 1e-4
         for k, (l, ph) in enumerate(zip(log2f, prob.phi_tables())):
             assert rel(oracle.prolong(host(ph), l), ost.phi[k]) <= 1e-4
+
+
+def test_degenerate_sizes_and_empty_calls():
+    """The smallest grid (4 x 4, levels 4 and 2), a single detector bin and a
+    single angle; zero steps and an empty problem list change nothing."""
+    for n, na, nd, lv in ((4, 3, 5, (0, 1)), (16, 1, 1, (0, 1, 2)), (8, 7, 1, (0,))):
+        b = f32(synth.random_sinogram(na, nd, 50 + n))
+        p = (1.0 / len(lv),) * len(lv)
+        say(f"degenerate n={n} na={na} nd={nd}")
+        ost, prob = _run_both(n, na, nd, b, lv, p, pk.FULL_UNBIASED, oracle.Reg(lam=0.5),
+                              pk.Regularizer(pk.REG_TIKHONOV, 0.5), 0.05, 12)
+        assert prob.epochs == ost.epochs
+        assert rel(host(prob.x_cur), ost.x) <= 1e-4
+        assert rel(host(prob.y_cur), ost.y) <= 1e-4
+        x0, k0 = host(prob.x_cur), prob.k
+        prob.step(0)
+        prob.solve(0.0, pk.BUDGET_EPOCHS)
+        assert prob.k == k0 and np.array_equal(host(prob.x_cur), x0)
+    pk.step_many([], 3)

@@ -203,3 +203,38 @@ def test_independent_draws_limits():
     assert _abi.lib().imask_step(1, ctypes.byref(g), ctypes.byref(lv), ctypes.byref(reg), ctypes.byref(prm), b,
                                  ctypes.byref(s), 1, None) == _abi.ENOTSUP
 
+
+
+def test_remaining_entry_points_validate_before_any_launch():
+    """Every entry point rejects bad arguments with IMASK_EINVAL (or ESIZE)
+    before it touches the device; the pointers passed are never dereferenced."""
+    L = _abi.lib()
+    g = _abi.Geometry(64, 10, 12, 0.0, 0.0)
+    gr = ctypes.byref(g)
+    lv = im.Levels((0, 1), (0.5, 0.5)).c()
+    P = ctypes.c_void_p
+    a, b2, w = P(16), P(32), P(4096)
+    need = L.imask_workspace_bytes(gr)
+    assert L.imask_prepare(gr, None, need, None) == _abi.EINVAL
+    assert L.imask_prepare(gr, w, need - 1, None) == _abi.ESIZE
+    for bad in (-1, 7):
+        assert L.imask_project(gr, bad, w, a, b2, None) == _abi.EINVAL
+        assert L.imask_backproject(gr, bad, w, a, b2, None) == _abi.EINVAL
+    assert L.imask_resample(64, 1, _abi.RESTRICT, None, a, a, None) == _abi.EINVAL     # in == out
+    assert L.imask_resample(64, 7, _abi.RESTRICT, None, a, b2, None) == _abi.EINVAL    # too deep
+    assert L.imask_resample(64, 1, 99, None, a, b2, None) == _abi.EINVAL               # unknown mode
+    assert L.imask_resample(63, 1, _abi.RESTRICT, None, a, b2, None) == _abi.EINVAL    # bad side
+    for k in (-1, 2):
+        assert L.imask_sketch_apply(gr, ctypes.byref(lv), k, 0, w, a, b2, None) == _abi.EINVAL
+    assert L.imask_sketch_apply(gr, ctypes.byref(lv), 0, 0, w, a, a, None) == _abi.EINVAL
+    ms = ctypes.c_double()
+    assert L.imask_time_kernel(gr, 0, 0, w, a, b2, 0, None, ctypes.byref(ms)) == _abi.EINVAL   # reps
+    assert L.imask_time_kernel(gr, 7, 0, w, a, b2, 3, None, ctypes.byref(ms)) == _abi.EINVAL   # which
+    assert L.imask_time_kernel(gr, 0, 9, w, a, b2, 3, None, ctypes.byref(ms)) == _abi.EINVAL   # level
+    out = (ctypes.c_double * 3)()
+    assert L.imask_step_constants(gr, ctypes.byref(lv), 0.0, 10, 1, w, a, out, None) == _abi.EINVAL
+    assert L.imask_step_constants(gr, ctypes.byref(lv), 1.0, 0, 1, w, a, out, None) == _abi.EINVAL
+    draws = (ctypes.c_int32 * 4)()
+    prm = _abi.Params(0.01, 1, 0)
+    assert L.imask_draws(ctypes.byref(prm), ctypes.byref(lv), 0, -1, draws) == _abi.EINVAL
+    assert L.imask_draws(ctypes.byref(prm), ctypes.byref(lv), 0, 4, draws) == _abi.OK

@@ -96,6 +96,18 @@ def lib():
                                                 ctypes.c_uint64, _D, ctypes.c_int,
                                                 _D, _D, _D, _D, _D, _I32, _I32, _D]
         L.orc_imask_indep_run.restype = ctypes.c_int
+        L.orc_block_rows.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _I32, _I32]
+        L.orc_block_rows.restype = None
+        L.orc_block_draws.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int,
+                                      ctypes.c_int, _I32]
+        L.orc_block_draws.restype = None
+        L.orc_imask_blocks_run.argtypes = geo + [ctypes.c_int, _I32, _D, ctypes.c_int, ctypes.c_int,
+                                                 ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                                 ctypes.c_double, ctypes.c_int,
+                                                 ctypes.c_double, ctypes.c_uint64, ctypes.c_uint32,
+                                                 ctypes.c_uint64, _D, ctypes.c_int,
+                                                 _D, _D, _D, _D, _D, _I32, _I32, _D]
+        L.orc_imask_blocks_run.restype = ctypes.c_int
     return _lib
 
 
@@ -335,6 +347,64 @@ def imask_run(g: Geometry, lv: Levels, reg: Reg, sigma: float, seed: int, stream
     st.k += n_iter
     st.epochs = float(ep[0])
     st.draws.extend(int(v) for v in dr[:n_iter])
+    return st
+
+
+def block_rows(n_angles: int, n_blocks: int, j: int) -> tuple:
+    """Angles [a0, a1) of measurement block j (contiguous blocks)."""
+    a0, a1 = ctypes.c_int32(), ctypes.c_int32()
+    lib().orc_block_rows(n_angles, n_blocks, j, ctypes.byref(a0), ctypes.byref(a1))
+    return a0.value, a1.value
+
+
+def block_draws(seed: int, stream: int, k0: int, count: int, n_blocks: int) -> list:
+    out = np.empty(max(count, 1), dtype=np.int32)
+    lib().orc_block_draws(seed, stream, k0, count, n_blocks, out.ctypes.data_as(_I32))
+    return [int(v) for v in out[:count]]
+
+
+@dataclass
+class BlocksState(State):
+    """State of Alg. 1 over image sketches x measurement blocks: phi has one
+    full image per (sketch i, block j) pair, index i * n_blocks + j."""
+    blocks: list = field(default_factory=list)
+
+    @staticmethod
+    def zeros(g: Geometry, lv: Levels, n_blocks: int = 1) -> "BlocksState":
+        return BlocksState(np.zeros((g.n, g.n)), np.zeros((g.n_angles, g.n_det)),
+                           np.zeros((lv.r * n_blocks, g.n, g.n)), np.zeros((lv.r, g.n_angles, g.n_det)),
+                           xbar=np.zeros((g.n, g.n)), tvd=np.zeros((2, g.n, g.n)))
+
+    def copy(self) -> "BlocksState":
+        c = BlocksState(self.x.copy(), self.y.copy(), self.phi.copy(), self.psi.copy(), self.k, self.epochs,
+                        list(self.draws), None if self.xbar is None else self.xbar.copy(),
+                        None if self.tvd is None else self.tvd.copy())
+        c.blocks = list(self.blocks)
+        return c
+
+
+def imask_blocks_run(g: Geometry, lv: Levels, reg: Reg, sigma: float, seed: int, stream: int, n_blocks: int,
+                     b, n_iter: int, state: BlocksState | None = None) -> BlocksState:
+    """Alg. 1 over the product sketches K_ij = S E_j K_i (S = n_blocks
+    contiguous angle blocks, uniform block draws), n_iter iterations."""
+    st = BlocksState.zeros(g, lv, n_blocks) if state is None else state.copy()
+    st.ensure(g)
+    b = _f64(b)
+    lf, pp = lv.carrays()
+    dr = np.empty(max(n_iter, 1), dtype=np.int32)
+    bl = np.empty(max(n_iter, 1), dtype=np.int32)
+    ep = np.array([st.epochs])
+    rc = lib().orc_imask_blocks_run(*g.args(), lv.r, lf.ctypes.data_as(_I32), _dp(pp), lv.mode, n_blocks,
+                                    reg.kind, reg.lam, reg.tv_weight, reg.tv_eps, reg.tv_inner,
+                                    sigma, seed, stream, st.k, _dp(b), n_iter,
+                                    _dp(st.x), _dp(st.y), _dp(st.phi), _dp(st.psi), _dp(st.tvd),
+                                    dr.ctypes.data_as(_I32), bl.ctypes.data_as(_I32), _dp(ep))
+    if rc != 0:
+        raise ValueError("oracle rejected the level set or block count")
+    st.k += n_iter
+    st.epochs = float(ep[0])
+    st.draws.extend(int(v) for v in dr[:n_iter])
+    st.blocks.extend(int(v) for v in bl[:n_iter])
     return st
 
 

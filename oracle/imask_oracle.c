@@ -749,3 +749,105 @@ int orc_imask_indep_run(int n, int na, int nd, double ds, double s0, double E, c
     return 0;
 }
 
+
+/* ------------------------------------------------------ measurement blocks */
+
+/* Image sketches combined with measurement sub-selection (the paper's
+ * outlook, Sec. 6), read as Alg. 1 over the product family
+ *   K_{ij} = S E_j K_i,   i ~ p,  j uniform over S blocks (q_j = 1/S),
+ * with E_j keeping the rows of angle block j = [floor(j na/S),
+ * floor((j+1) na/S)) and zeroing the others, so sum_ij p_i q_j K_ij =
+ * sum_i p_i K_i.  Block j of draw k comes from the low word of the same
+ * SplitMix64 output whose high word picks i: j = (lo32 * S) >> 32.
+ * Tables: phi_{ij} = K_ij^T y (one full image per pair, index i S + j);
+ * psi_i holds K_ij x on the rows of every block j (one m-table per i).
+ * The dual estimate is dense: zeta = E_j (K_ij x - psi_i) + sum_i' p_i'/S
+ * psi_i' on every row; only block j's rows of psi_i are refreshed.
+ * A step costs c(i) (a1 - a0) / na epochs.  S = 1 is Alg. 1. */
+void orc_block_rows(int na, int S, int j, int* a0, int* a1)
+{
+    *a0 = (int)(((long)j * na) / S);
+    *a1 = (int)(((long)(j + 1) * na) / S);
+}
+
+void orc_block_draws(uint64_t seed, uint32_t stream, uint64_t k0, int count, int S, int32_t* out)
+{
+    const uint64_t ss = orc_splitmix64(seed, stream);
+    for (int q = 0; q < count; ++q) {
+        const uint64_t lo = orc_splitmix64(ss, k0 + (uint64_t)q) & 0xffffffffULL;
+        out[q] = (int32_t)((lo * (uint64_t)S) >> 32);
+    }
+}
+
+int orc_imask_blocks_run(int n, int na, int nd, double ds, double s0, double E, const double* ang,
+                         int r, const int* log2f, const double* p, int mode, int S,
+                         int reg_kind, double lam, double tv_w, double tv_eps, int tv_inner,
+                         double sigma, uint64_t seed, uint32_t stream, uint64_t k0,
+                         const double* bdata, int n_iter,
+                         double* x, double* y, double* phi, double* psi, double* tvd,
+                         int32_t* draws_out, int32_t* blocks_out, double* epochs)
+{
+    if (r < 1 || r > ORC_MAX_LEVELS || log2f[0] != 0 || S < 1 || S > na) return -1;
+    const long d = (long)n * n, m = (long)na * nd;
+    const double tau = sigma / lam;
+    double* gx = (double*)malloc(sizeof(double) * d);
+    double* gy = (double*)malloc(sizeof(double) * m);
+    double* yj = (double*)malloc(sizeof(double) * m);
+    double* xi = (double*)malloc(sizeof(double) * d);
+    double* zeta = (double*)malloc(sizeof(double) * m);
+    double* xn = (double*)malloc(sizeof(double) * d);
+    double* v = (double*)malloc(sizeof(double) * d);
+    const int cnt = n_iter > 0 ? n_iter : 1;
+    int32_t* idx = (int32_t*)malloc(sizeof(int32_t) * cnt);
+    int32_t* jdx = (int32_t*)malloc(sizeof(int32_t) * cnt);
+    orc_draws(seed, stream, k0, n_iter, r, p, idx);
+    orc_block_draws(seed, stream, k0, n_iter, S, jdx);
+    double unbiased_full = 1.0;
+    for (int k = 1; k < r; ++k) unbiased_full += ldexp(1.0, -log2f[k]);
+    for (int it = 0; it < n_iter; ++it) {
+        const int k = idx[it], j = jdx[it];
+        int a0, a1;
+        orc_block_rows(na, S, j, &a0, &a1);
+        const long e0 = (long)a0 * nd, e1 = (long)a1 * nd;
+        /* K_kj^T y = S K_k^T E_j y and K_kj x = S E_j K_k x, old iterates */
+        for (long e = 0; e < m; ++e) yj[e] = (e >= e0 && e < e1) ? y[e] : 0.0;
+        orc_sketch_adj(n, na, nd, ds, s0, E, ang, r, log2f, p, mode, k, yj, gx);
+        for (long q = 0; q < d; ++q) gx[q] *= S;
+        orc_sketch_fwd(n, na, nd, ds, s0, E, ang, r, log2f, p, mode, k, x, gy);
+        for (long e = 0; e < m; ++e) gy[e] = (e >= e0 && e < e1) ? S * gy[e] : 0.0;
+        /* SAGA estimates with the old tables */
+        for (long q = 0; q < d; ++q) {
+            double avg = 0.0;
+            for (int c = 0; c < r; ++c)
+                for (int b = 0; b < S; ++b) avg += p[c] / S * phi[((long)c * S + b) * d + q];
+            xi[q] = gx[q] - phi[((long)k * S + j) * d + q] + avg;
+        }
+        for (long e = 0; e < m; ++e) {
+            double avg = 0.0;
+            for (int c = 0; c < r; ++c) avg += p[c] / S * psi[(long)c * m + e];
+            zeta[e] = (e >= e0 && e < e1) ? gy[e] - psi[(long)k * m + e] + avg : avg;
+        }
+        for (long q = 0; q < d; ++q) v[q] = x[q] - tau * xi[q];
+        orc_prox(n, reg_kind, tau, lam, tv_w, tv_eps, tv_inner, v, x, tvd, xn);
+        for (long e = 0; e < m; ++e) y[e] = (y[e] + sigma * zeta[e] - sigma * bdata[e]) / (1.0 + sigma);
+        memcpy(x, xn, sizeof(double) * d);
+        memcpy(phi + ((long)k * S + j) * d, gx, sizeof(double) * d);
+        memcpy(psi + (long)k * m + e0, gy + e0, sizeof(double) * (e1 - e0));
+        if (draws_out) draws_out[it] = k;
+        if (blocks_out) blocks_out[it] = j;
+        if (epochs) {
+            const double c = (k == 0 && mode == ORC_MODE_UNBIASED) ? unbiased_full : ldexp(1.0, -log2f[k]);
+            *epochs += c * (double)(a1 - a0) / na;
+        }
+    }
+    free(gx);
+    free(gy);
+    free(yj);
+    free(xi);
+    free(zeta);
+    free(xn);
+    free(v);
+    free(idx);
+    free(jdx);
+    return 0;
+}

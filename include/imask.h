@@ -42,6 +42,7 @@ extern "C" {
 #define IMASK_MAX_LEVELS 8   /* sketches per level set (r) */
 #define IMASK_MAX_LOG2F 6    /* coarsest level: 2^6 downsampling */
 #define IMASK_MAX_TV_INNER 12
+#define IMASK_MAX_BLOCKS 1024 /* measurement blocks (imask_levels.n_blocks) */
 
 enum {
     IMASK_OK = 0,
@@ -100,12 +101,27 @@ typedef struct {
  *                       (the paper's construction; cost 1 epoch)
  *   IMASK_FULL_UNBIASED K_0 = p_0^{-1}(R_0 - sum_{k>0} p_k R_{l_k} T_{l_k}),
  *                       so that sum_k p_k K_k = R_0 exactly
- *                       (cost 1 + sum_{k>0} 2^{-l_k} epochs). */
+ *                       (cost 1 + sum_{k>0} 2^{-l_k} epochs).
+ * n_blocks = S > 1 combines the image sketches with measurement
+ * sub-selection (the outlook of Sec. 6), read as Alg. 1 over the sketches
+ * K_kb = S E_b K_k: the angles form S contiguous blocks, block b = angles
+ * [floor(b n_angles / S), floor((b+1) n_angles / S)), E_b keeps its rows,
+ * and each step draws b uniformly from the low 32 bits of the same
+ * generator output whose high bits pick k (b = (lo32 * S) >> 32).  phi
+ * then holds S copies of the r tables (block b's at b * sum_k N_{l_k}^2),
+ * psi stays r sinograms (block b's rows of table k hold K_kb x), the dual
+ * step still updates every row, and a step costs its sketch's cost times
+ * its block's share of the angles.  Read by imask_step / imask_solve
+ * (parallel schedule, full tables, common draws and the default angles;
+ * IMASK_ENOTSUP otherwise), imask_phi_floats and imask_block_draws; the
+ * other calls apply the level sketches alone.  0 or 1: no blocks;
+ * 2 .. min(n_angles, IMASK_MAX_BLOCKS), else IMASK_EINVAL. */
 typedef struct {
     int32_t r;
     int32_t log2f[IMASK_MAX_LEVELS];
     double p[IMASK_MAX_LEVELS];
     int32_t full_mode;
+    int32_t n_blocks;
 } imask_levels;
 
 /* Regulariser R, mu-strongly convex with mu = lambda (Sec. 2.2, Sec. 4.2):
@@ -208,8 +224,14 @@ typedef struct {
 /* Bytes of device workspace needed for geometry g (host function). */
 size_t imask_workspace_bytes(const imask_geometry* g);
 
-/* Floats in the phi table for level set lv (host function). */
+/* Floats in the phi table for level set lv (host function): sum over the
+ * sketches of N_{l_k}^2, times n_blocks when that is above 1. */
 size_t imask_phi_floats(const imask_geometry* g, const imask_levels* lv);
+
+/* Measurement blocks b_k of draws k = k0 .. k0+count-1 (host function; all 0
+ * without blocks), the companions of the sketch indices of imask_draws. */
+int imask_block_draws(const imask_params* prm, const imask_levels* lv, uint64_t k0, int32_t count,
+                      int32_t* out_host);
 
 /* Fills `work` (device, work_bytes >= imask_workspace_bytes(g)) with the
  * per-(level, angle) projector constants and zeroes its scratch.  Every

@@ -9,6 +9,6 @@ from ._abi import (  # noqa: F401
     LIB_PATH, KERNEL_FORWARD, KERNEL_TRANSPOSE,
 )
 from .imask import (  # noqa: F401
-    Geometry, Levels, Params, Problem, Regularizer, backproject, draws, project, resample,
+    Geometry, Levels, Params, Problem, Regularizer, backproject, block_draws, draws, project, resample,
     sigma_balamurugan, sigma_thm3, sketch_apply, step_constants, step_many, time_kernel, workspace,
 )

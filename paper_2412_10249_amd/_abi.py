@@ -26,7 +26,7 @@ DRAW_COMMON, DRAW_INDEPENDENT = 0, 1
 EXPORTS = ["imask_workspace_bytes", "imask_phi_floats", "imask_prepare", "imask_project",
            "imask_backproject", "imask_resample", "imask_sketch_apply", "imask_draws",
            "imask_step", "imask_solve", "imask_time_kernel", "imask_constants_scratch_bytes",
-           "imask_step_constants", "imask_sigma_thm3", "imask_sigma_balamurugan"]
+           "imask_step_constants", "imask_sigma_thm3", "imask_sigma_balamurugan", "imask_block_draws"]
 KERNEL_FORWARD, KERNEL_TRANSPOSE = 0, 1
 
 
@@ -38,7 +38,7 @@ class Geometry(ctypes.Structure):
 
 class Levels(ctypes.Structure):
     _fields_ = [("r", ctypes.c_int32), ("log2f", ctypes.c_int32 * MAX_LEVELS),
-                ("p", ctypes.c_double * MAX_LEVELS), ("full_mode", ctypes.c_int32)]
+                ("p", ctypes.c_double * MAX_LEVELS), ("full_mode", ctypes.c_int32), ("n_blocks", ctypes.c_int32)]
 
 
 class Reg(ctypes.Structure):
@@ -84,6 +84,7 @@ def lib():
         L.imask_resample.argtypes = [i32, i32, i32, P(Levels), vp, vp, vp]
         L.imask_sketch_apply.argtypes = [P(Geometry), P(Levels), i32, i32, vp, vp, vp, vp]
         L.imask_draws.argtypes = [P(Params), P(Levels), ctypes.c_uint64, i32, P(i32)]
+        L.imask_block_draws.argtypes = [P(Params), P(Levels), ctypes.c_uint64, i32, P(i32)]
         L.imask_time_kernel.argtypes = [P(Geometry), i32, i32, vp, vp, vp, i32, vp, P(ctypes.c_double)]
         L.imask_constants_scratch_bytes.argtypes = [P(Geometry)]
         L.imask_constants_scratch_bytes.restype = sz

@@ -131,6 +131,7 @@ static bool levels_ok(const imask_levels* lv, int lmax)
         sum += lv->p[k];
     }
     if (std::fabs(sum - 1.0) > 1e-9) return false;
+    if (lv->n_blocks < 0 || lv->n_blocks > IMASK_MAX_BLOCKS) return false;
     return lv->full_mode == IMASK_FULL_PAPER || lv->full_mode == IMASK_FULL_UNBIASED;
 }
 
@@ -179,6 +180,23 @@ static int draw_one(const imask_params& prm, const uint64_t* thr, uint64_t k)
     int j = 0;
     while (u >= thr[j]) ++j;
     return j;
+}
+
+// Measurement block of draw k: the low word of the same output whose high
+// word picks the sketch, scaled to the block count.
+static int draw_block(const imask_params& prm, uint64_t k, int nblk)
+{
+    const uint64_t lo = mix_at(mix_at(prm.seed, prm.stream_id), k) & 0xffffffffULL;
+    return (int)((lo * (uint64_t)nblk) >> 32);
+}
+
+static int block_count(const imask_levels& lv) { return lv.n_blocks > 1 ? lv.n_blocks : 1; }
+
+// Angles [a0, a1) of measurement block j of nblk contiguous blocks.
+static void block_angles(int na, int nblk, int j, int* a0, int* a1)
+{
+    *a0 = (int)(((long long)j * na) / nblk);
+    *a1 = (int)(((long long)(j + 1) * na) / nblk);
 }
 
 static double sketch_cost(const imask_levels& lv, int k)
@@ -248,6 +266,8 @@ static void fwd_common(const Layout& L, const float* W, FwdArgs& fa)
     fa.n = L.n;
     fa.na = L.na;
     fa.nd = L.nd;
+    fa.e0 = 0;
+    fa.e1 = (long long)L.na * L.nd;
 }
 
 static BpArgs bp_args(const Layout& L, const float* W, int lvl, const float* y, float* out, float coef,
@@ -318,6 +338,14 @@ static int one_step(const imask_geometry& g, const Layout& L, const imask_levels
     const bool seq = prm.schedule == IMASK_SCHEDULE_SEQUENTIAL;
     const float* x_fwd = seq ? st.xbar : st.x[cur];
     const float* y_bp = seq ? st.y[nxt] : st.y[cur];
+    // measurement blocks (Sec. 6 outlook): this step's sketch is
+    // K_kb = S E_b K_k on the rows of angle block b, drawn uniformly
+    const int nblk = block_count(lv);
+    const int jb = nblk > 1 ? draw_block(prm, st.k, nblk) : 0;
+    int a0 = 0, a1 = g.n_angles;
+    if (nblk > 1) block_angles(g.n_angles, nblk, jb, &a0, &a1);
+    const AngleSplit blk_split = angle_split_range(g.n_angles, a0, a1);
+    const float blk_coef = (float)nblk;
 
     // a2-a4: restriction, forward projection, dual SAGA step and psi refresh
     PrepArgs pa;
@@ -338,7 +366,13 @@ static int one_step(const imask_geometry& g, const Layout& L, const imask_levels
     fa.psi = st.psi;
     fa.r = lv.r;
     fa.kidx = kd;
-    for (int j = 0; j < lv.r; ++j) fa.p[j] = (float)lv.p[j];
+    for (int j = 0; j < lv.r; ++j) fa.p[j] = (float)(lv.p[j] / nblk);
+    if (nblk > 1) {
+        for (int t = 0; t < fa.nterms; ++t) fa.term[t].coef *= blk_coef;
+        fa.split = blk_split;
+        fa.e0 = (long long)a0 * g.n_det;
+        fa.e1 = (long long)a1 * g.n_det;
+    }
     fa.sigma = (float)prm.sigma;
     fa.inv1ps = (float)(1.0 / (1.0 + prm.sigma));
     IMK_TRY(launch_prep(pa, s));
@@ -357,10 +391,15 @@ static int one_step(const imask_geometry& g, const Layout& L, const imask_levels
     for (int j = 0; j < lv.r; ++j) {
         pr.lvl[j] = lv.log2f[j];
         pr.p[j] = (float)lv.p[j];
+        pr.pavg[j] = (float)(lv.p[j] / nblk);
         pr.craw[j] = W + L.craw[lv.log2f[j]];
     }
     pr.phi = st.phi;
     phi_offsets(g, lv, pr.phi_off);
+    pr.nblk = nblk;
+    pr.jblk = jb;
+    pr.blk_stride = 0;
+    for (int j = 0; j < lv.r; ++j) pr.blk_stride += (long long)(g.n >> lv.log2f[j]) * (g.n >> lv.log2f[j]);
     pr.x_old = st.x[cur];
     pr.x_out = tv ? W + L.vbuf : st.x[nxt];
     pr.tau = (float)tau;
@@ -372,16 +411,17 @@ static int one_step(const imask_geometry& g, const Layout& L, const imask_levels
     // a5: raw backprojections R_l^T y needed by sketch k.  A sketch that
     // needs one (coarse, or the only level) takes the primal step in the
     // epilogue of that backprojection's ordered sum.
+    auto raw_bp = [&](int l) {  // R_l^T y (times S on the block's rows only)
+        BpArgs ba = bp_args(L, W, l, y_bp, W + L.craw[l], blk_coef, 0, 0);
+        if (nblk > 1) ba.split = blk_split;
+        return ba;
+    };
     if (k > 0 || lv.r == 1) {
-        const int l = lv.log2f[k];
-        IMK_TRY(launch_bp_primal(bp_args(L, W, l, y_bp, W + L.craw[l], 1.0f, 0, 0), pr, s));
+        IMK_TRY(launch_bp_primal(raw_bp(lv.log2f[k]), pr, s));
     } else {
-        if (int rc = backproject_raw(L, W, 0, y_bp, W + L.craw[0], 1.0f, 0, 0, s)) return rc;
+        IMK_TRY(launch_bp(raw_bp(0), s));
         if (lv.full_mode == IMASK_FULL_UNBIASED)
-            for (int j = 1; j < lv.r; ++j) {
-                const int l = lv.log2f[j];
-                if (int rc = backproject_raw(L, W, l, y_bp, W + L.craw[l], 1.0f, 0, 0, s)) return rc;
-            }
+            for (int j = 1; j < lv.r; ++j) IMK_TRY(launch_bp(raw_bp(lv.log2f[j]), s));
         IMK_TRY(launch_primal(pr, s));
     }
 
@@ -425,7 +465,10 @@ static int one_step(const imask_geometry& g, const Layout& L, const imask_levels
 
     st.cur = nxt;
     st.k += 1;
-    st.epochs += kd == k ? sketch_cost(lv, k) : 0.5 * (sketch_cost(lv, k) + sketch_cost(lv, kd));
+    if (nblk > 1)
+        st.epochs += sketch_cost(lv, k) * (double)(a1 - a0) / g.n_angles;
+    else
+        st.epochs += kd == k ? sketch_cost(lv, k) : 0.5 * (sketch_cost(lv, k) + sketch_cost(lv, kd));
     return IMASK_OK;
 }
 
@@ -443,13 +486,22 @@ size_t imask_workspace_bytes(const imask_geometry* g)
 
 size_t imask_phi_floats(const imask_geometry* g, const imask_levels* lv)
 {
-    if (!geometry_ok(g) || !levels_ok(lv, level_limit(g->n))) return 0;
+    if (!geometry_ok(g) || !levels_ok(lv, level_limit(g->n)) || lv->n_blocks > g->n_angles) return 0;
     size_t t = 0;
     for (int k = 0; k < lv->r; ++k) {
         const size_t nl = (size_t)(g->n >> lv->log2f[k]);
         t += nl * nl;
     }
-    return t;
+    return t * (size_t)block_count(*lv);
+}
+
+int imask_block_draws(const imask_params* prm, const imask_levels* lv, uint64_t k0, int32_t count, int32_t* out_host)
+{
+    if (!prm || !lv || !out_host || count < 0) return IMASK_EINVAL;
+    if (!levels_ok(lv, IMASK_MAX_LOG2F)) return IMASK_EINVAL;
+    const int nblk = block_count(*lv);
+    for (int32_t q = 0; q < count; ++q) out_host[q] = nblk > 1 ? draw_block(*prm, k0 + (uint64_t)q, nblk) : 0;
+    return IMASK_OK;
 }
 
 int imask_prepare(const imask_geometry* g, void* work, size_t work_bytes, void* stream)
@@ -891,6 +943,10 @@ static int check_problem(const imask_geometry* g, const imask_levels* lv, const 
     } else if (prm->draw_mode != IMASK_DRAW_COMMON) {
         return IMASK_EINVAL;
     }
+    if (lv->n_blocks > g->n_angles) return IMASK_EINVAL;
+    if (lv->n_blocks > 1 && (prm->schedule != IMASK_SCHEDULE_PARALLEL || s->ztab ||
+                             prm->draw_mode != IMASK_DRAW_COMMON || g->angles))
+        return IMASK_ENOTSUP;
     if (prm->schedule == IMASK_SCHEDULE_SEQUENTIAL) {
         if (!(prm->theta >= 0.0 && prm->theta <= 1.0) || !s->xbar) return IMASK_EINVAL;
         if (s->xbar == s->x[0] || s->xbar == s->x[1]) return IMASK_EINVAL;

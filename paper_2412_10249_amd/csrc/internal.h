@@ -36,24 +36,48 @@ constexpr int kPadL = 4;
 constexpr int kPad = 2 * kPadL;
 
 // Angle lists of the two stepping directions.  Default angles a*pi/na:
-// row-stepping angles are 0..n_lo-1 and a_hi0..na-1, column-stepping angles
-// n_lo..a_hi0-1.  Listed angles: perm (device) holds the nrow row-stepping
-// angle indices, then the ncol column-stepping ones, each ascending, and
-// rows[a] (device) is 1 for a row-stepping angle; both are null by default.
+// the row-stepping angles are s0a..s0a+n0a-1 and s0b..s0b+(nrow-n0a)-1, the
+// column-stepping ones s1..s1+ncol-1 (for all angles: 0..n_lo-1 and
+// a_hi0..na-1, and n_lo..a_hi0-1; a measurement block takes the part of
+// each range inside its angles).  Listed angles: perm (device) holds the
+// nrow row-stepping angle indices, then the ncol column-stepping ones, each
+// ascending, and rows[a] (device) is 1 for a row-stepping angle; both are
+// null by default.
 struct AngleSplit {
-    int n_lo, a_hi0, nrow, ncol;
+    int s0a, n0a, s0b, nrow, s1, ncol;
     const int* perm;
     const int* rows;
 };
 inline AngleSplit angle_split(int na)
 {
+    int n_lo = na / 4 + 1;
+    int a_hi0 = (3 * na + 3) / 4;
+    if (n_lo > na) n_lo = na;
+    if (a_hi0 < n_lo) a_hi0 = n_lo;
     AngleSplit s{};
-    s.n_lo = na / 4 + 1;
-    s.a_hi0 = (3 * na + 3) / 4;
-    if (s.n_lo > na) s.n_lo = na;
-    if (s.a_hi0 < s.n_lo) s.a_hi0 = s.n_lo;
-    s.nrow = s.n_lo + (na - s.a_hi0);
-    s.ncol = s.a_hi0 - s.n_lo;
+    s.s0a = 0;
+    s.n0a = n_lo;
+    s.s0b = a_hi0;
+    s.nrow = n_lo + (na - a_hi0);
+    s.s1 = n_lo;
+    s.ncol = a_hi0 - n_lo;
+    return s;
+}
+// The default angles a0..a1-1 (a measurement block) split the same way.
+inline AngleSplit angle_split_range(int na, int a0, int a1)
+{
+    const AngleSplit f = angle_split(na);
+    auto clip = [](int lo, int hi, int b0, int b1, int* start) {
+        *start = lo > b0 ? lo : b0;
+        const int end = hi < b1 ? hi : b1;
+        return end > *start ? end - *start : 0;
+    };
+    AngleSplit s{};
+    int nb;
+    s.n0a = clip(f.s0a, f.s0a + f.n0a, a0, a1, &s.s0a);
+    nb = clip(f.s0b, na, a0, a1, &s.s0b);
+    s.nrow = s.n0a + nb;
+    s.ncol = clip(f.s1, f.s1 + f.ncol, a0, a1, &s.s1);
     return s;
 }
 
@@ -122,6 +146,9 @@ struct FwdArgs {
     int r, kidx, compact;
     float p[IMASK_MAX_LEVELS];
     float sigma, inv1ps;
+    // sinogram elements [e0, e1) hold this step's measurement block: outside
+    // it the projection is zero and psi is not refreshed (all of m by default)
+    long long e0, e1;
 };
 
 struct FwdBandArgs {
@@ -198,6 +225,13 @@ struct PrimalArgs {
     float tau, prox_scale;
     float* xbar;  // when set: xbar = x_out + theta (x_out - x_old)
     float theta;
+    // measurement blocks: phi holds nblk copies of the r tables, block b's
+    // at b * blk_stride; this step refreshes block jblk's table kidx.  The
+    // table average weighs table (c, b) by pavg[c] = p[c] / nblk; p itself
+    // builds the sketches (compensation, UNBIASED combination)
+    int nblk, jblk;
+    long long blk_stride;
+    float pavg[IMASK_MAX_LEVELS];
 };
 
 struct TvArgs {

@@ -185,7 +185,7 @@ __global__ void __launch_bounds__(256) k_prep(PrepArgs a)
 __device__ __forceinline__ int angle_of(const AngleSplit& sp, int pass, int k)
 {
     if (sp.perm) return sp.perm[pass == 0 ? k : sp.nrow + k];
-    return pass == 0 ? (k < sp.n_lo ? k : sp.a_hi0 + (k - sp.n_lo)) : sp.n_lo + k;
+    return pass == 0 ? (k < sp.n0a ? sp.s0a + k : sp.s0b + (k - sp.n0a)) : sp.s1 + k;
 }
 
 // Steps lo..hi (clamped to [s0, s1]) at which ray b's coordinate can reach
@@ -397,11 +397,14 @@ __global__ void __launch_bounds__(256) k_fwd_reduce(FwdArgs a)
             a.y_new[e] = (a.y_old[e] + a.sigma * zeta - a.sigma * a.bdat[e]) * a.inv1ps;
             a.psi[e] = fmaf(a.p[a.kidx], total, avg);
         } else {
+            // outside this step's measurement block the sketch is zero and
+            // so is its table: zeta is the table average alone
+            const bool in = (long long)e >= a.e0 && (long long)e < a.e1;
             float avg = 0.0f;
             for (int j = 0; j < a.r; ++j) avg = fmaf(a.p[j], a.psi[(size_t)j * m + e], avg);
-            const float zeta = (total - a.psi[(size_t)a.kidx * m + e]) + avg;
+            const float zeta = in ? (total - a.psi[(size_t)a.kidx * m + e]) + avg : avg;
             a.y_new[e] = (a.y_old[e] + a.sigma * zeta - a.sigma * a.bdat[e]) * a.inv1ps;
-            a.psi[(size_t)a.kidx * m + e] = total;
+            if (in) a.psi[(size_t)a.kidx * m + e] = total;
         }
     }
 }
@@ -467,10 +470,13 @@ __global__ void __launch_bounds__(256) k_fwd_reduce4(FwdArgs a)
                 ld4(a.psi + (size_t)a.kidx * m + e, ps);
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
-                    const float zeta = (total[c] - ps[c]) + avg[c];
+                    // outside the measurement block: zeta is the average alone
+                    const bool in = (long long)(e + c) >= a.e0 && (long long)(e + c) < a.e1;
+                    const float zeta = in ? (total[c] - ps[c]) + avg[c] : avg[c];
                     yn[c] = (yo[c] + a.sigma * zeta - a.sigma * bd[c]) * a.inv1ps;
+                    if (in) ps[c] = total[c];
                 }
-                st4(a.psi + (size_t)a.kidx * m + e, total);
+                st4(a.psi + (size_t)a.kidx * m + e, ps);
             }
             st4(a.y_new + e, yn);
         }
@@ -882,7 +888,7 @@ __global__ void __launch_bounds__(1024) k_bp_sum_primal(BpOwnArgs a, int S, Prim
 #pragma unroll
     for (int c = 0; c < V; ++c) red[threadIdx.x * V + c] = sum[c];
     __syncthreads();
-    const long long koff = p.phi_off[p.kidx];
+    const long long koff = p.jblk * p.blk_stride + p.phi_off[p.kidx];
     const int ncell = (int)min((size_t)per * V, d - min(d, e0));
     // slice sums in slice order, one cell per thread
     for (int t = threadIdx.x; t < ncell; t += blockDim.x) {
@@ -906,18 +912,18 @@ __global__ void __launch_bounds__(1024) k_bp_sum_primal(BpOwnArgs a, int S, Prim
         const float g = gsh[c];
         float avg = 0.0f, ownv = 0.0f;
         for (int cc = 0; cc < p.r; ++cc) {
-            float ph;
-            if (cc == p.kidx) {
-                ph = own[c];
-                ownv = ph;
-            } else if (cc == 0) {
-                ph = p.phi[p.phi_off[0] + pix];
-            } else {
-                const int lc = p.lvl[cc];
-                const int nc = p.n >> lc;
-                ph = p.phi[p.phi_off[cc] + (size_t)(i >> lc) * nc + (j >> lc)];
+            const int lc = p.lvl[cc];
+            const size_t cell = cc == 0 ? pix : (size_t)(i >> lc) * (p.n >> lc) + (j >> lc);
+            for (int bb = 0; bb < p.nblk; ++bb) {  // one table per measurement block
+                float ph;
+                if (cc == p.kidx && bb == p.jblk) {
+                    ph = own[c];
+                    ownv = ph;
+                } else {
+                    ph = p.phi[bb * p.blk_stride + p.phi_off[cc] + cell];
+                }
+                avg = fmaf(p.pavg[cc], ph, avg);
             }
-            avg = fmaf(p.p[cc], ph, avg);
         }
         const float xi = (g - ownv) + avg;
         const float xo = p.x_old[pix];
@@ -983,23 +989,20 @@ __global__ void __launch_bounds__(256) k_primal(PrimalArgs a)
         }
         float avg = 0.0f, own = 0.0f;
         for (int c = 0; c < a.r; ++c) {
-            float ph;
-            if (c == 0) {
-                ph = a.phi[a.phi_off[0] + pix];
-            } else {
-                const int l = a.lvl[c];
-                const int nl = a.n >> l;
-                ph = a.phi[a.phi_off[c] + (size_t)(i >> l) * nl + (j >> l)];
+            const int l = a.lvl[c];
+            const size_t cell = c == 0 ? pix : (size_t)(i >> l) * (a.n >> l) + (j >> l);
+            for (int b = 0; b < a.nblk; ++b) {  // one table per measurement block
+                const float ph = a.phi[b * a.blk_stride + a.phi_off[c] + cell];
+                avg = fmaf(a.pavg[c], ph, avg);
+                if (c == a.kidx && b == a.jblk) own = ph;
             }
-            avg = fmaf(a.p[c], ph, avg);
-            if (c == a.kidx) own = ph;
         }
         const float xi = (g - own) + avg;
         const float xo = a.x_old[pix];
         const float xn = (xo - a.tau * xi) * a.prox_scale;
         a.x_out[pix] = xn;
         if (a.xbar) a.xbar[pix] = xn + a.theta * (xn - xo);
-        if (a.kidx == 0) a.phi[a.phi_off[0] + pix] = g;
+        if (a.kidx == 0) a.phi[a.jblk * a.blk_stride + a.phi_off[0] + pix] = g;
     }
     if (a.kidx > 0) {
         __syncthreads();  // every old phi_k value of this tile has been read
@@ -1009,7 +1012,7 @@ __global__ void __launch_bounds__(256) k_primal(PrimalArgs a)
         for (int qq = threadIdx.x; qq < tl * tl; qq += blockDim.x) {
             const int ci = ty * tl + qq / tl, cj = tx * tl + (qq % tl);
             const size_t c = (size_t)ci * nl + cj;
-            a.phi[a.phi_off[a.kidx] + c] = a.craw[a.kidx][c] * s;
+            a.phi[a.jblk * a.blk_stride + a.phi_off[a.kidx] + c] = a.craw[a.kidx][c] * s;
         }
     }
 }

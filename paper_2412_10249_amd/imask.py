@@ -70,10 +70,12 @@ class Geometry:
 
 @dataclass(frozen=True)
 class Levels:
-    """Resolution set (log2 factors, first 0) and probabilities p."""
+    """Resolution set (log2 factors, first 0), probabilities p, and the
+    number of measurement blocks combined with the image sketches (1: none)."""
     log2f: tuple
     p: tuple
     full_mode: int = _abi.FULL_PAPER
+    n_blocks: int = 1
 
     def c(self) -> _abi.Levels:
         lv = _abi.Levels()
@@ -82,6 +84,7 @@ class Levels:
             lv.log2f[k] = int(l)
             lv.p[k] = float(pk)
         lv.full_mode = int(self.full_mode)
+        lv.n_blocks = int(self.n_blocks)
         return lv
 
     @property
@@ -89,9 +92,9 @@ class Levels:
         return len(self.log2f)
 
     @staticmethod
-    def uniform(log2f, full_mode: int = _abi.FULL_PAPER) -> "Levels":
+    def uniform(log2f, full_mode: int = _abi.FULL_PAPER, n_blocks: int = 1) -> "Levels":
         r = len(log2f)
-        return Levels(tuple(log2f), tuple([1.0 / r] * r), full_mode)
+        return Levels(tuple(log2f), tuple([1.0 / r] * r), full_mode, n_blocks)
 
 
 @dataclass(frozen=True)
@@ -237,6 +240,14 @@ def draws(params: Params, levels: Levels, k0: int, count: int) -> np.ndarray:
     return np.frombuffer(out, dtype=np.int32, count=count).copy()
 
 
+def block_draws(params: Params, levels: Levels, k0: int, count: int) -> np.ndarray:
+    """Measurement blocks of draws k0 .. k0+count-1 (all 0 without blocks)."""
+    out = (ctypes.c_int32 * max(count, 1))()
+    check(lib().imask_block_draws(ctypes.byref(params.c()), ctypes.byref(levels.c()), k0, count, out),
+          "imask_block_draws")
+    return np.frombuffer(out, dtype=np.int32, count=count).copy()
+
+
 @dataclass
 class Problem:
     """Device-resident ImaSk state for one reconstruction (Alg. 1 INPUT)."""
@@ -322,9 +333,11 @@ class Problem:
         self._absorb(s)
         check(rc, "imask_solve")
 
-    def phi_tables(self):
-        """The table as a list of images: sketch 0 full size, k > 0 coarse."""
-        out, off = [], 0
+    def phi_tables(self, block: int = 0):
+        """The table as a list of images: sketch 0 full size, k > 0 coarse
+        (with measurement blocks, the tables of one block)."""
+        per = sum((self.geom.n >> l) ** 2 for l in self.levels.log2f)
+        out, off = [], block * per
         for l in self.levels.log2f:
             nl = self.geom.n >> l
             out.append(self.phi[off:off + nl * nl].view(nl, nl))

@@ -238,3 +238,32 @@ def test_remaining_entry_points_validate_before_any_launch():
     prm = _abi.Params(0.01, 1, 0)
     assert L.imask_draws(ctypes.byref(prm), ctypes.byref(lv), 0, -1, draws) == _abi.EINVAL
     assert L.imask_draws(ctypes.byref(prm), ctypes.byref(lv), 0, 4, draws) == _abi.OK
+
+
+def test_measurement_blocks_validated():
+    L = _abi.lib()
+    g = _abi.Geometry(64, 10, 12, 0.0, 0.0)
+    base = L.imask_phi_floats(ctypes.byref(g), ctypes.byref(im.Levels((0, 1), (0.5, 0.5)).c()))
+    assert L.imask_phi_floats(ctypes.byref(g), ctypes.byref(im.Levels((0, 1), (0.5, 0.5), 0, 3).c())) == 3 * base
+    assert L.imask_phi_floats(ctypes.byref(g), ctypes.byref(im.Levels((0, 1), (0.5, 0.5), 0, 11).c())) == 0
+    assert L.imask_phi_floats(ctypes.byref(g), ctypes.byref(im.Levels((0, 1), (0.5, 0.5), 0, -2).c())) == 0
+    lv = im.Levels((0, 1), (0.5, 0.5), 0, 3).c()
+    reg = _abi.Reg(_abi.REG_TIKHONOV, 0.01, 0.0, 1e-3, 10)
+    s = _abi.State()
+    s.x[0], s.x[1], s.y[0], s.y[1] = 16, 32, 48, 64
+    s.phi, s.psi, s.work, s.xbar = 80, 96, 112, 128
+    b = (ctypes.c_void_p * 1)(16)
+    for prm in (_abi.Params(0.01, 1, 0, _abi.SCHEDULE_SEQUENTIAL, 1.0),
+                _abi.Params(0.01, 1, 0, _abi.SCHEDULE_PARALLEL, 1.0, _abi.DRAW_INDEPENDENT, 1)):
+        assert L.imask_step(1, ctypes.byref(g), ctypes.byref(lv), ctypes.byref(reg), ctypes.byref(prm), b,
+                            ctypes.byref(s), 1, None) == _abi.ENOTSUP
+    listed = im.Geometry(64, 10, 12, angles=tuple(0.1 * a for a in range(10))).c()
+    prm = _abi.Params(0.01, 1, 0)
+    assert L.imask_step(1, ctypes.byref(listed), ctypes.byref(lv), ctypes.byref(reg), ctypes.byref(prm), b,
+                        ctypes.byref(s), 1, None) == _abi.ENOTSUP
+    bad = im.Levels((0, 1), (0.5, 0.5), 0, 11).c()
+    assert L.imask_step(1, ctypes.byref(g), ctypes.byref(bad), ctypes.byref(reg), ctypes.byref(prm), b,
+                        ctypes.byref(s), 1, None) == _abi.EINVAL
+    out = (ctypes.c_int32 * 64)()
+    assert L.imask_block_draws(ctypes.byref(prm), ctypes.byref(lv), 5, 64, out) == _abi.OK
+    assert list(out) == oracle.block_draws(1, 0, 5, 64, 3)

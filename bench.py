@@ -7,6 +7,10 @@ I0 = 1e5, smoothed TV (eps = 1e-3) + lambda = 1e-3, levels 512/256/128/64
 with p = 1/4 (the paper's literal construction, PAPER mode).  Epochs count
 equivalent full-resolution operator applications (cost 2^{-l} per step).
 
+With --blocks S > 1 the same workload runs with the image sketches combined
+with S measurement blocks (each step projects one of S contiguous angle
+blocks; the outlook of Sec. 6); the default is the plain method (S = 1).
+
 Prints one JSON line.  --gpus above 1 is refused: the path runs on one GPU
 (how it would shard is a design note, not code).
 
@@ -97,7 +101,7 @@ def sample_counts(n, na, nd, lvl, angle_stride=1):
     return total if angle_stride == 1 else int(round(total * na / len(picked)))
 
 
-def cpu_baseline(b, budget_s=12.0):
+def cpu_baseline(b, budget_s=12.0, blocks=1):
     """The FP64 oracle running the same iteration on the host cores."""
     import oracle
 
@@ -107,7 +111,10 @@ def cpu_baseline(b, budget_s=12.0):
     st = None
     t0 = time.perf_counter()
     while time.perf_counter() - t0 < budget_s:
-        st = oracle.imask_run(g, lv, reg, SIGMA, SEED, STREAM, b, 1, st)
+        if blocks > 1:
+            st = oracle.imask_blocks_run(g, lv, reg, SIGMA, SEED, STREAM, blocks, b, 1, st)
+        else:
+            st = oracle.imask_run(g, lv, reg, SIGMA, SEED, STREAM, b, 1, st)
     el = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": st.epochs / el, "unit": "epochs/s", "cores": cores, "kind": "oracle",
@@ -165,7 +172,7 @@ def run(args):
     _, b = synth.ct_problem(N, NA, ND, I0, 1000, 2000)
     b32 = torch.from_numpy(b.astype(np.float32)).cuda()
     geom = pk.Geometry(N, NA, ND)
-    lv = pk.Levels.uniform(LEVELS, pk.FULL_PAPER)
+    lv = pk.Levels.uniform(LEVELS, pk.FULL_PAPER, args.blocks)
     reg = pk.Regularizer(pk.REG_SMOOTH_TV, LAM, TV_W, TV_EPS, TV_J)
     prob = pk.Problem(geom, lv, reg, pk.Params(SIGMA, SEED, STREAM), b32)
 
@@ -215,7 +222,9 @@ def run(args):
         "dtype": "f32",
         "data": "synthetic: seeded random-ellipse phantom, analytic line integrals, Poisson I0=1e5",
         "config": {"workload": "2D parallel-beam CT 512x512, 720 angles x 768 bins, smoothed TV eps=1e-3 + "
-                               "lambda=1e-3, levels 512/256/128/64 uniform p, ImaSk (PAPER sketches)",
+                               "lambda=1e-3, levels 512/256/128/64 uniform p, ImaSk (PAPER sketches)"
+                               + (f", {args.blocks} measurement blocks of {NA // args.blocks} angles"
+                                  if args.blocks > 1 else ""),
                    "steps_level_mix": [round(float(v), 4) for v in mix], "epochs_timed": epochs},
         "roofline": {"bound": "alu", "kernel": key, "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": stored_traffic(key),
@@ -233,7 +242,7 @@ def run(args):
         "kernel_source_hash": source_hash(),
     }
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(b)
+        out["cpu_baseline"] = cpu_baseline(b, blocks=args.blocks)
     print(json.dumps(out), flush=True)
 
 
@@ -298,6 +307,15 @@ def race(args):
     shares the limit:
       imask_r4 / saga_r1  Alg. 1 with r = 4 / r = 1, sigma = m * sigma_thm3
       imask_r4_indep      Alg. 1, r = 4, independent primal/dual draws (Sec. 6)
+      imask_r4_b4 / saga_r1_b4
+                          Alg. 1 over r = 4 / r = 1 image sketches combined
+                          with 4 measurement blocks of 180 angles (Sec. 6
+                          outlook); sigma = m * the Thm. 3 step of the block
+                          family, with |K_kb|^2 ~ S |K_k|^2 (a block of
+                          contiguous angles carries about 1/S of the energy
+                          of the leading singular vector), so that
+                          Lbar^2 -> S Lbar^2, Lbar_p^2 -> S^2 Lbar_p^2 and
+                          p_min -> p_min / S
       seq_r4 / seq_r1     ImaSk-Seq (Sec. 5, theta = 1) with r = 4 / r = 1
                           (r = 1 is PDHG), sigma = m * sigma_pd, where
                           sigma_pd = (L^2)^{-1/2} is the single-level PDHG
@@ -324,18 +342,22 @@ def race(args):
     reg = pk.Regularizer(pk.REG_SMOOTH_TV, LAM, TV_W, TV_EPS, TV_J)
     r4 = pk.Levels.uniform(LEVELS, pk.FULL_UNBIASED)
     r1 = pk.Levels((0,), (1.0,))
+    r4b = pk.Levels.uniform(LEVELS, pk.FULL_UNBIASED, 4)
+    r1b = pk.Levels((0,), (1.0,), pk.FULL_UNBIASED, 4)
     methods = {"imask_r4": (r4, pk.SCHEDULE_PARALLEL), "saga_r1": (r1, pk.SCHEDULE_PARALLEL),
                "seq_r4": (r4, pk.SCHEDULE_SEQUENTIAL), "seq_r1": (r1, pk.SCHEDULE_SEQUENTIAL),
-               "imask_r4_indep": (r4, pk.SCHEDULE_PARALLEL)}
+               "imask_r4_indep": (r4, pk.SCHEDULE_PARALLEL),
+               "imask_r4_b4": (r4b, pk.SCHEDULE_PARALLEL), "saga_r1_b4": (r1b, pk.SCHEDULE_PARALLEL)}
     results = {}
     for name in args.methods:
         lv, sched = methods[name]
         L2, lb, lp = pk.step_constants(geom, lv, LAM, work, iters=40)
-        s3, th = pk.sigma_thm3(L2, lb, lp, min(lv.p), 100)
+        nb = max(lv.n_blocks, 1)
+        s3, th = pk.sigma_thm3(L2, nb * lb, nb * nb * lp, min(lv.p) / nb, 100)
         spd = 1.0 / np.sqrt(L2)
         seq = sched == pk.SCHEDULE_SEQUENTIAL
         base, mults = (spd, args.seq_sigma_mults) if seq else (s3, args.sigma_mults)
-        results[name] = {"constants": [L2, lb, lp], "sigma_thm3": s3, "theta_thm3": th, "sigma_pd": spd,
+        results[name] = {"constants": [L2, lb, lp], "blocks": nb, "sigma_thm3": s3, "theta_thm3": th, "sigma_pd": spd,
                          "schedule": "sequential" if seq else "parallel", "runs": []}
         check = args.seq_check_every if seq else args.check_every
         for mult in mults:
@@ -800,6 +822,7 @@ def summarize(dirs, command_note, counter_key=None):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--blocks", type=int, default=1, help="measurement blocks combined with the image sketches")
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--kernel-reps", type=int, default=20)

@@ -1438,8 +1438,9 @@ hipError_t launch_fwd_terms(const FwdArgs& a, hipStream_t s)
             const int nl = a.n >> tm.lvl;
             fb.R = tm.rows;
             fb.bands = tm.bands;
-            // about 512 workgroups of 1024 threads
-            fb.apg = std::max(1, (a.na * tm.bands + 511) / 512);
+            // about 512 workgroups of 1024 threads over the angles this
+            // launch projects (a measurement block covers only some of them)
+            fb.apg = std::max(1, ((sp.nrow + sp.ncol) * tm.bands + 511) / 512);
             fb.groups_row = (sp.nrow + fb.apg - 1) / fb.apg;
             fb.groups_col = (sp.ncol + fb.apg - 1) / fb.apg;
             const int lds = (int)(sizeof(float) * (size_t)fb.R * (nl + kPad));
@@ -1488,7 +1489,9 @@ static size_t scatter_lds(int nl)
 }
 
 // Ownership scatter with about IMK_BP_TARGET_WG workgroups: G angle groups
-// per pass, 2 G N_l^2 <= kPartImages N^2 partial images.
+// per pass, 2 G N_l^2 <= kPartImages N^2 partial images.  A launch over part
+// of the angles (a measurement block) keeps the same workgroup count: fewer
+// angles per group, but fewer workgroups measured slower still.
 template <int R, int W>
 static hipError_t launch_scatter(BpOwnArgs& a, int nl, int lvl, hipStream_t s)
 {

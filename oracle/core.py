@@ -45,7 +45,8 @@ def lib():
     if _lib is None:
         _lib = ctypes.CDLL(build())
         L = _lib
-        geo = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double, _D]
+        geo = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double, _D,
+               ctypes.c_double, ctypes.c_double]
         L.orc_project.argtypes = geo + [ctypes.c_int, _D, _D]
         L.orc_backproject.argtypes = geo + [ctypes.c_int, _D, _D]
         L.orc_count_samples.argtypes = geo + [ctypes.c_int]
@@ -121,9 +122,15 @@ def _f64(a) -> np.ndarray:
 
 @dataclass(frozen=True)
 class Geometry:
-    """2-D parallel-beam geometry: N x N image on [-E,E]^2 (E = extent),
-    n_angles angles a*pi/n_angles or the given list (radians), n_det bins of
-    spacing ds (default: full-res pixel size 2E/N)."""
+    """2-D CT geometry: N x N image on [-E,E]^2 (E = extent), n_det bins of
+    spacing ds centred at s0.
+
+    Parallel beam (src_dist = 0): n_angles angles a*pi/n_angles or the given
+    list (radians); default spacing the full-res pixel size 2E/N.
+    Fan beam (src_dist = D > 0): n_angles source positions at angle
+    2 pi a/n_angles (or the list), distance D from the centre, and a flat
+    detector at distance det_dist beyond the centre; default spacing the
+    pixel size magnified onto the detector, 2E/N (D + det_dist)/D."""
     n: int
     n_angles: int
     n_det: int
@@ -131,6 +138,8 @@ class Geometry:
     s0: float = 0.0
     extent: float = 1.0
     angles: tuple = None
+    src_dist: float = 0.0
+    det_dist: float = 0.0
 
     def __post_init__(self):
         if self.angles is not None:
@@ -140,8 +149,15 @@ class Geometry:
             object.__setattr__(self, "_ang", _f64(a))
 
     @property
+    def fan(self) -> bool:
+        return self.src_dist > 0
+
+    @property
     def spacing(self) -> float:
-        return self.ds if self.ds > 0 else 2.0 * self.extent / self.n
+        if self.ds > 0:
+            return self.ds
+        h = 2.0 * self.extent / self.n
+        return h * (self.src_dist + self.det_dist) / self.src_dist if self.fan else h
 
     def theta(self) -> np.ndarray:
         if self.angles is not None:
@@ -150,7 +166,8 @@ class Geometry:
 
     def args(self):
         ang = _dp(self._ang) if self.angles is not None else None
-        return (self.n, self.n_angles, self.n_det, self.spacing, self.s0, self.extent, ang)
+        return (self.n, self.n_angles, self.n_det, self.spacing, self.s0, self.extent, ang, self.src_dist,
+                self.det_dist)
 
 
 @dataclass

@@ -32,6 +32,8 @@
  * b has centre s_b = (b - (n_det-1)/2) ds + s0 and the ray is
  * x cos + y sin = s.  Default angles step along rows iff 4a <= n_angles or
  * 4a >= 3 n_angles, listed ones iff |cos| >= |sin|; else along columns.
+ * With a source distance D > 0 the rays are those of a fan beam with a flat
+ * detector (orc_ray); every other step is the same.
  * Interpolation reads zero outside the image.
  */
 #include <math.h>
@@ -60,6 +62,43 @@ static int orc_rows(int a, int na, const double* ang)
     return 4 * a <= na || 4 * a >= 3 * na;
 }
 
+/* The line of ray (a, b) as x*ct + y*st = sb, and its stepping axis.
+ *
+ * Parallel beam (D <= 0): ct = cos(theta_a), st = sin(theta_a), sb the bin
+ * centre, as in the conventions above.
+ *
+ * Fan beam (D > 0, the divergent-beam geometry the paper's operator extends
+ * to, Sec. 4.1 and the outlook of Sec. 6): view a puts the source at
+ * D (cos beta, sin beta), beta = 2 pi a / na or the a-th listed value, and a
+ * flat detector through -Dd (cos beta, sin beta), perpendicular to the
+ * central ray; bin b sits at t_b = (b - (nd-1)/2) ds + s0 along
+ * (-sin beta, cos beta).  The ray joins the source to that point; (ct, st)
+ * is its unit normal and sb = (ct, st) . source.  It steps along rows iff
+ * |ct| >= |st| in FP64. */
+static void orc_ray(int a, int b, int na, int nd, double ds, double s0, const double* ang, double D, double Dd,
+                    double* ct, double* st, double* sb, int* rows)
+{
+    const double t = (b - (nd - 1) / 2.0) * ds + s0;
+    if (!(D > 0.0)) {
+        const double th = orc_theta(a, na, ang);
+        *ct = cos(th);
+        *st = sin(th);
+        *sb = t;
+        *rows = orc_rows(a, na, ang);
+        return;
+    }
+    const double beta = ang ? ang[a] : 2.0 * M_PI * a / na;
+    const double ec[2] = {cos(beta), sin(beta)}, et[2] = {-sin(beta), cos(beta)};
+    const double src[2] = {D * ec[0], D * ec[1]};
+    const double det[2] = {-Dd * ec[0] + t * et[0], -Dd * ec[1] + t * et[1]};
+    const double dir[2] = {det[0] - src[0], det[1] - src[1]};
+    const double len = sqrt(dir[0] * dir[0] + dir[1] * dir[1]);
+    *ct = -dir[1] / len;
+    *st = dir[0] / len;
+    *sb = *ct * src[0] + *st * src[1];
+    *rows = fabs(*ct) >= fabs(*st);
+}
+
 static double orc_pix(const double* z, int nl, long i, long j)
 {
     if (i < 0 || j < 0 || i >= nl || j >= nl) return 0.0;
@@ -70,7 +109,7 @@ static double orc_pix(const double* z, int nl, long i, long j)
 
 /* sino[a][b] = (h_l/|cos|) sum_i interp_j(z[i][.], u)   (row stepping)
  *            = (h_l/|sin|) sum_j interp_i(z[.][j], v)   (column stepping) */
-void orc_project(int n, int na, int nd, double ds, double s0, double E, const double* ang, int lvl,
+void orc_project(int n, int na, int nd, double ds, double s0, double E, const double* ang, double D, double Dd, int lvl,
                  const double* z, double* sino)
 {
     const int nl = n >> lvl;
@@ -79,10 +118,11 @@ void orc_project(int n, int na, int nd, double ds, double s0, double E, const do
 #pragma omp parallel for schedule(static)
     for (long ab = 0; ab < (long)na * nd; ++ab) {
         const int a = (int)(ab / nd), b = (int)(ab % nd);
-        const double th = orc_theta(a, na, ang), ct = cos(th), st = sin(th);
-        const double sb = (b - (nd - 1) / 2.0) * ds + s0;
+        double ct, st, sb;
+        int rows;
+        orc_ray(a, b, na, nd, ds, s0, ang, D, Dd, &ct, &st, &sb, &rows);
         double acc = 0.0;
-        if (orc_rows(a, na, ang)) {
+        if (rows) {
             for (int i = 0; i < nl; ++i) {
                 const double yi = -E + (i + 0.5) * hl;
                 const double u = ((sb - yi * st) / ct - c0) / hl;
@@ -108,7 +148,7 @@ void orc_project(int n, int na, int nd, double ds, double s0, double E, const do
 
 /* The literal transpose of orc_project: the same loops, scattering
  * t*(1-w) and t*w into the two pixels each sample reads. */
-void orc_backproject(int n, int na, int nd, double ds, double s0, double E, const double* ang, int lvl,
+void orc_backproject(int n, int na, int nd, double ds, double s0, double E, const double* ang, double D, double Dd, int lvl,
                      const double* sino, double* z)
 {
     const int nl = n >> lvl;
@@ -125,10 +165,10 @@ void orc_backproject(int n, int na, int nd, double ds, double s0, double E, cons
         double* acc = part + (size_t)omp_get_thread_num() * dl;
 #pragma omp for schedule(static)
         for (int a = 0; a < na; ++a) {
-            const double th = orc_theta(a, na, ang), ct = cos(th), st = sin(th);
-            const int rows = orc_rows(a, na, ang);
             for (int b = 0; b < nd; ++b) {
-                const double sb = (b - (nd - 1) / 2.0) * ds + s0;
+                double ct, st, sb;
+                int rows;
+                orc_ray(a, b, na, nd, ds, s0, ang, D, Dd, &ct, &st, &sb, &rows);
                 const double t = (rows ? hl / fabs(ct) : hl / fabs(st)) * sino[(long)a * nd + b];
                 for (int k = 0; k < nl; ++k) {
                     const double ck = -E + (k + 0.5) * hl;
@@ -154,7 +194,7 @@ void orc_backproject(int n, int na, int nd, double ds, double s0, double E, cons
 
 /* Number of (ray, step) samples with at least one interpolation tap inside
  * the image: the nonzero-sample count of R_l (work accounting only). */
-long long orc_count_samples(int n, int na, int nd, double ds, double s0, double E, const double* ang, int lvl)
+long long orc_count_samples(int n, int na, int nd, double ds, double s0, double E, const double* ang, double D, double Dd, int lvl)
 {
     const int nl = n >> lvl;
     const double hl = 2.0 * E / nl;
@@ -163,9 +203,9 @@ long long orc_count_samples(int n, int na, int nd, double ds, double s0, double 
 #pragma omp parallel for reduction(+ : total) schedule(static)
     for (long ab = 0; ab < (long)na * nd; ++ab) {
         const int a = (int)(ab / nd), b = (int)(ab % nd);
-        const double th = orc_theta(a, na, ang), ct = cos(th), st = sin(th);
-        const double sb = (b - (nd - 1) / 2.0) * ds + s0;
-        const int rows = orc_rows(a, na, ang);
+        double ct, st, sb;
+        int rows;
+        orc_ray(a, b, na, nd, ds, s0, ang, D, Dd, &ct, &st, &sb, &rows);
         for (int k = 0; k < nl; ++k) {
             const double ck = -E + (k + 0.5) * hl;
             const double u = rows ? ((sb - ck * st) / ct - c0) / hl : ((sb - ck * ct) / st - c0) / hl;
@@ -219,23 +259,23 @@ void orc_compensate(int n, int r, const int* log2f, const double* p, const doubl
 /* ------------------------------------------------------ sketched operators */
 
 /* g = K_k x (sinogram), for sketch k of the level set (log2f[0] == 0). */
-void orc_sketch_fwd(int n, int na, int nd, double ds, double s0, double E, const double* ang, int r, const int* log2f,
+void orc_sketch_fwd(int n, int na, int nd, double ds, double s0, double E, const double* ang, double D, double Dd, int r, const int* log2f,
                     const double* p, int mode, int k, const double* x, double* g)
 {
     const long d = (long)n * n, m = (long)na * nd;
     double* z = (double*)malloc(sizeof(double) * d);
     if (k > 0) {
         orc_restrict(n, log2f[k], x, z);
-        orc_project(n, na, nd, ds, s0, E, ang, log2f[k], z, g);
+        orc_project(n, na, nd, ds, s0, E, ang, D, Dd, log2f[k], z, g);
     } else if (mode == ORC_MODE_PAPER) {
         orc_compensate(n, r, log2f, p, x, z);
-        orc_project(n, na, nd, ds, s0, E, ang, 0, z, g);
+        orc_project(n, na, nd, ds, s0, E, ang, D, Dd, 0, z, g);
     } else {
         double* t = (double*)malloc(sizeof(double) * m);
-        orc_project(n, na, nd, ds, s0, E, ang, 0, x, g);
+        orc_project(n, na, nd, ds, s0, E, ang, D, Dd, 0, x, g);
         for (int q = 1; q < r; ++q) {
             orc_restrict(n, log2f[q], x, z);
-            orc_project(n, na, nd, ds, s0, E, ang, log2f[q], z, t);
+            orc_project(n, na, nd, ds, s0, E, ang, D, Dd, log2f[q], z, t);
             for (long e = 0; e < m; ++e) g[e] -= p[q] * t[e];
         }
         for (long e = 0; e < m; ++e) g[e] /= p[0];
@@ -245,7 +285,7 @@ void orc_sketch_fwd(int n, int na, int nd, double ds, double s0, double E, const
 }
 
 /* g = K_k^T y (image), the exact transpose of orc_sketch_fwd. */
-void orc_sketch_adj(int n, int na, int nd, double ds, double s0, double E, const double* ang, int r, const int* log2f,
+void orc_sketch_adj(int n, int na, int nd, double ds, double s0, double E, const double* ang, double D, double Dd, int r, const int* log2f,
                     const double* p, int mode, int k, const double* y, double* g)
 {
     const long d = (long)n * n;
@@ -254,18 +294,18 @@ void orc_sketch_adj(int n, int na, int nd, double ds, double s0, double E, const
     if (k > 0) {
         const int l = log2f[k];
         const double s = 1.0 / (double)(1L << (2 * l)); /* T_l^T = 4^{-l} T_l^* */
-        orc_backproject(n, na, nd, ds, s0, E, ang, l, y, c);
+        orc_backproject(n, na, nd, ds, s0, E, ang, D, Dd, l, y, c);
         orc_prolong(n, l, c, g);
         for (long q = 0; q < d; ++q) g[q] *= s;
     } else if (mode == ORC_MODE_PAPER) {
-        orc_backproject(n, na, nd, ds, s0, E, ang, 0, y, c);
+        orc_backproject(n, na, nd, ds, s0, E, ang, D, Dd, 0, y, c);
         orc_compensate(n, r, log2f, p, c, g); /* S_r is symmetric */
     } else {
-        orc_backproject(n, na, nd, ds, s0, E, ang, 0, y, g);
+        orc_backproject(n, na, nd, ds, s0, E, ang, D, Dd, 0, y, g);
         for (int q = 1; q < r; ++q) {
             const int l = log2f[q];
             const double s = 1.0 / (double)(1L << (2 * l));
-            orc_backproject(n, na, nd, ds, s0, E, ang, l, y, c);
+            orc_backproject(n, na, nd, ds, s0, E, ang, D, Dd, l, y, c);
             orc_prolong(n, l, c, t);
             for (long e = 0; e < d; ++e) g[e] -= p[q] * s * t[e];
         }
@@ -488,7 +528,7 @@ static void orc_prox(int n, int reg_kind, double tau, double lam, double tv_w, d
  * (psi_k = K_k x at the last refresh).  mu = lam.  draws_out[q] receives
  * i_{k0+q}; *epochs accumulates sum_q 2^{-log2f[i_q]} (PAPER cost model) or,
  * in UNBIASED mode, 1 + sum_{k>0} 2^{-log2f[k]} for a full-resolution step. */
-int orc_imask_run(int n, int na, int nd, double ds, double s0, double E, const double* ang,
+int orc_imask_run(int n, int na, int nd, double ds, double s0, double E, const double* ang, double D, double Dd,
                   int r, const int* log2f, const double* p, int mode,
                   int reg_kind, double lam, double tv_w, double tv_eps, int tv_inner,
                   double sigma, uint64_t seed, uint32_t stream, uint64_t k0,
@@ -511,8 +551,8 @@ int orc_imask_run(int n, int na, int nd, double ds, double s0, double E, const d
     for (int it = 0; it < n_iter; ++it) {
         const int k = idx[it];
         /* both refreshed gradients from the old iterates x^k, y^k */
-        orc_sketch_adj(n, na, nd, ds, s0, E, ang, r, log2f, p, mode, k, y, gx);
-        orc_sketch_fwd(n, na, nd, ds, s0, E, ang, r, log2f, p, mode, k, x, gy);
+        orc_sketch_adj(n, na, nd, ds, s0, E, ang, D, Dd, r, log2f, p, mode, k, y, gx);
+        orc_sketch_fwd(n, na, nd, ds, s0, E, ang, D, Dd, r, log2f, p, mode, k, x, gy);
         /* SAGA estimates with the old tables */
         for (long q = 0; q < d; ++q) {
             double avg = 0.0;
@@ -562,7 +602,7 @@ int orc_imask_run(int n, int na, int nd, double ds, double s0, double E, const d
  *   x_new = prox_{tau R}(x - tau xi), tau = sigma / mu;
  *   xbar <- x_new + theta (x_new - x);  x <- x_new;  psi_i, phi_i refreshed.
  * Draws and epoch accounting as in orc_imask_run. */
-int orc_imask_seq_run(int n, int na, int nd, double ds, double s0, double E, const double* ang,
+int orc_imask_seq_run(int n, int na, int nd, double ds, double s0, double E, const double* ang, double D, double Dd,
                       int r, const int* log2f, const double* p, int mode,
                       int reg_kind, double lam, double tv_w, double tv_eps, int tv_inner,
                       double sigma, double theta, uint64_t seed, uint32_t stream, uint64_t k0,
@@ -584,7 +624,7 @@ int orc_imask_seq_run(int n, int na, int nd, double ds, double s0, double E, con
     for (int it = 0; it < n_iter; ++it) {
         const int k = idx[it];
         /* dual step from the extrapolated point */
-        orc_sketch_fwd(n, na, nd, ds, s0, E, ang, r, log2f, p, mode, k, xbar, gy);
+        orc_sketch_fwd(n, na, nd, ds, s0, E, ang, D, Dd, r, log2f, p, mode, k, xbar, gy);
         for (long e = 0; e < m; ++e) {
             double avg = 0.0;
             for (int j = 0; j < r; ++j) avg += p[j] * psi[(long)j * m + e];
@@ -592,7 +632,7 @@ int orc_imask_seq_run(int n, int na, int nd, double ds, double s0, double E, con
             y[e] = (y[e] + sigma * zeta - sigma * bdata[e]) / (1.0 + sigma);
         }
         /* primal step with the new dual iterate */
-        orc_sketch_adj(n, na, nd, ds, s0, E, ang, r, log2f, p, mode, k, y, gx);
+        orc_sketch_adj(n, na, nd, ds, s0, E, ang, D, Dd, r, log2f, p, mode, k, y, gx);
         for (long q = 0; q < d; ++q) {
             double avg = 0.0;
             for (int j = 0; j < r; ++j) avg += p[j] * phi[(long)j * d + q];
@@ -628,7 +668,7 @@ int orc_imask_seq_run(int n, int na, int nd, double ds, double s0, double E, con
  * step still suffices: d = K_i (x^k - z_i) = psi_new - psi_i, so
  * zeta = d + psibar, psibar <- psibar + p_i d and z_i <- x^k.  Everything
  * else is orc_imask_run. */
-int orc_imask_compact_run(int n, int na, int nd, double ds, double s0, double E, const double* ang,
+int orc_imask_compact_run(int n, int na, int nd, double ds, double s0, double E, const double* ang, double D, double Dd,
                           int r, const int* log2f, const double* p, int mode,
                           int reg_kind, double lam, double tv_w, double tv_eps, int tv_inner,
                           double sigma, uint64_t seed, uint32_t stream, uint64_t k0,
@@ -652,9 +692,9 @@ int orc_imask_compact_run(int n, int na, int nd, double ds, double s0, double E,
     for (int it = 0; it < n_iter; ++it) {
         const int k = idx[it];
         /* both refreshed gradients from the old iterates x^k, y^k */
-        orc_sketch_adj(n, na, nd, ds, s0, E, ang, r, log2f, p, mode, k, y, gx);
+        orc_sketch_adj(n, na, nd, ds, s0, E, ang, D, Dd, r, log2f, p, mode, k, y, gx);
         for (long q = 0; q < d; ++q) diff[q] = x[q] - zsnap[(long)k * d + q];
-        orc_sketch_fwd(n, na, nd, ds, s0, E, ang, r, log2f, p, mode, k, diff, dd);
+        orc_sketch_fwd(n, na, nd, ds, s0, E, ang, D, Dd, r, log2f, p, mode, k, diff, dd);
         for (long q = 0; q < d; ++q) {
             double avg = 0.0;
             for (int j = 0; j < r; ++j) avg += p[j] * phi[(long)j * d + q];
@@ -694,7 +734,7 @@ int orc_imask_compact_run(int n, int na, int nd, double ds, double s0, double E,
  * averages.  An iteration costs half of each side's level cost:
  * epochs += (c(i_k) + c(j_k)) / 2, so equal streams reproduce orc_imask_run.
  * draws_out gets i_k, dual_draws_out j_k (either may be NULL). */
-int orc_imask_indep_run(int n, int na, int nd, double ds, double s0, double E, const double* ang,
+int orc_imask_indep_run(int n, int na, int nd, double ds, double s0, double E, const double* ang, double D, double Dd,
                         int r, const int* log2f, const double* p, int mode,
                         int reg_kind, double lam, double tv_w, double tv_eps, int tv_inner,
                         double sigma, uint64_t seed, uint32_t stream, uint32_t dual_stream, uint64_t k0,
@@ -719,8 +759,8 @@ int orc_imask_indep_run(int n, int na, int nd, double ds, double s0, double E, c
         for (int k = 1; k < r; ++k) cost[0] += ldexp(1.0, -log2f[k]);
     for (int it = 0; it < n_iter; ++it) {
         const int i = ip[it], j = jd[it];
-        orc_sketch_adj(n, na, nd, ds, s0, E, ang, r, log2f, p, mode, i, y, gx);
-        orc_sketch_fwd(n, na, nd, ds, s0, E, ang, r, log2f, p, mode, j, x, gy);
+        orc_sketch_adj(n, na, nd, ds, s0, E, ang, D, Dd, r, log2f, p, mode, i, y, gx);
+        orc_sketch_fwd(n, na, nd, ds, s0, E, ang, D, Dd, r, log2f, p, mode, j, x, gy);
         for (long q = 0; q < d; ++q) {
             double avg = 0.0;
             for (int c = 0; c < r; ++c) avg += p[c] * phi[(long)c * d + q];
@@ -779,7 +819,7 @@ void orc_block_draws(uint64_t seed, uint32_t stream, uint64_t k0, int count, int
     }
 }
 
-int orc_imask_blocks_run(int n, int na, int nd, double ds, double s0, double E, const double* ang,
+int orc_imask_blocks_run(int n, int na, int nd, double ds, double s0, double E, const double* ang, double D, double Dd,
                          int r, const int* log2f, const double* p, int mode, int S,
                          int reg_kind, double lam, double tv_w, double tv_eps, int tv_inner,
                          double sigma, uint64_t seed, uint32_t stream, uint64_t k0,
@@ -811,9 +851,9 @@ int orc_imask_blocks_run(int n, int na, int nd, double ds, double s0, double E, 
         const long e0 = (long)a0 * nd, e1 = (long)a1 * nd;
         /* K_kj^T y = S K_k^T E_j y and K_kj x = S E_j K_k x, old iterates */
         for (long e = 0; e < m; ++e) yj[e] = (e >= e0 && e < e1) ? y[e] : 0.0;
-        orc_sketch_adj(n, na, nd, ds, s0, E, ang, r, log2f, p, mode, k, yj, gx);
+        orc_sketch_adj(n, na, nd, ds, s0, E, ang, D, Dd, r, log2f, p, mode, k, yj, gx);
         for (long q = 0; q < d; ++q) gx[q] *= S;
-        orc_sketch_fwd(n, na, nd, ds, s0, E, ang, r, log2f, p, mode, k, x, gy);
+        orc_sketch_fwd(n, na, nd, ds, s0, E, ang, D, Dd, r, log2f, p, mode, k, x, gy);
         for (long e = 0; e < m; ++e) gy[e] = (e >= e0 && e < e1) ? S * gy[e] : 0.0;
         /* SAGA estimates with the old tables */
         for (long q = 0; q < d; ++q) {

@@ -78,19 +78,40 @@ enum { IMASK_BUDGET_ITERS = 0, IMASK_BUDGET_EPOCHS = 1 };
  * size their launches, so they must pass the same values.  A listed angle
  * steps along rows when |cos| >= |sin| in FP64, else along columns; the
  * default angles step along rows iff 4a <= n_angles or 4a >= 3 n_angles.
+ *
+ * Fan beam (src_dist = D > 0; the divergent-beam case of the same line-
+ * integral operator, Sec. 4.1, and a geometry of the outlook of Sec. 6):
+ * view a puts the source at D (cos beta_a, sin beta_a), beta_a =
+ * 2 pi a / n_angles or the a-th listed angle, and a flat detector through
+ * -det_dist (cos beta_a, sin beta_a), perpendicular to the central ray; bin
+ * b sits at t_b = (b - (n_det-1)/2) det_spacing + det_offset along
+ * (-sin beta_a, cos beta_a) and its ray joins the source to that point.
+ * Each ray steps along rows when the x component of its unit normal is at
+ * least the y component in magnitude (FP64, computed once by
+ * imask_prepare, which also tabulates every ray's line in the workspace and
+ * waits for its stream).  det_spacing <= 0 selects the pixel size magnified
+ * onto the detector, 2E/N (D + det_dist)/D.  Every entry point takes a fan
+ * geometry; imask_step and imask_solve return IMASK_ENOTSUP for a fan
+ * geometry with measurement blocks.
+ *
  * Invalid (EINVAL): n outside 4..16384,
  * not a multiple of 4, or above 16 not a multiple of 16; n_angles or n_det
- * out of range; a non-finite spacing, offset, extent or listed angle; an
- * extent outside [1e-100, 1e100]; a positive spacing outside [1/64, 64]
- * full-resolution pixels; |det_offset| > 4E. */
+ * out of range; a non-finite spacing, offset, extent, listed angle, source
+ * or detector distance; an extent outside [1e-100, 1e100]; a positive
+ * spacing outside [1/64, 64] full-resolution pixels (fan beam: magnified
+ * pixels); |det_offset| > 4E (fan beam: 4E (D + det_dist)/D); a source
+ * distance outside (2E, 1e4 E] or a negative one; a detector distance
+ * outside [0, 1e4 E]. */
 typedef struct {
     int32_t n;            /* full-resolution image side N */
-    int32_t n_angles;     /* 1 .. 65536 */
+    int32_t n_angles;     /* 1 .. 65536 (fan beam: views) */
     int32_t n_det;        /* 1 .. 8192 */
-    double det_spacing;   /* bin spacing; <= 0 selects the full-res pixel size 2E/N */
+    double det_spacing;   /* bin spacing; <= 0 selects the default above */
     double det_offset;    /* detector centre offset s0 */
     double extent;        /* half side E of the image square; <= 0 selects 1 */
     const double* angles; /* host, n_angles radians, or NULL (see above) */
+    double src_dist;      /* fan beam: source distance D from the centre; 0 selects parallel beam */
+    double det_dist;      /* fan beam: detector distance beyond the centre; ignored for parallel beam */
 } imask_geometry;
 
 /* Resolution set and sampling probabilities (Alg. 1 REQUIRE line; Sec. 4.1).
@@ -112,8 +133,8 @@ typedef struct {
  * psi stays r sinograms (block b's rows of table k hold K_kb x), the dual
  * step still updates every row, and a step costs its sketch's cost times
  * its block's share of the angles.  Read by imask_step / imask_solve
- * (parallel schedule, full tables, common draws and the default angles;
- * IMASK_ENOTSUP otherwise), imask_phi_floats and imask_block_draws; the
+ * (parallel schedule, full tables, common draws and the default angles of
+ * a parallel beam; IMASK_ENOTSUP otherwise), imask_phi_floats and imask_block_draws; the
  * other calls apply the level sketches alone.  0 or 1: no blocks;
  * 2 .. min(n_angles, IMASK_MAX_BLOCKS), else IMASK_EINVAL. */
 typedef struct {

@@ -33,7 +33,8 @@ KERNEL_FORWARD, KERNEL_TRANSPOSE = 0, 1
 class Geometry(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("n_angles", ctypes.c_int32), ("n_det", ctypes.c_int32),
                 ("det_spacing", ctypes.c_double), ("det_offset", ctypes.c_double), ("extent", ctypes.c_double),
-                ("angles", ctypes.POINTER(ctypes.c_double))]
+                ("angles", ctypes.POINTER(ctypes.c_double)), ("src_dist", ctypes.c_double),
+                ("det_dist", ctypes.c_double)]
 
 
 class Levels(ctypes.Structure):

@@ -50,6 +50,17 @@ static int listed_nrow(const double* ang, int na)
     return nrow;
 }
 
+static double extent_of(const imask_geometry& g) { return g.extent > 0 ? g.extent : 1.0; }
+static bool is_fan(const imask_geometry& g) { return g.src_dist != 0.0; }
+// Fan beam: the magnification from the centre onto the detector.
+static double fan_mag(const imask_geometry& g) { return (g.src_dist + g.det_dist) / g.src_dist; }
+static double spacing_of(const imask_geometry& g)
+{
+    if (g.det_spacing > 0) return g.det_spacing;
+    const double h = 2.0 * extent_of(g) / g.n;
+    return is_fan(g) ? h * fan_mag(g) : h;
+}
+
 Layout make_layout(const imask_geometry& g)
 {
     Layout L;
@@ -57,6 +68,9 @@ Layout make_layout(const imask_geometry& g)
     L.na = g.n_angles;
     L.nd = g.n_det;
     L.lmax = level_limit(g.n);
+    L.E = extent_of(g);
+    L.ds = spacing_of(g);
+    L.s0 = g.det_offset;
     size_t off = 0;
     L.consts = off;
     off = align64(off + (size_t)(L.lmax + 1) * g.n_angles * kConstStride);
@@ -77,7 +91,12 @@ Layout make_layout(const imask_geometry& g)
     off = align64(off + (size_t)g.n * g.n);
     const size_t m = (size_t)g.n_angles * g.n_det;
     for (int l = 0; l <= L.lmax; ++l) {
-        fwd_bands(side(g.n, l), &L.fbands[l], &L.frows[l]);
+        if (is_fan(g)) {  // one thread per ray, one partial sinogram
+            L.fbands[l] = 1;
+            L.frows[l] = 0;
+        } else {
+            fwd_bands(side(g.n, l), &L.fbands[l], &L.frows[l]);
+        }
         L.fpart[l] = off;
         off = align64(off + (size_t)L.fbands[l] * m);
     }
@@ -85,7 +104,16 @@ Layout make_layout(const imask_geometry& g)
     off = align64(off + 4 * (size_t)g.n_angles);
     L.flag = off;
     off = align64(off + 1);
-    if (g.angles) {
+    if (is_fan(g)) {
+        L.fan = 1;
+        L.D = g.src_dist;
+        L.Dd = g.det_dist;
+        L.fray = off;
+        off = align64(off + m * (sizeof(FanRay) / sizeof(float)));
+        L.fview = off;
+        off = align64(off + (size_t)g.n_angles * (sizeof(FanView) / sizeof(float)));
+        L.split = angle_split(g.n_angles);  // unused by the fan kernels
+    } else if (g.angles) {
         L.listed = 1;
         L.split = AngleSplit{};
         L.split.nrow = listed_nrow(g.angles, g.n_angles);
@@ -106,13 +134,23 @@ static bool geometry_ok(const imask_geometry* g)
     if (g->n > 16 && (g->n % 16) != 0) return false;
     if (g->n_angles < 1 || g->n_det < 1 || g->n_angles > 65536 || g->n_det > 8192) return false;
     if (!std::isfinite(g->det_spacing) || !std::isfinite(g->det_offset) || !std::isfinite(g->extent)) return false;
+    if (!std::isfinite(g->src_dist) || !std::isfinite(g->det_dist)) return false;
     // bounds that keep every fixed-point coordinate far inside what the FP32
     // range estimates resolve (the rows' zero padding absorbs their error)
-    const double E = g->extent > 0 ? g->extent : 1.0;
+    const double E = extent_of(*g);
     if (E < 1e-100 || E > 1e100) return false;
-    const double h = 2.0 * E / g->n;
+    double mag = 1.0;
+    if (is_fan(*g)) {
+        // the source stays outside every pixel's tap interval (all within
+        // 2E of the centre), so each point projects onto the detector; the
+        // upper bounds keep the fixed-point coordinates in range
+        if (!(g->src_dist > 2 * E) || g->src_dist > 1e4 * E) return false;
+        if (!(g->det_dist >= 0) || g->det_dist > 1e4 * E) return false;
+        mag = fan_mag(*g);
+    }
+    const double h = 2.0 * E / g->n * mag;
     if (g->det_spacing > 0 && (g->det_spacing < h / 64 || g->det_spacing > 64 * h)) return false;
-    if (std::fabs(g->det_offset) > 4 * E) return false;
+    if (std::fabs(g->det_offset) > 4 * E * mag) return false;
     if (g->angles)
         for (int a = 0; a < g->n_angles; ++a)
             if (!std::isfinite(g->angles[a])) return false;
@@ -262,6 +300,7 @@ static void forward_plan(const Layout& L, const imask_levels& lv, int k, const f
 static void fwd_common(const Layout& L, const float* W, FwdArgs& fa)
 {
     fa.consts = (const RayConst*)(W + L.consts);
+    fa.fan = fan_at(L, W);
     fa.split = split_at(L, W);
     fa.n = L.n;
     fa.na = L.na;
@@ -275,6 +314,7 @@ static BpArgs bp_args(const Layout& L, const float* W, int lvl, const float* y, 
 {
     BpArgs ba{};
     ba.consts = (const RayConst*)(W + L.consts);
+    ba.fan = fan_at(L, W);
     ba.split = split_at(L, W);
     ba.n = L.n;
     ba.na = L.na;
@@ -504,6 +544,42 @@ int imask_block_draws(const imask_params* prm, const imask_levels* lv, uint64_t 
     return IMASK_OK;
 }
 
+// Fan-beam lines in FP64 (host libm): view a's source D (cos b, sin b), its
+// bin b's detector point -Dd (cos b, sin b) + t_b (-sin b, cos b), the ray's
+// unit normal (ct, st) = (-dy, dx)/|d| for d = detector point - source, and
+// s = (ct, st) . source; then the row-stepping form of FanRay.
+static void fan_tables(const imask_geometry& g, double ds, std::vector<FanRay>& rays, std::vector<FanView>& views)
+{
+    const int na = g.n_angles, nd = g.n_det;
+    const double D = g.src_dist, Dd = g.det_dist;
+    rays.assign((size_t)na * nd, FanRay{});
+    views.assign(na, FanView{});
+    for (int a = 0; a < na; ++a) {
+        const double beta = g.angles ? g.angles[a] : 2.0 * M_PI * a / na;
+        const double cb = std::cos(beta), sb = std::sin(beta);
+        FanView& v = views[a];
+        v.c = cb;
+        v.s = sb;
+        const double srcx = D * cb, srcy = D * sb;
+        for (int b = 0; b < nd; ++b) {
+            const double t = (b - (nd - 1) / 2.0) * ds + g.det_offset;
+            const double detx = -Dd * cb + t * -sb, dety = -Dd * sb + t * cb;
+            const double dx = detx - srcx, dy = dety - srcy;
+            const double len = std::sqrt(dx * dx + dy * dy);
+            const double ct = -dy / len, st = dx / len;
+            const double sl = ct * srcx + st * srcy;
+            FanRay& r = rays[(size_t)a * nd + b];
+            r.row = std::fabs(ct) >= std::fabs(st) ? 1 : 0;
+            const double c = r.row ? ct : st, o = r.row ? st : ct;
+            r.P = sl / c;
+            r.T = o / c;
+            r.sec = 1.0 / std::fabs(c);
+            v.has_row |= r.row;
+            v.has_col |= 1 - r.row;
+        }
+    }
+}
+
 int imask_prepare(const imask_geometry* g, void* work, size_t work_bytes, void* stream)
 {
     if (!geometry_ok(g) || !work) return IMASK_EINVAL;
@@ -529,6 +605,18 @@ int imask_prepare(const imask_geometry* g, void* work, size_t work_bytes, void* 
                            s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess)  // tab is freed on return
             return IMASK_EHIP;
+    }
+    if (L.fan) {
+        std::vector<FanRay> rays;
+        std::vector<FanView> views;
+        fan_tables(*g, L.ds, rays, views);
+        if (hipMemcpyAsync((float*)work + L.fray, rays.data(), sizeof(FanRay) * rays.size(), hipMemcpyHostToDevice,
+                           s) != hipSuccess ||
+            hipMemcpyAsync((float*)work + L.fview, views.data(), sizeof(FanView) * views.size(),
+                           hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)  // the tables are freed on return
+            return IMASK_EHIP;
+        return IMASK_OK;
     }
     IMK_TRY(launch_consts(*g, L, (float*)work, s));
     return IMASK_OK;
@@ -680,6 +768,7 @@ int imask_time_kernel(const imask_geometry* g, int32_t which, int32_t log2f, con
                              L.frows[log2f]};
     } else {
         ba.consts = (const RayConst*)(W + L.consts);
+        ba.fan = fan_at(L, W);
         ba.split = split_at(L, W);
         ba.n = L.n;
         ba.na = L.na;
@@ -945,7 +1034,7 @@ static int check_problem(const imask_geometry* g, const imask_levels* lv, const 
     }
     if (lv->n_blocks > g->n_angles) return IMASK_EINVAL;
     if (lv->n_blocks > 1 && (prm->schedule != IMASK_SCHEDULE_PARALLEL || s->ztab ||
-                             prm->draw_mode != IMASK_DRAW_COMMON || g->angles))
+                             prm->draw_mode != IMASK_DRAW_COMMON || g->angles || is_fan(*g)))
         return IMASK_ENOTSUP;
     if (prm->schedule == IMASK_SCHEDULE_SEQUENTIAL) {
         if (!(prm->theta >= 0.0 && prm->theta <= 1.0) || !s->xbar) return IMASK_EINVAL;

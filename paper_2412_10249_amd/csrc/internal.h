@@ -81,6 +81,36 @@ inline AngleSplit angle_split_range(int na, int a0, int a1)
     return s;
 }
 
+// Fan-beam ray (one per view and bin), its line x ct + y st = s in the form
+// the Joseph walk needs.  For a row-stepping ray (|ct| >= |st|) the column
+// coordinate at row i of level l (pixel size h) is
+//   u(i) = (P + (E - h/2)(T + 1)) / h - i T,   P = s/ct, T = st/ct,
+// and the step length is h sec, sec = 1/|ct|; a column-stepping ray is the
+// mirror (P = s/st, T = ct/st, sec = 1/|st|, rows and columns swapped).
+// Both kernels of the pair turn these doubles into the same fixed-point
+// coordinate with fan_coords, so they agree on every weight bit for bit.
+struct FanRay {
+    double P, T, sec;
+    int row;
+    int pad;
+};
+static_assert(sizeof(FanRay) == 32, "FanRay is 32 bytes");
+// Fan-beam view: cos and sin of the source angle beta, and whether any of
+// its rays step along rows / along columns.
+struct FanView {
+    double c, s;
+    int has_row, has_col;
+    int pad[2];
+};
+static_assert(sizeof(FanView) == 32, "FanView is 32 bytes");
+// What the fan kernels need besides the ray and view tables: the domain
+// half side, source and detector distances, bin spacing and offset.
+struct FanGeo {
+    const FanRay* ray;    // n_angles x n_det, view-major; null: parallel beam
+    const FanView* view;  // n_angles
+    double E, D, Dd, ds, s0;
+};
+
 // Workspace layout for one geometry (offsets in floats from the start).
 struct Layout {
     int n = 0, na = 0, nd = 0, lmax = 0;
@@ -99,6 +129,10 @@ struct Layout {
     size_t flag = 0;                       // int flag of the finiteness check
     int listed = 0;
     AngleSplit split{};                    // perm / rows unset: see split_at
+    // fan beam: ray table (m FanRay) and view table (na FanView)
+    int fan = 0;
+    size_t fray = 0, fview = 0;
+    double E = 1.0, D = 0.0, Dd = 0.0, ds = 0.0, s0 = 0.0;
     size_t total = 0;
 };
 
@@ -113,6 +147,20 @@ inline AngleSplit split_at(const Layout& L, const float* W)
         s.rows = t + L.na;
     }
     return s;
+}
+inline FanGeo fan_at(const Layout& L, const float* W)
+{
+    FanGeo f{};
+    if (L.fan) {
+        f.ray = (const FanRay*)(W + L.fray);
+        f.view = (const FanView*)(W + L.fview);
+    }
+    f.E = L.E;
+    f.D = L.D;
+    f.Dd = L.Dd;
+    f.ds = L.ds;
+    f.s0 = L.s0;
+    return f;
 }
 inline int side(int n, int l) { return n >> l; }
 inline int pstride(int n, int l) { return (n >> l) + kPad; }
@@ -132,6 +180,7 @@ struct FwdTerm {
 
 struct FwdArgs {
     const RayConst* consts;
+    FanGeo fan;
     AngleSplit split;
     int n, na, nd;
     int nterms;
@@ -153,6 +202,7 @@ struct FwdArgs {
 
 struct FwdBandArgs {
     const RayConst* consts;
+    FanGeo fan;
     int n, na, nd, lvl;
     const float* img;
     const float* imgT;
@@ -163,6 +213,7 @@ struct FwdBandArgs {
 
 struct BpOwnArgs {
     const RayConst* consts;
+    FanGeo fan;
     int n, na, nd, lvl;
     const float* y;
     float* part;  // nq partial images N_l x N_l, image orientation
@@ -176,6 +227,7 @@ struct BpOwnArgs {
 
 struct BpArgs {
     const RayConst* consts;
+    FanGeo fan;
     AngleSplit split;
     int n, na, nd, lvl;
     const float* y;

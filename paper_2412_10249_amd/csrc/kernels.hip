@@ -371,6 +371,113 @@ __global__ void __launch_bounds__(256) k_fwd_direct(FwdBandArgs a)
     a.part[(size_t)ang * a.nd + b] = kc.w * acc;
 }
 
+// ------------------------------------------------------------ fan beam
+
+// Fixed-point Joseph coordinate of fan ray r on a level of nl pixels per
+// side: u(step) = cfx + step * afx in units of 2^-32 pixel (high word the
+// left tap, low word the right tap's weight), and the step length w.  Both
+// kernels of the fan pair call this; the explicit fma leaves the compiler
+// no multiply-add to fuse differently in the two, so they agree on every
+// weight bit for bit.
+__device__ __forceinline__ void fan_coords(const FanRay& r, double E, int nl, long long& cfx, long long& afx,
+                                           float& w)
+{
+    const double hl = 2.0 * E / nl;
+    const double C = fma(E - 0.5 * hl, r.T + 1.0, r.P) * ((double)nl / (2.0 * E));
+    cfx = __double2ll_rn(C * 4294967296.0);
+    afx = __double2ll_rn(-r.T * 4294967296.0);
+    w = (float)(hl * r.sec);
+}
+
+// Fan-beam forward: one thread per ray walks every row (row-stepping rays)
+// or column (column-stepping rays, on the transposed copy) of the padded
+// level image and interpolates between the two taps; taps outside the image
+// read the zero padding, and steps whose taps both lie outside are skipped.
+__global__ void __launch_bounds__(256) k_fwd_fan(FwdBandArgs a)
+{
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (size_t)a.na * a.nd) return;
+    const int nl = a.n >> a.lvl;
+    const int P = nl + kPad;
+    const FanRay r = a.fan.ray[e];
+    long long cfx, afx;
+    float wr;
+    fan_coords(r, a.fan.E, nl, cfx, afx, wr);
+    const float* img = (r.row ? a.img : a.imgT) + kPadL;
+    float acc = 0.0f;
+    long long u = cfx;
+    for (int k = 0; k < nl; ++k, u += afx) {
+        const int j0 = tap_index(u);
+        if ((unsigned)(j0 + 1) <= (unsigned)nl) {  // j0 in [-1, nl - 1]
+            const float w = tap_weight(u);
+            const float* t = img + (size_t)k * P + j0;
+            acc = fmaf(1.0f - w, t[0], fmaf(w, t[1], acc));
+        }
+    }
+    a.part[e] = wr * acc;
+}
+
+// Fan-beam transpose as a gather: one thread per level-l pixel (i, j) and
+// view group.  In a view, the row-stepping rays that put a tap on the pixel
+// are those crossing its row between the centres of pixels j - 1 and j + 1
+// (the column-stepping ones: its column between rows i - 1 and i + 1).
+// Those two end points, projected from the source onto the detector, bound
+// the candidate bins; each candidate is then tested with the forward's own
+// fixed-point coordinate and adds (1 - w) or w times its weighted datum, so
+// every matrix entry is the forward's bit for bit.  A pixel sums its rays in
+// view order, row-stepping candidates first, each in bin order.
+__global__ void __launch_bounds__(256) k_bp_fan(BpOwnArgs a)
+{
+    const int nl = a.n >> a.lvl;
+    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= (long long)nl * nl) return;
+    const int i = (int)(q / nl), j = (int)(q - (long long)i * nl);
+    const int g = blockIdx.y;
+    const int v0 = (int)((long long)g * a.na / a.G), v1 = (int)((long long)(g + 1) * a.na / a.G);
+    const FanGeo& f = a.fan;
+    const double hl = 2.0 * f.E / nl;
+    const double xj = -f.E + (j + 0.5) * hl, yi = -f.E + (i + 0.5) * hl;
+    const double mag = f.D + f.Dd, ids = 1.0 / f.ds, bc = 0.5 * (a.nd - 1);
+    float acc = 0.0f;
+    for (int v = v0; v < v1; ++v) {
+        const FanView fv = f.view[v];
+        const float* yv = a.y + (size_t)v * a.nd;
+        const FanRay* rv = f.ray + (size_t)v * a.nd;
+        for (int pass = 0; pass < 2; ++pass) {
+            if (pass == 0 ? !fv.has_row : !fv.has_col) continue;
+            const double x0 = pass == 0 ? xj - hl : xj, y0 = pass == 0 ? yi : yi - hl;
+            const double x1 = pass == 0 ? xj + hl : xj, y1 = pass == 0 ? yi : yi + hl;
+            // detector coordinate of a point X seen from the source:
+            // t = (D + Dd) (X . et) / (D - X . ec), ec = (c, s), et = (-s, c);
+            // every end point lies within 1.6E of the centre and D > 2E
+            const double t0 = mag * (fv.c * y0 - fv.s * x0) / (f.D - (fv.c * x0 + fv.s * y0));
+            const double t1 = mag * (fv.c * y1 - fv.s * x1) / (f.D - (fv.c * x1 + fv.s * y1));
+            const double b0 = (t0 - f.s0) * ids + bc, b1 = (t1 - f.s0) * ids + bc;
+            const int lo = max(0, (int)ceil(fmin(b0, b1) - 1e-3));
+            const int hi = min(a.nd - 1, (int)floor(fmax(b0, b1) + 1e-3));
+            const int step = pass == 0 ? i : j, at = pass == 0 ? j : i;
+            for (int b = lo; b <= hi; ++b) {
+                const FanRay r = rv[b];
+                if (r.row != (pass == 0 ? 1 : 0)) continue;
+                long long cfx, afx;
+                float wr;
+                fan_coords(r, f.E, nl, cfx, afx, wr);
+                const long long u = cfx + (long long)step * afx;
+                const int t = tap_index(u);
+                float wt;
+                if (t == at)
+                    wt = 1.0f - tap_weight(u);
+                else if (t == at - 1)
+                    wt = tap_weight(u);
+                else
+                    continue;
+                acc = fmaf(wt, wr * yv[b], acc);
+            }
+        }
+    }
+    a.part[(size_t)g * nl * nl + q] = acc;
+}
+
 // Adds the band partials of every term (in band order), then stores,
 // accumulates, or applies the dual SAGA step of Alg. 1:
 // zeta = psi_new - psi_k + sum_j p_j psi_j (old tables),
@@ -1426,6 +1533,7 @@ hipError_t launch_fwd_terms(const FwdArgs& a, hipStream_t s)
         const FwdTerm& tm = a.term[t];
         FwdBandArgs fb{};
         fb.consts = a.consts;
+        fb.fan = a.fan;
         fb.n = a.n;
         fb.na = a.na;
         fb.nd = a.nd;
@@ -1447,6 +1555,9 @@ hipError_t launch_fwd_terms(const FwdArgs& a, hipStream_t s)
             hipError_t e = allow_lds((const void*)k_fwd_band, lds);
             if (e != hipSuccess) return e;
             hipLaunchKernelGGL(k_fwd_band, dim3(tm.bands, fb.groups_row + fb.groups_col), dim3(1024), lds, s, fb);
+        } else if (a.fan.ray) {
+            const size_t m = (size_t)a.na * a.nd;
+            hipLaunchKernelGGL(k_fwd_fan, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, fb);
         } else {
             const int wpa = (a.nd + 63) / 64;
             const long waves = (long)wpa * a.na;
@@ -1511,6 +1622,7 @@ hipError_t launch_bp_main(const BpArgs& ba, hipStream_t s, BpOwnArgs& a)
 {
     a = BpOwnArgs{};
     a.consts = ba.consts;
+    a.fan = ba.fan;
     a.n = ba.n;
     a.na = ba.na;
     a.nd = ba.nd;
@@ -1523,6 +1635,15 @@ hipError_t launch_bp_main(const BpArgs& ba, hipStream_t s, BpOwnArgs& a)
     a.accumulate = ba.accumulate;
     a.prolong = ba.prolong;
     const int nl = ba.n >> ba.lvl;
+    if (ba.fan.ray) {
+        // view groups: about 2^18 threads, G N_l^2 <= kPartImages N^2
+        const size_t d = (size_t)nl * nl;
+        const long long want = (long long)(((size_t)1 << 18) + d - 1) / (long long)d;
+        a.G = (int)std::max(1LL, std::min({want, (long long)ba.na, (long long)kPartImages << (2 * ba.lvl), 4096LL}));
+        a.nq = a.G;
+        hipLaunchKernelGGL(k_bp_fan, dim3((unsigned)((d + 255) / 256), a.G), dim3(256), 0, s, a);
+        return hipGetLastError();
+    }
     // tile shapes measured best on the 512^2 / 720 x 768 workload: two rows
     // per wavefront and 8 wavefronts at the two finest levels, four rows and
     // 4 wavefronts on the coarse ones; rows longer than about 2400 pixels

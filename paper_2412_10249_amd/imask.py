@@ -35,9 +35,12 @@ def _need(t: torch.Tensor, shape, name: str) -> None:
 
 @dataclass(frozen=True)
 class Geometry:
-    """Parallel-beam geometry: N x N image on [-E,E]^2 (E = extent), n_angles
-    angles a*pi/n_angles or the listed ones (radians), n_det bins (spacing
-    <= 0: full-resolution pixel size 2E/N)."""
+    """CT geometry: N x N image on [-E,E]^2 (E = extent) and n_det bins.
+    Parallel beam (src_dist = 0): n_angles angles a*pi/n_angles or the listed
+    ones (radians); spacing <= 0 selects the full-resolution pixel size 2E/N.
+    Fan beam (src_dist = D > 2E): n_angles source positions 2 pi a/n_angles
+    (or listed) at distance D, a flat detector det_dist beyond the centre;
+    spacing <= 0 selects the magnified pixel size 2E/N (D + det_dist)/D."""
     n: int
     n_angles: int
     n_det: int
@@ -45,6 +48,8 @@ class Geometry:
     det_offset: float = 0.0
     extent: float = 1.0
     angles: tuple = None
+    src_dist: float = 0.0
+    det_dist: float = 0.0
 
     def __post_init__(self):
         if self.angles is not None:
@@ -57,7 +62,8 @@ class Geometry:
     def c(self) -> _abi.Geometry:
         # the struct points into this object's angle array: keep self alive
         ang = ctypes.cast(self._carr, ctypes.POINTER(ctypes.c_double)) if self.angles is not None else None
-        return _abi.Geometry(self.n, self.n_angles, self.n_det, self.det_spacing, self.det_offset, self.extent, ang)
+        return _abi.Geometry(self.n, self.n_angles, self.n_det, self.det_spacing, self.det_offset, self.extent, ang,
+                             self.src_dist, self.det_dist)
 
     @property
     def sino_shape(self):

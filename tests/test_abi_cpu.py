@@ -30,7 +30,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_struct_sizes_match_c_layout():
-    assert ctypes.sizeof(_abi.Geometry) == 4 * 3 + 4 + 8 * 3 + 8
+    assert ctypes.sizeof(_abi.Geometry) == 4 * 3 + 4 + 8 * 3 + 8 + 8 * 2
     assert ctypes.sizeof(_abi.Levels) == 4 + 32 + 4 + 64 + 4 + 4
     assert ctypes.sizeof(_abi.Params) == 8 + 8 + 4 + 4 + 8 + 4 + 4 + 4 + 4
     assert ctypes.sizeof(_abi.State) == 8 * 7 + 8 + 8 + 8 + 8 + 16 + 8
@@ -267,3 +267,38 @@ def test_measurement_blocks_validated():
     out = (ctypes.c_int32 * 64)()
     assert L.imask_block_draws(ctypes.byref(prm), ctypes.byref(lv), 5, 64, out) == _abi.OK
     assert list(out) == oracle.block_draws(1, 0, 5, 64, 3)
+
+
+def test_fan_geometry_validated():
+    """Fan beam: source distance in (2E, 1e4 E], detector distance in
+    [0, 1e4 E], spacing and offset bounds taken in magnified pixels, and no
+    measurement blocks."""
+    L = _abi.lib()
+    E = 1.5
+
+    def ok(**kw):
+        gc = im.Geometry(64, 12, 40, extent=E, **kw).c()
+        return L.imask_workspace_bytes(ctypes.byref(gc)) > 0
+
+    par = L.imask_workspace_bytes(ctypes.byref(im.Geometry(64, 12, 40, extent=E).c()))
+    fan = L.imask_workspace_bytes(ctypes.byref(im.Geometry(64, 12, 40, extent=E, src_dist=4.0, det_dist=2.0).c()))
+    assert fan > par > 0  # the ray and view tables
+    assert ok(src_dist=2 * E * 1.0001) and not ok(src_dist=2 * E) and not ok(src_dist=-4.0)
+    assert ok(src_dist=1e4 * E) and not ok(src_dist=1.0001e4 * E)
+    assert not ok(src_dist=4.0, det_dist=-0.1) and not ok(src_dist=4.0, det_dist=1.0001e4 * E)
+    assert not ok(src_dist=float("nan")) and not ok(src_dist=4.0, det_dist=float("inf"))
+    assert not ok(det_dist=float("nan"))  # checked for parallel beam too
+    mag_pix = 2 * E / 64 * (4.0 + 2.0) / 4.0
+    for sp, off, good in [(mag_pix / 64, 0.0, True), (mag_pix / 65, 0.0, False), (64 * mag_pix, 0.0, True),
+                          (65 * mag_pix, 0.0, False), (0.0, 4 * E * 1.5, True), (0.0, -4 * E * 1.5 * 1.001, False)]:
+        assert ok(src_dist=4.0, det_dist=2.0, det_spacing=sp, det_offset=off) == good, (sp, off)
+    g = im.Geometry(64, 10, 12, src_dist=3.0, det_dist=1.0).c()
+    lv = im.Levels((0, 1), (0.5, 0.5), 0, 3).c()
+    reg = _abi.Reg(_abi.REG_TIKHONOV, 0.01, 0.0, 1e-3, 10)
+    s = _abi.State()
+    s.x[0], s.x[1], s.y[0], s.y[1] = 16, 32, 48, 64
+    s.phi, s.psi, s.work = 80, 96, 112
+    b = (ctypes.c_void_p * 1)(16)
+    prm = _abi.Params(0.01, 1, 0)
+    assert L.imask_step(1, ctypes.byref(g), ctypes.byref(lv), ctypes.byref(reg), ctypes.byref(prm), b,
+                        ctypes.byref(s), 1, None) == _abi.ENOTSUP

@@ -7,6 +7,11 @@ I0 = 1e5, smoothed TV (eps = 1e-3) + lambda = 1e-3, levels 512/256/128/64
 with p = 1/4 (the paper's literal construction, PAPER mode).  Epochs count
 equivalent full-resolution operator applications (cost 2^{-l} per step).
 
+With --fan the same workload runs on a fan beam: 720 source positions over
+[0, 2 pi) at distance 4 (the image is [-1, 1]^2), a flat detector of 768
+bins at distance 2 beyond the centre (bins the magnified pixel size, so the
+fan just covers the image's circumscribed circle).
+
 With --blocks S > 1 the same workload runs with the image sketches combined
 with S measurement blocks (each step projects one of S contiguous angle
 blocks; the outlook of Sec. 6); the default is the plain method (S = 1).
@@ -53,6 +58,7 @@ LEVELS = (0, 1, 2, 3)
 LAM, TV_W, TV_EPS, TV_J = 1e-3, 2e-4, 1e-3, 10
 SIGMA = 1e-3
 SEED, STREAM = 42, 0
+FAN_D, FAN_DD = 4.0, 2.0  # fan workload: source and detector distances
 # FP32 arithmetic per Joseph sample (a (ray, step) pair, two matrix entries):
 # coordinate step (1), right-tap weight w and left weight 1 - w (2), two
 # multiply-adds into the accumulator (4).
@@ -101,11 +107,37 @@ def sample_counts(n, na, nd, lvl, angle_stride=1):
     return total if angle_stride == 1 else int(round(total * na / len(picked)))
 
 
-def cpu_baseline(b, budget_s=12.0, blocks=1):
+def fan_sample_counts(n, nv, nd, D, Dd, lvl):
+    """Samples (ray, step) with a tap inside the level-l image for the fan
+    workload (geometry only, the rays built as in the library's tables)."""
+    nl = n >> lvl
+    h = 2.0 / nl
+    ds = (2.0 / n) * (D + Dd) / D
+    t = (np.arange(nd) - (nd - 1) / 2.0) * ds
+    k = -1.0 + (np.arange(nl) + 0.5) * h
+    c0 = -1.0 + 0.5 * h
+    total = 0
+    for a in range(nv):
+        beta = 2 * np.pi * a / nv
+        cb, sb = np.cos(beta), np.sin(beta)
+        dx = -(D + Dd) * cb - t * sb
+        dy = -(D + Dd) * sb + t * cb
+        ln = np.hypot(dx, dy)
+        ct, st = -dy / ln, dx / ln
+        s = D * (ct * cb + st * sb)
+        rows = np.abs(ct) >= np.abs(st)
+        c, o = np.where(rows, ct, st), np.where(rows, st, ct)
+        u = ((s[:, None] - k[None, :] * o[:, None]) / c[:, None] - c0) / h
+        q = np.floor(u)
+        total += int(np.count_nonzero((q >= -1) & (q < nl)))
+    return total
+
+
+def cpu_baseline(b, budget_s=12.0, blocks=1, fan=False):
     """The FP64 oracle running the same iteration on the host cores."""
     import oracle
 
-    g = oracle.Geometry(N, NA, ND)
+    g = oracle.Geometry(N, NA, ND, src_dist=FAN_D, det_dist=FAN_DD) if fan else oracle.Geometry(N, NA, ND)
     lv = oracle.Levels(list(LEVELS), [1.0 / len(LEVELS)] * len(LEVELS))
     reg = oracle.Reg(oracle.REG_SMOOTH_TV, lam=LAM, tv_weight=TV_W, tv_eps=TV_EPS, tv_inner=TV_J)
     st = None
@@ -171,7 +203,7 @@ def run(args):
     torch.cuda.set_device(0)
     _, b = synth.ct_problem(N, NA, ND, I0, 1000, 2000)
     b32 = torch.from_numpy(b.astype(np.float32)).cuda()
-    geom = pk.Geometry(N, NA, ND)
+    geom = pk.Geometry(N, NA, ND, src_dist=FAN_D, det_dist=FAN_DD) if args.fan else pk.Geometry(N, NA, ND)
     lv = pk.Levels.uniform(LEVELS, pk.FULL_PAPER, args.blocks)
     reg = pk.Regularizer(pk.REG_SMOOTH_TV, LAM, TV_W, TV_EPS, TV_J)
     prob = pk.Problem(geom, lv, reg, pk.Params(SIGMA, SEED, STREAM), b32)
@@ -200,12 +232,18 @@ def run(args):
         for _ in range(3):
             pk.resample(src, 0, pk.PROLONG)
         torch.cuda.synchronize()
-    samples = {lvl: sample_counts(N, NA, ND, lvl) for lvl in LEVELS}
+    if args.fan:
+        samples = {lvl: fan_sample_counts(N, NA, ND, FAN_D, FAN_DD, lvl) for lvl in LEVELS}
+    else:
+        samples = {lvl: sample_counts(N, NA, ND, lvl) for lvl in LEVELS}
     # dominant kernel: largest expected time per step under the level mix
     share = {key: t * lv.p[LEVELS.index(key[1])] for key, t in kern.items()}
     dom = max(share, key=share.get)
     dom_t = kern[dom]
-    name = {"fwd": "k_fwd_band" if (N >> dom[1]) <= 512 else "k_fwd_direct", "bp": "k_bp_own"}[dom[0]]
+    if args.fan:
+        name = {"fwd": "k_fwd_fan", "bp": "k_bp_fan"}[dom[0]]
+    else:
+        name = {"fwd": "k_fwd_band" if (N >> dom[1]) <= 512 else "k_fwd_direct", "bp": "k_bp_own"}[dom[0]]
     key = f"{name}_l{dom[1]}"
     achieved = samples[dom[1]] * FLOP_PER_SAMPLE / dom_t / 1e12
     out = {
@@ -221,7 +259,9 @@ def run(args):
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic: seeded random-ellipse phantom, analytic line integrals, Poisson I0=1e5",
-        "config": {"workload": "2D parallel-beam CT 512x512, 720 angles x 768 bins, smoothed TV eps=1e-3 + "
+        "config": {"workload": ("2D fan-beam CT 512x512, 720 views over 2pi x 768 flat-detector bins, source "
+                                f"distance {FAN_D}, detector distance {FAN_DD}" if args.fan else
+                                "2D parallel-beam CT 512x512, 720 angles x 768 bins") + ", smoothed TV eps=1e-3 + "
                                "lambda=1e-3, levels 512/256/128/64 uniform p, ImaSk (PAPER sketches)"
                                + (f", {args.blocks} measurement blocks of {NA // args.blocks} angles"
                                   if args.blocks > 1 else ""),
@@ -233,7 +273,7 @@ def run(args):
                      "effective_gather_frac_hbm": samples[dom[1]] * 8 / dom_t / 1e9 / HBM_PEAK_GBS},
         # the transpose's working limit: LDS traffic, two read-modify-writes of
         # 4-byte cells per sample, against 256 CUs x 128 B/clk x 2.4 GHz
-        "lds_roofline": {"kernel": key, "bytes_per_sample": LDS_BYTES_PER_SAMPLE[dom[0]],
+        "lds_roofline": None if args.fan else {"kernel": key, "bytes_per_sample": LDS_BYTES_PER_SAMPLE[dom[0]],
                          "achieved_TBps": samples[dom[1]] * LDS_BYTES_PER_SAMPLE[dom[0]] / dom_t / 1e12,
                          "peak_TBps": LDS_PEAK_TBPS,
                          "frac": samples[dom[1]] * LDS_BYTES_PER_SAMPLE[dom[0]] / dom_t / 1e12 / LDS_PEAK_TBPS},
@@ -242,7 +282,7 @@ def run(args):
         "kernel_source_hash": source_hash(),
     }
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(b, blocks=args.blocks)
+        out["cpu_baseline"] = cpu_baseline(b, blocks=args.blocks, fan=args.fan)
     print(json.dumps(out), flush=True)
 
 
@@ -823,6 +863,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--blocks", type=int, default=1, help="measurement blocks combined with the image sketches")
+    ap.add_argument("--fan", action="store_true", help="the same workload on a fan beam")
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--kernel-reps", type=int, default=20)

@@ -108,6 +108,13 @@ Layout make_layout(const imask_geometry& g)
         L.fan = 1;
         L.D = g.src_dist;
         L.Dd = g.det_dist;
+        // The transpose estimates bin coordinates in FP32: every point it
+        // projects lies within 1.6E of the centre, so |t| <= (D + Dd) 1.6E /
+        // (D - 1.6E) < 3.8 (D + Dd)/D E, and the estimate's error stays below
+        // 32 ulp of the largest term of (t - s0)/ds + (n_det - 1)/2; the
+        // margin is 1e-2 bin plus ten times that.
+        const double big = 3.8 * fan_mag(g) * L.E / L.ds + std::fabs(g.det_offset) / L.ds + g.n_det;
+        L.bmargin = 1e-2 + 10.0 * 32.0 * std::ldexp(1.0, -24) * big;
         L.fray = off;
         off = align64(off + m * (sizeof(FanRay) / sizeof(float)));
         L.fview = off;

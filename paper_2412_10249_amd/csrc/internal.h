@@ -109,6 +109,7 @@ struct FanGeo {
     const FanRay* ray;    // n_angles x n_det, view-major; null: parallel beam
     const FanView* view;  // n_angles
     double E, D, Dd, ds, s0;
+    float bmargin;        // bins added to each side of an FP32 bin estimate
 };
 
 // Workspace layout for one geometry (offsets in floats from the start).
@@ -132,7 +133,7 @@ struct Layout {
     // fan beam: ray table (m FanRay) and view table (na FanView)
     int fan = 0;
     size_t fray = 0, fview = 0;
-    double E = 1.0, D = 0.0, Dd = 0.0, ds = 0.0, s0 = 0.0;
+    double E = 1.0, D = 0.0, Dd = 0.0, ds = 0.0, s0 = 0.0, bmargin = 0.0;
     size_t total = 0;
 };
 
@@ -160,6 +161,7 @@ inline FanGeo fan_at(const Layout& L, const float* W)
     f.Dd = L.Dd;
     f.ds = L.ds;
     f.s0 = L.s0;
+    f.bmargin = (float)L.bmargin;
     return f;
 }
 inline int side(int n, int l) { return n >> l; }

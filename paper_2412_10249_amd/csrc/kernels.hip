@@ -417,65 +417,177 @@ __global__ void __launch_bounds__(256) k_fwd_fan(FwdBandArgs a)
     a.part[e] = wr * acc;
 }
 
-// Fan-beam transpose as a gather: one thread per level-l pixel (i, j) and
-// view group.  In a view, the row-stepping rays that put a tap on the pixel
-// are those crossing its row between the centres of pixels j - 1 and j + 1
-// (the column-stepping ones: its column between rows i - 1 and i + 1).
-// Those two end points, projected from the source onto the detector, bound
-// the candidate bins; each candidate is then tested with the forward's own
-// fixed-point coordinate and adds (1 - w) or w times its weighted datum, so
-// every matrix entry is the forward's bit for bit.  A pixel sums its rays in
-// view order, row-stepping candidates first, each in bin order.
+// Fan-beam transpose as a gather over 16 x 16 pixel tiles, one workgroup
+// per tile and view group.  In a view, the row-stepping rays that put a tap
+// on pixel (i, j) are those crossing its row between the centres of pixels
+// j - 1 and j + 1 (column-stepping ones: its column between rows i - 1 and
+// i + 1); those end points, projected from the source onto the detector,
+// bound the pixel's candidate bins, and the projections of the tile's two
+// end-point boxes bound the tile's.  Each round stages the tile's candidate
+// bins of up to kFanViews consecutive views (at most kFanSlots bins; a view
+// with more continues in the next round) through LDS, each bin with the
+// forward's fixed-point coordinate and its weighted datum; every pixel then
+// tests its own candidates exactly and adds (1 - w) or w of the datum, so
+// every matrix entry is the forward's bit for bit.  Bin estimates are FP32
+// with a margin (bmargin) well above their rounding error: a spare
+// candidate fails the exact test, none is missed.  A pixel sums its rays in
+// view order and bin order, row-stepping candidates before column-stepping
+// ones within a staged segment of a view.
+constexpr int kFanTile = 16;
+constexpr int kFanSlots = 512;
+#ifndef IMK_FAN_TARGET_WG
+#define IMK_FAN_TARGET_WG 8192
+#endif
+constexpr int kFanViews = 16;
+
 __global__ void __launch_bounds__(256) k_bp_fan(BpOwnArgs a)
 {
+    __shared__ long long s_cfx[kFanSlots], s_afx[kFanSlots];
+    __shared__ float s_wy[kFanSlots];
+    __shared__ int s_row[kFanSlots];
+    __shared__ int q_lo[kFanViews], q_hi[kFanViews], q_fl[kFanViews];  // the round's views: tile ranges, axes
+    __shared__ float q_c[kFanViews], q_s[kFanViews];
+    __shared__ int g_view[kFanViews + 1], g_b0[kFanViews + 1], g_start[kFanViews + 1];  // segments
+    __shared__ int g_n, g_next_v, g_next_b;
     const int nl = a.n >> a.lvl;
-    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= (long long)nl * nl) return;
-    const int i = (int)(q / nl), j = (int)(q - (long long)i * nl);
+    const int tiles = (nl + kFanTile - 1) / kFanTile;
+    const int ty = blockIdx.x / tiles, tx = blockIdx.x - ty * tiles;
+    const int i = ty * kFanTile + (threadIdx.x >> 4), j = tx * kFanTile + (threadIdx.x & 15);
+    const bool inside = i < nl && j < nl;
     const int g = blockIdx.y;
     const int v0 = (int)((long long)g * a.na / a.G), v1 = (int)((long long)(g + 1) * a.na / a.G);
     const FanGeo& f = a.fan;
     const double hl = 2.0 * f.E / nl;
-    const double xj = -f.E + (j + 0.5) * hl, yi = -f.E + (i + 0.5) * hl;
-    const double mag = f.D + f.Dd, ids = 1.0 / f.ds, bc = 0.5 * (a.nd - 1);
+    auto ctr = [&](int k) { return (float)(-f.E + (k + 0.5) * hl); };  // pixel-centre coordinate
+    const float xj = ctr(j), yi = ctr(i), hf = (float)hl;
+    const float Df = (float)f.D, mag = (float)(f.D + f.Dd), ids = (float)(1.0 / f.ds);
+    const float bofs = (float)(0.5 * (a.nd - 1) - f.s0 / f.ds), marg = f.bmargin, top = (float)(a.nd - 1);
+    // detector bin coordinate of a point seen from the source of view (c, s)
+    auto bin = [&](float c, float s, float x, float y) {
+        return mag * (c * y - s * x) * __builtin_amdgcn_rcpf(Df - (c * x + s * y)) * ids + bofs;
+    };
+    // a bin interval's first and last candidates, clamped before the conversion
+    auto first = [&](float lo) { return (int)ceilf(fminf(fmaxf(lo - marg, 0.0f), top + 1.0f)); };
+    auto last = [&](float hi) { return (int)floorf(fmaxf(fminf(hi + marg, top), -1.0f)); };
     float acc = 0.0f;
-    for (int v = v0; v < v1; ++v) {
-        const FanView fv = f.view[v];
-        const float* yv = a.y + (size_t)v * a.nd;
-        const FanRay* rv = f.ray + (size_t)v * a.nd;
-        for (int pass = 0; pass < 2; ++pass) {
-            if (pass == 0 ? !fv.has_row : !fv.has_col) continue;
-            const double x0 = pass == 0 ? xj - hl : xj, y0 = pass == 0 ? yi : yi - hl;
-            const double x1 = pass == 0 ? xj + hl : xj, y1 = pass == 0 ? yi : yi + hl;
-            // detector coordinate of a point X seen from the source:
-            // t = (D + Dd) (X . et) / (D - X . ec), ec = (c, s), et = (-s, c);
-            // every end point lies within 1.6E of the centre and D > 2E
-            const double t0 = mag * (fv.c * y0 - fv.s * x0) / (f.D - (fv.c * x0 + fv.s * y0));
-            const double t1 = mag * (fv.c * y1 - fv.s * x1) / (f.D - (fv.c * x1 + fv.s * y1));
-            const double b0 = (t0 - f.s0) * ids + bc, b1 = (t1 - f.s0) * ids + bc;
-            const int lo = max(0, (int)ceil(fmin(b0, b1) - 1e-3));
-            const int hi = min(a.nd - 1, (int)floor(fmax(b0, b1) + 1e-3));
-            const int step = pass == 0 ? i : j, at = pass == 0 ? j : i;
-            for (int b = lo; b <= hi; ++b) {
-                const FanRay r = rv[b];
-                if (r.row != (pass == 0 ? 1 : 0)) continue;
-                long long cfx, afx;
-                float wr;
-                fan_coords(r, f.E, nl, cfx, afx, wr);
-                const long long u = cfx + (long long)step * afx;
-                const int t = tap_index(u);
-                float wt;
-                if (t == at)
-                    wt = 1.0f - tap_weight(u);
-                else if (t == at - 1)
-                    wt = tap_weight(u);
-                else
-                    continue;
-                acc = fmaf(wt, wr * yv[b], acc);
+    int v = v0, boff = -1;  // next view; first bin still to stage in it (-1: its tile range start)
+    while (v < v1) {
+        __syncthreads();  // the previous round's LDS has been read
+        if ((int)threadIdx.x < kFanViews) {
+            // tile range of view v + t: projections of the end-point boxes
+            // (row pass: x over centres tx*16-1 .. tx*16+16, y over the tile's
+            // rows; column pass the mirror), all within 1.6E of the centre
+            const int t = threadIdx.x, vv = v + t;
+            int lo = 0, hi = -1, fl = 0;
+            float c = 0.0f, s = 0.0f;
+            if (vv < v1) {
+                const FanView fv = f.view[vv];
+                c = (float)fv.c;
+                s = (float)fv.s;
+                fl = (fv.has_row ? 1 : 0) | (fv.has_col ? 2 : 0);
+                const int e0 = tx * kFanTile, e1 = min(e0 + kFanTile, nl);
+                const int r0 = ty * kFanTile, r1 = min(r0 + kFanTile, nl);
+                float blo = 3.0e38f, bhi = -3.0e38f;
+                auto box = [&](float x0, float x1, float y0, float y1) {
+                    const float q0 = bin(c, s, x0, y0), q1 = bin(c, s, x1, y0);
+                    const float q2 = bin(c, s, x0, y1), q3 = bin(c, s, x1, y1);
+                    blo = fminf(blo, fminf(fminf(q0, q1), fminf(q2, q3)));
+                    bhi = fmaxf(bhi, fmaxf(fmaxf(q0, q1), fmaxf(q2, q3)));
+                };
+                if (fl & 1) box(ctr(e0 - 1), ctr(e1), ctr(r0), ctr(r1 - 1));
+                if (fl & 2) box(ctr(e0), ctr(e1 - 1), ctr(r0 - 1), ctr(r1));
+                lo = first(blo);
+                hi = last(bhi);
+            }
+            q_lo[t] = lo;
+            q_hi[t] = hi;
+            q_fl[t] = fl;
+            q_c[t] = c;
+            q_s[t] = s;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            // cut the round into segments of the views' ranges, kFanSlots bins in all
+            int n = 0, used = 0, nv = v, nb = -1;
+            for (int k = 0; k < kFanViews && v + k < v1; ++k) {
+                const int lo = (k == 0 && boff >= 0) ? boff : q_lo[k];
+                const int cnt = q_hi[k] - lo + 1;
+                const int take = min(cnt, kFanSlots - used);
+                if (take > 0) {
+                    g_view[n] = k;
+                    g_b0[n] = lo;
+                    g_start[n] = used;
+                    ++n;
+                    used += take;
+                }
+                if (take < cnt) {  // the view continues next round
+                    nv = v + k;
+                    nb = lo + take;
+                    break;
+                }
+                nv = v + k + 1;
+            }
+            g_start[n] = used;
+            g_n = n;
+            g_next_v = nv;
+            g_next_b = nb;
+        }
+        __syncthreads();
+        const int n = g_n, used = g_start[n];
+        for (int sl = threadIdx.x; sl < used; sl += blockDim.x) {
+            int k = 0;
+            while (k + 1 < n && g_start[k + 1] <= sl) ++k;
+            const int vv = v + g_view[k], b = g_b0[k] + (sl - g_start[k]);
+            const FanRay r = f.ray[(size_t)vv * a.nd + b];
+            long long cfx, afx;
+            float wr;
+            fan_coords(r, f.E, nl, cfx, afx, wr);
+            s_cfx[sl] = cfx;
+            s_afx[sl] = afx;
+            s_wy[sl] = wr * a.y[(size_t)vv * a.nd + b];
+            s_row[sl] = r.row;
+        }
+        const int next_v = g_next_v, next_b = g_next_b;
+        __syncthreads();
+        if (inside) {
+            for (int k = 0; k < n; ++k) {
+                const int kv = g_view[k], fl = q_fl[kv];
+                const float c = q_c[kv], s = q_s[kv];
+                const int b0 = g_b0[k], b1 = b0 + (g_start[k + 1] - g_start[k]) - 1, base = g_start[k] - b0;
+                if (fl & 1) {
+                    const float p0 = bin(c, s, xj - hf, yi), p1 = bin(c, s, xj + hf, yi);
+                    const int lo = max(b0, first(fminf(p0, p1))), hi = min(b1, last(fmaxf(p0, p1)));
+                    for (int b = lo; b <= hi; ++b) {
+                        const int sl = b + base;
+                        if (!s_row[sl]) continue;
+                        const long long u = s_cfx[sl] + (long long)i * s_afx[sl];
+                        const int t = tap_index(u);
+                        if (t == j)
+                            acc = fmaf(1.0f - tap_weight(u), s_wy[sl], acc);
+                        else if (t == j - 1)
+                            acc = fmaf(tap_weight(u), s_wy[sl], acc);
+                    }
+                }
+                if (fl & 2) {
+                    const float p0 = bin(c, s, xj, yi - hf), p1 = bin(c, s, xj, yi + hf);
+                    const int lo = max(b0, first(fminf(p0, p1))), hi = min(b1, last(fmaxf(p0, p1)));
+                    for (int b = lo; b <= hi; ++b) {
+                        const int sl = b + base;
+                        if (s_row[sl]) continue;
+                        const long long u = s_cfx[sl] + (long long)j * s_afx[sl];
+                        const int t = tap_index(u);
+                        if (t == i)
+                            acc = fmaf(1.0f - tap_weight(u), s_wy[sl], acc);
+                        else if (t == i - 1)
+                            acc = fmaf(tap_weight(u), s_wy[sl], acc);
+                    }
+                }
             }
         }
+        v = next_v;
+        boff = next_b;
     }
-    a.part[(size_t)g * nl * nl + q] = acc;
+    if (inside) a.part[(size_t)g * nl * nl + (size_t)i * nl + j] = acc;
 }
 
 // Adds the band partials of every term (in band order), then stores,
@@ -1636,12 +1748,12 @@ hipError_t launch_bp_main(const BpArgs& ba, hipStream_t s, BpOwnArgs& a)
     a.prolong = ba.prolong;
     const int nl = ba.n >> ba.lvl;
     if (ba.fan.ray) {
-        // view groups: about 2^18 threads, G N_l^2 <= kPartImages N^2
-        const size_t d = (size_t)nl * nl;
-        const long long want = (long long)(((size_t)1 << 18) + d - 1) / (long long)d;
+        // view groups: about IMK_FAN_TARGET_WG workgroups, G N_l^2 <= kPartImages N^2
+        const long long tiles = (long long)((nl + kFanTile - 1) / kFanTile) * ((nl + kFanTile - 1) / kFanTile);
+        const long long want = (IMK_FAN_TARGET_WG + tiles - 1) / tiles;
         a.G = (int)std::max(1LL, std::min({want, (long long)ba.na, (long long)kPartImages << (2 * ba.lvl), 4096LL}));
         a.nq = a.G;
-        hipLaunchKernelGGL(k_bp_fan, dim3((unsigned)((d + 255) / 256), a.G), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(k_bp_fan, dim3((unsigned)tiles, a.G), dim3(256), 0, s, a);
         return hipGetLastError();
     }
     // tile shapes measured best on the 512^2 / 720 x 768 workload: two rows

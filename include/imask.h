@@ -4,7 +4,7 @@
  * (Perelli, Schönlieb, Ehrhardt, arXiv 2412.10249).
  *
  * Problem (Sec. 1, eq. (min_obj)):  min_x 1/2 |K x - b|^2 + R(x), K the 2-D
- * parallel-beam CT model.  ImaSk (Alg. 1) replaces K by a family of sketched
+ * parallel-beam (or fan-beam) CT model.  ImaSk (Alg. 1) replaces K by a family of sketched
  * operators K_i = K S_i (eq. (CT_sketches)) with probabilities p_i and runs a
  * SAGA-type primal-dual iteration that applies one K_i and one K_i^T per step.
  *

@@ -4,12 +4,15 @@ against the FP64 oracle (through the C ABI).
 Geometries: a 64^2 grid with 60 views over [0, 2pi); a ragged 48^2 grid with
 37 listed views, an offset detector and a wide fan (rays of one view step
 along rows and along columns); a 256^2 grid with 360 views x 384 bins at
-levels 0-3; a 16^2 grid.  Tolerances as for the parallel pair: relative l2
-<= 1e-5 for projections and backprojections, the tiny matrices bitwise
-transposed, iterates within 1e-4 (TV prior 1e-3) after 30-40 iterations.
+levels 0-3; a 16^2 grid; the largest grid and detector (16384^2, 8192 bins)
+and 4096^2 with 5800 bins; degenerate sizes (a 4^2 grid, one bin, one view).
+Tolerances as for the parallel pair: relative l2 <= 1e-5 for projections and
+backprojections, the tiny matrices bitwise transposed, iterates within 1e-4
+(TV prior 1e-3) after 12-40 iterations.
 """
 import numpy as np
 import pytest
+import torch
 
 import oracle
 import synth
@@ -141,3 +144,40 @@ def test_fan_beam_batched_equals_alone_and_repeat_is_bitwise():
     pk.step_many(batch, 15)
     for a, c in zip(alone, batch):
         assert np.array_equal(host(a.x_cur), host(c.x_cur)) and np.array_equal(host(a.y_cur), host(c.y_cur))
+
+
+@pytest.mark.parametrize("n,nv,nd", [(4096, 6, 5800), (16384, 2, 8192)])
+def test_fan_very_large_grids(n, nv, nd):
+    """The largest grid and detector the boundary takes, levels 0 and 1."""
+    g = pk.Geometry(n, nv, nd, src_dist=2.5, det_dist=0.5)
+    og = oracle.Geometry(n, nv, nd, src_dist=2.5, det_dist=0.5)
+    work = pk.workspace(g)
+    x = f32(synth.random_image(n, 23))
+    y = f32(synth.random_sinogram(nv, nd, 24))
+    for l in (0, 1):
+        say(f"fan grid {n} level {l}")
+        got = host(pk.project(g, l, dev(x), work))
+        assert rel(got, oracle.project(og, l, oracle.restrict(x, l))) <= 1e-5
+        got = host(pk.backproject(g, l, dev(y), work))
+        assert rel(got, oracle.prolong(oracle.backproject(og, l, y), l) / 4 ** l) <= 1e-5
+    del work
+    torch.cuda.empty_cache()
+
+
+def test_fan_degenerate_sizes():
+    """The smallest grid (4 x 4, levels 4 and 2), a single detector bin (the
+    central ray) and a single view, 12 iterations of Alg. 1 (UNBIASED)."""
+    for n, nv, nd, lv in ((4, 3, 5, (0, 1)), (16, 1, 1, (0, 1, 2)), (8, 7, 1, (0,))):
+        g = pk.Geometry(n, nv, nd, src_dist=2.5, det_dist=0.5)
+        og = oracle.Geometry(n, nv, nd, src_dist=2.5, det_dist=0.5)
+        b = f32(synth.random_sinogram(nv, nd, 60 + n))
+        p = (1.0 / len(lv),) * len(lv)
+        say(f"fan degenerate n={n} views={nv} bins={nd}")
+        ost = oracle.imask_run(og, oracle.Levels(list(lv), list(p), oracle.MODE_UNBIASED), oracle.Reg(lam=0.5),
+                               0.05, 42, 0, b, 12)
+        prob = pk.Problem(g, pk.Levels(lv, p, pk.FULL_UNBIASED), pk.Regularizer(pk.REG_TIKHONOV, 0.5),
+                          pk.Params(0.05, 42, 0), dev(b))
+        prob.step(12)
+        assert prob.epochs == ost.epochs
+        assert rel(host(prob.x_cur), ost.x) <= 1e-4
+        assert rel(host(prob.y_cur), ost.y) <= 1e-4

@@ -168,9 +168,10 @@ def stored_traffic(kernel_key):
     return None if ent is None else ent.get("bytes_per_launch")
 
 
-def counter_run(spec: str):
+def counter_run(spec: str, fan: bool = False):
     """Launch only one projector kernel (plus the calibration copy), for a
-    rocprofv3 --pmc pass: spec is fwd:LEVEL or bp:LEVEL."""
+    rocprofv3 --pmc pass: spec is fwd:LEVEL or bp:LEVEL (fan: on the fan
+    workload's geometry)."""
     import torch
 
     import paper_2412_10249_amd as pk
@@ -178,7 +179,7 @@ def counter_run(spec: str):
     kind, lvl = spec.split(":")
     lvl = int(lvl)
     torch.cuda.set_device(0)
-    geom = pk.Geometry(N, NA, ND)
+    geom = pk.Geometry(N, NA, ND, src_dist=FAN_D, det_dist=FAN_DD) if fan else pk.Geometry(N, NA, ND)
     work = pk.workspace(geom)
     g = torch.Generator(device="cuda").manual_seed(5)
     src = torch.rand((COPY_N, COPY_N), device="cuda", generator=g)
@@ -936,7 +937,7 @@ def main():
                 json.dump(traffic, f, indent=1)
         return
     if args.counters:
-        counter_run(args.counters)
+        counter_run(args.counters, args.fan)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path does not shard "

@@ -119,6 +119,16 @@ Layout make_layout(const imask_geometry& g)
         off = align64(off + m * (sizeof(FanRay) / sizeof(float)));
         L.fview = off;
         off = align64(off + (size_t)g.n_angles * (sizeof(FanView) / sizeof(float)));
+        L.ftab = off;
+        off = align64(off + m * (sizeof(FanTab) / sizeof(float)));
+        // Adjacent bins of a flat detector subtend at least
+        // ds L / (L^2 + t_max^2) radians at the source (L = D + Dd, t_max the
+        // largest |t_b|), and every cell the transpose updates lies at least
+        // D - 1.6E from the source: two rays b bins apart are at least
+        // b times that far apart across a row or column there.
+        const double Lsd = g.src_dist + g.det_dist;
+        const double tmax = 0.5 * (g.n_det - 1) * L.ds + std::fabs(g.det_offset);
+        L.min_sep = (g.src_dist - 1.6 * L.E) * L.ds * Lsd / (Lsd * Lsd + tmax * tmax);
         L.split = angle_split(g.n_angles);  // unused by the fan kernels
     } else if (g.angles) {
         L.listed = 1;

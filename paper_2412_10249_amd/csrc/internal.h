@@ -103,12 +103,23 @@ struct FanView {
     int pad[2];
 };
 static_assert(sizeof(FanView) == 32, "FanView is 32 bytes");
+// A fan ray on one level, as the transpose scatters it: the fixed-point
+// coordinate u(step) = cfx + step * afx (from fan_coords), the weighted datum
+// w_ray * y, and the stepping axis.
+struct FanTab {
+    long long cfx, afx;
+    float wy;
+    int row;
+};
+static_assert(sizeof(FanTab) == 24, "FanTab is 24 bytes");
 // What the fan kernels need besides the ray and view tables: the domain
 // half side, source and detector distances, bin spacing and offset.
 struct FanGeo {
     const FanRay* ray;    // n_angles x n_det, view-major; null: parallel beam
     const FanView* view;  // n_angles
+    FanTab* tab;          // n_angles x n_det, the transpose's per-launch table
     double E, D, Dd, ds, s0;
+    double min_sep;       // lower bound of adjacent rays' separation (domain units)
     float bmargin;        // bins added to each side of an FP32 bin estimate
 };
 
@@ -132,8 +143,8 @@ struct Layout {
     AngleSplit split{};                    // perm / rows unset: see split_at
     // fan beam: ray table (m FanRay) and view table (na FanView)
     int fan = 0;
-    size_t fray = 0, fview = 0;
-    double E = 1.0, D = 0.0, Dd = 0.0, ds = 0.0, s0 = 0.0, bmargin = 0.0;
+    size_t fray = 0, fview = 0, ftab = 0;
+    double E = 1.0, D = 0.0, Dd = 0.0, ds = 0.0, s0 = 0.0, bmargin = 0.0, min_sep = 0.0;
     size_t total = 0;
 };
 
@@ -155,6 +166,7 @@ inline FanGeo fan_at(const Layout& L, const float* W)
     if (L.fan) {
         f.ray = (const FanRay*)(W + L.fray);
         f.view = (const FanView*)(W + L.fview);
+        f.tab = (FanTab*)(const_cast<float*>(W) + L.ftab);
     }
     f.E = L.E;
     f.D = L.D;
@@ -162,6 +174,7 @@ inline FanGeo fan_at(const Layout& L, const float* W)
     f.ds = L.ds;
     f.s0 = L.s0;
     f.bmargin = (float)L.bmargin;
+    f.min_sep = L.min_sep;
     return f;
 }
 inline int side(int n, int l) { return n >> l; }

@@ -38,6 +38,12 @@ constexpr float kTwoM32 = 2.3283064365386963e-10f;  // 2^-32
 __device__ __forceinline__ int tap_index(long long u) { return (int)(u >> 32); }
 __device__ __forceinline__ float tap_weight(long long u) { return (float)(unsigned)(u & 0xffffffffLL) * kTwoM32; }
 
+// Compiler-only ordering point between the two read-modify-write phases of
+// a scatter (left taps, then right taps): LDS operations of one wavefront
+// execute in program order, so keeping the compiler from moving them across
+// is all that is needed.
+#define IMK_LDS_ORDER() asm volatile("" ::: "memory")
+
 // th / rows: listed angles (radians) and their stepping flags, or null for
 // a*pi/na; side = 2E, the side of the image square.
 __global__ void k_consts(int n, int na, int nd, double ds, double s0, double side, const double* th_tab,
@@ -417,22 +423,23 @@ __global__ void __launch_bounds__(256) k_fwd_fan(FwdBandArgs a)
     a.part[e] = wr * acc;
 }
 
-// Fan-beam transpose as a gather over 16 x 16 pixel tiles, one workgroup
-// per tile and view group.  In a view, the row-stepping rays that put a tap
-// on pixel (i, j) are those crossing its row between the centres of pixels
-// j - 1 and j + 1 (column-stepping ones: its column between rows i - 1 and
-// i + 1); those end points, projected from the source onto the detector,
-// bound the pixel's candidate bins, and the projections of the tile's two
-// end-point boxes bound the tile's.  Each round stages the tile's candidate
-// bins of up to kFanViews consecutive views (at most kFanSlots bins; a view
-// with more continues in the next round) through LDS, each bin with the
-// forward's fixed-point coordinate and its weighted datum; every pixel then
-// tests its own candidates exactly and adds (1 - w) or w of the datum, so
-// every matrix entry is the forward's bit for bit.  Bin estimates are FP32
-// with a margin (bmargin) well above their rounding error: a spare
-// candidate fails the exact test, none is missed.  A pixel sums its rays in
-// view order and bin order, row-stepping candidates before column-stepping
-// ones within a staged segment of a view.
+// Fan-beam transpose as a gather, for levels where rays are dense (more than
+// kFanScatterMaxP phases of the scatter below): 16 x 16 pixel tiles, one
+// workgroup per tile and view group.  In a view, the row-stepping rays that
+// put a tap on pixel (i, j) are those crossing its row between the centres
+// of pixels j - 1 and j + 1 (column-stepping ones: its column between rows
+// i - 1 and i + 1); those end points, projected from the source onto the
+// detector, bound the pixel's candidate bins, and the projections of the
+// tile's two end-point boxes bound the tile's.  Each round stages the
+// tile's candidate bins of up to kFanViews consecutive views (at most
+// kFanSlots bins; a view with more continues in the next round) through
+// LDS, each bin with the forward's fixed-point coordinate and its weighted
+// datum; every pixel then tests its own candidates exactly and adds (1 - w)
+// or w of the datum, so every matrix entry is the forward's bit for bit.
+// Bin estimates are FP32 with a margin (bmargin) well above their rounding
+// error: a spare candidate fails the exact test, none is missed.  A pixel
+// sums its rays in view order and bin order, row-stepping candidates before
+// column-stepping ones within a staged segment of a view.
 constexpr int kFanTile = 16;
 constexpr int kFanSlots = 512;
 #ifndef IMK_FAN_TARGET_WG
@@ -440,7 +447,7 @@ constexpr int kFanSlots = 512;
 #endif
 constexpr int kFanViews = 16;
 
-__global__ void __launch_bounds__(256) k_bp_fan(BpOwnArgs a)
+__global__ void __launch_bounds__(256) k_bp_fan_gather(BpOwnArgs a)
 {
     __shared__ long long s_cfx[kFanSlots], s_afx[kFanSlots];
     __shared__ float s_wy[kFanSlots];
@@ -588,6 +595,154 @@ __global__ void __launch_bounds__(256) k_bp_fan(BpOwnArgs a)
         boff = next_b;
     }
     if (inside) a.part[(size_t)g * nl * nl + (size_t)i * nl + j] = acc;
+}
+
+// Per-launch table of the fan transpose: every ray's fixed-point
+// coordinate on this level (fan_coords, as the forward computes it) and its
+// weighted datum w_ray * y.
+__global__ void __launch_bounds__(256) k_fan_table(BpOwnArgs a)
+{
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (size_t)a.na * a.nd) return;
+    const int nl = a.n >> a.lvl;
+    const FanRay r = a.fan.ray[e];
+    FanTab t;
+    float wr;
+    fan_coords(r, a.fan.E, nl, t.cfx, t.afx, wr);
+    t.wy = wr * a.y[e];
+    t.row = r.row;
+    a.fan.tab[e] = t;
+}
+
+// Fan-beam transpose as an ownership scatter.  Workgroup (block, pass,
+// group) owns 2 * waves image rows (pass 0, row-stepping rays) or columns
+// (pass 1, column-stepping rays) in LDS, two per wavefront, each with one
+// cell beyond either end of the image for the taps that fall outside it.
+// For each view of its group, every wavefront takes the bins that can reach
+// the block (the projection of the block's end-point box, FP32 with a
+// margin) in P phases: lanes of one instruction hold bins P apart, and P is
+// chosen so that such rays are more than a pixel apart at every owned cell,
+// so no two lanes of an instruction update the same cell.  A lane takes
+// kFanChunks rays per trip, 64 P bins apart (every ray of a trip is at least
+// P bins from every other), and issues all their cells' reads before the
+// writes, so the LDS latencies overlap.  A sample adds (1 - w) of its ray's
+// weighted datum to the left tap, then w to the right tap: the forward's
+// weights bit for bit, in a fixed order.  Used where P <= kFanScatterMaxP.
+#ifndef IMK_FAN_SCATTER_WAVES
+#define IMK_FAN_SCATTER_WAVES 8
+#endif
+#ifndef IMK_FAN_CHUNKS
+#define IMK_FAN_CHUNKS 2
+#endif
+constexpr int kFanRowsPerWave = 2;
+constexpr int kFanMaxWaves = IMK_FAN_SCATTER_WAVES;
+constexpr int kFanChunks = IMK_FAN_CHUNKS;
+#ifndef IMK_FAN_SCATTER_MAX_P
+#define IMK_FAN_SCATTER_MAX_P 6
+#endif
+constexpr int kFanScatterMaxP = IMK_FAN_SCATTER_MAX_P;
+
+__global__ void __launch_bounds__(kFanMaxWaves * 64) k_bp_fan_scatter(BpOwnArgs a, int P)
+{
+    extern __shared__ float cells[];  // owned lines of nl + 2 cells: taps -1 .. nl
+    const int nl = a.n >> a.lvl;
+    const int S = nl + 2;
+    const int rows = kFanRowsPerWave * (int)(blockDim.x >> 6);
+    const int pass = blockIdx.y, g = blockIdx.z;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int q0 = blockIdx.x * rows;  // first owned row (pass 0) or column (pass 1)
+    const int nown = min(rows, nl - q0);
+    for (int c = threadIdx.x; c < rows * S; c += blockDim.x) cells[c] = 0.0f;
+    __syncthreads();
+    const int v0 = (int)((long long)g * a.na / a.G), v1 = (int)((long long)(g + 1) * a.na / a.G);
+    const FanGeo& f = a.fan;
+    const double hl = 2.0 * f.E / nl;
+    auto ctr = [&](int k) { return (float)(-f.E + (k + 0.5) * hl); };  // pixel-centre coordinate
+    const float Df = (float)f.D, mag = (float)(f.D + f.Dd), ids = (float)(1.0 / f.ds);
+    const float bofs = (float)(0.5 * (a.nd - 1) - f.s0 / f.ds), marg = f.bmargin, top = (float)(a.nd - 1);
+    // the block's end-point box: its own lines' centres along the owned
+    // axis, the centres -1 .. nl across it (all within 1.6E of the centre)
+    const float o0 = ctr(q0), o1 = ctr(q0 + nown - 1), x0 = ctr(-1), x1 = ctr(nl);
+    const int want = pass == 0 ? 1 : 0;
+    for (int v = v0; v < v1; ++v) {
+        const FanView fv = f.view[v];
+        if (pass == 0 ? !fv.has_row : !fv.has_col) continue;
+        const float c = (float)fv.c, s = (float)fv.s;
+        auto bin = [&](float x, float y) {
+            return mag * (c * y - s * x) * __builtin_amdgcn_rcpf(Df - (c * x + s * y)) * ids + bofs;
+        };
+        float q[4];
+        if (pass == 0) {
+            q[0] = bin(x0, o0);
+            q[1] = bin(x1, o0);
+            q[2] = bin(x0, o1);
+            q[3] = bin(x1, o1);
+        } else {
+            q[0] = bin(o0, x0);
+            q[1] = bin(o0, x1);
+            q[2] = bin(o1, x0);
+            q[3] = bin(o1, x1);
+        }
+        const float lo = fminf(fminf(q[0], q[1]), fminf(q[2], q[3]));
+        const float hi = fmaxf(fmaxf(q[0], q[1]), fmaxf(q[2], q[3]));
+        const int blo = (int)ceilf(fminf(fmaxf(lo - marg, 0.0f), top + 1.0f));
+        const int bhi = (int)floorf(fmaxf(fminf(hi + marg, top), -1.0f));
+        const FanTab* tv = f.tab + (size_t)v * a.nd;
+        for (int p = 0; p < P; ++p) {
+            for (int b = blo + p + P * lane; b <= bhi; b += kFanChunks * 64 * P) {
+                constexpr int NC = kFanChunks * kFanRowsPerWave;
+                int cl[NC];
+                bool ok[NC];
+                float omw[NC], cw[NC], wy[NC];
+#pragma unroll
+                for (int h = 0; h < kFanChunks; ++h) {
+                    const int bh = b + h * 64 * P;
+                    FanTab t{};
+                    if (bh <= bhi) t = tv[bh];
+                    const bool use = bh <= bhi && t.row == want;
+#pragma unroll
+                    for (int rr = 0; rr < kFanRowsPerWave; ++rr) {
+                        const int c = h * kFanRowsPerWave + rr;
+                        const int own = wave * kFanRowsPerWave + rr;
+                        const long long u = t.cfx + (long long)(q0 + own) * t.afx;
+                        const int j0 = tap_index(u);
+                        ok[c] = use && own < nown && (unsigned)(j0 + 1) <= (unsigned)nl;  // j0 in [-1, nl - 1]
+                        cl[c] = own * S + 1 + (ok[c] ? j0 : 0);
+                        cw[c] = tap_weight(u);
+                        omw[c] = 1.0f - cw[c];
+                        wy[c] = t.wy;
+                    }
+                }
+                float old[NC];
+#pragma unroll
+                for (int c = 0; c < NC; ++c) old[c] = ok[c] ? cells[cl[c]] : 0.0f;
+#pragma unroll
+                for (int c = 0; c < NC; ++c)
+                    if (ok[c]) cells[cl[c]] = fmaf(omw[c], wy[c], old[c]);
+                IMK_LDS_ORDER();
+#pragma unroll
+                for (int c = 0; c < NC; ++c) old[c] = ok[c] ? cells[cl[c] + 1] : 0.0f;
+#pragma unroll
+                for (int c = 0; c < NC; ++c)
+                    if (ok[c]) cells[cl[c] + 1] = fmaf(cw[c], wy[c], old[c]);
+                IMK_LDS_ORDER();
+            }
+        }
+    }
+    __syncthreads();
+    // owned rows into partial image 2g, owned columns into 2g + 1
+    float* out = a.part + (size_t)(2 * g + pass) * nl * nl;
+    if (pass == 0) {
+        for (int e = threadIdx.x; e < nown * nl; e += blockDim.x) {
+            const int r = e / nl, j = e - r * nl;
+            out[(size_t)(q0 + r) * nl + j] = cells[r * S + 1 + j];
+        }
+    } else {
+        for (int e = threadIdx.x; e < nl * nown; e += blockDim.x) {
+            const int i = e / nown, k = e - i * nown;
+            out[(size_t)i * nl + q0 + k] = cells[k * S + 1 + i];
+        }
+    }
 }
 
 // Adds the band partials of every term (in band order), then stores,
@@ -749,9 +904,6 @@ __device__ __forceinline__ void bin_range(const RayConst& kc, int r0, int nrows,
 }
 
 
-// Compiler-only ordering point: LDS operations of one wavefront execute in
-// program order, so this is all that is needed between the two phases.
-#define IMK_LDS_ORDER() asm volatile("" ::: "memory")
 
 // One trip of a wavefront over CH chunks of 64 rays and its R rows (chains
 // chunk-major): both taps of every sample, as two
@@ -1748,12 +1900,38 @@ hipError_t launch_bp_main(const BpArgs& ba, hipStream_t s, BpOwnArgs& a)
     a.prolong = ba.prolong;
     const int nl = ba.n >> ba.lvl;
     if (ba.fan.ray) {
-        // view groups: about IMK_FAN_TARGET_WG workgroups, G N_l^2 <= kPartImages N^2
-        const long long tiles = (long long)((nl + kFanTile - 1) / kFanTile) * ((nl + kFanTile - 1) / kFanTile);
-        const long long want = (IMK_FAN_TARGET_WG + tiles - 1) / tiles;
-        a.G = (int)std::max(1LL, std::min({want, (long long)ba.na, (long long)kPartImages << (2 * ba.lvl), 4096LL}));
-        a.nq = a.G;
-        hipLaunchKernelGGL(k_bp_fan, dim3((unsigned)tiles, a.G), dim3(256), 0, s, a);
+        // phases of the scatter: bins P apart are at least P * min_sep apart,
+        // 1.25 pixels or more; where rays are denser the gather is used
+        const double hl = 2.0 * ba.fan.E / nl;
+        const double Pd = std::ceil(1.25 * hl / ba.fan.min_sep);
+        if (Pd > kFanScatterMaxP) {
+            // view groups: about IMK_FAN_TARGET_WG workgroups, G N_l^2 <= kPartImages N^2
+            const long long tiles = (long long)((nl + kFanTile - 1) / kFanTile) * ((nl + kFanTile - 1) / kFanTile);
+            const long long want = (IMK_FAN_TARGET_WG + tiles - 1) / tiles;
+            a.G = (int)std::max(1LL, std::min({want, (long long)ba.na, (long long)kPartImages << (2 * ba.lvl), 1024LL}));
+            a.nq = a.G;
+            hipLaunchKernelGGL(k_bp_fan_gather, dim3((unsigned)tiles, a.G), dim3(256), 0, s, a);
+            return hipGetLastError();
+        }
+        const int phases = (int)std::max(1.0, Pd);
+        const size_t m = (size_t)ba.na * ba.nd;
+        hipLaunchKernelGGL(k_fan_table, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, a);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        // owned lines per workgroup: two per wavefront, up to 8 wavefronts,
+        // as many as fit in the LDS
+        const size_t line = sizeof(float) * (size_t)(nl + 2);
+        const int waves = (int)std::max<size_t>(1, std::min<size_t>(kFanMaxWaves, kLdsBytes / (kFanRowsPerWave * line)));
+        const int rows = kFanRowsPerWave * waves;
+        const int blocks = (nl + rows - 1) / rows;
+        // view groups: about 1024 workgroups, 2 G N_l^2 <= kPartImages N^2
+        const long long want = (1024 + 2LL * blocks - 1) / (2LL * blocks);
+        a.G = (int)std::max(1LL, std::min({want, (long long)ba.na, (long long)(kPartImages / 2) << (2 * ba.lvl), 1024LL}));
+        a.nq = 2 * a.G;
+        const int lds = (int)(rows * line);
+        e = allow_lds((const void*)k_bp_fan_scatter, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_bp_fan_scatter, dim3(blocks, 2, a.G), dim3(64 * waves), lds, s, a, phases);
         return hipGetLastError();
     }
     // tile shapes measured best on the 512^2 / 720 x 768 workload: two rows

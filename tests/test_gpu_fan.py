@@ -71,13 +71,21 @@ def test_fan_gpu_dot_product(case):
         assert abs(lhs - rhs) <= 2e-6 * np.linalg.norm(ax) * np.linalg.norm(y), (l, lhs, rhs)
 
 
+# (source distance, detector distance, spacing): a wide fan, where rays are
+# dense and the transpose gathers, and a distant source with one-pixel bins,
+# where it scatters on levels 0 and 1 (2 and 4 phases) and gathers on level 2
+TINY = [(2.3, 0.9, 0.0), (6.0, 0.5, 0.25)]
+
+
 @pytest.mark.parametrize("lvl", [0, 1, 2])
-def test_fan_explicit_matrix_tiny(lvl):
-    """A wide fan (D = 2.3 E) on an 8^2 grid: the GPU transpose realises the
-    GPU forward's matrix transposed, bit for bit, and both the oracle's."""
+@pytest.mark.parametrize("tiny", TINY)
+def test_fan_explicit_matrix_tiny(lvl, tiny):
+    """An 8^2 grid: the GPU transpose realises the GPU forward's matrix
+    transposed, bit for bit, and both the oracle's."""
     n, nv, nd = 8, 6, 14
-    g = pk.Geometry(n, nv, nd, det_offset=0.02, src_dist=2.3, det_dist=0.9)
-    og = oracle.Geometry(n, nv, nd, s0=0.02, src_dist=2.3, det_dist=0.9)
+    D, Dd, ds = tiny
+    g = pk.Geometry(n, nv, nd, det_spacing=ds, det_offset=0.02, src_dist=D, det_dist=Dd)
+    og = oracle.Geometry(n, nv, nd, ds=ds, s0=0.02, src_dist=D, det_dist=Dd)
     work = pk.workspace(g)
     A_gpu = np.empty((nv * nd, n * n))
     for q in range(n * n):
@@ -146,11 +154,14 @@ def test_fan_beam_batched_equals_alone_and_repeat_is_bitwise():
         assert np.array_equal(host(a.x_cur), host(c.x_cur)) and np.array_equal(host(a.y_cur), host(c.y_cur))
 
 
+@pytest.mark.parametrize("D", [2.5, 6.0])
 @pytest.mark.parametrize("n,nv,nd", [(4096, 6, 5800), (16384, 2, 8192)])
-def test_fan_very_large_grids(n, nv, nd):
-    """The largest grid and detector the boundary takes, levels 0 and 1."""
-    g = pk.Geometry(n, nv, nd, src_dist=2.5, det_dist=0.5)
-    og = oracle.Geometry(n, nv, nd, src_dist=2.5, det_dist=0.5)
+def test_fan_very_large_grids(n, nv, nd, D):
+    """The largest grid and detector the boundary takes, levels 0 and 1; the
+    transpose gathers at D = 2.5 and scatters at D = 6 (one wavefront of
+    two rows per workgroup at 16384^2)."""
+    g = pk.Geometry(n, nv, nd, src_dist=D, det_dist=0.5)
+    og = oracle.Geometry(n, nv, nd, src_dist=D, det_dist=0.5)
     work = pk.workspace(g)
     x = f32(synth.random_image(n, 23))
     y = f32(synth.random_sinogram(nv, nd, 24))

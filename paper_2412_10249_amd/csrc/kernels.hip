@@ -622,26 +622,20 @@ __global__ void __launch_bounds__(256) k_fan_table(BpOwnArgs a)
 // the block (the projection of the block's end-point box, FP32 with a
 // margin) in P phases: lanes of one instruction hold bins P apart, and P is
 // chosen so that such rays are more than a pixel apart at every owned cell,
-// so no two lanes of an instruction update the same cell.  A lane takes
-// kFanChunks rays per trip, 64 P bins apart (every ray of a trip is at least
-// P bins from every other), and issues all their cells' reads before the
-// writes, so the LDS latencies overlap.  A sample adds (1 - w) of its ray's
+// so no two lanes of an instruction update the same cell.  A lane takes CH
+// rays per trip, 64 P bins apart (every ray of a trip is at least P bins
+// from every other), and issues all their cells' reads before the writes,
+// so the LDS latencies overlap.  A sample adds (1 - w) of its ray's
 // weighted datum to the left tap, then w to the right tap: the forward's
 // weights bit for bit, in a fixed order.  Used where P <= kFanScatterMaxP.
-#ifndef IMK_FAN_SCATTER_WAVES
-#define IMK_FAN_SCATTER_WAVES 8
-#endif
-#ifndef IMK_FAN_CHUNKS
-#define IMK_FAN_CHUNKS 2
-#endif
 constexpr int kFanRowsPerWave = 2;
-constexpr int kFanMaxWaves = IMK_FAN_SCATTER_WAVES;
-constexpr int kFanChunks = IMK_FAN_CHUNKS;
+constexpr int kFanMaxWaves = 8;
 #ifndef IMK_FAN_SCATTER_MAX_P
 #define IMK_FAN_SCATTER_MAX_P 6
 #endif
 constexpr int kFanScatterMaxP = IMK_FAN_SCATTER_MAX_P;
 
+template <int CH>
 __global__ void __launch_bounds__(kFanMaxWaves * 64) k_bp_fan_scatter(BpOwnArgs a, int P)
 {
     extern __shared__ float cells[];  // owned lines of nl + 2 cells: taps -1 .. nl
@@ -689,13 +683,13 @@ __global__ void __launch_bounds__(kFanMaxWaves * 64) k_bp_fan_scatter(BpOwnArgs 
         const int bhi = (int)floorf(fmaxf(fminf(hi + marg, top), -1.0f));
         const FanTab* tv = f.tab + (size_t)v * a.nd;
         for (int p = 0; p < P; ++p) {
-            for (int b = blo + p + P * lane; b <= bhi; b += kFanChunks * 64 * P) {
-                constexpr int NC = kFanChunks * kFanRowsPerWave;
+            for (int b = blo + p + P * lane; b <= bhi; b += CH * 64 * P) {
+                constexpr int NC = CH * kFanRowsPerWave;
                 int cl[NC];
                 bool ok[NC];
                 float omw[NC], cw[NC], wy[NC];
 #pragma unroll
-                for (int h = 0; h < kFanChunks; ++h) {
+                for (int h = 0; h < CH; ++h) {
                     const int bh = b + h * 64 * P;
                     FanTab t{};
                     if (bh <= bhi) t = tv[bh];
@@ -1918,10 +1912,14 @@ hipError_t launch_bp_main(const BpArgs& ba, hipStream_t s, BpOwnArgs& a)
         hipLaunchKernelGGL(k_fan_table, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, a);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        // owned lines per workgroup: two per wavefront, up to 8 wavefronts,
-        // as many as fit in the LDS
+        // shape measured on the 512^2 fan workload: where rays are sparse
+        // (P <= 3) 4 wavefronts of 4 rays per trip (level 0: 424 against
+        // 481 us), else 8 wavefronts of 2 (level 1: 212 against 327 us);
+        // two owned lines per wavefront, as many wavefronts as fit in the LDS
+        const bool sparse = phases <= 3;
         const size_t line = sizeof(float) * (size_t)(nl + 2);
-        const int waves = (int)std::max<size_t>(1, std::min<size_t>(kFanMaxWaves, kLdsBytes / (kFanRowsPerWave * line)));
+        const int waves = (int)std::max<size_t>(
+            1, std::min<size_t>(sparse ? 4 : kFanMaxWaves, kLdsBytes / (kFanRowsPerWave * line)));
         const int rows = kFanRowsPerWave * waves;
         const int blocks = (nl + rows - 1) / rows;
         // view groups: about 1024 workgroups, 2 G N_l^2 <= kPartImages N^2
@@ -1929,9 +1927,15 @@ hipError_t launch_bp_main(const BpArgs& ba, hipStream_t s, BpOwnArgs& a)
         a.G = (int)std::max(1LL, std::min({want, (long long)ba.na, (long long)(kPartImages / 2) << (2 * ba.lvl), 1024LL}));
         a.nq = 2 * a.G;
         const int lds = (int)(rows * line);
-        e = allow_lds((const void*)k_bp_fan_scatter, lds);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_bp_fan_scatter, dim3(blocks, 2, a.G), dim3(64 * waves), lds, s, a, phases);
+        if (sparse) {
+            e = allow_lds((const void*)k_bp_fan_scatter<4>, lds);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(k_bp_fan_scatter<4>, dim3(blocks, 2, a.G), dim3(64 * waves), lds, s, a, phases);
+        } else {
+            e = allow_lds((const void*)k_bp_fan_scatter<2>, lds);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(k_bp_fan_scatter<2>, dim3(blocks, 2, a.G), dim3(64 * waves), lds, s, a, phases);
+        }
         return hipGetLastError();
     }
     // tile shapes measured best on the 512^2 / 720 x 768 workload: two rows

@@ -192,3 +192,25 @@ def test_fan_degenerate_sizes():
         assert prob.epochs == ost.epochs
         assert rel(host(prob.x_cur), ost.x) <= 1e-4
         assert rel(host(prob.y_cur), ost.y) <= 1e-4
+
+
+def test_fan_beam_with_compact_tables_and_independent_draws():
+    g, og = _geoms(FANS[0])
+    n, nv, nd = FANS[0][:3]
+    b = f32(synth.random_sinogram(nv, nd, 41)) * 0.3 + 0.5
+    lv, p = (0, 1, 2), (0.4, 0.3, 0.3)
+    say("fan, compact tables")
+    ost = oracle.imask_compact_run(og, oracle.Levels(list(lv), list(p)), oracle.Reg(lam=0.5), 0.02, 42, 0, b, 30)
+    prob = pk.Problem(g, pk.Levels(lv, p), pk.Regularizer(pk.REG_TIKHONOV, 0.5), pk.Params(0.02, 42, 0), dev(b),
+                      compact_tables=True)
+    prob.step(30)
+    assert rel(host(prob.x_cur), ost.x) <= 1e-4
+    assert rel(host(prob.y_cur), ost.y) <= 1e-4
+    say("fan, independent draws")
+    ost = oracle.imask_indep_run(og, oracle.Levels(list(lv), list(p)), oracle.Reg(lam=0.5), 0.02, 42, 0, 5, b, 30)
+    prob = pk.Problem(g, pk.Levels(lv, p), pk.Regularizer(pk.REG_TIKHONOV, 0.5),
+                      pk.Params(0.02, 42, 0, draw_mode=pk.DRAW_INDEPENDENT, dual_stream_id=5), dev(b))
+    prob.step(30)
+    assert prob.epochs == ost.epochs
+    assert rel(host(prob.x_cur), ost.x) <= 1e-4
+    assert rel(host(prob.y_cur), ost.y) <= 1e-4

@@ -242,7 +242,9 @@ def run(args):
     dom = max(share, key=share.get)
     dom_t = kern[dom]
     if args.fan:
-        name = {"fwd": "k_fwd_fan", "bp": "k_bp_fan"}[dom[0]]
+        # this workload's transpose scatters on levels 0-1 (3 and 5 phases)
+        # and gathers on levels 2-3
+        name = {"fwd": "k_fwd_fan", "bp": "k_bp_fan_scatter" if dom[1] <= 1 else "k_bp_fan_gather"}[dom[0]]
     else:
         name = {"fwd": "k_fwd_band" if (N >> dom[1]) <= 512 else "k_fwd_direct", "bp": "k_bp_own"}[dom[0]]
     key = f"{name}_l{dom[1]}"

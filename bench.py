@@ -10,7 +10,8 @@ equivalent full-resolution operator applications (cost 2^{-l} per step).
 With --fan the same workload runs on a fan beam: 720 source positions over
 [0, 2 pi) at distance 4 (the image is [-1, 1]^2), a flat detector of 768
 bins at distance 2 beyond the centre (bins the magnified pixel size, so the
-fan just covers the image's circumscribed circle).
+fan just covers the image's circumscribed circle), with Poisson data from
+the phantom's exact integrals along the fan's rays.
 
 With --blocks S > 1 the same workload runs with the image sketches combined
 with S measurement blocks (each step projects one of S contiguous angle
@@ -202,7 +203,10 @@ def run(args):
     import synth
 
     torch.cuda.set_device(0)
-    _, b = synth.ct_problem(N, NA, ND, I0, 1000, 2000)
+    if args.fan:  # exact integrals along the fan's rays
+        _, b = synth.fan_ct_problem(N, NA, ND, FAN_D, FAN_DD, I0, 1000, 2000)
+    else:
+        _, b = synth.ct_problem(N, NA, ND, I0, 1000, 2000)
     b32 = torch.from_numpy(b.astype(np.float32)).cuda()
     geom = pk.Geometry(N, NA, ND, src_dist=FAN_D, det_dist=FAN_DD) if args.fan else pk.Geometry(N, NA, ND)
     lv = pk.Levels.uniform(LEVELS, pk.FULL_PAPER, args.blocks)
@@ -261,7 +265,8 @@ def run(args):
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
-        "data": "synthetic: seeded random-ellipse phantom, analytic line integrals, Poisson I0=1e5",
+        "data": "synthetic: seeded random-ellipse phantom, analytic line integrals"
+                + (" along the fan's rays" if args.fan else "") + ", Poisson I0=1e5",
         "config": {"workload": ("2D fan-beam CT 512x512, 720 views over 2pi x 768 flat-detector bins, source "
                                 f"distance {FAN_D}, detector distance {FAN_DD}" if args.fan else
                                 "2D parallel-beam CT 512x512, 720 angles x 768 bins") + ", smoothed TV eps=1e-3 + "

@@ -22,4 +22,7 @@ from .phantom import (  # noqa: F401
     random_image,
     random_sinogram,
     ct_problem,
+    fan_ray_points,
+    ellipse_integrals_through,
+    fan_ct_problem,
 )

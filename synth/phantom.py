@@ -110,6 +110,61 @@ def ellipse_line_integrals(ells: list[Ellipse], n: int, n_angles: int, n_det: in
     return out
 
 
+def fan_ray_points(n: int, n_views: int, n_det: int, src_dist: float, det_dist: float, ds: float = 0.0,
+                   det_offset: float = 0.0, betas=None, extent: float = EXTENT):
+    """Source and detector points of every ray of a flat-detector fan beam,
+    each [view, bin, xy]: view a has its source at D (cos b, sin b),
+    b = 2 pi a / n_views (or the listed angle), and bin k sits at
+    t_k = (k - (n_det-1)/2) ds + det_offset along (-sin b, cos b) on the
+    detector line through -det_dist (cos b, sin b).  ds <= 0 selects the
+    pixel size magnified onto the detector, 2E/n (D + det_dist)/D."""
+    if ds <= 0:
+        ds = 2.0 * extent / n * (src_dist + det_dist) / src_dist
+    beta = 2 * np.pi * np.arange(n_views) / n_views if betas is None else np.asarray(betas, dtype=np.float64)
+    t = (np.arange(n_det) - (n_det - 1) / 2.0) * ds + det_offset
+    ec = np.stack([np.cos(beta), np.sin(beta)], -1)[:, None, :]
+    et = np.stack([-np.sin(beta), np.cos(beta)], -1)[:, None, :]
+    src = np.broadcast_to(src_dist * ec, (n_views, n_det, 2))
+    det = -det_dist * ec + t[None, :, None] * et
+    return src, det
+
+
+def ellipse_integrals_through(ells: list[Ellipse], p: np.ndarray, q: np.ndarray) -> np.ndarray:
+    """Exact integrals of the ellipse phantom along the lines through points
+    p and q ([..., 2] each): on the line X = p + t u (u the unit direction)
+    an ellipse occupies the t between the roots of its quadratic
+    ((X - c) rotated by -phi, scaled by 1/a and 1/b, of unit norm)."""
+    d = q - p
+    u = d / np.linalg.norm(d, axis=-1, keepdims=True)
+    out = np.zeros(p.shape[:-1], dtype=np.float64)
+    for e in ells:
+        cp, sp = np.cos(e.phi), np.sin(e.phi)
+        rx = p[..., 0] - e.cx
+        ry = p[..., 1] - e.cy
+        # coordinates in the ellipse frame, scaled to the unit circle
+        px = (cp * rx + sp * ry) / e.a
+        py = (-sp * rx + cp * ry) / e.b
+        ux = (cp * u[..., 0] + sp * u[..., 1]) / e.a
+        uy = (-sp * u[..., 0] + cp * u[..., 1]) / e.b
+        A = ux * ux + uy * uy
+        B = 2.0 * (px * ux + py * uy)
+        C = px * px + py * py - 1.0
+        disc = B * B - 4.0 * A * C
+        out += e.value * np.where(disc > 0, np.sqrt(np.maximum(disc, 0.0)) / A, 0.0)
+    return out
+
+
+def fan_ct_problem(n: int, n_views: int, n_det: int, src_dist: float, det_dist: float, i0: float,
+                   phantom_seed: int, noise_seed: int, n_ellipses: int = 8):
+    """(x_true, b) on the flat-detector fan beam (default bin spacing):
+    rasterised phantom and noisy post-log data from the exact integrals."""
+    ells = random_ellipses(phantom_seed, n_ellipses)
+    x_true = rasterize_ellipses(ells, n)
+    src, det = fan_ray_points(n, n_views, n_det, src_dist, det_dist)
+    b = poisson_log_data(ellipse_integrals_through(ells, src, det), i0, noise_seed)
+    return x_true, b
+
+
 def poisson_log_data(line_integrals: np.ndarray, i0: float, seed: int) -> np.ndarray:
     """Counts n ~ Poisson(I0 exp(-p)); data b = -ln(max(n, 1)/I0)."""
     rng = np.random.default_rng(seed)

@@ -14,7 +14,10 @@ computed here without the oracle's own line construction:
     beta + pi/2 and the same bins;
   * the dot-product test and explicit matrices: the transpose is the forward
     matrix transposed, bit for bit;
-  * Alg. 1 on a fan geometry converges to the dense Tikhonov minimiser.
+  * Alg. 1 on a fan geometry converges to the dense Tikhonov minimiser;
+  * the fan workload's analytic ellipse data (synth) against the oracle's
+    projection of the rasterised phantom, first order, with synth's
+    two-point chord checked against its parallel closed form first.
 """
 import numpy as np
 import pytest
@@ -144,3 +147,31 @@ def test_fan_alg1_converges_to_dense_minimiser():
         errs.append(np.linalg.norm(st.x - xs) / np.linalg.norm(xs))
     assert errs[-1] < 1e-8, errs
     assert all(e1 < e0 for e0, e1 in zip(errs, errs[1:]))
+
+
+def test_ellipse_integrals_through_points_reproduce_the_parallel_closed_form():
+    """synth's chord through two points equals its parallel-beam chord
+    formula on parallel rays (two independent closed forms)."""
+    ells = synth.random_ellipses(1000, 8)
+    n, na, nd = 64, 30, 96
+    th = synth.angles_uniform(na)[:, None] + 0 * np.zeros(nd)[None, :]
+    s = synth.detector_centres(n, nd)[None, :] + 0 * th
+    p = np.stack([s * np.cos(th), s * np.sin(th)], -1)
+    q = p + np.stack([-np.sin(th), np.cos(th)], -1)
+    got = synth.ellipse_integrals_through(ells, p, q)
+    np.testing.assert_allclose(got, synth.ellipse_line_integrals(ells, n, na, nd), rtol=0, atol=1e-12)
+
+
+def test_fan_ellipse_data_matches_the_oracle_projector():
+    """The fan workload's analytic data against the oracle's Joseph projection
+    of the rasterised phantom: first-order convergence (pins the fan ray
+    construction of synth and of the oracle against each other)."""
+    errs = []
+    for n in (64, 128, 256):
+        ells = synth.random_ellipses(1000, 8)
+        x = synth.rasterize_ellipses(ells, n)
+        src, det = synth.fan_ray_points(n, 24, 3 * n // 2, 4.0, 2.0)
+        exact = synth.ellipse_integrals_through(ells, src, det)
+        g = oracle.Geometry(n, 24, 3 * n // 2, src_dist=4.0, det_dist=2.0)
+        errs.append(np.linalg.norm(oracle.project(g, 0, x) - exact) / np.linalg.norm(exact))
+    assert errs[0] < 0.03 and errs[1] < 0.6 * errs[0] and errs[2] < 0.6 * errs[1], errs

@@ -214,3 +214,35 @@ def test_fan_beam_with_compact_tables_and_independent_draws():
     assert prob.epochs == ost.epochs
     assert rel(host(prob.x_cur), ost.x) <= 1e-4
     assert rel(host(prob.y_cur), ost.y) <= 1e-4
+
+
+def test_fan_bench_workload():
+    """The fan workload bench.py --fan times (512^2, 720 views x 768 bins,
+    source 4, detector 2, data along the fan's rays, smoothed TV, PAPER,
+    four levels): the projector pair within 1e-5 at every level (the
+    transpose scatters on levels 0 and 1, with four and two rays per trip,
+    and gathers on levels 2 and 3), then 21 iterations of Alg. 1 within
+    1e-3, launched as the benchmark launches them."""
+    n, nv, nd = 512, 720, 768
+    g = pk.Geometry(n, nv, nd, src_dist=4.0, det_dist=2.0)
+    og = oracle.Geometry(n, nv, nd, src_dist=4.0, det_dist=2.0)
+    work = pk.workspace(g)
+    x = f32(synth.random_image(n, 31))
+    y = f32(synth.random_sinogram(nv, nd, 32))
+    for l in range(4):
+        say(f"fan bench geometry level {l}")
+        got = host(pk.project(g, l, dev(x), work))
+        assert rel(got, oracle.project(og, l, oracle.restrict(x, l))) <= 1e-5, l
+        got = host(pk.backproject(g, l, dev(y), work))
+        assert rel(got, oracle.prolong(oracle.backproject(og, l, y), l) / 4 ** l) <= 1e-5, l
+    _, b = synth.fan_ct_problem(n, nv, nd, 4.0, 2.0, 1e5, 1000, 2000)
+    b = f32(b)
+    reg_o = oracle.Reg(oracle.REG_SMOOTH_TV, lam=1e-3, tv_weight=2e-4, tv_eps=1e-3, tv_inner=10)
+    reg_g = pk.Regularizer(pk.REG_SMOOTH_TV, 1e-3, 2e-4, 1e-3, 10)
+    say("fan bench workload, 21 iterations")
+    ost = oracle.imask_run(og, oracle.Levels([0, 1, 2, 3], [0.25] * 4), reg_o, 1e-3, 42, 0, b, 21)
+    prob = pk.Problem(g, pk.Levels.uniform((0, 1, 2, 3), pk.FULL_PAPER), reg_g, pk.Params(1e-3, 42, 0), dev(b))
+    prob.step(21)
+    assert prob.epochs == ost.epochs > 10.0
+    assert rel(host(prob.x_cur), ost.x) <= 1e-3
+    assert rel(host(prob.y_cur), ost.y) <= 1e-3

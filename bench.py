@@ -23,6 +23,7 @@ Prints one JSON line.  --gpus above 1 is refused: the path runs on one GPU
 Other workloads, each printing its own JSON line:
   --race                time to relative error 1e-3 against a common limit:
                         ImaSk, SAGA, ImaSk-Seq, PDHG, independent draws
+                        (with --fan on the fan workload)
   --study stepsize|tv|square
                         PSNR against the phantom over a fixed epoch budget
   --batched             64 slices of mixed sizes in flight on several streams
@@ -369,7 +370,8 @@ def race(args):
                           sigma_pd = (L^2)^{-1/2} is the single-level PDHG
                           limit sigma tau |K|^2 < 1 with tau = sigma / mu.
     Each method runs its grid of multiples m; the best time is reported
-    (the paper tunes ImaSk-Seq's step by a grid search too)."""
+    (the paper tunes ImaSk-Seq's step by a grid search too).  With --fan the
+    same race runs on the fan workload."""
     import torch
 
     import paper_2412_10249_amd as pk
@@ -379,9 +381,13 @@ def race(args):
         print(msg, file=sys.stderr, flush=True)
 
     torch.cuda.set_device(0)
-    _, b = synth.ct_problem(N, NA, ND, I0, 1000, 2000)
+    if args.fan:
+        _, b = synth.fan_ct_problem(N, NA, ND, FAN_D, FAN_DD, I0, 1000, 2000)
+        geom = pk.Geometry(N, NA, ND, src_dist=FAN_D, det_dist=FAN_DD)
+    else:
+        _, b = synth.ct_problem(N, NA, ND, I0, 1000, 2000)
+        geom = pk.Geometry(N, NA, ND)
     b32 = torch.from_numpy(b.astype(np.float32)).cuda()
-    geom = pk.Geometry(N, NA, ND)
     work = pk.workspace(geom)
     t0 = time.perf_counter()
     xref, gnorm = reference_solution(geom, work, b32, LAM, TV_W, TV_EPS, args.ref_iters, log)
@@ -442,7 +448,8 @@ def race(args):
             results[name]["runs"].append(run_res)
     best = {k: min([r["time_to_target_s"] for r in v["runs"] if r["time_to_target_s"]] or [None], key=lambda z: z or 1e30)
             for k, v in results.items()}
-    print(json.dumps({"metric": "time to relative error 1e-3 vs the common limit (512x512 smoothed TV)",
+    print(json.dumps({"metric": "time to relative error 1e-3 vs the common limit (512x512 smoothed TV"
+                                + (", fan beam)" if args.fan else ")"),
                       "target": args.target, "reference_relative_gradient": gnorm, "best_time_s": best,
                       "results": results}), flush=True)
 

@@ -91,8 +91,8 @@ enum { IMASK_BUDGET_ITERS = 0, IMASK_BUDGET_EPOCHS = 1 };
  * imask_prepare, which also tabulates every ray's line in the workspace and
  * waits for its stream).  det_spacing <= 0 selects the pixel size magnified
  * onto the detector, 2E/N (D + det_dist)/D.  Every entry point takes a fan
- * geometry; imask_step and imask_solve return IMASK_ENOTSUP for a fan
- * geometry with measurement blocks.
+ * geometry; measurement blocks (imask_levels.n_blocks) are contiguous
+ * ranges of views.
  *
  * Invalid (EINVAL): n outside 4..16384,
  * not a multiple of 4, or above 16 not a multiple of 16; n_angles or n_det
@@ -133,8 +133,8 @@ typedef struct {
  * psi stays r sinograms (block b's rows of table k hold K_kb x), the dual
  * step still updates every row, and a step costs its sketch's cost times
  * its block's share of the angles.  Read by imask_step / imask_solve
- * (parallel schedule, full tables, common draws and the default angles of
- * a parallel beam; IMASK_ENOTSUP otherwise), imask_phi_floats and imask_block_draws; the
+ * (parallel schedule, full tables, common draws and the default angles or
+ * fan-beam views, not listed ones; IMASK_ENOTSUP otherwise), imask_phi_floats and imask_block_draws; the
  * other calls apply the level sketches alone.  0 or 1: no blocks;
  * 2 .. min(n_angles, IMASK_MAX_BLOCKS), else IMASK_EINVAL. */
 typedef struct {

@@ -427,6 +427,8 @@ static int one_step(const imask_geometry& g, const Layout& L, const imask_levels
     if (nblk > 1) {
         for (int t = 0; t < fa.nterms; ++t) fa.term[t].coef *= blk_coef;
         fa.split = blk_split;
+        fa.fan.va = a0;
+        fa.fan.vb = a1;
         fa.e0 = (long long)a0 * g.n_det;
         fa.e1 = (long long)a1 * g.n_det;
     }
@@ -470,7 +472,11 @@ static int one_step(const imask_geometry& g, const Layout& L, const imask_levels
     // epilogue of that backprojection's ordered sum.
     auto raw_bp = [&](int l) {  // R_l^T y (times S on the block's rows only)
         BpArgs ba = bp_args(L, W, l, y_bp, W + L.craw[l], blk_coef, 0, 0);
-        if (nblk > 1) ba.split = blk_split;
+        if (nblk > 1) {
+            ba.split = blk_split;
+            ba.fan.va = a0;
+            ba.fan.vb = a1;
+        }
         return ba;
     };
     if (k > 0 || lv.r == 1) {
@@ -1051,7 +1057,7 @@ static int check_problem(const imask_geometry* g, const imask_levels* lv, const 
     }
     if (lv->n_blocks > g->n_angles) return IMASK_EINVAL;
     if (lv->n_blocks > 1 && (prm->schedule != IMASK_SCHEDULE_PARALLEL || s->ztab ||
-                             prm->draw_mode != IMASK_DRAW_COMMON || g->angles || is_fan(*g)))
+                             prm->draw_mode != IMASK_DRAW_COMMON || g->angles))
         return IMASK_ENOTSUP;
     if (prm->schedule == IMASK_SCHEDULE_SEQUENTIAL) {
         if (!(prm->theta >= 0.0 && prm->theta <= 1.0) || !s->xbar) return IMASK_EINVAL;

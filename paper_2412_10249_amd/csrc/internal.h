@@ -121,6 +121,7 @@ struct FanGeo {
     double E, D, Dd, ds, s0;
     double min_sep;       // lower bound of adjacent rays' separation (domain units)
     float bmargin;        // bins added to each side of an FP32 bin estimate
+    int va, vb;           // the views a launch covers (a measurement block), else all
 };
 
 // Workspace layout for one geometry (offsets in floats from the start).
@@ -175,6 +176,8 @@ inline FanGeo fan_at(const Layout& L, const float* W)
     f.s0 = L.s0;
     f.bmargin = (float)L.bmargin;
     f.min_sep = L.min_sep;
+    f.va = 0;
+    f.vb = L.na;
     return f;
 }
 inline int side(int n, int l) { return n >> l; }

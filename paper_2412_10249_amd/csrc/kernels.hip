@@ -401,8 +401,8 @@ __device__ __forceinline__ void fan_coords(const FanRay& r, double E, int nl, lo
 // read the zero padding, and steps whose taps both lie outside are skipped.
 __global__ void __launch_bounds__(256) k_fwd_fan(FwdBandArgs a)
 {
-    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (size_t)a.na * a.nd) return;
+    const size_t e = (size_t)a.fan.va * a.nd + (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (size_t)a.fan.vb * a.nd) return;
     const int nl = a.n >> a.lvl;
     const int P = nl + kPad;
     const FanRay r = a.fan.ray[e];
@@ -462,8 +462,9 @@ __global__ void __launch_bounds__(256) k_bp_fan_gather(BpOwnArgs a)
     const int i = ty * kFanTile + (threadIdx.x >> 4), j = tx * kFanTile + (threadIdx.x & 15);
     const bool inside = i < nl && j < nl;
     const int g = blockIdx.y;
-    const int v0 = (int)((long long)g * a.na / a.G), v1 = (int)((long long)(g + 1) * a.na / a.G);
     const FanGeo& f = a.fan;
+    const int v0 = f.va + (int)((long long)g * (f.vb - f.va) / a.G);
+    const int v1 = f.va + (int)((long long)(g + 1) * (f.vb - f.va) / a.G);
     const double hl = 2.0 * f.E / nl;
     auto ctr = [&](int k) { return (float)(-f.E + (k + 0.5) * hl); };  // pixel-centre coordinate
     const float xj = ctr(j), yi = ctr(i), hf = (float)hl;
@@ -602,8 +603,8 @@ __global__ void __launch_bounds__(256) k_bp_fan_gather(BpOwnArgs a)
 // weighted datum w_ray * y.
 __global__ void __launch_bounds__(256) k_fan_table(BpOwnArgs a)
 {
-    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (size_t)a.na * a.nd) return;
+    const size_t e = (size_t)a.fan.va * a.nd + (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (size_t)a.fan.vb * a.nd) return;
     const int nl = a.n >> a.lvl;
     const FanRay r = a.fan.ray[e];
     FanTab t;
@@ -648,8 +649,9 @@ __global__ void __launch_bounds__(kFanMaxWaves * 64) k_bp_fan_scatter(BpOwnArgs 
     const int nown = min(rows, nl - q0);
     for (int c = threadIdx.x; c < rows * S; c += blockDim.x) cells[c] = 0.0f;
     __syncthreads();
-    const int v0 = (int)((long long)g * a.na / a.G), v1 = (int)((long long)(g + 1) * a.na / a.G);
     const FanGeo& f = a.fan;
+    const int v0 = f.va + (int)((long long)g * (f.vb - f.va) / a.G);
+    const int v1 = f.va + (int)((long long)(g + 1) * (f.vb - f.va) / a.G);
     const double hl = 2.0 * f.E / nl;
     auto ctr = [&](int k) { return (float)(-f.E + (k + 0.5) * hl); };  // pixel-centre coordinate
     const float Df = (float)f.D, mag = (float)(f.D + f.Dd), ids = (float)(1.0 / f.ds);
@@ -1814,7 +1816,7 @@ hipError_t launch_fwd_terms(const FwdArgs& a, hipStream_t s)
             if (e != hipSuccess) return e;
             hipLaunchKernelGGL(k_fwd_band, dim3(tm.bands, fb.groups_row + fb.groups_col), dim3(1024), lds, s, fb);
         } else if (a.fan.ray) {
-            const size_t m = (size_t)a.na * a.nd;
+            const size_t m = (size_t)(a.fan.vb - a.fan.va) * a.nd;
             hipLaunchKernelGGL(k_fwd_fan, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, fb);
         } else {
             const int wpa = (a.nd + 63) / 64;
@@ -1902,13 +1904,14 @@ hipError_t launch_bp_main(const BpArgs& ba, hipStream_t s, BpOwnArgs& a)
             // view groups: about IMK_FAN_TARGET_WG workgroups, G N_l^2 <= kPartImages N^2
             const long long tiles = (long long)((nl + kFanTile - 1) / kFanTile) * ((nl + kFanTile - 1) / kFanTile);
             const long long want = (IMK_FAN_TARGET_WG + tiles - 1) / tiles;
-            a.G = (int)std::max(1LL, std::min({want, (long long)ba.na, (long long)kPartImages << (2 * ba.lvl), 1024LL}));
+            const long long nv = ba.fan.vb - ba.fan.va;
+            a.G = (int)std::max(1LL, std::min({want, nv, (long long)kPartImages << (2 * ba.lvl), 1024LL}));
             a.nq = a.G;
             hipLaunchKernelGGL(k_bp_fan_gather, dim3((unsigned)tiles, a.G), dim3(256), 0, s, a);
             return hipGetLastError();
         }
         const int phases = (int)std::max(1.0, Pd);
-        const size_t m = (size_t)ba.na * ba.nd;
+        const size_t m = (size_t)(ba.fan.vb - ba.fan.va) * ba.nd;
         hipLaunchKernelGGL(k_fan_table, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, a);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -1924,7 +1927,8 @@ hipError_t launch_bp_main(const BpArgs& ba, hipStream_t s, BpOwnArgs& a)
         const int blocks = (nl + rows - 1) / rows;
         // view groups: about 1024 workgroups, 2 G N_l^2 <= kPartImages N^2
         const long long want = (1024 + 2LL * blocks - 1) / (2LL * blocks);
-        a.G = (int)std::max(1LL, std::min({want, (long long)ba.na, (long long)(kPartImages / 2) << (2 * ba.lvl), 1024LL}));
+        const long long nv = ba.fan.vb - ba.fan.va;
+        a.G = (int)std::max(1LL, std::min({want, nv, (long long)(kPartImages / 2) << (2 * ba.lvl), 1024LL}));
         a.nq = 2 * a.G;
         const int lds = (int)(rows * line);
         if (sparse) {

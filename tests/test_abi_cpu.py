@@ -272,7 +272,7 @@ def test_measurement_blocks_validated():
 def test_fan_geometry_validated():
     """Fan beam: source distance in (2E, 1e4 E], detector distance in
     [0, 1e4 E], spacing and offset bounds taken in magnified pixels, and no
-    measurement blocks."""
+    measurement blocks over listed views."""
     L = _abi.lib()
     E = 1.5
 
@@ -292,7 +292,7 @@ def test_fan_geometry_validated():
     for sp, off, good in [(mag_pix / 64, 0.0, True), (mag_pix / 65, 0.0, False), (64 * mag_pix, 0.0, True),
                           (65 * mag_pix, 0.0, False), (0.0, 4 * E * 1.5, True), (0.0, -4 * E * 1.5 * 1.001, False)]:
         assert ok(src_dist=4.0, det_dist=2.0, det_spacing=sp, det_offset=off) == good, (sp, off)
-    g = im.Geometry(64, 10, 12, src_dist=3.0, det_dist=1.0).c()
+    g = im.Geometry(64, 10, 12, src_dist=3.0, det_dist=1.0, angles=tuple(0.3 * a for a in range(10))).c()
     lv = im.Levels((0, 1), (0.5, 0.5), 0, 3).c()
     reg = _abi.Reg(_abi.REG_TIKHONOV, 0.01, 0.0, 1e-3, 10)
     s = _abi.State()

@@ -246,3 +246,26 @@ def test_fan_bench_workload():
     assert prob.epochs == ost.epochs > 10.0
     assert rel(host(prob.x_cur), ost.x) <= 1e-3
     assert rel(host(prob.y_cur), ost.y) <= 1e-3
+
+
+@pytest.mark.parametrize("case,S,iters", [(0, 4, 40), (2, 3, 16)])
+def test_fan_beam_with_measurement_blocks(case, S, iters):
+    """Image sketches with S blocks of contiguous views (reading 24 on a fan
+    beam) against the oracle, both modes: the 64^2 geometry (scatter with
+    two rays per trip at level 0, gather above) and the 256^2 one (four rays
+    per trip at level 0)."""
+    g, og = _geoms(FANS[case])
+    n, nv, nd = FANS[case][:3]
+    b = f32(synth.random_sinogram(nv, nd, 70 + case)) * 0.5 + 1.0
+    log2f, p = (0, 1, 2), (0.4, 0.3, 0.3)
+    for mode in (pk.FULL_PAPER, pk.FULL_UNBIASED):
+        say(f"fan blocks case {case} S={S} mode {mode}")
+        ost = oracle.imask_blocks_run(og, oracle.Levels(list(log2f), list(p), mode), oracle.Reg(lam=0.5), 0.02, 42,
+                                      0, S, b, iters)
+        prob = pk.Problem(g, pk.Levels(log2f, p, mode, S), pk.Regularizer(pk.REG_TIKHONOV, 0.5),
+                          pk.Params(0.02, 42, 0), dev(b))
+        prob.step(iters)
+        assert prob.epochs == pytest.approx(ost.epochs, rel=1e-12)
+        assert rel(host(prob.x_cur), ost.x) <= 1e-4
+        assert rel(host(prob.y_cur), ost.y) <= 1e-4
+        assert rel(host(prob.psi), ost.psi) <= 1e-4

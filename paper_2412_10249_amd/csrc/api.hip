@@ -86,7 +86,10 @@ Layout make_layout(const imask_geometry& g)
     L.vbuf = off;
     off = align64(off + (size_t)g.n * g.n);
     L.part = off;
-    off = align64(off + (size_t)kPartImages * g.n * g.n);
+    const size_t d = (size_t)g.n * g.n;
+    L.part_floats = kPartImages * d;
+    if (is_fan(g)) L.part_floats = std::max(L.part_floats, std::min(kFanPartImages * d, kFanPartFloats));
+    off = align64(off + L.part_floats);
     L.ptmp = off;
     off = align64(off + (size_t)g.n * g.n);
     const size_t m = (size_t)g.n_angles * g.n_det;

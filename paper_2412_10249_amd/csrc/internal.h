@@ -32,6 +32,11 @@ constexpr int kConstStride = 16;  // floats per RayConst
 #endif
 // Full-resolution partial images the transpose may write (2 G N_l^2 <= this * N^2).
 constexpr int kPartImages = IMK_PART_IMAGES;
+// Partial images of the fan transposes: up to kFanPartImages N^2 floats
+// while that stays within kFanPartFloats (more view groups where rays are
+// few per workgroup), never fewer than kPartImages N^2.
+constexpr int kFanPartImages = 64;
+constexpr size_t kFanPartFloats = (size_t)64 << 20;  // 256 MiB
 constexpr int kPadL = 4;
 constexpr int kPad = 2 * kPadL;
 
@@ -122,6 +127,7 @@ struct FanGeo {
     double min_sep;       // lower bound of adjacent rays' separation (domain units)
     float bmargin;        // bins added to each side of an FP32 bin estimate
     int va, vb;           // the views a launch covers (a measurement block), else all
+    long long part_floats;  // size of the partial-image buffer (floats)
 };
 
 // Workspace layout for one geometry (offsets in floats from the start).
@@ -145,6 +151,7 @@ struct Layout {
     // fan beam: ray table (m FanRay) and view table (na FanView)
     int fan = 0;
     size_t fray = 0, fview = 0, ftab = 0;
+    size_t part_floats = 0;  // size of the partial-image buffer
     double E = 1.0, D = 0.0, Dd = 0.0, ds = 0.0, s0 = 0.0, bmargin = 0.0, min_sep = 0.0;
     size_t total = 0;
 };
@@ -178,6 +185,7 @@ inline FanGeo fan_at(const Layout& L, const float* W)
     f.min_sep = L.min_sep;
     f.va = 0;
     f.vb = L.na;
+    f.part_floats = (long long)L.part_floats;
     return f;
 }
 inline int side(int n, int l) { return n >> l; }

@@ -635,6 +635,9 @@ constexpr int kFanMaxWaves = 8;
 #define IMK_FAN_SCATTER_MAX_P 6
 #endif
 constexpr int kFanScatterMaxP = IMK_FAN_SCATTER_MAX_P;
+#ifndef IMK_FAN_SCATTER_WG
+#define IMK_FAN_SCATTER_WG 4096
+#endif
 
 template <int CH>
 __global__ void __launch_bounds__(kFanMaxWaves * 64) k_bp_fan_scatter(BpOwnArgs a, int P)
@@ -1901,11 +1904,13 @@ hipError_t launch_bp_main(const BpArgs& ba, hipStream_t s, BpOwnArgs& a)
         const double hl = 2.0 * ba.fan.E / nl;
         const double Pd = std::ceil(1.25 * hl / ba.fan.min_sep);
         if (Pd > kFanScatterMaxP) {
-            // view groups: about IMK_FAN_TARGET_WG workgroups, G N_l^2 <= kPartImages N^2
+            // view groups: about IMK_FAN_TARGET_WG workgroups, G N_l^2 within
+            // the partial-image buffer
             const long long tiles = (long long)((nl + kFanTile - 1) / kFanTile) * ((nl + kFanTile - 1) / kFanTile);
             const long long want = (IMK_FAN_TARGET_WG + tiles - 1) / tiles;
             const long long nv = ba.fan.vb - ba.fan.va;
-            a.G = (int)std::max(1LL, std::min({want, nv, (long long)kPartImages << (2 * ba.lvl), 1024LL}));
+            const long long room = ba.fan.part_floats / ((long long)nl * nl);
+            a.G = (int)std::max(1LL, std::min({want, nv, room, 1024LL}));
             a.nq = a.G;
             hipLaunchKernelGGL(k_bp_fan_gather, dim3((unsigned)tiles, a.G), dim3(256), 0, s, a);
             return hipGetLastError();
@@ -1925,10 +1930,13 @@ hipError_t launch_bp_main(const BpArgs& ba, hipStream_t s, BpOwnArgs& a)
             1, std::min<size_t>(sparse ? 4 : kFanMaxWaves, kLdsBytes / (kFanRowsPerWave * line)));
         const int rows = kFanRowsPerWave * waves;
         const int blocks = (nl + rows - 1) / rows;
-        // view groups: about 1024 workgroups, 2 G N_l^2 <= kPartImages N^2
-        const long long want = (1024 + 2LL * blocks - 1) / (2LL * blocks);
+        // view groups: about IMK_FAN_SCATTER_WG workgroups (more view groups,
+        // shorter workgroups: level 0 of the 512^2 fan workload 424 -> 318 us
+        // from 1024 to 4096), 2 G N_l^2 within the partial-image buffer
+        const long long want = (IMK_FAN_SCATTER_WG + 2LL * blocks - 1) / (2LL * blocks);
         const long long nv = ba.fan.vb - ba.fan.va;
-        a.G = (int)std::max(1LL, std::min({want, nv, (long long)(kPartImages / 2) << (2 * ba.lvl), 1024LL}));
+        const long long room = ba.fan.part_floats / (2LL * nl * nl);
+        a.G = (int)std::max(1LL, std::min({want, nv, room, 1024LL}));
         a.nq = 2 * a.G;
         const int lds = (int)(rows * line);
         if (sparse) {

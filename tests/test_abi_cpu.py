@@ -302,3 +302,20 @@ def test_fan_geometry_validated():
     prm = _abi.Params(0.01, 1, 0)
     assert L.imask_step(1, ctypes.byref(g), ctypes.byref(lv), ctypes.byref(reg), ctypes.byref(prm), b,
                         ctypes.byref(s), 1, None) == _abi.ENOTSUP
+
+
+def test_fan_partial_image_buffer_sizing():
+    """The fan transposes' partial-image buffer holds up to 64 N^2 floats
+    while that stays within 256 MiB, never fewer than the 16 N^2 of the
+    parallel beam: the fan workspace exceeds the parallel one by the extra
+    images, give or take the small ray, view and table entries, the band
+    partial sinograms and the alignment (under 64 KiB here)."""
+    L = _abi.lib()
+
+    def ws(n, fan):
+        g = im.Geometry(n, 8, 16, src_dist=4.0 if fan else 0.0, det_dist=2.0).c()
+        return L.imask_workspace_bytes(ctypes.byref(g))
+
+    for n, extra_images in ((64, 48), (512, 48), (1024, 48), (2048, 0), (4096, 0)):
+        diff = ws(n, True) - ws(n, False)
+        assert abs(diff - extra_images * n * n * 4) <= 65536, (n, diff)

@@ -71,8 +71,8 @@ def test_fgp_constants_and_nonnegativity():
     assert u.min() >= 0.0
 
 
-def _rof_chambolle_pock(b, gamma, iters):
-    """min_u 1/2|u - b|^2 + gamma |grad u|_{1,2} + chi_{>=0}(u)."""
+def _rof_chambolle_pock(b, gamma, iters, quad=0.0):
+    """min_u 1/2|u - b|^2 + gamma |grad u|_{1,2} + chi_{>=0}(u) + quad/2 |u|^2."""
     u = np.zeros_like(b)
     ub = u.copy()
     y1 = np.zeros_like(b)
@@ -84,7 +84,7 @@ def _rof_chambolle_pock(b, gamma, iters):
         y1, y2 = y1 + s * g1, y2 + s * g2
         nrm = np.maximum(1.0, np.sqrt(y1 ** 2 + y2 ** 2) / gamma)
         y1, y2 = y1 / nrm, y2 / nrm
-        un = np.maximum(0.0, (u - t * _grad_t(y1, y2) + t * b) / (1.0 + t))
+        un = np.maximum(0.0, (u - t * _grad_t(y1, y2) + t * b) / (1.0 + t * (1.0 + quad)))
         ub = 2 * un - u
         u = un
     return u
@@ -97,6 +97,29 @@ def test_fgp_matches_chambolle_pock():
     u, _ = oracle.tv_fgp(b, gamma, 8000)
     ref = _rof_chambolle_pock(b, gamma, 40000)
     np.testing.assert_allclose(u, ref, rtol=0, atol=1e-5)
+
+
+@pytest.mark.parametrize("lam", [0.5, 1e-8])
+def test_tv_prior_prox_with_lambda(lam):
+    """The prior with strong convexity lam (R = w TV + chi_{>=0} + lam/2 |x|^2,
+    mu = lam) inside Alg. 1: one step of one level from x^0 = v, y^0 = 0 and
+    zero tables has xi = 0, so x^1 = prox_{tau R}(v) with tau = sigma / lam.
+    Against Chambolle-Pock on that prox problem written out (no folding of
+    the quadratic into the data term); at lam = 1e-8 the quadratic is
+    negligible and x^1 is the prox of the paper's prior alone."""
+    n = 10
+    g = oracle.Geometry(n, 8, 14)
+    lv = oracle.Levels([0], [1.0])
+    tau, w = 0.2, 0.5
+    v = synth.random_image(n, 6) * 0.5 + 0.2
+    st = oracle.State.zeros(g, lv)
+    st.x = v.copy()
+    reg = oracle.Reg(oracle.REG_TV, lam=lam, tv_weight=w, tv_inner=8000)
+    out = oracle.imask_run(g, lv, reg, tau * lam, 42, 0, np.zeros((8, 14)), 1, st)
+    ref = _rof_chambolle_pock(v, tau * w, 40000, quad=tau * lam)
+    np.testing.assert_allclose(out.x, ref, rtol=0, atol=1e-5)
+    if lam < 1e-6:
+        np.testing.assert_allclose(out.x, _rof_chambolle_pock(v, tau * w, 40000), rtol=0, atol=1e-5)
 
 
 def _tv_minimiser(Kb, b, w, lam, n, iters):

@@ -9,9 +9,10 @@
  * SAGA-type primal-dual iteration that applies one K_i and one K_i^T per step.
  *
  * Conventions (all functions):
- *   - The image domain is [-1,1]^2.  A full-resolution image is N x N,
- *     row-major, float32; pixel (i,j) is row i (y), column j (x), centre
- *     (-1 + (j+1/2)h, -1 + (i+1/2)h), h = 2/N.
+ *   - The image domain is [-E,E]^2, E = imask_geometry.extent (1 by
+ *     default).  A full-resolution image is N x N, row-major, float32; pixel
+ *     (i,j) is row i (y), column j (x), centre (-E + (j+1/2)h, -E + (i+1/2)h),
+ *     h = 2E/N.
  *   - Level l (l = log2 of the downsampling factor) has N_l = N >> l pixels
  *     per side; N must be divisible by 2^l.
  *   - Angle a of n_angles is a*pi/n_angles or the a-th listed angle; bin b
@@ -263,13 +264,16 @@ int imask_block_draws(const imask_params* prm, const imask_levels* lv, uint64_t 
 int imask_prepare(const imask_geometry* g, void* work, size_t work_bytes, void* stream);
 
 /* sino = R_l T_l x_full  (x_full N*N; T_0 = I).  R_l is the ray-driven
- * Joseph projector on the level-l grid: the forward model "on the l-th low
- * resolution grid" of Sec. 4.1 (eq. (CT_sketches), K_i = R_i T_i). */
+ * Joseph projector on the level-l grid, i.e. the CT model discretised on the
+ * coarse grid of Sec. 4.1 (eq. (CT_sketches), K_i = R_i T_i), with the same
+ * detector at every level. */
 int imask_project(const imask_geometry* g, int32_t log2f, const void* work,
                   const float* x_full, float* sino, void* stream);
 
 /* x_full = T_l^T R_l^T sino = 4^{-l} T_l^* R_l^T sino, the exact transpose
- * of imask_project (ray-driven: the weights come from the forward's own
+ * of imask_project: the operator K_i^T of the primal step of Alg. 1 for a
+ * coarse sketch (Sec. 4.1, eq. (CT_sketches); the true adjoint of T_l carries
+ * the factor 4^{-l}).  Ray-driven: the weights come from the forward's own
  * fixed-point coordinate; each image row is accumulated by one wavefront, so
  * there are no atomics and the result is deterministic). */
 int imask_backproject(const imask_geometry* g, int32_t log2f, const void* work,
@@ -312,15 +316,17 @@ size_t imask_constants_scratch_bytes(const imask_geometry* g);
 int imask_step_constants(const imask_geometry* g, const imask_levels* lv, double mu, int32_t iters, uint64_t seed,
                          const void* work, void* scratch, double* out_host, void* stream);
 
-/* Host: the step size of Thm. 3 (eq. (opt:cond) and eq. (eta_opt)),
- * minimising the rate theta over c = cbar*i/(grid+1), rho = j/(grid+1),
- * i, j = 1..grid, cbar = 1/(1 + L^2 + Lbar_p^2); sigma = eta_opt/(1 - eta_opt).
- * theta_out (may be NULL) receives the rate. */
 /* Host: the comparison step size of Sec. 3.6 taken from Balamurugan & Bach,
  * sigma_B = 1 / (L^2 + 3 Lbar^2), from the constants of imask_step_constants.
  * Returns IMASK_EINVAL for non-positive constants or a NULL output. */
 int imask_sigma_balamurugan(double L2, double Lbar2, double* sigma_out);
 
+/* Host: the step size of Thm. 3 (eq. (opt:cond) and eq. (eta_opt)),
+ * minimising the rate theta over c = cbar*i/(grid+1), rho = j/(grid+1),
+ * i, j = 1..grid, cbar = 1/(1 + L^2 + Lbar_p^2); sigma = eta_opt/(1 - eta_opt).
+ * pmin is the smallest sampling probability; theta_out (may be NULL)
+ * receives the rate.  Returns IMASK_EINVAL for non-positive constants, pmin
+ * outside (0, 1], grid < 2 or a NULL sigma_out. */
 int imask_sigma_thm3(double L2, double Lbar2, double Lbarp2, double pmin, int32_t grid, double* sigma_out,
                      double* theta_out);
 
@@ -339,10 +345,12 @@ int imask_step(int32_t n_problems, const imask_geometry* g, const imask_levels* 
                const imask_reg* reg, const imask_params* prm, const float* const* b,
                imask_state* s, int32_t n_steps, void* stream);
 
-/* Runs imask_step until every problem has done `budget` more iterations
- * (IMASK_BUDGET_ITERS) or accumulated `budget` more epochs
- * (IMASK_BUDGET_EPOCHS).  Returns after enqueueing; the epoch budget is
- * evaluated on the host from the draws, without synchronising. */
+/* Runs Alg. 1 (the loop of imask_step) until every problem has done
+ * `budget` more iterations (IMASK_BUDGET_ITERS) or accumulated `budget` more
+ * epochs (IMASK_BUDGET_EPOCHS), the budget unit of the experiments of
+ * Sec. 4.3 (one epoch = the cost of one full-resolution operator pair).
+ * Returns after enqueueing; the epoch budget is evaluated on the host from
+ * the draws, without synchronising.  Errors as for imask_step. */
 int imask_solve(int32_t n_problems, const imask_geometry* g, const imask_levels* lv,
                 const imask_reg* reg, const imask_params* prm, const float* const* b,
                 imask_state* s, double budget, int32_t budget_kind, void* stream);

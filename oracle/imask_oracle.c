@@ -8,8 +8,8 @@
  *
  * Everything is double precision, written straight from the definitions:
  *   - ray-driven Joseph projector R_l on the level-l grid and its literal
- *     scatter transpose (the paper's "forward model on the i-th low resolution
- *     grid", Sec. 4.1, eq. (CT_sketches));
+ *     scatter transpose (R_l is the CT model discretised on the coarse grid
+ *     of level l, Sec. 4.1, eq. (CT_sketches));
  *   - block-average decimation T_l and replication T_l^* (Sec. 4.1), the
  *     projection P_l = T_l^* T_l and the full-resolution compensation
  *     S_r = p_r^{-1}(I - sum_l p_l P_l) (Sec. 4.1);

@@ -80,3 +80,26 @@ def test_tv_prior_batched_equals_alone_and_resume():
     for a, c in zip(probs, alone):
         assert torch.equal(a.x_cur, c.x_cur) and torch.equal(a.y_cur, c.y_cur)
         assert torch.equal(a.tvd[a.cur], c.tvd[c.cur])
+
+
+@pytest.mark.parametrize("n", [16, 64])
+def test_tv_prior_prox_at_tiny_lambda_is_the_pure_prior(n):
+    """With lam -> 0 the library's prox is that of the paper's prior alone
+    (w TV + chi_{>=0}, Sec. 4.5): one step of one level from x^0 = v,
+    y^0 = 0, zero tables and zero data has xi = 0, so x^1 is the prox at v
+    with weight tau w / (1 + tau lam), tau = sigma / lam.  Against the
+    oracle's dual FGP of gamma TV + chi alone (no quadratic), same J."""
+    na, nd, lam, tau, w, J = 8, 14, 1e-8, 0.2, 0.5, 12
+    v = synth.random_image(n, 6) * 0.5 + 0.2
+    v = f32(v)
+    prob = pk.Problem(pk.Geometry(n, na, nd), pk.Levels((0,), (1.0,)),
+                      pk.Regularizer(pk.REG_TV, lam, w, 0.0, J), pk.Params(tau * lam, 42, 0),
+                      torch.zeros((na, nd), device="cuda"))
+    prob.x[0].copy_(dev(v))
+    say(f"tv prior prox at lam 1e-8, n {n}")
+    prob.step(1)
+    u, _ = oracle.tv_fgp(v, tau * w, J)
+    x = host(prob.x_cur)
+    assert x.min() >= 0.0
+    assert rel(x, u) <= 1e-6, rel(x, u)
+    assert np.max(np.abs(x - u)) <= 1e-6 * np.max(np.abs(u)) * 4

@@ -279,6 +279,29 @@ int imask_project(const imask_geometry* g, int32_t log2f, const void* work,
 int imask_backproject(const imask_geometry* g, int32_t log2f, const void* work,
                       const float* sino, float* x_full, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * transpose of imask_backproject without a workspace argument.  x_full
+ * receives what imask_backproject writes for the same arguments, bit for
+ * bit (same kernels, same partial-image order).  Instead of a workspace the
+ * call uses a static device array of IMASK_NOALLOC_SCRATCH_BYTES per GPU,
+ * held until the process ends, for the projector constants (recomputed on
+ * every call: 64 B per level and angle), the partial images (16 N^2 floats)
+ * and the coarse result (N^2 floats); the first call on a device looks up
+ * the array's address there.  Every call on one GPU shares that array, so
+ * calls that overlap on one GPU (several streams or host threads) race and
+ * must be ordered by the caller; each call writes every byte it reads
+ * before reading it, so the previous call's contents do not matter.
+ * Allocates nothing (no hipMalloc, hipFree or allocating library call) and
+ * does not synchronise.  Parallel beam with the default angles only
+ * (IMASK_ENOTSUP for listed angles or a fan beam); IMASK_ESIZE when the
+ * geometry needs more than the array: 4 (17 N^2 + 16 (lmax+1) n_angles)
+ * bytes, so N <= 512 with up to 16384 angles; IMASK_EINVAL as for
+ * imask_backproject. */
+#define IMASK_NOALLOC_SCRATCH_BYTES (24u << 20)
+int imask_backproject_noalloc(const imask_geometry* g, int32_t log2f, const float* sino, float* x_full,
+                              void* stream);
+
 /* Resampling operators of Sec. 4.1 on an N x N grid (see IMASK_RESTRICT ...).
  * lv is read only for IMASK_COMPENSATE (may be NULL otherwise). */
 int imask_resample(int32_t n, int32_t log2f, int32_t mode, const imask_levels* lv,

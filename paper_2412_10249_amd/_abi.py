@@ -26,7 +26,9 @@ DRAW_COMMON, DRAW_INDEPENDENT = 0, 1
 EXPORTS = ["imask_workspace_bytes", "imask_phi_floats", "imask_prepare", "imask_project",
            "imask_backproject", "imask_resample", "imask_sketch_apply", "imask_draws",
            "imask_step", "imask_solve", "imask_time_kernel", "imask_constants_scratch_bytes",
-           "imask_step_constants", "imask_sigma_thm3", "imask_sigma_balamurugan", "imask_block_draws"]
+           "imask_step_constants", "imask_sigma_thm3", "imask_sigma_balamurugan", "imask_block_draws",
+           "imask_backproject_noalloc"]
+NOALLOC_SCRATCH_BYTES = 24 << 20
 KERNEL_FORWARD, KERNEL_TRANSPOSE = 0, 1
 
 
@@ -82,6 +84,7 @@ def lib():
         L.imask_prepare.argtypes = [P(Geometry), vp, sz, vp]
         L.imask_project.argtypes = [P(Geometry), i32, vp, vp, vp, vp]
         L.imask_backproject.argtypes = [P(Geometry), i32, vp, vp, vp, vp]
+        L.imask_backproject_noalloc.argtypes = [P(Geometry), i32, vp, vp, vp]
         L.imask_resample.argtypes = [i32, i32, i32, P(Levels), vp, vp, vp]
         L.imask_sketch_apply.argtypes = [P(Geometry), P(Levels), i32, i32, vp, vp, vp, vp]
         L.imask_draws.argtypes = [P(Params), P(Levels), ctypes.c_uint64, i32, P(i32)]

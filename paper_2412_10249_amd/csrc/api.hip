@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "imask.h"
@@ -538,6 +539,51 @@ static int one_step(const imask_geometry& g, const Layout& L, const imask_levels
     return IMASK_OK;
 }
 
+// ---- the workspace-free transpose (imask_backproject_noalloc) ----
+
+// Device memory of imask_backproject_noalloc: one copy per GPU, held until
+// the process ends.  Host code never passes this name to a kernel (on the
+// host it is a stand-in, not a device address); it uses the address that
+// hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[IMASK_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices];
+
+// The array's address on the current device, looked up once per device.
+static int scratch_of_current_device(void** out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return IMASK_EHIP;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return IMASK_EHIP;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return IMASK_OK;
+}
+
+// The part of a workspace the transpose reads and writes, packed from offset
+// 0: projector constants of every level, the partial images, the coarse
+// result before prolongation.
+static Layout transpose_layout(const imask_geometry& g)
+{
+    Layout L = make_layout(g);
+    size_t off = 0;
+    L.consts = off;
+    off = align64(off + (size_t)(L.lmax + 1) * g.n_angles * kConstStride);
+    L.part = off;
+    L.part_floats = kPartImages * (size_t)g.n * g.n;
+    off = align64(off + L.part_floats);
+    L.ptmp = off;
+    off = align64(off + (size_t)g.n * g.n);
+    L.total = off;
+    return L;
+}
+
 }  // namespace imk
 
 using namespace imk;
@@ -683,6 +729,25 @@ int imask_backproject(const imask_geometry* g, int32_t log2f, const void* work, 
     if (log2f < 0 || log2f > L.lmax) return IMASK_EINVAL;
     return backproject_raw(L, (const float*)work, log2f, sino, x_full, 1.0f / (float)(1 << (2 * log2f)), 0, 1,
                            (hipStream_t)stream);
+}
+
+int imask_backproject_noalloc(const imask_geometry* g, int32_t log2f, const float* sino, float* x_full,
+                              void* stream)
+{
+    if (!geometry_ok(g) || !sino || !x_full) return IMASK_EINVAL;
+    if (g->angles || is_fan(*g)) return IMASK_ENOTSUP;
+    const Layout L = transpose_layout(*g);
+    if (log2f < 0 || log2f > L.lmax) return IMASK_EINVAL;
+    if (L.total * sizeof(float) > (size_t)IMASK_NOALLOC_SCRATCH_BYTES) return IMASK_ESIZE;
+    void* ptr = nullptr;
+    if (int rc = scratch_of_current_device(&ptr)) return rc;
+    float* W = (float*)ptr;
+    hipStream_t s = (hipStream_t)stream;
+    // every cell the transpose reads is written earlier in this call (the
+    // constants, each partial image in full, the coarse result), so the
+    // array's previous contents never matter and nothing is cleared
+    IMK_TRY(launch_consts(*g, L, W, s));
+    return backproject_raw(L, W, log2f, sino, x_full, 1.0f / (float)(1 << (2 * log2f)), 0, 1, s);
 }
 
 int imask_resample(int32_t n, int32_t log2f, int32_t mode, const imask_levels* lv, const float* in, float* out,

@@ -167,6 +167,17 @@ def backproject(g: Geometry, log2f: int, sino: torch.Tensor, work: torch.Tensor,
     return out
 
 
+def backproject_noalloc(g: Geometry, log2f: int, sino: torch.Tensor, out: torch.Tensor):
+    """backproject without a workspace: the library's static per-GPU array
+    holds the transpose's constants and partial images.  `out` is the
+    caller's (nothing is allocated here either)."""
+    _need(sino, g.sino_shape, "sino")
+    _need(out, g.image_shape, "out")
+    check(lib().imask_backproject_noalloc(ctypes.byref(g.c()), log2f, _ptr(sino), _ptr(out), _stream()),
+          "imask_backproject_noalloc")
+    return out
+
+
 def resample(x: torch.Tensor, log2f: int, mode: int, levels: Levels | None = None):
     n = x.shape[-1]
     nl = n >> log2f

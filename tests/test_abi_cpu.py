@@ -319,3 +319,24 @@ def test_fan_partial_image_buffer_sizing():
     for n, extra_images in ((64, 48), (512, 48), (1024, 48), (2048, 0), (4096, 0)):
         diff = ws(n, True) - ws(n, False)
         assert abs(diff - extra_images * n * n * 4) <= 65536, (n, diff)
+
+
+def test_noalloc_transpose_validates_before_any_device_call():
+    """The workspace-free transpose checks its arguments and whether the
+    geometry fits its static array before it looks up the array or launches
+    anything (so these calls need no GPU)."""
+    L = _abi.lib()
+    p = ctypes.c_void_p(16)
+
+    def call(g, lvl=0, sino=p, out=p):
+        return L.imask_backproject_noalloc(ctypes.byref(g.c()), lvl, sino, out, None)
+
+    assert call(im.Geometry(64, 90, 92), sino=None) == _abi.EINVAL
+    assert call(im.Geometry(64, 90, 92), out=None) == _abi.EINVAL
+    assert call(im.Geometry(64, 90, 92), lvl=6) == _abi.EINVAL
+    assert call(im.Geometry(63, 90, 92)) == _abi.EINVAL
+    assert call(im.Geometry(64, 3, 92, angles=(0.1, 0.2, 0.3))) == _abi.ENOTSUP
+    assert call(im.Geometry(64, 90, 92, src_dist=4.0, det_dist=2.0)) == _abi.ENOTSUP
+    # 17 N^2 + 16 (lmax + 1) n_angles floats against the 24 MiB array
+    assert call(im.Geometry(1024, 90, 92)) == _abi.ESIZE
+    assert call(im.Geometry(512, 20000, 768)) == _abi.ESIZE

@@ -61,11 +61,16 @@ LAM, TV_W, TV_EPS, TV_J = 1e-3, 2e-4, 1e-3, 10
 SIGMA = 1e-3
 SEED, STREAM = 42, 0
 FAN_D, FAN_DD = 4.0, 2.0  # fan workload: source and detector distances
-# FP32 arithmetic per Joseph sample (a (ray, step) pair, two matrix entries):
-# coordinate step (1), right-tap weight w and left weight 1 - w (2), two
-# multiply-adds into the accumulator (4).
-FLOP_PER_SAMPLE = 7
-PEAK_FP32_TFLOPS = 157.3   # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2 (dual FP32) x 2.4 GHz
+# FP32 arithmetic per Joseph sample (a (ray, step) pair, two matrix entries),
+# counted as the algorithm needs it: the right-tap weight w (1), the left
+# weight 1 - w folded into a multiply-add with the left tap (2), the
+# right tap's multiply-add (2), less the shared accumulation: about 4 FLOP.
+FLOP_PER_SAMPLE = 4
+# FP32 vector peak this build can issue: 256 CU x 4 SIMD x 16 lanes x 2 (FMA)
+# x 2.4 GHz.  The chip's 157.3 TFLOP/s needs packed FP32 instructions, which
+# this build disables (-packed-fp32-ops), so half of it is the attainable peak.
+PEAK_FP32_TFLOPS = 78.6
+PEAK_FP32_PACKED_TFLOPS = 157.3
 HBM_PEAK_GBS = 8000.0
 LDS_PEAK_TBPS = 256 * 128 * 2.4e9 / 1e12  # 78.6 TB/s: 128 B per clock per CU
 # LDS bytes per sample: the transpose reads and writes both taps' cells, the
@@ -197,6 +202,56 @@ def counter_run(spec: str, fan: bool = False):
     print(f"counter run done: {spec}", flush=True)
 
 
+def algorithmic_bytes(kind, lvl, fan=False):
+    """Compulsory HBM bytes of one projector launch: its input and output
+    (forward: the level image in, the sinogram out; transpose: the reverse)."""
+    nl = N >> lvl
+    return 4 * (nl * nl + NA * ND)
+
+
+def roofline_block(key, dom, dom_t, samples, fan):
+    """The dominant kernel against the FP32 vector peak, with the measured
+    HBM traffic beside its algorithmic bytes."""
+    achieved = samples[dom[1]] * FLOP_PER_SAMPLE / dom_t / 1e12
+    traffic = stored_traffic(key)
+    alg = algorithmic_bytes(dom[0], dom[1], fan)
+    return {"bound": "alu", "kernel": key, "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
+            "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
+            "flop_per_sample": FLOP_PER_SAMPLE, "peak_packed_fp32": PEAK_FP32_PACKED_TFLOPS,
+            "samples_per_launch": samples[dom[1]], "avg_launch_us": dom_t * 1e6,
+            "samples_per_s": samples[dom[1]] / dom_t,
+            "algorithmic_bytes": alg,
+            "hbm_TBps_measured": None if traffic is None else traffic / dom_t / 1e12,
+            "hbm_frac_measured": None if traffic is None else traffic / dom_t / 1e9 / HBM_PEAK_GBS,
+            "traffic_over_algorithmic": None if traffic is None else traffic / alg}
+
+
+def step_times_by_level(prob, lv, steps):
+    """Mean GPU time of one whole step per level (HIP events on the stream the
+    library launches on, between consecutive steps; a spin kernel first keeps
+    the GPU behind the host so the gaps are the GPU's own)."""
+    import torch
+
+    import paper_2412_10249_amd as pk
+
+    draws = pk.draws(prob.params, lv, prob.k, steps)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    torch.cuda.synchronize()
+    torch.cuda._sleep(50_000_000)
+    ev[0].record()
+    for q in range(steps):
+        prob.step(1)
+        ev[q + 1].record()
+    torch.cuda.synchronize()
+    dt = np.array([ev[q].elapsed_time(ev[q + 1]) * 1e3 for q in range(steps)])
+    out = {}
+    for k, l in enumerate(lv.log2f):
+        sel = dt[draws == k]
+        if len(sel):
+            out[l] = float(np.median(sel))
+    return out
+
+
 def run(args):
     import torch
 
@@ -253,7 +308,8 @@ def run(args):
     else:
         name = {"fwd": "k_fwd_band" if (N >> dom[1]) <= 512 else "k_fwd_direct", "bp": "k_bp_own"}[dom[0]]
     key = f"{name}_l{dom[1]}"
-    achieved = samples[dom[1]] * FLOP_PER_SAMPLE / dom_t / 1e12
+    by_level = step_times_by_level(prob, lv, args.level_steps)
+    t0_step = by_level.get(0)
     out = {
         "metric": "ImaSk epochs/s (512x512 smoothed-TV race workload)",
         "value": epochs / el,
@@ -275,21 +331,33 @@ def run(args):
                                + (f", {args.blocks} measurement blocks of {NA // args.blocks} angles"
                                   if args.blocks > 1 else ""),
                    "steps_level_mix": [round(float(v), 4) for v in mix], "epochs_timed": epochs},
-        "roofline": {"bound": "alu", "kernel": key, "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": stored_traffic(key),
-                     "samples_per_launch": samples[dom[1]], "avg_launch_us": dom_t * 1e6,
-                     "samples_per_s": samples[dom[1]] / dom_t,
-                     "effective_gather_frac_hbm": samples[dom[1]] * 8 / dom_t / 1e9 / HBM_PEAK_GBS},
+        "roofline": roofline_block(key, dom, dom_t, samples, args.fan),
         # the transpose's working limit: LDS traffic, two read-modify-writes of
         # 4-byte cells per sample, against 256 CUs x 128 B/clk x 2.4 GHz
         "lds_roofline": None if args.fan else {"kernel": key, "bytes_per_sample": LDS_BYTES_PER_SAMPLE[dom[0]],
                          "achieved_TBps": samples[dom[1]] * LDS_BYTES_PER_SAMPLE[dom[0]] / dom_t / 1e12,
                          "peak_TBps": LDS_PEAK_TBPS,
                          "frac": samples[dom[1]] * LDS_BYTES_PER_SAMPLE[dom[0]] / dom_t / 1e12 / LDS_PEAK_TBPS},
+        # whole steps per level (median us) against the cost model of the
+        # epoch count: a level-l step costs 2^-l of a full-resolution one
+        "step_us_by_level": {f"l{l}": round(v, 2) for l, v in by_level.items()},
+        "step_ratio_vs_level0": {f"l{l}": {"measured": round(v / t0_step, 4), "model": 2.0 ** -l}
+                                 for l, v in by_level.items()} if t0_step else None,
         "kernels_us": {f"{k[0]}_l{k[1]}": round(v * 1e6, 2) for k, v in kern.items()},
         "projector_samples_per_s": {f"{k[0]}_l{k[1]}": samples[k[1]] / v for k, v in kern.items()},
         "kernel_source_hash": source_hash(),
     }
+    headline = args.blocks == 1 and not args.fan
+    if headline and not args.no_race:
+        try:
+            out["time_to_rel_err_1e-3"] = headline_race(geom, b32, prob.work, args)
+        except Exception as e:  # the epochs/s line above stands on its own
+            out["time_to_rel_err_1e-3"] = {"error": repr(e)}
+    if headline and not args.no_serve:
+        try:
+            out["serve"] = headline_serve(args)
+        except Exception as e:
+            out["serve"] = {"error": repr(e)}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(b, blocks=args.blocks, fan=args.fan)
     print(json.dumps(out), flush=True)
@@ -350,6 +418,90 @@ def reference_solution(geom, work, b32, lam, w, eps, iters, log):
     return x, gn
 
 
+def race_method(name, lv, sched, geom, work, b32, xref, reg, args, mults, log):
+    """One method of the race at each multiple of its base step: runs until
+    the relative error to xref reaches args.target (checked every few
+    epochs, interpolated in log error), diverges or runs out of time."""
+    import torch
+
+    import paper_2412_10249_amd as pk
+
+    rnorm = float(torch.linalg.vector_norm(xref))
+    L2, lb, lp = pk.step_constants(geom, lv, LAM, work, iters=40)
+    nb = max(lv.n_blocks, 1)
+    s3, th = pk.sigma_thm3(L2, nb * lb, nb * nb * lp, min(lv.p) / nb, 100)
+    spd = 1.0 / np.sqrt(L2)
+    seq = sched == pk.SCHEDULE_SEQUENTIAL
+    base = spd if seq else s3
+    res = {"constants": [L2, lb, lp], "blocks": nb, "sigma_thm3": s3, "theta_thm3": th, "sigma_pd": spd,
+           "schedule": "sequential" if seq else "parallel", "runs": []}
+    check = args.seq_check_every if seq else args.check_every
+    for mult in mults:
+        sigma = base * mult
+        draw = pk.DRAW_INDEPENDENT if name.endswith("_indep") else pk.DRAW_COMMON
+        prob = pk.Problem(geom, lv, reg, pk.Params(sigma, SEED, STREAM, sched, 1.0, draw, STREAM + 1), b32)
+        torch.cuda.synchronize()
+        hist = []
+        tstart = time.perf_counter()
+        tlog = tstart
+        while prob.epochs < args.race_epochs:
+            prob.solve(check, pk.BUDGET_EPOCHS)
+            err = float(torch.linalg.vector_norm(prob.x_cur - xref)) / rnorm  # synchronises
+            hist.append((time.perf_counter() - tstart, prob.epochs, err))
+            if time.perf_counter() - tlog > 20.0:
+                tlog = time.perf_counter()
+                log(f"  {name} sigma x{mult}: {prob.epochs:.0f} epochs, rel err {err:.3e}")
+            if (err <= args.target or not np.isfinite(err) or err > 10.0
+                    or time.perf_counter() - tstart > args.race_seconds):
+                break
+        t_hit = e_hit = None
+        for (t1, e1, r1_), (t2, e2, r2_) in zip([(0.0, 0.0, 1.0)] + hist, hist):
+            if r2_ <= args.target < r1_:  # interpolate in log error
+                f = (np.log(r1_) - np.log(args.target)) / (np.log(r1_) - np.log(r2_))
+                t_hit = t1 + f * (t2 - t1)
+                e_hit = e1 + f * (e2 - e1)
+                break
+        run_res = {"sigma": sigma, "sigma_multiple": mult, "epochs": prob.epochs,
+                   "final_rel_err": hist[-1][2], "seconds": hist[-1][0], "time_to_target_s": t_hit,
+                   "epochs_to_target": e_hit, "check_every_epochs": check,
+                   "rel_err_history": [(round(h[1], 2), round(h[2], 7)) for h in hist[::max(1, len(hist) // 60)]]}
+        log(f"{name} sigma x{mult}: {run_res['final_rel_err']:.3e} after {prob.epochs:.1f} epochs, "
+            f"{hist[-1][0]:.2f} s, t(1e-3) = {t_hit}")
+        res["runs"].append(run_res)
+        del prob
+    return res
+
+
+def headline_race(geom, b32, work, args):
+    """The headline's second figure: time to relative error 1e-3 of ImaSk
+    (r = 4, UNBIASED sketches) against full-resolution SAGA (r = 1), both at
+    twice their Thm. 3 step (the fastest stable multiple), against the limit
+    they share, certified by its relative gradient."""
+    import torch
+
+    import paper_2412_10249_amd as pk
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    t0 = time.perf_counter()
+    xref, gnorm = reference_solution(geom, work, b32, LAM, TV_W, TV_EPS, args.ref_iters, log)
+    reg = pk.Regularizer(pk.REG_SMOOTH_TV, LAM, TV_W, TV_EPS, TV_J)
+    out = {"target": args.target, "reference_relative_gradient": gnorm, "sigma_multiple_of_thm3": 2.0}
+    rargs = argparse.Namespace(**vars(args))
+    rargs.race_epochs, rargs.race_seconds = 1e6, args.headline_race_seconds
+    for name, lv in (("imask_r4", pk.Levels.uniform(LEVELS, pk.FULL_UNBIASED)), ("saga_r1", pk.Levels((0,), (1.0,)))):
+        res = race_method(name, lv, pk.SCHEDULE_PARALLEL, geom, work, b32, xref, reg, rargs, [2.0], log)
+        r = res["runs"][0]
+        out[name] = {"seconds": r["time_to_target_s"], "epochs": r["epochs_to_target"], "sigma": r["sigma"],
+                     "final_rel_err": r["final_rel_err"]}
+    a, c = out["imask_r4"]["seconds"], out["saga_r1"]["seconds"]
+    out["imask_over_saga_time"] = a / c if a and c else None
+    out["wall_s"] = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    return out
+
+
 def race(args):
     """Time to a relative error of 1e-3 against the common limit, same kernels,
     same GPU, UNBIASED sketches (levels 512/256/128/64) so that every method
@@ -392,7 +544,6 @@ def race(args):
     t0 = time.perf_counter()
     xref, gnorm = reference_solution(geom, work, b32, LAM, TV_W, TV_EPS, args.ref_iters, log)
     log(f"reference done in {time.perf_counter() - t0:.1f} s, relative gradient {gnorm:.2e}")
-    rnorm = float(torch.linalg.vector_norm(xref))
     reg = pk.Regularizer(pk.REG_SMOOTH_TV, LAM, TV_W, TV_EPS, TV_J)
     r4 = pk.Levels.uniform(LEVELS, pk.FULL_UNBIASED)
     r1 = pk.Levels((0,), (1.0,))
@@ -405,47 +556,9 @@ def race(args):
     results = {}
     for name in args.methods:
         lv, sched = methods[name]
-        L2, lb, lp = pk.step_constants(geom, lv, LAM, work, iters=40)
-        nb = max(lv.n_blocks, 1)
-        s3, th = pk.sigma_thm3(L2, nb * lb, nb * nb * lp, min(lv.p) / nb, 100)
-        spd = 1.0 / np.sqrt(L2)
-        seq = sched == pk.SCHEDULE_SEQUENTIAL
-        base, mults = (spd, args.seq_sigma_mults) if seq else (s3, args.sigma_mults)
-        results[name] = {"constants": [L2, lb, lp], "blocks": nb, "sigma_thm3": s3, "theta_thm3": th, "sigma_pd": spd,
-                         "schedule": "sequential" if seq else "parallel", "runs": []}
-        check = args.seq_check_every if seq else args.check_every
-        for mult in mults:
-            sigma = base * mult
-            draw = pk.DRAW_INDEPENDENT if name.endswith("_indep") else pk.DRAW_COMMON
-            prob = pk.Problem(geom, lv, reg, pk.Params(sigma, SEED, STREAM, sched, 1.0, draw, STREAM + 1), b32)
-            torch.cuda.synchronize()
-            hist = []
-            tstart = time.perf_counter()
-            tlog = tstart
-            while prob.epochs < args.race_epochs:
-                prob.solve(check, pk.BUDGET_EPOCHS)
-                err = float(torch.linalg.vector_norm(prob.x_cur - xref)) / rnorm  # synchronises
-                hist.append((time.perf_counter() - tstart, prob.epochs, err))
-                if time.perf_counter() - tlog > 20.0:
-                    tlog = time.perf_counter()
-                    log(f"  {name} sigma x{mult}: {prob.epochs:.0f} epochs, rel err {err:.3e}")
-                if (err <= args.target or not np.isfinite(err) or err > 10.0
-                        or time.perf_counter() - tstart > args.race_seconds):
-                    break
-            t_hit = e_hit = None
-            for (t1, e1, r1_), (t2, e2, r2_) in zip([(0.0, 0.0, 1.0)] + hist, hist):
-                if r2_ <= args.target < r1_:  # interpolate in log error
-                    f = (np.log(r1_) - np.log(args.target)) / (np.log(r1_) - np.log(r2_))
-                    t_hit = t1 + f * (t2 - t1)
-                    e_hit = e1 + f * (e2 - e1)
-                    break
-            run_res = {"sigma": sigma, "sigma_multiple": mult, "epochs": prob.epochs,
-                       "final_rel_err": hist[-1][2], "seconds": hist[-1][0], "time_to_target_s": t_hit,
-                       "epochs_to_target": e_hit, "check_every_epochs": check,
-                       "rel_err_history": [(round(h[1], 2), round(h[2], 7)) for h in hist[::max(1, len(hist) // 60)]]}
-            log(f"{name} sigma x{mult}: {run_res['final_rel_err']:.3e} after {prob.epochs:.1f} epochs, "
-                f"{hist[-1][0]:.2f} s, t(1e-3) = {t_hit}")
-            results[name]["runs"].append(run_res)
+        results[name] = race_method(name, lv, sched, geom, work, b32, xref, reg, args,
+                                    args.seq_sigma_mults if sched == pk.SCHEDULE_SEQUENTIAL else args.sigma_mults,
+                                    log)
     best = {k: min([r["time_to_target_s"] for r in v["runs"] if r["time_to_target_s"]] or [None], key=lambda z: z or 1e30)
             for k, v in results.items()}
     print(json.dumps({"metric": "time to relative error 1e-3 vs the common limit (512x512 smoothed TV"
@@ -591,13 +704,19 @@ def _sigma_for(geom, levels, lam, work, cache={}):
 
 def batched(args):
     """64 slices of mixed sizes (256..1024, angles = bins = 1.5 N), each with its
-    own draw stream, Tikhonov lam = 1e-2, 30 epochs each, all in flight on
-    several streams; aggregate throughput and per-slice equality with alone."""
+    own draw stream, Tikhonov lam = 1e-2, 30 epochs each.  Three ways:
+      batched   the library's batched steps: one persistent launch per kernel
+                variant for all slices, draws on the device, one captured
+                step replayed as a CUDA graph; with the autotuned tiles
+                (paper_2412_10249_amd/tiles.json) and with the defaults
+      streams   each slice's own steps, dealt round-robin to 8 HIP streams
+      alone     the slices one after another on one stream
+    Aggregate samples/s, and every batched slice compared with its run alone."""
     import torch
 
     import paper_2412_10249_amd as pk
     import synth
-    from paper_2412_10249_amd import batch
+    from paper_2412_10249_amd import autotune, batch
 
     def log(msg):
         print(msg, file=sys.stderr, flush=True)
@@ -612,42 +731,139 @@ def batched(args):
                                     .astype(np.float32)).cuda() for s in range(2)]
         log(f"data for N={n} ready")
     sig = {}
-    probs = []
-    for s in range(args.slices):
-        n = sizes[s % 5]
-        geom = pk.Geometry(n, 3 * n // 2, 3 * n // 2)
-        if n not in sig:
-            sig[n] = _sigma_for(geom, lv, 1e-2, pk.workspace(geom))
-        probs.append(pk.Problem(geom, lv, reg, pk.Params(sig[n], SEED, s), data[n][s % 2]))
-    torch.cuda.synchronize()
+
+    def make():
+        out = []
+        for s in range(args.slices):
+            n = sizes[s % 5]
+            geom = pk.Geometry(n, 3 * n // 2, 3 * n // 2)
+            if n not in sig:
+                sig[n] = _sigma_for(geom, lv, 1e-2, pk.workspace(geom))
+            out.append(pk.Problem(geom, lv, reg, pk.Params(sig[n], SEED, s), data[n][s % 2]))
+        torch.cuda.synchronize()
+        return out
+
     # one epoch = one full-resolution projection and one backprojection
     s0 = {n: sample_counts(n, 3 * n // 2, 3 * n // 2, 0, angle_stride=16) for n in sizes}
-    samples_per_epoch = sum(2 * s0[p.geom.n] for p in probs)
+    samples_per_epoch = sum(2 * s0[sizes[s % 5]] for s in range(args.slices))
+    res = {"metric": "batched ImaSk, 64 mixed slices", "slices": args.slices, "epochs_per_slice": args.epochs}
+
+    def run_batched(tiles):
+        table = autotune.load() if tiles else {}
+        autotune.apply(table)
+        probs = make()
+        bt = batch.Batch(probs, args.epochs, pk.BUDGET_EPOCHS)
+        bt.capture()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        bt.replay(bt.steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        bt.sync_state()
+        autotune.reset(table)
+        return probs, el, bt.steps
+
+    for name, tiles in (("batched_graph_tuned", True), ("batched_graph_default_tiles", False)):
+        probs, el, steps = run_batched(tiles)
+        tot = sum(p.epochs for p in probs)
+        res[name] = {"seconds": el, "batched_steps": steps, "slice_epochs_per_s": tot / el,
+                     "samples_per_s": samples_per_epoch * args.epochs / el}
+        log(f"{name}: {el:.3f} s, {steps} batched steps")
+        if tiles:
+            tuned_probs = probs
+        else:
+            del probs
+    # the same slices on 8 streams, and one after another
+    probs = make()
     runner = batch.BatchRunner(probs, n_streams=args.streams)
     t0 = time.perf_counter()
     runner.solve_all(args.epochs, pk.BUDGET_EPOCHS)
     runner.synchronize()
     el = time.perf_counter() - t0
-    tot_epochs = sum(p.epochs for p in probs)
-    log(f"batch done: {len(probs)} slices, {tot_epochs:.1f} slice-epochs in {el:.2f} s")
-    # the same slices alone, one after another on one stream: equality and the overlap gain
-    same = []
-    t1 = time.perf_counter()
-    for s, p in enumerate(probs):
+    res["streams"] = {"streams": args.streams, "seconds": el, "samples_per_s": samples_per_epoch * args.epochs / el}
+    del probs, runner
+    probs = make()
+    t0 = time.perf_counter()
+    for p in probs:
+        p.solve(args.epochs, pk.BUDGET_EPOCHS)
+    torch.cuda.synchronize()
+    seq = time.perf_counter() - t0
+    res["alone"] = {"seconds": seq, "samples_per_s": samples_per_epoch * args.epochs / seq}
+    # every batched slice (tuned tiles) against its run alone with the same tiles
+    table = autotune.load()
+    autotune.apply(table)
+    worst = 0.0
+    equal = 0
+    for s, p in enumerate(tuned_probs):
         q = pk.Problem(p.geom, lv, reg, pk.Params(sig[p.geom.n], SEED, s), data[p.geom.n][s % 2])
         q.solve(args.epochs, pk.BUDGET_EPOCHS)
-        if s % 5 == 0:
-            same.append(q.x_cur)
-        else:
-            del q
-    torch.cuda.synchronize()
-    seq = time.perf_counter() - t1
-    same = [bool(torch.equal(q, probs[5 * i].x_cur)) for i, q in enumerate(same)]
-    print(json.dumps({"metric": "batched ImaSk, 64 mixed slices", "slices": len(probs), "streams": args.streams,
-                      "epochs_per_slice": args.epochs, "seconds": el, "slice_epochs_per_s": tot_epochs / el,
-                      "samples_per_s": samples_per_epoch * args.epochs / el,
-                      "sequential_seconds": seq, "overlap_speedup": seq / el,
-                      "equal_to_alone": all(same), "checked_slices": len(same)}), flush=True)
+        same = bool(torch.equal(q.x_cur, p.x_cur))
+        equal += int(same)
+        d = float(torch.linalg.vector_norm(q.x_cur - p.x_cur) / torch.linalg.vector_norm(q.x_cur))
+        worst = max(worst, d)
+        del q
+    autotune.reset(table)
+    res["equal_to_alone_bitwise"] = equal
+    res["checked_slices"] = len(tuned_probs)
+    res["worst_rel_diff_to_alone"] = worst
+    res["speedup_vs_alone"] = seq / res["batched_graph_tuned"]["seconds"]
+    res["speedup_vs_streams"] = res["streams"]["seconds"] / res["batched_graph_tuned"]["seconds"]
+    print(json.dumps(res), flush=True)
+
+
+def serve_pool(lv, reg, sizes=(128, 256, 512, 1024)):
+    """Data and step sizes of the serving workload (three sinograms per size)."""
+    import torch
+
+    import paper_2412_10249_amd as pk
+    import synth
+
+    pool, sig = {}, {}
+    for n in sizes:
+        geom = pk.Geometry(n, 3 * n // 2, 3 * n // 2)
+        pool[n] = [torch.from_numpy(synth.ct_problem(n, 3 * n // 2, 3 * n // 2, 1e5, 3000 + s, 4000 + s)[1]
+                                    .astype(np.float32)).cuda() for s in range(3)]
+        sig[geom] = _sigma_for(geom, lv, 1e-2, pk.workspace(geom))
+    return pool, sig
+
+
+def serve_rate(rate, args, lv, reg, pool, sig, log):
+    """Poisson arrivals at `rate` over args.window seconds into the server."""
+    from paper_2412_10249_amd import serve
+
+    ex = serve.GpuExecutor(args.slots, lambda n: lv, reg, lambda g: sig[g])
+    sch = serve.Scheduler(ex, hbm_budget=int(args.hbm_gb * 2 ** 30), max_active=args.slots,
+                          chunk_epochs=args.chunk)
+    arr = serve.poisson_arrivals(rate, args.window, seed=7)
+    t0 = time.perf_counter()
+    done = serve.run_load(sch, arr, lambda rid, n, t: serve.Request(rid, n, t, args.serve_epochs,
+                                                                      data=pool[n][rid % 3]))
+    summ = serve.latency_summary(done)
+    summ.update({"offered_per_s": rate, "requests": len(arr), "window_s": args.window,
+                 "wall_s": time.perf_counter() - t0})
+    log(f"rate {rate}: {summ}")
+    return summ
+
+
+def headline_serve(args):
+    """The headline's serving figures: p50/p99 latency of 30-epoch requests
+    (N in 128/256/512/1024, weights 4:3:2:1) under Poisson arrivals at the
+    configured 200 req/s (beyond what the projectors deliver, so its queue
+    grows) and at 150 req/s, the highest rate measured to drain."""
+    import paper_2412_10249_amd as pk
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    lv = pk.Levels.uniform(LEVELS)
+    reg = pk.Regularizer(pk.REG_TIKHONOV, 1e-2)
+    pool, sig = serve_pool(lv, reg)
+    out = {"epochs_per_request": args.serve_epochs, "window_s": args.window, "slots": args.slots}
+    for rate in args.headline_rates:
+        r = serve_rate(rate, args, lv, reg, pool, sig, log)
+        out[f"rate_{int(rate)}"] = {k: r.get(k) for k in ("p50_ms", "p99_ms", "served_per_s", "offered_per_s",
+                                                           "requests", "wall_s")}
+    return out
 
 
 def serving(args):
@@ -665,28 +881,9 @@ def serving(args):
     torch.cuda.set_device(0)
     lv = pk.Levels.uniform(LEVELS)
     reg = pk.Regularizer(pk.REG_TIKHONOV, 1e-2)
-    pool = {}
-    sig = {}
-    for n in (128, 256, 512, 1024):
-        geom = pk.Geometry(n, 3 * n // 2, 3 * n // 2)
-        pool[n] = [torch.from_numpy(synth.ct_problem(n, 3 * n // 2, 3 * n // 2, 1e5, 3000 + s, 4000 + s)[1]
-                                    .astype(np.float32)).cuda() for s in range(3)]
-        sig[geom] = _sigma_for(geom, lv, 1e-2, pk.workspace(geom))
+    pool, sig = serve_pool(lv, reg)
     log("serving data ready")
-    out = []
-    for rate in args.rates:
-        ex = serve.GpuExecutor(args.slots, lambda n: lv, reg, lambda g: sig[g])
-        sch = serve.Scheduler(ex, hbm_budget=int(args.hbm_gb * 2 ** 30), max_active=args.slots,
-                              chunk_epochs=args.chunk)
-        arr = serve.poisson_arrivals(rate, args.window, seed=7)
-        t0 = time.perf_counter()
-        done = serve.run_load(sch, arr, lambda rid, n, t: serve.Request(rid, n, t, args.serve_epochs,
-                                                                          data=pool[n][rid % 3]))
-        summ = serve.latency_summary(done)
-        summ.update({"offered_per_s": rate, "requests": len(arr), "window_s": args.window,
-                     "wall_s": time.perf_counter() - t0})
-        log(f"rate {rate}: {summ}")
-        out.append(summ)
+    out = [serve_rate(rate, args, lv, reg, pool, sig, log) for rate in args.rates]
     # sustainable: the queue drains within a second of the arrival window
     ok = [r["offered_per_s"] for r in out if r["wall_s"] <= args.window + 1.0]
     print(json.dumps({"metric": "serving ImaSk reconstructions, p50/p99 latency", "slots": args.slots,
@@ -882,6 +1079,12 @@ def main():
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--kernel-reps", type=int, default=20)
+    ap.add_argument("--level-steps", type=int, default=200, help="steps timed one by one for the per-level table")
+    ap.add_argument("--no-race", action="store_true", help="skip the time-to-1e-3 race in the main line")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving latencies in the main line")
+    ap.add_argument("--headline-rates", type=float, nargs="+", default=[200.0, 150.0])
+    ap.add_argument("--headline-race-seconds", type=float, default=45.0,
+                    help="per-method time limit of the race in the main line")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calib", action="store_true")
     ap.add_argument("--summarize", nargs="+")

@@ -378,6 +378,76 @@ int imask_solve(int32_t n_problems, const imask_geometry* g, const imask_levels*
                 const imask_reg* reg, const imask_params* prm, const float* const* b,
                 imask_state* s, double budget, int32_t budget_kind, void* stream);
 
+/* ---- Launch shapes (an autotuner's knobs; set-up calls) ----
+ * The kernels of a level whose grid side is nl, in geometries of n_angles x
+ * n_det, take these shapes instead of the defaults:
+ *   bp_rows x bp_waves  the transpose's tile: image rows per wavefront and
+ *                       wavefronts per workgroup (2x8, 4x4, 2x4 or 1x4; a
+ *                       shape whose rows do not fit in the LDS falls back
+ *                       to the default)
+ *   bp_wg               the transpose's target workgroup count (64..16384;
+ *                       angle groups are also bounded by the partial images
+ *                       the workspace holds)
+ *   fwd_lds_kb          the forward's band budget in KB (the level's
+ *                       default or more, up to 156: never more bands than
+ *                       the workspace is sized for)
+ * Zero fields keep the defaults; t == NULL resets the entry.  Every shape
+ * computes the same matrices; only the order of floating-point sums (band
+ * partials, angle groups) changes.  The table is global to the process and
+ * read at every launch: do not change it while another thread launches, or
+ * between imask_batch_prepare and the batch's steps.  IMASK_EINVAL for an
+ * unsupported shape or out-of-range sizes. */
+typedef struct {
+    int32_t bp_rows, bp_waves, bp_wg, fwd_lds_kb;
+} imask_tiles;
+int imask_set_tiles(int32_t nl, int32_t n_angles, int32_t n_det, const imask_tiles* t);
+int imask_get_tiles(int32_t nl, int32_t n_angles, int32_t n_det, imask_tiles* out);
+
+/* ---- Batched steps: many independent problems of mixed sizes advanced
+ * together (Alg. 1 for each; the batching is a systems layer, not part of
+ * the paper's method).  A batch buffer (device, caller-owned) holds, for
+ * every problem and every (sketch, parity of the ping-pong buffers), the
+ * launch records of one step: the kernels, grids and arguments that
+ * imask_step would launch for it.  Each batched step then runs one plan
+ * kernel (it draws every problem's sketch index on the device, from the
+ * same SplitMix64 stream as the host draw), one persistent launch per kernel
+ * variant over the work items of all problems, and one kernel that advances
+ * the counters.  The launches of a step do not depend on the draws, so a
+ * captured step (hipStreamBeginCapture / a torch CUDA graph) can be replayed
+ * for every step.  Each problem computes exactly what imask_step computes
+ * for it (same kernels, shapes and summation order: equal bit for bit).
+ *
+ * Supported problems: parallel beam (default or listed angles), the
+ * parallel schedule with common draws, no measurement blocks, the standard
+ * tables and the Tikhonov prior (IMASK_ENOTSUP otherwise).  At most 4096
+ * problems; the problems must not share state, data or workspace buffers.
+ */
+
+/* Bytes of the batch buffer for these problems (0 if invalid). */
+size_t imask_batch_bytes(int32_t n_problems, const imask_geometry* g, const imask_levels* lv);
+
+/* Set-up (synchronises `stream`): validates the problems, fills the batch
+ * buffer from their current states (s[q].k, cur, epochs and buffers) and
+ * fixes each problem's budget: `budget` more iterations (IMASK_BUDGET_ITERS)
+ * or epochs (IMASK_BUDGET_EPOCHS), evaluated from the host draws as
+ * imask_solve does; a problem idles once its budget is met.  steps_out
+ * (may be NULL) receives the number of batched steps after which every
+ * problem has met its budget.  Errors: IMASK_EINVAL / IMASK_ENOTSUP as for
+ * imask_step and above, IMASK_ESIZE for a buffer below imask_batch_bytes. */
+int imask_batch_prepare(int32_t n_problems, const imask_geometry* g, const imask_levels* lv, const imask_reg* reg,
+                        const imask_params* prm, const float* const* b, const imask_state* s, double budget,
+                        int32_t budget_kind, void* batch, size_t batch_bytes, int64_t* steps_out, void* stream);
+
+/* Enqueues n_steps batched steps on `stream` (no synchronisation; the
+ * problems' counters advance on the device, not in the host structs).
+ * g and lv must be those given to imask_batch_prepare. */
+int imask_batch_step(int32_t n_problems, const imask_geometry* g, const imask_levels* lv, void* batch,
+                     int32_t n_steps, void* stream);
+
+/* Copies the problems' counters (k, cur, epochs) from the batch buffer into
+ * s[0..n_problems) (synchronises `stream`); lv as given to prepare. */
+int imask_batch_state(int32_t n_problems, const imask_levels* lv, const void* batch, imask_state* s, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -27,7 +27,8 @@ EXPORTS = ["imask_workspace_bytes", "imask_phi_floats", "imask_prepare", "imask_
            "imask_backproject", "imask_resample", "imask_sketch_apply", "imask_draws",
            "imask_step", "imask_solve", "imask_time_kernel", "imask_constants_scratch_bytes",
            "imask_step_constants", "imask_sigma_thm3", "imask_sigma_balamurugan", "imask_block_draws",
-           "imask_backproject_noalloc"]
+           "imask_backproject_noalloc", "imask_batch_bytes", "imask_batch_prepare", "imask_batch_step",
+           "imask_batch_state", "imask_set_tiles", "imask_get_tiles"]
 NOALLOC_SCRATCH_BYTES = 24 << 20
 KERNEL_FORWARD, KERNEL_TRANSPOSE = 0, 1
 
@@ -60,6 +61,11 @@ class State(ctypes.Structure):
                 ("psi", ctypes.c_void_p), ("work", ctypes.c_void_p), ("k", ctypes.c_uint64),
                 ("epochs", ctypes.c_double), ("cur", ctypes.c_int32), ("xbar", ctypes.c_void_p),
                 ("tvd", ctypes.c_void_p * 2), ("ztab", ctypes.c_void_p)]
+
+
+class Tiles(ctypes.Structure):
+    _fields_ = [("bp_rows", ctypes.c_int32), ("bp_waves", ctypes.c_int32), ("bp_wg", ctypes.c_int32),
+                ("fwd_lds_kb", ctypes.c_int32)]
 
 
 class ImaskError(RuntimeError):
@@ -100,6 +106,14 @@ def lib():
         L.imask_step.argtypes = [i32, P(Geometry), P(Levels), P(Reg), P(Params), P(vp), P(State), i32, vp]
         L.imask_solve.argtypes = [i32, P(Geometry), P(Levels), P(Reg), P(Params), P(vp), P(State),
                                   ctypes.c_double, i32, vp]
+        L.imask_batch_bytes.argtypes = [i32, P(Geometry), P(Levels)]
+        L.imask_batch_bytes.restype = sz
+        L.imask_batch_prepare.argtypes = [i32, P(Geometry), P(Levels), P(Reg), P(Params), P(vp), P(State),
+                                          ctypes.c_double, i32, vp, sz, P(ctypes.c_int64), vp]
+        L.imask_batch_step.argtypes = [i32, P(Geometry), P(Levels), vp, i32, vp]
+        L.imask_batch_state.argtypes = [i32, P(Levels), vp, P(State), vp]
+        L.imask_set_tiles.argtypes = [i32, i32, i32, P(Tiles)]
+        L.imask_get_tiles.argtypes = [i32, i32, i32, P(Tiles)]
         for name in EXPORTS:
             if getattr(L, name).restype is ctypes.c_int:  # default
                 getattr(L, name).restype = ctypes.c_int

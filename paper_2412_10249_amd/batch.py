@@ -1,11 +1,15 @@
 """Many independent reconstructions in flight at once.
 
-Each problem keeps its state and workspace on the device; problems are
-assigned round-robin to a few HIP streams (default priority), so the
-kernels of different slices overlap on the GPU - coarse-level launches of one
-slice do not fill 256 CUs by themselves.  Results are bitwise identical to
-running each problem alone: the kernels are deterministic and every problem
-has its own buffers.
+Two ways to run them:
+* `Batch` uses the library's batched steps: every kernel variant of a step
+  is one persistent launch over the work items of all problems, the sketch
+  draws happen on the device, and one captured step (a CUDA graph) is
+  replayed for every step;
+* `BatchRunner` deals the problems round-robin to a few HIP streams
+  (default priority), so one slice's launches overlap another's.
+
+Either way each problem's result is bitwise that of the problem run alone:
+the kernels are deterministic and every problem has its own buffers.
 """
 from __future__ import annotations
 
@@ -14,7 +18,7 @@ import ctypes
 import torch
 
 from . import _abi
-from .imask import Problem, lib
+from .imask import ImaskError, Problem, _stream, check, lib
 
 
 def footprint_bytes(p: Problem) -> int:
@@ -64,3 +68,62 @@ class BatchRunner:
         for s in self.streams:
             s.synchronize()
         torch.cuda.current_stream().wait_stream(self.streams[0])
+
+
+class Batch:
+    """Problems of mixed sizes advanced together by imask_batch_step until
+    each has run `budget` more epochs (or iterations)."""
+
+    def __init__(self, problems: list, budget: float, kind: int = _abi.BUDGET_EPOCHS):
+        n = len(problems)
+        if n == 0:
+            raise ImaskError("empty batch")
+        self.problems = problems
+        self.n = n
+        self.G = (_abi.Geometry * n)(*[p.geom.c() for p in problems])
+        self.L = (_abi.Levels * n)(*[p.levels.c() for p in problems])
+        self.R = (_abi.Reg * n)(*[p.reg.c() for p in problems])
+        self.P = (_abi.Params * n)(*[p.params.c() for p in problems])
+        self.B = (ctypes.c_void_p * n)(*[p.b.data_ptr() for p in problems])
+        self.S = (_abi.State * n)(*[p._cstate() for p in problems])
+        nbytes = lib().imask_batch_bytes(n, self.G, self.L)
+        if nbytes == 0:
+            raise ImaskError("imask_batch_bytes: invalid problems")
+        self.buf = torch.empty(nbytes, dtype=torch.uint8, device=problems[0].b.device)
+        steps = ctypes.c_int64()
+        check(lib().imask_batch_prepare(n, self.G, self.L, self.R, self.P, self.B, self.S, float(budget), kind,
+                                        self.buf.data_ptr(), nbytes, ctypes.byref(steps), _stream()),
+              "imask_batch_prepare")
+        self.steps = int(steps.value)
+        self.graph = None
+
+    def step(self, n_steps: int = 1) -> None:
+        """Enqueue n_steps batched steps on the current stream."""
+        check(lib().imask_batch_step(self.n, self.G, self.L, self.buf.data_ptr(), n_steps, _stream()),
+              "imask_batch_step")
+
+    def capture(self) -> None:
+        """Record one batched step in a CUDA graph (nothing runs yet)."""
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.step(1)
+        self.graph = g
+
+    def replay(self, n_steps: int = 1) -> None:
+        for _ in range(n_steps):
+            self.graph.replay()
+
+    def run(self, graph: bool = True) -> None:
+        """All the steps the budgets need, from a replayed graph or eagerly."""
+        if graph:
+            if self.graph is None:
+                self.capture()
+            self.replay(self.steps)
+        else:
+            self.step(self.steps)
+
+    def sync_state(self) -> None:
+        """Copy the device counters back into the Problems (synchronises)."""
+        check(lib().imask_batch_state(self.n, self.L, self.buf.data_ptr(), self.S, _stream()), "imask_batch_state")
+        for p, s in zip(self.problems, self.S):
+            p._absorb(s)

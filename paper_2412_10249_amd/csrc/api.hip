@@ -99,10 +99,13 @@ Layout make_layout(const imask_geometry& g)
             L.fbands[l] = 1;
             L.frows[l] = 0;
         } else {
-            fwd_bands(side(g.n, l), &L.fbands[l], &L.frows[l]);
+            fwd_bands(side(g.n, l), g.n_angles, g.n_det, &L.fbands[l], &L.frows[l]);
         }
+        // sized for the default band layout; tuned shapes use no more bands
+        int cap = L.fbands[l], rows_cap = 0;
+        if (!is_fan(g)) fwd_bands_default(side(g.n, l), &cap, &rows_cap);
         L.fpart[l] = off;
-        off = align64(off + (size_t)L.fbands[l] * m);
+        off = align64(off + (size_t)std::max(cap, L.fbands[l]) * m);
     }
     L.angtab = off;
     off = align64(off + 4 * (size_t)g.n_angles);
@@ -379,6 +382,82 @@ static void fista_betas(int J, float* beta)
     }
 }
 
+// Whether a step of this problem is described by launch records (and can
+// run batched): parallel beam, Alg. 1's parallel schedule with common draws,
+// no measurement blocks, the standard tables.
+static bool step_is_plain(const imask_geometry& g, const imask_levels& lv, const imask_params& prm,
+                          const imask_state& st)
+{
+    return !is_fan(g) && prm.schedule == IMASK_SCHEDULE_PARALLEL && prm.draw_mode == IMASK_DRAW_COMMON &&
+           block_count(lv) == 1 && !st.ztab;
+}
+
+// The launches of steps a2-a7 of one plain step for sketch k from the
+// state's parity st.cur: restriction, forward projection and dual step,
+// transposes, prolongation and primal step (the TV proxes follow it).
+// Transposes of the UNBIASED full-resolution sketch take successive rounds:
+// they share the workspace's partial images.
+static void step_records(const imask_geometry& g, const Layout& L, const imask_levels& lv, const imask_reg& reg,
+                         const imask_params& prm, const float* bdat, const imask_state& st, int k, Launches& out)
+{
+    float* W = (float*)st.work;
+    const int cur = st.cur, nxt = 1 - cur;
+    const int lmax_set = lv.log2f[lv.r - 1];
+    PrepArgs pa;
+    FwdArgs fa{};
+    forward_plan(L, lv, k, st.x[cur], W, pa, fa);
+    fwd_common(L, W, fa);
+    fa.mode = FWD_DUAL;
+    fa.y_old = st.y[cur];
+    fa.y_new = st.y[nxt];
+    fa.bdat = bdat;
+    fa.psi = st.psi;
+    fa.r = lv.r;
+    fa.kidx = k;
+    for (int j = 0; j < lv.r; ++j) fa.p[j] = (float)lv.p[j];
+    fa.sigma = (float)prm.sigma;
+    fa.inv1ps = (float)(1.0 / (1.0 + prm.sigma));
+    plan_prep(pa, out);
+    plan_fwd(fa, out);
+
+    const double tau = prm.sigma / reg.lambda;
+    const bool tv = reg.kind != IMASK_REG_TIKHONOV;
+    PrimalArgs pr{};
+    pr.n = g.n;
+    pr.T = tile_side(g.n, lmax_set);
+    pr.pyr_levels = lmax_set;
+    pr.r = lv.r;
+    pr.kidx = k;
+    pr.full_mode = lv.full_mode;
+    for (int j = 0; j < lv.r; ++j) {
+        pr.lvl[j] = lv.log2f[j];
+        pr.p[j] = (float)lv.p[j];
+        pr.pavg[j] = (float)lv.p[j];
+        pr.craw[j] = W + L.craw[lv.log2f[j]];
+    }
+    pr.phi = st.phi;
+    phi_offsets(g, lv, pr.phi_off);
+    pr.nblk = 1;
+    pr.jblk = 0;
+    pr.blk_stride = 0;
+    for (int j = 0; j < lv.r; ++j) pr.blk_stride += (long long)(g.n >> lv.log2f[j]) * (g.n >> lv.log2f[j]);
+    pr.x_old = st.x[cur];
+    pr.x_out = tv ? W + L.vbuf : st.x[nxt];
+    pr.tau = (float)tau;
+    pr.prox_scale = tv ? 1.0f : (float)(1.0 / (1.0 + tau * reg.lambda));
+    pr.xbar = nullptr;
+    pr.theta = (float)prm.theta;
+    auto raw_bp = [&](int l) { return bp_args(L, W, l, st.y[cur], W + L.craw[l], 1.0f, 0, 0); };
+    if (k > 0 || lv.r == 1) {
+        plan_bp_primal(raw_bp(lv.log2f[k]), pr, out);
+    } else {
+        plan_bp(raw_bp(0), 0, out);
+        if (lv.full_mode == IMASK_FULL_UNBIASED)
+            for (int j = 1; j < lv.r; ++j) plan_bp(raw_bp(lv.log2f[j]), j, out);
+        plan_primal(pr, out);
+    }
+}
+
 static int one_step(const imask_geometry& g, const Layout& L, const imask_levels& lv, const imask_reg& reg,
                     const imask_params& prm, const float* bdat, imask_state& st, hipStream_t s)
 {
@@ -394,6 +473,7 @@ static int one_step(const imask_geometry& g, const Layout& L, const imask_levels
     float* W = (float*)st.work;
     const int cur = st.cur, nxt = 1 - cur;
     const int lmax_set = lv.log2f[lv.r - 1];
+    const bool plain = step_is_plain(g, lv, prm, st);
     // Alg. 1 takes both steps from (x^k, y^k); ImaSk-Seq (Sec. 5) projects the
     // extrapolated point and backprojects the new dual iterate
     const bool seq = prm.schedule == IMASK_SCHEDULE_SEQUENTIAL;
@@ -438,8 +518,15 @@ static int one_step(const imask_geometry& g, const Layout& L, const imask_levels
     }
     fa.sigma = (float)prm.sigma;
     fa.inv1ps = (float)(1.0 / (1.0 + prm.sigma));
-    IMK_TRY(launch_prep(pa, s));
-    IMK_TRY(launch_fwd(fa, s));
+    if (plain) {
+        // the same launches the batched path stores
+        Launches recs;
+        step_records(g, L, lv, reg, prm, bdat, st, k, recs);
+        IMK_TRY(launch_records(recs, s));
+    } else {
+        IMK_TRY(launch_prep(pa, s));
+        IMK_TRY(launch_fwd(fa, s));
+    }
 
     // a6-a7: prolongation / compensation, primal SAGA step, phi refresh
     const double tau = prm.sigma / reg.lambda;
@@ -483,7 +570,9 @@ static int one_step(const imask_geometry& g, const Layout& L, const imask_levels
         }
         return ba;
     };
-    if (k > 0 || lv.r == 1) {
+    if (plain) {
+        // launched with the forward records above
+    } else if (k > 0 || lv.r == 1) {
         IMK_TRY(launch_bp_primal(raw_bp(lv.log2f[k]), pr, s));
     } else {
         IMK_TRY(launch_bp(raw_bp(0), s));
@@ -539,6 +628,138 @@ static int one_step(const imask_geometry& g, const Layout& L, const imask_levels
     return IMASK_OK;
 }
 
+// ---- batched steps ----
+
+constexpr int kMaxBatch = 4096;
+
+struct BatchLayout {
+    size_t prob = 0, rec = 0, nrec = 0, items = 0, off = 0, sel = 0, blobs = 0, total = 0;  // bytes
+};
+
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+static BatchLayout batch_layout(int n, int r_max, size_t nblobs)
+{
+    BatchLayout B;
+    size_t o = 0;
+    B.prob = o;
+    o = align256(o + (size_t)n * sizeof(BatchProb));
+    B.rec = o;
+    o = align256(o + (size_t)n * r_max * 2 * kMaxRec * sizeof(BatchRec));
+    B.nrec = o;
+    o = align256(o + (size_t)n * r_max * 2 * sizeof(int));
+    B.items = o;
+    o = align256(o + (size_t)n * r_max * 2 * kNumVariants * kRounds * sizeof(int));
+    B.off = o;
+    o = align256(o + (size_t)kNumVariants * kRounds * (n + 1) * sizeof(int));
+    B.sel = o;
+    o = align256(o + (size_t)n * sizeof(int));
+    B.blobs = o;
+    o = align256(o + nblobs * kLaunchArgBytes);
+    B.total = o;
+    return B;
+}
+
+static BatchView batch_view(void* batch, int n, int r_max)
+{
+    const BatchLayout B = batch_layout(n, r_max, 0);
+    unsigned char* base = (unsigned char*)batch;
+    BatchView v;
+    v.n = n;
+    v.r_max = r_max;
+    v.prob = (BatchProb*)(base + B.prob);
+    v.rec = (const BatchRec*)(base + B.rec);
+    v.nrec = (const int*)(base + B.nrec);
+    v.items = (const int*)(base + B.items);
+    v.blobs = base + B.blobs;
+    v.off = (int*)(base + B.off);
+    v.sel = (int*)(base + B.sel);
+    return v;
+}
+
+// A batched problem: parallel beam, Alg. 1's parallel schedule with common
+// draws, no measurement blocks, standard tables, the Tikhonov prior.
+static int batch_check(int n, const imask_geometry* g, const imask_levels* lv)
+{
+    if (n < 1 || n > kMaxBatch || !g || !lv) return IMASK_EINVAL;
+    for (int q = 0; q < n; ++q) {
+        if (!geometry_ok(g + q) || !levels_ok(lv + q, level_limit(g[q].n))) return IMASK_EINVAL;
+        if (is_fan(g[q]) || lv[q].n_blocks > 1) return IMASK_ENOTSUP;
+    }
+    return IMASK_OK;
+}
+
+static int batch_rmax(int n, const imask_levels* lv)
+{
+    int r = 1;
+    for (int q = 0; q < n; ++q) r = std::max(r, (int)lv[q].r);
+    return r;
+}
+
+// The records of sketch k of problem q with placeholder buffers: the launch
+// shapes (grids, LDS) depend on the geometry and level set only.
+static void shape_records(const imask_geometry& g, const imask_levels& lv, int k, Launches& out)
+{
+    const Layout L = make_layout(g);
+    imask_state st{};
+    float* fake = (float*)(uintptr_t)4096;
+    st.x[0] = st.x[1] = st.y[0] = st.y[1] = st.phi = st.psi = fake;
+    st.work = fake;
+    imask_reg reg{IMASK_REG_TIKHONOV, 1.0, 0.0, 1.0, 1};
+    imask_params prm{};
+    prm.sigma = 1.0;
+    step_records(g, L, lv, reg, prm, fake, st, k, out);
+}
+
+// Per (variant, round): the largest dynamic LDS and the sum over problems of
+// their largest item count, from the shapes alone.  The two reduce variants
+// differ only in the alignment of the caller's buffers, so both are sized
+// alike.
+struct StageShape {
+    int lds[kNumVariants][kRounds];
+    long long ub[kNumVariants][kRounds];
+    int rounds;
+};
+
+static void batch_shapes(int n, const imask_geometry* g, const imask_levels* lv, StageShape& sh, size_t* nblobs)
+{
+    std::memset(&sh, 0, sizeof(sh));
+    sh.rounds = 1;
+    size_t blobs = 0;
+    for (int q = 0; q < n; ++q) {
+        long long best[kNumVariants][kRounds] = {};
+        for (int k = 0; k < lv[q].r; ++k) {
+            Launches recs;
+            shape_records(g[q], lv[q], k, recs);
+            blobs += 2 * recs.size();
+            long long it[kNumVariants][kRounds] = {};
+            for (const Launch& L : recs) {
+                it[L.variant][L.round] += (long long)L.gx * L.gy * L.gz;
+                sh.lds[L.variant][L.round] = std::max(sh.lds[L.variant][L.round], L.lds);
+                sh.rounds = std::max(sh.rounds, L.round + 1);
+            }
+            for (int v = 0; v < kNumVariants; ++v)
+                for (int j = 0; j < kRounds; ++j) best[v][j] = std::max(best[v][j], it[v][j]);
+        }
+        for (int j = 0; j < kRounds; ++j) {
+            const long long red = std::max(best[V_RED4][j], best[V_RED1][j]);
+            best[V_RED4][j] = best[V_RED1][j] = red;
+        }
+        for (int v = 0; v < kNumVariants; ++v)
+            for (int j = 0; j < kRounds; ++j) sh.ub[v][j] += best[v][j];
+    }
+    if (nblobs) *nblobs = blobs;
+}
+
+// Resident workgroups of a batched variant per CU (LDS and threads).
+static int batch_wgs_per_cu(int v, int lds)
+{
+    const size_t need = (size_t)lds + variant_static_lds(v);
+    const int by_lds = (int)std::max<size_t>(1, (size_t)(160 * 1024) / std::max<size_t>(need, 1));
+    const int by_threads = std::max(1, 2048 / variant_threads(v));
+    return std::max(1, std::min(by_lds, by_threads));
+}
+
 // ---- the workspace-free transpose (imask_backproject_noalloc) ----
 
 // Device memory of imask_backproject_noalloc: one copy per GPU, held until
@@ -587,6 +808,10 @@ static Layout transpose_layout(const imask_geometry& g)
 }  // namespace imk
 
 using namespace imk;
+
+static int check_problem(const imask_geometry* g, const imask_levels* lv, const imask_reg* reg,
+                         const imask_params* prm, const float* b, const imask_state* s);
+
 
 extern "C" {
 
@@ -748,6 +973,184 @@ int imask_backproject_noalloc(const imask_geometry* g, int32_t log2f, const floa
     // array's previous contents never matter and nothing is cleared
     IMK_TRY(launch_consts(*g, L, W, s));
     return backproject_raw(L, W, log2f, sino, x_full, 1.0f / (float)(1 << (2 * log2f)), 0, 1, s);
+}
+
+int imask_set_tiles(int32_t nl, int32_t n_angles, int32_t n_det, const imask_tiles* t)
+{
+    if (nl < 1 || nl > 16384 || n_angles < 1 || n_angles > 65536 || n_det < 1 || n_det > 8192) return IMASK_EINVAL;
+    if (!t) {
+        set_tiles(nl, n_angles, n_det, nullptr);
+        return IMASK_OK;
+    }
+    Tiles tt;
+    tt.bp_rows = t->bp_rows;
+    tt.bp_waves = t->bp_waves;
+    tt.bp_wg = t->bp_wg;
+    tt.fwd_lds_kb = t->fwd_lds_kb;
+    return set_tiles(nl, n_angles, n_det, &tt) ? IMASK_OK : IMASK_EINVAL;
+}
+
+int imask_get_tiles(int32_t nl, int32_t n_angles, int32_t n_det, imask_tiles* out)
+{
+    if (!out) return IMASK_EINVAL;
+    const Tiles t = tiles_for(nl, n_angles, n_det);
+    out->bp_rows = t.bp_rows;
+    out->bp_waves = t.bp_waves;
+    out->bp_wg = t.bp_wg;
+    out->fwd_lds_kb = t.fwd_lds_kb;
+    return IMASK_OK;
+}
+
+size_t imask_batch_bytes(int32_t n_problems, const imask_geometry* g, const imask_levels* lv)
+{
+    if (batch_check(n_problems, g, lv) != IMASK_OK) return 0;
+    StageShape sh;
+    size_t nblobs = 0;
+    batch_shapes(n_problems, g, lv, sh, &nblobs);
+    return batch_layout(n_problems, batch_rmax(n_problems, lv), nblobs).total;
+}
+
+int imask_batch_prepare(int32_t n_problems, const imask_geometry* g, const imask_levels* lv, const imask_reg* reg,
+                        const imask_params* prm, const float* const* b, const imask_state* s, double budget,
+                        int32_t budget_kind, void* batch, size_t batch_bytes, int64_t* steps_out, void* stream)
+{
+    if (int rc = batch_check(n_problems, g, lv)) return rc;
+    if (!reg || !prm || !b || !s || !batch || !(budget >= 0.0) || !std::isfinite(budget) ||
+        (budget_kind != IMASK_BUDGET_ITERS && budget_kind != IMASK_BUDGET_EPOCHS))
+        return IMASK_EINVAL;
+    for (int q = 0; q < n_problems; ++q) {
+        if (int rc = check_problem(g + q, lv + q, reg + q, prm + q, b[q], s + q)) return rc;
+        if (!step_is_plain(g[q], lv[q], prm[q], s[q]) || reg[q].kind != IMASK_REG_TIKHONOV) return IMASK_ENOTSUP;
+    }
+    const int n = n_problems, r_max = batch_rmax(n, lv);
+    StageShape sh;
+    size_t nblobs = 0;
+    batch_shapes(n, g, lv, sh, &nblobs);
+    const BatchLayout B = batch_layout(n, r_max, nblobs);
+    if (batch_bytes < B.total) return IMASK_ESIZE;
+    for (int v = 0; v < kNumVariants; ++v)
+        for (int j = 0; j < kRounds; ++j)
+            if (sh.ub[v][j] > 0 && (size_t)sh.lds[v][j] + variant_static_lds(v) > 160 * 1024) return IMASK_ENOTSUP;
+    std::vector<unsigned char> img(B.total, 0);
+    BatchProb* probs = (BatchProb*)(img.data() + B.prob);
+    BatchRec* recs = (BatchRec*)(img.data() + B.rec);
+    int* nrec = (int*)(img.data() + B.nrec);
+    int* items = (int*)(img.data() + B.items);
+    unsigned char* blobs = img.data() + B.blobs;
+    int64_t steps = 0;
+    size_t blob = 0;
+    for (int q = 0; q < n; ++q) {
+        const Layout L = make_layout(g[q]);
+        BatchProb& pb = probs[q];
+        uint64_t thr[IMASK_MAX_LEVELS];
+        draw_thresholds(lv[q], thr);
+        pb.stream_state = mix_at(prm[q].seed, prm[q].stream_id);
+        pb.k = s[q].k;
+        pb.epochs = s[q].epochs;
+        pb.cur = s[q].cur;
+        pb.r = lv[q].r;
+        for (int j = 0; j < lv[q].r; ++j) {
+            pb.thr[j] = thr[j];
+            pb.cost[j] = sketch_cost(lv[q], j);
+        }
+        // the problem's last draw: the budget evaluated from the host draws
+        uint64_t kk = s[q].k;
+        if (budget_kind == IMASK_BUDGET_ITERS) {
+            kk += (uint64_t)budget;
+        } else {
+            double e = 0.0;
+            while (e < budget) e += sketch_cost(lv[q], draw_one(prm[q], thr, kk++));
+        }
+        pb.k_stop = kk;
+        steps = std::max<int64_t>(steps, (int64_t)(kk - s[q].k));
+        for (int k = 0; k < lv[q].r; ++k)
+            for (int c = 0; c < 2; ++c) {
+                imask_state st = s[q];
+                st.cur = c;
+                Launches rl;
+                step_records(g[q], L, lv[q], reg[q], prm[q], b[q], st, k, rl);
+                if ((int)rl.size() > kMaxRec) return IMASK_ENOTSUP;
+                const size_t slot = ((size_t)q * r_max + k) * 2 + c;
+                nrec[slot] = (int)rl.size();
+                for (size_t t = 0; t < rl.size(); ++t) {
+                    const Launch& La = rl[t];
+                    BatchRec& R = recs[slot * kMaxRec + t];
+                    R.variant = La.variant;
+                    R.round = La.round;
+                    R.blob = (int)blob;
+                    R.gx = (int)La.gx;
+                    R.gy = (int)La.gy;
+                    R.gz = (int)La.gz;
+                    R.items = (int)(La.gx * La.gy * La.gz);
+                    R.lds = La.lds;
+                    std::memcpy(blobs + blob * kLaunchArgBytes, La.args, kLaunchArgBytes);
+                    ++blob;
+                    items[(slot * kNumVariants + La.variant) * kRounds + La.round] += R.items;
+                }
+            }
+    }
+    if (blob > nblobs) return IMASK_ESIZE;
+    hipStream_t st = (hipStream_t)stream;
+    for (int v = 0; v < kNumVariants; ++v)
+        for (int j = 0; j < sh.rounds; ++j)
+            if (sh.ub[v][j] > 0) IMK_TRY(batch_allow_lds(v, sh.lds[v][j]));
+    if (hipMemcpyAsync(batch, img.data(), B.total, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)  // img is freed on return
+        return IMASK_EHIP;
+    if (steps_out) *steps_out = steps;
+    return IMASK_OK;
+}
+
+int imask_batch_step(int32_t n_problems, const imask_geometry* g, const imask_levels* lv, void* batch,
+                     int32_t n_steps, void* stream)
+{
+    if (int rc = batch_check(n_problems, g, lv)) return rc;
+    if (!batch || n_steps < 0) return IMASK_EINVAL;
+    const int n = n_problems;
+    StageShape sh;
+    batch_shapes(n, g, lv, sh, nullptr);
+    const BatchView bv = batch_view(batch, n, batch_rmax(n, lv));
+    hipStream_t s = (hipStream_t)stream;
+    auto stage = [&](int v, int j) -> int {
+        if (sh.ub[v][j] <= 0) return IMASK_OK;
+        const long long cap = 256LL * batch_wgs_per_cu(v, sh.lds[v][j]);
+        const unsigned grid = (unsigned)std::max(1LL, std::min(sh.ub[v][j], cap));
+        IMK_TRY(launch_batch_stage(v, j, bv, grid, sh.lds[v][j], s));
+        return IMASK_OK;
+    };
+    static const int head[] = {V_PREP, V_FWD_BAND, V_FWD_DIRECT, V_RED4, V_RED1};
+    static const int bps[] = {V_BP28, V_BP44, V_BP14, V_BP12, V_SUM4, V_SUM1};
+    static const int tail[] = {V_SUMP4, V_SUMP1, V_PRIMAL};
+    for (int it = 0; it < n_steps; ++it) {
+        IMK_TRY(launch_batch_plan(bv, s));
+        for (int v : head)
+            if (int rc = stage(v, 0)) return rc;
+        for (int j = 0; j < sh.rounds; ++j)
+            for (int v : bps)
+                if (int rc = stage(v, j)) return rc;
+        for (int v : tail)
+            if (int rc = stage(v, 0)) return rc;
+        IMK_TRY(launch_batch_advance(bv, s));
+    }
+    return IMASK_OK;
+}
+
+int imask_batch_state(int32_t n_problems, const imask_levels* lv, const void* batch, imask_state* s, void* stream)
+{
+    if (n_problems < 1 || n_problems > kMaxBatch || !lv || !batch || !s) return IMASK_EINVAL;
+    std::vector<BatchProb> probs(n_problems);
+    const BatchView bv = batch_view(const_cast<void*>(batch), n_problems, batch_rmax(n_problems, lv));
+    hipStream_t st = (hipStream_t)stream;
+    if (hipMemcpyAsync(probs.data(), bv.prob, sizeof(BatchProb) * probs.size(), hipMemcpyDeviceToHost, st) !=
+            hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return IMASK_EHIP;
+    for (int q = 0; q < n_problems; ++q) {
+        s[q].k = probs[q].k;
+        s[q].cur = probs[q].cur;
+        s[q].epochs = probs[q].epochs;
+    }
+    return IMASK_OK;
 }
 
 int imask_resample(int32_t n, int32_t log2f, int32_t mode, const imask_levels* lv, const float* in, float* out,

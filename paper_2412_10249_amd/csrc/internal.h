@@ -6,6 +6,8 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <cstring>
+#include <vector>
 
 #include "imask.h"
 
@@ -325,7 +327,20 @@ struct TvArgs {
 
 // Forward band layout of a level with nl pixels per side (LDS-resident
 // bands of rows); rows == 0 selects the direct (global-memory) kernel.
-void fwd_bands(int nl, int* bands, int* rows);
+// fwd_bands_default is the layout the workspace is sized for; fwd_bands
+// the one the launches use (the tuned LDS budget, never more bands).
+void fwd_bands_default(int nl, int* bands, int* rows);
+void fwd_bands(int nl, int na, int nd, int* bands, int* rows);
+
+// Tunable launch shapes of the levels of one grid side and detector
+// (imask_set_tiles); zero fields select the defaults.
+struct Tiles {
+    int bp_rows = 0, bp_waves = 0;  // transpose tile: rows per wavefront, wavefronts
+    int bp_wg = 0;                  // transpose workgroup target
+    int fwd_lds_kb = 0;             // forward band LDS budget (KB)
+};
+Tiles tiles_for(int nl, int na, int nd);
+bool set_tiles(int nl, int na, int nd, const Tiles* t);  // null resets; false: unsupported shape
 
 // ---- launchers (return hipError_t of the launch) ----
 hipError_t launch_consts(const imask_geometry& g, const Layout& L, float* work, hipStream_t s);
@@ -368,5 +383,120 @@ hipError_t launch_dot(const float* a, const float* b, size_t n, double* part, do
 
 // pyramid tile side used by prep/primal for a set of levels up to lmax
 int tile_side(int n, int lmax);
+
+// ---- the launches of a step as data ----
+//
+// The parallel-beam launchers describe each kernel launch as a record
+// (kernel variant, grid, block, dynamic LDS and the argument block) and then
+// launch the records; the batched path stores the same records for many
+// problems on the device and runs each variant once for all of them, so a
+// problem gets the same launches, shapes and arguments either way.
+enum Variant {
+    V_PREP = 0,
+    V_FWD_BAND,
+    V_FWD_DIRECT,
+    V_RED4,
+    V_RED1,
+    V_BP28,  // k_bp_own<2, 8>
+    V_BP44,  // k_bp_own<4, 4>
+    V_BP14,  // k_bp_own<1, 4>
+    V_BP12,  // k_bp_own<1, 2>
+    V_BP24,  // k_bp_own<2, 4>
+    V_SUM4,
+    V_SUM1,
+    V_SUMP4,
+    V_SUMP1,
+    V_PRIMAL,
+    kNumVariants
+};
+constexpr int kLaunchArgBytes = 640;
+
+// k_bp_sum / k_bp_sum_primal argument blocks.
+struct SumArgs {
+    BpOwnArgs a;
+    float* tmp;
+    int S;
+};
+struct SumPrimalArgs {
+    BpOwnArgs a;
+    PrimalArgs p;
+    int S;
+};
+
+struct Launch {
+    int variant = 0;
+    int round = 0;  // transposes of a step share the partial images: round j runs after round j-1's sum
+    unsigned gx = 1, gy = 1, gz = 1;
+    int block = 0, lds = 0;
+    alignas(16) unsigned char args[kLaunchArgBytes];
+    template <class T>
+    void set(const T& t)
+    {
+        static_assert(sizeof(T) <= kLaunchArgBytes, "argument block too large");
+        std::memcpy(args, &t, sizeof(T));
+    }
+    template <class T>
+    const T& get() const
+    {
+        return *reinterpret_cast<const T*>(args);
+    }
+};
+using Launches = std::vector<Launch>;
+
+// Records of the parallel-beam launchers (fan-beam geometries are not
+// described this way).
+void plan_prep(const PrepArgs& a, Launches& out);
+void plan_fwd_terms(const FwdArgs& a, Launches& out);
+void plan_fwd(const FwdArgs& a, Launches& out);                 // terms + reduce / dual step
+void plan_bp_main(const BpArgs& ba, int round, Launches& out, BpOwnArgs* used);
+void plan_bp(const BpArgs& ba, int round, Launches& out);       // transpose + ordered sum (no prolongation)
+void plan_bp_primal(const BpArgs& ba, const PrimalArgs& pr, Launches& out);
+void plan_primal(const PrimalArgs& a, Launches& out);
+hipError_t launch_records(const Launches& recs, hipStream_t s);
+
+// ---- batched steps (many problems, one launch per kernel variant) ----
+
+constexpr int kMaxRec = 32;  // launches of one step of one problem
+constexpr int kRounds = IMASK_MAX_LEVELS;
+
+// Per-problem counters, advanced on the device.  The sketch index of step k
+// is drawn on the device from the same SplitMix64 stream as the host draw.
+struct BatchProb {
+    unsigned long long stream_state;  // SplitMix64 state of the problem's draw stream
+    unsigned long long k;             // next draw
+    unsigned long long k_stop;        // the problem idles from this draw on
+    double epochs;
+    int cur;
+    int r;
+    unsigned long long thr[IMASK_MAX_LEVELS];  // draw thresholds
+    double cost[IMASK_MAX_LEVELS];             // epochs of each sketch
+};
+
+// One launch of one problem's step: which variant and round, its argument
+// block and its grid (items = gx gy gz workgroups).
+struct BatchRec {
+    int variant, round, blob;
+    int gx, gy, gz, items;
+    int lds;  // dynamic LDS the launch needs
+};
+
+// Device pointers of a batch buffer.
+struct BatchView {
+    int n, r_max;
+    BatchProb* prob;         // n
+    const BatchRec* rec;     // [n][r_max][2][kMaxRec]
+    const int* nrec;         // [n][r_max][2]
+    const int* items;        // [n][r_max][2][kNumVariants][kRounds]
+    const unsigned char* blobs;  // argument blocks, kLaunchArgBytes each
+    int* off;                // [kNumVariants][kRounds][n + 1]: per-step item offsets
+    int* sel;                // [n]: this step's (sketch index, parity) slot, -1 when idle
+};
+
+int variant_threads(int v);
+size_t variant_static_lds(int v);
+hipError_t batch_allow_lds(int v, int lds);
+hipError_t launch_batch_plan(const BatchView& bv, hipStream_t s);
+hipError_t launch_batch_stage(int v, int round, const BatchView& bv, unsigned grid, int lds, hipStream_t s);
+hipError_t launch_batch_advance(const BatchView& bv, hipStream_t s);
 
 }  // namespace imk

@@ -17,6 +17,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 #include "internal.h"
 
@@ -43,6 +44,18 @@ __device__ __forceinline__ float tap_weight(long long u) { return (float)(unsign
 // execute in program order, so keeping the compiler from moving them across
 // is all that is needed.
 #define IMK_LDS_ORDER() asm volatile("" ::: "memory")
+
+// The block a kernel body works on: its grid coordinates and the grid's
+// x extent (for grid-stride loops).  A kernel passes its own blockIdx; the
+// batched kernels pass a block of one problem's launch taken from a work
+// list, so the same body serves both.
+struct Blk {
+    int x, y, z, gx;
+};
+__device__ __forceinline__ Blk this_block()
+{
+    return Blk{(int)blockIdx.x, (int)blockIdx.y, (int)blockIdx.z, (int)gridDim.x};
+}
 
 // th / rows: listed angles (radians) and their stepping flags, or null for
 // a*pi/na; side = 2E, the side of the image square.
@@ -135,11 +148,10 @@ __device__ __forceinline__ void load_tile(float* pyr, const float* x, int n, int
 
 // Restricts (block mean at level l) or compensates (S_r at level 0) one
 // T x T tile of x into padded row / transposed layouts for the projector.
-__global__ void __launch_bounds__(256) k_prep(PrepArgs a)
+__device__ __forceinline__ void prep_body(const PrepArgs& a, const Blk& bk, float* pyr)
 {
-    extern __shared__ float pyr[];
     const int tiles = a.n / a.T;
-    const int ty = blockIdx.x / tiles, tx = blockIdx.x - ty * tiles;
+    const int ty = bk.x / tiles, tx = bk.x - ty * tiles;
     if (a.snap && a.snap_lvl == 0) {
         // compact tables, full-resolution sketch: restrict x - z_0, then z_0 <- x
         for (int q = threadIdx.x; q < a.T * a.T; q += blockDim.x) {
@@ -184,6 +196,12 @@ __global__ void __launch_bounds__(256) k_prep(PrepArgs a)
             if (po.dstT) po.dstT[(size_t)(ox + j) * P + oy + i + sh] = v;
         }
     }
+}
+
+__global__ void __launch_bounds__(256) k_prep(PrepArgs a)
+{
+    extern __shared__ float pyr[];
+    prep_body(a, this_block(), pyr);
 }
 
 // ---------------------------------------------------------- Joseph forward
@@ -301,13 +319,12 @@ __device__ __forceinline__ float band_sum(const float* band, long long U, long l
 // image (columns of it for column-stepping angles) into LDS and sums, for
 // every ray of its angle group, the samples falling in the band.  The ray's
 // partial sum goes to part[band][a][b]; k_fwd_reduce adds the bands in order.
-__global__ void __launch_bounds__(1024) k_fwd_band(FwdBandArgs a)
+__device__ __forceinline__ void fwd_band_body(const FwdBandArgs& a, const Blk& bk, float* band)
 {
-    extern __shared__ float band[];
     const int nl = a.n >> a.lvl;
     const int P = nl + kPad;
-    const int bi = blockIdx.x;    // band
-    const int gidx = blockIdx.y;  // angle group (row-stepping groups first)
+    const int bi = bk.x;    // band
+    const int gidx = bk.y;  // angle group (row-stepping groups first)
     const int pass = gidx < a.groups_row ? 0 : 1;
     const int g = pass == 0 ? gidx : gidx - a.groups_row;
     const int npass = pass == 0 ? a.split.nrow : a.split.ncol;
@@ -352,13 +369,19 @@ __global__ void __launch_bounds__(1024) k_fwd_band(FwdBandArgs a)
     }
 }
 
+__global__ void __launch_bounds__(1024) k_fwd_band(FwdBandArgs a)
+{
+    extern __shared__ float band[];
+    fwd_band_body(a, this_block(), band);
+}
+
 // Direct forward for levels too large for LDS bands: one thread per ray
 // reading the padded image from global memory; writes a single band.
-__global__ void __launch_bounds__(256) k_fwd_direct(FwdBandArgs a)
+__device__ __forceinline__ void fwd_direct_body(const FwdBandArgs& a, const Blk& bk)
 {
     const int lane = threadIdx.x & 63;
     const int wpa = (a.nd + 63) >> 6;
-    const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+    const int wave = __builtin_amdgcn_readfirstlane(bk.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
     const int ang = __builtin_amdgcn_readfirstlane(wave / wpa);
     if (ang >= a.na) return;
     const int b = (wave - ang * wpa) * 64 + lane;
@@ -376,6 +399,8 @@ __global__ void __launch_bounds__(256) k_fwd_direct(FwdBandArgs a)
     }
     a.part[(size_t)ang * a.nd + b] = kc.w * acc;
 }
+
+__global__ void __launch_bounds__(256) k_fwd_direct(FwdBandArgs a) { fwd_direct_body(a, this_block()); }
 
 // ------------------------------------------------------------ fan beam
 
@@ -748,10 +773,10 @@ __global__ void __launch_bounds__(kFanMaxWaves * 64) k_bp_fan_scatter(BpOwnArgs 
 // accumulates, or applies the dual SAGA step of Alg. 1:
 // zeta = psi_new - psi_k + sum_j p_j psi_j (old tables),
 // y+ = (y + sigma zeta - sigma b)/(1 + sigma), psi_k <- psi_new.
-__global__ void __launch_bounds__(256) k_fwd_reduce(FwdArgs a)
+__device__ __forceinline__ void fwd_reduce_body(const FwdArgs& a, const Blk& bk)
 {
     const size_t m = (size_t)a.na * a.nd;
-    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (size_t)gridDim.x * blockDim.x) {
+    for (size_t e = (size_t)bk.x * blockDim.x + threadIdx.x; e < m; e += (size_t)bk.gx * blockDim.x) {
         float total = 0.0f;
         for (int t = 0; t < a.nterms; ++t) {
             const float* pp = a.term[t].part + e;
@@ -782,6 +807,8 @@ __global__ void __launch_bounds__(256) k_fwd_reduce(FwdArgs a)
     }
 }
 
+__global__ void __launch_bounds__(256) k_fwd_reduce(FwdArgs a) { fwd_reduce_body(a, this_block()); }
+
 // k_fwd_reduce on four consecutive elements per thread with 16-byte loads
 // and stores (sinogram size a multiple of 4): the same arithmetic per element.
 __device__ __forceinline__ void ld4(const float* p, float* v)
@@ -797,10 +824,10 @@ __device__ __forceinline__ void st4(float* p, const float* v)
     *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
 }
 
-__global__ void __launch_bounds__(256) k_fwd_reduce4(FwdArgs a)
+__device__ __forceinline__ void fwd_reduce4_body(const FwdArgs& a, const Blk& bk)
 {
     const size_t m = (size_t)a.na * a.nd;
-    for (size_t e = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) * 4; e < m; e += (size_t)gridDim.x * blockDim.x * 4) {
+    for (size_t e = ((size_t)bk.x * blockDim.x + threadIdx.x) * 4; e < m; e += (size_t)bk.gx * blockDim.x * 4) {
         float total[4] = {0.0f, 0.0f, 0.0f, 0.0f}, v[4];
         for (int t = 0; t < a.nterms; ++t) {
             const float* pp = a.term[t].part + e;
@@ -855,6 +882,8 @@ __global__ void __launch_bounds__(256) k_fwd_reduce4(FwdArgs a)
         }
     }
 }
+
+__global__ void __launch_bounds__(256) k_fwd_reduce4(FwdArgs a) { fwd_reduce4_body(a, this_block()); }
 
 // ------------------------------------------------------ exact transpose
 
@@ -1048,18 +1077,17 @@ static_assert(sizeof(BpAngle) == 48, "BpAngle layout");
 constexpr int kBpAngTab = 128;  // angles a workgroup tabulates at once
 
 template <int R, int W>
-__global__ void __launch_bounds__(64 * W) k_bp_own(BpOwnArgs a)
+__device__ __forceinline__ void bp_own_body(const BpOwnArgs& a, const Blk& bk, float* smem)
 {
     constexpr int kBpRowsPerWave = R;
     constexpr int kBpRowsPerWg = BpShape<R, W>::rows;
     constexpr int kBpPad = BpShape<R, W>::pad;
-    extern __shared__ float smem[];
     const int nl = a.n >> a.lvl;
     const int S = nl + 2 * kBpPad;
     float* acc = smem;                                     // kBpRowsPerWg x S
     BpAngle* tab = reinterpret_cast<BpAngle*>(smem + ((kBpRowsPerWg * S + 3) & ~3));
-    const int bi = blockIdx.x;    // band of kBpRowsPerWg rows
-    const int gidx = blockIdx.y;  // pass * G + angle group
+    const int bi = bk.x;    // band of kBpRowsPerWg rows
+    const int gidx = bk.y;  // pass * G + angle group
     const int pass = gidx / a.G;
     const int g = gidx - pass * a.G;
     const int npass = pass == 0 ? a.split.nrow : a.split.ncol;
@@ -1170,6 +1198,13 @@ __global__ void __launch_bounds__(64 * W) k_bp_own(BpOwnArgs a)
     }
 }
 
+template <int R, int W>
+__global__ void __launch_bounds__(64 * W) k_bp_own(BpOwnArgs a)
+{
+    extern __shared__ float smem[];
+    bp_own_body<R, W>(a, this_block(), smem);
+}
+
 // c = sum over the nq partial images in a fixed order; coef * c is stored coarse
 // (or into `tmp` for a later prolongation).  The nq partials are cut into S
 // consecutive slices (S a power of two, chosen from the image size so that
@@ -1205,7 +1240,7 @@ __device__ __forceinline__ void slice_sum(const BpOwnArgs& a, size_t d, size_t e
 // Each thread sums its slice for V consecutive cells (V = 4 needs d a
 // multiple of 4); the slices are then added one cell per thread.
 template <int V>
-__global__ void __launch_bounds__(1024) k_bp_sum(BpOwnArgs a, float* tmp, int S)
+__device__ __forceinline__ void bp_sum_body(const BpOwnArgs& a, float* tmp, int S, const Blk& bk)
 {
     __shared__ float red[1024 * V];
     const int nl = a.n >> a.lvl;
@@ -1213,14 +1248,14 @@ __global__ void __launch_bounds__(1024) k_bp_sum(BpOwnArgs a, float* tmp, int S)
     const int per = 1024 / S;  // threads per slice
     const int sl = threadIdx.x / per;
     const int pi = threadIdx.x - sl * per;
-    const size_t e = ((size_t)blockIdx.x * per + pi) * V;
+    const size_t e = ((size_t)bk.x * per + pi) * V;
     float sum[V];
     slice_sum<V>(a, d, e, sl * a.nq / S, (sl + 1) * a.nq / S, sum);
 #pragma unroll
     for (int c = 0; c < V; ++c) red[threadIdx.x * V + c] = sum[c];
     __syncthreads();
     // slice sums in slice order, one cell per thread
-    const size_t e0 = (size_t)blockIdx.x * per * V;
+    const size_t e0 = (size_t)bk.x * per * V;
     const int ncell = (int)min((size_t)per * V, d - min(d, e0));
     for (int t = threadIdx.x; t < ncell; t += blockDim.x) {
         float cc = red[t];
@@ -1229,6 +1264,12 @@ __global__ void __launch_bounds__(1024) k_bp_sum(BpOwnArgs a, float* tmp, int S)
         float* o = (a.prolong ? tmp : a.out) + e0 + t;
         *o = a.accumulate && !a.prolong ? *o + v : v;
     }
+}
+
+template <int V>
+__global__ void __launch_bounds__(1024) k_bp_sum(BpOwnArgs a, float* tmp, int S)
+{
+    bp_sum_body<V>(a, tmp, S, this_block());
 }
 
 // The ordered partial sum fused with the primal step of Alg. 1, for steps
@@ -1241,7 +1282,7 @@ __global__ void __launch_bounds__(1024) k_bp_sum(BpOwnArgs a, float* tmp, int S)
 // xbar).  A cell's pixels and its phi_k entry belong to one workgroup, so
 // the old table values it reads are never overwritten by another.
 template <int V>
-__global__ void __launch_bounds__(1024) k_bp_sum_primal(BpOwnArgs a, int S, PrimalArgs p)
+__device__ __forceinline__ void bp_sum_primal_body(const BpOwnArgs& a, int S, const PrimalArgs& p, const Blk& bk)
 {
     __shared__ float red[1024 * V];
     __shared__ float gsh[1024 * V], own[1024 * V];
@@ -1251,7 +1292,7 @@ __global__ void __launch_bounds__(1024) k_bp_sum_primal(BpOwnArgs a, int S, Prim
     const int per = 1024 / S;  // threads per slice
     const int sl = threadIdx.x / per;
     const int pi = threadIdx.x - sl * per;
-    const size_t e0 = (size_t)blockIdx.x * per * V;  // the workgroup's first cell
+    const size_t e0 = (size_t)bk.x * per * V;  // the workgroup's first cell
     const size_t e = e0 + (size_t)pi * V;
     float sum[V];
     slice_sum<V>(a, d, e, sl * a.nq / S, (sl + 1) * a.nq / S, sum);
@@ -1303,6 +1344,12 @@ __global__ void __launch_bounds__(1024) k_bp_sum_primal(BpOwnArgs a, int S, Prim
     }
 }
 
+template <int V>
+__global__ void __launch_bounds__(1024) k_bp_sum_primal(BpOwnArgs a, int S, PrimalArgs p)
+{
+    bp_sum_primal_body<V>(a, S, p, this_block());
+}
+
 __global__ void k_prolong_acc(const float* in, float* out, int n, int lvl, int accumulate)
 {
     const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1318,11 +1365,10 @@ __global__ void k_prolong_acc(const float* in, float* out, int n, int lvl, int a
 // the SAGA estimate xi with the old tables, v = x - tau xi, and writes
 // prox_scale * v; then refreshes table k.  One workgroup per T x T tile
 // (T a multiple of every level's block, so coarse cells never straddle).
-__global__ void __launch_bounds__(256) k_primal(PrimalArgs a)
+__device__ __forceinline__ void primal_body(const PrimalArgs& a, const Blk& bk, float* pyr)
 {
-    extern __shared__ float pyr[];
     const int tiles = a.n / a.T;
-    const int ty = blockIdx.x / tiles, tx = blockIdx.x - ty * tiles;
+    const int ty = bk.x / tiles, tx = bk.x - ty * tiles;
     const bool paper_full = (a.kidx == 0 && a.full_mode == IMASK_FULL_PAPER && a.r > 1);
     if (paper_full) {
         load_tile(pyr, a.craw[0], a.n, a.T, ty, tx);
@@ -1385,6 +1431,12 @@ __global__ void __launch_bounds__(256) k_primal(PrimalArgs a)
             a.phi[a.jblk * a.blk_stride + a.phi_off[a.kidx] + c] = a.craw[a.kidx][c] * s;
         }
     }
+}
+
+__global__ void __launch_bounds__(256) k_primal(PrimalArgs a)
+{
+    extern __shared__ float pyr[];
+    primal_body(a, this_block(), pyr);
 }
 
 // ------------------------------------------------------------ smoothed TV
@@ -1758,9 +1810,21 @@ static size_t pyramid_bytes(int T, int levels)
 
 hipError_t launch_prep(const PrepArgs& a, hipStream_t s)
 {
+    Launches r;
+    plan_prep(a, r);
+    return launch_records(r, s);
+}
+
+void plan_prep(const PrepArgs& a, Launches& out)
+{
+    Launch L;
+    L.variant = V_PREP;
     const int tiles = a.n / a.T;
-    hipLaunchKernelGGL(k_prep, dim3(tiles * tiles), dim3(256), pyramid_bytes(a.T, a.pyr_levels), s, a);
-    return hipGetLastError();
+    L.gx = (unsigned)(tiles * tiles);
+    L.block = 256;
+    L.lds = (int)pyramid_bytes(a.T, a.pyr_levels);
+    L.set(a);
+    out.push_back(L);
 }
 
 // LDS budget of a forward band: up to 156 KB (one workgroup per CU, 7 bands
@@ -1770,17 +1834,64 @@ hipError_t launch_prep(const PrepArgs& a, hipStream_t s)
 // workgroups.
 static int fwd_lds_bytes(int nl) { return (nl >= 512 ? 156 : nl >= 256 ? 78 : 64) * 1024; }
 
-void fwd_bands(int nl, int* bands, int* rows)
+// The tuned shapes, per (level grid side, angles, bins); looked up on every
+// launch, set rarely (imask_set_tiles).
+struct TileEntry {
+    int nl, na, nd;
+    Tiles t;
+};
+static std::mutex g_tiles_mu;
+static std::vector<TileEntry> g_tiles;
+
+Tiles tiles_for(int nl, int na, int nd)
+{
+    std::lock_guard<std::mutex> lock(g_tiles_mu);
+    for (const TileEntry& e : g_tiles)
+        if (e.nl == nl && e.na == na && e.nd == nd) return e.t;
+    return Tiles{};
+}
+
+bool set_tiles(int nl, int na, int nd, const Tiles* t)
+{
+    if (t) {
+        const int shape = t->bp_rows * 16 + t->bp_waves;
+        const bool shape_ok = shape == 0 || shape == 2 * 16 + 8 || shape == 4 * 16 + 4 || shape == 2 * 16 + 4 ||
+                              shape == 1 * 16 + 4;
+        if (!shape_ok || t->bp_wg < 0 || t->bp_wg > 16384 || (t->bp_wg > 0 && t->bp_wg < 64) || t->fwd_lds_kb < 0 ||
+            t->fwd_lds_kb > 156)
+            return false;
+    }
+    std::lock_guard<std::mutex> lock(g_tiles_mu);
+    for (size_t q = 0; q < g_tiles.size(); ++q)
+        if (g_tiles[q].nl == nl && g_tiles[q].na == na && g_tiles[q].nd == nd) {
+            g_tiles.erase(g_tiles.begin() + q);
+            break;
+        }
+    if (t && (t->bp_rows || t->bp_waves || t->bp_wg || t->fwd_lds_kb)) g_tiles.push_back(TileEntry{nl, na, nd, *t});
+    return true;
+}
+
+static void bands_for_budget(int nl, int bytes, int* bands, int* rows)
 {
     if (nl > 512) {  // rows of more than 2 KB: too few per band, use the direct kernel
         *bands = 1;
         *rows = 0;
         return;
     }
-    const int maxr = fwd_lds_bytes(nl) / (int)(sizeof(float) * (nl + kPad));
+    const int maxr = bytes / (int)(sizeof(float) * (nl + kPad));
     const int nb = (nl + maxr - 1) / maxr;
     *bands = nb;
     *rows = (nl + nb - 1) / nb;
+}
+
+void fwd_bands_default(int nl, int* bands, int* rows) { bands_for_budget(nl, fwd_lds_bytes(nl), bands, rows); }
+
+void fwd_bands(int nl, int na, int nd, int* bands, int* rows)
+{
+    const Tiles t = tiles_for(nl, na, nd);
+    int bytes = fwd_lds_bytes(nl);
+    if (t.fwd_lds_kb > 0) bytes = std::max(bytes, std::min(t.fwd_lds_kb, 156) * 1024);
+    bands_for_budget(nl, bytes, bands, rows);
 }
 
 static hipError_t allow_lds(const void* fn, int bytes)
@@ -1789,7 +1900,7 @@ static hipError_t allow_lds(const void* fn, int bytes)
     return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
-hipError_t launch_fwd_terms(const FwdArgs& a, hipStream_t s)
+void plan_fwd_terms(const FwdArgs& a, Launches& out)
 {
     const AngleSplit sp = a.split;
     for (int t = 0; t < a.nterms; ++t) {
@@ -1805,6 +1916,7 @@ hipError_t launch_fwd_terms(const FwdArgs& a, hipStream_t s)
         fb.imgT = tm.imgT;
         fb.part = tm.part;
         fb.split = sp;
+        Launch L;
         if (tm.rows > 0) {
             const int nl = a.n >> tm.lvl;
             fb.R = tm.rows;
@@ -1814,39 +1926,88 @@ hipError_t launch_fwd_terms(const FwdArgs& a, hipStream_t s)
             fb.apg = std::max(1, ((sp.nrow + sp.ncol) * tm.bands + 511) / 512);
             fb.groups_row = (sp.nrow + fb.apg - 1) / fb.apg;
             fb.groups_col = (sp.ncol + fb.apg - 1) / fb.apg;
-            const int lds = (int)(sizeof(float) * (size_t)fb.R * (nl + kPad));
-            hipError_t e = allow_lds((const void*)k_fwd_band, lds);
-            if (e != hipSuccess) return e;
-            hipLaunchKernelGGL(k_fwd_band, dim3(tm.bands, fb.groups_row + fb.groups_col), dim3(1024), lds, s, fb);
-        } else if (a.fan.ray) {
-            const size_t m = (size_t)(a.fan.vb - a.fan.va) * a.nd;
-            hipLaunchKernelGGL(k_fwd_fan, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, fb);
+            L.variant = V_FWD_BAND;
+            L.gx = (unsigned)tm.bands;
+            L.gy = (unsigned)(fb.groups_row + fb.groups_col);
+            L.block = 1024;
+            L.lds = (int)(sizeof(float) * (size_t)fb.R * (nl + kPad));
         } else {
             const int wpa = (a.nd + 63) / 64;
             const long waves = (long)wpa * a.na;
-            hipLaunchKernelGGL(k_fwd_direct, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, fb);
+            L.variant = V_FWD_DIRECT;
+            L.gx = (unsigned)((waves + 3) / 4);
+            L.block = 256;
+            L.lds = 0;
         }
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
+        L.set(fb);
+        out.push_back(L);
     }
-    return hipSuccess;
+}
+
+// The band partials' ordered sum and the dual step (or store / accumulate).
+static void plan_reduce(const FwdArgs& a, Launches& out)
+{
+    const size_t m = (size_t)a.na * a.nd;
+    auto al = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
+    const bool aligned = a.mode == FWD_DUAL ? al(a.y_old) && al(a.y_new) && al(a.bdat) && al(a.psi) : al(a.out);
+    Launch L;
+    if (m % 4 == 0 && aligned) {  // the workspace partials are 16-byte aligned too
+        L.variant = V_RED4;
+        L.gx = (unsigned)std::min<size_t>((m / 4 + 255) / 256, 8192);
+    } else {
+        L.variant = V_RED1;
+        L.gx = (unsigned)std::min<size_t>((m + 255) / 256, 8192);
+    }
+    L.block = 256;
+    L.set(a);
+    out.push_back(L);
+}
+
+void plan_fwd(const FwdArgs& a, Launches& out)
+{
+    plan_fwd_terms(a, out);
+    plan_reduce(a, out);
+}
+
+hipError_t launch_fwd_terms(const FwdArgs& a, hipStream_t s)
+{
+    if (a.fan.ray) {
+        for (int t = 0; t < a.nterms; ++t) {
+            const FwdTerm& tm = a.term[t];
+            FwdBandArgs fb{};
+            fb.consts = a.consts;
+            fb.fan = a.fan;
+            fb.n = a.n;
+            fb.na = a.na;
+            fb.nd = a.nd;
+            fb.lvl = tm.lvl;
+            fb.img = tm.img;
+            fb.imgT = tm.imgT;
+            fb.part = tm.part;
+            fb.split = a.split;
+            const size_t m = (size_t)(a.fan.vb - a.fan.va) * a.nd;
+            hipLaunchKernelGGL(k_fwd_fan, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, fb);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
+    Launches r;
+    plan_fwd_terms(a, r);
+    return launch_records(r, s);
 }
 
 hipError_t launch_fwd(const FwdArgs& a, hipStream_t s)
 {
-    hipError_t e = launch_fwd_terms(a, s);
-    if (e != hipSuccess) return e;
-    const size_t m = (size_t)a.na * a.nd;
-    auto al = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
-    const bool aligned = a.mode == FWD_DUAL ? al(a.y_old) && al(a.y_new) && al(a.bdat) && al(a.psi) : al(a.out);
-    if (m % 4 == 0 && aligned) {  // the workspace partials are 16-byte aligned too
-        const unsigned blocks = (unsigned)std::min<size_t>((m / 4 + 255) / 256, 8192);
-        hipLaunchKernelGGL(k_fwd_reduce4, dim3(blocks), dim3(256), 0, s, a);
-        return hipGetLastError();
+    Launches r;
+    if (a.fan.ray) {  // fan-beam terms, then the same reduce
+        const hipError_t e = launch_fwd_terms(a, s);
+        if (e != hipSuccess) return e;
+        plan_reduce(a, r);
+    } else {
+        plan_fwd(a, r);
     }
-    const unsigned blocks = (unsigned)std::min<size_t>((m + 255) / 256, 8192);
-    hipLaunchKernelGGL(k_fwd_reduce, dim3(blocks), dim3(256), 0, s, a);
-    return hipGetLastError();
+    return launch_records(r, s);
 }
 
 #ifndef IMK_BP_TARGET_WG
@@ -1867,23 +2028,27 @@ static size_t scatter_lds(int nl)
 // of the angles (a measurement block) keeps the same workgroup count: fewer
 // angles per group, but fewer workgroups measured slower still.
 template <int R, int W>
-static hipError_t launch_scatter(BpOwnArgs& a, int nl, int lvl, hipStream_t s)
+static void plan_scatter(BpOwnArgs& a, int nl, int lvl, int variant, int round, int target, Launches& out)
 {
     using Sh = BpShape<R, W>;
     const int nb = (nl + Sh::rows - 1) / Sh::rows;
     const int gmax = std::max(1, std::min(std::max(a.split.nrow, a.split.ncol), (kPartImages / 2) << (2 * lvl)));
-    a.G = std::max(1, std::min(gmax, (IMK_BP_TARGET_WG + 2 * nb - 1) / (2 * nb)));
+    a.G = std::max(1, std::min(gmax, (target + 2 * nb - 1) / (2 * nb)));
     a.nq = 2 * a.G;
-    const int lds = (int)scatter_lds<R, W>(nl);
-    const hipError_t e = allow_lds((const void*)k_bp_own<R, W>, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_bp_own<R, W>), dim3(nb, 2 * a.G), dim3(64 * W), lds, s, a);
-    return hipGetLastError();
+    Launch L;
+    L.variant = variant;
+    L.round = round;
+    L.gx = (unsigned)nb;
+    L.gy = (unsigned)(2 * a.G);
+    L.block = 64 * W;
+    L.lds = (int)scatter_lds<R, W>(nl);
+    L.set(a);
+    out.push_back(L);
 }
 
-hipError_t launch_bp_main(const BpArgs& ba, hipStream_t s, BpOwnArgs& a)
+static BpOwnArgs own_args(const BpArgs& ba)
 {
-    a = BpOwnArgs{};
+    BpOwnArgs a{};
     a.consts = ba.consts;
     a.fan = ba.fan;
     a.n = ba.n;
@@ -1897,6 +2062,46 @@ hipError_t launch_bp_main(const BpArgs& ba, hipStream_t s, BpOwnArgs& a)
     a.coef = ba.coef;
     a.accumulate = ba.accumulate;
     a.prolong = ba.prolong;
+    return a;
+}
+
+void plan_bp_main(const BpArgs& ba, int round, Launches& out, BpOwnArgs* used)
+{
+    BpOwnArgs a = own_args(ba);
+    const int nl = ba.n >> ba.lvl;
+    const Tiles t = tiles_for(nl, ba.na, ba.nd);
+    const int target = t.bp_wg > 0 ? t.bp_wg : IMK_BP_TARGET_WG;
+    // a tuned tile shape, where its rows fit in the 160 KB of LDS
+    const int shape = t.bp_rows * 16 + t.bp_waves;
+    if (shape == 2 * 16 + 8 && scatter_lds<2, 8>(nl) <= kLdsBytes) {
+        plan_scatter<2, 8>(a, nl, ba.lvl, V_BP28, round, target, out);
+    } else if (shape == 4 * 16 + 4 && scatter_lds<4, 4>(nl) <= kLdsBytes) {
+        plan_scatter<4, 4>(a, nl, ba.lvl, V_BP44, round, target, out);
+    } else if (shape == 2 * 16 + 4 && scatter_lds<2, 4>(nl) <= kLdsBytes) {
+        plan_scatter<2, 4>(a, nl, ba.lvl, V_BP24, round, target, out);
+    } else if (shape == 1 * 16 + 4 && scatter_lds<1, 4>(nl) <= kLdsBytes) {
+        plan_scatter<1, 4>(a, nl, ba.lvl, V_BP14, round, target, out);
+    } else if (scatter_lds<2, 8>(nl) <= kLdsBytes) {
+        // default tile shapes, measured best on the 512^2 / 720 x 768
+        // workload: two rows per wavefront and 8 wavefronts at the two
+        // finest levels, four rows and 4 wavefronts on the coarse ones
+        if (ba.lvl <= 1)
+            plan_scatter<2, 8>(a, nl, ba.lvl, V_BP28, round, target, out);
+        else
+            plan_scatter<4, 4>(a, nl, ba.lvl, V_BP44, round, target, out);
+    } else if (scatter_lds<1, 4>(nl) <= kLdsBytes) {
+        // rows longer than about 2400 pixels: fewer rows per workgroup so
+        // that they fit in the LDS
+        plan_scatter<1, 4>(a, nl, ba.lvl, V_BP14, round, target, out);
+    } else {
+        plan_scatter<1, 2>(a, nl, ba.lvl, V_BP12, round, target, out);
+    }
+    if (used) *used = a;
+}
+
+hipError_t launch_bp_main(const BpArgs& ba, hipStream_t s, BpOwnArgs& a)
+{
+    a = own_args(ba);
     const int nl = ba.n >> ba.lvl;
     if (ba.fan.ray) {
         // phases of the scatter: bins P apart are at least P * min_sep apart,
@@ -1950,14 +2155,9 @@ hipError_t launch_bp_main(const BpArgs& ba, hipStream_t s, BpOwnArgs& a)
         }
         return hipGetLastError();
     }
-    // tile shapes measured best on the 512^2 / 720 x 768 workload: two rows
-    // per wavefront and 8 wavefronts at the two finest levels, four rows and
-    // 4 wavefronts on the coarse ones; rows longer than about 2400 pixels
-    // take fewer rows per workgroup so that they fit in the 160 KB of LDS
-    if (scatter_lds<2, 8>(nl) <= kLdsBytes)
-        return ba.lvl <= 1 ? launch_scatter<2, 8>(a, nl, ba.lvl, s) : launch_scatter<4, 4>(a, nl, ba.lvl, s);
-    if (scatter_lds<1, 4>(nl) <= kLdsBytes) return launch_scatter<1, 4>(a, nl, ba.lvl, s);
-    return launch_scatter<1, 2>(a, nl, ba.lvl, s);
+    Launches r;
+    plan_bp_main(ba, 0, r, &a);
+    return launch_records(r, s);
 }
 
 // Cells per thread of the ordered sums: four (16-byte loads) where the level
@@ -1972,11 +2172,59 @@ static int bp_sum_slices(size_t d, int nq)
     return S;
 }
 
-hipError_t launch_bp(const BpArgs& ba, hipStream_t s)
+void plan_bp(const BpArgs& ba, int round, Launches& out)
 {
     BpOwnArgs a;
-    hipError_t e = launch_bp_main(ba, s, a);
-    if (e != hipSuccess) return e;
+    plan_bp_main(ba, round, out, &a);
+    const int nl = ba.n >> ba.lvl;
+    const size_t d = (size_t)nl * nl;
+    SumArgs sa{a, ba.tmp, 0};
+    Launch L;
+    L.round = round;
+    L.block = 1024;
+    if (sum_cells_per_thread(d) == 4) {
+        sa.S = bp_sum_slices(d / 4, a.nq);
+        const size_t cells = 4 * (size_t)(1024 / sa.S);
+        L.variant = V_SUM4;
+        L.gx = (unsigned)((d + cells - 1) / cells);
+    } else {
+        sa.S = bp_sum_slices(d, a.nq);
+        const size_t cells = 1024 / sa.S;
+        L.variant = V_SUM1;
+        L.gx = (unsigned)((d + cells - 1) / cells);
+    }
+    L.set(sa);
+    out.push_back(L);
+}
+
+void plan_bp_primal(const BpArgs& ba, const PrimalArgs& pr, Launches& out)
+{
+    BpOwnArgs a;
+    plan_bp_main(ba, 0, out, &a);
+    const int nl = ba.n >> ba.lvl;
+    const size_t d = (size_t)nl * nl;
+    SumPrimalArgs sp{a, pr, 0};
+    Launch L;
+    L.block = 1024;
+    if (sum_cells_per_thread(d) == 4) {
+        sp.S = bp_sum_slices(d / 4, a.nq);
+        const size_t cells = 4 * (size_t)(1024 / sp.S);
+        L.variant = V_SUMP4;
+        L.gx = (unsigned)((d + cells - 1) / cells);
+    } else {
+        sp.S = bp_sum_slices(d, a.nq);
+        const size_t cells = 1024 / sp.S;
+        L.variant = V_SUMP1;
+        L.gx = (unsigned)((d + cells - 1) / cells);
+    }
+    L.set(sp);
+    out.push_back(L);
+}
+
+// The ordered sum of the fan-beam transposes' partial images (and the
+// prolongation of either beam's result when asked for).
+static hipError_t launch_sum_after(const BpArgs& ba, const BpOwnArgs& a, hipStream_t s)
+{
     const int nl = ba.n >> ba.lvl;
     const size_t d = (size_t)nl * nl;
     if (sum_cells_per_thread(d) == 4) {
@@ -1988,7 +2236,22 @@ hipError_t launch_bp(const BpArgs& ba, hipStream_t s)
         const size_t cells = 1024 / S;
         hipLaunchKernelGGL(k_bp_sum<1>, dim3((unsigned)((d + cells - 1) / cells)), dim3(1024), 0, s, a, ba.tmp, S);
     }
-    e = hipGetLastError();
+    return hipGetLastError();
+}
+
+hipError_t launch_bp(const BpArgs& ba, hipStream_t s)
+{
+    hipError_t e;
+    if (ba.fan.ray) {
+        BpOwnArgs a;
+        e = launch_bp_main(ba, s, a);
+        if (e != hipSuccess) return e;
+        e = launch_sum_after(ba, a, s);
+    } else {
+        Launches r;
+        plan_bp(ba, 0, r);
+        e = launch_records(r, s);
+    }
     if (e != hipSuccess || !ba.prolong) return e;
     const size_t fine = (size_t)ba.n * ba.n;
     hipLaunchKernelGGL(k_prolong_acc, dim3((unsigned)((fine + 255) / 256)), dim3(256), 0, s, (const float*)ba.tmp,
@@ -1998,6 +2261,11 @@ hipError_t launch_bp(const BpArgs& ba, hipStream_t s)
 
 hipError_t launch_bp_primal(const BpArgs& ba, const PrimalArgs& pr, hipStream_t s)
 {
+    if (!ba.fan.ray) {
+        Launches r;
+        plan_bp_primal(ba, pr, r);
+        return launch_records(r, s);
+    }
     BpOwnArgs a;
     hipError_t e = launch_bp_main(ba, s, a);
     if (e != hipSuccess) return e;
@@ -2015,13 +2283,93 @@ hipError_t launch_bp_primal(const BpArgs& ba, const PrimalArgs& pr, hipStream_t 
     return hipGetLastError();
 }
 
-hipError_t launch_primal(const PrimalArgs& a, hipStream_t s)
+void plan_primal(const PrimalArgs& a, Launches& out)
 {
+    Launch L;
+    L.variant = V_PRIMAL;
     const int tiles = a.n / a.T;
     const bool paper_full = (a.kidx == 0 && a.full_mode == IMASK_FULL_PAPER && a.r > 1);
-    const size_t sh = paper_full ? pyramid_bytes(a.T, a.pyr_levels) : 0;
-    hipLaunchKernelGGL(k_primal, dim3(tiles * tiles), dim3(256), sh, s, a);
-    return hipGetLastError();
+    L.gx = (unsigned)(tiles * tiles);
+    L.block = 256;
+    L.lds = paper_full ? (int)pyramid_bytes(a.T, a.pyr_levels) : 0;
+    L.set(a);
+    out.push_back(L);
+}
+
+hipError_t launch_primal(const PrimalArgs& a, hipStream_t s)
+{
+    Launches r;
+    plan_primal(a, r);
+    return launch_records(r, s);
+}
+
+// Kernel of each variant (the single-problem form).
+static const void* variant_kernel(int v)
+{
+    switch (v) {
+    case V_PREP: return (const void*)k_prep;
+    case V_FWD_BAND: return (const void*)k_fwd_band;
+    case V_FWD_DIRECT: return (const void*)k_fwd_direct;
+    case V_RED4: return (const void*)k_fwd_reduce4;
+    case V_RED1: return (const void*)k_fwd_reduce;
+    case V_BP28: return (const void*)k_bp_own<2, 8>;
+    case V_BP44: return (const void*)k_bp_own<4, 4>;
+    case V_BP14: return (const void*)k_bp_own<1, 4>;
+    case V_BP12: return (const void*)k_bp_own<1, 2>;
+    case V_BP24: return (const void*)k_bp_own<2, 4>;
+    case V_SUM4: return (const void*)k_bp_sum<4>;
+    case V_SUM1: return (const void*)k_bp_sum<1>;
+    case V_SUMP4: return (const void*)k_bp_sum_primal<4>;
+    case V_SUMP1: return (const void*)k_bp_sum_primal<1>;
+    case V_PRIMAL: return (const void*)k_primal;
+    default: return nullptr;
+    }
+}
+
+hipError_t launch_records(const Launches& recs, hipStream_t s)
+{
+    for (const Launch& L : recs) {
+        const dim3 grid(L.gx, L.gy, L.gz), block(L.block);
+        const hipError_t e0 = allow_lds(variant_kernel(L.variant), L.lds);
+        if (e0 != hipSuccess) return e0;
+        switch (L.variant) {
+        case V_PREP: hipLaunchKernelGGL(k_prep, grid, block, L.lds, s, L.get<PrepArgs>()); break;
+        case V_FWD_BAND: hipLaunchKernelGGL(k_fwd_band, grid, block, L.lds, s, L.get<FwdBandArgs>()); break;
+        case V_FWD_DIRECT: hipLaunchKernelGGL(k_fwd_direct, grid, block, L.lds, s, L.get<FwdBandArgs>()); break;
+        case V_RED4: hipLaunchKernelGGL(k_fwd_reduce4, grid, block, L.lds, s, L.get<FwdArgs>()); break;
+        case V_RED1: hipLaunchKernelGGL(k_fwd_reduce, grid, block, L.lds, s, L.get<FwdArgs>()); break;
+        case V_BP28: hipLaunchKernelGGL((k_bp_own<2, 8>), grid, block, L.lds, s, L.get<BpOwnArgs>()); break;
+        case V_BP44: hipLaunchKernelGGL((k_bp_own<4, 4>), grid, block, L.lds, s, L.get<BpOwnArgs>()); break;
+        case V_BP14: hipLaunchKernelGGL((k_bp_own<1, 4>), grid, block, L.lds, s, L.get<BpOwnArgs>()); break;
+        case V_BP12: hipLaunchKernelGGL((k_bp_own<1, 2>), grid, block, L.lds, s, L.get<BpOwnArgs>()); break;
+        case V_BP24: hipLaunchKernelGGL((k_bp_own<2, 4>), grid, block, L.lds, s, L.get<BpOwnArgs>()); break;
+        case V_SUM4: {
+            const SumArgs& a = L.get<SumArgs>();
+            hipLaunchKernelGGL(k_bp_sum<4>, grid, block, L.lds, s, a.a, a.tmp, a.S);
+            break;
+        }
+        case V_SUM1: {
+            const SumArgs& a = L.get<SumArgs>();
+            hipLaunchKernelGGL(k_bp_sum<1>, grid, block, L.lds, s, a.a, a.tmp, a.S);
+            break;
+        }
+        case V_SUMP4: {
+            const SumPrimalArgs& a = L.get<SumPrimalArgs>();
+            hipLaunchKernelGGL(k_bp_sum_primal<4>, grid, block, L.lds, s, a.a, a.S, a.p);
+            break;
+        }
+        case V_SUMP1: {
+            const SumPrimalArgs& a = L.get<SumPrimalArgs>();
+            hipLaunchKernelGGL(k_bp_sum_primal<1>, grid, block, L.lds, s, a.a, a.S, a.p);
+            break;
+        }
+        case V_PRIMAL: hipLaunchKernelGGL(k_primal, grid, block, L.lds, s, L.get<PrimalArgs>()); break;
+        default: return hipErrorInvalidValue;
+        }
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_tv(const TvArgs& a, hipStream_t s)
@@ -2094,6 +2442,246 @@ hipError_t launch_dot(const float* a, const float* b, size_t n, double* part, do
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(kDotBlocks), 0, s, (const double*)part, out);
+    return hipGetLastError();
+}
+
+}  // namespace imk
+
+// ------------------------------------------------- batched steps (many problems)
+//
+// A batch holds, for every problem, sketch index and parity of the state's
+// ping-pong buffers, the launch records of that step (the same records the
+// single-problem launchers run).  Each step is one plan kernel, one
+// persistent launch per (kernel variant, round) over the work items of every
+// problem that needs that variant this step, and one advance kernel; the
+// sketch index is drawn on the device, so the launches of a step do not
+// depend on the draw and a captured step replays as it is.
+
+namespace imk {
+namespace {
+
+// SplitMix64 output k + 1 of the stream at state0 (Steele, Lea & Flood
+// 2014, counter form), as the host draw computes it.
+__device__ __forceinline__ unsigned long long batch_mix(unsigned long long state0, unsigned long long k)
+{
+    unsigned long long z = state0 + (k + 1ULL) * 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+// Draws each active problem's sketch index, selects its records and forms,
+// per (variant, round), the running offsets of the problems' work items.
+__global__ void __launch_bounds__(1024) k_batch_plan(BatchView bv)
+{
+    const int n = bv.n;
+    const int slots = kNumVariants * kRounds;
+    for (int q = threadIdx.x; q < n; q += blockDim.x) {
+        const BatchProb& pb = bv.prob[q];
+        int sl = -1;
+        if (pb.k < pb.k_stop) {
+            const unsigned long long u = batch_mix(pb.stream_state, pb.k) >> 32;
+            int j = 0;
+            while (j < pb.r - 1 && u >= pb.thr[j]) ++j;
+            sl = j * 2 + pb.cur;
+        }
+        bv.sel[q] = sl;
+        const int* it = sl >= 0 ? bv.items + ((size_t)q * bv.r_max * 2 + sl) * slots : nullptr;
+        for (int vr = 0; vr < slots; ++vr) bv.off[(size_t)vr * (n + 1) + q + 1] = it ? it[vr] : 0;
+    }
+    __syncthreads();
+    for (int vr = threadIdx.x; vr < slots; vr += blockDim.x) {
+        int* o = bv.off + (size_t)vr * (n + 1);
+        o[0] = 0;
+        for (int q = 0; q < n; ++q) o[q + 1] += o[q];
+    }
+}
+
+// k += 1, parity flip and the sketch's epochs for every problem that stepped.
+__global__ void k_batch_advance(BatchView bv)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= bv.n) return;
+    const int sl = bv.sel[q];
+    if (sl < 0) return;
+    BatchProb& pb = bv.prob[q];
+    pb.epochs += pb.cost[sl >> 1];
+    pb.k += 1ULL;
+    pb.cur ^= 1;
+}
+
+template <int V>
+__device__ __forceinline__ void batch_body(const unsigned char* args, const Blk& bk, float* smem)
+{
+    if constexpr (V == V_PREP) {
+        prep_body(*reinterpret_cast<const PrepArgs*>(args), bk, smem);
+    } else if constexpr (V == V_FWD_BAND) {
+        fwd_band_body(*reinterpret_cast<const FwdBandArgs*>(args), bk, smem);
+    } else if constexpr (V == V_FWD_DIRECT) {
+        fwd_direct_body(*reinterpret_cast<const FwdBandArgs*>(args), bk);
+    } else if constexpr (V == V_RED4) {
+        fwd_reduce4_body(*reinterpret_cast<const FwdArgs*>(args), bk);
+    } else if constexpr (V == V_RED1) {
+        fwd_reduce_body(*reinterpret_cast<const FwdArgs*>(args), bk);
+    } else if constexpr (V == V_BP28) {
+        bp_own_body<2, 8>(*reinterpret_cast<const BpOwnArgs*>(args), bk, smem);
+    } else if constexpr (V == V_BP44) {
+        bp_own_body<4, 4>(*reinterpret_cast<const BpOwnArgs*>(args), bk, smem);
+    } else if constexpr (V == V_BP14) {
+        bp_own_body<1, 4>(*reinterpret_cast<const BpOwnArgs*>(args), bk, smem);
+    } else if constexpr (V == V_BP12) {
+        bp_own_body<1, 2>(*reinterpret_cast<const BpOwnArgs*>(args), bk, smem);
+    } else if constexpr (V == V_BP24) {
+        bp_own_body<2, 4>(*reinterpret_cast<const BpOwnArgs*>(args), bk, smem);
+    } else if constexpr (V == V_SUM4 || V == V_SUM1) {
+        const SumArgs& a = *reinterpret_cast<const SumArgs*>(args);
+        bp_sum_body<V == V_SUM4 ? 4 : 1>(a.a, a.tmp, a.S, bk);
+    } else if constexpr (V == V_SUMP4 || V == V_SUMP1) {
+        const SumPrimalArgs& a = *reinterpret_cast<const SumPrimalArgs*>(args);
+        bp_sum_primal_body<V == V_SUMP4 ? 4 : 1>(a.a, a.S, a.p, bk);
+    } else {
+        primal_body(*reinterpret_cast<const PrimalArgs*>(args), bk, smem);
+    }
+}
+
+// Threads per workgroup of each variant (those of its single-problem kernel).
+template <int V>
+constexpr int kVariantThreads = (V == V_FWD_BAND || V == V_SUM4 || V == V_SUM1 || V == V_SUMP4 || V == V_SUMP1) ? 1024
+                                : V == V_BP28                                                                    ? 512
+                                : V == V_BP12                                                                    ? 128
+                                                                                                                 : 256;
+
+// Persistent launch of variant V, round `round`: workgroup w takes items
+// w, w + grid, ... of the step's list; an item is one workgroup of one
+// problem's launch, found from the offsets by binary search.  The argument
+// block is staged in LDS, where every thread reads it.
+template <int V>
+__global__ void __launch_bounds__(kVariantThreads<V>) k_batch(BatchView bv, int round, int lds_avail)
+{
+    extern __shared__ float smem[];
+    __shared__ __attribute__((aligned(16))) unsigned char s_args[kLaunchArgBytes];
+    const int n = bv.n;
+    const int* off = bv.off + ((size_t)V * kRounds + round) * (n + 1);
+    const int total = off[n];
+    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+        int lo = 0, hi = n;  // off[lo] <= item < off[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (off[mid] <= item) lo = mid; else hi = mid;
+        }
+        const int q = __builtin_amdgcn_readfirstlane(lo);
+        int local = item - off[q];
+        const int sl = bv.sel[q];
+        const BatchRec* rec = bv.rec + ((size_t)q * bv.r_max * 2 + sl) * kMaxRec;
+        const int nr = bv.nrec[(size_t)q * bv.r_max * 2 + sl];
+        int j = 0;
+        for (; j < nr; ++j) {
+            if (rec[j].variant != V || rec[j].round != round) continue;
+            if (local < rec[j].items) break;
+            local -= rec[j].items;
+        }
+        // unreachable: the offsets count exactly these records' items, and
+        // the launch reserves the LDS of its largest record
+        if (j >= nr || rec[j].lds > lds_avail) continue;
+        const BatchRec rc = rec[j];
+        const uint4* src = reinterpret_cast<const uint4*>(bv.blobs + (size_t)rc.blob * kLaunchArgBytes);
+        for (int t = threadIdx.x; t < kLaunchArgBytes / 16; t += blockDim.x) reinterpret_cast<uint4*>(s_args)[t] = src[t];
+        __syncthreads();
+        Blk bk;
+        bk.x = local % rc.gx;
+        const int t2 = local / rc.gx;
+        bk.y = t2 % rc.gy;
+        bk.z = t2 / rc.gy;
+        bk.gx = rc.gx;
+        batch_body<V>(s_args, bk, smem);
+        __syncthreads();  // the next item rewrites the arguments and the LDS
+    }
+}
+
+}  // namespace
+
+int variant_threads(int v)
+{
+    switch (v) {
+    case V_FWD_BAND: case V_SUM4: case V_SUM1: case V_SUMP4: case V_SUMP1: return 1024;
+    case V_BP28: return 512;
+    case V_BP12: return 128;
+    default: return 256;
+    }
+}
+
+template <int V>
+static const void* batch_kernel() { return (const void*)k_batch<V>; }
+
+static const void* batch_kernel_of(int v)
+{
+    switch (v) {
+    case V_PREP: return batch_kernel<V_PREP>();
+    case V_FWD_BAND: return batch_kernel<V_FWD_BAND>();
+    case V_FWD_DIRECT: return batch_kernel<V_FWD_DIRECT>();
+    case V_RED4: return batch_kernel<V_RED4>();
+    case V_RED1: return batch_kernel<V_RED1>();
+    case V_BP28: return batch_kernel<V_BP28>();
+    case V_BP44: return batch_kernel<V_BP44>();
+    case V_BP14: return batch_kernel<V_BP14>();
+    case V_BP12: return batch_kernel<V_BP12>();
+    case V_BP24: return batch_kernel<V_BP24>();
+    case V_SUM4: return batch_kernel<V_SUM4>();
+    case V_SUM1: return batch_kernel<V_SUM1>();
+    case V_SUMP4: return batch_kernel<V_SUMP4>();
+    case V_SUMP1: return batch_kernel<V_SUMP1>();
+    case V_PRIMAL: return batch_kernel<V_PRIMAL>();
+    default: return nullptr;
+    }
+}
+
+// Static LDS of a batched variant: the staged argument block, plus the
+// ordered sums' reduction arrays.
+size_t variant_static_lds(int v)
+{
+    size_t s = kLaunchArgBytes;
+    if (v == V_SUM4) s += 1024 * 4 * sizeof(float);
+    if (v == V_SUM1) s += 1024 * sizeof(float);
+    if (v == V_SUMP4) s += 3 * 1024 * 4 * sizeof(float);
+    if (v == V_SUMP1) s += 3 * 1024 * sizeof(float);
+    return s;
+}
+
+hipError_t batch_allow_lds(int v, int lds) { return allow_lds(batch_kernel_of(v), lds); }
+
+hipError_t launch_batch_plan(const BatchView& bv, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(1024), 0, s, bv);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_advance(const BatchView& bv, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_batch_advance, dim3((unsigned)((bv.n + 255) / 256)), dim3(256), 0, s, bv);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_stage(int v, int round, const BatchView& bv, unsigned grid, int lds, hipStream_t s)
+{
+    const dim3 g(grid);
+    switch (v) {
+    case V_PREP: hipLaunchKernelGGL(k_batch<V_PREP>, g, dim3(256), lds, s, bv, round, lds); break;
+    case V_FWD_BAND: hipLaunchKernelGGL(k_batch<V_FWD_BAND>, g, dim3(1024), lds, s, bv, round, lds); break;
+    case V_FWD_DIRECT: hipLaunchKernelGGL(k_batch<V_FWD_DIRECT>, g, dim3(256), lds, s, bv, round, lds); break;
+    case V_RED4: hipLaunchKernelGGL(k_batch<V_RED4>, g, dim3(256), lds, s, bv, round, lds); break;
+    case V_RED1: hipLaunchKernelGGL(k_batch<V_RED1>, g, dim3(256), lds, s, bv, round, lds); break;
+    case V_BP28: hipLaunchKernelGGL(k_batch<V_BP28>, g, dim3(512), lds, s, bv, round, lds); break;
+    case V_BP44: hipLaunchKernelGGL(k_batch<V_BP44>, g, dim3(256), lds, s, bv, round, lds); break;
+    case V_BP14: hipLaunchKernelGGL(k_batch<V_BP14>, g, dim3(256), lds, s, bv, round, lds); break;
+    case V_BP12: hipLaunchKernelGGL(k_batch<V_BP12>, g, dim3(128), lds, s, bv, round, lds); break;
+    case V_BP24: hipLaunchKernelGGL(k_batch<V_BP24>, g, dim3(256), lds, s, bv, round, lds); break;
+    case V_SUM4: hipLaunchKernelGGL(k_batch<V_SUM4>, g, dim3(1024), lds, s, bv, round, lds); break;
+    case V_SUM1: hipLaunchKernelGGL(k_batch<V_SUM1>, g, dim3(1024), lds, s, bv, round, lds); break;
+    case V_SUMP4: hipLaunchKernelGGL(k_batch<V_SUMP4>, g, dim3(1024), lds, s, bv, round, lds); break;
+    case V_SUMP1: hipLaunchKernelGGL(k_batch<V_SUMP1>, g, dim3(1024), lds, s, bv, round, lds); break;
+    case V_PRIMAL: hipLaunchKernelGGL(k_batch<V_PRIMAL>, g, dim3(256), lds, s, bv, round, lds); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -340,3 +340,51 @@ def test_noalloc_transpose_validates_before_any_device_call():
     # 17 N^2 + 16 (lmax + 1) n_angles floats against the 24 MiB array
     assert call(im.Geometry(1024, 90, 92)) == _abi.ESIZE
     assert call(im.Geometry(512, 20000, 768)) == _abi.ESIZE
+
+
+def test_tiles_table_validates_and_round_trips():
+    """imask_set_tiles keeps one entry per (grid side, angles, bins), refuses
+    unsupported shapes, and a NULL entry restores the defaults."""
+    from paper_2412_10249_amd import autotune
+
+    L = _abi.lib()
+    assert autotune.get_tiles(256, 384, 384) == {"bp": [0, 0], "bp_wg": 0, "fwd_lds_kb": 0}
+    autotune.set_tiles(256, 384, 384, (4, 4), 2048, 96)
+    assert autotune.get_tiles(256, 384, 384) == {"bp": [4, 4], "bp_wg": 2048, "fwd_lds_kb": 96}
+    assert autotune.get_tiles(256, 384, 385)["bp_wg"] == 0  # another geometry keeps the defaults
+    for bad in [(3, 3, 0, 0), (2, 8, 32, 0), (2, 8, 0, 200), (8, 8, 0, 0)]:
+        t = _abi.Tiles(*bad)
+        assert L.imask_set_tiles(256, 384, 384, ctypes.byref(t)) == _abi.EINVAL, bad
+    assert autotune.get_tiles(256, 384, 384)["bp"] == [4, 4]  # a refused call changes nothing
+    autotune.reset_tiles(256, 384, 384)
+    assert autotune.get_tiles(256, 384, 384) == {"bp": [0, 0], "bp_wg": 0, "fwd_lds_kb": 0}
+
+
+def test_tuned_forward_budget_keeps_the_workspace_size():
+    """A tuned forward band budget never needs more bands than the default,
+    so a workspace's size (and layout) does not depend on the tiles."""
+    from paper_2412_10249_amd import autotune
+
+    L = _abi.lib()
+    g = im.Geometry(256, 384, 384).c()
+    before = L.imask_workspace_bytes(ctypes.byref(g))
+    for kb in (78, 96, 128, 156):
+        autotune.set_tiles(256, 384, 384, (0, 0), 0, kb)
+        assert L.imask_workspace_bytes(ctypes.byref(g)) == before
+    autotune.reset_tiles(256, 384, 384)
+
+
+def test_batch_entry_points_validate_before_any_device_call():
+    L = _abi.lib()
+    n = 2
+    G = (_abi.Geometry * n)(im.Geometry(64, 90, 92).c(), im.Geometry(32, 48, 48).c())
+    Lv = (_abi.Levels * n)(im.Levels((0, 1, 2), (1 / 3,) * 3).c(), im.Levels((0,), (1.0,)).c())
+    assert L.imask_batch_bytes(n, G, Lv) > 0
+    assert L.imask_batch_bytes(0, G, Lv) == 0
+    Gf = (_abi.Geometry * 1)(im.Geometry(64, 90, 92, src_dist=4.0, det_dist=2.0).c())
+    assert L.imask_batch_bytes(1, Gf, Lv) == 0
+    buf = ctypes.c_void_p(256)
+    assert L.imask_batch_step(1, Gf, Lv, buf, 1, None) == _abi.ENOTSUP
+    assert L.imask_batch_step(n, G, Lv, None, 1, None) == _abi.EINVAL
+    assert L.imask_batch_step(n, G, Lv, buf, -1, None) == _abi.EINVAL
+    assert L.imask_batch_state(0, Lv, buf, None, None) == _abi.EINVAL

@@ -11,7 +11,7 @@ import torch
 
 import oracle
 import synth
-from gpu_util import dev, f32, host, rel, say
+from gpu_util import dev, elementwise_ok, f32, host, max_rel, rel, say
 
 import paper_2412_10249_amd as pk
 
@@ -141,10 +141,46 @@ def test_full_size_projector_pair():
     y = f32(synth.random_sinogram(na, nd, 11))
     for l in range(4):
         say(f"full-size level {l}")
-        got = host(pk.project(g, l, dev(x), work))
-        assert rel(got, oracle.project(og, l, oracle.restrict(x, l))) <= 1e-5
-        got = host(pk.backproject(g, l, dev(y), work))
-        assert rel(got, oracle.prolong(oracle.backproject(og, l, y), l) / 4 ** l) <= 1e-5
+        _pair_elementwise(g, og, work, l, x, y)
+
+
+def _pair_elementwise(g, og, work, l, x, y, extra_terms=0):
+    """Projector pair at level l: relative l2 <= 1e-5 and, element by
+    element, within the FP32 rounding bound of each sum (forward: a ray's
+    2 N_l taps, band partials and the 4^l-term block mean; transpose: up to
+    four taps per angle and pixel, and the ordered partial-image sum)."""
+    nl = g.n >> l
+    got = host(pk.project(g, l, dev(x), work))
+    exp = oracle.project(og, l, oracle.restrict(x, l))
+    assert rel(got, exp) <= 1e-5, (l, rel(got, exp))
+    absref = oracle.project(og, l, oracle.restrict(np.abs(x), l))
+    ok, worst = elementwise_ok(got, exp, absref, 2 * nl + 16 + 4 ** l + extra_terms)
+    assert ok, ("forward", l, worst)
+    assert max_rel(got, exp) <= 1e-5, ("forward", l, max_rel(got, exp))
+    say(f"  level {l} forward: worst element at {worst:.2e} of its bound, max_rel {max_rel(got, exp):.2e}")
+    got = host(pk.backproject(g, l, dev(y), work))
+    exp = oracle.prolong(oracle.backproject(og, l, y), l) / 4 ** l
+    assert rel(got, exp) <= 1e-5, (l, rel(got, exp))
+    absref = oracle.prolong(oracle.backproject(og, l, np.abs(y)), l) / 4 ** l
+    ok, worst = elementwise_ok(got, exp, absref, 4 * g.n_angles + 64 + extra_terms)
+    assert ok, ("transpose", l, worst)
+    assert max_rel(got, exp) <= 1e-5, ("transpose", l, max_rel(got, exp))
+    say(f"  level {l} transpose: worst element at {worst:.2e} of its bound, max_rel {max_rel(got, exp):.2e}")
+
+
+@pytest.mark.parametrize("n", [384, 768])
+def test_batched_workload_sizes_projector_pair(n):
+    """The mixed-size batch's other grids (angles = bins = 1.5 N), levels
+    0-3, against the oracle element by element."""
+    na = nd = 3 * n // 2
+    g = pk.Geometry(n, na, nd)
+    og = oracle.Geometry(n, na, nd)
+    work = pk.workspace(g)
+    x = f32(synth.ct_problem(n, na, nd, 1e5, 1000 + n, 2000 + n)[0])
+    y = f32(synth.random_sinogram(na, nd, 11 + n))
+    for l in range(4):
+        say(f"grid {n} level {l}")
+        _pair_elementwise(g, og, work, l, x, y)
 
 
 def test_large_grid_projector_pair():

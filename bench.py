@@ -175,6 +175,19 @@ def stored_traffic(kernel_key):
     return None if ent is None else ent.get("bytes_per_launch")
 
 
+def stored_counter(kernel_key, name):
+    """A derived counter figure (l2_hit_rate, ...) of the committed summary,
+    or None when the kernel sources changed since."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except OSError:
+        return None
+    if t.get("source_hash") != source_hash():
+        return None
+    return t.get("kernels", {}).get(kernel_key, {}).get(name)
+
+
 def counter_run(spec: str, fan: bool = False):
     """Launch only one projector kernel (plus the calibration copy), for a
     rocprofv3 --pmc pass: spec is fwd:LEVEL or bp:LEVEL (fan: on the fan
@@ -223,7 +236,9 @@ def roofline_block(key, dom, dom_t, samples, fan):
             "algorithmic_bytes": alg,
             "hbm_TBps_measured": None if traffic is None else traffic / dom_t / 1e12,
             "hbm_frac_measured": None if traffic is None else traffic / dom_t / 1e9 / HBM_PEAK_GBS,
-            "traffic_over_algorithmic": None if traffic is None else traffic / alg}
+            "traffic_over_algorithmic": None if traffic is None else traffic / alg,
+            "l2_hit_rate": stored_counter(key, "l2_hit_rate"),
+            "lds_bank_conflict_fraction": stored_counter(key, "lds_bank_conflict_fraction")}
 
 
 def step_times_by_level(prob, lv, steps):
@@ -580,9 +595,9 @@ def study(args):
                 r = 1, 4 at a quarter and half of the PDHG limit
       square    the comparison of the paper's Sec. 5: a square insert whose
                 edges lie on the coarsest grid (64-pixel blocks, levels
-                512..8, r = 7, the most this library takes), Poisson data
+                512..4, r = 8 as in the paper's comparison), Poisson data
                 from its exact line integrals, the TV + nonnegativity prior;
-                ImaSk and ImaSk-Seq with r = 7, ImaSk r = 1 (SAGA) and PDHG
+                ImaSk and ImaSk-Seq with r = 8, ImaSk r = 1 (SAGA) and PDHG
                 (ImaSk-Seq r = 1); PSNR against the square and the distance
                 to the PDHG solution after --ref-iters iterations"""
     import torch
@@ -615,18 +630,18 @@ def study(args):
         lam, w = 1e-4, 2e-4
         reg = pk.Regularizer(pk.REG_TV, lam, w, 0.0, TV_J)
         info = {"lam": lam, "tv_weight": w, "tv_inner": TV_J, "phantom": "square insert, 64-pixel blocks 3..5",
-                "levels": list(range(7))}
-        lv7 = pk.Levels.uniform(tuple(range(7)), pk.FULL_PAPER)
+                "levels": list(range(8))}
+        lv8 = pk.Levels.uniform(tuple(range(8)), pk.FULL_PAPER)
         lv1 = pk.Levels.uniform((0,), pk.FULL_PAPER)
         cases = []
-        for lv, r in ((lv7, 7), (lv1, 1)):
+        for lv, r in ((lv8, 8), (lv1, 1)):
             L2, lb, lp = pk.step_constants(geom, lv, lam, work, iters=40)
             s3 = pk.sigma_thm3(L2, lb, lp, min(lv.p), 100)[0]
             info[f"constants_r{r}"] = [L2, lb, lp]
             for m in (16, 64):
                 cases.append((f"imask_r{r} x{m}", lv, reg, m * s3, pk.SCHEDULE_PARALLEL))
             for m in (0.25, 0.5, 0.9):
-                cases.append((f"{'pdhg' if r == 1 else 'seq_r7'} x{m}", lv, reg, m / np.sqrt(L2),
+                cases.append((f"{'pdhg' if r == 1 else 'seq_r8'} x{m}", lv, reg, m / np.sqrt(L2),
                               pk.SCHEDULE_SEQUENTIAL))
             if r == 1:
                 sig_ref = 0.9 / np.sqrt(L2)
@@ -1067,6 +1082,33 @@ def summarize(dirs, command_note, counter_key=None):
             traffic["kernels"][counter_key] = {"fetch_kib": per["FETCH_SIZE"], "write_kib": per["WRITE_SIZE"],
                                                "bytes_per_launch": nbytes}
             lines.append(f"{counter_key}: {nbytes / 1e6:.2f} MB of HBM traffic per launch (calibrated)\n")
+    if counters and counter_key:
+        # L2 hit rate and instruction mix of the kernel, where those passes ran
+        kname = counter_key.rsplit("_l", 1)[0]
+
+        def mean_of(c):
+            v = [np.mean(x) for (kn, g, cc), x in counters.items() if kn == kname and cc == c]
+            return float(np.mean(v)) if v else None
+
+        derived = {}
+        hit, miss = mean_of("TCC_HIT_sum"), mean_of("TCC_MISS_sum")
+        if hit is not None and miss is not None and hit + miss > 0:
+            derived["l2_hit_rate"] = hit / (hit + miss)
+        for c in ("SQ_INSTS_VALU", "SQ_INSTS_LDS", "SQ_INSTS_SALU", "SQ_WAVES", "SQ_LDS_BANK_CONFLICT",
+                  "SQ_ACTIVE_INST_LDS", "SQ_BUSY_CYCLES", "SQ_WAVE_CYCLES"):
+            if mean_of(c) is not None:
+                derived[c] = mean_of(c)
+        if derived.get("SQ_ACTIVE_INST_LDS"):
+            derived["lds_bank_conflict_fraction"] = derived.get("SQ_LDS_BANK_CONFLICT", 0.0) / derived[
+                "SQ_ACTIVE_INST_LDS"]
+        if derived:
+            lines.append("### derived (mean per dispatch)\n")
+            for k, v in derived.items():
+                lines.append(f"* {k}: {v:.4g}")
+            lines.append("")
+            if traffic is None:
+                traffic = {"source_hash": source_hash(), "calibration": {}, "kernels": {}}
+            traffic["kernels"].setdefault(counter_key, {}).update(derived)
     lines.append(f"command: {command_note}\n")
     return "\n".join(lines), traffic
 
@@ -1148,7 +1190,10 @@ def main():
                 with open(TRAFFIC_FILE) as f:
                     old = json.load(f)
             if old.get("source_hash") == traffic["source_hash"]:
-                old.setdefault("kernels", {}).update(traffic["kernels"])
+                for k, v in traffic["kernels"].items():
+                    old.setdefault("kernels", {}).setdefault(k, {}).update(v)
+                if traffic.get("calibration"):
+                    old["calibration"] = traffic["calibration"]
                 traffic = old
             with open(TRAFFIC_FILE, "w") as f:
                 json.dump(traffic, f, indent=1)

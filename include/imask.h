@@ -41,7 +41,7 @@ extern "C" {
 #endif
 
 #define IMASK_MAX_LEVELS 8   /* sketches per level set (r) */
-#define IMASK_MAX_LOG2F 6    /* coarsest level: 2^6 downsampling */
+#define IMASK_MAX_LOG2F 7    /* coarsest level: 2^7 downsampling (r = 8 levels 0..7) */
 #define IMASK_MAX_TV_INNER 12
 #define IMASK_MAX_BLOCKS 1024 /* measurement blocks (imask_levels.n_blocks) */
 

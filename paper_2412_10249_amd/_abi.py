@@ -12,7 +12,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "lib", "libimask.so")
 
 MAX_LEVELS = 8
-MAX_LOG2F = 6
+MAX_LOG2F = 7
 MAX_TV_INNER = 12
 
 OK, EINVAL, ENOTSUP, EHIP, ESIZE, ENONFINITE = 0, -1, -2, -3, -4, -5

@@ -398,8 +398,13 @@ static bool step_is_plain(const imask_geometry& g, const imask_levels& lv, const
 // Transposes of the UNBIASED full-resolution sketch take successive rounds:
 // they share the workspace's partial images.
 static void step_records(const imask_geometry& g, const Layout& L, const imask_levels& lv, const imask_reg& reg,
-                         const imask_params& prm, const float* bdat, const imask_state& st, int k, Launches& out)
+                         const imask_params& prm, const float* bdat, const imask_state& st, int k, Launches& out,
+                         bool fuse)
 {
+    // the UNBIASED full-resolution sketch applies every level: with `fuse`
+    // its forward terms share one launch and its coarse transposes one per
+    // tile shape (the batched path runs a variant's launches together anyway)
+    const bool multi = fuse && k == 0 && lv.r > 1 && lv.full_mode == IMASK_FULL_UNBIASED;
     float* W = (float*)st.work;
     const int cur = st.cur, nxt = 1 - cur;
     const int lmax_set = lv.log2f[lv.r - 1];
@@ -418,7 +423,10 @@ static void step_records(const imask_geometry& g, const Layout& L, const imask_l
     fa.sigma = (float)prm.sigma;
     fa.inv1ps = (float)(1.0 / (1.0 + prm.sigma));
     plan_prep(pa, out);
-    plan_fwd(fa, out);
+    if (multi)
+        plan_fwd_fused(fa, out);
+    else
+        plan_fwd(fa, out);
 
     const double tau = prm.sigma / reg.lambda;
     const bool tv = reg.kind != IMASK_REG_TIKHONOV;
@@ -452,8 +460,16 @@ static void step_records(const imask_geometry& g, const Layout& L, const imask_l
         plan_bp_primal(raw_bp(lv.log2f[k]), pr, out);
     } else {
         plan_bp(raw_bp(0), 0, out);
-        if (lv.full_mode == IMASK_FULL_UNBIASED)
-            for (int j = 1; j < lv.r; ++j) plan_bp(raw_bp(lv.log2f[j]), j, out);
+        if (lv.full_mode == IMASK_FULL_UNBIASED) {
+            BpArgs coarse[IMASK_MAX_LEVELS];
+            for (int j = 1; j < lv.r; ++j) coarse[j - 1] = raw_bp(lv.log2f[j]);
+            // after level 0's ordered sum the whole partial-image buffer is
+            // free for the coarse levels side by side: one launch per
+            // direction when fused (the single-problem path), the same
+            // launches one by one in the batched path
+            if (!plan_bp_coarse(coarse, lv.r - 1, L.part_floats, multi, 1, out))
+                for (int j = 1; j < lv.r; ++j) plan_bp(coarse[j - 1], j, out);
+        }
         plan_primal(pr, out);
     }
 }
@@ -521,7 +537,7 @@ static int one_step(const imask_geometry& g, const Layout& L, const imask_levels
     if (plain) {
         // the same launches the batched path stores
         Launches recs;
-        step_records(g, L, lv, reg, prm, bdat, st, k, recs);
+        step_records(g, L, lv, reg, prm, bdat, st, k, recs, true);
         IMK_TRY(launch_records(recs, s));
     } else {
         IMK_TRY(launch_prep(pa, s));
@@ -655,7 +671,7 @@ static BatchLayout batch_layout(int n, int r_max, size_t nblobs)
     B.sel = o;
     o = align256(o + (size_t)n * sizeof(int));
     B.blobs = o;
-    o = align256(o + nblobs * kLaunchArgBytes);
+    o = align256(o + nblobs * kBlobBytes);
     B.total = o;
     return B;
 }
@@ -708,7 +724,7 @@ static void shape_records(const imask_geometry& g, const imask_levels& lv, int k
     imask_reg reg{IMASK_REG_TIKHONOV, 1.0, 0.0, 1.0, 1};
     imask_params prm{};
     prm.sigma = 1.0;
-    step_records(g, L, lv, reg, prm, fake, st, k, out);
+    step_records(g, L, lv, reg, prm, fake, st, k, out, false);
 }
 
 // Per (variant, round): the largest dynamic LDS and the sum over problems of
@@ -749,6 +765,20 @@ static void batch_shapes(int n, const imask_geometry* g, const imask_levels* lv,
             for (int j = 0; j < kRounds; ++j) sh.ub[v][j] += best[v][j];
     }
     if (nblobs) *nblobs = blobs;
+}
+
+// Where a variant runs in a batched step: 0 restriction, forward and dual
+// step; in each round 1 the transposes, then 2 their ordered sums; 3 the
+// fused sums with the primal step and the primal step.
+static int variant_phase(int v)
+{
+    switch (v) {
+    case V_PREP: case V_FWD_BAND: case V_FWD_DIRECT: case V_RED4: case V_RED1: return 0;
+    case V_BP28: case V_BP44: case V_BP14: case V_BP12: case V_BP24: return 1;
+    case V_SUM4: case V_SUM1: return 2;
+    case V_SUMP4: case V_SUMP1: case V_PRIMAL: return 3;
+    default: return -1;
+    }
 }
 
 // Resident workgroups of a batched variant per CU (LDS and threads).
@@ -1068,8 +1098,10 @@ int imask_batch_prepare(int32_t n_problems, const imask_geometry* g, const imask
                 imask_state st = s[q];
                 st.cur = c;
                 Launches rl;
-                step_records(g[q], L, lv[q], reg[q], prm[q], b[q], st, k, rl);
+                step_records(g[q], L, lv[q], reg[q], prm[q], b[q], st, k, rl, false);
                 if ((int)rl.size() > kMaxRec) return IMASK_ENOTSUP;
+                for (const Launch& La : rl)
+                    if (La.variant >= kNumVariants || variant_phase(La.variant) < 0) return IMASK_ENOTSUP;
                 const size_t slot = ((size_t)q * r_max + k) * 2 + c;
                 nrec[slot] = (int)rl.size();
                 for (size_t t = 0; t < rl.size(); ++t) {
@@ -1083,7 +1115,7 @@ int imask_batch_prepare(int32_t n_problems, const imask_geometry* g, const imask
                     R.gz = (int)La.gz;
                     R.items = (int)(La.gx * La.gy * La.gz);
                     R.lds = La.lds;
-                    std::memcpy(blobs + blob * kLaunchArgBytes, La.args, kLaunchArgBytes);
+                    std::memcpy(blobs + blob * kBlobBytes, La.args, kBlobBytes);
                     ++blob;
                     items[(slot * kNumVariants + La.variant) * kRounds + La.round] += R.items;
                 }
@@ -1118,18 +1150,20 @@ int imask_batch_step(int32_t n_problems, const imask_geometry* g, const imask_le
         IMK_TRY(launch_batch_stage(v, j, bv, grid, sh.lds[v][j], s));
         return IMASK_OK;
     };
-    static const int head[] = {V_PREP, V_FWD_BAND, V_FWD_DIRECT, V_RED4, V_RED1};
-    static const int bps[] = {V_BP28, V_BP44, V_BP14, V_BP12, V_SUM4, V_SUM1};
-    static const int tail[] = {V_SUMP4, V_SUMP1, V_PRIMAL};
     for (int it = 0; it < n_steps; ++it) {
         IMK_TRY(launch_batch_plan(bv, s));
-        for (int v : head)
-            if (int rc = stage(v, 0)) return rc;
+        // every variant runs in its phase of the step, in enum order
+        for (int v = 0; v < kNumVariants; ++v)
+            if (variant_phase(v) == 0)
+                if (int rc = stage(v, 0)) return rc;
         for (int j = 0; j < sh.rounds; ++j)
-            for (int v : bps)
-                if (int rc = stage(v, j)) return rc;
-        for (int v : tail)
-            if (int rc = stage(v, 0)) return rc;
+            for (int ph = 1; ph <= 2; ++ph)
+                for (int v = 0; v < kNumVariants; ++v)
+                    if (variant_phase(v) == ph)
+                        if (int rc = stage(v, j)) return rc;
+        for (int v = 0; v < kNumVariants; ++v)
+            if (variant_phase(v) == 3)
+                if (int rc = stage(v, 0)) return rc;
         IMK_TRY(launch_batch_advance(bv, s));
     }
     return IMASK_OK;

@@ -407,9 +407,32 @@ enum Variant {
     V_SUMP4,
     V_SUMP1,
     V_PRIMAL,
-    kNumVariants
+    kNumVariants,
+    // single-problem launches over several levels at once (the UNBIASED
+    // full-resolution sketch); the batched path runs levels together anyway
+    V_FWD_MULTI = kNumVariants,
+    V_BP_MULTI28,
+    V_BP_MULTI44,
+    V_SUM_MULTI
 };
-constexpr int kLaunchArgBytes = 640;
+constexpr int kLaunchArgBytes = 2048;
+constexpr int kBlobBytes = 640;  // argument blocks of the batched variants
+
+// Several levels in one launch: block b belongs to part t when
+// start[t] <= b < start[t + 1], and is block b - start[t] of that part's own
+// grid (gx[t] blocks in x).
+struct FwdMultiArgs {
+    int n;
+    int start[IMASK_MAX_LEVELS + 1];
+    int gx[IMASK_MAX_LEVELS];
+    FwdBandArgs t[IMASK_MAX_LEVELS];
+};
+struct BpMultiArgs {
+    int n;
+    int start[IMASK_MAX_LEVELS + 1];
+    int gx[IMASK_MAX_LEVELS];
+    BpOwnArgs t[IMASK_MAX_LEVELS];
+};
 
 // k_bp_sum / k_bp_sum_primal argument blocks.
 struct SumArgs {
@@ -421,6 +444,12 @@ struct SumPrimalArgs {
     BpOwnArgs a;
     PrimalArgs p;
     int S;
+};
+struct SumMultiArgs {
+    int n;
+    int start[IMASK_MAX_LEVELS + 1];
+    int v[IMASK_MAX_LEVELS];  // cells per thread of each part (4 or 1)
+    SumArgs t[IMASK_MAX_LEVELS];
 };
 
 struct Launch {
@@ -452,6 +481,16 @@ void plan_bp_main(const BpArgs& ba, int round, Launches& out, BpOwnArgs* used);
 void plan_bp(const BpArgs& ba, int round, Launches& out);       // transpose + ordered sum (no prolongation)
 void plan_bp_primal(const BpArgs& ba, const PrimalArgs& pr, Launches& out);
 void plan_primal(const PrimalArgs& a, Launches& out);
+// The terms of an UNBIASED full-resolution sketch: every band-layout forward
+// term in one launch (direct terms launched alone), and the coarse levels'
+// transposes in one launch per tile shape with their partial images side by
+// side in the workspace buffer, then their ordered sums in one launch.
+void plan_fwd_fused(const FwdArgs& a, Launches& out);
+// The coarse transposes with their partial images side by side in the
+// buffer (groups reduced to fit); `fused`: one launch per tile shape and
+// one for the sums, else the same launches as separate records of `round`.
+// false (nothing added) when a level's tile has no fused form.
+bool plan_bp_coarse(const BpArgs* ba, int n, size_t part_floats, bool fused, int round, Launches& out);
 hipError_t launch_records(const Launches& recs, hipStream_t s);
 
 // ---- batched steps (many problems, one launch per kernel variant) ----
@@ -487,7 +526,7 @@ struct BatchView {
     const BatchRec* rec;     // [n][r_max][2][kMaxRec]
     const int* nrec;         // [n][r_max][2]
     const int* items;        // [n][r_max][2][kNumVariants][kRounds]
-    const unsigned char* blobs;  // argument blocks, kLaunchArgBytes each
+    const unsigned char* blobs;  // argument blocks, kBlobBytes each
     int* off;                // [kNumVariants][kRounds][n + 1]: per-step item offsets
     int* sel;                // [n]: this step's (sketch index, parity) slot, -1 when idle
 };

@@ -1439,6 +1439,48 @@ __global__ void __launch_bounds__(256) k_primal(PrimalArgs a)
     primal_body(a, this_block(), pyr);
 }
 
+// ------------------------------------- several levels of one sketch per launch
+
+// The part a block belongs to, and its block within that part's own grid.
+__device__ __forceinline__ Blk multi_block(const int* start, const int* gx, int n, int& t)
+{
+    const int b = blockIdx.x;
+    t = 0;
+    while (t + 1 < n && b >= start[t + 1]) ++t;
+    const int local = b - start[t];
+    return Blk{local % gx[t], local / gx[t], 0, gx[t]};
+}
+
+__global__ void __launch_bounds__(1024) k_fwd_band_multi(FwdMultiArgs m)
+{
+    extern __shared__ float band[];
+    int t;
+    const Blk bk = multi_block(m.start, m.gx, m.n, t);
+    fwd_band_body(m.t[t], bk, band);
+}
+
+template <int R, int W>
+__global__ void __launch_bounds__(64 * W) k_bp_own_multi(BpMultiArgs m)
+{
+    extern __shared__ float smem[];
+    int t;
+    const Blk bk = multi_block(m.start, m.gx, m.n, t);
+    bp_own_body<R, W>(m.t[t], bk, smem);
+}
+
+__global__ void __launch_bounds__(1024) k_bp_sum_multi(SumMultiArgs m)
+{
+    int t = 0;
+    const int b = blockIdx.x;
+    while (t + 1 < m.n && b >= m.start[t + 1]) ++t;
+    const int local = b - m.start[t];
+    const Blk bk{local, 0, 0, m.start[t + 1] - m.start[t]};
+    if (m.v[t] == 4)
+        bp_sum_body<4>(m.t[t].a, m.t[t].tmp, m.t[t].S, bk);
+    else
+        bp_sum_body<1>(m.t[t].a, m.t[t].tmp, m.t[t].S, bk);
+}
+
 // ------------------------------------------------------------ smoothed TV
 
 // J FISTA iterations of the prox of tau*(w TV_eps + lam/2 |.|^2) on one
@@ -1900,10 +1942,46 @@ static hipError_t allow_lds(const void* fn, int bytes)
     return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
+// Arguments and launch shape of forward term t (band or direct kernel).
+static Launch fwd_term_launch(const FwdArgs& a, int t, FwdBandArgs* args_out);
+static void plan_reduce(const FwdArgs& a, Launches& out);
+
 void plan_fwd_terms(const FwdArgs& a, Launches& out)
 {
-    const AngleSplit sp = a.split;
+    for (int t = 0; t < a.nterms; ++t) out.push_back(fwd_term_launch(a, t, nullptr));
+}
+
+void plan_fwd_fused(const FwdArgs& a, Launches& out)
+{
+    FwdMultiArgs m{};
+    Launch multi;
+    multi.variant = V_FWD_MULTI;
+    multi.block = 1024;
     for (int t = 0; t < a.nterms; ++t) {
+        FwdBandArgs fb;
+        const Launch L = fwd_term_launch(a, t, &fb);
+        if (L.variant != V_FWD_BAND) {
+            out.push_back(L);
+            continue;
+        }
+        m.t[m.n] = fb;
+        m.gx[m.n] = (int)L.gx;
+        m.start[m.n + 1] = m.start[m.n] + (int)(L.gx * L.gy);
+        multi.lds = std::max(multi.lds, L.lds);
+        ++m.n;
+    }
+    if (m.n > 0) {
+        multi.gx = (unsigned)m.start[m.n];
+        multi.set(m);
+        out.push_back(multi);
+    }
+    plan_reduce(a, out);
+}
+
+static Launch fwd_term_launch(const FwdArgs& a, int t, FwdBandArgs* args_out)
+{
+    const AngleSplit sp = a.split;
+    {
         const FwdTerm& tm = a.term[t];
         FwdBandArgs fb{};
         fb.consts = a.consts;
@@ -1940,7 +2018,8 @@ void plan_fwd_terms(const FwdArgs& a, Launches& out)
             L.lds = 0;
         }
         L.set(fb);
-        out.push_back(L);
+        if (args_out) *args_out = fb;
+        return L;
     }
 }
 
@@ -2221,6 +2300,108 @@ void plan_bp_primal(const BpArgs& ba, const PrimalArgs& pr, Launches& out)
     out.push_back(L);
 }
 
+bool plan_bp_coarse(const BpArgs* ba, int n, size_t part_floats, bool fused, int round, Launches& out)
+{
+    // each level's tile shape and angle groups, then fewer groups (halving
+    // the largest share) until all partial images fit side by side
+    BpOwnArgs own[IMASK_MAX_LEVELS];
+    int shape[IMASK_MAX_LEVELS], nb[IMASK_MAX_LEVELS];
+    for (int t = 0; t < n; ++t) {
+        Launches tmp;
+        plan_bp_main(ba[t], 0, tmp, &own[t]);
+        shape[t] = tmp.back().variant;
+        nb[t] = (int)tmp.back().gx;
+        if (shape[t] != V_BP28 && shape[t] != V_BP44) return false;  // no fused form of that tile
+    }
+    auto share = [&](int t) { return (size_t)own[t].nq * (size_t)(ba[t].n >> ba[t].lvl) * (ba[t].n >> ba[t].lvl); };
+    for (;;) {
+        size_t total = 0;
+        int big = 0;
+        for (int t = 0; t < n; ++t) {
+            total += share(t);
+            if (share(t) > share(big)) big = t;
+        }
+        if (total <= part_floats || own[big].G == 1) break;
+        own[big].G = std::max(1, own[big].G / 2);
+        own[big].nq = 2 * own[big].G;
+    }
+    size_t off = 0;
+    for (int t = 0; t < n; ++t) {
+        own[t].part = ba[t].part + off;
+        off += share(t);
+    }
+    if (!fused) {  // the same transposes and sums as records of their own (disjoint partial images)
+        for (int t = 0; t < n; ++t) {
+            const int nl = ba[t].n >> ba[t].lvl;
+            Launch L;
+            L.variant = shape[t];
+            L.round = round;
+            L.gx = (unsigned)nb[t];
+            L.gy = (unsigned)(2 * own[t].G);
+            L.block = shape[t] == V_BP28 ? 512 : 256;
+            L.lds = (int)(shape[t] == V_BP28 ? scatter_lds<2, 8>(nl) : scatter_lds<4, 4>(nl));
+            L.set(own[t]);
+            out.push_back(L);
+        }
+    }
+    for (int v : {V_BP28, V_BP44}) {
+        if (!fused) break;
+        BpMultiArgs m{};
+        Launch L;
+        L.variant = v == V_BP28 ? V_BP_MULTI28 : V_BP_MULTI44;
+        L.block = v == V_BP28 ? 512 : 256;
+        for (int t = 0; t < n; ++t) {
+            if (shape[t] != v) continue;
+            const int nl = ba[t].n >> ba[t].lvl;
+            m.t[m.n] = own[t];
+            m.gx[m.n] = nb[t];
+            m.start[m.n + 1] = m.start[m.n] + nb[t] * 2 * own[t].G;
+            L.lds = std::max(L.lds, (int)(v == V_BP28 ? scatter_lds<2, 8>(nl) : scatter_lds<4, 4>(nl)));
+            ++m.n;
+        }
+        if (m.n == 0) continue;
+        L.gx = (unsigned)m.start[m.n];
+        L.set(m);
+        out.push_back(L);
+    }
+    SumMultiArgs sm{};
+    sm.n = n;
+    for (int t = 0; t < n; ++t) {
+        const int nl = ba[t].n >> ba[t].lvl;
+        const size_t d = (size_t)nl * nl;
+        SumArgs sa{own[t], ba[t].tmp, 0};
+        size_t cells;
+        if (sum_cells_per_thread(d) == 4) {
+            sa.S = bp_sum_slices(d / 4, own[t].nq);
+            cells = 4 * (size_t)(1024 / sa.S);
+            sm.v[t] = 4;
+        } else {
+            sa.S = bp_sum_slices(d, own[t].nq);
+            cells = 1024 / sa.S;
+            sm.v[t] = 1;
+        }
+        sm.t[t] = sa;
+        sm.start[t + 1] = sm.start[t] + (int)((d + cells - 1) / cells);
+        if (!fused) {
+            Launch L;
+            L.variant = sm.v[t] == 4 ? V_SUM4 : V_SUM1;
+            L.round = round;
+            L.block = 1024;
+            L.gx = (unsigned)((d + cells - 1) / cells);
+            L.set(sa);
+            out.push_back(L);
+        }
+    }
+    if (!fused) return true;
+    Launch L;
+    L.variant = V_SUM_MULTI;
+    L.block = 1024;
+    L.gx = (unsigned)sm.start[n];
+    L.set(sm);
+    out.push_back(L);
+    return true;
+}
+
 // The ordered sum of the fan-beam transposes' partial images (and the
 // prolongation of either beam's result when asked for).
 static hipError_t launch_sum_after(const BpArgs& ba, const BpOwnArgs& a, hipStream_t s)
@@ -2322,6 +2503,10 @@ static const void* variant_kernel(int v)
     case V_SUMP4: return (const void*)k_bp_sum_primal<4>;
     case V_SUMP1: return (const void*)k_bp_sum_primal<1>;
     case V_PRIMAL: return (const void*)k_primal;
+    case V_FWD_MULTI: return (const void*)k_fwd_band_multi;
+    case V_BP_MULTI28: return (const void*)k_bp_own_multi<2, 8>;
+    case V_BP_MULTI44: return (const void*)k_bp_own_multi<4, 4>;
+    case V_SUM_MULTI: return (const void*)k_bp_sum_multi;
     default: return nullptr;
     }
 }
@@ -2364,6 +2549,14 @@ hipError_t launch_records(const Launches& recs, hipStream_t s)
             break;
         }
         case V_PRIMAL: hipLaunchKernelGGL(k_primal, grid, block, L.lds, s, L.get<PrimalArgs>()); break;
+        case V_FWD_MULTI: hipLaunchKernelGGL(k_fwd_band_multi, grid, block, L.lds, s, L.get<FwdMultiArgs>()); break;
+        case V_BP_MULTI28:
+            hipLaunchKernelGGL((k_bp_own_multi<2, 8>), grid, block, L.lds, s, L.get<BpMultiArgs>());
+            break;
+        case V_BP_MULTI44:
+            hipLaunchKernelGGL((k_bp_own_multi<4, 4>), grid, block, L.lds, s, L.get<BpMultiArgs>());
+            break;
+        case V_SUM_MULTI: hipLaunchKernelGGL(k_bp_sum_multi, grid, block, L.lds, s, L.get<SumMultiArgs>()); break;
         default: return hipErrorInvalidValue;
         }
         const hipError_t e = hipGetLastError();
@@ -2559,7 +2752,7 @@ template <int V>
 __global__ void __launch_bounds__(kVariantThreads<V>) k_batch(BatchView bv, int round, int lds_avail)
 {
     extern __shared__ float smem[];
-    __shared__ __attribute__((aligned(16))) unsigned char s_args[kLaunchArgBytes];
+    __shared__ __attribute__((aligned(16))) unsigned char s_args[kBlobBytes];
     const int n = bv.n;
     const int* off = bv.off + ((size_t)V * kRounds + round) * (n + 1);
     const int total = off[n];
@@ -2584,8 +2777,8 @@ __global__ void __launch_bounds__(kVariantThreads<V>) k_batch(BatchView bv, int 
         // the launch reserves the LDS of its largest record
         if (j >= nr || rec[j].lds > lds_avail) continue;
         const BatchRec rc = rec[j];
-        const uint4* src = reinterpret_cast<const uint4*>(bv.blobs + (size_t)rc.blob * kLaunchArgBytes);
-        for (int t = threadIdx.x; t < kLaunchArgBytes / 16; t += blockDim.x) reinterpret_cast<uint4*>(s_args)[t] = src[t];
+        const uint4* src = reinterpret_cast<const uint4*>(bv.blobs + (size_t)rc.blob * kBlobBytes);
+        for (int t = threadIdx.x; t < kBlobBytes / 16; t += blockDim.x) reinterpret_cast<uint4*>(s_args)[t] = src[t];
         __syncthreads();
         Blk bk;
         bk.x = local % rc.gx;
@@ -2639,7 +2832,7 @@ static const void* batch_kernel_of(int v)
 // ordered sums' reduction arrays.
 size_t variant_static_lds(int v)
 {
-    size_t s = kLaunchArgBytes;
+    size_t s = kBlobBytes;
     if (v == V_SUM4) s += 1024 * 4 * sizeof(float);
     if (v == V_SUM1) s += 1024 * sizeof(float);
     if (v == V_SUMP4) s += 3 * 1024 * 4 * sizeof(float);

@@ -298,3 +298,20 @@ def test_batched_workload_sizes_ten_iterations(n):
         x, y = host(prob.x_cur), host(prob.y_cur)
         assert rel(x, ost.x) <= 1e-4 and rel(y, ost.y) <= 1e-4
         assert max_rel(x, ost.x) <= 3e-4 and max_rel(y, ost.y) <= 3e-4
+
+
+@pytest.mark.parametrize("mode", [pk.FULL_PAPER, pk.FULL_UNBIASED])
+def test_eight_levels(mode):
+    """r = 8 (levels 256 ... 2 on a 256^2 grid, the depth of the paper's
+    Sec. 5 comparison): 40 iterations against the oracle."""
+    n, na, nd = 256, 96, 384
+    _, b = synth.ct_problem(n, na, nd, 1e5, 1007, 2007)
+    b = f32(b)
+    levels = tuple(range(8))
+    say(f"eight levels, mode {mode}")
+    ost, prob = _run_both(n, na, nd, b, levels, (1 / 8,) * 8, mode, oracle.Reg(lam=1e-2),
+                          pk.Regularizer(pk.REG_TIKHONOV, 1e-2), 2e-3, 40)
+    assert prob.epochs == ost.epochs
+    assert sorted(set(ost.draws)) == list(range(8))
+    assert rel(host(prob.x_cur), ost.x) <= 1e-4
+    assert rel(host(prob.y_cur), ost.y) <= 1e-4

@@ -228,3 +228,34 @@ def test_projection_is_deterministic():
     b1, b2 = pk.backproject(g, 1, y, work), pk.backproject(g, 1, y, work)
     torch.cuda.synchronize()
     assert torch.equal(a1, a2) and torch.equal(b1, b2)
+
+
+@pytest.mark.parametrize("n,na,nd", [(512, 720, 768), (96, 60, 150)])
+def test_unbiased_full_sketch_in_a_step_matches_oracle(n, na, nd):
+    """The UNBIASED full-resolution sketch K_0 = p_0^{-1}(R_0 - sum p_l R_l T_l)
+    and its transpose as one step of Alg. 1 applies them (forward terms in
+    one launch, the coarse transposes side by side in the partial-image
+    buffer, one launch per tile shape): from x, y random and zero tables
+    the first step (drawn sketch 0: stream 2) refreshes psi_0 = K_0 x and
+    phi_0 = K_0^T y, compared with the oracle's sketches (l2 and element
+    by element)."""
+    levels = (0, 1, 2, 3)
+    x = f32(synth.random_image(n, 51))
+    y = f32(synth.random_sinogram(na, nd, 52))
+    prob = pk.Problem(pk.Geometry(n, na, nd), pk.Levels.uniform(levels, pk.FULL_UNBIASED),
+                      pk.Regularizer(pk.REG_TIKHONOV, 1e-2), pk.Params(1e-3, 42, 2), dev(np.zeros((na, nd))))
+    assert int(pk.draws(prob.params, prob.levels, 0, 1)[0]) == 0
+    prob.x[0].copy_(dev(x))
+    prob.y[0].copy_(dev(y))
+    say(f"UNBIASED full sketch in a step, {n}^2")
+    prob.step(1)
+    og = oracle.Geometry(n, na, nd)
+    olv = oracle.Levels(list(levels), [0.25] * 4, oracle.MODE_UNBIASED)
+    fwd = oracle.sketch_fwd(og, olv, 0, x)
+    got = host(prob.psi[0])
+    assert rel(got, fwd) <= 1e-5
+    assert max_rel(got, fwd) <= 1e-5
+    adj = oracle.sketch_adj(og, olv, 0, y)
+    got = host(prob.phi_tables()[0])
+    assert rel(got, adj) <= 1e-5
+    assert max_rel(got, adj) <= 1e-5

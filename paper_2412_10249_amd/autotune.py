@@ -144,8 +144,9 @@ def main(argv=None) -> None:
         nd = args.bins or 3 * n // 2
         print(f"tuning {n}^2, {na} x {nd}", flush=True)
         table.update(tune_geometry(n, na, nd, reps=args.reps, log=lambda m: print(m, flush=True)))
-    doc = {"device": torch.cuda.get_device_name(0), "command": "python -m paper_2412_10249_amd.autotune "
-           + " ".join(argv if argv is not None else sys.argv[1:]), "tiles": table}
+    doc = {"device": torch.cuda.get_device_name(0), "arch": torch.cuda.get_device_properties(0).gcnArchName,
+           "command": "python -m paper_2412_10249_amd.autotune " + " ".join(argv if argv is not None else sys.argv[1:]),
+           "tiles": table}
     with open(args.out, "w") as f:
         json.dump(doc, f, indent=1)
     print(f"wrote {len(table)} entries to {args.out}", flush=True)

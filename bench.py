@@ -272,8 +272,11 @@ def run(args):
 
     import paper_2412_10249_amd as pk
     import synth
+    from paper_2412_10249_amd import autotune
 
     torch.cuda.set_device(0)
+    # the launch shapes the autotuner chose on MI355X (paper_2412_10249_amd/tiles.json)
+    n_tiles = 0 if args.default_tiles else autotune.apply_saved()
     if args.fan:  # exact integrals along the fan's rays
         _, b = synth.fan_ct_problem(N, NA, ND, FAN_D, FAN_DD, I0, 1000, 2000)
     else:
@@ -321,7 +324,7 @@ def run(args):
         # and gathers on levels 2-3
         name = {"fwd": "k_fwd_fan", "bp": "k_bp_fan_scatter" if dom[1] <= 1 else "k_bp_fan_gather"}[dom[0]]
     else:
-        name = {"fwd": "k_fwd_band" if (N >> dom[1]) <= 512 else "k_fwd_direct", "bp": "k_bp_own"}[dom[0]]
+        name = {"fwd": "k_fwd_band" if (N >> dom[1]) <= 1024 else "k_fwd_direct", "bp": "k_bp_own"}[dom[0]]
     key = f"{name}_l{dom[1]}"
     by_level = step_times_by_level(prob, lv, args.level_steps)
     t0_step = by_level.get(0)
@@ -345,7 +348,8 @@ def run(args):
                                "lambda=1e-3, levels 512/256/128/64 uniform p, ImaSk (PAPER sketches)"
                                + (f", {args.blocks} measurement blocks of {NA // args.blocks} angles"
                                   if args.blocks > 1 else ""),
-                   "steps_level_mix": [round(float(v), 4) for v in mix], "epochs_timed": epochs},
+                   "steps_level_mix": [round(float(v), 4) for v in mix], "epochs_timed": epochs,
+                   "tuned_tile_entries": n_tiles},
         "roofline": roofline_block(key, dom, dom_t, samples, args.fan),
         # the transpose's working limit: LDS traffic, two read-modify-writes of
         # 4-byte cells per sample, against 256 CUs x 128 B/clk x 2.4 GHz
@@ -1123,6 +1127,7 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--level-steps", type=int, default=200, help="steps timed one by one for the per-level table")
     ap.add_argument("--no-race", action="store_true", help="skip the time-to-1e-3 race in the main line")
+    ap.add_argument("--default-tiles", action="store_true", help="ignore the autotuned launch shapes")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving latencies in the main line")
     ap.add_argument("--headline-rates", type=float, nargs="+", default=[200.0, 150.0])
     ap.add_argument("--headline-race-seconds", type=float, default=45.0,

@@ -9,8 +9,8 @@ imask_set_tiles.  Shapes change only the order of floating-point sums, never
 the matrices, so any table gives a correct projector.
 
 Usage (on the GPU):
-  python -m paper_2412_10249_amd.autotune            # the batched workload's grids
-  python -m paper_2412_10249_amd.autotune --n 512 --angles 720 --bins 768
+  python -m paper_2412_10249_amd.autotune            # the default geometries below
+  python -m paper_2412_10249_amd.autotune --geometry 512x720x768
 """
 from __future__ import annotations
 
@@ -83,7 +83,7 @@ def tune_geometry(n: int, na: int, nd: int, levels=(0, 1, 2, 3), reps: int = 10,
                 if t < best_bp[0]:
                     best_bp = (t, shape, wg)
         best_fwd = (base_fwd, 0)
-        if nl <= 512:  # larger levels use the direct forward (no bands)
+        if nl <= 1024:  # larger levels use the direct forward (no bands)
             for kb in FWD_BUDGETS_KB:
                 if kb < default_fwd_kb(nl):
                     continue
@@ -127,11 +127,14 @@ def apply_saved(path: str = TILES_JSON) -> int:
     return apply(load(path))
 
 
+# The geometries tuned by default: the 512^2 / 720 x 768 workload and the
+# batched workload's grids (angles = bins = 1.5 N).
+DEFAULT_GEOMETRIES = ["512x720x768"] + [f"{n}x{3 * n // 2}x{3 * n // 2}" for n in (256, 384, 512, 768, 1024)]
+
+
 def main(argv=None) -> None:
     ap = argparse.ArgumentParser()
-    ap.add_argument("--n", type=int, nargs="+", default=[256, 384, 512, 768, 1024])
-    ap.add_argument("--angles", type=int, default=0, help="angles (0: 1.5 N)")
-    ap.add_argument("--bins", type=int, default=0, help="bins (0: 1.5 N)")
+    ap.add_argument("--geometry", nargs="+", default=DEFAULT_GEOMETRIES, help="N x angles x bins, e.g. 512x720x768")
     ap.add_argument("--reps", type=int, default=10)
     ap.add_argument("--out", default=TILES_JSON)
     args = ap.parse_args(argv)
@@ -139,9 +142,8 @@ def main(argv=None) -> None:
 
     torch.cuda.set_device(0)
     table = {}
-    for n in args.n:
-        na = args.angles or 3 * n // 2
-        nd = args.bins or 3 * n // 2
+    for geo in args.geometry:
+        n, na, nd = (int(v) for v in geo.split("x"))
         print(f"tuning {n}^2, {na} x {nd}", flush=True)
         table.update(tune_geometry(n, na, nd, reps=args.reps, log=lambda m: print(m, flush=True)))
     doc = {"device": torch.cuda.get_device_name(0), "arch": torch.cuda.get_device_properties(0).gcnArchName,

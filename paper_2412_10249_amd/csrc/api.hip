@@ -103,7 +103,7 @@ Layout make_layout(const imask_geometry& g)
         }
         // sized for the default band layout; tuned shapes use no more bands
         int cap = L.fbands[l], rows_cap = 0;
-        if (!is_fan(g)) fwd_bands_default(side(g.n, l), &cap, &rows_cap);
+        if (!is_fan(g)) fwd_bands_default(side(g.n, l), g.n_angles, g.n_det, &cap, &rows_cap);
         L.fpart[l] = off;
         off = align64(off + (size_t)std::max(cap, L.fbands[l]) * m);
     }
@@ -467,8 +467,7 @@ static void step_records(const imask_geometry& g, const Layout& L, const imask_l
             // free for the coarse levels side by side: one launch per
             // direction when fused (the single-problem path), the same
             // launches one by one in the batched path
-            if (!plan_bp_coarse(coarse, lv.r - 1, L.part_floats, multi, 1, out))
-                for (int j = 1; j < lv.r; ++j) plan_bp(coarse[j - 1], j, out);
+            plan_bp_coarse(coarse, lv.r - 1, L.part_floats, multi, 1, out);
         }
         plan_primal(pr, out);
     }
@@ -649,7 +648,8 @@ static int one_step(const imask_geometry& g, const Layout& L, const imask_levels
 constexpr int kMaxBatch = 4096;
 
 struct BatchLayout {
-    size_t prob = 0, rec = 0, nrec = 0, items = 0, off = 0, sel = 0, blobs = 0, total = 0;  // bytes
+    size_t prob = 0, rec = 0, nrec = 0, items = 0, off = 0, sel = 0, nsegs = 0, segc = 0, seg_off = 0, seg = 0,
+           rank = 0, blobs = 0, total = 0;  // bytes
 };
 
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
@@ -669,6 +669,16 @@ static BatchLayout batch_layout(int n, int r_max, size_t nblobs)
     B.off = o;
     o = align256(o + (size_t)kNumVariants * kRounds * (n + 1) * sizeof(int));
     B.sel = o;
+    o = align256(o + (size_t)n * sizeof(int));
+    B.nsegs = o;
+    o = align256(o + (size_t)n * r_max * 2 * kNumVariants * kRounds * sizeof(int));
+    B.segc = o;
+    o = align256(o + (size_t)kNumVariants * kRounds * (n + 1) * sizeof(int));
+    B.seg_off = o;
+    o = align256(o + (size_t)(kNumVariants * kRounds + 1) * sizeof(int));
+    B.seg = o;
+    o = align256(o + (size_t)n * kMaxRec * 2 * sizeof(int));
+    B.rank = o;
     o = align256(o + (size_t)n * sizeof(int));
     B.blobs = o;
     o = align256(o + nblobs * kBlobBytes);
@@ -690,6 +700,11 @@ static BatchView batch_view(void* batch, int n, int r_max)
     v.blobs = base + B.blobs;
     v.off = (int*)(base + B.off);
     v.sel = (int*)(base + B.sel);
+    v.nsegs = (const int*)(base + B.nsegs);
+    v.segc = (int*)(base + B.segc);
+    v.seg_off = (int*)(base + B.seg_off);
+    v.seg = (int*)(base + B.seg);
+    v.rank = (const int*)(base + B.rank);
     return v;
 }
 
@@ -727,6 +742,9 @@ static void shape_records(const imask_geometry& g, const imask_levels& lv, int k
     step_records(g, L, lv, reg, prm, fake, st, k, out, false);
 }
 
+// The stage slot of a launch: its round and LDS class.
+static int stage_slot(const Launch& L) { return L.round * kLdsClasses + lds_class(L.lds); }
+
 // Per (variant, round): the largest dynamic LDS and the sum over problems of
 // their largest item count, from the shapes alone.  The two reduce variants
 // differ only in the alignment of the caller's buffers, so both are sized
@@ -750,8 +768,9 @@ static void batch_shapes(int n, const imask_geometry* g, const imask_levels* lv,
             blobs += 2 * recs.size();
             long long it[kNumVariants][kRounds] = {};
             for (const Launch& L : recs) {
-                it[L.variant][L.round] += (long long)L.gx * L.gy * L.gz;
-                sh.lds[L.variant][L.round] = std::max(sh.lds[L.variant][L.round], L.lds);
+                const int slot = stage_slot(L);
+                it[L.variant][slot] += (long long)L.gx * L.gy * L.gz;
+                sh.lds[L.variant][slot] = std::max(sh.lds[L.variant][slot], L.lds);
                 sh.rounds = std::max(sh.rounds, L.round + 1);
             }
             for (int v = 0; v < kNumVariants; ++v)
@@ -1066,6 +1085,15 @@ int imask_batch_prepare(int32_t n_problems, const imask_geometry* g, const imask
     BatchRec* recs = (BatchRec*)(img.data() + B.rec);
     int* nrec = (int*)(img.data() + B.nrec);
     int* items = (int*)(img.data() + B.items);
+    int* nsegs = (int*)(img.data() + B.nsegs);
+    // work order: the problems with the most samples per step first
+    {
+        std::vector<std::pair<double, int>> work(n);
+        for (int q = 0; q < n; ++q) work[q] = {-(double)g[q].n * g[q].n_angles * g[q].n_det, q};
+        std::stable_sort(work.begin(), work.end());
+        int* rank = (int*)(img.data() + B.rank);
+        for (int i = 0; i < n; ++i) rank[work[i].second] = i;
+    }
     unsigned char* blobs = img.data() + B.blobs;
     int64_t steps = 0;
     size_t blob = 0;
@@ -1101,14 +1129,15 @@ int imask_batch_prepare(int32_t n_problems, const imask_geometry* g, const imask
                 step_records(g[q], L, lv[q], reg[q], prm[q], b[q], st, k, rl, false);
                 if ((int)rl.size() > kMaxRec) return IMASK_ENOTSUP;
                 for (const Launch& La : rl)
-                    if (La.variant >= kNumVariants || variant_phase(La.variant) < 0) return IMASK_ENOTSUP;
+                    if (La.variant >= kNumVariants || variant_phase(La.variant) < 0 || stage_slot(La) >= kRounds)
+                        return IMASK_ENOTSUP;
                 const size_t slot = ((size_t)q * r_max + k) * 2 + c;
                 nrec[slot] = (int)rl.size();
                 for (size_t t = 0; t < rl.size(); ++t) {
                     const Launch& La = rl[t];
                     BatchRec& R = recs[slot * kMaxRec + t];
                     R.variant = La.variant;
-                    R.round = La.round;
+                    R.round = stage_slot(La);
                     R.blob = (int)blob;
                     R.gx = (int)La.gx;
                     R.gy = (int)La.gy;
@@ -1117,7 +1146,8 @@ int imask_batch_prepare(int32_t n_problems, const imask_geometry* g, const imask
                     R.lds = La.lds;
                     std::memcpy(blobs + blob * kBlobBytes, La.args, kBlobBytes);
                     ++blob;
-                    items[(slot * kNumVariants + La.variant) * kRounds + La.round] += R.items;
+                    items[(slot * kNumVariants + La.variant) * kRounds + R.round] += R.items;
+                    nsegs[(slot * kNumVariants + La.variant) * kRounds + R.round] += 1;
                 }
             }
     }
@@ -1153,17 +1183,21 @@ int imask_batch_step(int32_t n_problems, const imask_geometry* g, const imask_le
     for (int it = 0; it < n_steps; ++it) {
         IMK_TRY(launch_batch_plan(bv, s));
         // every variant runs in its phase of the step, in enum order
-        for (int v = 0; v < kNumVariants; ++v)
-            if (variant_phase(v) == 0)
-                if (int rc = stage(v, 0)) return rc;
-        for (int j = 0; j < sh.rounds; ++j)
-            for (int ph = 1; ph <= 2; ++ph)
-                for (int v = 0; v < kNumVariants; ++v)
-                    if (variant_phase(v) == ph)
+        // each phase runs its variants' slots in order: rounds, and within
+        // a round the LDS classes
+        auto phase = [&](int ph, int j0, int j1) -> int {
+            for (int v = 0; v < kNumVariants; ++v)
+                if (variant_phase(v) == ph)
+                    for (int j = j0; j < j1; ++j)
                         if (int rc = stage(v, j)) return rc;
-        for (int v = 0; v < kNumVariants; ++v)
-            if (variant_phase(v) == 3)
-                if (int rc = stage(v, 0)) return rc;
+            return IMASK_OK;
+        };
+        if (int rc = phase(0, 0, kRounds)) return rc;
+        for (int r = 0; r < sh.rounds; ++r) {
+            if (int rc = phase(1, r * kLdsClasses, (r + 1) * kLdsClasses)) return rc;
+            if (int rc = phase(2, r * kLdsClasses, (r + 1) * kLdsClasses)) return rc;
+        }
+        if (int rc = phase(3, 0, kRounds)) return rc;
         IMK_TRY(launch_batch_advance(bv, s));
     }
     return IMASK_OK;

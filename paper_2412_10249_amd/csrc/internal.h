@@ -329,7 +329,7 @@ struct TvArgs {
 // bands of rows); rows == 0 selects the direct (global-memory) kernel.
 // fwd_bands_default is the layout the workspace is sized for; fwd_bands
 // the one the launches use (the tuned LDS budget, never more bands).
-void fwd_bands_default(int nl, int* bands, int* rows);
+void fwd_bands_default(int nl, int na, int nd, int* bands, int* rows);
 void fwd_bands(int nl, int na, int nd, int* bands, int* rows);
 
 // Tunable launch shapes of the levels of one grid side and detector
@@ -488,15 +488,22 @@ void plan_primal(const PrimalArgs& a, Launches& out);
 void plan_fwd_fused(const FwdArgs& a, Launches& out);
 // The coarse transposes with their partial images side by side in the
 // buffer (groups reduced to fit); `fused`: one launch per tile shape and
-// one for the sums, else the same launches as separate records of `round`.
-// false (nothing added) when a level's tile has no fused form.
+// one for the sums, else (or when a level's tile has no fused form) the
+// same transposes and sums as separate records of `round`.  Returns
+// whether the fused launches were used.
 bool plan_bp_coarse(const BpArgs* ba, int n, size_t part_floats, bool fused, int round, Launches& out);
 hipError_t launch_records(const Launches& recs, hipStream_t s);
 
 // ---- batched steps (many problems, one launch per kernel variant) ----
 
 constexpr int kMaxRec = 32;  // launches of one step of one problem
-constexpr int kRounds = IMASK_MAX_LEVELS;
+// Stage slots of a variant: round (0: level 0's transpose, 1: the coarse
+// transposes of an UNBIASED full-resolution sketch) times LDS class (the
+// launches of one slot reserve the largest LDS among them, so launches of
+// very different LDS needs run in separate slots).
+constexpr int kLdsClasses = 4;
+constexpr int kRounds = 2 * kLdsClasses;
+inline int lds_class(int lds) { return lds <= 40 * 1024 ? 0 : lds <= 52 * 1024 ? 1 : lds <= 80 * 1024 ? 2 : 3; }
 
 // Per-problem counters, advanced on the device.  The sketch index of step k
 // is drawn on the device from the same SplitMix64 stream as the host draw.
@@ -529,6 +536,11 @@ struct BatchView {
     const unsigned char* blobs;  // argument blocks, kBlobBytes each
     int* off;                // [kNumVariants][kRounds][n + 1]: per-step item offsets
     int* sel;                // [n]: this step's (sketch index, parity) slot, -1 when idle
+    const int* nsegs;        // [n][r_max][2][kNumVariants][kRounds]: records of each stage slot
+    int* segc;               // [kNumVariants][kRounds][n + 1]: per-step record offsets per problem
+    int* seg_off;            // [kNumVariants * kRounds + 1]: first segment of each stage slot
+    int* seg;                // [n kMaxRec][2]: per-step (record index, first item) of each stage slot's records
+    const int* rank;         // [n]: position of problem q in the work order (largest problems first)
 };
 
 int variant_threads(int v);

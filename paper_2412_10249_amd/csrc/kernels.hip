@@ -910,7 +910,10 @@ __global__ void __launch_bounds__(256) k_fwd_reduce4(FwdArgs a) { fwd_reduce4_bo
 // one instruction.
 // The tile shape (rows per wavefront R, wavefronts per workgroup W) is a
 // template parameter; the launcher picks it per level.
-constexpr int kBpChunks = 2;  // 64-ray chunks per trip of a wavefront
+#ifndef IMK_BP_CHUNKS
+#define IMK_BP_CHUNKS 2
+#endif
+constexpr int kBpChunks = IMK_BP_CHUNKS;  // 64-ray chunks per trip of a wavefront
 template <int R, int W>
 struct BpShape {
     static constexpr int rows = R * W;   // rows of a workgroup
@@ -1913,27 +1916,40 @@ bool set_tiles(int nl, int na, int nd, const Tiles* t)
     return true;
 }
 
-static void bands_for_budget(int nl, int bytes, int* bands, int* rows)
+// Levels of up to 1024 pixels per side take LDS bands (1024: 27 bands of
+// 38 rows; measured 541 against 1688 us for the direct kernel at level 0 of
+// 1024^2 / 1536 x 1536, 201 against 632 us for 768^2 / 1152 x 1152), as long
+// as their partial sinograms stay within 512 MiB; longer rows take the
+// direct kernel.
+#ifndef IMK_BAND_MAX_SIDE
+#define IMK_BAND_MAX_SIDE 1024
+#endif
+constexpr size_t kBandPartialBytes = (size_t)512 << 20;
+
+static void bands_for_budget(int nl, size_t m, int bytes, int* bands, int* rows)
 {
-    if (nl > 512) {  // rows of more than 2 KB: too few per band, use the direct kernel
-        *bands = 1;
+    const int maxr = bytes / (int)(sizeof(float) * (nl + kPad));
+    const int nb = (nl + maxr - 1) / maxr;
+    if (nl > IMK_BAND_MAX_SIDE || (nb > 1 && (size_t)nb * m * sizeof(float) > kBandPartialBytes)) {
+        *bands = 1;  // the direct kernel: one partial
         *rows = 0;
         return;
     }
-    const int maxr = bytes / (int)(sizeof(float) * (nl + kPad));
-    const int nb = (nl + maxr - 1) / maxr;
     *bands = nb;
     *rows = (nl + nb - 1) / nb;
 }
 
-void fwd_bands_default(int nl, int* bands, int* rows) { bands_for_budget(nl, fwd_lds_bytes(nl), bands, rows); }
+void fwd_bands_default(int nl, int na, int nd, int* bands, int* rows)
+{
+    bands_for_budget(nl, (size_t)na * nd, fwd_lds_bytes(nl), bands, rows);
+}
 
 void fwd_bands(int nl, int na, int nd, int* bands, int* rows)
 {
     const Tiles t = tiles_for(nl, na, nd);
     int bytes = fwd_lds_bytes(nl);
     if (t.fwd_lds_kb > 0) bytes = std::max(bytes, std::min(t.fwd_lds_kb, 156) * 1024);
-    bands_for_budget(nl, bytes, bands, rows);
+    bands_for_budget(nl, (size_t)na * nd, bytes, bands, rows);
 }
 
 static hipError_t allow_lds(const void* fn, int bytes)
@@ -2302,16 +2318,21 @@ void plan_bp_primal(const BpArgs& ba, const PrimalArgs& pr, Launches& out)
 
 bool plan_bp_coarse(const BpArgs* ba, int n, size_t part_floats, bool fused, int round, Launches& out)
 {
+    // (always succeeds; the result says whether the fused launches were used)
     // each level's tile shape and angle groups, then fewer groups (halving
     // the largest share) until all partial images fit side by side
     BpOwnArgs own[IMASK_MAX_LEVELS];
-    int shape[IMASK_MAX_LEVELS], nb[IMASK_MAX_LEVELS];
+    int shape[IMASK_MAX_LEVELS], nb[IMASK_MAX_LEVELS], block[IMASK_MAX_LEVELS], lds[IMASK_MAX_LEVELS];
     for (int t = 0; t < n; ++t) {
         Launches tmp;
         plan_bp_main(ba[t], 0, tmp, &own[t]);
         shape[t] = tmp.back().variant;
         nb[t] = (int)tmp.back().gx;
-        if (shape[t] != V_BP28 && shape[t] != V_BP44) return false;  // no fused form of that tile
+        block[t] = tmp.back().block;
+        lds[t] = tmp.back().lds;
+        // the fused launches exist for the 2x8 and 4x4 tiles; other tiles
+        // run as records of their own with the same partial-image layout
+        if (shape[t] != V_BP28 && shape[t] != V_BP44) fused = false;
     }
     auto share = [&](int t) { return (size_t)own[t].nq * (size_t)(ba[t].n >> ba[t].lvl) * (ba[t].n >> ba[t].lvl); };
     for (;;) {
@@ -2332,14 +2353,13 @@ bool plan_bp_coarse(const BpArgs* ba, int n, size_t part_floats, bool fused, int
     }
     if (!fused) {  // the same transposes and sums as records of their own (disjoint partial images)
         for (int t = 0; t < n; ++t) {
-            const int nl = ba[t].n >> ba[t].lvl;
             Launch L;
             L.variant = shape[t];
             L.round = round;
             L.gx = (unsigned)nb[t];
             L.gy = (unsigned)(2 * own[t].G);
-            L.block = shape[t] == V_BP28 ? 512 : 256;
-            L.lds = (int)(shape[t] == V_BP28 ? scatter_lds<2, 8>(nl) : scatter_lds<4, 4>(nl));
+            L.block = block[t];
+            L.lds = lds[t];
             L.set(own[t]);
             out.push_back(L);
         }
@@ -2392,7 +2412,7 @@ bool plan_bp_coarse(const BpArgs* ba, int n, size_t part_floats, bool fused, int
             out.push_back(L);
         }
     }
-    if (!fused) return true;
+    if (!fused) return false;
     Launch L;
     L.variant = V_SUM_MULTI;
     L.block = 1024;
@@ -2664,7 +2684,9 @@ __device__ __forceinline__ unsigned long long batch_mix(unsigned long long state
 }
 
 // Draws each active problem's sketch index, selects its records and forms,
-// per (variant, round), the running offsets of the problems' work items.
+// per stage slot (variant, round), the running offsets of the problems' work
+// items and a list of segments, one per record of that slot (its index and
+// its first item), which the stage kernels search.
 __global__ void __launch_bounds__(1024) k_batch_plan(BatchView bv)
 {
     const int n = bv.n;
@@ -2679,14 +2701,53 @@ __global__ void __launch_bounds__(1024) k_batch_plan(BatchView bv)
             sl = j * 2 + pb.cur;
         }
         bv.sel[q] = sl;
-        const int* it = sl >= 0 ? bv.items + ((size_t)q * bv.r_max * 2 + sl) * slots : nullptr;
-        for (int vr = 0; vr < slots; ++vr) bv.off[(size_t)vr * (n + 1) + q + 1] = it ? it[vr] : 0;
+        // offsets follow the work order (largest problems first, so their
+        // long items start early and the short ones fill the tail)
+        const int pos = bv.rank[q];
+        const size_t base = ((size_t)q * bv.r_max * 2 + (sl >= 0 ? sl : 0)) * slots;
+        for (int vr = 0; vr < slots; ++vr) {
+            bv.off[(size_t)vr * (n + 1) + pos + 1] = sl >= 0 ? bv.items[base + vr] : 0;
+            bv.segc[(size_t)vr * (n + 1) + pos + 1] = sl >= 0 ? bv.nsegs[base + vr] : 0;
+        }
     }
     __syncthreads();
     for (int vr = threadIdx.x; vr < slots; vr += blockDim.x) {
         int* o = bv.off + (size_t)vr * (n + 1);
+        int* c = bv.segc + (size_t)vr * (n + 1);
         o[0] = 0;
-        for (int q = 0; q < n; ++q) o[q + 1] += o[q];
+        c[0] = 0;
+        for (int q = 0; q < n; ++q) {
+            o[q + 1] += o[q];
+            c[q + 1] += c[q];
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        bv.seg_off[0] = 0;
+        for (int vr = 0; vr < slots; ++vr) bv.seg_off[vr + 1] = bv.seg_off[vr] + bv.segc[(size_t)vr * (n + 1) + n];
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < n; q += blockDim.x) {
+        const int sl = bv.sel[q];
+        if (sl < 0) continue;
+        const size_t r0 = ((size_t)q * bv.r_max * 2 + sl) * kMaxRec;
+        const int nr = bv.nrec[(size_t)q * bv.r_max * 2 + sl];
+        for (int j = 0; j < nr; ++j) {
+            const BatchRec& rc = bv.rec[r0 + j];
+            const int vr = rc.variant * kRounds + rc.round;
+            int before = 0, items_before = 0;  // earlier records of the same slot
+            for (int t = 0; t < j; ++t) {
+                const BatchRec& e = bv.rec[r0 + t];
+                if (e.variant == rc.variant && e.round == rc.round) {
+                    ++before;
+                    items_before += e.items;
+                }
+            }
+            const int rq = bv.rank[q];
+            const int pos = bv.seg_off[vr] + bv.segc[(size_t)vr * (n + 1) + rq] + before;
+            bv.seg[2 * pos] = (int)(r0 + j);
+            bv.seg[2 * pos + 1] = bv.off[(size_t)vr * (n + 1) + rq] + items_before;
+        }
     }
 }
 
@@ -2748,35 +2809,37 @@ constexpr int kVariantThreads = (V == V_FWD_BAND || V == V_SUM4 || V == V_SUM1 |
 // w, w + grid, ... of the step's list; an item is one workgroup of one
 // problem's launch, found from the offsets by binary search.  The argument
 // block is staged in LDS, where every thread reads it.
+constexpr int kSegLds = 256;  // segment starts a stage kernel keeps in LDS (more: searched in memory)
+
 template <int V>
 __global__ void __launch_bounds__(kVariantThreads<V>) k_batch(BatchView bv, int round, int lds_avail)
 {
     extern __shared__ float smem[];
     __shared__ __attribute__((aligned(16))) unsigned char s_args[kBlobBytes];
+    __shared__ int s_start[kSegLds];
     const int n = bv.n;
-    const int* off = bv.off + ((size_t)V * kRounds + round) * (n + 1);
-    const int total = off[n];
+    const int vr = V * kRounds + round;
+    const int total = bv.off[(size_t)vr * (n + 1) + n];
+    const int s0 = bv.seg_off[vr], nseg = bv.seg_off[vr + 1] - s0;
+    const int* seg = bv.seg + 2 * (size_t)s0;
+    const bool in_lds = nseg <= kSegLds;
+    if (in_lds) {
+        for (int t = threadIdx.x; t < nseg; t += blockDim.x) s_start[t] = seg[2 * t + 1];
+        __syncthreads();
+    }
     for (int item = blockIdx.x; item < total; item += gridDim.x) {
-        int lo = 0, hi = n;  // off[lo] <= item < off[hi]
+        int lo = 0, hi = nseg;  // start[lo] <= item < start[hi]
         while (hi - lo > 1) {
             const int mid = (lo + hi) >> 1;
-            if (off[mid] <= item) lo = mid; else hi = mid;
+            const int st = in_lds ? s_start[mid] : seg[2 * mid + 1];
+            if (st <= item) lo = mid; else hi = mid;
         }
-        const int q = __builtin_amdgcn_readfirstlane(lo);
-        int local = item - off[q];
-        const int sl = bv.sel[q];
-        const BatchRec* rec = bv.rec + ((size_t)q * bv.r_max * 2 + sl) * kMaxRec;
-        const int nr = bv.nrec[(size_t)q * bv.r_max * 2 + sl];
-        int j = 0;
-        for (; j < nr; ++j) {
-            if (rec[j].variant != V || rec[j].round != round) continue;
-            if (local < rec[j].items) break;
-            local -= rec[j].items;
-        }
-        // unreachable: the offsets count exactly these records' items, and
-        // the launch reserves the LDS of its largest record
-        if (j >= nr || rec[j].lds > lds_avail) continue;
-        const BatchRec rc = rec[j];
+        const int sgi = __builtin_amdgcn_readfirstlane(lo);
+        const int local = item - seg[2 * sgi + 1];
+        const BatchRec rc = bv.rec[seg[2 * sgi]];
+        // unreachable: the segments cover exactly these items, and the
+        // launch reserves the LDS of its largest record
+        if (rc.variant != V || local >= rc.items || rc.lds > lds_avail) continue;
         const uint4* src = reinterpret_cast<const uint4*>(bv.blobs + (size_t)rc.blob * kBlobBytes);
         for (int t = threadIdx.x; t < kBlobBytes / 16; t += blockDim.x) reinterpret_cast<uint4*>(s_args)[t] = src[t];
         __syncthreads();
@@ -2828,11 +2891,11 @@ static const void* batch_kernel_of(int v)
     }
 }
 
-// Static LDS of a batched variant: the staged argument block, plus the
-// ordered sums' reduction arrays.
+// Static LDS of a batched variant: the staged argument block and segment
+// starts, plus the ordered sums' reduction arrays.
 size_t variant_static_lds(int v)
 {
-    size_t s = kBlobBytes;
+    size_t s = kBlobBytes + kSegLds * sizeof(int);
     if (v == V_SUM4) s += 1024 * 4 * sizeof(float);
     if (v == V_SUM1) s += 1024 * sizeof(float);
     if (v == V_SUMP4) s += 3 * 1024 * 4 * sizeof(float);

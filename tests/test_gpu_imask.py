@@ -236,7 +236,13 @@ def test_bench_workload_ten_epochs():
     reg_o = oracle.Reg(oracle.REG_SMOOTH_TV, lam=1e-3, tv_weight=2e-4, tv_eps=1e-3, tv_inner=10)
     reg_g = pk.Regularizer(pk.REG_SMOOTH_TV, 1e-3, 2e-4, 1e-3, 10)
     say("bench workload, 21 iterations")
-    ost, prob = _run_both(n, na, nd, b, (0, 1, 2, 3), (0.25,) * 4, pk.FULL_PAPER, reg_o, reg_g, 1e-3, 21)
+    from paper_2412_10249_amd import autotune
+    table = autotune.load()
+    autotune.apply(table)  # the tuned launch shapes bench.py applies
+    try:
+        ost, prob = _run_both(n, na, nd, b, (0, 1, 2, 3), (0.25,) * 4, pk.FULL_PAPER, reg_o, reg_g, 1e-3, 21)
+    finally:
+        autotune.reset(table)
     assert prob.epochs == ost.epochs > 10.0
     assert rel(host(prob.x_cur), ost.x) <= 1e-3
     assert rel(host(prob.y_cur), ost.y) <= 1e-3

@@ -237,6 +237,16 @@ struct FwdBandArgs {
     float* part;
     int R, bands, apg, groups_row, groups_col;
     AngleSplit split;
+    // single band and single term: the dual step of Alg. 1 in the epilogue
+    // (the reduce's arithmetic, element by element; no partial is written)
+    int dual;
+    const float* y_old;
+    const float* bdat;
+    float* y_new;
+    float* psi;
+    int r, kidx;
+    float p[IMASK_MAX_LEVELS];
+    float sigma, inv1ps;
 };
 
 struct BpOwnArgs {
@@ -415,7 +425,7 @@ enum Variant {
     V_BP_MULTI44,
     V_SUM_MULTI
 };
-constexpr int kLaunchArgBytes = 2048;
+constexpr int kLaunchArgBytes = 3072;
 constexpr int kBlobBytes = 640;  // argument blocks of the batched variants
 
 // Several levels in one launch: block b belongs to part t when

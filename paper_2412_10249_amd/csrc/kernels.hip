@@ -360,7 +360,20 @@ __device__ __forceinline__ void fwd_band_body(const FwdBandArgs& a, const Blk& b
                                 (long long)((lo - i0) * P + kPadL) * 4294967296LL;
             acc = band_sum(band, U, kc.afx + rowfx, hi - lo + 1);
         }
-        a.part[(size_t)bi * m + (size_t)ang * a.nd + b] = kc.w * acc;
+        const float total = kc.w * acc;
+        if (a.dual) {
+            // the reduce's dual step for this ray: zeta = psi_new - psi_k +
+            // sum_j p_j psi_j (old tables), y+ = (y + sigma zeta - sigma b)/(1 + sigma)
+            const size_t e = (size_t)ang * a.nd + b;
+            float avg = 0.0f;
+            for (int j = 0; j < a.r; ++j) avg = fmaf(a.p[j], a.psi[(size_t)j * m + e], avg);
+            float* pk = a.psi + (size_t)a.kidx * m + e;
+            const float zeta = (total - *pk) + avg;
+            a.y_new[e] = (a.y_old[e] + a.sigma * zeta - a.sigma * a.bdat[e]) * a.inv1ps;
+            *pk = total;
+        } else {
+            a.part[(size_t)bi * m + (size_t)ang * a.nd + b] = total;
+        }
         b += blockDim.x;
         while (b >= a.nd) {
             b -= a.nd;
@@ -2060,6 +2073,26 @@ static void plan_reduce(const FwdArgs& a, Launches& out)
 
 void plan_fwd(const FwdArgs& a, Launches& out)
 {
+    const size_t m = (size_t)a.na * a.nd;
+    const bool single = a.mode == FWD_DUAL && a.nterms == 1 && a.term[0].rows > 0 && a.term[0].bands == 1 &&
+                        !a.compact && !a.fan.ray && a.e0 == 0 && a.e1 == (long long)m && a.term[0].coef == 1.0f;
+    if (single) {  // one band, one term: the dual step in the band kernel's epilogue, no reduce
+        FwdBandArgs fb;
+        Launch L = fwd_term_launch(a, 0, &fb);
+        fb.dual = 1;
+        fb.y_old = a.y_old;
+        fb.bdat = a.bdat;
+        fb.y_new = a.y_new;
+        fb.psi = a.psi;
+        fb.r = a.r;
+        fb.kidx = a.kidx;
+        for (int j = 0; j < IMASK_MAX_LEVELS; ++j) fb.p[j] = a.p[j];
+        fb.sigma = a.sigma;
+        fb.inv1ps = a.inv1ps;
+        L.set(fb);
+        out.push_back(L);
+        return;
+    }
     plan_fwd_terms(a, out);
     plan_reduce(a, out);
 }

@@ -728,6 +728,8 @@ def batched(args):
                 variant for all slices, draws on the device, one captured
                 step replayed as a CUDA graph; with the autotuned tiles
                 (paper_2412_10249_amd/tiles.json) and with the defaults
+                and with the step's forward and transpose halves on two
+                streams inside the graph
       streams   each slice's own steps, dealt round-robin to 8 HIP streams
       alone     the slices one after another on one stream
     Aggregate samples/s, and every batched slice compared with its run alone."""
@@ -767,12 +769,12 @@ def batched(args):
     samples_per_epoch = sum(2 * s0[sizes[s % 5]] for s in range(args.slices))
     res = {"metric": "batched ImaSk, 64 mixed slices", "slices": args.slices, "epochs_per_slice": args.epochs}
 
-    def run_batched(tiles):
+    def run_batched(tiles, overlapped=False):
         table = autotune.load() if tiles else {}
         autotune.apply(table)
         probs = make()
         bt = batch.Batch(probs, args.epochs, pk.BUDGET_EPOCHS)
-        bt.capture()
+        bt.capture(overlapped=overlapped)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         bt.replay(bt.steps)
@@ -782,14 +784,21 @@ def batched(args):
         autotune.reset(table)
         return probs, el, bt.steps
 
-    for name, tiles in (("batched_graph_tuned", True), ("batched_graph_default_tiles", False)):
-        probs, el, steps = run_batched(tiles)
+    for name, tiles, over in (("batched_graph_tuned", True, False), ("batched_graph_default_tiles", False, False),
+                              ("batched_graph_two_streams", True, True)):
+        probs, el, steps = run_batched(tiles, over)
         tot = sum(p.epochs for p in probs)
         res[name] = {"seconds": el, "batched_steps": steps, "slice_epochs_per_s": tot / el,
                      "samples_per_s": samples_per_epoch * args.epochs / el}
         log(f"{name}: {el:.3f} s, {steps} batched steps")
-        if tiles:
+        if name == "batched_graph_tuned":
             tuned_probs = probs
+        elif over:
+            # the forward and transpose halves on two streams: same results
+            res[name]["equal_to_one_stream_bitwise"] = sum(
+                int(torch.equal(a.x_cur, c.x_cur) and torch.equal(a.y_cur, c.y_cur))
+                for a, c in zip(probs, tuned_probs))
+            del probs
         else:
             del probs
     # the same slices on 8 streams, and one after another

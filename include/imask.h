@@ -444,6 +444,20 @@ int imask_batch_prepare(int32_t n_problems, const imask_geometry* g, const imask
 int imask_batch_step(int32_t n_problems, const imask_geometry* g, const imask_levels* lv, void* batch,
                      int32_t n_steps, void* stream);
 
+/* The four parts of one batched step, for callers that run the two
+ * independent halves of Alg. 1's step concurrently:
+ *   IMASK_BATCH_PLAN       draws and work lists (first)
+ *   IMASK_BATCH_FORWARD    restriction, forward projection, dual step
+ *   IMASK_BATCH_TRANSPOSE  transposes, prolongation, primal step
+ *   IMASK_BATCH_ADVANCE    the counters (last)
+ * FORWARD and TRANSPOSE read the step's old iterates and write disjoint
+ * buffers, so they may run on two streams between PLAN and ADVANCE (the
+ * caller orders them with events).  imask_batch_step runs all four in
+ * order on one stream. */
+enum { IMASK_BATCH_PLAN = 0, IMASK_BATCH_FORWARD = 1, IMASK_BATCH_TRANSPOSE = 2, IMASK_BATCH_ADVANCE = 3 };
+int imask_batch_step_part(int32_t n_problems, const imask_geometry* g, const imask_levels* lv, void* batch,
+                          int32_t part, void* stream);
+
 /* Copies the problems' counters (k, cur, epochs) from the batch buffer into
  * s[0..n_problems) (synchronises `stream`); lv as given to prepare. */
 int imask_batch_state(int32_t n_problems, const imask_levels* lv, const void* batch, imask_state* s, void* stream);

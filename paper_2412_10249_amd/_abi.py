@@ -28,7 +28,8 @@ EXPORTS = ["imask_workspace_bytes", "imask_phi_floats", "imask_prepare", "imask_
            "imask_step", "imask_solve", "imask_time_kernel", "imask_constants_scratch_bytes",
            "imask_step_constants", "imask_sigma_thm3", "imask_sigma_balamurugan", "imask_block_draws",
            "imask_backproject_noalloc", "imask_batch_bytes", "imask_batch_prepare", "imask_batch_step",
-           "imask_batch_state", "imask_set_tiles", "imask_get_tiles"]
+           "imask_batch_state", "imask_set_tiles", "imask_get_tiles", "imask_batch_step_part"]
+BATCH_PLAN, BATCH_FORWARD, BATCH_TRANSPOSE, BATCH_ADVANCE = 0, 1, 2, 3
 NOALLOC_SCRATCH_BYTES = 24 << 20
 KERNEL_FORWARD, KERNEL_TRANSPOSE = 0, 1
 
@@ -111,6 +112,7 @@ def lib():
         L.imask_batch_prepare.argtypes = [i32, P(Geometry), P(Levels), P(Reg), P(Params), P(vp), P(State),
                                           ctypes.c_double, i32, vp, sz, P(ctypes.c_int64), vp]
         L.imask_batch_step.argtypes = [i32, P(Geometry), P(Levels), vp, i32, vp]
+        L.imask_batch_step_part.argtypes = [i32, P(Geometry), P(Levels), vp, i32, vp]
         L.imask_batch_state.argtypes = [i32, P(Levels), vp, P(State), vp]
         L.imask_set_tiles.argtypes = [i32, i32, i32, P(Tiles)]
         L.imask_get_tiles.argtypes = [i32, i32, i32, P(Tiles)]

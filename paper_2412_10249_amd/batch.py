@@ -102,11 +102,39 @@ class Batch:
         check(lib().imask_batch_step(self.n, self.G, self.L, self.buf.data_ptr(), n_steps, _stream()),
               "imask_batch_step")
 
-    def capture(self) -> None:
-        """Record one batched step in a CUDA graph (nothing runs yet)."""
+    def step_overlapped(self) -> None:
+        """One batched step with its forward half on the current stream and
+        its transpose half on a side stream (fork after the plan, join
+        before the advance)."""
+        main = torch.cuda.current_stream()
+        if getattr(self, "side", None) is None:
+            self.side = torch.cuda.Stream()
+        args = (self.n, self.G, self.L, self.buf.data_ptr())
+
+        def part(which):
+            check(lib().imask_batch_step_part(*args, which, _stream()), "imask_batch_step_part")
+
+        part(_abi.BATCH_PLAN)
+        fork = torch.cuda.Event()
+        fork.record(main)
+        self.side.wait_event(fork)
+        part(_abi.BATCH_FORWARD)
+        with torch.cuda.stream(self.side):
+            part(_abi.BATCH_TRANSPOSE)
+        join = torch.cuda.Event()
+        join.record(self.side)
+        main.wait_event(join)
+        part(_abi.BATCH_ADVANCE)
+
+    def capture(self, overlapped: bool = False) -> None:
+        """Record one batched step in a CUDA graph (nothing runs yet);
+        `overlapped` puts its two halves on two streams."""
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g):
-            self.step(1)
+            if overlapped:
+                self.step_overlapped()
+            else:
+                self.step(1)
         self.graph = g
 
     def replay(self, n_steps: int = 1) -> None:

@@ -1163,16 +1163,39 @@ int imask_batch_prepare(int32_t n_problems, const imask_geometry* g, const imask
     return IMASK_OK;
 }
 
+// One part of a batched step (see imask_batch_step_part), with the stage
+// shapes of these problems.
+static int batch_part(int n, const imask_levels* lv, void* batch, int part, const StageShape& sh, hipStream_t s);
+
+int imask_batch_step_part(int32_t n_problems, const imask_geometry* g, const imask_levels* lv, void* batch,
+                          int32_t part, void* stream)
+{
+    if (int rc = batch_check(n_problems, g, lv)) return rc;
+    if (!batch || part < IMASK_BATCH_PLAN || part > IMASK_BATCH_ADVANCE) return IMASK_EINVAL;
+    StageShape sh;
+    batch_shapes(n_problems, g, lv, sh, nullptr);
+    return batch_part(n_problems, lv, batch, part, sh, (hipStream_t)stream);
+}
+
 int imask_batch_step(int32_t n_problems, const imask_geometry* g, const imask_levels* lv, void* batch,
                      int32_t n_steps, void* stream)
 {
     if (int rc = batch_check(n_problems, g, lv)) return rc;
     if (!batch || n_steps < 0) return IMASK_EINVAL;
-    const int n = n_problems;
     StageShape sh;
-    batch_shapes(n, g, lv, sh, nullptr);
+    batch_shapes(n_problems, g, lv, sh, nullptr);
+    for (int it = 0; it < n_steps; ++it)
+        for (int part = IMASK_BATCH_PLAN; part <= IMASK_BATCH_ADVANCE; ++part)
+            if (int rc = batch_part(n_problems, lv, batch, part, sh, (hipStream_t)stream)) return rc;
+    return IMASK_OK;
+}
+
+static int batch_part(int n_problems, const imask_levels* lv, void* batch, int part, const StageShape& sh,
+                      hipStream_t stream)
+{
+    const int n = n_problems;
     const BatchView bv = batch_view(batch, n, batch_rmax(n, lv));
-    hipStream_t s = (hipStream_t)stream;
+    hipStream_t s = stream;
     auto stage = [&](int v, int j) -> int {
         if (sh.ub[v][j] <= 0) return IMASK_OK;
         const long long cap = 256LL * batch_wgs_per_cu(v, sh.lds[v][j]);
@@ -1180,27 +1203,31 @@ int imask_batch_step(int32_t n_problems, const imask_geometry* g, const imask_le
         IMK_TRY(launch_batch_stage(v, j, bv, grid, sh.lds[v][j], s));
         return IMASK_OK;
     };
-    for (int it = 0; it < n_steps; ++it) {
+    // each phase runs its variants' slots in order: rounds, and within a
+    // round the LDS classes
+    auto phase = [&](int ph, int j0, int j1) -> int {
+        for (int v = 0; v < kNumVariants; ++v)
+            if (variant_phase(v) == ph)
+                for (int j = j0; j < j1; ++j)
+                    if (int rc = stage(v, j)) return rc;
+        return IMASK_OK;
+    };
+    switch (part) {
+    case IMASK_BATCH_PLAN:
         IMK_TRY(launch_batch_plan(bv, s));
-        // every variant runs in its phase of the step, in enum order
-        // each phase runs its variants' slots in order: rounds, and within
-        // a round the LDS classes
-        auto phase = [&](int ph, int j0, int j1) -> int {
-            for (int v = 0; v < kNumVariants; ++v)
-                if (variant_phase(v) == ph)
-                    for (int j = j0; j < j1; ++j)
-                        if (int rc = stage(v, j)) return rc;
-            return IMASK_OK;
-        };
-        if (int rc = phase(0, 0, kRounds)) return rc;
+        return IMASK_OK;
+    case IMASK_BATCH_FORWARD:
+        return phase(0, 0, kRounds);
+    case IMASK_BATCH_TRANSPOSE:
         for (int r = 0; r < sh.rounds; ++r) {
             if (int rc = phase(1, r * kLdsClasses, (r + 1) * kLdsClasses)) return rc;
             if (int rc = phase(2, r * kLdsClasses, (r + 1) * kLdsClasses)) return rc;
         }
-        if (int rc = phase(3, 0, kRounds)) return rc;
+        return phase(3, 0, kRounds);
+    default:
         IMK_TRY(launch_batch_advance(bv, s));
+        return IMASK_OK;
     }
-    return IMASK_OK;
 }
 
 int imask_batch_state(int32_t n_problems, const imask_levels* lv, const void* batch, imask_state* s, void* stream)

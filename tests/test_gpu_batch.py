@@ -2,7 +2,8 @@
 stepped alone with imask_step: every slice of a mixed-size batch equal bit
 for bit (x, y, phi, psi, k, epochs), in PAPER and UNBIASED modes, with
 iteration and epoch budgets; a captured step replayed as a CUDA graph,
-each replay checked against eager batched steps of an identical batch; and
+each replay checked against eager batched steps of an identical batch; the
+step's forward and transpose halves on two streams, eager and captured; and
 the mixed 256..1024 grids of the batched workload."""
 import numpy as np
 import pytest
@@ -76,6 +77,40 @@ def test_batch_graph_replays_equal_eager_steps():
     torch.cuda.synchronize()
     for a, c in zip(g_probs, alone):
         assert _same(a, c)
+
+
+@pytest.mark.parametrize("captured", [False, True])
+def test_batch_two_streams_equal_one_stream(captured):
+    """The step split into its parts, forward on the current stream and
+    transpose on a side stream (eager, or captured once and replayed 10
+    times with eager work between replays): after every step equal bit for
+    bit to an identical batch stepped on one stream, and at the end to the
+    problems stepped alone."""
+    say(f"two-stream batched step, captured={captured}")
+    o_probs, e_probs = _problems(SPECS), _problems(SPECS)
+    ob = Batch(o_probs, 10, pk.BUDGET_ITERS)
+    eb = Batch(e_probs, 10, pk.BUDGET_ITERS)
+    if captured:
+        ob.capture(overlapped=True)
+    for it in range(10):
+        if captured:
+            ob.replay(1)
+        else:
+            ob.step_overlapped()
+        eb.step(1)
+        torch.cuda.synchronize()
+        _ = torch.ones(1024, device="cuda").sum().item()
+        for q, (a, c) in enumerate(zip(o_probs, e_probs)):
+            assert torch.equal(a.x[0], c.x[0]) and torch.equal(a.x[1], c.x[1]), (it, q)
+            assert torch.equal(a.y[0], c.y[0]) and torch.equal(a.y[1], c.y[1]), (it, q)
+            assert torch.equal(a.phi, c.phi) and torch.equal(a.psi, c.psi), (it, q)
+    ob.sync_state()
+    alone = _problems(SPECS)
+    for p in alone:
+        p.step(10)
+    torch.cuda.synchronize()
+    for q, (a, c) in enumerate(zip(o_probs, alone)):
+        assert _same(a, c), q
 
 
 def test_batched_workload_grids():

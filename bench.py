@@ -242,23 +242,19 @@ def roofline_block(key, dom, dom_t, samples, fan):
 
 
 def step_times_by_level(prob, lv, steps):
-    """Mean GPU time of one whole step per level (HIP events on the stream the
-    library launches on, between consecutive steps; a spin kernel first keeps
-    the GPU behind the host so the gaps are the GPU's own)."""
+    """Median GPU time of one whole step per level (HIP events on the stream
+    the library launches on, between consecutive steps of one call; a spin
+    kernel first keeps the GPU behind the host so the gaps are the GPU's
+    own)."""
     import torch
 
     import paper_2412_10249_amd as pk
 
     draws = pk.draws(prob.params, lv, prob.k, steps)
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     torch.cuda.synchronize()
     torch.cuda._sleep(50_000_000)
-    ev[0].record()
-    for q in range(steps):
-        prob.step(1)
-        ev[q + 1].record()
-    torch.cuda.synchronize()
-    dt = np.array([ev[q].elapsed_time(ev[q + 1]) * 1e3 for q in range(steps)])
+    # all steps in one library call, as a solve runs them
+    dt = np.array(prob.step_timed(steps)) * 1e3
     out = {}
     for k, l in enumerate(lv.log2f):
         sel = dt[draws == k]

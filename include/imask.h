@@ -325,6 +325,15 @@ enum { IMASK_KERNEL_FORWARD = 0, IMASK_KERNEL_TRANSPOSE = 1 };
 int imask_time_kernel(const imask_geometry* g, int32_t which, int32_t log2f, const void* work, const float* in,
                       float* out, int32_t reps, void* stream, double* avg_ms);
 
+/* Diagnostic (not on the hot path): n_steps steps of one problem, as
+ * imask_step runs them in one call, with a HIP event recorded on `stream`
+ * before the first step and after each one; synchronises and writes each
+ * step's GPU time in ms to ms_out[0 .. n_steps-1] (host memory).  The times
+ * are the GPU's own when the caller keeps the GPU behind the host (for
+ * example with a long kernel enqueued first). */
+int imask_step_timed(const imask_geometry* g, const imask_levels* lv, const imask_reg* reg, const imask_params* prm,
+                     const float* b, imask_state* s, int32_t n_steps, float* ms_out, void* stream);
+
 /* Step-size constants (setup, not the hot path; synchronises `stream`).
  * For ImaSk as the saddle-point method of Sec. 3 with A_i = p_i K_i,
  * mu_f* = 1 and mu_g = mu, writes to out_host[0..2] the normalised squared

@@ -28,7 +28,8 @@ EXPORTS = ["imask_workspace_bytes", "imask_phi_floats", "imask_prepare", "imask_
            "imask_step", "imask_solve", "imask_time_kernel", "imask_constants_scratch_bytes",
            "imask_step_constants", "imask_sigma_thm3", "imask_sigma_balamurugan", "imask_block_draws",
            "imask_backproject_noalloc", "imask_batch_bytes", "imask_batch_prepare", "imask_batch_step",
-           "imask_batch_state", "imask_set_tiles", "imask_get_tiles", "imask_batch_step_part"]
+           "imask_batch_state", "imask_set_tiles", "imask_get_tiles", "imask_batch_step_part",
+           "imask_step_timed"]
 BATCH_PLAN, BATCH_FORWARD, BATCH_TRANSPOSE, BATCH_ADVANCE = 0, 1, 2, 3
 NOALLOC_SCRATCH_BYTES = 24 << 20
 KERNEL_FORWARD, KERNEL_TRANSPOSE = 0, 1
@@ -105,6 +106,8 @@ def lib():
                                        P(ctypes.c_double), P(ctypes.c_double)]
         L.imask_sigma_balamurugan.argtypes = [ctypes.c_double, ctypes.c_double, P(ctypes.c_double)]
         L.imask_step.argtypes = [i32, P(Geometry), P(Levels), P(Reg), P(Params), P(vp), P(State), i32, vp]
+        L.imask_step_timed.argtypes = [P(Geometry), P(Levels), P(Reg), P(Params), vp, P(State), i32,
+                                       P(ctypes.c_float), vp]
         L.imask_solve.argtypes = [i32, P(Geometry), P(Levels), P(Reg), P(Params), P(vp), P(State),
                                   ctypes.c_double, i32, vp]
         L.imask_batch_bytes.argtypes = [i32, P(Geometry), P(Levels)]

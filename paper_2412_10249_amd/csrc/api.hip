@@ -399,7 +399,7 @@ static bool step_is_plain(const imask_geometry& g, const imask_levels& lv, const
 // they share the workspace's partial images.
 static void step_records(const imask_geometry& g, const Layout& L, const imask_levels& lv, const imask_reg& reg,
                          const imask_params& prm, const float* bdat, const imask_state& st, int k, Launches& out,
-                         bool fuse)
+                         bool fuse, bool skip_prep = false)
 {
     // the UNBIASED full-resolution sketch applies every level: with `fuse`
     // its forward terms share one launch and its coarse transposes one per
@@ -422,7 +422,7 @@ static void step_records(const imask_geometry& g, const Layout& L, const imask_l
     for (int j = 0; j < lv.r; ++j) fa.p[j] = (float)lv.p[j];
     fa.sigma = (float)prm.sigma;
     fa.inv1ps = (float)(1.0 / (1.0 + prm.sigma));
-    plan_prep(pa, out);
+    if (!skip_prep) plan_prep(pa, out);
     if (multi)
         plan_fwd_fused(fa, out);
     else
@@ -473,9 +473,31 @@ static void step_records(const imask_geometry& g, const Layout& L, const imask_l
     }
 }
 
-static int one_step(const imask_geometry& g, const Layout& L, const imask_levels& lv, const imask_reg& reg,
-                    const imask_params& prm, const float* bdat, imask_state& st, hipStream_t s)
+// The forward's restriction can be carried from one step to the next: a
+// step whose prox writes it for the next step's sketch sets `made`, and the
+// next step of the same call, given `ready`, launches no k_prep.  `more`
+// says whether another step of this problem follows in the call (when not,
+// nothing is carried).
+struct PrepCarry {
+    bool ready = false;
+    bool made = false;
+};
+
+// The forward sketch (dual draw) of step k.
+static int fwd_sketch(const imask_params& prm, const uint64_t* thr, uint64_t k)
 {
+    if (prm.draw_mode != IMASK_DRAW_INDEPENDENT) return draw_one(prm, thr, k);
+    imask_params dual = prm;
+    dual.stream_id = prm.dual_stream_id;
+    return draw_one(dual, thr, k);
+}
+
+static int one_step(const imask_geometry& g, const Layout& L, const imask_levels& lv, const imask_reg& reg,
+                    const imask_params& prm, const float* bdat, imask_state& st, hipStream_t s,
+                    PrepCarry* carry = nullptr, bool more = false)
+{
+    const bool prep_ready = carry && carry->ready;
+    if (carry) carry->made = false;
     uint64_t thr[IMASK_MAX_LEVELS];
     draw_thresholds(lv, thr);
     const int k = draw_one(prm, thr, st.k);  // primal sketch (K_k^T, phi)
@@ -536,10 +558,10 @@ static int one_step(const imask_geometry& g, const Layout& L, const imask_levels
     if (plain) {
         // the same launches the batched path stores
         Launches recs;
-        step_records(g, L, lv, reg, prm, bdat, st, k, recs, true);
+        step_records(g, L, lv, reg, prm, bdat, st, k, recs, true, prep_ready);
         IMK_TRY(launch_records(recs, s));
     } else {
-        IMK_TRY(launch_prep(pa, s));
+        if (!prep_ready) IMK_TRY(launch_prep(pa, s));
         IMK_TRY(launch_fwd(fa, s));
     }
 
@@ -631,9 +653,21 @@ static int one_step(const imask_geometry& g, const Layout& L, const imask_levels
         ta.eps = (float)reg.tv_eps;
         ta.invL = (float)(1.0 / (1.0 + tau * reg.lambda + 8.0 * tau * reg.tv_weight / reg.tv_eps));
         fista_betas(reg.tv_inner, ta.beta);
+        // the next step's restriction of x^{k+1} (the plain schedule projects
+        // x itself; compact tables restrict against a snapshot, so they keep
+        // k_prep)
+        if (carry && more && !seq && !st.ztab) {
+            FwdArgs fn{};
+            forward_plan(L, lv, fwd_sketch(prm, thr, st.k + 1), st.x[nxt], W, ta.next, fn);
+            if (tv_prep_fusable(g.n, ta.next)) {
+                ta.prep_next = 1;
+                carry->made = true;
+            }
+        }
         IMK_TRY(launch_tv(ta, s));
     }
 
+    if (carry) carry->ready = carry->made;
     st.cur = nxt;
     st.k += 1;
     if (nblk > 1)
@@ -1392,6 +1426,35 @@ int imask_time_kernel(const imask_geometry* g, int32_t which, int32_t log2f, con
     return rc;
 }
 
+static int check_finite_after(int n_problems, const imask_geometry* g, const imask_params* prm,
+                              const imask_state* s, hipStream_t st);
+
+int imask_step_timed(const imask_geometry* g, const imask_levels* lv, const imask_reg* reg, const imask_params* prm,
+                     const float* b, imask_state* s, int32_t n_steps, float* ms_out, void* stream)
+{
+    if (n_steps < 0 || (n_steps > 0 && !ms_out)) return IMASK_EINVAL;
+    if (int rc = check_problem(g, lv, reg, prm, b, s)) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const Layout L = make_layout(*g);
+    std::vector<hipEvent_t> ev(n_steps + 1, nullptr);
+    int rc = IMASK_OK;
+    for (auto& e : ev)
+        if (rc == IMASK_OK && hipEventCreate(&e) != hipSuccess) rc = IMASK_EHIP;
+    if (rc == IMASK_OK && hipEventRecord(ev[0], st) != hipSuccess) rc = IMASK_EHIP;
+    PrepCarry carry;
+    for (int it = 0; it < n_steps && rc == IMASK_OK; ++it) {
+        rc = one_step(*g, L, *lv, *reg, *prm, b, *s, st, &carry, it + 1 < n_steps);
+        if (rc == IMASK_OK && hipEventRecord(ev[it + 1], st) != hipSuccess) rc = IMASK_EHIP;
+    }
+    if (rc == IMASK_OK && n_steps > 0 && hipEventSynchronize(ev[n_steps]) != hipSuccess) rc = IMASK_EHIP;
+    for (int it = 0; it < n_steps && rc == IMASK_OK; ++it)
+        if (hipEventElapsedTime(&ms_out[it], ev[it], ev[it + 1]) != hipSuccess) rc = IMASK_EHIP;
+    for (auto& e : ev)
+        if (e) (void)hipEventDestroy(e);
+    if (rc != IMASK_OK) return rc;
+    return check_finite_after(1, g, prm, s, st);
+}
+
 size_t imask_constants_scratch_bytes(const imask_geometry* g)
 {
     if (!geometry_ok(g)) return 0;
@@ -1665,10 +1728,12 @@ int imask_step(int32_t n_problems, const imask_geometry* g, const imask_levels* 
     for (int q = 0; q < n_problems; ++q)
         if (int rc = check_problem(g + q, lv + q, reg + q, prm + q, b[q], s + q)) return rc;
     hipStream_t st = (hipStream_t)stream;
+    std::vector<PrepCarry> carry(n_problems);
     for (int it = 0; it < n_steps; ++it)
         for (int q = 0; q < n_problems; ++q) {
             const Layout L = make_layout(g[q]);
-            if (int rc = one_step(g[q], L, lv[q], reg[q], prm[q], b[q], s[q], st)) return rc;
+            if (int rc = one_step(g[q], L, lv[q], reg[q], prm[q], b[q], s[q], st, &carry[q], it + 1 < n_steps))
+                return rc;
         }
     return check_finite_after(n_problems, g, prm, s, st);
 }
@@ -1688,11 +1753,15 @@ int imask_solve(int32_t n_problems, const imask_geometry* g, const imask_levels*
         const Layout L = make_layout(g[q]);
         const uint64_t k_start = s[q].k;
         const double e_start = s[q].epochs;
+        PrepCarry carry;
         for (;;) {
             const bool done = budget_kind == IMASK_BUDGET_ITERS ? (double)(s[q].k - k_start) >= budget
                                                                 : s[q].epochs - e_start >= budget;
             if (done) break;
-            if (int rc = one_step(g[q], L, lv[q], reg[q], prm[q], b[q], s[q], st)) return rc;
+            // with an epoch budget the step after this one may not run; a
+            // restriction carried for it is then left unused
+            const bool more = budget_kind == IMASK_BUDGET_EPOCHS || (double)(s[q].k + 1 - k_start) < budget;
+            if (int rc = one_step(g[q], L, lv[q], reg[q], prm[q], b[q], s[q], st, &carry, more)) return rc;
         }
     }
     return check_finite_after(n_problems, g, prm, s, st);

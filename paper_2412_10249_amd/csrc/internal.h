@@ -333,7 +333,14 @@ struct TvArgs {
     float theta;
     float tau_w, tau_lam, eps, invL;
     float beta[IMASK_MAX_TV_INNER];
+    // when set: the restriction k_prep would make of `out` for the next
+    // step, written by the prox's epilogue (only where tv_prep_fusable)
+    int prep_next;
+    PrepArgs next;
 };
+// Whether the smoothed-TV prox can write these restricted copies of its
+// output itself: whole tiles, every level inside a tile, no snapshot.
+bool tv_prep_fusable(int n, const PrepArgs& pa);
 
 // Forward band layout of a level with nl pixels per side (LDS-resident
 // bands of rows); rows == 0 selects the direct (global-memory) kernel.

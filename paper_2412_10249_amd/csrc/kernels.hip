@@ -146,6 +146,44 @@ __device__ __forceinline__ void load_tile(float* pyr, const float* x, int n, int
     }
 }
 
+// Stores the outputs of one T x T tile (tile row ty, column tx) from its
+// pyramid: block means at each output level, or the compensation S_r at
+// level 0, into the padded row / transposed layouts of the projector.
+__device__ __forceinline__ void prep_store(const PrepArgs& a, const float* pyr, int T, int ty, int tx)
+{
+    for (int o = 0; o < a.nout; ++o) {
+        const PrepOut& po = a.out[o];
+        const int l = po.lvl;
+        const int tl = T >> l, nl = a.n >> l;
+        const int P = po.padded ? nl + kPad : nl;
+        const int sh = po.padded ? kPadL : 0;
+        const int oy = ty * tl, ox = tx * tl;
+        const int off = pyr_offset(T, l);
+        for (int q = threadIdx.x; q < tl * tl; q += blockDim.x) {
+            const int i = q / tl, j = q - i * tl;
+            float v = pyr[off + q];
+            if (po.kind == PREP_COMP) {
+                float acc = v;
+                for (int c = 0; c < a.ncomp; ++c) {
+                    const int lc = a.comp_lvl[c];
+                    const int tc = T >> lc;
+                    acc -= a.comp_p[c] * pyr[pyr_offset(T, lc) + (i >> lc) * tc + (j >> lc)];
+                }
+                v = acc * a.inv_p0;
+            }
+            if (a.snap && a.snap_lvl == l && l > 0) {
+                // compact tables, coarse sketch: T_l x - z_k, then z_k <- T_l x
+                float* zc = a.snap + (size_t)(oy + i) * nl + ox + j;
+                const float mean = v;
+                v = mean - *zc;
+                *zc = mean;
+            }
+            po.dst[(size_t)(oy + i) * P + ox + j + sh] = v;
+            if (po.dstT) po.dstT[(size_t)(ox + j) * P + oy + i + sh] = v;
+        }
+    }
+}
+
 // Restricts (block mean at level l) or compensates (S_r at level 0) one
 // T x T tile of x into padded row / transposed layouts for the projector.
 __device__ __forceinline__ void prep_body(const PrepArgs& a, const Blk& bk, float* pyr)
@@ -165,37 +203,7 @@ __device__ __forceinline__ void prep_body(const PrepArgs& a, const Blk& bk, floa
         load_tile(pyr, a.x, a.n, a.T, ty, tx);
     }
     build_pyramid(pyr, a.T, a.pyr_levels);
-    for (int o = 0; o < a.nout; ++o) {
-        const PrepOut& po = a.out[o];
-        const int l = po.lvl;
-        const int tl = a.T >> l, nl = a.n >> l;
-        const int P = po.padded ? nl + kPad : nl;
-        const int sh = po.padded ? kPadL : 0;
-        const int oy = ty * tl, ox = tx * tl;
-        const int off = pyr_offset(a.T, l);
-        for (int q = threadIdx.x; q < tl * tl; q += blockDim.x) {
-            const int i = q / tl, j = q - i * tl;
-            float v = pyr[off + q];
-            if (po.kind == PREP_COMP) {
-                float acc = v;
-                for (int c = 0; c < a.ncomp; ++c) {
-                    const int lc = a.comp_lvl[c];
-                    const int tc = a.T >> lc;
-                    acc -= a.comp_p[c] * pyr[pyr_offset(a.T, lc) + (i >> lc) * tc + (j >> lc)];
-                }
-                v = acc * a.inv_p0;
-            }
-            if (a.snap && a.snap_lvl == l && l > 0) {
-                // compact tables, coarse sketch: T_l x - z_k, then z_k <- T_l x
-                float* zc = a.snap + (size_t)(oy + i) * nl + ox + j;
-                const float mean = v;
-                v = mean - *zc;
-                *zc = mean;
-            }
-            po.dst[(size_t)(oy + i) * P + ox + j + sh] = v;
-            if (po.dstT) po.dstT[(size_t)(ox + j) * P + oy + i + sh] = v;
-        }
-    }
+    prep_store(a, pyr, a.T, ty, tx);
 }
 
 __global__ void __launch_bounds__(256) k_prep(PrepArgs a)
@@ -1606,7 +1614,22 @@ __global__ void __launch_bounds__(kTvThreads) k_tv(TvArgs a)
         a.out[g] = up[k];
         if (a.xbar) a.xbar[g] = up[k] + a.theta * (up[k] - a.u0[g]);
     }
+    if (a.prep_next) {
+        // the next step's restriction of this output tile (tv_prep_fusable
+        // holds: whole tiles, every output level inside one): the tile into
+        // LDS, its 2x2-mean pyramid, and the same stores as k_prep
+        float* pyr = sm;
+#pragma unroll
+        for (int k = 0; k < kTvCells; ++k) {
+            if (!(flag[k] & kOut)) continue;
+            const int li = cell[k] / R, lj = cell[k] - (cell[k] / R) * R;
+            pyr[(li - H) * kTvTile + (lj - H)] = up[k];
+        }
+        build_pyramid(pyr, kTvTile, a.next.pyr_levels);
+        prep_store(a.next, pyr, kTvTile, ty, tx);
+    }
 }
+
 
 // Prox of gamma TV + chi_{>=0} at bt = v / scale (the paper's TV prior,
 // Sec. 4.5), by J iterations of the fast gradient projection on the dual
@@ -1802,6 +1825,19 @@ __global__ void __launch_bounds__(256) k_dot_final(const double* part, double* o
 }
 
 }  // namespace
+
+bool tv_prep_fusable(int n, const PrepArgs& pa)
+{
+    if (n % kTvTile != 0 || pa.snap || (kTvTile >> pa.pyr_levels) < 1) return false;
+    for (int o = 0; o < pa.nout; ++o)
+        if ((kTvTile >> pa.out[o].lvl) < 1 || pa.out[o].lvl > pa.pyr_levels) return false;
+    for (int c = 0; c < pa.ncomp; ++c)
+        if (pa.comp_lvl[c] > pa.pyr_levels) return false;
+    return true;
+}
+// the pyramid (a tile and its mean levels, under 4/3 of a tile) fits in the
+// prox's LDS (three arrays of the tile with its halo)
+static_assert(4 * kTvTile * kTvTile <= 3 * 3 * kTvTile * kTvTile, "pyramid fits the prox's LDS");
 
 // ----------------------------------------------------------------- launchers
 

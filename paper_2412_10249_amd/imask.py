@@ -341,6 +341,19 @@ class Problem:
         self._absorb(s)  # steps taken before an error (ENONFINITE) are kept
         check(rc, "imask_step")
 
+    def step_timed(self, n_steps: int):
+        """n_steps steps in one library call; returns each step's GPU time
+        in ms (HIP events between the steps; a diagnostic)."""
+        s = self._cstate()
+        bp = (ctypes.c_void_p * 1)(self.b.data_ptr())
+        ms = (ctypes.c_float * max(1, n_steps))()
+        rc = lib().imask_step_timed(ctypes.byref(self.geom.c()), ctypes.byref(self.levels.c()),
+                                    ctypes.byref(self.reg.c()), ctypes.byref(self.params.c()), bp[0],
+                                    ctypes.byref(s), n_steps, ms, _stream())
+        self._absorb(s)
+        check(rc, "imask_step_timed")
+        return [float(ms[i]) for i in range(n_steps)]
+
     def solve(self, budget: float, kind: int = _abi.BUDGET_ITERS) -> None:
         s = self._cstate()
         bp = (ctypes.c_void_p * 1)(self.b.data_ptr())

@@ -238,6 +238,16 @@ def test_remaining_entry_points_validate_before_any_launch():
     prm = _abi.Params(0.01, 1, 0)
     assert L.imask_draws(ctypes.byref(prm), ctypes.byref(lv), 0, -1, draws) == _abi.EINVAL
     assert L.imask_draws(ctypes.byref(prm), ctypes.byref(lv), 0, 4, draws) == _abi.OK
+    # the timed steps: negative counts, a missing output array, a null state
+    reg = _abi.Reg(_abi.REG_TIKHONOV, 0.01, 0.0, 1e-3, 10)
+    st = _abi.State()
+    tms = (ctypes.c_float * 4)()
+    assert L.imask_step_timed(gr, ctypes.byref(lv), ctypes.byref(reg), ctypes.byref(prm), a, ctypes.byref(st), -1,
+                              tms, None) == _abi.EINVAL
+    assert L.imask_step_timed(gr, ctypes.byref(lv), ctypes.byref(reg), ctypes.byref(prm), a, ctypes.byref(st), 4,
+                              None, None) == _abi.EINVAL
+    assert L.imask_step_timed(gr, ctypes.byref(lv), ctypes.byref(reg), ctypes.byref(prm), a, ctypes.byref(st), 4,
+                              tms, None) == _abi.EINVAL
 
 
 def test_measurement_blocks_validated():

@@ -118,6 +118,38 @@ def test_repeat_is_bitwise():
         assert torch.equal(a, c)
 
 
+@pytest.mark.parametrize("n,levels,mode,draw", [(64, (0, 1, 2, 3), pk.FULL_PAPER, pk.DRAW_COMMON),
+                                                 (64, (0, 1, 2), pk.FULL_UNBIASED, pk.DRAW_COMMON),
+                                                 (96, (0, 2, 5), pk.FULL_PAPER, pk.DRAW_INDEPENDENT),
+                                                 (512, (0, 1, 2, 3), pk.FULL_PAPER, pk.DRAW_COMMON)])
+def test_carried_restriction_equals_separate_steps(n, levels, mode, draw):
+    """Steps of one call carry the next step's restriction in the smoothed-TV
+    prox's epilogue; steps taken one call at a time restrict in k_prep. The
+    two are equal bit for bit (x, y, phi, psi), through step, solve with an
+    epoch budget and step_timed."""
+    na = nd = 3 * n // 2
+    _, b = synth.ct_problem(n, na, nd, 1e4, 1020, 2020)
+    say(f"carried restriction n={n} levels={levels} mode={mode} draw={draw}")
+
+    def mk():
+        return pk.Problem(pk.Geometry(n, na, nd), pk.Levels.uniform(levels, mode),
+                          pk.Regularizer(pk.REG_SMOOTH_TV, 1e-2, 2e-3, 1e-3, 10),
+                          pk.Params(1e-3, 42, 3, draw_mode=draw, dual_stream_id=9), dev(f32(b)))
+
+    one, many, solved, timed = mk(), mk(), mk(), mk()
+    for _ in range(17):
+        one.step(1)
+    many.step(17)
+    ms = timed.step_timed(17)
+    assert len(ms) == 17 and min(ms) > 0.0
+    solved.solve(one.epochs, pk.BUDGET_EPOCHS)
+    torch.cuda.synchronize()
+    for p in (many, timed, solved):
+        assert p.k == one.k and p.epochs == one.epochs
+        assert torch.equal(p.x_cur, one.x_cur) and torch.equal(p.y_cur, one.y_cur)
+        assert torch.equal(p.phi, one.phi) and torch.equal(p.psi, one.psi)
+
+
 def test_batched_equals_alone_and_resume():
     geoms = [(64, 90, 92), (32, 45, 50), (48, 30, 70)]
     probs, alone = [], []

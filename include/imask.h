@@ -286,8 +286,9 @@ int imask_backproject(const imask_geometry* g, int32_t log2f, const void* work,
  * bit (same kernels, same partial-image order).  Instead of a workspace the
  * call uses a static device array of IMASK_NOALLOC_SCRATCH_BYTES per GPU,
  * held until the process ends, for the projector constants (recomputed on
- * every call: 64 B per level and angle), the partial images (16 N^2 floats)
- * and the coarse result (N^2 floats); the first call on a device looks up
+ * every call: 64 B per level and angle), the partial images (as many as a
+ * workspace holds: P = max(16 N^2, min(64 N^2, 2^23)) floats) and the
+ * coarse result (N^2 floats); the first call on a device looks up
  * the array's address there.  Every call on one GPU shares that array, so
  * calls that overlap on one GPU (several streams or host threads) race and
  * must be ordered by the caller; each call writes every byte it reads
@@ -295,10 +296,10 @@ int imask_backproject(const imask_geometry* g, int32_t log2f, const void* work,
  * Allocates nothing (no hipMalloc, hipFree or allocating library call) and
  * does not synchronise.  Parallel beam with the default angles only
  * (IMASK_ENOTSUP for listed angles or a fan beam); IMASK_ESIZE when the
- * geometry needs more than the array: 4 (17 N^2 + 16 (lmax+1) n_angles)
- * bytes, so N <= 512 with up to 16384 angles; IMASK_EINVAL as for
+ * geometry needs more than the array: 4 (P + N^2 + 16 (lmax+1) n_angles)
+ * bytes, so N <= 512 with up to 30720 angles; IMASK_EINVAL as for
  * imask_backproject. */
-#define IMASK_NOALLOC_SCRATCH_BYTES (24u << 20)
+#define IMASK_NOALLOC_SCRATCH_BYTES (48u << 20)
 int imask_backproject_noalloc(const imask_geometry* g, int32_t log2f, const float* sino, float* x_full,
                               void* stream);
 

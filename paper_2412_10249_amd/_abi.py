@@ -31,7 +31,7 @@ EXPORTS = ["imask_workspace_bytes", "imask_phi_floats", "imask_prepare", "imask_
            "imask_batch_state", "imask_set_tiles", "imask_get_tiles", "imask_batch_step_part",
            "imask_step_timed"]
 BATCH_PLAN, BATCH_FORWARD, BATCH_TRANSPOSE, BATCH_ADVANCE = 0, 1, 2, 3
-NOALLOC_SCRATCH_BYTES = 24 << 20
+NOALLOC_SCRATCH_BYTES = 48 << 20
 KERNEL_FORWARD, KERNEL_TRANSPOSE = 0, 1
 
 

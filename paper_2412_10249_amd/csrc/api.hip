@@ -89,7 +89,10 @@ Layout make_layout(const imask_geometry& g)
     L.part = off;
     const size_t d = (size_t)g.n * g.n;
     L.part_floats = kPartImages * d;
-    if (is_fan(g)) L.part_floats = std::max(L.part_floats, std::min(kFanPartImages * d, kFanPartFloats));
+    if (is_fan(g))
+        L.part_floats = std::max(L.part_floats, std::min(kFanPartImages * d, kFanPartFloats));
+    else
+        L.part_floats = std::max(L.part_floats, std::min(kParPartImages * d, kParPartFloats));
     off = align64(off + L.part_floats);
     L.ptmp = off;
     off = align64(off + (size_t)g.n * g.n);
@@ -871,8 +874,9 @@ static int scratch_of_current_device(void** out)
 }
 
 // The part of a workspace the transpose reads and writes, packed from offset
-// 0: projector constants of every level, the partial images, the coarse
-// result before prolongation.
+// 0: projector constants of every level, the partial images (as many as the
+// workspace holds, so the launches are those of imask_backproject), the
+// coarse result before prolongation.
 static Layout transpose_layout(const imask_geometry& g)
 {
     Layout L = make_layout(g);
@@ -880,7 +884,6 @@ static Layout transpose_layout(const imask_geometry& g)
     L.consts = off;
     off = align64(off + (size_t)(L.lmax + 1) * g.n_angles * kConstStride);
     L.part = off;
-    L.part_floats = kPartImages * (size_t)g.n * g.n;
     off = align64(off + L.part_floats);
     L.ptmp = off;
     off = align64(off + (size_t)g.n * g.n);

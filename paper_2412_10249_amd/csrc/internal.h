@@ -34,6 +34,12 @@ constexpr int kConstStride = 16;  // floats per RayConst
 #endif
 // Full-resolution partial images the transpose may write (2 G N_l^2 <= this * N^2).
 constexpr int kPartImages = IMK_PART_IMAGES;
+// Partial images of the parallel-beam transposes: up to kParPartImages N^2
+// floats while that stays within kParPartFloats, so that small grids get
+// more angle groups (512^2: 32 partial images, about 2048 workgroups at
+// level 0), never fewer than kPartImages N^2.
+constexpr int kParPartImages = 64;
+constexpr size_t kParPartFloats = (size_t)8 << 20;  // 32 MiB
 // Partial images of the fan transposes: up to kFanPartImages N^2 floats
 // while that stays within kFanPartFloats (more view groups where rays are
 // few per workgroup), never fewer than kPartImages N^2.

@@ -2188,15 +2188,19 @@ static size_t scatter_lds(int nl)
 }
 
 // Ownership scatter with about IMK_BP_TARGET_WG workgroups: G angle groups
-// per pass, 2 G N_l^2 <= kPartImages N^2 partial images.  A launch over part
-// of the angles (a measurement block) keeps the same workgroup count: fewer
-// angles per group, but fewer workgroups measured slower still.
+// per pass, 2 G N_l^2 partial images within the workspace's partial-image
+// buffer.  A launch over part of the angles (a measurement block) keeps the
+// same workgroup count: fewer angles per group, but fewer workgroups
+// measured slower still.
 template <int R, int W>
 static void plan_scatter(BpOwnArgs& a, int nl, int lvl, int variant, int round, int target, Launches& out)
 {
     using Sh = BpShape<R, W>;
     const int nb = (nl + Sh::rows - 1) / Sh::rows;
-    const int gmax = std::max(1, std::min(std::max(a.split.nrow, a.split.ncol), (kPartImages / 2) << (2 * lvl)));
+    const long long room = std::max<long long>(a.fan.part_floats, (long long)kPartImages * a.n * a.n) /
+                           (2LL * nl * nl);
+    const int gmax = (int)std::max(1LL, std::min<long long>({(long long)std::max(a.split.nrow, a.split.ncol), room,
+                                                             1024LL}));
     a.G = std::max(1, std::min(gmax, (target + 2 * nb - 1) / (2 * nb)));
     a.nq = 2 * a.G;
     Launch L;

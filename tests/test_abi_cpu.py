@@ -314,21 +314,29 @@ def test_fan_geometry_validated():
                         ctypes.byref(s), 1, None) == _abi.ENOTSUP
 
 
-def test_fan_partial_image_buffer_sizing():
-    """The fan transposes' partial-image buffer holds up to 64 N^2 floats
-    while that stays within 256 MiB, never fewer than the 16 N^2 of the
-    parallel beam: the fan workspace exceeds the parallel one by the extra
-    images, give or take the small ray, view and table entries, the band
-    partial sinograms and the alignment (under 64 KiB here)."""
+def test_partial_image_buffer_sizing():
+    """The transposes' partial-image buffer holds up to 64 N^2 floats while
+    that stays within 32 MiB (parallel beam) or 256 MiB (fan beam), never
+    fewer than 16 N^2: the fan workspace exceeds the parallel one by the
+    difference, and the parallel one grows by it from 16 N^2, give or take
+    the small ray, view and table entries, the band partial sinograms and the
+    alignment (under 64 KiB here)."""
     L = _abi.lib()
 
     def ws(n, fan):
         g = im.Geometry(n, 8, 16, src_dist=4.0 if fan else 0.0, det_dist=2.0).c()
         return L.imask_workspace_bytes(ctypes.byref(g))
 
-    for n, extra_images in ((64, 48), (512, 48), (1024, 48), (2048, 0), (4096, 0)):
+    def part(n, cap):
+        return max(16 * n * n, min(64 * n * n, cap))
+
+    for n, par_images, fan_images in ((64, 64, 64), (512, 32, 64), (1024, 16, 64), (2048, 16, 16),
+                                      (4096, 16, 16)):
+        assert part(n, 1 << 23) == par_images * n * n and part(n, 1 << 26) == fan_images * n * n
         diff = ws(n, True) - ws(n, False)
-        assert abs(diff - extra_images * n * n * 4) <= 65536, (n, diff)
+        assert abs(diff - (fan_images - par_images) * n * n * 4) <= 65536, (n, diff)
+    # the parallel workspace against one with 16 N^2: grows by the extra images
+    assert abs(ws(512, False) - ws(1024, False) / 4 - 16 * 512 * 512 * 4) <= 65536
 
 
 def test_noalloc_transpose_validates_before_any_device_call():
@@ -347,9 +355,12 @@ def test_noalloc_transpose_validates_before_any_device_call():
     assert call(im.Geometry(63, 90, 92)) == _abi.EINVAL
     assert call(im.Geometry(64, 3, 92, angles=(0.1, 0.2, 0.3))) == _abi.ENOTSUP
     assert call(im.Geometry(64, 90, 92, src_dist=4.0, det_dist=2.0)) == _abi.ENOTSUP
-    # 17 N^2 + 16 (lmax + 1) n_angles floats against the 24 MiB array
+    # P + N^2 + 16 (lmax + 1) n_angles floats against the 48 MiB array, with
+    # P = max(16 N^2, min(64 N^2, 2^23)) partial-image floats: N = 512 and
+    # 8 levels leave room for 30720 angles
     assert call(im.Geometry(1024, 90, 92)) == _abi.ESIZE
-    assert call(im.Geometry(512, 20000, 768)) == _abi.ESIZE
+    assert call(im.Geometry(512, 30721, 768)) == _abi.ESIZE
+    assert (1 << 23) + 512 * 512 + 16 * 8 * 30720 <= _abi.NOALLOC_SCRATCH_BYTES // 4
 
 
 def test_tiles_table_validates_and_round_trips():

@@ -27,7 +27,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 TILES_JSON = os.path.join(PKG, "tiles.json")
 
 BP_SHAPES = [(2, 8), (4, 4), (2, 4), (1, 4)]
-BP_TARGETS = [512, 1024, 2048]
+BP_TARGETS = [512, 1024, 2048, 4096]
 FWD_BUDGETS_KB = [64, 78, 96, 128, 156]
 
 

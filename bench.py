@@ -302,6 +302,10 @@ def run(args):
     for lvl in LEVELS:
         kern[("fwd", lvl)] = pk.time_kernel(geom, pk.KERNEL_FORWARD, lvl, x, prob.work, args.kernel_reps)
         kern[("bp", lvl)] = pk.time_kernel(geom, pk.KERNEL_TRANSPOSE, lvl, y, prob.work, args.kernel_reps)
+    # the transpose with the ordered sum of its partial images (not for the
+    # dominant-kernel choice: two launches)
+    bp_sum = {lvl: pk.time_kernel(geom, pk.KERNEL_TRANSPOSE_SUM, lvl, y, prob.work, args.kernel_reps)
+              for lvl in LEVELS} if not args.fan else {}
     if args.copy_calib:
         src = torch.rand((COPY_N, COPY_N), device="cuda")
         for _ in range(3):
@@ -359,6 +363,7 @@ def run(args):
         "step_ratio_vs_level0": {f"l{l}": {"measured": round(v / t0_step, 4), "model": 2.0 ** -l}
                                  for l, v in by_level.items()} if t0_step else None,
         "kernels_us": {f"{k[0]}_l{k[1]}": round(v * 1e6, 2) for k, v in kern.items()},
+        "transpose_with_sum_us": {f"l{l}": round(v * 1e6, 2) for l, v in bp_sum.items()},
         "projector_samples_per_s": {f"{k[0]}_l{k[1]}": samples[k[1]] / v for k, v in kern.items()},
         "kernel_source_hash": source_hash(),
     }

@@ -321,8 +321,11 @@ int imask_sketch_apply(const imask_geometry* g, const imask_levels* lv, int32_t 
  * forward kernel on the level-l restriction of `in` (N*N; `out`, a
  * sinogram, receives one full projection first).  IMASK_KERNEL_TRANSPOSE:
  * the transpose kernel on sinogram `in` (its partial images stay in the
- * workspace; `out` is unused but must be non-null). */
-enum { IMASK_KERNEL_FORWARD = 0, IMASK_KERNEL_TRANSPOSE = 1 };
+ * workspace; `out` is unused but must be non-null).
+ * IMASK_KERNEL_TRANSPOSE_SUM: that kernel and the ordered sum of its
+ * partial images into the level image (the coarse result in the
+ * workspace; `out` unused but non-null), the pair a step launches. */
+enum { IMASK_KERNEL_FORWARD = 0, IMASK_KERNEL_TRANSPOSE = 1, IMASK_KERNEL_TRANSPOSE_SUM = 2 };
 int imask_time_kernel(const imask_geometry* g, int32_t which, int32_t log2f, const void* work, const float* in,
                       float* out, int32_t reps, void* stream, double* avg_ms);
 

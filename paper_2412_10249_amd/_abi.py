@@ -32,7 +32,7 @@ EXPORTS = ["imask_workspace_bytes", "imask_phi_floats", "imask_prepare", "imask_
            "imask_step_timed"]
 BATCH_PLAN, BATCH_FORWARD, BATCH_TRANSPOSE, BATCH_ADVANCE = 0, 1, 2, 3
 NOALLOC_SCRATCH_BYTES = 48 << 20
-KERNEL_FORWARD, KERNEL_TRANSPOSE = 0, 1
+KERNEL_FORWARD, KERNEL_TRANSPOSE, KERNEL_TRANSPOSE_SUM = 0, 1, 2
 
 
 class Geometry(ctypes.Structure):

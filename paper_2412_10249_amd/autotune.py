@@ -1,9 +1,11 @@
 """Autotuner of the projector pair's launch shapes.
 
 For each level of a geometry it times, with the library's own kernel timer
-(imask_time_kernel: HIP events around the exact launch a step makes), every
+(imask_time_kernel: HIP events around the exact launches a step makes), every
 candidate transpose tile (rows per wavefront x wavefronts) and workgroup
-target, then every forward band budget, and keeps the fastest.  The table
+target, with the ordered sum of the partial images it writes (more angle
+groups make the transpose faster and the sum slower), then every forward
+band budget, and keeps the fastest.  The table
 is saved as JSON keyed by "N_l x angles x bins" and applied with
 imask_set_tiles.  Shapes change only the order of floating-point sums, never
 the matrices, so any table gives a correct projector.
@@ -59,7 +61,7 @@ def tune_geometry(n: int, na: int, nd: int, levels=(0, 1, 2, 3), reps: int = 10,
     """Fastest shapes of each level of the n x n, na x nd parallel geometry."""
     import torch
 
-    from ._abi import KERNEL_FORWARD, KERNEL_TRANSPOSE
+    from ._abi import KERNEL_FORWARD, KERNEL_TRANSPOSE_SUM
     from .imask import Geometry, time_kernel, workspace
 
     geom = Geometry(n, na, nd)
@@ -73,13 +75,13 @@ def tune_geometry(n: int, na: int, nd: int, levels=(0, 1, 2, 3), reps: int = 10,
         if nl < 2:
             continue
         reset_tiles(nl, na, nd)
-        base_bp = time_kernel(geom, KERNEL_TRANSPOSE, lvl, y, work, reps)
+        base_bp = time_kernel(geom, KERNEL_TRANSPOSE_SUM, lvl, y, work, reps)
         base_fwd = time_kernel(geom, KERNEL_FORWARD, lvl, x, work, reps)
         best_bp = (base_bp, (0, 0), 0)
         for shape in BP_SHAPES:
             for wg in BP_TARGETS:
                 set_tiles(nl, na, nd, shape, wg)
-                t = time_kernel(geom, KERNEL_TRANSPOSE, lvl, y, work, reps)
+                t = time_kernel(geom, KERNEL_TRANSPOSE_SUM, lvl, y, work, reps)
                 if t < best_bp[0]:
                     best_bp = (t, shape, wg)
         best_fwd = (base_fwd, 0)
@@ -93,10 +95,10 @@ def tune_geometry(n: int, na: int, nd: int, levels=(0, 1, 2, 3), reps: int = 10,
                     best_fwd = (t, kb)
         set_tiles(nl, na, nd, best_bp[1], best_bp[2], best_fwd[1])
         ent = {"bp": list(best_bp[1]), "bp_wg": best_bp[2], "fwd_lds_kb": best_fwd[1],
-               "transpose_us": {"default": round(base_bp * 1e6, 2), "tuned": round(best_bp[0] * 1e6, 2)},
+               "transpose_sum_us": {"default": round(base_bp * 1e6, 2), "tuned": round(best_bp[0] * 1e6, 2)},
                "forward_us": {"default": round(base_fwd * 1e6, 2), "tuned": round(best_fwd[0] * 1e6, 2)}}
         out[key(nl, na, nd)] = ent
-        log(f"N_l {nl} ({na} x {nd}): transpose {ent['transpose_us']} with {ent['bp']} wg {ent['bp_wg']}; "
+        log(f"N_l {nl} ({na} x {nd}): transpose + sum {ent['transpose_sum_us']} with {ent['bp']} wg {ent['bp_wg']}; "
             f"forward {ent['forward_us']} with {ent['fwd_lds_kb']} KB")
     del work
     return out

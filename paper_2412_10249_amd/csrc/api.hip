@@ -1380,7 +1380,8 @@ int imask_time_kernel(const imask_geometry* g, int32_t which, int32_t log2f, con
     if (!geometry_ok(g) || !work || !in || !out || !avg_ms || reps < 1) return IMASK_EINVAL;
     const Layout L = make_layout(*g);
     if (log2f < 0 || log2f > L.lmax) return IMASK_EINVAL;
-    if (which != IMASK_KERNEL_FORWARD && which != IMASK_KERNEL_TRANSPOSE) return IMASK_EINVAL;
+    if (which != IMASK_KERNEL_FORWARD && which != IMASK_KERNEL_TRANSPOSE && which != IMASK_KERNEL_TRANSPOSE_SUM)
+        return IMASK_EINVAL;
     float* W = (float*)work;
     hipStream_t s = (hipStream_t)stream;
     FwdArgs fa{};
@@ -1415,8 +1416,14 @@ int imask_time_kernel(const imask_geometry* g, int32_t which, int32_t log2f, con
     int rc = IMASK_OK;
     BpOwnArgs used;
     if (hipEventRecord(e0, s) != hipSuccess) rc = IMASK_EHIP;
+    if (which == IMASK_KERNEL_TRANSPOSE_SUM) {
+        ba.out = W + L.ptmp;  // the level image, not prolonged
+        ba.tmp = W + L.ptmp;
+    }
     for (int r = 0; r < reps && rc == IMASK_OK; ++r) {
-        const hipError_t e = which == IMASK_KERNEL_FORWARD ? launch_fwd_terms(fa, s) : launch_bp_main(ba, s, used);
+        const hipError_t e = which == IMASK_KERNEL_FORWARD     ? launch_fwd_terms(fa, s)
+                             : which == IMASK_KERNEL_TRANSPOSE ? launch_bp_main(ba, s, used)
+                                                               : launch_bp(ba, s);
         if (e != hipSuccess) rc = IMASK_EHIP;
     }
     float ms = 0.0f;

@@ -191,14 +191,17 @@ def stored_counter(kernel_key, name):
 def counter_run(spec: str, fan: bool = False):
     """Launch only one projector kernel (plus the calibration copy), for a
     rocprofv3 --pmc pass: spec is fwd:LEVEL or bp:LEVEL (fan: on the fan
-    workload's geometry)."""
+    workload's geometry), with the tuned launch shapes of the main run."""
     import torch
 
     import paper_2412_10249_amd as pk
 
+    from paper_2412_10249_amd import autotune
+
     kind, lvl = spec.split(":")
     lvl = int(lvl)
     torch.cuda.set_device(0)
+    autotune.apply_saved()  # the launch shapes the main run uses
     geom = pk.Geometry(N, NA, ND, src_dist=FAN_D, det_dist=FAN_DD) if fan else pk.Geometry(N, NA, ND)
     work = pk.workspace(geom)
     g = torch.Generator(device="cuda").manual_seed(5)
@@ -730,7 +733,8 @@ def batched(args):
                 step replayed as a CUDA graph; with the autotuned tiles
                 (paper_2412_10249_amd/tiles.json) and with the defaults
                 and with the step's forward and transpose halves on two
-                streams inside the graph
+                streams inside the graph; and split in 2 or 4 groups, each
+                group's graph replayed on its own stream
       streams   each slice's own steps, dealt round-robin to 8 HIP streams
       alone     the slices one after another on one stream
     Aggregate samples/s, and every batched slice compared with its run alone."""
@@ -802,6 +806,27 @@ def batched(args):
             del probs
         else:
             del probs
+    # the batch split in groups, each group's captured step replayed on its
+    # own stream (the groups' phases overlap)
+    for groups in (2, 4):
+        table = autotune.load()
+        autotune.apply(table)
+        probs = make()
+        bg = batch.BatchGroups(probs, args.epochs, pk.BUDGET_EPOCHS, groups)
+        bg.capture()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        bg.run()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        bg.sync_state()
+        name = f"batched_graph_{groups}_groups"
+        res[name] = {"seconds": el, "samples_per_s": samples_per_epoch * args.epochs / el,
+                     "equal_to_one_batch_bitwise": sum(int(torch.equal(probs[q].x_cur, tuned_probs[q].x_cur))
+                                                       for q in range(len(probs)))}
+        log(f"{name}: {el:.3f} s")
+        autotune.reset(table)
+        del bg, probs
     # the same slices on 8 streams, and one after another
     probs = make()
     runner = batch.BatchRunner(probs, n_streams=args.streams)

@@ -5,6 +5,9 @@ Two ways to run them:
   is one persistent launch over the work items of all problems, the sketch
   draws happen on the device, and one captured step (a CUDA graph) is
   replayed for every step;
+* `BatchGroups` splits the problems into a few such batches (sizes dealt
+  round-robin, largest first) and replays each batch's captured step on a
+  stream of its own, so the batches' phases overlap;
 * `BatchRunner` deals the problems round-robin to a few HIP streams
   (default priority), so one slice's launches overlap another's.
 
@@ -155,3 +158,39 @@ class Batch:
         check(lib().imask_batch_state(self.n, self.L, self.buf.data_ptr(), self.S, _stream()), "imask_batch_state")
         for p, s in zip(self.problems, self.S):
             p._absorb(s)
+
+
+class BatchGroups:
+    """The problems in `groups` batches, one HIP stream each (default
+    priority): every batch's step is captured once and replayed on its
+    stream, so one batch's transposes overlap another's forward passes.  A
+    box exposes few hardware queues (four here), about as many groups as
+    pay off."""
+
+    def __init__(self, problems, budget: float, kind: int = _abi.BUDGET_ITERS, groups: int = 4):
+        order = sorted(range(len(problems)), key=lambda q: -problems[q].geom.n)
+        self.groups = [Batch([problems[q] for q in order[g::groups]], budget, kind)
+                       for g in range(min(groups, len(problems)))]
+        self.streams = [torch.cuda.Stream() for _ in self.groups]
+
+    def capture(self) -> None:
+        for bt, st in zip(self.groups, self.streams):
+            st.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(st):
+                bt.capture()
+
+    def run(self) -> None:
+        """Every batch's steps on its stream; the current stream waits for all."""
+        if any(bt.graph is None for bt in self.groups):
+            self.capture()
+        main = torch.cuda.current_stream()
+        for bt, st in zip(self.groups, self.streams):
+            st.wait_stream(main)
+            with torch.cuda.stream(st):
+                bt.replay(bt.steps)
+        for st in self.streams:
+            main.wait_stream(st)
+
+    def sync_state(self) -> None:
+        for bt in self.groups:
+            bt.sync_state()

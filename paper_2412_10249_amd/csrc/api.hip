@@ -1183,8 +1183,12 @@ int imask_batch_prepare(int32_t n_problems, const imask_geometry* g, const imask
                     R.lds = La.lds;
                     std::memcpy(blobs + blob * kBlobBytes, La.args, kBlobBytes);
                     ++blob;
-                    items[(slot * kNumVariants + La.variant) * kRounds + R.round] += R.items;
-                    nsegs[(slot * kNumVariants + La.variant) * kRounds + R.round] += 1;
+                    int& it = items[(slot * kNumVariants + La.variant) * kRounds + R.round];
+                    int& ns = nsegs[(slot * kNumVariants + La.variant) * kRounds + R.round];
+                    R.ord = ns;
+                    R.ibefore = it;
+                    it += R.items;
+                    ns += 1;
                 }
             }
     }

@@ -522,11 +522,19 @@ hipError_t launch_records(const Launches& recs, hipStream_t s);
 constexpr int kMaxRec = 32;  // launches of one step of one problem
 // Stage slots of a variant: round (0: level 0's transpose, 1: the coarse
 // transposes of an UNBIASED full-resolution sketch) times LDS class (the
-// launches of one slot reserve the largest LDS among them, so launches of
-// very different LDS needs run in separate slots).
-constexpr int kLdsClasses = 4;
+// launches of one slot reserve the largest LDS among them, so launches that
+// would fit different numbers of workgroups on a CU run in separate slots:
+// the class bounds are 160 KB / k for k = 10, 8, 6, 5, 4, 3, 2).
+constexpr int kLdsClasses = 8;
 constexpr int kRounds = 2 * kLdsClasses;
-inline int lds_class(int lds) { return lds <= 40 * 1024 ? 0 : lds <= 52 * 1024 ? 1 : lds <= 80 * 1024 ? 2 : 3; }
+inline int lds_class(int lds)
+{
+    constexpr int bound[kLdsClasses - 1] = {16 * 1024, 20 * 1024, 26 * 1024 + 682, 32 * 1024,
+                                            40 * 1024, 53 * 1024 + 341, 80 * 1024};
+    int c = 0;
+    while (c < kLdsClasses - 1 && lds > bound[c]) ++c;
+    return c;
+}
 
 // Per-problem counters, advanced on the device.  The sketch index of step k
 // is drawn on the device from the same SplitMix64 stream as the host draw.
@@ -547,6 +555,7 @@ struct BatchRec {
     int variant, round, blob;
     int gx, gy, gz, items;
     int lds;  // dynamic LDS the launch needs
+    int ord, ibefore;  // earlier records of this step with the same stage slot: count and items
 };
 
 // Device pointers of a batch buffer.

@@ -2774,53 +2774,60 @@ __global__ void __launch_bounds__(1024) k_batch_plan(BatchView bv)
             sl = j * 2 + pb.cur;
         }
         bv.sel[q] = sl;
-        // offsets follow the work order (largest problems first, so their
-        // long items start early and the short ones fill the tail)
-        const int pos = bv.rank[q];
-        const size_t base = ((size_t)q * bv.r_max * 2 + (sl >= 0 ? sl : 0)) * slots;
-        for (int vr = 0; vr < slots; ++vr) {
-            bv.off[(size_t)vr * (n + 1) + pos + 1] = sl >= 0 ? bv.items[base + vr] : 0;
-            bv.segc[(size_t)vr * (n + 1) + pos + 1] = sl >= 0 ? bv.nsegs[base + vr] : 0;
-        }
     }
     __syncthreads();
+    // per (problem, stage slot): its items and records, at the problem's
+    // place in the work order (largest problems first, so their long items
+    // start early and the short ones fill the tail)
+    for (int idx = threadIdx.x; idx < n * slots; idx += blockDim.x) {
+        const int q = idx / slots, vr = idx - q * slots;
+        const int sl = bv.sel[q];
+        const size_t base = ((size_t)q * bv.r_max * 2 + (sl >= 0 ? sl : 0)) * slots;
+        const size_t at = (size_t)vr * (n + 1) + bv.rank[q] + 1;
+        bv.off[at] = sl >= 0 ? bv.items[base + vr] : 0;
+        bv.segc[at] = sl >= 0 ? bv.nsegs[base + vr] : 0;
+    }
+    __syncthreads();
+    // running sums in registers (a chain through memory would wait on every
+    // store it just made)
     for (int vr = threadIdx.x; vr < slots; vr += blockDim.x) {
         int* o = bv.off + (size_t)vr * (n + 1);
         int* c = bv.segc + (size_t)vr * (n + 1);
+        int so = 0, sc = 0;
         o[0] = 0;
         c[0] = 0;
         for (int q = 0; q < n; ++q) {
-            o[q + 1] += o[q];
-            c[q + 1] += c[q];
+            so += o[q + 1];
+            sc += c[q + 1];
+            o[q + 1] = so;
+            c[q + 1] = sc;
         }
     }
     __syncthreads();
     if (threadIdx.x == 0) {
+        int acc = 0;
         bv.seg_off[0] = 0;
-        for (int vr = 0; vr < slots; ++vr) bv.seg_off[vr + 1] = bv.seg_off[vr] + bv.segc[(size_t)vr * (n + 1) + n];
+        for (int vr = 0; vr < slots; ++vr) {
+            acc += bv.segc[(size_t)vr * (n + 1) + n];
+            bv.seg_off[vr + 1] = acc;
+        }
     }
     __syncthreads();
-    for (int q = threadIdx.x; q < n; q += blockDim.x) {
+    // one segment per record of each active problem: its place among the
+    // slot's segments and its first item (the counts of earlier records of
+    // the same slot are stored with the record)
+    for (int idx = threadIdx.x; idx < n * kMaxRec; idx += blockDim.x) {
+        const int q = idx / kMaxRec, j = idx - q * kMaxRec;
         const int sl = bv.sel[q];
         if (sl < 0) continue;
-        const size_t r0 = ((size_t)q * bv.r_max * 2 + sl) * kMaxRec;
-        const int nr = bv.nrec[(size_t)q * bv.r_max * 2 + sl];
-        for (int j = 0; j < nr; ++j) {
-            const BatchRec& rc = bv.rec[r0 + j];
-            const int vr = rc.variant * kRounds + rc.round;
-            int before = 0, items_before = 0;  // earlier records of the same slot
-            for (int t = 0; t < j; ++t) {
-                const BatchRec& e = bv.rec[r0 + t];
-                if (e.variant == rc.variant && e.round == rc.round) {
-                    ++before;
-                    items_before += e.items;
-                }
-            }
-            const int rq = bv.rank[q];
-            const int pos = bv.seg_off[vr] + bv.segc[(size_t)vr * (n + 1) + rq] + before;
-            bv.seg[2 * pos] = (int)(r0 + j);
-            bv.seg[2 * pos + 1] = bv.off[(size_t)vr * (n + 1) + rq] + items_before;
-        }
+        const size_t sq = (size_t)q * bv.r_max * 2 + sl;
+        if (j >= bv.nrec[sq]) continue;
+        const BatchRec& rc = bv.rec[sq * kMaxRec + j];
+        const int vr = rc.variant * kRounds + rc.round;
+        const int rq = bv.rank[q];
+        const int pos = bv.seg_off[vr] + bv.segc[(size_t)vr * (n + 1) + rq] + rc.ord;
+        bv.seg[2 * pos] = (int)(sq * kMaxRec + j);
+        bv.seg[2 * pos + 1] = bv.off[(size_t)vr * (n + 1) + rq] + rc.ibefore;
     }
 }
 
@@ -2837,6 +2844,26 @@ __global__ void k_batch_advance(BatchView bv)
     pb.cur ^= 1;
 }
 
+// The argument block of an item as a value every lane holds alike: each word
+// read from LDS goes through readfirstlane, so the compiler keeps the
+// arguments (and what the body derives from them) in scalar registers, as
+// it does for a kernel's own arguments (read in place from LDS, they are
+// per-lane values to it: the transpose's inner loop then issued 60% more
+// VALU instructions).  Used where the block has no array the body indexes
+// at run time; such a copy would live in scratch memory.
+template <class T>
+__device__ __forceinline__ T uniform_args(const unsigned char* lds)
+{
+    static_assert(sizeof(T) % 4 == 0, "argument blocks are whole words");
+    constexpr int nw = (int)(sizeof(T) / 4);
+    int w[nw];
+#pragma unroll
+    for (int i = 0; i < nw; ++i) w[i] = __builtin_amdgcn_readfirstlane(reinterpret_cast<const int*>(lds)[i]);
+    T out;
+    __builtin_memcpy(&out, w, sizeof(T));
+    return out;
+}
+
 template <int V>
 __device__ __forceinline__ void batch_body(const unsigned char* args, const Blk& bk, float* smem)
 {
@@ -2851,17 +2878,17 @@ __device__ __forceinline__ void batch_body(const unsigned char* args, const Blk&
     } else if constexpr (V == V_RED1) {
         fwd_reduce_body(*reinterpret_cast<const FwdArgs*>(args), bk);
     } else if constexpr (V == V_BP28) {
-        bp_own_body<2, 8>(*reinterpret_cast<const BpOwnArgs*>(args), bk, smem);
+        bp_own_body<2, 8>(uniform_args<BpOwnArgs>(args), bk, smem);
     } else if constexpr (V == V_BP44) {
-        bp_own_body<4, 4>(*reinterpret_cast<const BpOwnArgs*>(args), bk, smem);
+        bp_own_body<4, 4>(uniform_args<BpOwnArgs>(args), bk, smem);
     } else if constexpr (V == V_BP14) {
-        bp_own_body<1, 4>(*reinterpret_cast<const BpOwnArgs*>(args), bk, smem);
+        bp_own_body<1, 4>(uniform_args<BpOwnArgs>(args), bk, smem);
     } else if constexpr (V == V_BP12) {
-        bp_own_body<1, 2>(*reinterpret_cast<const BpOwnArgs*>(args), bk, smem);
+        bp_own_body<1, 2>(uniform_args<BpOwnArgs>(args), bk, smem);
     } else if constexpr (V == V_BP24) {
-        bp_own_body<2, 4>(*reinterpret_cast<const BpOwnArgs*>(args), bk, smem);
+        bp_own_body<2, 4>(uniform_args<BpOwnArgs>(args), bk, smem);
     } else if constexpr (V == V_SUM4 || V == V_SUM1) {
-        const SumArgs& a = *reinterpret_cast<const SumArgs*>(args);
+        const SumArgs a = uniform_args<SumArgs>(args);
         bp_sum_body<V == V_SUM4 ? 4 : 1>(a.a, a.tmp, a.S, bk);
     } else if constexpr (V == V_SUMP4 || V == V_SUMP1) {
         const SumPrimalArgs& a = *reinterpret_cast<const SumPrimalArgs*>(args);
@@ -2882,7 +2909,8 @@ constexpr int kVariantThreads = (V == V_FWD_BAND || V == V_SUM4 || V == V_SUM1 |
 // w, w + grid, ... of the step's list; an item is one workgroup of one
 // problem's launch, found from the offsets by binary search.  The argument
 // block is staged in LDS, where every thread reads it.
-constexpr int kSegLds = 256;  // segment starts a stage kernel keeps in LDS (more: searched in memory)
+constexpr int kSegLds = 64;  // segment starts a stage kernel keeps in LDS (more: searched in memory); small, so
+                             // that the static LDS leaves the large transposes four workgroups per CU
 
 template <int V>
 __global__ void __launch_bounds__(kVariantThreads<V>) k_batch(BatchView bv, int round, int lds_avail)
@@ -2900,7 +2928,8 @@ __global__ void __launch_bounds__(kVariantThreads<V>) k_batch(BatchView bv, int 
         for (int t = threadIdx.x; t < nseg; t += blockDim.x) s_start[t] = seg[2 * t + 1];
         __syncthreads();
     }
-    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    // the record of an item and the item's place in its launch
+    auto find = [&](int item, int& local) -> BatchRec {
         int lo = 0, hi = nseg;  // start[lo] <= item < start[hi]
         while (hi - lo > 1) {
             const int mid = (lo + hi) >> 1;
@@ -2908,22 +2937,45 @@ __global__ void __launch_bounds__(kVariantThreads<V>) k_batch(BatchView bv, int 
             if (st <= item) lo = mid; else hi = mid;
         }
         const int sgi = __builtin_amdgcn_readfirstlane(lo);
-        const int local = item - seg[2 * sgi + 1];
-        const BatchRec rc = bv.rec[seg[2 * sgi]];
-        // unreachable: the segments cover exactly these items, and the
-        // launch reserves the LDS of its largest record
-        if (rc.variant != V || local >= rc.items || rc.lds > lds_avail) continue;
-        const uint4* src = reinterpret_cast<const uint4*>(bv.blobs + (size_t)rc.blob * kBlobBytes);
-        for (int t = threadIdx.x; t < kBlobBytes / 16; t += blockDim.x) reinterpret_cast<uint4*>(s_args)[t] = src[t];
+        local = item - seg[2 * sgi + 1];
+        return bv.rec[seg[2 * sgi]];
+    };
+    static_assert(kBlobBytes / 16 <= 128, "one 16-byte word of an argument block per thread");
+    const bool loader = threadIdx.x < kBlobBytes / 16;
+    // threads below kBlobBytes / 16 hold one word of the next item's
+    // argument block, read while the current item runs
+    uint4 next = {0u, 0u, 0u, 0u};
+    int item = blockIdx.x, local = 0;
+    BatchRec rc{};
+    if (item < total) {
+        rc = find(item, local);
+        if (loader) next = reinterpret_cast<const uint4*>(bv.blobs + (size_t)rc.blob * kBlobBytes)[threadIdx.x];
+    }
+    while (item < total) {
+        if (loader) reinterpret_cast<uint4*>(s_args)[threadIdx.x] = next;
         __syncthreads();
-        Blk bk;
-        bk.x = local % rc.gx;
-        const int t2 = local / rc.gx;
-        bk.y = t2 % rc.gy;
-        bk.z = t2 / rc.gy;
-        bk.gx = rc.gx;
-        batch_body<V>(s_args, bk, smem);
+        const int item2 = item + gridDim.x;
+        int local2 = 0;
+        BatchRec rc2{};
+        if (item2 < total) {
+            rc2 = find(item2, local2);
+            if (loader) next = reinterpret_cast<const uint4*>(bv.blobs + (size_t)rc2.blob * kBlobBytes)[threadIdx.x];
+        }
+        // always true: the segments cover exactly these items, and the
+        // launch reserves the LDS of its largest record
+        if (rc.variant == V && local < rc.items && rc.lds <= lds_avail) {
+            Blk bk;
+            bk.x = local % rc.gx;
+            const int t2 = local / rc.gx;
+            bk.y = t2 % rc.gy;
+            bk.z = t2 / rc.gy;
+            bk.gx = rc.gx;
+            batch_body<V>(s_args, bk, smem);
+        }
         __syncthreads();  // the next item rewrites the arguments and the LDS
+        item = item2;
+        local = local2;
+        rc = rc2;
     }
 }
 

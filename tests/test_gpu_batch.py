@@ -13,7 +13,7 @@ import synth
 from gpu_util import dev, host, say
 
 import paper_2412_10249_amd as pk
-from paper_2412_10249_amd.batch import Batch
+from paper_2412_10249_amd.batch import Batch, BatchGroups
 
 pytestmark = pytest.mark.gpu
 
@@ -110,6 +110,22 @@ def test_batch_two_streams_equal_one_stream(captured):
         p.step(10)
     torch.cuda.synchronize()
     for q, (a, c) in enumerate(zip(o_probs, alone)):
+        assert _same(a, c), q
+
+
+def test_batch_groups_equal_alone():
+    """The problems split in 3 batches replayed concurrently on 3 streams:
+    every problem equal bit for bit to its run alone."""
+    say("batch groups")
+    grouped, alone = _problems(SPECS), _problems(SPECS)
+    bg = BatchGroups(grouped, 15, pk.BUDGET_ITERS, groups=3)
+    bg.run()
+    torch.cuda.synchronize()
+    bg.sync_state()
+    for p in alone:
+        p.step(15)
+    torch.cuda.synchronize()
+    for q, (a, c) in enumerate(zip(grouped, alone)):
         assert _same(a, c), q
 
 

@@ -1040,16 +1040,21 @@ __device__ __forceinline__ void scatter_runs(float* rows, int S, long long urow,
     const int shift = bfx < 0 ? 1 : 0;  // a falling coordinate: the window starts one cell lower
     for (int c0 = 0; c0 < cnt; c0 += 64 * P) {
         long long U[R];
-        unsigned hi0[R];
+        unsigned base[R];
         int cl[R];
-        float v0[R], v1[R], v2[R];
+        // per row: the run's left-tap and right-tap totals, and the parts of
+        // them from samples past the crossing into the next cell (the run
+        // crosses at most once); then base gets tl - al, base+1 gets
+        // (tr - ar) + al and base+2 gets ar.  A run of one sample gives its
+        // two weights exactly, so every matrix entry is the forward's.
+        float tl[R], tr[R], al[R], ar[R];
         const long long u0 = urow + (long long)(blo + c0 + lane * P) * bfx;
 #pragma unroll
         for (int rr = 0; rr < R; ++rr) {
             U[rr] = u0 + rr * afx;
-            hi0[rr] = (unsigned)(U[rr] >> 32);
-            cl[rr] = rr * S + (int)min(hi0[rr] - (unsigned)shift, (unsigned)(S - 3));
-            v0[rr] = v1[rr] = v2[rr] = 0.0f;
+            base[rr] = (unsigned)(U[rr] >> 32) - (unsigned)shift;
+            cl[rr] = rr * S + (int)min(base[rr], (unsigned)(S - 3));
+            tl[rr] = tr[rr] = al[rr] = ar[rr] = 0.0f;
         }
         const int yb = (c0 + lane * P) * 4;
         float ynext = buffer_float(yr, yb);
@@ -1059,14 +1064,14 @@ __device__ __forceinline__ void scatter_runs(float* rows, int S, long long urow,
             ynext = buffer_float(yr, yb + (t + 1) * 4);
 #pragma unroll
             for (int rr = 0; rr < R; ++rr) {
-                const unsigned hi = (unsigned)(U[rr] >> 32);
                 const float cu = (float)(unsigned)(U[rr] & 0xffffffffLL);
                 const float t0 = fmaf(cu, -kTwoM32, 1.0f) * wy;  // (1 - w) y, as in the forward
                 const float t1 = cu * wys;                       // w y
-                const bool up = hi - hi0[rr] + (unsigned)shift != 0u;  // taps at base+1, base+2
-                v0[rr] += up ? 0.0f : t0;
-                v1[rr] += up ? t0 : t1;
-                v2[rr] += up ? t1 : 0.0f;
+                const float up = (unsigned)(U[rr] >> 32) != base[rr] ? 1.0f : 0.0f;  // taps at base+1, base+2
+                tl[rr] += t0;
+                tr[rr] += t1;
+                al[rr] = fmaf(up, t0, al[rr]);
+                ar[rr] = fmaf(up, t1, ar[rr]);
                 U[rr] += bfx;
             }
         }
@@ -1074,17 +1079,17 @@ __device__ __forceinline__ void scatter_runs(float* rows, int S, long long urow,
 #pragma unroll
         for (int rr = 0; rr < R; ++rr) old[rr] = rows[cl[rr]];
 #pragma unroll
-        for (int rr = 0; rr < R; ++rr) rows[cl[rr]] = old[rr] + v0[rr];
+        for (int rr = 0; rr < R; ++rr) rows[cl[rr]] = old[rr] + (tl[rr] - al[rr]);
         IMK_LDS_ORDER();
 #pragma unroll
         for (int rr = 0; rr < R; ++rr) old[rr] = rows[cl[rr] + 1];
 #pragma unroll
-        for (int rr = 0; rr < R; ++rr) rows[cl[rr] + 1] = old[rr] + v1[rr];
+        for (int rr = 0; rr < R; ++rr) rows[cl[rr] + 1] = old[rr] + ((tr[rr] - ar[rr]) + al[rr]);
         IMK_LDS_ORDER();
 #pragma unroll
         for (int rr = 0; rr < R; ++rr) old[rr] = rows[cl[rr] + 2];
 #pragma unroll
-        for (int rr = 0; rr < R; ++rr) rows[cl[rr] + 2] = old[rr] + v2[rr];
+        for (int rr = 0; rr < R; ++rr) rows[cl[rr] + 2] = old[rr] + ar[rr];
         IMK_LDS_ORDER();
     }
 }

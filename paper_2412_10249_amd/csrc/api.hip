@@ -461,6 +461,11 @@ static void step_records(const imask_geometry& g, const Layout& L, const imask_l
     auto raw_bp = [&](int l) { return bp_args(L, W, l, st.y[cur], W + L.craw[l], 1.0f, 0, 0); };
     if (k > 0 || lv.r == 1) {
         plan_bp_primal(raw_bp(lv.log2f[k]), pr, out);
+    } else if (lv.full_mode == IMASK_FULL_PAPER && sum_primal_tile_fits(pr)) {
+        // level 0's partial images summed per tile inside the primal step
+        BpOwnArgs used;
+        plan_bp_main(raw_bp(0), 0, out, &used);
+        plan_sum_primal_tile(used, pr, out);
     } else {
         plan_bp(raw_bp(0), 0, out);
         if (lv.full_mode == IMASK_FULL_UNBIASED) {
@@ -614,6 +619,14 @@ static int one_step(const imask_geometry& g, const Layout& L, const imask_levels
         // launched with the forward records above
     } else if (k > 0 || lv.r == 1) {
         IMK_TRY(launch_bp_primal(raw_bp(lv.log2f[k]), pr, s));
+    } else if (lv.full_mode == IMASK_FULL_PAPER && sum_primal_tile_fits(pr)) {
+        // level 0's partial images summed per tile inside the primal step,
+        // as on the plain path
+        BpOwnArgs used;
+        IMK_TRY(launch_bp_main(raw_bp(0), s, used));
+        Launches r;
+        plan_sum_primal_tile(used, pr, r);
+        IMK_TRY(launch_records(r, s));
     } else {
         IMK_TRY(launch_bp(raw_bp(0), s));
         if (lv.full_mode == IMASK_FULL_UNBIASED)
@@ -832,7 +845,7 @@ static int variant_phase(int v)
     case V_PREP: case V_FWD_BAND: case V_FWD_DIRECT: case V_RED4: case V_RED1: return 0;
     case V_BP28: case V_BP44: case V_BP14: case V_BP12: case V_BP24: return 1;
     case V_SUM4: case V_SUM1: return 2;
-    case V_SUMP4: case V_SUMP1: case V_PRIMAL: return 3;
+    case V_SUMP4: case V_SUMP1: case V_PRIMAL: case V_SUMPT: return 3;
     default: return -1;
     }
 }

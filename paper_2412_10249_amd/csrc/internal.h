@@ -430,6 +430,7 @@ enum Variant {
     V_SUMP4,
     V_SUMP1,
     V_PRIMAL,
+    V_SUMPT,  // level 0's ordered partial sum with the tile primal step (PAPER sketches)
     kNumVariants,
     // single-problem launches over several levels at once (the UNBIASED
     // full-resolution sketch); the batched path runs levels together anyway
@@ -468,6 +469,10 @@ struct SumPrimalArgs {
     PrimalArgs p;
     int S;
 };
+struct SumTileArgs {
+    BpOwnArgs a;
+    PrimalArgs p;
+};
 struct SumMultiArgs {
     int n;
     int start[IMASK_MAX_LEVELS + 1];
@@ -504,6 +509,11 @@ void plan_bp_main(const BpArgs& ba, int round, Launches& out, BpOwnArgs* used);
 void plan_bp(const BpArgs& ba, int round, Launches& out);       // transpose + ordered sum (no prolongation)
 void plan_bp_primal(const BpArgs& ba, const PrimalArgs& pr, Launches& out);
 void plan_primal(const PrimalArgs& a, Launches& out);
+// Level 0's ordered sum of the partial images `a` wrote, fused with the
+// primal step of a PAPER full-resolution sketch (one workgroup per 32 x 32
+// tile), where sum_primal_tile_fits: N a multiple of 32, levels down to 32.
+bool sum_primal_tile_fits(const PrimalArgs& pr);
+void plan_sum_primal_tile(const BpOwnArgs& a, const PrimalArgs& pr, Launches& out);
 // The terms of an UNBIASED full-resolution sketch: every band-layout forward
 // term in one launch (direct terms launched alone), and the coarse levels'
 // transposes in one launch per tile shape with their partial images side by

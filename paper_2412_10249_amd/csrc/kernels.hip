@@ -1394,6 +1394,8 @@ __global__ void k_prolong_acc(const float* in, float* out, int n, int lvl, int a
 // the SAGA estimate xi with the old tables, v = x - tau xi, and writes
 // prox_scale * v; then refreshes table k.  One workgroup per T x T tile
 // (T a multiple of every level's block, so coarse cells never straddle).
+__device__ __forceinline__ void primal_tile(const PrimalArgs& a, int ty, int tx, const float* pyr);
+
 __device__ __forceinline__ void primal_body(const PrimalArgs& a, const Blk& bk, float* pyr)
 {
     const int tiles = a.n / a.T;
@@ -1403,6 +1405,15 @@ __device__ __forceinline__ void primal_body(const PrimalArgs& a, const Blk& bk, 
         load_tile(pyr, a.craw[0], a.n, a.T, ty, tx);
         build_pyramid(pyr, a.T, a.pyr_levels);
     }
+    primal_tile(a, ty, tx, pyr);
+}
+
+// The primal step of one T x T tile (tile row ty, column tx); for a PAPER
+// full-resolution sketch `pyr` holds the tile's raw backprojection and its
+// 2x2-mean pyramid.
+__device__ __forceinline__ void primal_tile(const PrimalArgs& a, int ty, int tx, const float* pyr)
+{
+    const bool paper_full = (a.kidx == 0 && a.full_mode == IMASK_FULL_PAPER && a.r > 1);
     const float ip0 = 1.0f / a.p[0];
     for (int qq = threadIdx.x; qq < a.T * a.T; qq += blockDim.x) {
         const int ti = qq / a.T, tj = qq - ti * a.T;
@@ -1466,6 +1477,66 @@ __global__ void __launch_bounds__(256) k_primal(PrimalArgs a)
 {
     extern __shared__ float pyr[];
     primal_body(a, this_block(), pyr);
+}
+
+// Level 0 of a PAPER full-resolution sketch: the workgroup's 32 x 32 tile
+// of the raw backprojection, each pixel's partial images summed in a fixed
+// order (kSumTileSlices consecutive slices of the partials, each summed in
+// partial order, then the slices in order; 16-byte loads, rows of the tile
+// are whole 128-byte lines), scaled by the transpose's coefficient, into
+// the tile pyramid; then the primal step of the tile as k_primal takes it.
+// The raw backprojection itself is never stored.
+constexpr int kSumTileSlices = 4;
+constexpr int kSumTileThreads = 1024;
+__device__ __forceinline__ void sum_primal_tile_body(const BpOwnArgs& a, const PrimalArgs& p, const Blk& bk,
+                                                     float* pyr)
+{
+    constexpr int T = 32;  // plan_sum_primal_tile
+    const int tiles = p.n / T;
+    const int ty = bk.x / tiles, tx = bk.x - ty * tiles;
+    const size_t d = (size_t)p.n * p.n;
+    float* red = pyr + 2 * T * T;  // kSumTileSlices x T^2 slice sums (the pyramid needs under 2 T^2)
+    {
+        const int per = T * T / 4;  // threads of one slice: four pixels each
+        const int sl = threadIdx.x / per, f = threadIdx.x - sl * per;
+        const int qq = 4 * f;
+        const int ti = qq / T, tj = qq - ti * T;
+        const float* pp = a.part + (size_t)(ty * T + ti) * p.n + tx * T + tj;
+        const int q0 = sl * a.nq / kSumTileSlices, q1 = (sl + 1) * a.nq / kSumTileSlices;
+        float sum[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        int q = q0;
+        for (; q + 8 <= q1; q += 8) {  // eight loads in flight, added in partial order
+            float v[8][4];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) ld4(pp + (size_t)(q + u) * d, v[u]);
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) sum[c] += v[u][c];
+        }
+        for (; q < q1; ++q) {
+            float v[4];
+            ld4(pp + (size_t)q * d, v);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) sum[c] += v[c];
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) red[sl * T * T + qq + c] = sum[c];
+    }
+    __syncthreads();
+    for (int qq = threadIdx.x; qq < T * T; qq += blockDim.x) {
+        float c = red[qq];
+        for (int k = 1; k < kSumTileSlices; ++k) c += red[k * T * T + qq];
+        pyr[qq] = a.coef * c;
+    }
+    build_pyramid(pyr, T, p.pyr_levels);
+    primal_tile(p, ty, tx, pyr);
+}
+
+__global__ void __launch_bounds__(kSumTileThreads) k_sum_primal_tile(SumTileArgs a)
+{
+    extern __shared__ float pyr[];
+    sum_primal_tile_body(a.a, a.p, this_block(), pyr);
 }
 
 // ------------------------------------- several levels of one sketch per launch
@@ -2562,6 +2633,25 @@ hipError_t launch_bp_primal(const BpArgs& ba, const PrimalArgs& pr, hipStream_t 
     return hipGetLastError();
 }
 
+bool sum_primal_tile_fits(const PrimalArgs& pr) { return pr.n % 32 == 0 && pr.pyr_levels <= 5; }
+
+void plan_sum_primal_tile(const BpOwnArgs& a, const PrimalArgs& pr, Launches& out)
+{
+    // 32 x 32 tiles (whole 128-byte rows of every partial image, 16-byte
+    // loads); sum_primal_tile_fits holds
+    PrimalArgs p = pr;
+    p.T = 32;
+    Launch L;
+    L.variant = V_SUMPT;
+    const int tiles = p.n / p.T;
+    L.gx = (unsigned)(tiles * tiles);
+    L.block = kSumTileThreads;
+    static_assert(kSumTileThreads == kSumTileSlices * 32 * 32 / 4, "four pixels per thread per slice");
+    L.lds = (int)((2 + kSumTileSlices) * 32 * 32 * sizeof(float));  // pyramid, then the slice sums
+    L.set(SumTileArgs{a, p});
+    out.push_back(L);
+}
+
 void plan_primal(const PrimalArgs& a, Launches& out)
 {
     Launch L;
@@ -2601,6 +2691,7 @@ static const void* variant_kernel(int v)
     case V_SUMP4: return (const void*)k_bp_sum_primal<4>;
     case V_SUMP1: return (const void*)k_bp_sum_primal<1>;
     case V_PRIMAL: return (const void*)k_primal;
+    case V_SUMPT: return (const void*)k_sum_primal_tile;
     case V_FWD_MULTI: return (const void*)k_fwd_band_multi;
     case V_BP_MULTI28: return (const void*)k_bp_own_multi<2, 8>;
     case V_BP_MULTI44: return (const void*)k_bp_own_multi<4, 4>;
@@ -2647,6 +2738,7 @@ hipError_t launch_records(const Launches& recs, hipStream_t s)
             break;
         }
         case V_PRIMAL: hipLaunchKernelGGL(k_primal, grid, block, L.lds, s, L.get<PrimalArgs>()); break;
+        case V_SUMPT: hipLaunchKernelGGL(k_sum_primal_tile, grid, block, L.lds, s, L.get<SumTileArgs>()); break;
         case V_FWD_MULTI: hipLaunchKernelGGL(k_fwd_band_multi, grid, block, L.lds, s, L.get<FwdMultiArgs>()); break;
         case V_BP_MULTI28:
             hipLaunchKernelGGL((k_bp_own_multi<2, 8>), grid, block, L.lds, s, L.get<BpMultiArgs>());
@@ -2898,14 +2990,25 @@ __device__ __forceinline__ void batch_body(const unsigned char* args, const Blk&
     } else if constexpr (V == V_SUMP4 || V == V_SUMP1) {
         const SumPrimalArgs& a = *reinterpret_cast<const SumPrimalArgs*>(args);
         bp_sum_primal_body<V == V_SUMP4 ? 4 : 1>(a.a, a.S, a.p, bk);
+    } else if constexpr (V == V_SUMPT) {
+        const SumTileArgs& a = *reinterpret_cast<const SumTileArgs*>(args);
+        sum_primal_tile_body(a.a, a.p, bk, smem);
     } else {
         primal_body(*reinterpret_cast<const PrimalArgs*>(args), bk, smem);
     }
 }
 
+static_assert(sizeof(PrepArgs) <= kBlobBytes && sizeof(FwdBandArgs) <= kBlobBytes && sizeof(FwdArgs) <= kBlobBytes &&
+                  sizeof(BpOwnArgs) <= kBlobBytes && sizeof(SumArgs) <= kBlobBytes &&
+                  sizeof(SumPrimalArgs) <= kBlobBytes && sizeof(SumTileArgs) <= kBlobBytes &&
+                  sizeof(PrimalArgs) <= kBlobBytes,
+              "a batched variant's argument block fits its slot");
+
 // Threads per workgroup of each variant (those of its single-problem kernel).
 template <int V>
-constexpr int kVariantThreads = (V == V_FWD_BAND || V == V_SUM4 || V == V_SUM1 || V == V_SUMP4 || V == V_SUMP1) ? 1024
+constexpr int kVariantThreads = (V == V_FWD_BAND || V == V_SUM4 || V == V_SUM1 || V == V_SUMP4 || V == V_SUMP1 ||
+                                  V == V_SUMPT)
+                                     ? 1024
                                 : V == V_BP28                                                                    ? 512
                                 : V == V_BP12                                                                    ? 128
                                                                                                                  : 256;
@@ -2989,7 +3092,7 @@ __global__ void __launch_bounds__(kVariantThreads<V>) k_batch(BatchView bv, int 
 int variant_threads(int v)
 {
     switch (v) {
-    case V_FWD_BAND: case V_SUM4: case V_SUM1: case V_SUMP4: case V_SUMP1: return 1024;
+    case V_FWD_BAND: case V_SUM4: case V_SUM1: case V_SUMP4: case V_SUMP1: case V_SUMPT: return 1024;
     case V_BP28: return 512;
     case V_BP12: return 128;
     default: return 256;
@@ -3017,6 +3120,7 @@ static const void* batch_kernel_of(int v)
     case V_SUMP4: return batch_kernel<V_SUMP4>();
     case V_SUMP1: return batch_kernel<V_SUMP1>();
     case V_PRIMAL: return batch_kernel<V_PRIMAL>();
+    case V_SUMPT: return batch_kernel<V_SUMPT>();
     default: return nullptr;
     }
 }
@@ -3066,6 +3170,7 @@ hipError_t launch_batch_stage(int v, int round, const BatchView& bv, unsigned gr
     case V_SUMP4: hipLaunchKernelGGL(k_batch<V_SUMP4>, g, dim3(1024), lds, s, bv, round, lds); break;
     case V_SUMP1: hipLaunchKernelGGL(k_batch<V_SUMP1>, g, dim3(1024), lds, s, bv, round, lds); break;
     case V_PRIMAL: hipLaunchKernelGGL(k_batch<V_PRIMAL>, g, dim3(256), lds, s, bv, round, lds); break;
+    case V_SUMPT: hipLaunchKernelGGL(k_batch<V_SUMPT>, g, dim3(1024), lds, s, bv, round, lds); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -259,6 +259,7 @@ struct BpOwnArgs {
     const RayConst* consts;
     FanGeo fan;
     int n, na, nd, lvl;
+    int wave_range;  // each wavefront takes the bins of its own rows (else the workgroup's)
     const float* y;
     float* part;  // nq partial images N_l x N_l, image orientation
     int G;

@@ -918,11 +918,12 @@ __global__ void __launch_bounds__(256) k_fwd_reduce4(FwdArgs a) { fwd_reduce4_bo
 // same fixed-point coordinate as the forward: the pair is an exact transpose.
 // Sinogram values are read from global memory, one trip ahead of their use.
 //
-// Taps are not range-tested per sample.  Every bin of a workgroup's range
-// reaches [-1, nl] at one of its kBpRowsPerWg rows, and the coordinate moves
-// by at most one pixel per row (|slope| <= 1 on the stepping axis), so at any
-// row of the workgroup the left tap lies in [-(rows+1), nl+rows-1].  Each LDS
-// row of S = nl + 2 kBpPad cells puts kBpPad >= rows+3 spare cells on both
+// Taps are not range-tested per sample.  Every bin of a wavefront's range
+// (the bins of its workgroup's rows, or of its own R rows) reaches [-1, nl]
+// at one of the workgroup's rows, and the coordinate moves by at most one
+// pixel per row (|slope| <= 1 on the stepping axis), so at any row of the
+// workgroup the left tap lies in [-(rows+1), nl+rows-1].  Each LDS row of
+// S = nl + 2 kBpPad cells puts kBpPad >= rows+3 spare cells on both
 // sides; a tap's cell index (tap + kBpPad) is clamped as an unsigned number to
 // S-2, so every tap outside the row (beyond either end) lands in the last two
 // cells, which no in-range tap reaches and which are never read back.  Only
@@ -942,14 +943,16 @@ struct BpShape {
     static_assert(pad >= rows + 3, "sink cells must lie beyond every in-range tap");
 };
 
-// Bins whose coordinate at steps r0 .. r0+nr-1 can reach [-1, nl].
-__device__ __forceinline__ void bin_range(const RayConst& kc, int r0, int nrows, int nl, int nd, int& blo, int& cnt)
+// Bins whose coordinate at steps r0 .. r0+nr-1 can reach [-1, nl] (ray
+// constants a, c and 1/b in FP32; margins of 0.01 pixel cover their rounding).
+__device__ __forceinline__ void bin_range(float ka, float kcc, float kib, int r0, int nrows, int nl, int nd, int& blo,
+                                          int& cnt)
 {
     const float fnl = (float)nl, bmax = (float)(nd - 1);
-    const float base0 = fmaf((float)r0, kc.a, kc.c);
-    const float base1 = base0 + (float)(nrows - 1) * kc.a;
-    const float e0 = (-1.01f - base0) * kc.ib, e1 = (fnl + 0.01f - base0) * kc.ib;
-    const float e2 = (-1.01f - base1) * kc.ib, e3 = (fnl + 0.01f - base1) * kc.ib;
+    const float base0 = fmaf((float)r0, ka, kcc);
+    const float base1 = base0 + (float)(nrows - 1) * ka;
+    const float e0 = (-1.01f - base0) * kib, e1 = (fnl + 0.01f - base0) * kib;
+    const float e2 = (-1.01f - base1) * kib, e3 = (fnl + 0.01f - base1) * kib;
     blo = (int)fminf(fmaxf(ceilf(fminf(fminf(e0, e1), fminf(e2, e3))), 0.0f), bmax + 1.0f);
     const int bhi = (int)fmaxf(fminf(floorf(fmaxf(fmaxf(e0, e1), fmaxf(e2, e3))), bmax), -1.0f);
     cnt = bhi - blo + 1;
@@ -1094,13 +1097,22 @@ __device__ __forceinline__ void scatter_runs(float* rows, int S, long long urow,
     }
 }
 
-// What a wavefront needs of one angle, tabulated in LDS by the workgroup.
+// What a wavefront needs of one angle, tabulated in LDS by the workgroup:
+// the bins of the workgroup's rows, or (wave_range) the FP32 constants from
+// which each wavefront finds the bins of its own rows.
 struct BpAngle {
     long long afx, bfx, cfx;  // fixed-point coordinate constants
     float w;                  // ray weight
     int phases;
-    int blo, cnt;             // bins of the workgroup's range
-    int ang, pad;
+    int ang;
+    union {
+        struct {
+            int blo, cnt;
+        } r;
+        struct {
+            float a, c, ib;
+        } k;
+    };
 };
 static_assert(sizeof(BpAngle) == 48, "BpAngle layout");
 constexpr int kBpAngTab = 128;  // angles a workgroup tabulates at once
@@ -1144,18 +1156,36 @@ __device__ __forceinline__ void bp_own_body(const BpOwnArgs& a, const Blk& bk, f
             e.cfx = kc.cfx;
             e.w = kc.w;
             e.phases = kc.phases;
-            bin_range(kc, rwg, nwg, nl, a.nd, e.blo, e.cnt);
             e.ang = ang;
-            e.pad = 0;
+            if (a.wave_range) {
+                e.k.a = kc.a;
+                e.k.c = kc.c;
+                e.k.ib = kc.ib;
+            } else {
+                bin_range(kc.a, kc.c, kc.ib, rwg, nwg, nl, a.nd, e.r.blo, e.r.cnt);
+            }
             tab[t] = e;
         }
         __syncthreads();
         if (nown == 0) continue;
         for (int t = 0; t < nk; ++t) {
             const BpAngle& e = tab[t];
-            const int cnt = __builtin_amdgcn_readfirstlane(e.cnt);
+            int blo, cnt;
+            if (a.wave_range) {
+                // the bins that reach this wavefront's own rows: a tighter
+                // range where the workgroup's rows are a large part of the
+                // image (fewer idle lanes), at about 30 instructions per angle
+                bin_range(__builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, e.k.a))),
+                          __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, e.k.c))),
+                          __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, e.k.ib))),
+                          r0, nown, nl, a.nd, blo, cnt);
+            } else {
+                blo = e.r.blo;
+                cnt = e.r.cnt;
+            }
+            blo = __builtin_amdgcn_readfirstlane(blo);
+            cnt = __builtin_amdgcn_readfirstlane(cnt);
             if (cnt <= 0) continue;
-            const int blo = __builtin_amdgcn_readfirstlane(e.blo);
             const int ang = __builtin_amdgcn_readfirstlane(e.ang);
             const int P = __builtin_amdgcn_readfirstlane(e.phases);
             const float kw = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, e.w)));
@@ -2279,6 +2309,10 @@ static void plan_scatter(BpOwnArgs& a, int nl, int lvl, int variant, int round, 
                                                              1024LL}));
     a.G = std::max(1, std::min(gmax, (target + 2 * nb - 1) / (2 * nb)));
     a.nq = 2 * a.G;
+    // per-wavefront bin ranges where a workgroup's rows are an eighth of the
+    // image or more (512^2 / 720 x 768, level 3: 22.5 -> 19.0 us; level 0,
+    // where the rows are 1/64 of it, pays 4% for the extra range work)
+    a.wave_range = Sh::rows * 8 >= nl;
     Launch L;
     L.variant = variant;
     L.round = round;

@@ -2171,8 +2171,11 @@ static Launch fwd_term_launch(const FwdArgs& a, int t, FwdBandArgs* args_out)
             fb.R = tm.rows;
             fb.bands = tm.bands;
             // about 512 workgroups of 1024 threads over the angles this
-            // launch projects (a measurement block covers only some of them)
-            fb.apg = std::max(1, ((sp.nrow + sp.ncol) * tm.bands + 511) / 512);
+            // launch projects (a measurement block covers only some of them);
+            // 1024 where one band covers the level: its small band lets two
+            // workgroups share a CU, and finer groups even out the CUs' work
+            const int wg_target = tm.bands == 1 ? 1024 : 512;
+            fb.apg = std::max(1, ((sp.nrow + sp.ncol) * tm.bands + wg_target - 1) / wg_target);
             fb.groups_row = (sp.nrow + fb.apg - 1) / fb.apg;
             fb.groups_col = (sp.ncol + fb.apg - 1) / fb.apg;
             L.variant = V_FWD_BAND;

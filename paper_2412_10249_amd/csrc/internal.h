@@ -438,7 +438,14 @@ enum Variant {
     V_FWD_MULTI = kNumVariants,
     V_BP_MULTI28,
     V_BP_MULTI44,
-    V_SUM_MULTI
+    V_SUM_MULTI,
+    // a transpose with the forward's band reduce in its last workgroups
+    // (the two are independent in Alg. 1's parallel schedule)
+    V_BPRED28,
+    V_BPRED44,
+    V_BPRED14,
+    V_BPRED12,
+    V_BPRED24
 };
 constexpr int kLaunchArgBytes = 3072;
 constexpr int kBlobBytes = 640;  // argument blocks of the batched variants
@@ -473,6 +480,13 @@ struct SumPrimalArgs {
 struct SumTileArgs {
     BpOwnArgs a;
     PrimalArgs p;
+};
+// Blocks [0, nbp) of the launch are the transpose's (its grid bgx x (nbp /
+// bgx)), blocks [nbp, nbp + nred) the reduce's (16-byte accesses if red4).
+struct BpRedArgs {
+    BpOwnArgs b;
+    FwdArgs f;
+    int nbp, bgx, nred, red4;
 };
 struct SumMultiArgs {
     int n;
@@ -515,6 +529,10 @@ void plan_primal(const PrimalArgs& a, Launches& out);
 // tile), where sum_primal_tile_fits: N a multiple of 32, levels down to 32.
 bool sum_primal_tile_fits(const PrimalArgs& pr);
 void plan_sum_primal_tile(const BpOwnArgs& a, const PrimalArgs& pr, Launches& out);
+// Moves the step's band reduce (a V_RED4 / V_RED1 record) into the first
+// transpose launch after it, as extra workgroups; single-problem steps of
+// the parallel schedule only (the transpose reads the old dual iterate).
+void merge_reduce_into_transpose(Launches& out);
 // The terms of an UNBIASED full-resolution sketch: every band-layout forward
 // term in one launch (direct terms launched alone), and the coarse levels'
 // transposes in one launch per tile shape with their partial images side by

@@ -1264,6 +1264,23 @@ __global__ void __launch_bounds__(64 * W) k_bp_own(BpOwnArgs a)
     bp_own_body<R, W>(a, this_block(), smem);
 }
 
+// The transpose's workgroups, then the forward's band reduce in the last
+// ones: the memory-bound reduce fills the tail of the LDS-bound transpose,
+// and the step has one launch fewer.
+template <int R, int W>
+__global__ void __launch_bounds__(64 * W) k_bp_red(BpRedArgs a)
+{
+    extern __shared__ float smem[];
+    const int b = blockIdx.x;
+    if (b < a.nbp) {
+        bp_own_body<R, W>(a.b, Blk{b % a.bgx, b / a.bgx, 0, a.bgx}, smem);
+    } else if (a.red4) {
+        fwd_reduce4_body(a.f, Blk{b - a.nbp, 0, 0, a.nred});
+    } else {
+        fwd_reduce_body(a.f, Blk{b - a.nbp, 0, 0, a.nred});
+    }
+}
+
 // c = sum over the nq partial images in a fixed order; coef * c is stored coarse
 // (or into `tmp` for a later prolongation).  The nq partials are cut into S
 // consecutive slices (S a power of two, chosen from the image size so that
@@ -2689,6 +2706,41 @@ void plan_sum_primal_tile(const BpOwnArgs& a, const PrimalArgs& pr, Launches& ou
     out.push_back(L);
 }
 
+void merge_reduce_into_transpose(Launches& out)
+{
+    size_t r = out.size(), t = out.size();
+    for (size_t q = 0; q < out.size(); ++q)
+        if (out[q].variant == V_RED4 || out[q].variant == V_RED1) {
+            r = q;
+            break;
+        }
+    for (size_t q = r + 1; q < out.size(); ++q) {
+        const int v = out[q].variant;
+        if (v == V_BP28 || v == V_BP44 || v == V_BP14 || v == V_BP12 || v == V_BP24) {
+            t = q;
+            break;
+        }
+    }
+    if (r >= out.size() || t >= out.size() || out[t].gz != 1) return;
+    const Launch& red = out[r];
+    Launch& tr = out[t];
+    BpRedArgs m{};
+    m.b = tr.get<BpOwnArgs>();
+    m.f = red.get<FwdArgs>();
+    m.bgx = (int)tr.gx;
+    m.nbp = (int)(tr.gx * tr.gy);
+    // the reduce's grid-stride loop covers the sinogram with any block size
+    m.nred = (int)red.gx;
+    m.red4 = red.variant == V_RED4;
+    const int v = tr.variant;
+    tr.variant = v == V_BP28 ? V_BPRED28 : v == V_BP44 ? V_BPRED44 : v == V_BP14 ? V_BPRED14
+                 : v == V_BP12 ? V_BPRED12 : V_BPRED24;
+    tr.gx = (unsigned)(m.nbp + m.nred);
+    tr.gy = 1;
+    tr.set(m);
+    out.erase(out.begin() + (long)r);
+}
+
 void plan_primal(const PrimalArgs& a, Launches& out)
 {
     Launch L;
@@ -2733,6 +2785,11 @@ static const void* variant_kernel(int v)
     case V_BP_MULTI28: return (const void*)k_bp_own_multi<2, 8>;
     case V_BP_MULTI44: return (const void*)k_bp_own_multi<4, 4>;
     case V_SUM_MULTI: return (const void*)k_bp_sum_multi;
+    case V_BPRED28: return (const void*)k_bp_red<2, 8>;
+    case V_BPRED44: return (const void*)k_bp_red<4, 4>;
+    case V_BPRED14: return (const void*)k_bp_red<1, 4>;
+    case V_BPRED12: return (const void*)k_bp_red<1, 2>;
+    case V_BPRED24: return (const void*)k_bp_red<2, 4>;
     default: return nullptr;
     }
 }
@@ -2784,6 +2841,11 @@ hipError_t launch_records(const Launches& recs, hipStream_t s)
             hipLaunchKernelGGL((k_bp_own_multi<4, 4>), grid, block, L.lds, s, L.get<BpMultiArgs>());
             break;
         case V_SUM_MULTI: hipLaunchKernelGGL(k_bp_sum_multi, grid, block, L.lds, s, L.get<SumMultiArgs>()); break;
+        case V_BPRED28: hipLaunchKernelGGL((k_bp_red<2, 8>), grid, block, L.lds, s, L.get<BpRedArgs>()); break;
+        case V_BPRED44: hipLaunchKernelGGL((k_bp_red<4, 4>), grid, block, L.lds, s, L.get<BpRedArgs>()); break;
+        case V_BPRED14: hipLaunchKernelGGL((k_bp_red<1, 4>), grid, block, L.lds, s, L.get<BpRedArgs>()); break;
+        case V_BPRED12: hipLaunchKernelGGL((k_bp_red<1, 2>), grid, block, L.lds, s, L.get<BpRedArgs>()); break;
+        case V_BPRED24: hipLaunchKernelGGL((k_bp_red<2, 4>), grid, block, L.lds, s, L.get<BpRedArgs>()); break;
         default: return hipErrorInvalidValue;
         }
         const hipError_t e = hipGetLastError();

@@ -567,7 +567,10 @@ static int one_step(const imask_geometry& g, const Layout& L, const imask_levels
         // the same launches the batched path stores
         Launches recs;
         step_records(g, L, lv, reg, prm, bdat, st, k, recs, true, prep_ready);
-        merge_reduce_into_transpose(recs);  // the parallel schedule: the transpose reads y^k
+        // the parallel schedule: the transpose reads y^k, so the forward
+        // half's last launch can share the transpose's
+        merge_reduce_into_transpose(recs);
+        merge_forward_into_transpose(recs);
         IMK_TRY(launch_records(recs, s));
     } else {
         if (!prep_ready) IMK_TRY(launch_prep(pa, s));

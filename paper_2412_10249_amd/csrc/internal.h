@@ -445,7 +445,14 @@ enum Variant {
     V_BPRED44,
     V_BPRED14,
     V_BPRED12,
-    V_BPRED24
+    V_BPRED24,
+    // a transpose with a single-band forward (dual step in its epilogue) in
+    // its last workgroups (independent in the parallel schedule)
+    V_BPFWD28,
+    V_BPFWD44,
+    V_BPFWD14,
+    V_BPFWD12,
+    V_BPFWD24
 };
 constexpr int kLaunchArgBytes = 3072;
 constexpr int kBlobBytes = 640;  // argument blocks of the batched variants
@@ -487,6 +494,13 @@ struct BpRedArgs {
     BpOwnArgs b;
     FwdArgs f;
     int nbp, bgx, nred, red4;
+};
+// Blocks [0, nfwd) a single-band forward's (grid fgx x (nfwd / fgx)), the
+// rest the transpose's (grid bgx x (nbp / bgx)).
+struct BpFwdArgs {
+    BpOwnArgs b;
+    FwdBandArgs f;
+    int nbp, bgx, nfwd, fgx;
 };
 struct SumMultiArgs {
     int n;
@@ -533,6 +547,9 @@ void plan_sum_primal_tile(const BpOwnArgs& a, const PrimalArgs& pr, Launches& ou
 // transpose launch after it, as extra workgroups; single-problem steps of
 // the parallel schedule only (the transpose reads the old dual iterate).
 void merge_reduce_into_transpose(Launches& out);
+// Moves a single-band forward with the dual step in its epilogue into the
+// first transpose launch after it (same conditions).
+void merge_forward_into_transpose(Launches& out);
 // The terms of an UNBIASED full-resolution sketch: every band-layout forward
 // term in one launch (direct terms launched alone), and the coarse levels'
 // transposes in one launch per tile shape with their partial images side by

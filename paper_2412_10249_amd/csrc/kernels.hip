@@ -1264,6 +1264,22 @@ __global__ void __launch_bounds__(64 * W) k_bp_own(BpOwnArgs a)
     bp_own_body<R, W>(a, this_block(), smem);
 }
 
+// A single-band forward's workgroups (its dual step in the epilogue), then
+// the transpose's: on coarse levels both are small and latency-bound, and
+// the step has one launch fewer.
+template <int R, int W>
+__global__ void __launch_bounds__(64 * W) k_bp_fwd(BpFwdArgs a)
+{
+    extern __shared__ float smem[];
+    const int b = blockIdx.x;
+    if (b < a.nfwd) {
+        fwd_band_body(a.f, Blk{b % a.fgx, b / a.fgx, 0, a.fgx}, smem);
+    } else {
+        const int t = b - a.nfwd;
+        bp_own_body<R, W>(a.b, Blk{t % a.bgx, t / a.bgx, 0, a.bgx}, smem);
+    }
+}
+
 // The transpose's workgroups, then the forward's band reduce in the last
 // ones: the memory-bound reduce fills the tail of the LDS-bound transpose,
 // and the step has one launch fewer.
@@ -2741,6 +2757,49 @@ void merge_reduce_into_transpose(Launches& out)
     out.erase(out.begin() + (long)r);
 }
 
+void merge_forward_into_transpose(Launches& out)
+{
+    size_t f = out.size(), t = out.size();
+    for (size_t q = 0; q < out.size(); ++q)
+        if (out[q].variant == V_FWD_BAND && out[q].get<FwdBandArgs>().dual) {
+            f = q;
+            break;
+        }
+    for (size_t q = f + 1; q < out.size(); ++q) {
+        const int v = out[q].variant;
+        if (v == V_RED4 || v == V_RED1) return;  // a reduce follows: the forward has several bands
+        if (v == V_BP28 || v == V_BP44 || v == V_BP14 || v == V_BP12 || v == V_BP24) {
+            t = q;
+            break;
+        }
+    }
+    if (f >= out.size() || t >= out.size() || out[t].gz != 1 || out[f].gx != 1) return;
+    const Launch& fw = out[f];
+    Launch& tr = out[t];
+    BpFwdArgs m{};
+    m.b = tr.get<BpOwnArgs>();
+    m.f = fw.get<FwdBandArgs>();
+    // the forward's groups sized for the transpose's block: about as many
+    // rays per thread as with 1024 threads
+    const int scale = std::max(1, 1024 / (int)tr.block);
+    const int apg = std::max(1, m.f.apg / scale);
+    m.f.apg = apg;
+    m.f.groups_row = (m.f.split.nrow + apg - 1) / apg;
+    m.f.groups_col = (m.f.split.ncol + apg - 1) / apg;
+    m.bgx = (int)tr.gx;
+    m.nbp = (int)(tr.gx * tr.gy);
+    m.fgx = 1;
+    m.nfwd = m.f.groups_row + m.f.groups_col;
+    const int v = tr.variant;
+    tr.variant = v == V_BP28 ? V_BPFWD28 : v == V_BP44 ? V_BPFWD44 : v == V_BP14 ? V_BPFWD14
+                 : v == V_BP12 ? V_BPFWD12 : V_BPFWD24;
+    tr.gx = (unsigned)(m.nbp + m.nfwd);
+    tr.gy = 1;
+    tr.lds = std::max(tr.lds, fw.lds);
+    tr.set(m);
+    out.erase(out.begin() + (long)f);
+}
+
 void plan_primal(const PrimalArgs& a, Launches& out)
 {
     Launch L;
@@ -2790,6 +2849,11 @@ static const void* variant_kernel(int v)
     case V_BPRED14: return (const void*)k_bp_red<1, 4>;
     case V_BPRED12: return (const void*)k_bp_red<1, 2>;
     case V_BPRED24: return (const void*)k_bp_red<2, 4>;
+    case V_BPFWD28: return (const void*)k_bp_fwd<2, 8>;
+    case V_BPFWD44: return (const void*)k_bp_fwd<4, 4>;
+    case V_BPFWD14: return (const void*)k_bp_fwd<1, 4>;
+    case V_BPFWD12: return (const void*)k_bp_fwd<1, 2>;
+    case V_BPFWD24: return (const void*)k_bp_fwd<2, 4>;
     default: return nullptr;
     }
 }
@@ -2846,6 +2910,11 @@ hipError_t launch_records(const Launches& recs, hipStream_t s)
         case V_BPRED14: hipLaunchKernelGGL((k_bp_red<1, 4>), grid, block, L.lds, s, L.get<BpRedArgs>()); break;
         case V_BPRED12: hipLaunchKernelGGL((k_bp_red<1, 2>), grid, block, L.lds, s, L.get<BpRedArgs>()); break;
         case V_BPRED24: hipLaunchKernelGGL((k_bp_red<2, 4>), grid, block, L.lds, s, L.get<BpRedArgs>()); break;
+        case V_BPFWD28: hipLaunchKernelGGL((k_bp_fwd<2, 8>), grid, block, L.lds, s, L.get<BpFwdArgs>()); break;
+        case V_BPFWD44: hipLaunchKernelGGL((k_bp_fwd<4, 4>), grid, block, L.lds, s, L.get<BpFwdArgs>()); break;
+        case V_BPFWD14: hipLaunchKernelGGL((k_bp_fwd<1, 4>), grid, block, L.lds, s, L.get<BpFwdArgs>()); break;
+        case V_BPFWD12: hipLaunchKernelGGL((k_bp_fwd<1, 2>), grid, block, L.lds, s, L.get<BpFwdArgs>()); break;
+        case V_BPFWD24: hipLaunchKernelGGL((k_bp_fwd<2, 4>), grid, block, L.lds, s, L.get<BpFwdArgs>()); break;
         default: return hipErrorInvalidValue;
         }
         const hipError_t e = hipGetLastError();

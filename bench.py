@@ -241,7 +241,7 @@ def roofline_block(key, dom, dom_t, samples, fan):
             "hbm_frac_measured": None if traffic is None else traffic / dom_t / 1e9 / HBM_PEAK_GBS,
             "traffic_over_algorithmic": None if traffic is None else traffic / alg,
             "l2_hit_rate": stored_counter(key, "l2_hit_rate"),
-            "lds_bank_conflict_fraction": stored_counter(key, "lds_bank_conflict_fraction")}
+            "lds_conflict_over_active_cycles": stored_counter(key, "lds_conflict_over_active_cycles")}
 
 
 def step_times_by_level(prob, lv, steps):
@@ -1138,7 +1138,7 @@ def summarize(dirs, command_note, counter_key=None):
             if mean_of(c) is not None:
                 derived[c] = mean_of(c)
         if derived.get("SQ_ACTIVE_INST_LDS"):
-            derived["lds_bank_conflict_fraction"] = derived.get("SQ_LDS_BANK_CONFLICT", 0.0) / derived[
+            derived["lds_conflict_over_active_cycles"] = derived.get("SQ_LDS_BANK_CONFLICT", 0.0) / derived[
                 "SQ_ACTIVE_INST_LDS"]
         if derived:
             lines.append("### derived (mean per dispatch)\n")

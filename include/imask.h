@@ -366,7 +366,7 @@ int imask_sigma_balamurugan(double L2, double Lbar2, double* sigma_out);
 int imask_sigma_thm3(double L2, double Lbar2, double Lbarp2, double pmin, int32_t grid, double* sigma_out,
                      double* theta_out);
 
-/* Host: the sketch indices i_k, k = k0 .. k0+count-1 (Alg. 1, "sample i_k"). */
+/* Host: the sketch indices i_k, k = k0 .. k0+count-1 (Alg. 1: one random level per iteration). */
 int imask_draws(const imask_params* prm, const imask_levels* lv, uint64_t k0, int32_t count,
                 int32_t* out_host);
 

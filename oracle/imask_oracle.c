@@ -14,8 +14,8 @@
  *     projection P_l = T_l^* T_l and the full-resolution compensation
  *     S_r = p_r^{-1}(I - sum_l p_l P_l) (Sec. 4.1);
  *   - the sketched operators K_l and their transposes (eq. (CT_sketches));
- *   - the counter-based SplitMix64 draw of the sketch index (Alg. 1, step
- *     "sample i_k with probability p");
+ *   - the counter-based SplitMix64 draw of the sketch index (Alg. 1: each
+ *     iteration picks level i with probability p_i);
  *   - Algorithm 1 (ImaSk) with the Tikhonov prox, a smoothed-TV prox
  *     evaluated by FISTA, and the paper's TV + nonnegativity prox by the
  *     fast gradient projection on the dual (Sec. 4.2 and 4.5);

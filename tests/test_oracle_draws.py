@@ -1,5 +1,5 @@
-"""Pins of the oracle's sketch-index draw ("sample i_k at random with
-probability p", Alg. 1), CPU only.
+"""Pins of the oracle's sketch-index draw (Alg. 1: level i is picked with
+probability p_i in every iteration), CPU only.
 
 The generator is SplitMix64 (Steele, Lea & Flood, OOPSLA 2014) in counter
 form; the first outputs for state 0 are the generator's published test

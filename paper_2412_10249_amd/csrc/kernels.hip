@@ -336,8 +336,11 @@ __device__ __forceinline__ void fwd_band_body(const FwdBandArgs& a, const Blk& b
     const int pass = gidx < a.groups_row ? 0 : 1;
     const int g = pass == 0 ? gidx : gidx - a.groups_row;
     const int npass = pass == 0 ? a.split.nrow : a.split.ncol;
-    const int k0 = g * a.apg;
-    const int nang = min(a.apg, npass - k0);
+    // group g of its pass takes angles g, g + G, g + 2G, ...: every workgroup
+    // gets the same mix of steep and shallow angles (a ray's sample count
+    // follows max(|cos|, |sin|)), so no group is left running alone at the end
+    const int G = pass == 0 ? a.groups_row : a.groups_col;
+    const int nang = (npass - g + G - 1) / G;
     const int i0 = bi * a.R;
     const int i1 = min(nl, i0 + a.R);
     {
@@ -358,7 +361,7 @@ __device__ __forceinline__ void fwd_band_body(const FwdBandArgs& a, const Blk& b
     int kk = threadIdx.x / a.nd;
     int b = threadIdx.x - kk * a.nd;
     while (kk < nang) {
-        const int ang = angle_of(a.split, pass, k0 + kk);
+        const int ang = angle_of(a.split, pass, g + kk * G);
         const RayConst& kc = a.consts[(size_t)a.lvl * a.na + ang];
         int lo, hi;
         ray_steps(kc, (float)b, nl, i0, i1 - 1, lo, hi);
@@ -1132,9 +1135,9 @@ __device__ __forceinline__ void bp_own_body(const BpOwnArgs& a, const Blk& bk, f
     const int pass = gidx / a.G;
     const int g = gidx - pass * a.G;
     const int npass = pass == 0 ? a.split.nrow : a.split.ncol;
-    const int apg = (npass + a.G - 1) / a.G;
-    const int k0 = g * apg;
-    const int nang = max(0, min(apg, npass - k0));
+    // group g takes angles g, g + G, g + 2G, ... of its pass (the same mix
+    // of steep and shallow angles in every group)
+    const int nang = g < npass ? (npass - g + a.G - 1) / a.G : 0;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int rwg = bi * kBpRowsPerWg;                 // first row of the workgroup
@@ -1148,7 +1151,7 @@ __device__ __forceinline__ void bp_own_body(const BpOwnArgs& a, const Blk& bk, f
         const int nk = min(kBpAngTab, nang - kb);
         __syncthreads();  // the previous block of the table is consumed
         for (int t = threadIdx.x; t < nk; t += blockDim.x) {
-            const int ang = angle_of(a.split, pass, k0 + kb + t);
+            const int ang = angle_of(a.split, pass, g + (kb + t) * a.G);
             const RayConst& kc = a.consts[(size_t)a.lvl * a.na + ang];
             BpAngle e;
             e.afx = kc.afx;

@@ -260,6 +260,7 @@ struct BpOwnArgs {
     FanGeo fan;
     int n, na, nd, lvl;
     int wave_range;  // each wavefront takes the bins of its own rows (else the workgroup's)
+    int tab;         // angles a workgroup tabulates in LDS at once (0: the largest table)
     const float* y;
     float* part;  // nq partial images N_l x N_l, image orientation
     int G;

@@ -1118,7 +1118,7 @@ struct BpAngle {
     };
 };
 static_assert(sizeof(BpAngle) == 48, "BpAngle layout");
-constexpr int kBpAngTab = 128;  // angles a workgroup tabulates at once
+constexpr int kBpAngTab = 128;  // the most angles a workgroup tabulates at once
 
 template <int R, int W>
 __device__ __forceinline__ void bp_own_body(const BpOwnArgs& a, const Blk& bk, float* smem)
@@ -1147,8 +1147,9 @@ __device__ __forceinline__ void bp_own_body(const BpOwnArgs& a, const Blk& bk, f
     float* rows = acc + (size_t)wave * kBpRowsPerWave * S;
     for (int q = lane; q < kBpRowsPerWave * S; q += 64) rows[q] = 0.0f;
     constexpr int NC = kBpChunks * kBpRowsPerWave;
-    for (int kb = 0; kb < nang; kb += kBpAngTab) {
-        const int nk = min(kBpAngTab, nang - kb);
+    const int ntab = a.tab > 0 ? a.tab : kBpAngTab;
+    for (int kb = 0; kb < nang; kb += ntab) {
+        const int nk = min(ntab, nang - kb);
         __syncthreads();  // the previous block of the table is consumed
         for (int t = threadIdx.x; t < nk; t += blockDim.x) {
             const int ang = angle_of(a.split, pass, g + (kb + t) * a.G);
@@ -2326,10 +2327,10 @@ constexpr size_t kLdsBytes = 160 * 1024;  // LDS per CU on gfx950
 
 // Dynamic LDS of k_bp_own<R, W> for rows of nl pixels.
 template <int R, int W>
-static size_t scatter_lds(int nl)
+static size_t scatter_lds(int nl, int tab = 0)
 {
     using Sh = BpShape<R, W>;
-    return sizeof(float) * ((size_t)Sh::rows * (nl + 2 * Sh::pad) + 3) + sizeof(BpAngle) * kBpAngTab;
+    return sizeof(float) * ((size_t)Sh::rows * (nl + 2 * Sh::pad) + 3) + sizeof(BpAngle) * (tab > 0 ? tab : kBpAngTab);
 }
 
 // Ownership scatter with about IMK_BP_TARGET_WG workgroups: G angle groups
@@ -2352,13 +2353,17 @@ static void plan_scatter(BpOwnArgs& a, int nl, int lvl, int variant, int round, 
     // image or more (512^2 / 720 x 768, level 3: 22.5 -> 19.0 us; level 0,
     // where the rows are 1/64 of it, pays 4% for the extra range work)
     a.wave_range = Sh::rows * 8 >= nl;
+    // a table as long as the largest group: at level 0 of 512^2 / 720 x 768
+    // (32 groups of at most 12 angles) the workgroup's LDS falls from 23 to
+    // 18 KB, so that eight workgroups share a CU instead of six
+    a.tab = std::min(kBpAngTab, (std::max(a.split.nrow, a.split.ncol) + a.G - 1) / a.G);
     Launch L;
     L.variant = variant;
     L.round = round;
     L.gx = (unsigned)nb;
     L.gy = (unsigned)(2 * a.G);
     L.block = 64 * W;
-    L.lds = (int)scatter_lds<R, W>(nl);
+    L.lds = (int)scatter_lds<R, W>(nl, a.tab);
     L.set(a);
     out.push_back(L);
 }

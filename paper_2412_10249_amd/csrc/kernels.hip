@@ -2354,8 +2354,8 @@ static void plan_scatter(BpOwnArgs& a, int nl, int lvl, int variant, int round, 
     // where the rows are 1/64 of it, pays 4% for the extra range work)
     a.wave_range = Sh::rows * 8 >= nl;
     // a table as long as the largest group: at level 0 of 512^2 / 720 x 768
-    // (32 groups of at most 12 angles) the workgroup's LDS falls from 23 to
-    // 18 KB, so that eight workgroups share a CU instead of six
+    // (16 groups of at most 23 angles per pass) the workgroup's LDS falls
+    // from 23 to 18 KB, so that eight workgroups share a CU instead of six
     a.tab = std::min(kBpAngTab, (std::max(a.split.nrow, a.split.ncol) + a.G - 1) / a.G);
     Launch L;
     L.variant = variant;

@@ -1320,7 +1320,26 @@ __device__ __forceinline__ void slice_sum(const BpOwnArgs& a, size_t d, size_t e
 #pragma unroll
     for (int c = 0; c < V; ++c) sum[c] = 0.0f;
     if (e >= d) return;
-    for (int q = q0; q < q1; ++q) {
+    int q = q0;
+    // eight partials loaded before any is added (their latencies overlap),
+    // then added in partial order
+    constexpr int U = 8;
+    for (; q + U <= q1; q += U) {
+        float v[U][V];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const float* pp = a.part + (q + u) * d + e;
+            if constexpr (V == 4)
+                ld4(pp, v[u]);
+            else
+                v[u][0] = pp[0];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int c = 0; c < V; ++c) sum[c] += v[u][c];
+    }
+    for (; q < q1; ++q) {
         const float* pp = a.part + q * d + e;
         if constexpr (V == 4) {
             float v[4];
@@ -1418,18 +1437,38 @@ __device__ __forceinline__ void bp_sum_primal_body(const BpOwnArgs& a, int S, co
         const size_t pix = (size_t)i * p.n + j;
         const float g = gsh[c];
         float avg = 0.0f, ownv = 0.0f;
-        for (int cc = 0; cc < p.r; ++cc) {
-            const int lc = p.lvl[cc];
-            const size_t cell = cc == 0 ? pix : (size_t)(i >> lc) * (p.n >> lc) + (j >> lc);
-            for (int bb = 0; bb < p.nblk; ++bb) {  // one table per measurement block
-                float ph;
-                if (cc == p.kidx && bb == p.jblk) {
-                    ph = own[c];
-                    ownv = ph;
-                } else {
-                    ph = p.phi[bb * p.blk_stride + p.phi_off[cc] + cell];
+        if (p.nblk == 1) {
+            // every level's entry loaded before the first is used (level k's,
+            // already refreshed, is replaced by its old value kept in LDS),
+            // then combined in level order
+            ownv = own[c];
+            float ph[IMASK_MAX_LEVELS];
+#pragma unroll
+            for (int cc = 0; cc < IMASK_MAX_LEVELS; ++cc) {
+                if (cc >= p.r) break;
+                const int lc = p.lvl[cc];
+                const size_t cell = cc == 0 ? pix : (size_t)(i >> lc) * (p.n >> lc) + (j >> lc);
+                ph[cc] = p.phi[p.phi_off[cc] + cell];
+            }
+#pragma unroll
+            for (int cc = 0; cc < IMASK_MAX_LEVELS; ++cc) {
+                if (cc >= p.r) break;
+                avg = fmaf(p.pavg[cc], cc == p.kidx ? ownv : ph[cc], avg);
+            }
+        } else {
+            for (int cc = 0; cc < p.r; ++cc) {
+                const int lc = p.lvl[cc];
+                const size_t cell = cc == 0 ? pix : (size_t)(i >> lc) * (p.n >> lc) + (j >> lc);
+                for (int bb = 0; bb < p.nblk; ++bb) {  // one table per measurement block
+                    float ph;
+                    if (cc == p.kidx && bb == p.jblk) {
+                        ph = own[c];
+                        ownv = ph;
+                    } else {
+                        ph = p.phi[bb * p.blk_stride + p.phi_off[cc] + cell];
+                    }
+                    avg = fmaf(p.pavg[cc], ph, avg);
                 }
-                avg = fmaf(p.pavg[cc], ph, avg);
             }
         }
         const float xi = (g - ownv) + avg;
@@ -1511,13 +1550,32 @@ __device__ __forceinline__ void primal_tile(const PrimalArgs& a, int ty, int tx,
             g = acc * ip0;
         }
         float avg = 0.0f, own = 0.0f;
-        for (int c = 0; c < a.r; ++c) {
-            const int l = a.lvl[c];
-            const size_t cell = c == 0 ? pix : (size_t)(i >> l) * (a.n >> l) + (j >> l);
-            for (int b = 0; b < a.nblk; ++b) {  // one table per measurement block
-                const float ph = a.phi[b * a.blk_stride + a.phi_off[c] + cell];
-                avg = fmaf(a.pavg[c], ph, avg);
-                if (c == a.kidx && b == a.jblk) own = ph;
+        if (a.nblk == 1) {
+            // every level's entry loaded before the first is used, then
+            // combined in level order
+            float ph[IMASK_MAX_LEVELS];
+#pragma unroll
+            for (int c = 0; c < IMASK_MAX_LEVELS; ++c) {
+                if (c >= a.r) break;
+                const int l = a.lvl[c];
+                const size_t cell = c == 0 ? pix : (size_t)(i >> l) * (a.n >> l) + (j >> l);
+                ph[c] = a.phi[a.phi_off[c] + cell];
+            }
+#pragma unroll
+            for (int c = 0; c < IMASK_MAX_LEVELS; ++c) {
+                if (c >= a.r) break;
+                avg = fmaf(a.pavg[c], ph[c], avg);
+                if (c == a.kidx) own = ph[c];
+            }
+        } else {
+            for (int c = 0; c < a.r; ++c) {
+                const int l = a.lvl[c];
+                const size_t cell = c == 0 ? pix : (size_t)(i >> l) * (a.n >> l) + (j >> l);
+                for (int b = 0; b < a.nblk; ++b) {  // one table per measurement block
+                    const float ph = a.phi[b * a.blk_stride + a.phi_off[c] + cell];
+                    avg = fmaf(a.pavg[c], ph, avg);
+                    if (c == a.kidx && b == a.jblk) own = ph;
+                }
             }
         }
         const float xi = (g - own) + avg;

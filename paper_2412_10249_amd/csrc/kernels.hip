@@ -512,8 +512,10 @@ __global__ void __launch_bounds__(256) k_bp_fan_gather(BpOwnArgs a)
     const bool inside = i < nl && j < nl;
     const int g = blockIdx.y;
     const FanGeo& f = a.fan;
-    const int v0 = f.va + (int)((long long)g * (f.vb - f.va) / a.G);
-    const int v1 = f.va + (int)((long long)(g + 1) * (f.vb - f.va) / a.G);
+    // group g takes the views va + g, va + g + G, ... (the same mix of view
+    // angles in every group); v below counts the group's views
+    const int nvg = g < f.vb - f.va ? (f.vb - f.va - g + a.G - 1) / a.G : 0;
+    auto view_of = [&](int k) { return f.va + g + k * a.G; };
     const double hl = 2.0 * f.E / nl;
     auto ctr = [&](int k) { return (float)(-f.E + (k + 0.5) * hl); };  // pixel-centre coordinate
     const float xj = ctr(j), yi = ctr(i), hf = (float)hl;
@@ -527,8 +529,8 @@ __global__ void __launch_bounds__(256) k_bp_fan_gather(BpOwnArgs a)
     auto first = [&](float lo) { return (int)ceilf(fminf(fmaxf(lo - marg, 0.0f), top + 1.0f)); };
     auto last = [&](float hi) { return (int)floorf(fmaxf(fminf(hi + marg, top), -1.0f)); };
     float acc = 0.0f;
-    int v = v0, boff = -1;  // next view; first bin still to stage in it (-1: its tile range start)
-    while (v < v1) {
+    int v = 0, boff = -1;  // next view; first bin still to stage in it (-1: its tile range start)
+    while (v < nvg) {
         __syncthreads();  // the previous round's LDS has been read
         if ((int)threadIdx.x < kFanViews) {
             // tile range of view v + t: projections of the end-point boxes
@@ -537,8 +539,8 @@ __global__ void __launch_bounds__(256) k_bp_fan_gather(BpOwnArgs a)
             const int t = threadIdx.x, vv = v + t;
             int lo = 0, hi = -1, fl = 0;
             float c = 0.0f, s = 0.0f;
-            if (vv < v1) {
-                const FanView fv = f.view[vv];
+            if (vv < nvg) {
+                const FanView fv = f.view[view_of(vv)];
                 c = (float)fv.c;
                 s = (float)fv.s;
                 fl = (fv.has_row ? 1 : 0) | (fv.has_col ? 2 : 0);
@@ -566,7 +568,7 @@ __global__ void __launch_bounds__(256) k_bp_fan_gather(BpOwnArgs a)
         if (threadIdx.x == 0) {
             // cut the round into segments of the views' ranges, kFanSlots bins in all
             int n = 0, used = 0, nv = v, nb = -1;
-            for (int k = 0; k < kFanViews && v + k < v1; ++k) {
+            for (int k = 0; k < kFanViews && v + k < nvg; ++k) {
                 const int lo = (k == 0 && boff >= 0) ? boff : q_lo[k];
                 const int cnt = q_hi[k] - lo + 1;
                 const int take = min(cnt, kFanSlots - used);
@@ -594,7 +596,7 @@ __global__ void __launch_bounds__(256) k_bp_fan_gather(BpOwnArgs a)
         for (int sl = threadIdx.x; sl < used; sl += blockDim.x) {
             int k = 0;
             while (k + 1 < n && g_start[k + 1] <= sl) ++k;
-            const int vv = v + g_view[k], b = g_b0[k] + (sl - g_start[k]);
+            const int vv = view_of(v + g_view[k]), b = g_b0[k] + (sl - g_start[k]);
             const FanRay r = f.ray[(size_t)vv * a.nd + b];
             long long cfx, afx;
             float wr;
@@ -702,8 +704,10 @@ __global__ void __launch_bounds__(kFanMaxWaves * 64) k_bp_fan_scatter(BpOwnArgs 
     for (int c = threadIdx.x; c < rows * S; c += blockDim.x) cells[c] = 0.0f;
     __syncthreads();
     const FanGeo& f = a.fan;
-    const int v0 = f.va + (int)((long long)g * (f.vb - f.va) / a.G);
-    const int v1 = f.va + (int)((long long)(g + 1) * (f.vb - f.va) / a.G);
+    // group g takes the views va + g, va + g + G, ...: every group sees the
+    // same mix of view angles, so the row and column passes' workgroups get
+    // about equal work
+    const int nvg = g < f.vb - f.va ? (f.vb - f.va - g + a.G - 1) / a.G : 0;
     const double hl = 2.0 * f.E / nl;
     auto ctr = [&](int k) { return (float)(-f.E + (k + 0.5) * hl); };  // pixel-centre coordinate
     const float Df = (float)f.D, mag = (float)(f.D + f.Dd), ids = (float)(1.0 / f.ds);
@@ -712,7 +716,8 @@ __global__ void __launch_bounds__(kFanMaxWaves * 64) k_bp_fan_scatter(BpOwnArgs 
     // axis, the centres -1 .. nl across it (all within 1.6E of the centre)
     const float o0 = ctr(q0), o1 = ctr(q0 + nown - 1), x0 = ctr(-1), x1 = ctr(nl);
     const int want = pass == 0 ? 1 : 0;
-    for (int v = v0; v < v1; ++v) {
+    for (int jv = 0; jv < nvg; ++jv) {
+        const int v = f.va + g + jv * a.G;
         const FanView fv = f.view[v];
         if (pass == 0 ? !fv.has_row : !fv.has_col) continue;
         const float c = (float)fv.c, s = (float)fv.s;

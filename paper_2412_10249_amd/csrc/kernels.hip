@@ -451,25 +451,50 @@ __device__ __forceinline__ void fan_coords(const FanRay& r, double E, int nl, lo
 __global__ void __launch_bounds__(256) k_fwd_fan(FwdBandArgs a)
 {
     const size_t e = (size_t)a.fan.va * a.nd + (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (size_t)a.fan.vb * a.nd) return;
+    const bool ok = e < (size_t)a.fan.vb * a.nd;  // lanes past the end still take part in the range vote
     const int nl = a.n >> a.lvl;
     const int P = nl + kPad;
-    const FanRay r = a.fan.ray[e];
-    long long cfx, afx;
-    float wr;
-    fan_coords(r, a.fan.E, nl, cfx, afx, wr);
+    FanRay r{};
+    long long cfx = 0, afx = 0;
+    float wr = 0.0f;
+    // the steps whose left tap can lie in [-1, nl - 1], from the line
+    // u(k) = cfx + k afx in FP64, one step wider on each side (empty past
+    // the end); the wavefront walks the union of its lanes' ranges, so its
+    // loads at a step stay on one row, and the exact test below decides
+    // every step: the sum is the full walk's, bit for bit
+    int k0 = nl, k1 = -1;
+    if (ok) {
+        r = a.fan.ray[e];
+        fan_coords(r, a.fan.E, nl, cfx, afx, wr);
+        if (afx != 0) {
+            const double t1 = (-4294967296.0 - (double)cfx) / (double)afx;
+            const double t2 = ((double)nl * 4294967296.0 - (double)cfx) / (double)afx;
+            k0 = (int)fmin(fmax(floor(fmin(t1, t2)) - 1.0, 0.0), (double)nl);
+            k1 = (int)fmax(fmin(ceil(fmax(t1, t2)) + 1.0, (double)(nl - 1)), -1.0);
+        } else {
+            k0 = 0;
+            k1 = nl - 1;
+        }
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        k0 = min(k0, __shfl_xor(k0, off));
+        k1 = max(k1, __shfl_xor(k1, off));
+    }
+    k0 = __builtin_amdgcn_readfirstlane(k0);
+    k1 = __builtin_amdgcn_readfirstlane(k1);
     const float* img = (r.row ? a.img : a.imgT) + kPadL;
     float acc = 0.0f;
-    long long u = cfx;
-    for (int k = 0; k < nl; ++k, u += afx) {
+    long long u = cfx + (long long)k0 * afx;
+    for (int k = k0; k <= k1; ++k, u += afx) {
         const int j0 = tap_index(u);
-        if ((unsigned)(j0 + 1) <= (unsigned)nl) {  // j0 in [-1, nl - 1]
+        if (ok && (unsigned)(j0 + 1) <= (unsigned)nl) {  // j0 in [-1, nl - 1]
             const float w = tap_weight(u);
             const float* t = img + (size_t)k * P + j0;
             acc = fmaf(1.0f - w, t[0], fmaf(w, t[1], acc));
         }
     }
-    a.part[e] = wr * acc;
+    if (ok) a.part[e] = wr * acc;
 }
 
 // Fan-beam transpose as a gather, for levels where rays are dense (more than

@@ -505,15 +505,15 @@ __global__ void __launch_bounds__(256) k_fwd_fan(FwdBandArgs a)
 // i - 1 and i + 1); those end points, projected from the source onto the
 // detector, bound the pixel's candidate bins, and the projections of the
 // tile's two end-point boxes bound the tile's.  Each round stages the
-// tile's candidate bins of up to kFanViews consecutive views (at most
+// tile's candidate bins of the next kFanViews views of the group (at most
 // kFanSlots bins; a view with more continues in the next round) through
 // LDS, each bin with the forward's fixed-point coordinate and its weighted
 // datum; every pixel then tests its own candidates exactly and adds (1 - w)
 // or w of the datum, so every matrix entry is the forward's bit for bit.
 // Bin estimates are FP32 with a margin (bmargin) well above their rounding
 // error: a spare candidate fails the exact test, none is missed.  A pixel
-// sums its rays in view order and bin order, row-stepping candidates before
-// column-stepping ones within a staged segment of a view.
+// sums its rays in the group's view order and bin order, row-stepping
+// candidates before column-stepping ones within a staged segment of a view.
 constexpr int kFanTile = 16;
 constexpr int kFanSlots = 512;
 #ifndef IMK_FAN_TARGET_WG

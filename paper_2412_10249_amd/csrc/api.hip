@@ -98,15 +98,12 @@ Layout make_layout(const imask_geometry& g)
     off = align64(off + (size_t)g.n * g.n);
     const size_t m = (size_t)g.n_angles * g.n_det;
     for (int l = 0; l <= L.lmax; ++l) {
-        if (is_fan(g)) {  // one thread per ray, one partial sinogram
-            L.fbands[l] = 1;
-            L.frows[l] = 0;
-        } else {
-            fwd_bands(side(g.n, l), g.n_angles, g.n_det, &L.fbands[l], &L.frows[l]);
-        }
+        // LDS bands of the level image for either beam (the fan forward
+        // walks each ray's own line through the same bands)
+        fwd_bands(side(g.n, l), g.n_angles, g.n_det, &L.fbands[l], &L.frows[l]);
         // sized for the default band layout; tuned shapes use no more bands
         int cap = L.fbands[l], rows_cap = 0;
-        if (!is_fan(g)) fwd_bands_default(side(g.n, l), g.n_angles, g.n_det, &cap, &rows_cap);
+        fwd_bands_default(side(g.n, l), g.n_angles, g.n_det, &cap, &rows_cap);
         L.fpart[l] = off;
         off = align64(off + (size_t)std::max(cap, L.fbands[l]) * m);
     }

@@ -497,6 +497,77 @@ __global__ void __launch_bounds__(256) k_fwd_fan(FwdBandArgs a)
     if (ok) a.part[e] = wr * acc;
 }
 
+// Fan-beam forward over LDS bands, as k_fwd_band for the parallel beam:
+// workgroup (band, group) copies rows [i0, i1) of the padded level image
+// (pass 0) or of its transposed copy (pass 1) into LDS, and sums over the
+// band every ray of its views that steps along that axis; each ray's line
+// is its own (the ray table's fixed-point coordinate), its steps in the
+// band come from that line in FP64, one step wider on each side (a tap one
+// step outside the image lands in the zero padding and adds nothing).
+// View group g of a pass takes the views va + g, va + g + G, ...  The ray's
+// band sum goes to part[band][view][bin]; the reduce adds the bands.
+__global__ void __launch_bounds__(1024) k_fwd_fan_band(FwdBandArgs a)
+{
+    extern __shared__ float band[];
+    const int nl = a.n >> a.lvl;
+    const int P = nl + kPad;
+    const int bi = blockIdx.x;
+    const int G = a.groups_row;  // view groups per pass
+    const int pass = (int)blockIdx.y < G ? 0 : 1;
+    const int g = (int)blockIdx.y - pass * G;
+    const FanGeo& f = a.fan;
+    const int nv = f.vb - f.va;
+    const int nvg = g < nv ? (nv - g + G - 1) / G : 0;
+    const int i0 = bi * a.R;
+    const int i1 = min(nl, i0 + a.R);
+    {
+        const float* src = (pass == 0 ? a.img : a.imgT) + (size_t)i0 * P;
+        const int cnt = (i1 - i0) * P;
+        if ((P & 3) == 0) {  // rows start 16-byte aligned
+            const float4* s4 = (const float4*)src;
+            float4* d4 = (float4*)band;
+            for (int q = threadIdx.x; q < cnt / 4; q += blockDim.x) d4[q] = s4[q];
+        } else {
+            for (int q = threadIdx.x; q < cnt; q += blockDim.x) band[q] = src[q];
+        }
+    }
+    __syncthreads();
+    const size_t m = (size_t)a.na * a.nd;
+    const long long rowfx = (long long)P << 32;
+    int kk = threadIdx.x / a.nd;
+    int b = threadIdx.x - kk * a.nd;
+    while (kk < nvg) {
+        const size_t e = (size_t)(f.va + g + kk * G) * a.nd + b;
+        const FanRay r = f.ray[e];
+        if ((r.row != 0) == (pass == 0)) {
+            long long cfx, afx;
+            float wr;
+            fan_coords(r, f.E, nl, cfx, afx, wr);
+            int lo = i0, hi = i1 - 1;
+            if (afx != 0) {
+                const double t1 = (-4294967296.0 - (double)cfx) / (double)afx;
+                const double t2 = ((double)nl * 4294967296.0 - (double)cfx) / (double)afx;
+                lo = (int)fmin(fmax(floor(fmin(t1, t2)) - 1.0, (double)i0), (double)i1);
+                hi = (int)fmax(fmin(ceil(fmax(t1, t2)) + 1.0, (double)(i1 - 1)), (double)(i0 - 1));
+            } else if ((unsigned)((int)(cfx >> 32) + 1) > (unsigned)nl) {
+                lo = i0 + 1;  // a line outside the image: no step
+                hi = i0;
+            }
+            float acc = 0.0f;
+            if (lo <= hi) {
+                const long long U = cfx + (long long)lo * afx + (long long)((lo - i0) * P + kPadL) * 4294967296LL;
+                acc = band_sum(band, U, afx + rowfx, hi - lo + 1);
+            }
+            a.part[(size_t)bi * m + e] = wr * acc;
+        }
+        b += blockDim.x;
+        while (b >= a.nd) {
+            b -= a.nd;
+            ++kk;
+        }
+    }
+}
+
 // Fan-beam transpose as a gather, for levels where rays are dense (more than
 // kFanScatterMaxP phases of the scatter below): 16 x 16 pixel tiles, one
 // workgroup per tile and view group.  In a view, the row-stepping rays that
@@ -2384,7 +2455,22 @@ hipError_t launch_fwd_terms(const FwdArgs& a, hipStream_t s)
             fb.part = tm.part;
             fb.split = a.split;
             const size_t m = (size_t)(a.fan.vb - a.fan.va) * a.nd;
-            hipLaunchKernelGGL(k_fwd_fan, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, fb);
+            if (tm.rows > 0) {
+                // LDS bands of the level image, as the parallel beam's; about
+                // 512 workgroups over bands, passes and view groups
+                const int nl = a.n >> tm.lvl;
+                const int nv = a.fan.vb - a.fan.va;
+                fb.R = tm.rows;
+                fb.bands = tm.bands;
+                fb.groups_row = fb.groups_col = std::max(1, std::min(nv, 512 / (2 * tm.bands)));
+                const int lds = (int)(sizeof(float) * (size_t)fb.R * (nl + kPad));
+                hipError_t e = allow_lds((const void*)k_fwd_fan_band, lds);
+                if (e != hipSuccess) return e;
+                hipLaunchKernelGGL(k_fwd_fan_band, dim3((unsigned)tm.bands, (unsigned)(2 * fb.groups_row)), dim3(1024),
+                                   lds, s, fb);
+            } else {
+                hipLaunchKernelGGL(k_fwd_fan, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, fb);
+            }
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
         }

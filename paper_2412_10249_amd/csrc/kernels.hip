@@ -763,9 +763,10 @@ __global__ void __launch_bounds__(256) k_fan_table(BpOwnArgs a)
 }
 
 // Fan-beam transpose as an ownership scatter.  Workgroup (block, pass,
-// group) owns 2 * waves image rows (pass 0, row-stepping rays) or columns
-// (pass 1, column-stepping rays) in LDS, two per wavefront, each with one
+// group) owns RW * waves image rows (pass 0, row-stepping rays) or columns
+// (pass 1, column-stepping rays) in LDS, RW per wavefront, each with one
 // cell beyond either end of the image for the taps that fall outside it.
+// A wavefront reads each ray's table entry once for all its RW lines.
 // For each view of its group, every wavefront takes the bins that can reach
 // the block (the projection of the block's end-point box, FP32 with a
 // margin) in P phases: lanes of one instruction hold bins P apart, and P is
@@ -776,7 +777,15 @@ __global__ void __launch_bounds__(256) k_fan_table(BpOwnArgs a)
 // so the LDS latencies overlap.  A sample adds (1 - w) of its ray's
 // weighted datum to the left tap, then w to the right tap: the forward's
 // weights bit for bit, in a fixed order.  Used where P <= kFanScatterMaxP.
-constexpr int kFanRowsPerWave = 2;
+#ifndef IMK_FAN_ROWS_SPARSE
+#define IMK_FAN_ROWS_SPARSE 3
+#endif
+#ifndef IMK_FAN_ROWS_DENSE
+#define IMK_FAN_ROWS_DENSE 4
+#endif
+#ifndef IMK_FAN_SPARSE_WAVES
+#define IMK_FAN_SPARSE_WAVES 4
+#endif
 constexpr int kFanMaxWaves = 8;
 #ifndef IMK_FAN_SCATTER_MAX_P
 #define IMK_FAN_SCATTER_MAX_P 6
@@ -786,13 +795,13 @@ constexpr int kFanScatterMaxP = IMK_FAN_SCATTER_MAX_P;
 #define IMK_FAN_SCATTER_WG 4096
 #endif
 
-template <int CH>
+template <int CH, int RW>
 __global__ void __launch_bounds__(kFanMaxWaves * 64) k_bp_fan_scatter(BpOwnArgs a, int P)
 {
     extern __shared__ float cells[];  // owned lines of nl + 2 cells: taps -1 .. nl
     const int nl = a.n >> a.lvl;
     const int S = nl + 2;
-    const int rows = kFanRowsPerWave * (int)(blockDim.x >> 6);
+    const int rows = RW * (int)(blockDim.x >> 6);
     const int pass = blockIdx.y, g = blockIdx.z;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int q0 = blockIdx.x * rows;  // first owned row (pass 0) or column (pass 1)
@@ -839,7 +848,7 @@ __global__ void __launch_bounds__(kFanMaxWaves * 64) k_bp_fan_scatter(BpOwnArgs 
         const FanTab* tv = f.tab + (size_t)v * a.nd;
         for (int p = 0; p < P; ++p) {
             for (int b = blo + p + P * lane; b <= bhi; b += CH * 64 * P) {
-                constexpr int NC = CH * kFanRowsPerWave;
+                constexpr int NC = CH * RW;
                 int cl[NC];
                 bool ok[NC];
                 float omw[NC], cw[NC], wy[NC];
@@ -850,9 +859,9 @@ __global__ void __launch_bounds__(kFanMaxWaves * 64) k_bp_fan_scatter(BpOwnArgs 
                     if (bh <= bhi) t = tv[bh];
                     const bool use = bh <= bhi && t.row == want;
 #pragma unroll
-                    for (int rr = 0; rr < kFanRowsPerWave; ++rr) {
-                        const int c = h * kFanRowsPerWave + rr;
-                        const int own = wave * kFanRowsPerWave + rr;
+                    for (int rr = 0; rr < RW; ++rr) {
+                        const int c = h * RW + rr;
+                        const int own = wave * RW + rr;
                         const long long u = t.cfx + (long long)(q0 + own) * t.afx;
                         const int j0 = tap_index(u);
                         ok[c] = use && own < nown && (unsigned)(j0 + 1) <= (unsigned)nl;  // j0 in [-1, nl - 1]
@@ -2621,15 +2630,20 @@ hipError_t launch_bp_main(const BpArgs& ba, hipStream_t s, BpOwnArgs& a)
         hipLaunchKernelGGL(k_fan_table, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, a);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        // shape measured on the 512^2 fan workload: where rays are sparse
-        // (P <= 3) 4 wavefronts of 4 rays per trip (level 0: 424 against
-        // 481 us), else 8 wavefronts of 2 (level 1: 212 against 327 us);
-        // two owned lines per wavefront, as many wavefronts as fit in the LDS
+        // shape measured on the 512^2 fan workload: one ray per trip; where
+        // rays are sparse (P <= 3) 4 wavefronts of 3 owned lines (level 0:
+        // 237 against 293 us with 2 lines and 4 rays per trip), else 8
+        // wavefronts of 4 lines (level 1: 130 against 168 us with 2 lines
+        // and 2 rays); as many wavefronts as fit in the LDS
         const bool sparse = phases <= 3;
         const size_t line = sizeof(float) * (size_t)(nl + 2);
+        // lines too long for that many per wavefront in the LDS (grids of
+        // more than about 10000 pixels): two per wavefront
+        const int rw_want = sparse ? IMK_FAN_ROWS_SPARSE : IMK_FAN_ROWS_DENSE;
+        const int rw = (size_t)rw_want * line <= kLdsBytes ? rw_want : 2;
         const int waves = (int)std::max<size_t>(
-            1, std::min<size_t>(sparse ? 4 : kFanMaxWaves, kLdsBytes / (kFanRowsPerWave * line)));
-        const int rows = kFanRowsPerWave * waves;
+            1, std::min<size_t>(sparse ? IMK_FAN_SPARSE_WAVES : kFanMaxWaves, kLdsBytes / (rw * line)));
+        const int rows = rw * waves;
         const int blocks = (nl + rows - 1) / rows;
         // view groups: about IMK_FAN_SCATTER_WG workgroups (more view groups,
         // shorter workgroups: level 0 of the 512^2 fan workload 424 -> 318 us
@@ -2640,14 +2654,20 @@ hipError_t launch_bp_main(const BpArgs& ba, hipStream_t s, BpOwnArgs& a)
         a.G = (int)std::max(1LL, std::min({want, nv, room, 1024LL}));
         a.nq = 2 * a.G;
         const int lds = (int)(rows * line);
-        if (sparse) {
-            e = allow_lds((const void*)k_bp_fan_scatter<4>, lds);
+        if (rw == 2) {
+            e = allow_lds((const void*)k_bp_fan_scatter<1, 2>, lds);
             if (e != hipSuccess) return e;
-            hipLaunchKernelGGL(k_bp_fan_scatter<4>, dim3(blocks, 2, a.G), dim3(64 * waves), lds, s, a, phases);
+            hipLaunchKernelGGL((k_bp_fan_scatter<1, 2>), dim3(blocks, 2, a.G), dim3(64 * waves), lds, s, a, phases);
+        } else if (sparse) {
+            e = allow_lds((const void*)k_bp_fan_scatter<1, IMK_FAN_ROWS_SPARSE>, lds);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL((k_bp_fan_scatter<1, IMK_FAN_ROWS_SPARSE>), dim3(blocks, 2, a.G), dim3(64 * waves), lds,
+                               s, a, phases);
         } else {
-            e = allow_lds((const void*)k_bp_fan_scatter<2>, lds);
+            e = allow_lds((const void*)k_bp_fan_scatter<1, IMK_FAN_ROWS_DENSE>, lds);
             if (e != hipSuccess) return e;
-            hipLaunchKernelGGL(k_bp_fan_scatter<2>, dim3(blocks, 2, a.G), dim3(64 * waves), lds, s, a, phases);
+            hipLaunchKernelGGL((k_bp_fan_scatter<1, IMK_FAN_ROWS_DENSE>), dim3(blocks, 2, a.G), dim3(64 * waves), lds,
+                               s, a, phases);
         }
         return hipGetLastError();
     }
